@@ -1,0 +1,435 @@
+"""Oracle for the surface-conductivity-modified PMCHW system (plain FP64).
+
+TEST INFRASTRUCTURE ONLY: only tests/, the smoke check and the CPU-baseline leg
+of bench.py may import this package.  It shares no code with the GPU library.
+
+Two operators are defined here, both from the paper's discretisation
+(Appendix A, eq19):
+
+* ``dense()`` -- the Galerkin matrix A of the five-current system with
+  singularity-subtracted panel quadrature, solved by LU.
+* ``PFFT`` -- the precorrected-FFT approximation of the same operator (grid
+  projection, lattice convolution with G sampled on the grid, interpolation,
+  and exact-minus-grid corrections on near triangle pairs), applied step by
+  step; its convolution uses numpy's FFT as a library primitive.
+
+Readings of the paper that these follow are listed in the design notes:
+testing of eq13 rotated by n x (so sigma = 0 reduces to PMCHW), pointwise
+one-sided fields for the sigma-weighted tests, absorber edges = edges whose
+support has sigma > 0 at a quadrature point, 7-point rule everywhere.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import List, Optional, Sequence
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "scabs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NQ = 7
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C part with gcc (OpenMP, FP64, no -ffast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        zp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+        L.or_create.restype = P
+        L.or_create.argtypes = [C.c_int, dp, C.c_int, ip, ip, C.c_double, C.c_double, C.c_double, C.c_double, C.c_char_p]
+        L.or_free.argtypes = [P]
+        L.or_error.restype = C.c_char_p
+        L.or_error.argtypes = [P]
+        L.or_counts.argtypes = [P, ip]
+        L.or_get_points.argtypes = [P, dp, dp, dp]
+        L.or_get_edges.argtypes = [P, ip, ip, dp, ip, ip]
+        L.or_sigma_clear.argtypes = [P]
+        L.or_sigma_add_monomial.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double]
+        L.or_sigma_add_pwl.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+        L.or_sigma_pwl_jacobian.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+        L.or_sigma_set.argtypes = [P, dp]
+        L.or_sigma_get.argtypes = [P, dp]
+        L.or_layout.restype = C.c_int
+        L.or_layout.argtypes = [P, C.c_int]
+        L.or_get_layout.argtypes = [P, ip, ip]
+        L.or_point_basis.argtypes = [P, dp, dp]
+        L.or_static_integrals.argtypes = [dp, dp, dp, dp, dp, dp, dp]
+        L.or_dense.restype = C.c_int
+        L.or_dense.argtypes = [P, zp]
+        L.or_local_coo.restype = C.c_long
+        L.or_local_coo.argtypes = [P, ip, ip, zp, C.c_long]
+        L.or_dipole_field.argtypes = [C.c_double, C.c_double, dp, zp, dp, zp, zp]
+        L.or_rhs_dipole.argtypes = [P, dp, zp, C.c_int, zp]
+        L.or_incident_at_points.argtypes = [P, dp, zp, C.c_int, zp, zp]
+        L.or_point_fields.argtypes = [P, zp, zp, zp]
+        L.or_fields_at.argtypes = [P, zp, C.c_int, dp, C.c_int, zp, zp]
+        L.or_stencil.argtypes = [C.c_double, dp, ip, dp, dp]
+        L.or_grid_setup.argtypes = [P, C.c_double]
+        L.or_grid_weights.argtypes = [P, ip, dp, dp]
+        L.or_near_pairs.restype = C.c_long
+        L.or_near_pairs.argtypes = [P, C.c_double, ip, C.c_long]
+        L.or_singular_radius.restype = C.c_double
+        L.or_singular_radius.argtypes = [P]
+        L.or_pair_coo.restype = C.c_long
+        L.or_pair_coo.argtypes = [P, ip, C.c_long, C.c_int, ip, ip, zp, C.c_long]
+        L.or_grid_project.restype = C.c_int
+        L.or_grid_project.argtypes = [P, zp, C.c_int, ip, ip, zp]
+        L.or_grid_interp_rows.restype = C.c_int
+        L.or_grid_interp_rows.argtypes = [P, C.c_int, ip, ip, zp, zp]
+        _lib = L
+    return _lib
+
+
+def static_integrals(r, p0, p1, p2):
+    """I0 = int 1/R, I1 = int (r'-r)/R, Ig = int grad_r(1/R) (principal value)."""
+    I0 = np.zeros(1)
+    I1 = np.zeros(3)
+    Ig = np.zeros(3)
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    lib().or_static_integrals(f(r), f(p0), f(p1), f(p2), I0, I1, Ig)
+    return I0[0], I1, Ig
+
+
+def dipole_field(k, Z, r0, p, r):
+    E = np.zeros(3, complex)
+    H = np.zeros(3, complex)
+    lib().or_dipole_field(k, Z, np.ascontiguousarray(r0, float), np.ascontiguousarray(p, complex),
+                          np.ascontiguousarray(r, float), E, H)
+    return E, H
+
+
+class Oracle:
+    """Dense-Galerkin oracle bound to one mesh, media and sigma profile."""
+
+    def __init__(self, mesh, omega: float, eps_in: float, eps_out: float = 1.0, kappa_s: float = 1.37):
+        L = lib()
+        err = C.create_string_buffer(256)
+        v = np.ascontiguousarray(mesh.verts, dtype=np.float64)
+        t = np.ascontiguousarray(mesh.tris, dtype=np.int32)
+        b = np.ascontiguousarray(mesh.body, dtype=np.int32)
+        self._c = L.or_create(v.shape[0], v.ravel(), t.shape[0], t.ravel(), b, omega, eps_in, eps_out, kappa_s, err)
+        if not self._c:
+            raise ValueError(err.value.decode())
+        self.mesh = mesh
+        self.omega, self.eps_in, self.eps_out = omega, eps_in, eps_out
+        self.k_e, self.k_i = omega * math.sqrt(eps_out), omega * math.sqrt(eps_in)
+        self.Z_e, self.Z_i = 1 / math.sqrt(eps_out), 1 / math.sqrt(eps_in)
+        cnt = np.zeros(7, np.int32)
+        L.or_counts(self._c, cnt)
+        self.nv, self.nt, self.ne, self.nbody = map(int, cnt[:4])
+        self.np_ = self.nt * NQ
+        self.qp = np.zeros((self.np_, 3))
+        self.qw = np.zeros(self.np_)
+        self.nrm = np.zeros((self.nt, 3))
+        L.or_get_points(self._c, self.qp.ravel(), self.qw, self.nrm.ravel())
+        self.ev = np.zeros((self.ne, 2), np.int32)
+        self.et = np.zeros((self.ne, 2), np.int32)
+        self.elen = np.zeros(self.ne)
+        self.tedge = np.zeros((self.nt, 3), np.int32)
+        self.tsign = np.zeros((self.nt, 3), np.int32)
+        L.or_get_edges(self._c, self.ev.ravel(), self.et.ravel(), self.elen, self.tedge.ravel(), self.tsign.ravel())
+        self.N = None
+        self.set_sigma([])
+
+    def __del__(self):
+        if getattr(self, "_c", None):
+            lib().or_free(self._c)
+            self._c = None
+
+    # -- sigma and layout ------------------------------------------------
+    def set_sigma(self, ends: Sequence, force_all_R: bool = False):
+        L = lib()
+        L.or_sigma_clear(self._c)
+        for e in ends:
+            if e.ctrl is not None:
+                L.or_sigma_add_pwl(self._c, e.axis, e.x0, e.length, e.direction, len(e.ctrl),
+                                   np.ascontiguousarray(e.ctrl, dtype=np.float64))
+            else:
+                L.or_sigma_add_monomial(self._c, e.axis, e.x0, e.length, e.direction, e.degree, e.sigma0)
+        return self._layout(force_all_R)
+
+    def set_sigma_points(self, sigma: np.ndarray, force_all_R: bool = False):
+        lib().or_sigma_set(self._c, np.ascontiguousarray(sigma, dtype=np.float64))
+        return self._layout(force_all_R)
+
+    def _layout(self, force_all_R):
+        L = lib()
+        self.N = L.or_layout(self._c, 1 if force_all_R else 0)
+        cnt = np.zeros(7, np.int32)
+        L.or_counts(self._c, cnt)
+        self.NL, self.NR = int(cnt[5]), int(cnt[6])
+        self.isR = np.zeros(self.ne, np.int32)
+        self.eidx = np.zeros(self.ne, np.int32)
+        L.or_get_layout(self._c, self.isR, self.eidx)
+        self.sigma = np.zeros(self.np_)
+        L.or_sigma_get(self._c, self.sigma)
+        return self.N
+
+    def pwl_jacobian(self, end) -> np.ndarray:
+        J = np.zeros(self.np_ * len(end.ctrl))
+        lib().or_sigma_pwl_jacobian(self._c, end.axis, end.x0, end.length, end.direction, len(end.ctrl), J)
+        return J.reshape(self.np_, len(end.ctrl))
+
+    # -- unknown helpers ---------------------------------------------------
+    def edge_currents(self, x):
+        """(J_e, J_i, M) per edge from the unknown vector (eq10-eq12)."""
+        NL, NR = self.NL, self.NR
+        Je = np.zeros(self.ne, complex)
+        Ji = np.zeros(self.ne, complex)
+        M = np.zeros(self.ne, complex)
+        l = self.isR == 0
+        r = ~l
+        il, ir = self.eidx[l], self.eidx[r]
+        Je[l] = x[il]
+        Ji[l] = -x[il]
+        M[l] = x[NL + il]
+        Je[r] = x[2 * NL + ir]
+        Ji[r] = x[2 * NL + NR + ir]
+        M[r] = x[2 * NL + 2 * NR + ir]
+        return Je, Ji, M
+
+    # -- operators ---------------------------------------------------------
+    def dense(self) -> np.ndarray:
+        A = np.zeros((self.N, self.N), complex)
+        rc = lib().or_dense(self._c, A.ravel())
+        if rc:
+            raise RuntimeError(lib().or_error(self._c).decode())
+        return A
+
+    def local_coo(self):
+        cap = 64 * self.ne + 64
+        ri = np.zeros(cap, np.int32)
+        ci = np.zeros(cap, np.int32)
+        val = np.zeros(cap, complex)
+        n = lib().or_local_coo(self._c, ri, ci, val, cap)
+        assert n <= cap
+        return sp.coo_matrix((val[:n], (ri[:n], ci[:n])), shape=(self.N, self.N)).tocsr()
+
+    def rhs_dipole(self, dip) -> np.ndarray:
+        b = np.zeros(self.N, complex)
+        lib().or_rhs_dipole(self._c, np.ascontiguousarray(dip.pos, float), np.ascontiguousarray(dip.moment, complex),
+                            int(dip.body), b)
+        return b
+
+    def incident_at_points(self, dip):
+        E = np.zeros((self.np_, 3), complex)
+        H = np.zeros((self.np_, 3), complex)
+        lib().or_incident_at_points(self._c, np.ascontiguousarray(dip.pos, float),
+                                    np.ascontiguousarray(dip.moment, complex), int(dip.body), E.ravel(), H.ravel())
+        return E, H
+
+    def point_fields(self, x):
+        """One-sided fields E_e^+ and E_i^- (without E_inc) at all quadrature points."""
+        Ee = np.zeros((self.np_, 3), complex)
+        Ei = np.zeros((self.np_, 3), complex)
+        lib().or_point_fields(self._c, np.ascontiguousarray(x, complex), Ee.ravel(), Ei.ravel())
+        return Ee, Ei
+
+    def fields_at(self, x, pts, region: int):
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        E = np.zeros((pts.shape[0], 3), complex)
+        H = np.zeros((pts.shape[0], 3), complex)
+        lib().or_fields_at(self._c, np.ascontiguousarray(x, complex), pts.shape[0], pts.ravel(), region,
+                           E.ravel(), H.ravel())
+        return E, H
+
+    def point_basis(self):
+        fv = np.zeros((self.np_, 3, 3))
+        fd = np.zeros((self.np_, 3))
+        lib().or_point_basis(self._c, fv.ravel(), fd.ravel())
+        return fv, fd
+
+    # -- post-processing (powers) ------------------------------------------
+    def surface_currents_at_points(self, x):
+        Je, Ji, M = self.edge_currents(x)
+        fv, _ = self.point_basis()
+        tri = np.repeat(np.arange(self.nt), NQ)
+        e = self.tedge[tri]                      # (np, 3)
+        Jq = np.einsum("pja,pj->pa", fv, Je[e])
+        Jiq = np.einsum("pja,pj->pa", fv, Ji[e])
+        Mq = np.einsum("pja,pj->pa", fv, M[e])
+        return Jq, Jiq, Mq
+
+    def radiated_power(self, x) -> float:
+        """P_rad = 1/2 Re oint (E x H*).n = -1/2 Re oint J_e*.(n x M_e) (eq6, eq7)."""
+        Jq, _, Mq = self.surface_currents_at_points(x)
+        n = np.repeat(self.nrm, NQ, axis=0)
+        return float(-0.5 * np.real(np.sum(self.qw * np.einsum("pa,pa->p", np.conj(Jq), np.cross(n, Mq)))))
+
+    def absorbed_power(self, x, dip=None) -> float:
+        """P_abs = 1/2 int sigma |E_tan|^2 with the interior-limit field + E_inc."""
+        Ee, Ei = self.point_fields(x)
+        Et = Ei.copy()
+        if dip is not None:
+            Einc, _ = self.incident_at_points(dip)
+            Et += Einc
+        n = np.repeat(self.nrm, NQ, axis=0)
+        Et = Et - n * np.einsum("pa,pa->p", n, Et)[:, None]
+        return float(0.5 * np.sum(self.qw * self.sigma * np.sum(np.abs(Et) ** 2, axis=1)))
+
+    def dipole_power(self, x, dip) -> float:
+        """Power delivered by the dipole: P_0 - 1/2 Re[p* . E_scat(r0)]."""
+        k, Z = self.k_i, self.Z_i
+        P0 = Z * k * k * np.real(np.vdot(dip.moment, dip.moment)) / (12 * math.pi)
+        E, _ = self.fields_at(x, dip.pos[None, :], int(dip.body))
+        return float(P0 - 0.5 * np.real(np.vdot(dip.moment, E[0])))
+
+    # -- pFFT ----------------------------------------------------------------
+    def pfft(self, h: float, r_near: float) -> "PFFT":
+        return PFFT(self, h, r_near)
+
+    def singular_radius(self) -> float:
+        return float(lib().or_singular_radius(self._c))
+
+    def near_pairs(self, r_near: float) -> np.ndarray:
+        cap = 256 * self.nt
+        while True:
+            pairs = np.zeros(2 * cap, np.int32)
+            n = lib().or_near_pairs(self._c, r_near, pairs, cap)
+            if n <= cap:
+                return pairs[: 2 * n].reshape(-1, 2)
+            cap = n
+
+    def pair_coo(self, pairs: np.ndarray, mode: int):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+        cap = 100 * pairs.shape[0] + 64
+        ri = np.zeros(cap, np.int32)
+        ci = np.zeros(cap, np.int32)
+        val = np.zeros(cap, complex)
+        n = lib().or_pair_coo(self._c, pairs.ravel(), pairs.shape[0], mode, ri, ci, val, cap)
+        assert n <= cap, (n, cap)
+        return sp.coo_matrix((val[:n], (ri[:n], ci[:n])), shape=(self.N, self.N)).tocsr()
+
+
+def _grid_kernel_hat(k: float, h: float, n: Sequence[int]) -> np.ndarray:
+    """FFT of the circulant embedding (size 2n per axis) of H(d) = G(h|d|), H(0) = 0."""
+    axes = []
+    for m in n:
+        i = np.arange(2 * m)
+        d = np.where(i < m, i, i - 2 * m).astype(np.float64)
+        d[m] = np.inf   # offset +-m is never needed
+        axes.append(d)
+    dx, dy, dz = np.meshgrid(*axes, indexing="ij")
+    R = h * np.sqrt(dx * dx + dy * dy + dz * dz)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        Hk = np.exp(-1j * k * R) / (4 * math.pi * R)
+    Hk[~np.isfinite(R)] = 0
+    Hk[0, 0, 0] = 0
+    return np.fft.fftn(Hk)
+
+
+class PFFT:
+    """Precorrected-FFT operator A~ = grid(P, H, I) + (A_exact - A_grid)|near + local."""
+
+    def __init__(self, o: Oracle, h: float, r_near: float):
+        self.o = o
+        self.h = h
+        self.r_near = r_near
+        srad = o.singular_radius()
+        if not r_near > srad:
+            raise ValueError("r_near %.6g must exceed the singular-pair radius %.6g" % (r_near, srad))
+        L = lib()
+        L.or_grid_setup(o._c, h)
+        npn = o.np_
+        self.anchor = np.zeros((npn, 3), np.int32)
+        w = np.zeros(npn * 27)
+        gd = np.zeros(npn * 81)
+        L.or_grid_weights(o._c, self.anchor.ravel(), w, gd)
+        tri_body = o.mesh.body
+        pb = np.repeat(tri_body, NQ)
+        self.grids = []   # (which, origin, dims, k)
+        for which in [-1] + list(range(o.nbody)):
+            sel = np.ones(npn, bool) if which < 0 else (pb == which)
+            lo = self.anchor[sel].min(axis=0) - 1
+            hi = self.anchor[sel].max(axis=0) + 1
+            dims = (hi - lo + 1).astype(np.int32)
+            k = o.k_e if which < 0 else o.k_i
+            self.grids.append((which, lo.astype(np.int32), dims, k, _grid_kernel_hat(k, h, dims)))
+        self.pairs = o.near_pairs(r_near)
+        self.C_near = o.pair_coo(self.pairs, 0) + o.local_coo()
+
+    def grid_apply(self, x: np.ndarray) -> np.ndarray:
+        """grid part only: interpolate(H * project(x)) tested into rows"""
+        o = self.o
+        L = lib()
+        x = np.ascontiguousarray(x, complex)
+        y = np.zeros(o.N, complex)
+        for which, lo, dims, k, Hhat in self.grids:
+            G = int(np.prod(dims))
+            Q = np.zeros(8 * G, complex)
+            rc = L.or_grid_project(o._c, x, which, lo, dims, Q)
+            assert rc == 0
+            Q = Q.reshape(8, *dims)
+            Phi = np.empty_like(Q)
+            n0, n1, n2 = dims
+            for f in range(8):
+                Qp = np.zeros((2 * n0, 2 * n1, 2 * n2), complex)
+                Qp[:n0, :n1, :n2] = Q[f]
+                Phi[f] = np.fft.ifftn(np.fft.fftn(Qp) * Hhat)[:n0, :n1, :n2]
+            rc = L.or_grid_interp_rows(o._c, which, lo, dims, np.ascontiguousarray(Phi.ravel()), y)
+            assert rc == 0
+        return y
+
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        return self.grid_apply(x) + self.C_near @ x
+
+    def solve(self, b: np.ndarray, tol: float = 1e-12, restart: int = 200, maxiter: int = 20) -> np.ndarray:
+        """GMRES on A~ (iterative solve of the pFFT system)."""
+        op = spla.LinearOperator((self.o.N, self.o.N), matvec=self.matvec, dtype=complex)
+        x, info = spla.gmres(op, b, rtol=tol, atol=0.0, restart=restart, maxiter=maxiter)
+        if info != 0:
+            raise RuntimeError("oracle GMRES did not converge (info=%d)" % info)
+        return x
+
+
+def lu_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    lu, piv = sla.lu_factor(A)
+    return sla.lu_solve((lu, piv), b)
+
+
+def gmres_dense(A: np.ndarray, b: np.ndarray, tol: float = 1e-10) -> np.ndarray:
+    """Full (unrestarted) GMRES on the dense matrix, Arnoldi with modified
+    Gram-Schmidt and a least-squares solve of the Hessenberg system."""
+    n = A.shape[0]
+    beta = np.linalg.norm(b)
+    V = np.zeros((n, min(n, 2000) + 1), complex)
+    Hm = np.zeros((V.shape[1], V.shape[1] - 1), complex)
+    V[:, 0] = b / beta
+    for j in range(V.shape[1] - 1):
+        w = A @ V[:, j]
+        for i in range(j + 1):
+            Hm[i, j] = np.vdot(V[:, i], w)
+            w = w - Hm[i, j] * V[:, i]
+        Hm[j + 1, j] = np.linalg.norm(w)
+        e1 = np.zeros(j + 2, complex)
+        e1[0] = beta
+        y, *_ = np.linalg.lstsq(Hm[: j + 2, : j + 1], e1, rcond=None)
+        res = np.linalg.norm(Hm[: j + 2, : j + 1] @ y - e1) / beta
+        if res < tol or Hm[j + 1, j] == 0:
+            return V[:, : j + 1] @ y
+        V[:, j + 1] = w / Hm[j + 1, j]
+    return V[:, : V.shape[1] - 1] @ y
