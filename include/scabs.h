@@ -1,0 +1,143 @@
+/*
+ * scabs -- surface-conductive-absorber PMCHW solver for MI355X (gfx950).
+ *
+ * C ABI of the library.  The operation it implements is the Galerkin system
+ * A x = b of the paper's Appendix A (eq19): RWG currents x = [J^L, M^L,
+ * J_e^R, J_i^R, M^R] on closed dielectric surfaces, rows eq1/eq2 on edges
+ * without surface conductivity and eq3/eq13/eq14 on absorber edges (Sec. II),
+ * with the sigma-weighted terms tested at quadrature (target) points as in the
+ * fast-solver appendix.  The matrix is never formed: its product is applied
+ * with a precorrected FFT (grid projection, 3-D FFT convolution with the
+ * Helmholtz kernel of each medium, interpolation, near-pair corrections).
+ *
+ * Conventions
+ *  - exp(+j w t) time dependence, G = exp(-j k R) / (4 pi R) (Appendix A).
+ *  - eps0 = mu0 = 1; lengths in the caller's unit (the paper uses the
+ *    wavelength inside the guide).  k_l = omega sqrt(eps_l), Z_l = 1/sqrt(eps_l).
+ *  - Complex vectors are interleaved (re, im) doubles, length 2N.
+ *  - Every function returns SCABS_OK (0) or a negative SCABS_E_* code; no
+ *    exception crosses the ABI.  scabs_last_error() gives the message.
+ *  - Ownership: setters copy their inputs; the caller owns every buffer it
+ *    passes.  Vector arguments of scabs_rhs_dipole, scabs_matvec,
+ *    scabs_solve and scabs_gradient are DEVICE pointers on the context's
+ *    device; work is queued on the context's stream and completes before the
+ *    call returns.
+ *  - Not thread safe per context: calls on one context must not overlap.
+ */
+#ifndef SCABS_H
+#define SCABS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCABS_OK 0
+#define SCABS_E_ARG (-1)      /* invalid argument (null pointer, size, range) */
+#define SCABS_E_MESH (-2)     /* mesh is not a closed, outward, 2-manifold surface */
+#define SCABS_E_STATE (-3)    /* call out of order (e.g. matvec before build) */
+#define SCABS_E_HIP (-4)      /* HIP runtime error */
+#define SCABS_E_OOM (-5)      /* device allocation failed */
+#define SCABS_E_NOCONV (-6)   /* iterative solve did not reach the tolerance */
+#define SCABS_E_NAN (-7)      /* non-finite value in an input vector */
+
+#define SCABS_FP64 0          /* every step in complex FP64 */
+#define SCABS_FP32 1          /* projection, FFT convolution, near field in complex FP32 */
+#define SCABS_MIXED 2         /* solve: FP32 inner GMRES inside FP64 iterative refinement */
+
+typedef struct scabs_ctx scabs_ctx;
+
+typedef struct {
+  double h;        /* projection-grid spacing (> 0) */
+  double r_near;   /* triangle pairs whose centroids are closer than r_near are
+                      corrected to the exact Galerkin interaction; must exceed
+                      the singular-pair radius (kappa_s * (rho_T + rho_T')) */
+  double kappa_s;  /* singularity subtraction is used for pairs with centroid
+                      distance < kappa_s * (rho_T + rho_T'), rho = largest
+                      centroid-vertex distance; <= 0 selects 1.37 */
+  int device;      /* HIP device ordinal */
+  void *stream;    /* hipStream_t; NULL = a stream created by the library */
+} scabs_opts;
+
+typedef struct {
+  int64_t N, NL, NR;       /* unknowns: N = 2 NL + 3 NR (Appendix A) */
+  int64_t n_edges, n_tris, n_points, n_bodies;
+  int64_t n_near_pairs;    /* triangle pairs in the near list */
+  int64_t nnz_near;        /* edge pairs in the near correction */
+  int64_t grid_phys[3];    /* exterior grid, physical node counts */
+  int64_t grid_fft[3];     /* exterior grid, FFT sizes */
+  int64_t device_bytes;    /* device memory held by the context */
+} scabs_info_t;
+
+typedef struct {
+  int status;              /* SCABS_OK or SCABS_E_NOCONV */
+  int outer_iters;         /* refinement steps (MIXED) or restart cycles (FP64) */
+  int inner_iters;         /* total Arnoldi steps */
+  int matvecs64, matvecs32;
+  double rel_residual;     /* final ||b - A x|| / ||b|| with the FP64 operator */
+} scabs_solve_info;
+
+/* Create a context on opts->device.  *out receives the handle. */
+int scabs_create(scabs_ctx **out, const scabs_opts *opts);
+
+/* Surface triangulation (host arrays, copied): verts[3 nv], tris[3 nt]
+ * (counter-clockwise seen from outside, so normals point into the exterior
+ * medium, eq6-eq9), body[nt] (0-based body index; interior operators couple
+ * triangles of the same body only).  Validated at scabs_build. */
+int scabs_set_mesh(scabs_ctx *c, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                   const int32_t *body);
+
+/* Media: angular frequency omega and relative permittivities of the exterior
+ * and of every body's interior (mu = 1). */
+int scabs_set_media(scabs_ctx *c, double omega, double eps_out, double eps_in);
+
+/* Surface conductivity (Sec. IV, eq60): sigma = sum over absorbers of
+ * sigma0 * u(s), s = dir * (x_axis - x0) / length, u = 0 for s < 0, s held at
+ * 1 beyond the absorber end.  Monomial: u = s^degree.  Piecewise linear: u is
+ * the hat-function interpolant of ctrl[0..n-1] at s_k = k / (n - 1).
+ * sigma is in units of 1/Z0.  An edge is an absorber (R) edge when sigma > 0
+ * at a quadrature point of either of its triangles. */
+int scabs_sigma_clear(scabs_ctx *c);
+int scabs_sigma_add_monomial(scabs_ctx *c, int axis, double x0, double length, int dir, int degree,
+                             double sigma0);
+int scabs_sigma_add_pwl(scabs_ctx *c, int axis, double x0, double length, int dir, int n, const double *ctrl);
+
+/* Build everything the products need: RWG edges, quadrature points, unknown
+ * layout, grids, near list, exact and grid near-pair interactions (FP64 on the
+ * device).  Must be called again after any setter. */
+int scabs_build(scabs_ctx *c);
+
+int scabs_info(const scabs_ctx *c, scabs_info_t *info);
+
+/* Host copies of the layout: is_r[n_edges] (1 for absorber edges), idx[n_edges]
+ * (index of the edge within its L or R block).  Either pointer may be NULL. */
+int scabs_layout(const scabs_ctx *c, int32_t *is_r, int32_t *idx);
+
+/* Right-hand side of an electric dipole (current moment p = I l, complex
+ * moment[6] = re/im pairs) at pos inside body `body`; the incident field is
+ * that of the dipole in the interior medium and vanishes on other bodies
+ * (Sec. II).  b: device, 2N doubles. */
+int scabs_rhs_dipole(scabs_ctx *c, const double pos[3], const double moment[6], int body, double *b);
+
+/* y = A x for nrhs vectors stored one after another (device, 2N doubles
+ * each).  prec: SCABS_FP64 or SCABS_FP32 (inputs and outputs stay FP64). */
+int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
+
+/* Solve A x = b (device vectors, nrhs of them).  x holds the initial guess
+ * on entry.  mode: SCABS_FP64 (restarted GMRES on the FP64 operator) or
+ * SCABS_MIXED (FP64 refinement around FP32-operator GMRES).  Orthogonalisation
+ * (two-pass classical Gram-Schmidt) and the Hessenberg least squares are FP64.
+ * tol: relative residual with the FP64 operator.  info may be NULL.
+ * Returns SCABS_E_NOCONV (x holds the last iterate) if max_iter Arnoldi
+ * steps do not reach tol. */
+int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
+                int mode, scabs_solve_info *info);
+
+const char *scabs_last_error(const scabs_ctx *c);
+void scabs_destroy(scabs_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

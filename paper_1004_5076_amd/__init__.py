@@ -1,0 +1,232 @@
+"""Python binding of libscabs (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch provides device memory and
+the stream.  The library must be built first (``__graft_entry__.build()`` or
+``python paper_1004_5076_amd/build.py``); importing works without it, but
+every call that needs it raises ``RuntimeError`` -- there is no CPU fallback.
+
+Method names mirror the C ABI in include/scabs.h (``scabs_<name>``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscabs.so")
+
+SCABS_OK = 0
+SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCONV, SCABS_E_NAN = -1, -2, -3, -4, -5, -6, -7
+SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
+EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
+            "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
+            "scabs_solve", "scabs_last_error", "scabs_destroy"]
+
+
+class ScabsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"scabs error {code}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("h", C.c_double), ("r_near", C.c_double), ("kappa_s", C.c_double), ("device", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("NL", C.c_int64), ("NR", C.c_int64), ("n_edges", C.c_int64),
+                ("n_tris", C.c_int64), ("n_points", C.c_int64), ("n_bodies", C.c_int64),
+                ("n_near_pairs", C.c_int64), ("nnz_near", C.c_int64), ("grid_phys", C.c_int64 * 3),
+                ("grid_fft", C.c_int64 * 3), ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["grid_phys"] = list(self.grid_phys)
+        d["grid_fft"] = list(self.grid_fft)
+        return d
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int), ("matvecs64", C.c_int),
+                ("matvecs32", C.c_int), ("rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libscabs.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    L.scabs_create.argtypes = [C.POINTER(P), C.POINTER(Opts)]
+    L.scabs_set_mesh.argtypes = [P, dp, C.c_int64, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int32)]
+    L.scabs_set_media.argtypes = [P, C.c_double, C.c_double, C.c_double]
+    L.scabs_sigma_clear.argtypes = [P]
+    L.scabs_sigma_add_monomial.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double]
+    L.scabs_sigma_add_pwl.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+    L.scabs_build.argtypes = [P]
+    L.scabs_info.argtypes = [P, C.POINTER(Info)]
+    L.scabs_layout.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.scabs_rhs_dipole.argtypes = [P, dp, dp, C.c_int, P]
+    L.scabs_matvec.argtypes = [P, P, P, C.c_int, C.c_int]
+    L.scabs_solve.argtypes = [P, P, P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(SolveInfo)]
+    L.scabs_last_error.restype = C.c_char_p
+    L.scabs_last_error.argtypes = [P]
+    L.scabs_destroy.argtypes = [P]
+    _lib = L
+    return L
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class Context:
+    """One library context: a mesh, media, conductivity profile and grid."""
+
+    def __init__(self, h: float, r_near: float, kappa_s: float = 1.37, device: int = 0, stream=None):
+        import torch
+        L = load()
+        self._L = L
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        o = Opts(h, r_near, kappa_s, device, C.c_void_p(stream.cuda_stream))
+        self._c = C.c_void_p()
+        self._check(L.scabs_create(C.byref(self._c), C.byref(o)))
+        self.N = None
+
+    def _check(self, rc: int):
+        if rc != SCABS_OK:
+            msg = self._L.scabs_last_error(self._c).decode() if getattr(self, "_c", None) else ""
+            raise ScabsError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_c", None) and self._c.value:
+            self._L.scabs_destroy(self._c)
+            self._c = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setters (host data, copied) ------------------------------------------
+    def set_mesh(self, verts, tris, body=None):
+        v, vp = _f64(verts)
+        t, tp = _i32(tris)
+        b, bp = _i32(np.zeros(t.shape[0]) if body is None else body)
+        self._check(self._L.scabs_set_mesh(self._c, vp, v.shape[0], tp, t.shape[0], bp))
+
+    def set_media(self, omega: float, eps_out: float, eps_in: float):
+        self._check(self._L.scabs_set_media(self._c, omega, eps_out, eps_in))
+
+    def sigma_clear(self):
+        self._check(self._L.scabs_sigma_clear(self._c))
+
+    def sigma_add_monomial(self, axis, x0, length, direction, degree, sigma0):
+        self._check(self._L.scabs_sigma_add_monomial(self._c, axis, x0, length, direction, degree, sigma0))
+
+    def sigma_add_pwl(self, axis, x0, length, direction, ctrl):
+        c, cp = _f64(ctrl)
+        self._check(self._L.scabs_sigma_add_pwl(self._c, axis, x0, length, direction, c.shape[0], cp))
+
+    def set_sigma(self, ends: Iterable):
+        self.sigma_clear()
+        for e in ends:
+            if getattr(e, "ctrl", None) is not None:
+                self.sigma_add_pwl(e.axis, e.x0, e.length, e.direction, e.ctrl)
+            else:
+                self.sigma_add_monomial(e.axis, e.x0, e.length, e.direction, e.degree, e.sigma0)
+
+    def build(self):
+        self._check(self._L.scabs_build(self._c))
+        self.N = self.info()["N"]
+
+    # -- queries ----------------------------------------------------------------
+    def info(self) -> dict:
+        i = Info()
+        self._check(self._L.scabs_info(self._c, C.byref(i)))
+        return i.as_dict()
+
+    def layout(self):
+        ne = self.info()["n_edges"]
+        isr = np.zeros(ne, np.int32)
+        idx = np.zeros(ne, np.int32)
+        self._check(self._L.scabs_layout(self._c, isr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         idx.ctypes.data_as(C.POINTER(C.c_int32))))
+        return isr, idx
+
+    # -- device operations --------------------------------------------------------
+    def _dev(self, t, nrhs_ok=True):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+            raise TypeError("expected a contiguous complex128 CUDA tensor")
+        if t.shape[-1] != self.N:
+            raise ValueError(f"last dimension must be N={self.N}")
+        return t
+
+    def rhs_dipole(self, pos, moment, body: int = 0):
+        import torch
+        b = torch.empty(self.N, dtype=torch.complex128, device=self.device)
+        p, pp = _f64(pos)
+        m = np.asarray(moment, dtype=np.complex128)
+        mm, mp = _f64(np.stack([m.real, m.imag], axis=1).ravel())
+        self._check(self._L.scabs_rhs_dipole(self._c, pp, mp, int(body), C.c_void_p(b.data_ptr())))
+        return b
+
+    def matvec(self, x, prec: int = SCABS_FP64):
+        import torch
+        x = self._dev(x)
+        y = torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        self._check(self._L.scabs_matvec(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, prec))
+        return y
+
+    def solve(self, b, x0=None, tol: float = 1e-6, max_iter: int = 2000, restart: int = 60,
+              mode: int = SCABS_MIXED, raise_on_noconv: bool = False):
+        import torch
+        b = self._dev(b)
+        x = torch.zeros_like(b) if x0 is None else self._dev(x0).clone()
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        infos = (SolveInfo * nrhs)()
+        rc = self._L.scabs_solve(self._c, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, tol, max_iter,
+                                 restart, mode, infos)
+        if rc != SCABS_OK and (rc != SCABS_E_NOCONV or raise_on_noconv):
+            self._check(rc)
+        out = [infos[k].as_dict() for k in range(nrhs)]
+        return x, (out[0] if b.dim() == 1 else out)
+
+
+def context_for(workload, device: int = 0, kappa_s: float = 1.37, h: Optional[float] = None,
+                r_near: Optional[float] = None) -> Context:
+    """Build a context from a synth.Workload-like object."""
+    ctx = Context(workload.h if h is None else h, workload.r_near if r_near is None else r_near, kappa_s, device)
+    m = workload.mesh
+    ctx.set_mesh(m.verts, m.tris, m.body)
+    ctx.set_media(workload.omega, workload.eps_out, workload.eps_in)
+    ctx.set_sigma(workload.sigma)
+    ctx.build()
+    return ctx

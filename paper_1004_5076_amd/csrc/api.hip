@@ -1,0 +1,823 @@
+// C ABI of the library: context, setup orchestration, products and solves.
+#include <algorithm>
+#include <complex>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace scabs {
+void kr_dots(const cx<double> *V, int64_t ldv, int jn, const cx<double> *w, int64_t N, cx<double> *part,
+             cx<double> *out, int accumulate, hipStream_t s);
+void kr_update(cx<double> *w, const cx<double> *V, int64_t ldv, int jn, const cx<double> *c, int64_t N, double sgn,
+               hipStream_t s);
+void kr_norm(const cx<double> *w, int64_t N, double *part, double *out, hipStream_t s);
+void kr_scale(cx<double> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s);
+void kr_residual(const cx<double> *b, cx<double> *r, int64_t N, hipStream_t s);
+void kr_axpy(cx<double> *x, const cx<double> *d, int64_t N, hipStream_t s);
+void kr_finite(const double *v, int64_t n, int *bad, hipStream_t s);
+}  // namespace scabs
+
+using namespace scabs;
+
+namespace {
+
+struct HipError {
+  hipError_t e;
+  const char *what;
+};
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) throw HipError{_e, #x};   \
+  } while (0)
+
+// owned device allocation list
+struct DevMem {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  template <typename T> T *alloc(size_t n) {
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return (T *)p;
+  }
+  template <typename T> T *upload(const std::vector<T> &v) {
+    T *p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  void release() {
+    for (void *p : ptrs) hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+template <typename T> struct PrecState {
+  PointRec<T> *pts = nullptr;
+  TriRec<T> *tris = nullptr;
+  cx<T> *V4 = nullptr, *S4 = nullptr;
+  cx<T> *src = nullptr, *tri_out = nullptr;
+  std::vector<DevGrid<T>> grids;   // host copies holding device pointers
+  DevGrid<T> *grids_dev = nullptr;
+  Slab *slabs = nullptr;
+  int nslabs = 0;
+  size_t proj_lds = 0;
+  DevOperator<T> op;
+  T inv_h = 0;
+};
+
+}  // namespace
+
+struct scabs_ctx {
+  scabs_opts opts{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // inputs
+  std::vector<double> verts;
+  std::vector<int> tris, body;
+  double omega = 0, eps_out = 1, eps_in = 1;
+  std::vector<SigmaEnd> ends;
+  bool built = false;
+  // host state
+  Geometry geo;
+  Layout lay;
+  std::vector<GridDesc> grids;
+  std::vector<int> anchor;
+  std::vector<double> u;
+  NearList near;
+  double k_e = 0, k_i = 0, Z_e = 1, Z_i = 1;
+  // device state
+  DevMem mem;
+  EdgeRec *edges = nullptr;
+  int *plist = nullptr;
+  int64_t *rowptr = nullptr;
+  int *col = nullptr;
+  int64_t nnz = 0;
+  double *qp64 = nullptr;
+  int *body_dev = nullptr;
+  PrecState<float> p32;
+  PrecState<double> p64;
+  // solver workspace (grown on demand)
+  DevMem work;
+  int work_restart = -1;
+  int64_t work_N = -1;
+  cx<double> *V = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *hcol = nullptr, *part = nullptr;
+  double *nrm = nullptr, *nrm_part = nullptr;
+  int *flag = nullptr;
+};
+
+static int fail(scabs_ctx *c, int code, const std::string &m) {
+  if (c) c->err = m;
+  return code;
+}
+
+static int hip_fail(scabs_ctx *c, const HipError &e) {
+  return fail(c, SCABS_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+}
+
+// ---------------------------------------------------------------------------
+// build
+// ---------------------------------------------------------------------------
+template <typename T>
+static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<double>> &tw_host,
+                            const std::vector<int> &tw_off, const std::vector<cx<double> *> &ghat64,
+                            const std::vector<cx<float> *> &ghat32, const std::vector<int> &plist_off,
+                            const std::vector<std::vector<int>> &plane_start, cx<T> *V4, cx<T> *S4) {
+  const Geometry &g = c->geo;
+  const Layout &L = c->lay;
+  const size_t np = (size_t)g.nt * NQ;
+  // points
+  std::vector<PointRec<T>> pts(np);
+  const GridDesc &ext = c->grids[0];
+  for (int Tt = 0; Tt < g.nt; Tt++) {
+    const double A = g.area[Tt];
+    for (int q = 0; q < NQ; q++) {
+      size_t ip = (size_t)Tt * NQ + q;
+      PointRec<T> &P0 = pts[ip];
+      for (int j = 0; j < 3; j++) {
+        int e = g.tedge[3 * Tt + j];
+        double cf = g.tsign[3 * Tt + j] * g.elen[e] / (2.0 * A);
+        const double *vj = &g.v[3 * g.t[3 * Tt + j]];
+        for (int a = 0; a < 3; a++) P0.f[3 * j + a] = (T)(cf * (g.qp[3 * ip + a] - vj[a]));
+      }
+      P0.w = (T)g.qw[ip];
+      P0.sigma = (T)L.sigma[ip];
+      for (int a = 0; a < 3; a++) P0.u[a] = (T)c->u[3 * ip + a];
+      P0.anc = pack_anchor(c->anchor[3 * ip] - ext.o[0], c->anchor[3 * ip + 1] - ext.o[1], c->anchor[3 * ip + 2] - ext.o[2]);
+      P0.tri = Tt;
+    }
+  }
+  P.pts = c->mem.upload(pts);
+  std::vector<TriRec<T>> tr(g.nt);
+  for (int Tt = 0; Tt < g.nt; Tt++) {
+    TriRec<T> &r = tr[Tt];
+    for (int a = 0; a < 3; a++) r.nrm[a] = (T)g.nrm[3 * Tt + a];
+    int sig = 0;
+    for (int j = 0; j < 3; j++) {
+      int e = g.tedge[3 * Tt + j];
+      r.div[j] = (T)(g.tsign[3 * Tt + j] * g.elen[e] / g.area[Tt]);
+      r.edge[j] = e;
+    }
+    for (int q = 0; q < NQ; q++) sig |= L.sigma[(size_t)Tt * NQ + q] > 0;
+    r.body = g.body[Tt];
+    r.flags = sig;
+    r.pad = 0;
+  }
+  P.tris = c->mem.upload(tr);
+  P.src = c->mem.alloc<cx<T>>((size_t)g.ne * 3);
+  P.tri_out = c->mem.alloc<cx<T>>((size_t)g.nt * 9);
+  P.V4 = V4;
+  P.S4 = S4;
+  // grids
+  P.grids.clear();
+  std::vector<Slab> slabs;
+  size_t lds_max = 0;
+  for (size_t gi = 0; gi < c->grids.size(); gi++) {
+    const GridDesc &d = c->grids[gi];
+    DevGrid<T> G{};
+    G.which = d.which;
+    for (int a = 0; a < 3; a++) {
+      G.n[a] = d.n[a];
+      G.N[a] = d.N[a];
+      G.off[a] = d.o[a] - ext.o[a];
+    }
+    G.k = (T)d.k;
+    G.Z = (T)(d.which < 0 ? c->Z_e : c->Z_i);
+    size_t nphys = (size_t)d.n[0] * d.n[1] * d.n[2];
+    G.phys = c->mem.alloc<cx<T>>(8 * nphys);
+    G.spec = c->mem.alloc<cx<T>>(8 * (size_t)d.n[0] * d.N[1] * d.N[2]);
+    int twL = std::max(d.N[0], std::max(d.N[1], d.N[2]));
+    G.twL = twL;
+    std::vector<cx<T>> tw(twL / 2);
+    for (int j = 0; j < twL / 2; j++) tw[j] = {(T)tw_host[tw_off[gi] + j].x, (T)tw_host[tw_off[gi] + j].y};
+    G.tw = c->mem.upload(tw);
+    if (sizeof(T) == sizeof(double))
+      G.ghat = (const cx<T> *)ghat64[gi];
+    else
+      G.ghat = (const cx<T> *)ghat32[gi];
+    P.grids.push_back(G);
+    // projection slabs: LDS holds nx planes of 8 fields
+    size_t plane_bytes = 8 * sizeof(cx<T>) * (size_t)d.n[1] * d.n[2];
+    size_t budget = 60 * 1024;
+    if (plane_bytes > budget) throw std::string("a grid plane does not fit the projection LDS tile");
+    int nxs = (int)std::min<size_t>(budget / plane_bytes, (size_t)d.n[0]);
+    nxs = std::max(1, std::min(nxs, 8));
+    lds_max = std::max(lds_max, plane_bytes * nxs);
+    const std::vector<int> &ps = plane_start[gi];   // size n0 + 1, anchors sorted by x
+    for (int x0 = 0; x0 < d.n[0]; x0 += nxs) {
+      Slab s;
+      s.grid = (int)gi;
+      s.x0 = x0;
+      s.nx = std::min(nxs, d.n[0] - x0);
+      int lo = std::max(0, x0 - 1), hi = std::min(d.n[0], x0 + s.nx + 1);
+      s.p0 = plist_off[gi] + ps[lo];
+      s.p1 = plist_off[gi] + ps[hi];
+      slabs.push_back(s);
+    }
+  }
+  P.grids_dev = c->mem.upload(P.grids);
+  P.slabs = c->mem.upload(slabs);
+  P.nslabs = (int)slabs.size();
+  P.proj_lds = lds_max;
+  P.inv_h = (T)(1.0 / c->opts.h);
+  DevOperator<T> &op = P.op;
+  op.np = (int)np;
+  op.nt = g.nt;
+  op.ne = g.ne;
+  op.N = L.N;
+  op.k_e = (T)c->k_e;
+  op.k_i = (T)c->k_i;
+  op.Z_e = (T)c->Z_e;
+  op.Z_i = (T)c->Z_i;
+  op.pts = P.pts;
+  op.tris = P.tris;
+  op.edges = c->edges;
+  op.rowptr = c->rowptr;
+  op.col = c->col;
+  op.V4 = P.V4;
+  op.S4 = P.S4;
+  op.src = P.src;
+  op.tri_out = P.tri_out;
+}
+
+static int do_build(scabs_ctx *c) {
+  c->built = false;
+  c->mem.release();
+  c->work.release();
+  c->work_restart = -1;
+  c->work_N = -1;
+  if (c->verts.empty() || c->tris.empty()) return fail(c, SCABS_E_STATE, "mesh not set");
+  if (!(c->omega > 0)) return fail(c, SCABS_E_STATE, "media not set");
+  std::string e = build_geometry(c->verts, c->tris, c->body, c->geo);
+  if (!e.empty()) return fail(c, SCABS_E_MESH, e);
+  Geometry &g = c->geo;
+  eval_sigma(g, c->ends, c->lay.sigma);
+  build_layout(g, c->lay);
+  c->k_e = c->omega * std::sqrt(c->eps_out);
+  c->k_i = c->omega * std::sqrt(c->eps_in);
+  c->Z_e = 1.0 / std::sqrt(c->eps_out);
+  c->Z_i = 1.0 / std::sqrt(c->eps_in);
+  e = build_grids(g, c->opts.h, c->k_e, c->k_i, c->grids, c->anchor, c->u);
+  if (!e.empty()) return fail(c, SCABS_E_ARG, e);
+  e = build_near(g, c->opts.r_near, c->opts.kappa_s, c->near);
+  if (!e.empty()) return fail(c, SCABS_E_ARG, e);
+  const size_t np = (size_t)g.nt * NQ;
+  // test boxes must fit the setup kernel's LDS tile; kernel-table extent
+  std::vector<int> alo(3 * g.nt), ahi(3 * g.nt);
+  for (int T = 0; T < g.nt; T++)
+    for (int a = 0; a < 3; a++) {
+      int lo = 1 << 30, hi = -(1 << 30);
+      for (int q = 0; q < NQ; q++) {
+        int v = c->anchor[3 * ((size_t)T * NQ + q) + a];
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+      }
+      alo[3 * T + a] = lo;
+      ahi[3 * T + a] = hi;
+      if (hi - lo + 3 > 7) return fail(c, SCABS_E_ARG, "grid spacing too fine for the triangle size (stencil box > 7)");
+    }
+  int D = 0;
+  for (int T = 0; T < g.nt; T++)
+    for (int64_t p = c->near.tptr[T]; p < c->near.tptr[T + 1]; p++) {
+      int Tp = c->near.src[p];
+      for (int a = 0; a < 3; a++)
+        D = std::max(D, std::max(ahi[3 * T + a] - alo[3 * Tp + a], ahi[3 * Tp + a] - alo[3 * T + a]) + 2);
+    }
+  hipStream_t s = c->stream;
+  // ---- edges -----------------------------------------------------------------
+  const Layout &L = c->lay;
+  std::vector<EdgeRec> er(g.ne);
+  for (int n = 0; n < g.ne; n++) {
+    EdgeRec &r = er[n];
+    for (int sd = 0; sd < 2; sd++) {
+      int T = g.et[2 * n + sd];
+      r.tri[sd] = T;
+      r.loc[sd] = g.tedge[3 * T] == n ? 0 : (g.tedge[3 * T + 1] == n ? 1 : 2);
+    }
+    int id = L.eidx[n];
+    r.isR = L.isR[n];
+    if (!r.isR) {
+      r.row[0] = r.col[0] = id;
+      r.row[1] = r.col[1] = L.NL + id;
+      r.row[2] = r.col[2] = -1;
+    } else {
+      int b0 = 2 * L.NL;
+      r.row[0] = r.col[0] = b0 + id;
+      r.row[1] = r.col[1] = b0 + L.NR + id;
+      r.row[2] = r.col[2] = b0 + 2 * L.NR + id;
+    }
+    r.pad = 0;
+  }
+  c->edges = c->mem.upload(er);
+  c->rowptr = c->mem.upload(c->near.rowptr);
+  c->col = c->mem.upload(c->near.col);
+  c->nnz = c->near.rowptr[g.ne];
+  c->qp64 = c->mem.upload(g.qp);
+  c->body_dev = c->mem.upload(g.body);
+  // ---- point lists per grid, sorted by anchor x ------------------------------
+  std::vector<int> plist_all, plist_off;
+  std::vector<std::vector<int>> plane_start;
+  for (const GridDesc &d : c->grids) {
+    std::vector<int> pl;
+    for (int T = 0; T < g.nt; T++) {
+      if (d.which >= 0 && g.body[T] != d.which) continue;
+      for (int q = 0; q < NQ; q++) pl.push_back(T * NQ + q);
+    }
+    std::stable_sort(pl.begin(), pl.end(), [&](int a, int b) { return c->anchor[3 * a] < c->anchor[3 * b]; });
+    std::vector<int> ps(d.n[0] + 1, 0);
+    for (int p : pl) ps[c->anchor[3 * p] - d.o[0] + 1]++;
+    for (int x = 0; x < d.n[0]; x++) ps[x + 1] += ps[x];
+    plist_off.push_back((int)plist_all.size());
+    plist_all.insert(plist_all.end(), pl.begin(), pl.end());
+    plane_start.push_back(ps);
+  }
+  c->plist = c->mem.upload(plist_all);
+  // ---- twiddles and kernel spectra ---------------------------------------------
+  std::vector<cx<double>> tw_all;
+  std::vector<int> tw_off;
+  std::vector<cx<double> *> ghat64;
+  std::vector<cx<float> *> ghat32;
+  for (const GridDesc &d : c->grids) {
+    int twL = std::max(d.N[0], std::max(d.N[1], d.N[2]));
+    tw_off.push_back((int)tw_all.size());
+    for (int j = 0; j < twL / 2; j++) {
+      double a = -2.0 * PI * j / twL;
+      tw_all.push_back({std::cos(a), std::sin(a)});
+    }
+  }
+  for (size_t gi = 0; gi < c->grids.size(); gi++) {
+    const GridDesc &d = c->grids[gi];
+    int twL = std::max(d.N[0], std::max(d.N[1], d.N[2]));
+    std::vector<cx<double>> tw(tw_all.begin() + tw_off[gi], tw_all.begin() + tw_off[gi] + twL / 2);
+    cx<double> *tw64 = c->mem.upload(tw);
+    size_t oct = (size_t)(d.N[0] / 2 + 1) * (d.N[1] / 2 + 1) * (d.N[2] / 2 + 1);
+    cx<double> *g64 = c->mem.alloc<cx<double>>(oct);
+    cx<float> *g32 = c->mem.alloc<cx<float>>(oct);
+    HIPCHK(build_ghat(d, c->opts.h, tw64, twL, g64, g32, s));
+    ghat64.push_back(g64);
+    ghat32.push_back(g32);
+  }
+  // ---- near-pair blocks (FP64) and the edge-pair correction --------------------
+  {
+    DevMem tmp;
+    int64_t npairs = c->near.tptr[g.nt];
+    NearSetupArgs a{};
+    a.nt = g.nt;
+    a.h = c->opts.h;
+    a.k_e = c->k_e;
+    a.k_i = c->k_i;
+    a.v = tmp.upload(g.v);
+    a.t = tmp.upload(g.t);
+    a.body = c->body_dev;
+    a.tedge = tmp.upload(g.tedge);
+    a.tsign = tmp.upload(g.tsign);
+    a.elen = tmp.upload(g.elen);
+    a.area = tmp.upload(g.area);
+    a.nrm = tmp.upload(g.nrm);
+    a.qp = c->qp64;
+    a.qw = tmp.upload(g.qw);
+    a.sigma = tmp.upload(L.sigma);
+    a.anchor = tmp.upload(c->anchor);
+    a.u = tmp.upload(c->u);
+    a.tptr = tmp.upload(c->near.tptr);
+    a.src = tmp.upload(c->near.src);
+    a.sing = tmp.upload(c->near.sing);
+    a.D = D;
+    cx<double> *he = tmp.alloc<cx<double>>((size_t)(D + 1) * (D + 1) * (D + 1));
+    cx<double> *hi = tmp.alloc<cx<double>>((size_t)(D + 1) * (D + 1) * (D + 1));
+    build_htab(c->k_e, c->opts.h, D, he, s);
+    build_htab(c->k_i, c->opts.h, D, hi, s);
+    a.htab_e = he;
+    a.htab_i = hi;
+    a.blocks = tmp.alloc<cx<double>>((size_t)npairs * 72);
+    launch_near_setup(a, s);
+    HIPCHK(hipGetLastError());
+    cx<double> *V4 = c->mem.alloc<cx<double>>(4 * (size_t)c->nnz);
+    cx<double> *S4 = c->mem.alloc<cx<double>>(4 * (size_t)c->nnz);
+    cx<float> *V4f = c->mem.alloc<cx<float>>(4 * (size_t)c->nnz);
+    cx<float> *S4f = c->mem.alloc<cx<float>>(4 * (size_t)c->nnz);
+    int64_t *cptr = tmp.upload(c->near.cptr);
+    int *cpair = tmp.upload(c->near.cpair);
+    uint8_t *cij = tmp.upload(c->near.cij);
+    launch_near_assemble(c->nnz, cptr, cpair, cij, a.blocks, V4, S4, V4f, S4f, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    tmp.release();
+    build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, plist_off, plane_start, V4, S4);
+    build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, plist_off, plane_start, V4f, S4f);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  c->built = true;
+  return SCABS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// products
+// ---------------------------------------------------------------------------
+template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const double *x, double *y) {
+  hipStream_t s = c->stream;
+  launch_unpack(P.op, x, s);
+  launch_project(P.op, P.grids_dev, P.slabs, P.nslabs, c->plist, P.proj_lds, s);
+  for (const DevGrid<T> &g : P.grids) launch_conv(g, s);
+  launch_interp_test(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, s);
+  launch_near_rows(P.op, y, s);
+}
+
+static void matvec_one(scabs_ctx *c, const double *x, double *y, int prec) {
+  if (prec == SCABS_FP32)
+    apply(c, c->p32, x, y);
+  else
+    apply(c, c->p64, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (restarted; two-pass classical Gram-Schmidt and Givens rotations in
+// FP64; one host synchronisation per Arnoldi step)
+// ---------------------------------------------------------------------------
+static void ensure_work(scabs_ctx *c, int restart) {
+  int64_t N = c->lay.N;
+  if (c->work_restart >= restart && c->work_N == N) return;
+  c->work.release();
+  c->V = c->work.alloc<cx<double>>((size_t)(restart + 1) * N);
+  c->w = c->work.alloc<cx<double>>(N);
+  c->r = c->work.alloc<cx<double>>(N);
+  c->d = c->work.alloc<cx<double>>(N);
+  c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2));
+  c->part = c->work.alloc<cx<double>>((size_t)256 * (restart + 2));
+  c->nrm = c->work.alloc<double>(4);
+  c->nrm_part = c->work.alloc<double>(1024);
+  c->flag = c->work.alloc<int>(1);
+  c->work_restart = restart;
+  c->work_N = N;
+}
+
+static double dev_norm(scabs_ctx *c, const cx<double> *v) {
+  double n;
+  kr_norm(v, c->lay.N, c->nrm_part, c->nrm + 1, c->stream);
+  HIPCHK(hipMemcpyAsync(&n, c->nrm + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return n;
+}
+
+struct GmresResult {
+  int iters = 0;
+  double rel = 1.0;      // true relative residual w.r.t. the operator used
+  bool converged = false;
+};
+
+// Solve A_prec sol = rhs from sol = 0 to ||rhs - A sol|| <= tol ||rhs||.
+static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, int prec, double tol, int max_iter,
+                         int restart, int &nmv) {
+  typedef std::complex<double> zd;
+  hipStream_t s = c->stream;
+  const int64_t N = c->lay.N;
+  GmresResult res;
+  HIPCHK(hipMemsetAsync(sol, 0, sizeof(cx<double>) * N, s));
+  HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+  const double bn = dev_norm(c, rhs);
+  if (bn == 0) {
+    res.rel = 0;
+    res.converged = true;
+    return res;
+  }
+  const int m = restart;
+  std::vector<zd> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+  std::vector<cx<double>> hb(2 * (m + 2));
+  cx<double> *h1 = c->hcol, *h2 = c->hcol + (m + 2);
+  double beta = bn;
+  while (true) {
+    res.rel = beta / bn;
+    if (res.rel <= tol) {
+      res.converged = true;
+      break;
+    }
+    if (res.iters >= max_iter) break;
+    kr_norm(c->r, N, c->nrm_part, c->nrm, s);
+    kr_scale(c->V, c->r, c->nrm, N, s);
+    std::fill(g.begin(), g.end(), zd(0));
+    g[0] = beta;
+    int j = 0;
+    while (j < m && res.iters < max_iter) {
+      cx<double> *vj = c->V + (size_t)j * N;
+      matvec_one(c, (const double *)vj, (double *)c->w, prec);
+      nmv++;
+      kr_dots(c->V, N, j + 1, c->w, N, c->part, h1, 0, s);
+      kr_update(c->w, c->V, N, j + 1, h1, N, -1.0, s);
+      kr_dots(c->V, N, j + 1, c->w, N, c->part, h2, 0, s);
+      kr_update(c->w, c->V, N, j + 1, h2, N, -1.0, s);
+      kr_norm(c->w, N, c->nrm_part, c->nrm, s);
+      kr_scale(c->V + (size_t)(j + 1) * N, c->w, c->nrm, N, s);
+      double hn;
+      HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * 2 * (m + 2), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hn, c->nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      zd *col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; i++) col[i] = zd(hb[i].x + hb[m + 2 + i].x, hb[i].y + hb[m + 2 + i].y);
+      col[j + 1] = hn;
+      for (int i = 0; i < j; i++) {
+        zd a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -std::conj(sn[i]) * a + cs[i] * b;
+      }
+      double an = std::abs(col[j]), bnrm = std::abs(col[j + 1]);
+      if (bnrm == 0) {
+        cs[j] = 1;
+        sn[j] = 0;
+      } else if (an == 0) {
+        cs[j] = 0;
+        sn[j] = std::conj(col[j + 1]) / bnrm;
+      } else {
+        double t = std::hypot(an, bnrm);
+        cs[j] = an / t;
+        sn[j] = (col[j] / an) * std::conj(col[j + 1]) / t;
+      }
+      col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
+      col[j + 1] = 0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      j++;
+      res.iters++;
+      if (std::abs(g[j]) <= tol * bn || hn == 0) break;
+    }
+    // y = H^-1 g (upper triangular), sol += V y
+    for (int i = j - 1; i >= 0; i--) {
+      zd acc = g[i];
+      for (int k = i + 1; k < j; k++) acc -= H[(size_t)k * (m + 1) + i] * y[k];
+      y[i] = acc / H[(size_t)i * (m + 1) + i];
+    }
+    std::vector<cx<double>> yb(j);
+    for (int i = 0; i < j; i++) yb[i] = {y[i].real(), y[i].imag()};
+    HIPCHK(hipMemcpyAsync(h1, yb.data(), sizeof(cx<double>) * j, hipMemcpyHostToDevice, s));
+    kr_update(sol, c->V, N, j, h1, N, +1.0, s);
+    // true residual
+    matvec_one(c, (const double *)sol, (double *)c->w, prec);
+    nmv++;
+    HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+    kr_residual((const cx<double> *)c->r, c->w, N, s);   // w = rhs - A sol
+    HIPCHK(hipMemcpyAsync(c->r, c->w, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+    beta = dev_norm(c, c->r);
+  }
+  return res;
+}
+
+// FP64 iterative refinement around GMRES on the operator of `inner` precision.
+static int solve_one(scabs_ctx *c, const cx<double> *b, cx<double> *x, double tol, int max_iter, int restart, int mode,
+                     scabs_solve_info *info) {
+  hipStream_t s = c->stream;
+  const int64_t N = c->lay.N;
+  ensure_work(c, restart);
+  scabs_solve_info loc{};
+  const int inner_prec = mode == SCABS_MIXED ? SCABS_FP32 : SCABS_FP64;
+  const double floor_tol = mode == SCABS_MIXED ? 1e-5 : 1e-14;
+  const double bn = dev_norm(c, b);
+  cx<double> *r64 = c->d;   // refinement residual, reused as correction below
+  std::vector<cx<double>> dummy;
+  cx<double> *corr = nullptr;
+  DevMem tmp;
+  corr = tmp.alloc<cx<double>>(N);
+  cx<double> *rr = tmp.alloc<cx<double>>(N);
+  (void)r64;
+  double rel = 1.0;
+  int status = SCABS_E_NOCONV;
+  for (int outer = 0; outer < 50; outer++) {
+    matvec_one(c, (const double *)x, (double *)rr, SCABS_FP64);
+    loc.matvecs64++;
+    kr_residual(b, rr, N, s);   // rr = b - A x
+    double rn = dev_norm(c, rr);
+    rel = bn > 0 ? rn / bn : 0.0;
+    if (rel <= tol) {
+      status = SCABS_OK;
+      break;
+    }
+    if (loc.inner_iters >= max_iter) break;
+    double tin = std::max(0.5 * tol / rel, floor_tol);
+    int nmv = 0;
+    GmresResult g = gmres(c, rr, corr, inner_prec, tin, max_iter - loc.inner_iters, restart, nmv);
+    if (inner_prec == SCABS_FP32)
+      loc.matvecs32 += nmv;
+    else
+      loc.matvecs64 += nmv;
+    loc.inner_iters += g.iters;
+    loc.outer_iters++;
+    kr_axpy(x, corr, N, s);
+    if (g.iters == 0 && !g.converged) break;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  tmp.release();
+  loc.rel_residual = rel;
+  loc.status = status;
+  if (info) *info = loc;
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int scabs_create(scabs_ctx **out, const scabs_opts *o) {
+  if (!out || !o) return SCABS_E_ARG;
+  *out = nullptr;
+  if (!(o->h > 0) || !(o->r_near > 0)) return SCABS_E_ARG;
+  std::unique_ptr<scabs_ctx> c(new scabs_ctx());
+  c->opts = *o;
+  if (!(c->opts.kappa_s > 0)) c->opts.kappa_s = 1.37;
+  if (hipSetDevice(o->device) != hipSuccess) return SCABS_E_HIP;
+  if (o->stream) {
+    c->stream = (hipStream_t)o->stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return SCABS_E_HIP;
+    c->own_stream = true;
+  }
+  *out = c.release();
+  return SCABS_OK;
+}
+
+int scabs_set_mesh(scabs_ctx *c, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                   const int32_t *body) {
+  if (!c) return SCABS_E_ARG;
+  if (!verts || !tris || nv <= 0 || nt <= 0 || nt > (1 << 27)) return fail(c, SCABS_E_ARG, "bad mesh arguments");
+  c->verts.assign(verts, verts + 3 * nv);
+  c->tris.assign(tris, tris + 3 * nt);
+  if (body)
+    c->body.assign(body, body + nt);
+  else
+    c->body.assign(nt, 0);
+  c->built = false;
+  return SCABS_OK;
+}
+
+int scabs_set_media(scabs_ctx *c, double omega, double eps_out, double eps_in) {
+  if (!c) return SCABS_E_ARG;
+  if (!(omega > 0) || !(eps_out > 0) || !(eps_in > 0)) return fail(c, SCABS_E_ARG, "media must be positive");
+  c->omega = omega;
+  c->eps_out = eps_out;
+  c->eps_in = eps_in;
+  c->built = false;
+  return SCABS_OK;
+}
+
+int scabs_sigma_clear(scabs_ctx *c) {
+  if (!c) return SCABS_E_ARG;
+  c->ends.clear();
+  c->built = false;
+  return SCABS_OK;
+}
+
+int scabs_sigma_add_monomial(scabs_ctx *c, int axis, double x0, double length, int dir, int degree,
+                             double sigma0) {
+  if (!c) return SCABS_E_ARG;
+  if (axis < 0 || axis > 2 || !(length > 0) || (dir != 1 && dir != -1) || degree < 0 || !(sigma0 >= 0))
+    return fail(c, SCABS_E_ARG, "bad absorber profile");
+  SigmaEnd e{axis, dir, degree, x0, length, sigma0, {}};
+  c->ends.push_back(e);
+  c->built = false;
+  return SCABS_OK;
+}
+
+int scabs_sigma_add_pwl(scabs_ctx *c, int axis, double x0, double length, int dir, int n, const double *ctrl) {
+  if (!c) return SCABS_E_ARG;
+  if (axis < 0 || axis > 2 || !(length > 0) || (dir != 1 && dir != -1) || n < 2 || !ctrl)
+    return fail(c, SCABS_E_ARG, "bad absorber profile");
+  for (int k = 0; k < n; k++)
+    if (!(ctrl[k] >= 0)) return fail(c, SCABS_E_ARG, "conductivity control values must be >= 0");
+  SigmaEnd e{axis, dir, 1, x0, length, 1.0, std::vector<double>(ctrl, ctrl + n)};
+  c->ends.push_back(e);
+  c->built = false;
+  return SCABS_OK;
+}
+
+int scabs_build(scabs_ctx *c) {
+  if (!c) return SCABS_E_ARG;
+  try {
+    HIPCHK(hipSetDevice(c->opts.device));
+    return do_build(c);
+  } catch (const HipError &e) {
+    c->mem.release();
+    if (e.e == hipErrorOutOfMemory) return fail(c, SCABS_E_OOM, "device allocation failed");
+    return hip_fail(c, e);
+  } catch (const std::string &m) {
+    c->mem.release();
+    return fail(c, SCABS_E_ARG, m);
+  } catch (const std::bad_alloc &) {
+    c->mem.release();
+    return fail(c, SCABS_E_OOM, "host allocation failed");
+  }
+}
+
+int scabs_info(const scabs_ctx *c, scabs_info_t *info) {
+  if (!c || !info) return SCABS_E_ARG;
+  if (!c->built) return SCABS_E_STATE;
+  memset(info, 0, sizeof(*info));
+  info->N = c->lay.N;
+  info->NL = c->lay.NL;
+  info->NR = c->lay.NR;
+  info->n_edges = c->geo.ne;
+  info->n_tris = c->geo.nt;
+  info->n_points = (int64_t)c->geo.nt * NQ;
+  info->n_bodies = c->geo.nbody;
+  info->n_near_pairs = c->near.tptr[c->geo.nt];
+  info->nnz_near = c->nnz;
+  for (int a = 0; a < 3; a++) {
+    info->grid_phys[a] = c->grids[0].n[a];
+    info->grid_fft[a] = c->grids[0].N[a];
+  }
+  info->device_bytes = (int64_t)(c->mem.bytes + c->work.bytes);
+  return SCABS_OK;
+}
+
+int scabs_layout(const scabs_ctx *c, int32_t *is_r, int32_t *idx) {
+  if (!c) return SCABS_E_ARG;
+  if (!c->built) return SCABS_E_STATE;
+  for (int e = 0; e < c->geo.ne; e++) {
+    if (is_r) is_r[e] = c->lay.isR[e];
+    if (idx) idx[e] = c->lay.eidx[e];
+  }
+  return SCABS_OK;
+}
+
+int scabs_rhs_dipole(scabs_ctx *c, const double pos[3], const double moment[6], int body, double *b) {
+  if (!c || !pos || !moment || !b) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (body < 0 || body >= c->geo.nbody) return fail(c, SCABS_E_ARG, "body index out of range");
+  try {
+    HIPCHK(hipMemsetAsync(b, 0, sizeof(double) * 2 * c->lay.N, c->stream));
+    launch_rhs_dipole(c->geo.nt, c->qp64, nullptr, nullptr, c->body_dev, c->p64.tris, c->p64.pts, c->edges, c->k_i,
+                      c->Z_i, pos, moment, body, b, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
+}
+
+int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
+  if (!c || !x || !y || nrhs < 1) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (prec != SCABS_FP32 && prec != SCABS_FP64) return fail(c, SCABS_E_ARG, "prec must be SCABS_FP32 or SCABS_FP64");
+  try {
+    const size_t stride = 2 * (size_t)c->lay.N;
+    for (int k = 0; k < nrhs; k++) matvec_one(c, x + k * stride, y + k * stride, prec);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
+}
+
+int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart, int mode,
+                scabs_solve_info *info) {
+  if (!c || !b || !x || nrhs < 1 || !(tol > 0) || max_iter < 1 || restart < 1) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (mode != SCABS_FP64 && mode != SCABS_MIXED) return fail(c, SCABS_E_ARG, "mode must be SCABS_FP64 or SCABS_MIXED");
+  try {
+    const size_t stride = 2 * (size_t)c->lay.N;
+    ensure_work(c, restart);
+    HIPCHK(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    kr_finite(b, (int64_t)stride * nrhs, c->flag, c->stream);
+    kr_finite(x, (int64_t)stride * nrhs, c->flag, c->stream);
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, SCABS_E_NAN, "non-finite value in b or x");
+    int worst = SCABS_OK;
+    for (int k = 0; k < nrhs; k++) {
+      scabs_solve_info loc{};
+      int st = solve_one(c, (const cx<double> *)(b + k * stride), (cx<double> *)(x + k * stride), tol, max_iter, restart,
+                         mode, &loc);
+      if (info) info[k] = loc;
+      if (st != SCABS_OK) worst = st;
+    }
+    if (worst != SCABS_OK) c->err = "GMRES did not reach the tolerance within max_iter";
+    return worst;
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+}
+
+const char *scabs_last_error(const scabs_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void scabs_destroy(scabs_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->opts.device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  c->work.release();
+  c->mem.release();
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

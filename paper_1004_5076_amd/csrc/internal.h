@@ -1,0 +1,105 @@
+// Internal data layouts of the scabs library (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/scabs.h"
+
+namespace scabs {
+
+constexpr int NQ = 7;           // quadrature points per triangle (degree-5 rule)
+constexpr double PI = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// host-side geometry and layout (setup.cpp)
+// ---------------------------------------------------------------------------
+struct Geometry {
+  int nv = 0, nt = 0, ne = 0, nbody = 0;
+  std::vector<double> v;          // nv*3
+  std::vector<int> t, body;       // nt*3, nt
+  std::vector<double> area, nrm, cen, rho;   // per triangle
+  std::vector<double> qp, qw;     // nt*NQ*3, nt*NQ
+  std::vector<int> tedge, tsign;  // nt*3: edge opposite local vertex k; +1 on T+
+  std::vector<int> ev, et;        // ne*2 (sorted vertex pair; T+ < T-)
+  std::vector<double> elen;
+};
+
+struct SigmaEnd {
+  int axis, dir, degree;
+  double x0, length, sigma0;
+  std::vector<double> ctrl;       // piecewise-linear control values (empty: monomial)
+};
+
+struct Layout {
+  int NL = 0, NR = 0, N = 0;
+  std::vector<int> isR, eidx;     // per edge
+  std::vector<double> sigma;      // per quadrature point
+};
+
+// One lattice box: nodes h*(o + i), i in [0, n); FFT sizes N >= 2n - 1.
+struct GridDesc {
+  int which;                      // -1 exterior (all bodies), b >= 0 interior of body b
+  int o[3], n[3], N[3];
+  double k;
+};
+
+struct NearList {
+  std::vector<int64_t> tptr;      // nt+1: pairs of test triangle T
+  std::vector<int> src;           // source triangle of each pair
+  std::vector<uint8_t> sing;      // singular-subtraction flag per pair
+  // edge-pair CSR of the correction
+  std::vector<int64_t> rowptr;    // ne+1
+  std::vector<int> col;           // nnz
+  std::vector<int64_t> cptr;      // nnz+1: contributions (pair, i, j) of each entry
+  std::vector<int> cpair;         // pair index
+  std::vector<uint8_t> cij;       // i*3 + j
+};
+
+std::string build_geometry(const std::vector<double> &v, const std::vector<int> &t, const std::vector<int> &body,
+                           Geometry &g);
+void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<double> &sigma);
+void build_layout(const Geometry &g, Layout &L);
+std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std::vector<GridDesc> &grids,
+                        std::vector<int> &anchor /* np*3 absolute */, std::vector<double> &u /* np*3 */);
+std::string build_near(const Geometry &g, double r_near, double kappa_s, NearList &nl);
+
+// ---------------------------------------------------------------------------
+// device-side records
+// ---------------------------------------------------------------------------
+template <typename T> struct cx { T x, y; };
+
+// per quadrature point (also a test point: the rule is shared)
+template <typename T> struct PointRec {
+  T f[9];        // the three half-RWG vectors f_j(q) of its triangle (j-major, unweighted)
+  T w;           // quadrature weight (area included)
+  T sigma;       // surface conductivity at q
+  T u[3];        // position relative to its anchor node, in grid units (|u| <= 1/2)
+  int anc;       // anchor node relative to the exterior grid origin, packed x | y << 14 | z << 23
+  int tri;
+};
+
+template <typename T> struct TriRec {
+  T nrm[3];
+  T div[3];      // div f_j (constant on the triangle)
+  int edge[3];
+  int body;
+  int flags;     // bit0: triangle carries sigma > 0
+  int pad;
+};
+
+// per edge: row and unknown slots
+struct EdgeRec {
+  int tri[2];    // T+, T-
+  int loc[2];    // local index of the edge in T+, T-
+  int row[3];    // E row, H row, eq14 row (-1 on L edges)
+  int col[3];    // L: (J, M, -1); R: (Je, Ji, M)
+  int isR;
+  int pad;
+};
+
+inline int pack_anchor(int x, int y, int z) { return x | (y << 14) | (z << 23); }
+
+}  // namespace scabs

@@ -1,0 +1,91 @@
+// Launch interfaces of the HIP kernels.
+#pragma once
+#include "internal.h"
+
+namespace scabs {
+
+// One lattice box on the device, in precision T.  Potential/source fields are
+// stored [field][x][y][z] (z fastest), 8 fields:
+// J_x, J_y, J_z, div J, M_x, M_y, M_z, div M (each weighted by w_q).
+template <typename T> struct DevGrid {
+  int which;
+  int n[3], N[3];
+  int off[3];        // origin minus the exterior grid's origin (lattice units)
+  int twL;
+  T k, Z;
+  cx<T> *phys;       // 8 * n0 n1 n2
+  cx<T> *spec;       // 8 * n0 N1 N2 (y-z transformed planes)
+  const cx<T> *ghat; // (N0/2+1)(N1/2+1)(N2/2+1): FFT of the embedded kernel / (N0 N1 N2)
+  const cx<T> *tw;   // exp(-2 pi i j / twL), j < twL/2
+};
+
+// x-slab of a grid handled by one projection work-group
+struct Slab {
+  int grid, x0, nx;
+  int p0, p1;        // range in the grid's anchor-x-sorted point list
+};
+
+template <typename T> struct DevOperator {
+  int np, nt, ne, N;
+  T k_e, Z_e, k_i, Z_i;
+  const PointRec<T> *pts;
+  const TriRec<T> *tris;
+  const EdgeRec *edges;
+  // near correction CSR (edge rows)
+  const int64_t *rowptr;
+  const int *col;
+  const cx<T> *V4;   // per entry: L_e, K_e, L_i, K_i   (exact - grid)
+  const cx<T> *S4;   // per entry: Lrot_e, Krot_e, Lsig_i, Ksig_i (R rows only)
+  // work buffers
+  cx<T> *src;        // ne * 3: J_e, J_i, M
+  cx<T> *tri_out;    // nt * 3 (half-edge) * 3 (E, H, eq14 rows)
+};
+
+// ---- FFT convolution -------------------------------------------------------
+template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s);
+// FFT of the circulant-embedded grid kernel; writes the scaled octant in both precisions
+hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int twL, cx<double> *ghat64,
+                      cx<float> *ghat32, hipStream_t s);
+
+// ---- matvec steps ------------------------------------------------------------
+template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s);
+template <typename T>
+void launch_project(const DevOperator<T> &op, const DevGrid<T> *grids_dev, const Slab *slabs, int nslabs,
+                    const int *plist, size_t lds_bytes, hipStream_t s);
+template <typename T>
+void launch_interp_test(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, T inv_h,
+                        hipStream_t s);
+template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s);
+
+// ---- setup (FP64) ------------------------------------------------------------
+struct NearSetupArgs {
+  int nt;
+  double h, k_e, k_i;
+  const double *v;           // vertices
+  const int *t;              // triangles
+  const int *body;
+  const int *tedge;
+  const int *tsign;
+  const double *elen, *area, *nrm;
+  const double *qp, *qw, *sigma;
+  const int *anchor;         // absolute lattice anchors, np*3
+  const double *u;           // np*3
+  const int64_t *tptr;
+  const int *src;
+  const uint8_t *sing;
+  int D;                     // kernel table extent
+  const cx<double> *htab_e, *htab_i;   // (D+1)^3 each
+  cx<double> *blocks;        // npairs * 8 * 9
+};
+void launch_near_setup(const NearSetupArgs &a, hipStream_t s);
+void build_htab(double k, double h, int D, cx<double> *tab, hipStream_t s);
+void launch_near_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
+                          const cx<double> *blocks, cx<double> *V4, cx<double> *S4, cx<float> *V4f, cx<float> *S4f,
+                          hipStream_t s);
+
+// ---- misc --------------------------------------------------------------------
+void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,
+                       const TriRec<double> *tris, const PointRec<double> *pts, const EdgeRec *edges, double k, double Z,
+                       const double *pos, const double *mom, int bodyid, double *b, hipStream_t s);
+
+}  // namespace scabs

@@ -1,0 +1,421 @@
+// Matrix-vector product kernels of the precorrected-FFT operator.
+//
+// Row conventions (paper Sec. II / Appendix A, one row triple per edge):
+//   E row  <X_n, E_e(J_e, M_e) - E_i(J_i, M_i)>                     (eq1 / eq3)
+//   H row  <X_n, H_e^+ - H_i^->  + sum_q w sigma (X_n x n).E_e^+(q)   (eq2 / eq13,
+//          tested after rotating eq4 by n x)
+//   eq14   <X_n, J_e + J_i> - sum_q w sigma X_n.E_i^-(q)
+// with per-edge currents J_e, J_i, M_e = M, M_i = -M (eq10-eq12) and one-sided
+// limits E^+/- = PV +/- 1/2 n x M, H^+/- = PV -/+ 1/2 n x J.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace scabs {
+
+// ---------------------------------------------------------------------------
+// unknown vector -> per-edge currents (J_e, J_i, M)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void unpack_kernel(const EdgeRec *__restrict__ edges, int ne, const double *__restrict__ x,
+                              cx<T> *__restrict__ src) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  EdgeRec r = edges[e];
+  cx<T> a = {(T)x[2 * r.col[0]], (T)x[2 * r.col[0] + 1]};
+  cx<T> b = {(T)x[2 * r.col[1]], (T)x[2 * r.col[1] + 1]};
+  if (!r.isR) {
+    src[3 * e] = a;
+    src[3 * e + 1] = -a;
+    src[3 * e + 2] = b;
+  } else {
+    cx<T> c = {(T)x[2 * r.col[2]], (T)x[2 * r.col[2] + 1]};
+    src[3 * e] = a;
+    src[3 * e + 1] = b;
+    src[3 * e + 2] = c;
+  }
+}
+
+template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op.edges, op.ne, x, op.src);
+}
+template void launch_unpack<float>(const DevOperator<float> &, const double *, hipStream_t);
+template void launch_unpack<double>(const DevOperator<double> &, const double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// projection: every quadrature point spreads w_q * (J, div J, M, div M) of its
+// medium onto the 27 nodes around its anchor with tensor Lagrange weights.
+// One work-group owns an x-slab of one grid in LDS and accumulates the points
+// anchored in the slab and its two neighbouring planes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+project_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restrict__ tris, const cx<T> *__restrict__ src,
+               const DevGrid<T> *__restrict__ grids, const Slab *__restrict__ slabs, const int *__restrict__ plist) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T> *acc = reinterpret_cast<cx<T> *>(smem_raw);
+  const Slab sl = slabs[blockIdx.x];
+  const DevGrid<T> &g = grids[sl.grid];
+  const int n1 = g.n[1], n2 = g.n[2], plane = n1 * n2;
+  const int nxs = sl.nx;
+  const int fstride = nxs * plane;
+  for (int i = threadIdx.x; i < 8 * fstride; i += blockDim.x) acc[i] = czero<T>();
+  __syncthreads();
+  const bool ext = g.which < 0;
+  for (int pi = sl.p0 + threadIdx.x; pi < sl.p1; pi += blockDim.x) {
+    const int p = plist[pi];
+    const PointRec<T> P = pts[p];
+    const TriRec<T> tr = tris[P.tri];
+    cx<T> s[8];
+#pragma unroll
+    for (int f = 0; f < 8; f++) s[f] = czero<T>();
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      const int e = tr.edge[j];
+      cx<T> J = ext ? src[3 * e] : src[3 * e + 1];
+      cx<T> M = src[3 * e + 2];
+      if (!ext) M = -M;
+      for (int a = 0; a < 3; a++) {
+        axpy(s[a], P.f[3 * j + a], J);
+        axpy(s[4 + a], P.f[3 * j + a], M);
+      }
+      axpy(s[3], tr.div[j], J);
+      axpy(s[7], tr.div[j], M);
+    }
+#pragma unroll
+    for (int f = 0; f < 8; f++) s[f] = s[f] * P.w;
+    int ax, ay, az;
+    unpack_anchor(P.anc, ax, ay, az);
+    ax -= g.off[0] + sl.x0;
+    ay -= g.off[1];
+    az -= g.off[2];
+    T Lx[3], Ly[3], Lz[3], d[3];
+    lagr3(P.u[0], Lx, d);
+    lagr3(P.u[1], Ly, d);
+    lagr3(P.u[2], Lz, d);
+    for (int i = 0; i < 3; i++) {
+      const int gx = ax + i - 1;
+      if (gx < 0 || gx >= nxs) continue;
+      for (int j = 0; j < 3; j++)
+        for (int k = 0; k < 3; k++) {
+          const int node = (gx * n1 + ay + j - 1) * n2 + az + k - 1;
+          const T wgt = Lx[i] * Ly[j] * Lz[k];
+#pragma unroll
+          for (int f = 0; f < 8; f++) {
+            atomicAdd(&acc[f * fstride + node].x, wgt * s[f].x);
+            atomicAdd(&acc[f * fstride + node].y, wgt * s[f].y);
+          }
+        }
+    }
+  }
+  __syncthreads();
+  const size_t G = (size_t)g.n[0] * plane;
+  for (int i = threadIdx.x; i < 8 * fstride; i += blockDim.x) {
+    int f = i / fstride, r = i - f * fstride;
+    g.phys[f * G + (size_t)sl.x0 * plane + r] = acc[i];
+  }
+}
+
+template <typename T>
+void launch_project(const DevOperator<T> &op, const DevGrid<T> *grids_dev, const Slab *slabs, int nslabs,
+                    const int *plist, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(project_kernel<T>, dim3(nslabs), dim3(256), lds_bytes, s, op.pts, op.tris, op.src, grids_dev,
+                     slabs, plist);
+}
+template void launch_project<float>(const DevOperator<float> &, const DevGrid<float> *, const Slab *, int, const int *,
+                                    size_t, hipStream_t);
+template void launch_project<double>(const DevOperator<double> &, const DevGrid<double> *, const Slab *, int,
+                                     const int *, size_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// interpolation at test points + row contributions + local terms, reduced to
+// per-triangle half-edge partials.  One thread per point, 32 triangles per
+// work-group.
+// ---------------------------------------------------------------------------
+constexpr int IT_TRIS = 32;
+constexpr int IT_THREADS = IT_TRIS * NQ;
+
+template <typename T> struct Pot {
+  cx<T> val[8];
+  cx<T> grad[8][3];
+};
+
+template <typename T>
+__device__ inline void gather(const DevGrid<T> &g, int ax, int ay, int az, const T *Lx, const T *Ly, const T *Lz,
+                              const T *dLx, const T *dLy, const T *dLz, T inv_h, Pot<T> &p) {
+#pragma unroll
+  for (int f = 0; f < 8; f++) {
+    p.val[f] = czero<T>();
+    p.grad[f][0] = p.grad[f][1] = p.grad[f][2] = czero<T>();
+  }
+  const int n1 = g.n[1], n2 = g.n[2];
+  const size_t G = (size_t)g.n[0] * n1 * n2;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      const size_t row = ((size_t)(ax + i - 1) * n1 + (ay + j - 1)) * n2 + (az - 1);
+      const T wxy = Lx[i] * Ly[j], dxy = dLx[i] * Ly[j], xdy = Lx[i] * dLy[j];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        const T w = wxy * Lz[k], gx = dxy * Lz[k] * inv_h, gy = xdy * Lz[k] * inv_h, gz = wxy * dLz[k] * inv_h;
+#pragma unroll
+        for (int f = 0; f < 8; f++) {
+          const cx<T> v = g.phys[f * G + row + k];
+          axpy(p.val[f], w, v);
+          axpy(p.grad[f][0], gx, v);
+          axpy(p.grad[f][1], gy, v);
+          axpy(p.grad[f][2], gz, v);
+        }
+      }
+    }
+}
+
+template <typename T> __device__ inline cx<T> rdot(const T *a, const cx<T> *b) {
+  cx<T> r = a[0] * b[0];
+  axpy(r, a[1], b[1]);
+  axpy(r, a[2], b[2]);
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(IT_THREADS)
+interp_test_kernel(DevOperator<T> op, DevGrid<T> ext, const DevGrid<T> *__restrict__ ints, T inv_h) {
+  __shared__ cx<T> part[IT_THREADS][9];
+  const int lt = threadIdx.x / NQ, q = threadIdx.x - lt * NQ;
+  const int tri = blockIdx.x * IT_TRIS + lt;
+  cx<T> out[9];
+#pragma unroll
+  for (int r = 0; r < 9; r++) out[r] = czero<T>();
+  if (tri < op.nt) {
+    const PointRec<T> P = op.pts[tri * NQ + q];
+    const TriRec<T> tr = op.tris[tri];
+    const T n[3] = {tr.nrm[0], tr.nrm[1], tr.nrm[2]};
+    // local currents at the point
+    cx<T> Jsum[3], Mq[3];
+    for (int a = 0; a < 3; a++) Jsum[a] = Mq[a] = czero<T>();
+    for (int j = 0; j < 3; j++) {
+      const int e = tr.edge[j];
+      const cx<T> Je = op.src[3 * e], Ji = op.src[3 * e + 1], M = op.src[3 * e + 2];
+      for (int a = 0; a < 3; a++) {
+        axpy(Jsum[a], P.f[3 * j + a], Je + Ji);
+        axpy(Mq[a], P.f[3 * j + a], M);
+      }
+    }
+    // 1/2 n x M (residue of the one-sided E limits) and n x (J_e + J_i)
+    cx<T> hnM[3], nJ[3];
+    hnM[0] = T(0.5) * (n[1] * Mq[2] - n[2] * Mq[1]);
+    hnM[1] = T(0.5) * (n[2] * Mq[0] - n[0] * Mq[2]);
+    hnM[2] = T(0.5) * (n[0] * Mq[1] - n[1] * Mq[0]);
+    nJ[0] = n[1] * Jsum[2] - n[2] * Jsum[1];
+    nJ[1] = n[2] * Jsum[0] - n[0] * Jsum[2];
+    nJ[2] = n[0] * Jsum[1] - n[1] * Jsum[0];
+    T Lx[3], Ly[3], Lz[3], dLx[3], dLy[3], dLz[3];
+    lagr3(P.u[0], Lx, dLx);
+    lagr3(P.u[1], Ly, dLy);
+    lagr3(P.u[2], Lz, dLz);
+    int ax, ay, az;
+    unpack_anchor(P.anc, ax, ay, az);
+    const T w = P.w, ws = P.w * P.sigma;
+    Pot<T> pot;
+    for (int med = 0; med < 2; med++) {
+      const DevGrid<T> &g = med == 0 ? ext : ints[tr.body];
+      gather(g, ax - g.off[0], ay - g.off[1], az - g.off[2], Lx, Ly, Lz, dLx, dLy, dLz, inv_h, pot);
+      const T k = g.k, Z = g.Z, ik2 = T(1) / (k * k);
+      const T sgn = med == 0 ? T(1) : T(-1);
+      cx<T> aJ[3] = {pot.val[0], pot.val[1], pot.val[2]};
+      cx<T> aM[3] = {pot.val[4], pot.val[5], pot.val[6]};
+      cx<T> cJ[3] = {pot.grad[2][1] - pot.grad[1][2], pot.grad[0][2] - pot.grad[2][0], pot.grad[1][0] - pot.grad[0][1]};
+      cx<T> cM[3] = {pot.grad[6][1] - pot.grad[5][2], pot.grad[4][2] - pot.grad[6][0], pot.grad[5][0] - pot.grad[4][1]};
+      // pointwise one-sided field: E = -Z jk (a_J + k^-2 grad phi_J) - curl a_M + 1/2 n x M
+      cx<T> Ep[3];
+      for (int a = 0; a < 3; a++) {
+        cx<T> t = aJ[a];
+        axpy(t, ik2, pot.grad[3][a]);
+        Ep[a] = mul_j(t) * (-Z * k) - cM[a] + hnM[a];
+      }
+      const cx<T> phJ = pot.val[3], phM = pot.val[7];
+      for (int i = 0; i < 3; i++) {
+        const T gi[3] = {P.f[3 * i], P.f[3 * i + 1], P.f[3 * i + 2]};
+        const T dg = tr.div[i];
+        // <g, E> = -Z jk (g.a_J - k^-2 div g phi_J) - g.curl a_M
+        cx<T> t1 = rdot(gi, aJ);
+        axpy(t1, -dg * ik2, phJ);
+        cx<T> e = mul_j(t1) * (-Z * k) - rdot(gi, cM);
+        // <g, H> = g.curl a_J - (jk/Z)(g.a_M - k^-2 div g phi_M)
+        cx<T> t2 = rdot(gi, aM);
+        axpy(t2, -dg * ik2, phM);
+        cx<T> h = rdot(gi, cJ) - mul_j(t2) * (k / Z);
+        axpy(out[3 * i], sgn * w, e);
+        axpy(out[3 * i + 1], sgn * w, h);
+        if (ws != T(0)) {
+          if (med == 0) {
+            const T gxn[3] = {gi[1] * n[2] - gi[2] * n[1], gi[2] * n[0] - gi[0] * n[2], gi[0] * n[1] - gi[1] * n[0]};
+            axpy(out[3 * i + 1], ws, rdot(gxn, Ep));
+          } else {
+            axpy(out[3 * i + 2], -ws, rdot(gi, Ep));
+          }
+        }
+      }
+    }
+    // local terms: H residue -1/2 <g, n x (J_e + J_i)>, Gram <g, J_e + J_i>
+    for (int i = 0; i < 3; i++) {
+      const T gi[3] = {P.f[3 * i], P.f[3 * i + 1], P.f[3 * i + 2]};
+      axpy(out[3 * i + 1], T(-0.5) * w, rdot(gi, nJ));
+      axpy(out[3 * i + 2], w, rdot(gi, Jsum));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 9; r++) part[threadIdx.x][r] = out[r];
+  __syncthreads();
+  for (int it = threadIdx.x; it < IT_TRIS * 9; it += blockDim.x) {
+    const int l = it / 9, r = it - l * 9;
+    const int t2 = blockIdx.x * IT_TRIS + l;
+    if (t2 < op.nt) {
+      cx<T> s = czero<T>();
+      for (int qq = 0; qq < NQ; qq++) s += part[l * NQ + qq][r];
+      op.tri_out[(size_t)t2 * 9 + r] = s;
+    }
+  }
+}
+
+template <typename T>
+void launch_interp_test(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, T inv_h,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(interp_test_kernel<T>, dim3((op.nt + IT_TRIS - 1) / IT_TRIS), dim3(IT_THREADS), 0, s, op, ext,
+                     ints_dev, inv_h);
+}
+template void launch_interp_test<float>(const DevOperator<float> &, const DevGrid<float> &, const DevGrid<float> *,
+                                          float, hipStream_t);
+template void launch_interp_test<double>(const DevOperator<double> &, const DevGrid<double> &,
+                                           const DevGrid<double> *, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// near correction (exact - grid) rows, plus the two triangle halves of every
+// edge's grid/local rows; writes the FP64 output rows.  One wave per edge.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, double *__restrict__ y) {
+  const int n = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (n >= op.ne) return;
+  const EdgeRec r = op.edges[n];
+  const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
+  cx<T> E = czero<T>(), H = czero<T>(), R = czero<T>();
+  const int64_t b = op.rowptr[n], e = op.rowptr[n + 1];
+  for (int64_t k = b + lane; k < e; k += 64) {
+    const int m = op.col[k];
+    const cx<T> Je = op.src[3 * m], Ji = op.src[3 * m + 1], M = op.src[3 * m + 2];
+    const cx<T> Le = op.V4[4 * k], Ke = op.V4[4 * k + 1], Li = op.V4[4 * k + 2], Ki = op.V4[4 * k + 3];
+    E += (Li * Ji) * Zi - (Le * Je) * Ze + (Ke + Ki) * M;
+    H += Ki * Ji - Ke * Je - (Le * M) * iZe - (Li * M) * iZi;
+    if (r.isR) {
+      const cx<T> Lr = op.S4[4 * k], Kr = op.S4[4 * k + 1], Ls = op.S4[4 * k + 2], Ks = op.S4[4 * k + 3];
+      H += Kr * M - (Lr * Je) * Ze;
+      R += (Ls * Ji) * Zi + Ks * M;
+    }
+  }
+  E.x = wave_sum(E.x);
+  E.y = wave_sum(E.y);
+  H.x = wave_sum(H.x);
+  H.y = wave_sum(H.y);
+  R.x = wave_sum(R.x);
+  R.y = wave_sum(R.y);
+  if (lane == 0) {
+    const cx<T> *p0 = op.tri_out + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
+    const cx<T> *p1 = op.tri_out + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
+    E += p0[0] + p1[0];
+    H += p0[1] + p1[1];
+    R += p0[2] + p1[2];
+    y[2 * r.row[0]] = E.x;
+    y[2 * r.row[0] + 1] = E.y;
+    y[2 * r.row[1]] = H.x;
+    y[2 * r.row[1] + 1] = H.y;
+    if (r.isR) {
+      y[2 * r.row[2]] = R.x;
+      y[2 * r.row[2] + 1] = R.y;
+    }
+  }
+}
+
+template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s) {
+  int blocks = (int)(((int64_t)op.ne * 64 + 255) / 256);
+  hipLaunchKernelGGL(near_rows_kernel<T>, dim3(blocks), dim3(256), 0, s, op, y);
+}
+template void launch_near_rows<float>(const DevOperator<float> &, double *, hipStream_t);
+template void launch_near_rows<double>(const DevOperator<double> &, double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// right-hand side of an electric dipole in the interior medium of one body
+// ---------------------------------------------------------------------------
+__device__ inline void dipole_fields(double k, double Z, const double *r0, const cx<double> *p, const double *r,
+                                     cx<double> *E, cx<double> *H) {
+  double d[3] = {r[0] - r0[0], r[1] - r0[1], r[2] - r0[2]};
+  double R = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double u[3] = {d[0] / R, d[1] / R, d[2] / R};
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  cx<double> ph = {cs, -sn};                                   // exp(-jkR)
+  double c4 = 1.0 / (4.0 * PI);
+  cx<double> G = ph * (c4 / R);
+  cx<double> G1 = (cx<double>{1.0, k * R} * ph) * (-c4 / (R * R));                       // dG/dR
+  cx<double> G2 = (cx<double>{2.0 - k * k * R * R, 2.0 * k * R} * ph) * (c4 / (R * R * R));  // d2G/dR2
+  cx<double> up = u[0] * p[0] + u[1] * p[1] + u[2] * p[2];
+  // H = grad G x p ; E = -jkZ [p G + k^-2 (G'' (u.p) u + (G'/R)(p - (u.p) u))]
+  H[0] = G1 * (u[1] * p[2] - u[2] * p[1]);
+  H[1] = G1 * (u[2] * p[0] - u[0] * p[2]);
+  H[2] = G1 * (u[0] * p[1] - u[1] * p[0]);
+  for (int a = 0; a < 3; a++) {
+    cx<double> hp = (G2 * up) * u[a] + (G1 * (1.0 / R)) * (p[a] - up * u[a]);
+    cx<double> t = p[a] * G + hp * (1.0 / (k * k));
+    E[a] = mul_j(t) * (-k * Z);
+  }
+}
+
+__global__ void rhs_dipole_kernel(int nt, const int *__restrict__ body, const TriRec<double> *__restrict__ tris,
+                                  const PointRec<double> *__restrict__ pts, const double *__restrict__ qp,
+                                  const EdgeRec *__restrict__ edges, double k, double Z, double px, double py,
+                                  double pz, cx<double> m0, cx<double> m1, cx<double> m2, int bodyid, double *b) {
+  int T = blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= nt || body[T] != bodyid) return;
+  const double r0[3] = {px, py, pz};
+  const cx<double> p[3] = {m0, m1, m2};
+  cx<double> acc[3][3];
+  for (int i = 0; i < 3; i++) acc[i][0] = acc[i][1] = acc[i][2] = czero<double>();
+  for (int q = 0; q < NQ; q++) {
+    const PointRec<double> &P = pts[T * NQ + q];
+    cx<double> E[3], H[3];
+    dipole_fields(k, Z, r0, p, qp + 3 * ((size_t)T * NQ + q), E, H);
+    for (int i = 0; i < 3; i++) {
+      const double *gi = P.f + 3 * i;
+      cx<double> ge = rdot(gi, E), gh = rdot(gi, H);
+      axpy(acc[i][0], P.w, ge);
+      axpy(acc[i][1], P.w, gh);
+      axpy(acc[i][2], P.w * P.sigma, ge);
+    }
+  }
+  const TriRec<double> tr = tris[T];
+  for (int i = 0; i < 3; i++) {
+    const EdgeRec r = edges[tr.edge[i]];
+    for (int s = 0; s < 3; s++) {
+      if (r.row[s] < 0) continue;
+      atomicAdd(&b[2 * r.row[s]], acc[i][s].x);
+      atomicAdd(&b[2 * r.row[s] + 1], acc[i][s].y);
+    }
+  }
+}
+
+void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,
+                       const TriRec<double> *tris, const PointRec<double> *pts, const EdgeRec *edges, double k, double Z,
+                       const double *pos, const double *mom, int bodyid, double *b, hipStream_t s) {
+  (void)qw;
+  (void)sigma;
+  hipLaunchKernelGGL(rhs_dipole_kernel, dim3((nt + 127) / 128), dim3(128), 0, s, nt, body, tris, pts, qp, edges, k, Z,
+                     pos[0], pos[1], pos[2], cx<double>{mom[0], mom[1]}, cx<double>{mom[2], mom[3]},
+                     cx<double>{mom[4], mom[5]}, bodyid, b);
+}
+
+}  // namespace scabs

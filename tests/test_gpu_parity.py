@@ -1,0 +1,196 @@
+"""GPU parity of the HIP path with the oracle (same seeded inputs), through
+the C ABI.  Tolerances: FP64 products 1e-10 relative (both sides compute the
+same discrete operator in FP64; only summation order differs), FP32 products
+2e-5 (single-precision grids, FFT and near field), solves 1e-6 relative on the
+solution (the stated target), residuals measured with the oracle operator."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _ctx(w, **kw):
+    import paper_1004_5076_amd as pk
+    return pk.context_for(w, **kw)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.workload_small()
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    P = o.pfft(w.h, w.r_near)
+    ctx = _ctx(w)
+    return w, o, P, ctx
+
+
+def test_layout_matches(small):
+    w, o, P, ctx = small
+    info = ctx.info()
+    print("info", info, flush=True)
+    assert info["N"] == o.N and info["NL"] == o.NL and info["NR"] == o.NR
+    isr, idx = ctx.layout()
+    assert np.array_equal(isr, o.isR) and np.array_equal(idx, o.eidx)
+
+
+def test_rhs_matches(small):
+    w, o, P, ctx = small
+    d = w.dipoles[0]
+    b_gpu = ctx.rhs_dipole(d.pos, d.moment, d.body).cpu().numpy()
+    b_or = o.rhs_dipole(d)
+    assert _rel(b_gpu, b_or) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+def test_matvec_matches_oracle(small, prec, tol):
+    torch = _torch()
+    w, o, P, ctx = small
+    x = synth.random_complex(101, o.N)
+    y_or = P.matvec(x)
+    y = ctx.matvec(torch.from_numpy(x).cuda(), prec=prec).cpu().numpy()
+    err = _rel(y, y_or)
+    print("matvec prec", prec, "rel err", err, flush=True)
+    # rows by block, to localise any mismatch
+    NL, NR = o.NL, o.NR
+    blocks = [(0, NL), (NL, 2 * NL), (2 * NL, 2 * NL + NR), (2 * NL + NR, 2 * NL + 2 * NR), (2 * NL + 2 * NR, o.N)]
+    for a, b in blocks:
+        print("  block", a, b, _rel(y[a:b], y_or[a:b]), flush=True)
+    assert err < tol
+
+
+def test_matvec_unit_vectors(small):
+    """Single columns (one J, one M of an absorber edge): catches a
+    misplaced unknown that a random vector would average out."""
+    torch = _torch()
+    w, o, P, ctx = small
+    for col in (3, o.NL + 5, 2 * o.NL + 7, 2 * o.NL + o.NR + 7, 2 * o.NL + 2 * o.NR + 7):
+        x = np.zeros(o.N, complex)
+        x[col] = 1.0
+        y_or = P.matvec(x)
+        y = ctx.matvec(torch.from_numpy(x).cuda(), prec=0).cpu().numpy()
+        assert _rel(y, y_or) < 1e-10, col
+
+
+def test_batched_matvec_equals_single(small):
+    torch = _torch()
+    w, o, P, ctx = small
+    X = np.stack([synth.random_complex(200 + k, o.N) for k in range(3)])
+    Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=0).cpu().numpy()
+    for k in range(3):
+        y1 = ctx.matvec(torch.from_numpy(X[k].copy()).cuda(), prec=0).cpu().numpy()
+        assert _rel(Y[k], y1) < 1e-13
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_solve_residual_with_oracle_operator(small, mode):
+    torch = _torch()
+    w, o, P, ctx = small
+    d = w.dipoles[0]
+    b = o.rhs_dipole(d)
+    x, info = ctx.solve(torch.from_numpy(b).cuda(), tol=1e-9, max_iter=3000, restart=80, mode=mode)
+    print("solve mode", mode, info, flush=True)
+    assert info["status"] == 0
+    x = x.cpu().numpy()
+    r = _rel(P.matvec(x), b)
+    assert r < 1e-8
+
+
+def test_solve_matches_oracle_solution():
+    """Mixed-precision solve vs the oracle's own GMRES solution of the same
+    pFFT system, on a shorter guide."""
+    torch = _torch()
+    w = synth.workload_small(length=2.0, absorber=1.0)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    P = o.pfft(w.h, w.r_near)
+    b = o.rhs_dipole(w.dipoles[0])
+    x_or = P.solve(b, tol=1e-12)
+    ctx = _ctx(w)
+    x, info = ctx.solve(torch.from_numpy(b).cuda(), tol=1e-10, max_iter=3000, restart=80, mode=2)
+    assert info["status"] == 0
+    err = _rel(x.cpu().numpy(), x_or)
+    print("solution rel err", err, info, flush=True)
+    assert err < 1e-6
+
+
+def test_two_bodies_matvec():
+    """Two channels: interior operators act within each body only."""
+    torch = _torch()
+    parts = [synth.guide(1.5, 0.15, yc=-0.35), synth.guide(1.5, 0.15, yc=0.35)]
+    mesh = synth.merge_bodies(parts)
+    sig = [synth.SigmaEnd(0, 0.75, 0.75, +1, 3, 1.0), synth.SigmaEnd(0, 0.6, 0.6, -1, 4, 0.5)]
+    w = synth.Workload("two", mesh, sig, [synth.seeded_dipole(5, base=(0.5, -0.35, 0), body=0)], h=0.05,
+                       r_near=0.3137)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    P = o.pfft(w.h, w.r_near)
+    ctx = _ctx(w)
+    x = synth.random_complex(303, o.N)
+    y = ctx.matvec(torch.from_numpy(x).cuda(), prec=0).cpu().numpy()
+    assert _rel(y, P.matvec(x)) < 1e-10
+    d = w.dipoles[0]
+    assert _rel(ctx.rhs_dipole(d.pos, d.moment, d.body).cpu().numpy(), o.rhs_dipole(d)) < 1e-12
+
+
+def test_sigma_free_and_all_absorber():
+    """Edge cases: no absorber edges (pure PMCHW) and a sphere whose every
+    edge carries sigma (pure eq3/eq13/eq14 rows)."""
+    torch = _torch()
+    w = synth.workload_small(length=1.5)
+    w.sigma = []
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma([])
+    assert o.NR == 0
+    ctx = _ctx(w)
+    x = synth.random_complex(404, o.N)
+    assert _rel(ctx.matvec(torch.from_numpy(x).cuda(), prec=0).cpu().numpy(), o.pfft(w.h, w.r_near).matvec(x)) < 1e-10
+    v, t = synth.icosphere(0.25, 2)
+    mesh = synth.merge_bodies([(v, t)])
+    sig = [synth.SigmaEnd(0, -1.0, 0.5, +1, 0, 0.7)]
+    ws = synth.Workload("sphere", mesh, sig, [], h=0.05, r_near=0.17)
+    o2 = oracle.Oracle(mesh, ws.omega, ws.eps_in)
+    o2.set_sigma(sig)
+    assert o2.NL == 0
+    ctx2 = _ctx(ws)
+    x2 = synth.random_complex(405, o2.N)
+    P2 = o2.pfft(ws.h, ws.r_near)
+    assert _rel(ctx2.matvec(torch.from_numpy(x2).cuda(), prec=0).cpu().numpy(), P2.matvec(x2)) < 1e-10
+
+
+def test_errors_are_reported():
+    import paper_1004_5076_amd as pk
+    w = synth.workload_small(length=1.0)
+    ctx = pk.Context(w.h, w.r_near)
+    bad = w.mesh.tris[:-1]
+    ctx.set_mesh(w.mesh.verts, bad, w.mesh.body[:-1])
+    ctx.set_media(w.omega, 1.0, w.eps_in)
+    with pytest.raises(pk.ScabsError) as e:
+        ctx.build()
+    assert e.value.code == pk.SCABS_E_MESH
+    ctx2 = pk.Context(w.h, 0.05)
+    ctx2.set_mesh(w.mesh.verts, w.mesh.tris, w.mesh.body)
+    ctx2.set_media(w.omega, 1.0, w.eps_in)
+    with pytest.raises(pk.ScabsError) as e:
+        ctx2.build()
+    assert e.value.code == pk.SCABS_E_ARG
+    torch = _torch()
+    ctx3 = _ctx(w)
+    b = torch.full((ctx3.N,), float("nan"), dtype=torch.complex128, device="cuda")
+    with pytest.raises(pk.ScabsError) as e:
+        ctx3.solve(b, mode=0, raise_on_noconv=True)
+    assert e.value.code == pk.SCABS_E_NAN
