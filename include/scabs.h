@@ -58,6 +58,11 @@ typedef struct {
                       centroid-vertex distance; <= 0 selects 1.37 */
   int device;      /* HIP device ordinal */
   void *stream;    /* hipStream_t; NULL = a stream created by the library */
+  int precond;     /* 1: restricted additive Schwarz preconditioner on the exact
+                      near-field matrix (boxes of side pc_cell grown by
+                      pc_overlap); 0: none */
+  double pc_cell;     /* <= 0 selects 1.5 r_near */
+  double pc_overlap;  /* < 0 selects 0.75 r_near; must not exceed pc_cell */
 } scabs_opts;
 
 typedef struct {
@@ -67,6 +72,9 @@ typedef struct {
   int64_t nnz_near;        /* edge pairs in the near correction */
   int64_t grid_phys[3];    /* exterior grid, physical node counts */
   int64_t grid_fft[3];     /* exterior grid, FFT sizes */
+  int64_t nnz_near_r;      /* of which on absorber (R) rows */
+  int64_t n_clusters;      /* preconditioner clusters (0 without) */
+  int64_t precond_entries; /* stored preconditioner coefficients */
   int64_t device_bytes;    /* device memory held by the context */
 } scabs_info_t;
 
@@ -127,12 +135,30 @@ int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
 /* Solve A x = b (device vectors, nrhs of them).  x holds the initial guess
  * on entry.  mode: SCABS_FP64 (restarted GMRES on the FP64 operator) or
  * SCABS_MIXED (FP64 refinement around FP32-operator GMRES).  Orthogonalisation
- * (two-pass classical Gram-Schmidt) and the Hessenberg least squares are FP64.
+ * (two-pass classical Gram-Schmidt) and the Hessenberg least squares are FP64;
+ * the preconditioner (if enabled) is applied on the right.
  * tol: relative residual with the FP64 operator.  info may be NULL.
  * Returns SCABS_E_NOCONV (x holds the last iterate) if max_iter Arnoldi
  * steps do not reach tol. */
 int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                 int mode, scabs_solve_info *info);
+
+/* Stage timing (tracing): between scabs_profile_begin and scabs_profile_end
+ * every stage of every product and solve is bracketed by HIP events on the
+ * context stream.  scabs_profile_end synchronises the stream and returns, per
+ * stage, the summed duration in milliseconds and the number of launches
+ * (arrays of SCABS_NSTAGES entries; either may be NULL). */
+#define SCABS_STAGE_UNPACK 0     /* unknowns -> per-edge currents */
+#define SCABS_STAGE_PROJECT 1    /* sources -> grid */
+#define SCABS_STAGE_FFT 2        /* grid convolution (all grids) */
+#define SCABS_STAGE_INTERP 3     /* grid -> tested rows + local terms */
+#define SCABS_STAGE_NEAR 4       /* near correction rows */
+#define SCABS_STAGE_FP32_OFFSET 5  /* add to stages 0-4 for the FP32 product */
+#define SCABS_STAGE_PRECOND 10   /* preconditioner application */
+#define SCABS_STAGE_ORTHO 11     /* Gram-Schmidt, norms (FP64) */
+#define SCABS_NSTAGES 12
+int scabs_profile_begin(scabs_ctx *c);
+int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
 
 const char *scabs_last_error(const scabs_ctx *c);
 void scabs_destroy(scabs_ctx *c);

@@ -24,7 +24,9 @@ SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCO
 SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
-            "scabs_solve", "scabs_last_error", "scabs_destroy"]
+            "scabs_solve", "scabs_profile_begin", "scabs_profile_end", "scabs_last_error", "scabs_destroy"]
+STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
+          "near32", "precond", "ortho"]
 
 
 class ScabsError(RuntimeError):
@@ -35,14 +37,15 @@ class ScabsError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("h", C.c_double), ("r_near", C.c_double), ("kappa_s", C.c_double), ("device", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("precond", C.c_int), ("pc_cell", C.c_double), ("pc_overlap", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("N", C.c_int64), ("NL", C.c_int64), ("NR", C.c_int64), ("n_edges", C.c_int64),
                 ("n_tris", C.c_int64), ("n_points", C.c_int64), ("n_bodies", C.c_int64),
                 ("n_near_pairs", C.c_int64), ("nnz_near", C.c_int64), ("grid_phys", C.c_int64 * 3),
-                ("grid_fft", C.c_int64 * 3), ("device_bytes", C.c_int64)]
+                ("grid_fft", C.c_int64 * 3), ("nnz_near_r", C.c_int64), ("n_clusters", C.c_int64),
+                ("precond_entries", C.c_int64), ("device_bytes", C.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -84,6 +87,8 @@ def load() -> C.CDLL:
     L.scabs_rhs_dipole.argtypes = [P, dp, dp, C.c_int, P]
     L.scabs_matvec.argtypes = [P, P, P, C.c_int, C.c_int]
     L.scabs_solve.argtypes = [P, P, P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(SolveInfo)]
+    L.scabs_profile_begin.argtypes = [P]
+    L.scabs_profile_end.argtypes = [P, dp, C.POINTER(C.c_int64)]
     L.scabs_last_error.restype = C.c_char_p
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
@@ -104,7 +109,8 @@ def _i32(a):
 class Context:
     """One library context: a mesh, media, conductivity profile and grid."""
 
-    def __init__(self, h: float, r_near: float, kappa_s: float = 1.37, device: int = 0, stream=None):
+    def __init__(self, h: float, r_near: float, kappa_s: float = 1.37, device: int = 0, stream=None,
+                 precond: int = 1, pc_cell: float = -1.0, pc_overlap: float = -1.0):
         import torch
         L = load()
         self._L = L
@@ -112,7 +118,7 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        o = Opts(h, r_near, kappa_s, device, C.c_void_p(stream.cuda_stream))
+        o = Opts(h, r_near, kappa_s, device, C.c_void_p(stream.cuda_stream), precond, pc_cell, pc_overlap)
         self._c = C.c_void_p()
         self._check(L.scabs_create(C.byref(self._c), C.byref(o)))
         self.N = None
@@ -205,6 +211,15 @@ class Context:
         self._check(self._L.scabs_matvec(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, prec))
         return y
 
+    def profile_begin(self):
+        self._check(self._L.scabs_profile_begin(self._c))
+
+    def profile_end(self) -> dict:
+        ms = (C.c_double * len(STAGES))()
+        cnt = (C.c_int64 * len(STAGES))()
+        self._check(self._L.scabs_profile_end(self._c, ms, cnt))
+        return {name: {"ms": ms[k], "count": cnt[k]} for k, name in enumerate(STAGES)}
+
     def solve(self, b, x0=None, tol: float = 1e-6, max_iter: int = 2000, restart: int = 60,
               mode: int = SCABS_MIXED, raise_on_noconv: bool = False):
         import torch
@@ -221,9 +236,10 @@ class Context:
 
 
 def context_for(workload, device: int = 0, kappa_s: float = 1.37, h: Optional[float] = None,
-                r_near: Optional[float] = None) -> Context:
+                r_near: Optional[float] = None, **opts) -> Context:
     """Build a context from a synth.Workload-like object."""
-    ctx = Context(workload.h if h is None else h, workload.r_near if r_near is None else r_near, kappa_s, device)
+    ctx = Context(workload.h if h is None else h, workload.r_near if r_near is None else r_near, kappa_s, device,
+                  **opts)
     m = workload.mesh
     ctx.set_mesh(m.verts, m.tris, m.body)
     ctx.set_media(workload.omega, workload.eps_out, workload.eps_in)

@@ -60,6 +60,14 @@ struct DevMem {
     ptrs.clear();
     bytes = 0;
   }
+  void free_one(void *p) {
+    for (size_t i = 0; i < ptrs.size(); i++)
+      if (ptrs[i] == p) {
+        hipFree(p);
+        ptrs.erase(ptrs.begin() + i);
+        return;
+      }
+  }
 };
 
 template <typename T> struct PrecState {
@@ -108,14 +116,55 @@ struct scabs_ctx {
   int *body_dev = nullptr;
   PrecState<float> p32;
   PrecState<double> p64;
+  // preconditioner
+  bool has_pc = false;
+  Clusters cl;
+  int64_t nnzR = 0;
+  int64_t *pc_ext_ptr = nullptr, *pc_core_ptr = nullptr, *pc_r_off = nullptr;
+  int *pc_ext_slot = nullptr, *pc_core_slot = nullptr;
+  cx<float> *pc_Rt = nullptr;
   // solver workspace (grown on demand)
   DevMem work;
   int work_restart = -1;
   int64_t work_N = -1;
   cx<double> *V = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *hcol = nullptr, *part = nullptr;
+  cx<double> *z = nullptr, *t = nullptr;
+  // stage timing with HIP events on the context stream
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_recs;
   double *nrm = nullptr, *nrm_part = nullptr;
   int *flag = nullptr;
 };
+
+// RAII stage timer: records a start/end event pair on the context stream
+struct StageTimer {
+  scabs_ctx *c;
+  int stage;
+  hipEvent_t e0 = nullptr;
+  StageTimer(scabs_ctx *cc, int st);
+  ~StageTimer();
+};
+
+static hipEvent_t next_event(scabs_ctx *c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+StageTimer::StageTimer(scabs_ctx *cc, int st) : c(cc), stage(st) {
+  if (c->prof_on && (e0 = next_event(c))) hipEventRecord(e0, c->stream);
+}
+StageTimer::~StageTimer() {
+  if (!e0) return;
+  hipEvent_t e1 = next_event(c);
+  if (!e1) return;
+  hipEventRecord(e1, c->stream);
+  c->prof_recs.push_back({stage, {e0, e1}});
+}
 
 static int fail(scabs_ctx *c, int code, const std::string &m) {
   if (c) c->err = m;
@@ -251,8 +300,75 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   op.tri_out = P.tri_out;
 }
 
+// Restricted additive Schwarz preconditioner from the exact near-field values
+static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp) {
+  const Geometry &g = c->geo;
+  const Layout &L = c->lay;
+  hipStream_t s = c->stream;
+  double cell = c->opts.pc_cell > 0 ? c->opts.pc_cell : 1.5 * c->opts.r_near;
+  double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 0.75 * c->opts.r_near;
+  std::string e = build_clusters(g, L, cell, ov, c->cl);
+  if (!e.empty()) throw e;
+  LocalTerms lt;
+  build_local_terms(g, L, lt);
+  const Clusters &cl = c->cl;
+  std::vector<int> slot_edge(L.N);
+  std::vector<int8_t> slot_kind(L.N);
+  for (int ed = 0; ed < g.ne; ed++) {
+    int sl[3], ns;
+    edge_slots(L, ed, sl, &ns);
+    for (int k = 0; k < ns; k++) {
+      slot_edge[sl[k]] = ed;
+      slot_kind[sl[k]] = (int8_t)(ns == 2 ? k : (k == 0 ? 0 : (k == 1 ? 2 : 1)));
+    }
+  }
+  PrecondArgs p{};
+  p.nc = cl.nc;
+  p.Ze = c->Z_e;
+  p.Zi = c->Z_i;
+  p.rowptr = c->rowptr;
+  p.col = c->col;
+  p.X8 = X8;
+  p.lptr = tmp.upload(lt.ptr);
+  p.lcol = tmp.upload(lt.col);
+  p.lval = tmp.upload(lt.val);
+  p.slot_edge = tmp.upload(slot_edge);
+  p.slot_kind = tmp.upload(slot_kind);
+  p.isR = tmp.upload(L.isR);
+  c->pc_ext_ptr = c->mem.upload(cl.ext_ptr);
+  c->pc_ext_slot = c->mem.upload(cl.ext_slot);
+  c->pc_core_ptr = c->mem.upload(cl.core_ptr);
+  c->pc_core_slot = c->mem.upload(cl.core_slot);
+  c->pc_r_off = c->mem.upload(cl.r_off);
+  p.ext_ptr = c->pc_ext_ptr;
+  p.ext_slot = c->pc_ext_slot;
+  p.a_off = tmp.upload(cl.a_off);
+  p.A = tmp.alloc<cx<double>>((size_t)cl.a_off[cl.nc]);
+  int *core_pos = tmp.upload(cl.core_pos);
+  int *piv = tmp.alloc<int>((size_t)cl.ext_ptr[cl.nc]);
+  int *status = tmp.alloc<int>(1);
+  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+  c->pc_Rt = c->mem.alloc<cx<float>>((size_t)cl.r_off[cl.nc]);
+  int max_ext = 0;
+  for (int k = 0; k < cl.nc; k++) max_ext = std::max(max_ext, (int)(cl.ext_ptr[k + 1] - cl.ext_ptr[k]));
+  launch_precond_build(p, max_ext, c->pc_core_ptr, core_pos, c->pc_r_off, c->pc_Rt, piv, status, s);
+  HIPCHK(hipGetLastError());
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st) throw std::string("a preconditioner block is singular");
+  c->has_pc = true;
+}
+
+static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y) {
+  StageTimer tm(c, SCABS_STAGE_PRECOND);
+  launch_precond_apply(c->cl.nc, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot, c->pc_r_off, c->pc_Rt,
+                       x, y, c->stream);
+}
+
 static int do_build(scabs_ctx *c) {
   c->built = false;
+  c->has_pc = false;
   c->mem.release();
   c->work.release();
   c->work_restart = -1;
@@ -323,6 +439,9 @@ static int do_build(scabs_ctx *c) {
   c->rowptr = c->mem.upload(c->near.rowptr);
   c->col = c->mem.upload(c->near.col);
   c->nnz = c->near.rowptr[g.ne];
+  c->nnzR = 0;
+  for (int n = 0; n < g.ne; n++)
+    if (L.isR[n]) c->nnzR += c->near.rowptr[n + 1] - c->near.rowptr[n];
   c->qp64 = c->mem.upload(g.qp);
   c->body_dev = c->mem.upload(g.body);
   // ---- point lists per grid, sorted by anchor x ------------------------------
@@ -401,6 +520,7 @@ static int do_build(scabs_ctx *c) {
     a.htab_e = he;
     a.htab_i = hi;
     a.blocks = tmp.alloc<cx<double>>((size_t)npairs * 72);
+    a.blocks_exact = tmp.alloc<cx<double>>((size_t)npairs * 72);
     launch_near_setup(a, s);
     HIPCHK(hipGetLastError());
     cx<double> *V4 = c->mem.alloc<cx<double>>(4 * (size_t)c->nnz);
@@ -412,6 +532,15 @@ static int do_build(scabs_ctx *c) {
     uint8_t *cij = tmp.upload(c->near.cij);
     launch_near_assemble(c->nnz, cptr, cpair, cij, a.blocks, V4, S4, V4f, S4f, s);
     HIPCHK(hipGetLastError());
+    if (c->opts.precond) {
+      cx<double> *X8 = tmp.alloc<cx<double>>(8 * (size_t)c->nnz);
+      launch_exact_assemble(c->nnz, cptr, cpair, cij, a.blocks_exact, X8, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      tmp.free_one(a.blocks);
+      tmp.free_one(a.blocks_exact);
+      build_preconditioner(c, X8, tmp);
+    }
     HIPCHK(hipStreamSynchronize(s));
     tmp.release();
     build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, plist_off, plane_start, V4, S4);
@@ -427,11 +556,27 @@ static int do_build(scabs_ctx *c) {
 // ---------------------------------------------------------------------------
 template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const double *x, double *y) {
   hipStream_t s = c->stream;
-  launch_unpack(P.op, x, s);
-  launch_project(P.op, P.grids_dev, P.slabs, P.nslabs, c->plist, P.proj_lds, s);
-  for (const DevGrid<T> &g : P.grids) launch_conv(g, s);
-  launch_interp_test(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, s);
-  launch_near_rows(P.op, y, s);
+  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
+  {
+    StageTimer t(c, SCABS_STAGE_UNPACK + off);
+    launch_unpack(P.op, x, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_PROJECT + off);
+    launch_project(P.op, P.grids_dev, P.slabs, P.nslabs, c->plist, P.proj_lds, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_FFT + off);
+    for (const DevGrid<T> &g : P.grids) launch_conv(g, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_INTERP + off);
+    launch_interp_test(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_NEAR + off);
+    launch_near_rows(P.op, y, s);
+  }
 }
 
 static void matvec_one(scabs_ctx *c, const double *x, double *y, int prec) {
@@ -453,6 +598,8 @@ static void ensure_work(scabs_ctx *c, int restart) {
   c->w = c->work.alloc<cx<double>>(N);
   c->r = c->work.alloc<cx<double>>(N);
   c->d = c->work.alloc<cx<double>>(N);
+  c->z = c->work.alloc<cx<double>>(N);
+  c->t = c->work.alloc<cx<double>>(N);
   c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2));
   c->part = c->work.alloc<cx<double>>((size_t)256 * (restart + 2));
   c->nrm = c->work.alloc<double>(4);
@@ -510,14 +657,22 @@ static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, i
     int j = 0;
     while (j < m && res.iters < max_iter) {
       cx<double> *vj = c->V + (size_t)j * N;
-      matvec_one(c, (const double *)vj, (double *)c->w, prec);
+      if (c->has_pc) {
+        apply_precond(c, vj, c->z);
+        matvec_one(c, (const double *)c->z, (double *)c->w, prec);
+      } else {
+        matvec_one(c, (const double *)vj, (double *)c->w, prec);
+      }
       nmv++;
-      kr_dots(c->V, N, j + 1, c->w, N, c->part, h1, 0, s);
-      kr_update(c->w, c->V, N, j + 1, h1, N, -1.0, s);
-      kr_dots(c->V, N, j + 1, c->w, N, c->part, h2, 0, s);
-      kr_update(c->w, c->V, N, j + 1, h2, N, -1.0, s);
-      kr_norm(c->w, N, c->nrm_part, c->nrm, s);
-      kr_scale(c->V + (size_t)(j + 1) * N, c->w, c->nrm, N, s);
+      {
+        StageTimer tm(c, SCABS_STAGE_ORTHO);
+        kr_dots(c->V, N, j + 1, c->w, N, c->part, h1, 0, s);
+        kr_update(c->w, c->V, N, j + 1, h1, N, -1.0, s);
+        kr_dots(c->V, N, j + 1, c->w, N, c->part, h2, 0, s);
+        kr_update(c->w, c->V, N, j + 1, h2, N, -1.0, s);
+        kr_norm(c->w, N, c->nrm_part, c->nrm, s);
+        kr_scale(c->V + (size_t)(j + 1) * N, c->w, c->nrm, N, s);
+      }
       double hn;
       HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * 2 * (m + 2), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&hn, c->nrm, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -559,7 +714,15 @@ static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, i
     std::vector<cx<double>> yb(j);
     for (int i = 0; i < j; i++) yb[i] = {y[i].real(), y[i].imag()};
     HIPCHK(hipMemcpyAsync(h1, yb.data(), sizeof(cx<double>) * j, hipMemcpyHostToDevice, s));
-    kr_update(sol, c->V, N, j, h1, N, +1.0, s);
+    if (c->has_pc) {
+      // sol += M (V y)
+      HIPCHK(hipMemsetAsync(c->t, 0, sizeof(cx<double>) * N, s));
+      kr_update(c->t, c->V, N, j, h1, N, +1.0, s);
+      apply_precond(c, c->t, c->z);
+      kr_axpy(sol, c->z, N, s);
+    } else {
+      kr_update(sol, c->V, N, j, h1, N, +1.0, s);
+    }
     // true residual
     matvec_one(c, (const double *)sol, (double *)c->w, prec);
     nmv++;
@@ -733,6 +896,9 @@ int scabs_info(const scabs_ctx *c, scabs_info_t *info) {
     info->grid_phys[a] = c->grids[0].n[a];
     info->grid_fft[a] = c->grids[0].N[a];
   }
+  info->nnz_near_r = c->nnzR;
+  info->n_clusters = c->has_pc ? c->cl.nc : 0;
+  info->precond_entries = c->has_pc ? c->cl.r_off[c->cl.nc] : 0;
   info->device_bytes = (int64_t)(c->mem.bytes + c->work.bytes);
   return SCABS_OK;
 }
@@ -808,6 +974,35 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
   }
 }
 
+int scabs_profile_begin(scabs_ctx *c) {
+  if (!c) return SCABS_E_ARG;
+  c->prof_recs.clear();
+  c->ev_used = 0;
+  c->prof_on = true;
+  return SCABS_OK;
+}
+
+int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count) {
+  if (!c) return SCABS_E_ARG;
+  c->prof_on = false;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, SCABS_E_HIP, "stream synchronisation failed");
+  for (int k = 0; k < SCABS_NSTAGES; k++) {
+    if (ms) ms[k] = 0;
+    if (count) count[k] = 0;
+  }
+  for (auto &r : c->prof_recs) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, r.second.first, r.second.second) != hipSuccess) continue;
+    if (r.first >= 0 && r.first < SCABS_NSTAGES) {
+      if (ms) ms[r.first] += t;
+      if (count) count[r.first] += 1;
+    }
+  }
+  c->prof_recs.clear();
+  c->ev_used = 0;
+  return SCABS_OK;
+}
+
 const char *scabs_last_error(const scabs_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void scabs_destroy(scabs_ctx *c) {
@@ -816,6 +1011,7 @@ void scabs_destroy(scabs_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   c->work.release();
   c->mem.release();
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }

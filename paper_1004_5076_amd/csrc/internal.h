@@ -58,6 +58,25 @@ struct NearList {
   std::vector<uint8_t> cij;       // i*3 + j
 };
 
+// Overlapping box clusters of edges (restricted additive Schwarz on the
+// near-field matrix): core = edges whose midpoint lies in a cubic cell,
+// ext = edges whose midpoint lies in the cell grown by the overlap.
+struct Clusters {
+  int nc = 0;
+  std::vector<int64_t> ext_ptr, core_ptr, a_off, r_off;   // nc + 1 each
+  std::vector<int> ext_slot;    // unknown slots of the extended set (sorted)
+  std::vector<int> core_pos;    // position of each core unknown in its ext list
+  std::vector<int> core_slot;   // its unknown slot
+};
+
+// Same-triangle (local) interactions per edge pair, 4 values each:
+// Gram <g, f>, <g, n x f>, sum w sigma (g x n).(n x f), sum w sigma g.(n x f)
+struct LocalTerms {
+  std::vector<int64_t> ptr;     // ne + 1
+  std::vector<int> col;
+  std::vector<double> val;      // 4 per entry
+};
+
 std::string build_geometry(const std::vector<double> &v, const std::vector<int> &t, const std::vector<int> &body,
                            Geometry &g);
 void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<double> &sigma);
@@ -65,6 +84,9 @@ void build_layout(const Geometry &g, Layout &L);
 std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std::vector<GridDesc> &grids,
                         std::vector<int> &anchor /* np*3 absolute */, std::vector<double> &u /* np*3 */);
 std::string build_near(const Geometry &g, double r_near, double kappa_s, NearList &nl);
+std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl);
+void build_local_terms(const Geometry &g, const Layout &L, LocalTerms &lt);
+void edge_slots(const Layout &L, int e, int *slots, int *nslots);
 
 // ---------------------------------------------------------------------------
 // device-side records

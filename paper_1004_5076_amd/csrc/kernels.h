@@ -75,13 +75,40 @@ struct NearSetupArgs {
   const uint8_t *sing;
   int D;                     // kernel table extent
   const cx<double> *htab_e, *htab_i;   // (D+1)^3 each
-  cx<double> *blocks;        // npairs * 8 * 9
+  cx<double> *blocks;        // npairs * 8 * 9: exact - grid
+  cx<double> *blocks_exact;  // npairs * 8 * 9: exact
 };
 void launch_near_setup(const NearSetupArgs &a, hipStream_t s);
 void build_htab(double k, double h, int D, cx<double> *tab, hipStream_t s);
 void launch_near_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
                           const cx<double> *blocks, cx<double> *V4, cx<double> *S4, cx<float> *V4f, cx<float> *S4f,
                           hipStream_t s);
+
+// ---- preconditioner (restricted additive Schwarz on the exact near field) -----
+struct PrecondArgs {
+  int nc;
+  double Ze, Zi;
+  const int64_t *rowptr;
+  const int *col;
+  const cx<double> *X8;      // exact near values per CSR entry (8 operator types)
+  const int64_t *lptr;       // local-term CSR
+  const int *lcol;
+  const double *lval;
+  const int *slot_edge;      // unknown slot -> edge
+  const int8_t *slot_kind;   // 0: J / J_e / E row, 1: M / H row, 2: J_i / eq14 row
+  const int *isR;            // per edge
+  const int64_t *ext_ptr;
+  const int *ext_slot;
+  const int64_t *a_off;
+  cx<double> *A;             // dense cluster blocks
+};
+void launch_exact_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
+                           const cx<double> *blocks, cx<double> *X8, hipStream_t s);
+void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
+                          const int64_t *r_off, cx<float> *Rt, int *piv, int *status, hipStream_t s);
+void launch_precond_apply(int nc, const int64_t *ext_ptr, const int *ext_slot, const int64_t *core_ptr,
+                          const int *core_slot, const int64_t *r_off, const cx<float> *Rt, const cx<double> *x,
+                          cx<double> *y, hipStream_t s);
 
 // ---- misc --------------------------------------------------------------------
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,

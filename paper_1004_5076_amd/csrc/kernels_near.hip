@@ -130,8 +130,8 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
   __shared__ double s_Pw[NQ][27];
   __shared__ double s_sv[3][3], s_scoef[3], s_sdiv[3];
   __shared__ cx<double> s_Phi[NQ][MAXBOX];
-  __shared__ cx<double> s_D[NQ][NQ][4];
-  __shared__ cx<double> s_part[NQ][NTYPES * 9];
+  __shared__ cx<double> s_D[NQ][NQ][8];   // exact (value, grad), grid (value, grad)
+  __shared__ cx<double> s_part[2][NQ][NTYPES * 9];   // [exact - grid, exact]
 
   // ---- test triangle -------------------------------------------------------
   if (tid < NQ) {
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
       s_sdiv[tid] = 2.0 * s_scoef[tid];
       for (int c = 0; c < 3; c++) s_sv[tid][c] = a.v[3 * a.t[3 * Tp + tid] + c];
     }
-    for (int i = tid; i < NQ * NTYPES * 9; i += NS_THREADS) (&s_part[0][0])[i] = cx<double>{0.0, 0.0};
+    for (int i = tid; i < 2 * NQ * NTYPES * 9; i += NS_THREADS) (&s_part[0][0][0])[i] = cx<double>{0.0, 0.0};
     __syncthreads();
 
     for (int med = 0; med < (same ? 2 : 1); med++) {
@@ -254,20 +254,31 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
           gr[2] = dG * (dv.z / R);
         }
         const double ws = s_sw[s];
-        s_D[t][s][0] = (G - Hv) * ws;
-        for (int c = 0; c < 3; c++) s_D[t][s][1 + c] = (gr[c] - Hg[c]) * ws;
+        s_D[t][s][0] = G * ws;
+        s_D[t][s][4] = Hv * ws;
+        for (int c = 0; c < 3; c++) {
+          s_D[t][s][1 + c] = gr[c] * ws;
+          s_D[t][s][5 + c] = Hg[c] * ws;
+        }
       }
       __syncthreads();
-      // per test point: inner integrals, then its share of the tested blocks
-      if (tid < NQ) {
-        const int t = tid;
+      // per test point: inner integrals, then its share of the tested blocks,
+      // once for exact - grid (variant 0) and once for exact alone (variant 1)
+      if (tid < 2 * NQ) {
+        const int t = tid % NQ, var = tid / NQ;
         const D3 r = d3(s_tp[t]);
         cx<double> S0 = {0, 0};
         Z3 S1 = {{0, 0}, {0, 0}, {0, 0}}, Sg = S1, Sc[3] = {S1, S1, S1};
         for (int s = 0; s < NQ; s++) {
           const D3 sp = d3(s_sp[s]);
-          const cx<double> g0 = s_D[t][s][0];
-          const Z3 gv = {s_D[t][s][1], s_D[t][s][2], s_D[t][s][3]};
+          cx<double> g0 = s_D[t][s][0];
+          Z3 gv = {s_D[t][s][1], s_D[t][s][2], s_D[t][s][3]};
+          if (var == 0) {
+            g0 -= s_D[t][s][4];
+            gv.x -= s_D[t][s][5];
+            gv.y -= s_D[t][s][6];
+            gv.z -= s_D[t][s][7];
+          }
           S0 += g0;
           S1 = zadd(S1, zscale(g0, sp - r));
           Sg = zadd(Sg, gv);
@@ -293,6 +304,7 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
             Sc[j].z.x += c4 * cr.z;
           }
         }
+        cx<double> *part = s_part[var][t];
         const double w = s_tw[t], sg = s_tsig[t], ik2 = 1.0 / (k * k);
         for (int j = 0; j < 3; j++) {
           const D3 rv = r - d3(s_sv[j]);
@@ -312,19 +324,17 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
             const D3 gi = d3(s_tg[t][i]);
             cx<double> tl = zdot(gi, aj);
             axpy(tl, -s_tdiv[i] * ik2, phj);
-            const cx<double> Lt = mul_j(tl) * (k * w);
-            const cx<double> Kt = zdot(gi, Kv) * w;
             const int ij = i * 3 + j;
-            s_part[t][(med ? 2 : 0) * 9 + ij] = Lt;
-            s_part[t][(med ? 3 : 1) * 9 + ij] = Kt;
+            part[(med ? 2 : 0) * 9 + ij] = mul_j(tl) * (k * w);
+            part[(med ? 3 : 1) * 9 + ij] = zdot(gi, Kv) * w;
             if (sg != 0.0) {
               if (med == 0) {
                 const D3 gxn = crossd(gi, nT);
-                s_part[t][4 * 9 + ij] = zdot(gxn, Lv) * (w * sg);
-                s_part[t][5 * 9 + ij] = zdot(gxn, Kv) * (w * sg);
+                part[4 * 9 + ij] = zdot(gxn, Lv) * (w * sg);
+                part[5 * 9 + ij] = zdot(gxn, Kv) * (w * sg);
               } else {
-                s_part[t][6 * 9 + ij] = zdot(gi, Lv) * (w * sg);
-                s_part[t][7 * 9 + ij] = zdot(gi, Kv) * (w * sg);
+                part[6 * 9 + ij] = zdot(gi, Lv) * (w * sg);
+                part[7 * 9 + ij] = zdot(gi, Kv) * (w * sg);
               }
             }
           }
@@ -332,10 +342,11 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
       }
       __syncthreads();
     }
-    for (int e = tid; e < NTYPES * 9; e += NS_THREADS) {
+    for (int e = tid; e < 2 * NTYPES * 9; e += NS_THREADS) {
+      const int var = e / (NTYPES * 9), ee = e - var * NTYPES * 9;
       cx<double> s = {0, 0};
-      for (int t = 0; t < NQ; t++) s += s_part[t][e];
-      a.blocks[(size_t)p * NTYPES * 9 + e] = s;
+      for (int t = 0; t < NQ; t++) s += s_part[var][t][ee];
+      (var ? a.blocks_exact : a.blocks)[(size_t)p * NTYPES * 9 + ee] = s;
     }
     __syncthreads();
   }

@@ -1,0 +1,248 @@
+// Restricted additive Schwarz preconditioner built from the exact near-field
+// matrix: for every box cluster the dense near-field block on its extended
+// (overlapping) unknown set is assembled in FP64, inverted by Gauss-Jordan
+// elimination with partial pivoting, and the rows of its core unknowns are
+// kept (FP32).  Applying it is one dense block product per cluster.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace scabs {
+
+// exact values per CSR entry: L_e, K_e, L_i, K_i, Lrot_e, Krot_e, Lsig_i, Ksig_i
+__global__ void exact_assemble_kernel(int64_t nnz, const int64_t *__restrict__ cptr, const int *__restrict__ cpair,
+                                      const uint8_t *__restrict__ cij, const cx<double> *__restrict__ blocks,
+                                      cx<double> *__restrict__ X8) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    cx<double> acc[8];
+    for (int t = 0; t < 8; t++) acc[t] = {0.0, 0.0};
+    for (int64_t c = cptr[e]; c < cptr[e + 1]; c++) {
+      const cx<double> *b = blocks + (size_t)cpair[c] * 72 + cij[c];
+      for (int t = 0; t < 8; t++) acc[t] += b[t * 9];
+    }
+    for (int t = 0; t < 8; t++) X8[8 * e + t] = acc[t];
+  }
+}
+
+void launch_exact_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
+                           const cx<double> *blocks, cx<double> *X8, hipStream_t s) {
+  hipLaunchKernelGGL(exact_assemble_kernel, dim3(2048), dim3(256), 0, s, nnz, cptr, cpair, cij, blocks, X8);
+}
+
+// Near-field matrix entry (row slot a, column slot b).  Rows: E (eq1/eq3),
+// H (eq2/eq13), eq14; per-edge currents J_e, J_i, M with J_i = -J_e on L edges.
+__device__ cx<double> near_entry(const PrecondArgs &p, int a, int b) {
+  const int n = p.slot_edge[a], r = p.slot_kind[a];
+  const int m = p.slot_edge[b], cc = p.slot_kind[b];
+  cx<double> X[8];
+  for (int t = 0; t < 8; t++) X[t] = {0.0, 0.0};
+  {
+    int64_t lo = p.rowptr[n], hi = p.rowptr[n + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (p.col[mid] < m) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < p.rowptr[n + 1] && p.col[lo] == m)
+      for (int t = 0; t < 8; t++) X[t] = p.X8[8 * lo + t];
+  }
+  double gram = 0, nx = 0, srot = 0, snx = 0;
+  for (int64_t k = p.lptr[n]; k < p.lptr[n + 1]; k++)
+    if (p.lcol[k] == m) {
+      gram = p.lval[4 * k];
+      nx = p.lval[4 * k + 1];
+      srot = p.lval[4 * k + 2];
+      snx = p.lval[4 * k + 3];
+    }
+  const double Ze = p.Ze, Zi = p.Zi;
+  cx<double> cJe, cJi, cM;
+  if (r == 0) {
+    cJe = X[0] * (-Ze);
+    cJi = X[2] * Zi;
+    cM = X[1] + X[3];
+  } else if (r == 1) {
+    cJe = -X[1] - cx<double>{0.5 * nx, 0.0};
+    cJi = X[3] - cx<double>{0.5 * nx, 0.0};
+    cM = -(X[0] * (1.0 / Ze) + X[2] * (1.0 / Zi));
+    if (p.isR[n]) {
+      cJe -= X[4] * Ze;
+      cM += X[5] + cx<double>{0.5 * srot, 0.0};
+    }
+  } else {
+    cJe = {gram, 0.0};
+    cJi = X[6] * Zi + cx<double>{gram, 0.0};
+    cM = X[7] - cx<double>{0.5 * snx, 0.0};
+  }
+  if (p.isR[m]) return cc == 0 ? cJe : (cc == 2 ? cJi : cM);
+  return cc == 0 ? cJe - cJi : cM;
+}
+
+__global__ void block_assemble_kernel(PrecondArgs p) {
+  const int c = blockIdx.y;
+  const int64_t e0 = p.ext_ptr[c];
+  const int ne = (int)(p.ext_ptr[c + 1] - e0);
+  cx<double> *A = p.A + p.a_off[c];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)ne * ne;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(i / ne), b = (int)(i - (int64_t)a * ne);
+    A[i] = near_entry(p, p.ext_slot[e0 + a], p.ext_slot[e0 + b]);
+  }
+}
+
+// In-place inverse of each cluster block (row-major n x n) by Gauss-Jordan
+// elimination with partial pivoting; the row interchanges are undone as
+// column interchanges at the end.  One work-group per cluster.
+constexpr int GJ_THREADS = 1024;
+constexpr int GJ_MAXN = 2048;
+
+__global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ablocks, const int64_t *a_off,
+                                                                  const int64_t *ext_ptr, int *piv_all, int *status) {
+  const int c = blockIdx.x;
+  const int n = (int)(ext_ptr[c + 1] - ext_ptr[c]);
+  cx<double> *A = Ablocks + a_off[c];
+  int *piv = piv_all + ext_ptr[c];
+  __shared__ cx<double> rowk[GJ_MAXN];
+  __shared__ cx<double> colk[GJ_MAXN];
+  __shared__ double red_v[GJ_THREADS / 64];
+  __shared__ int red_i[GJ_THREADS / 64];
+  __shared__ int s_p;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int k = 0; k < n; k++) {
+    // pivot: largest |A[i][k]|, i >= k
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += blockDim.x) {
+      cx<double> v = A[(size_t)i * n + k];
+      double m = v.x * v.x + v.y * v.y;
+      if (m > best) {
+        best = m;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(best, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[wid] = best;
+      red_i[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bv = red_v[0];
+      int bb = red_i[0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bb)) {
+          bv = red_v[w];
+          bb = red_i[w];
+        }
+      s_p = bb;
+      piv[k] = bb;
+      if (!(bv > 0)) *status = 1;   // singular block
+    }
+    __syncthreads();
+    const int pr = s_p;
+    if (pr != k)
+      for (int j = tid; j < n; j += blockDim.x) {
+        cx<double> t = A[(size_t)k * n + j];
+        A[(size_t)k * n + j] = A[(size_t)pr * n + j];
+        A[(size_t)pr * n + j] = t;
+      }
+    __syncthreads();
+    // pivot row scaled by 1/d, pivot column saved
+    const cx<double> d = A[(size_t)k * n + k];
+    const double dn = d.x * d.x + d.y * d.y;
+    const cx<double> inv = dn > 0 ? cx<double>{d.x / dn, -d.y / dn} : cx<double>{0.0, 0.0};
+    for (int j = tid; j < n; j += blockDim.x) {
+      cx<double> v = j == k ? cx<double>{1.0, 0.0} : A[(size_t)k * n + j];
+      rowk[j] = v * inv;
+      colk[j] = A[(size_t)j * n + k];
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) A[(size_t)k * n + j] = rowk[j];
+    for (int64_t idx = tid; idx < (int64_t)n * n; idx += blockDim.x) {
+      const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+      if (i == k) continue;
+      const cx<double> f = colk[i];
+      if (j == k)
+        A[idx] = -(f * inv);
+      else
+        A[idx] -= f * rowk[j];
+    }
+    __syncthreads();
+  }
+  // undo row interchanges as column interchanges, last first
+  for (int k = n - 1; k >= 0; k--) {
+    const int pr = piv[k];
+    if (pr != k)
+      for (int i = tid; i < n; i += blockDim.x) {
+        cx<double> t = A[(size_t)i * n + k];
+        A[(size_t)i * n + k] = A[(size_t)i * n + pr];
+        A[(size_t)i * n + pr] = t;
+      }
+    __syncthreads();
+  }
+}
+
+// Rt[j][i] = inverse[core_pos[i]][j], FP32 (column-major over the core rows)
+__global__ void extract_kernel(const cx<double> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr,
+                               const int64_t *core_ptr, const int *core_pos, const int64_t *r_off, cx<float> *Rt) {
+  const int c = blockIdx.y;
+  const int ne = (int)(ext_ptr[c + 1] - ext_ptr[c]);
+  const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
+  const cx<double> *A = Ablocks + a_off[c];
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)ne * nc;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / nc), i = (int)(idx - (int64_t)j * nc);
+    const cx<double> v = A[(size_t)core_pos[core_ptr[c] + i] * ne + j];
+    Rt[r_off[c] + idx] = {(float)v.x, (float)v.y};
+  }
+}
+
+void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
+                          const int64_t *r_off, cx<float> *Rt, int *piv, int *status, hipStream_t s) {
+  (void)max_ext;
+  hipLaunchKernelGGL(block_assemble_kernel, dim3(64, p.nc), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(p.nc), dim3(GJ_THREADS), 0, s, p.A, p.a_off, p.ext_ptr, piv, status);
+  hipLaunchKernelGGL(extract_kernel, dim3(32, p.nc), dim3(256), 0, s, (const cx<double> *)p.A, p.a_off, p.ext_ptr,
+                     core_ptr, core_pos, r_off, Rt);
+}
+
+// y[core] = R_c x[ext] for every cluster; each unknown is in exactly one core
+constexpr int PA_THREADS = 256;
+__global__ void __launch_bounds__(PA_THREADS)
+precond_apply_kernel(const int64_t *__restrict__ ext_ptr, const int *__restrict__ ext_slot,
+                     const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
+                     const int64_t *__restrict__ r_off, const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x,
+                     cx<double> *__restrict__ y) {
+  __shared__ cx<double> xs[GJ_MAXN];
+  const int c = blockIdx.x;
+  const int64_t e0 = ext_ptr[c];
+  const int ne = (int)(ext_ptr[c + 1] - e0);
+  const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
+  for (int j = threadIdx.x; j < ne; j += blockDim.x) xs[j] = x[ext_slot[e0 + j]];
+  __syncthreads();
+  const cx<float> *R = Rt + r_off[c];
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    double ar = 0, ai = 0;
+    for (int j = 0; j < ne; j++) {
+      const cx<float> rv = R[(size_t)j * nc + i];
+      const cx<double> xv = xs[j];
+      ar += (double)rv.x * xv.x - (double)rv.y * xv.y;
+      ai += (double)rv.x * xv.y + (double)rv.y * xv.x;
+    }
+    y[core_slot[core_ptr[c] + i]] = {ar, ai};
+  }
+}
+
+void launch_precond_apply(int nc, const int64_t *ext_ptr, const int *ext_slot, const int64_t *core_ptr,
+                          const int *core_slot, const int64_t *r_off, const cx<float> *Rt, const cx<double> *x,
+                          cx<double> *y, hipStream_t s) {
+  hipLaunchKernelGGL(precond_apply_kernel, dim3(nc), dim3(PA_THREADS), 0, s, ext_ptr, ext_slot, core_ptr, core_slot,
+                     r_off, Rt, x, y);
+}
+
+}  // namespace scabs

@@ -1,6 +1,7 @@
 // Host-side setup: RWG edges, quadrature points, surface conductivity,
 // unknown layout, lattice boxes and the near-pair structure.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <numeric>
@@ -353,6 +354,174 @@ std::string build_near(const Geometry &g, double r_near, double kappa_s, NearLis
   }
   nl.cptr[nnz] = cnt[ne];
   return "";
+}
+
+// unknown slots of an edge: L -> (J, M), R -> (J_e, J_i, M) (Appendix A order)
+void edge_slots(const Layout &L, int e, int *slots, int *nslots) {
+  int id = L.eidx[e];
+  if (!L.isR[e]) {
+    slots[0] = id;
+    slots[1] = L.NL + id;
+    *nslots = 2;
+  } else {
+    int b = 2 * L.NL;
+    slots[0] = b + id;
+    slots[1] = b + L.NR + id;
+    slots[2] = b + 2 * L.NR + id;
+    *nslots = 3;
+  }
+}
+
+std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl) {
+  if (!(cell > 0) || overlap < 0 || overlap > cell) return "preconditioner cell must be > 0 and overlap in [0, cell]";
+  const int ne = g.ne;
+  std::vector<double> mid(3 * ne);
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int e = 0; e < ne; e++)
+    for (int a = 0; a < 3; a++) {
+      mid[3 * e + a] = 0.5 * (g.v[3 * g.ev[2 * e] + a] + g.v[3 * g.ev[2 * e + 1] + a]);
+      lo[a] = std::min(lo[a], mid[3 * e + a]);
+    }
+  std::vector<std::array<int, 3>> key(ne);
+  int nc3[3] = {0, 0, 0};
+  for (int e = 0; e < ne; e++)
+    for (int a = 0; a < 3; a++) {
+      key[e][a] = (int)std::floor((mid[3 * e + a] - lo[a]) / cell);
+      nc3[a] = std::max(nc3[a], key[e][a] + 1);
+    }
+  auto cid = [&](int x, int y, int z) { return ((int64_t)x * nc3[1] + y) * nc3[2] + z; };
+  std::vector<int> order(ne);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<int64_t> k1(ne);
+  for (int e = 0; e < ne; e++) k1[e] = cid(key[e][0], key[e][1], key[e][2]);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return k1[a] != k1[b] ? k1[a] < k1[b] : a < b; });
+  std::vector<int64_t> sk(ne);
+  for (int i = 0; i < ne; i++) sk[i] = k1[order[i]];
+  // one cluster per non-empty cell
+  std::vector<int64_t> cells;
+  for (int i = 0; i < ne; i++)
+    if (i == 0 || sk[i] != sk[i - 1]) cells.push_back(sk[i]);
+  cl = Clusters();
+  cl.nc = (int)cells.size();
+  std::vector<std::vector<int>> ext(cl.nc), core(cl.nc);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int c = 0; c < cl.nc; c++) {
+    int64_t k = cells[c];
+    int cx_ = (int)(k / ((int64_t)nc3[1] * nc3[2])), cy = (int)((k / nc3[2]) % nc3[1]), cz = (int)(k % nc3[2]);
+    int ck[3] = {cx_, cy, cz};
+    double blo[3], bhi[3];
+    for (int a = 0; a < 3; a++) {
+      blo[a] = lo[a] + ck[a] * cell - overlap;
+      bhi[a] = lo[a] + (ck[a] + 1) * cell + overlap;
+    }
+    std::vector<int> ee, cc;
+    for (int dx = -1; dx <= 1; dx++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dz = -1; dz <= 1; dz++) {
+          int x = cx_ + dx, y = cy + dy, z = cz + dz;
+          if (x < 0 || y < 0 || z < 0 || x >= nc3[0] || y >= nc3[1] || z >= nc3[2]) continue;
+          int64_t kk = cid(x, y, z);
+          auto it = std::lower_bound(sk.begin(), sk.end(), kk);
+          for (size_t i = it - sk.begin(); i < (size_t)ne && sk[i] == kk; i++) {
+            int e = order[i];
+            bool in = true;
+            for (int a = 0; a < 3; a++) in &= mid[3 * e + a] >= blo[a] && mid[3 * e + a] < bhi[a];
+            if (in) ee.push_back(e);
+            if (kk == k) cc.push_back(e);
+          }
+        }
+    std::vector<int> es, cs;
+    int sl[3], ns;
+    for (int e : ee) {
+      edge_slots(L, e, sl, &ns);
+      es.insert(es.end(), sl, sl + ns);
+    }
+    for (int e : cc) {
+      edge_slots(L, e, sl, &ns);
+      cs.insert(cs.end(), sl, sl + ns);
+    }
+    std::sort(es.begin(), es.end());
+    std::sort(cs.begin(), cs.end());
+    ext[c].swap(es);
+    core[c].swap(cs);
+  }
+  cl.ext_ptr.assign(cl.nc + 1, 0);
+  cl.core_ptr.assign(cl.nc + 1, 0);
+  cl.a_off.assign(cl.nc + 1, 0);
+  cl.r_off.assign(cl.nc + 1, 0);
+  size_t maxext = 0;
+  for (int c = 0; c < cl.nc; c++) {
+    size_t ne_c = ext[c].size(), nc_c = core[c].size();
+    maxext = std::max(maxext, ne_c);
+    cl.ext_ptr[c + 1] = cl.ext_ptr[c] + ne_c;
+    cl.core_ptr[c + 1] = cl.core_ptr[c] + nc_c;
+    cl.a_off[c + 1] = cl.a_off[c] + (int64_t)(ne_c * ne_c);
+    cl.r_off[c + 1] = cl.r_off[c] + (int64_t)(ne_c * nc_c);
+  }
+  if (maxext > 2048) return "preconditioner cluster too large (> 2048 unknowns); reduce the cell size";
+  cl.ext_slot.resize(cl.ext_ptr[cl.nc]);
+  cl.core_pos.resize(cl.core_ptr[cl.nc]);
+  cl.core_slot.resize(cl.core_ptr[cl.nc]);
+  for (int c = 0; c < cl.nc; c++) {
+    std::copy(ext[c].begin(), ext[c].end(), cl.ext_slot.begin() + cl.ext_ptr[c]);
+    for (size_t i = 0; i < core[c].size(); i++) {
+      int s = core[c][i];
+      cl.core_slot[cl.core_ptr[c] + i] = s;
+      cl.core_pos[cl.core_ptr[c] + i] = (int)(std::lower_bound(ext[c].begin(), ext[c].end(), s) - ext[c].begin());
+    }
+  }
+  return "";
+}
+
+void build_local_terms(const Geometry &g, const Layout &L, LocalTerms &lt) {
+  // per edge row: up to 5 neighbours (itself and the other edges of its two triangles)
+  std::vector<std::vector<std::pair<int, std::array<double, 4>>>> rows(g.ne);
+  for (int T = 0; T < g.nt; T++) {
+    const double *n = &g.nrm[3 * T];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        std::array<double, 4> acc = {0, 0, 0, 0};
+        for (int q = 0; q < NQ; q++) {
+          size_t ip = (size_t)T * NQ + q;
+          const double *r = &g.qp[3 * ip];
+          double w = g.qw[ip], sg = L.sigma[ip];
+          double gi[3], fj[3];
+          int ei = g.tedge[3 * T + i], ej = g.tedge[3 * T + j];
+          double ci = g.tsign[3 * T + i] * g.elen[ei] / (2 * g.area[T]);
+          double cj = g.tsign[3 * T + j] * g.elen[ej] / (2 * g.area[T]);
+          for (int a = 0; a < 3; a++) {
+            gi[a] = ci * (r[a] - g.v[3 * g.t[3 * T + i] + a]);
+            fj[a] = cj * (r[a] - g.v[3 * g.t[3 * T + j] + a]);
+          }
+          double nf[3] = {n[1] * fj[2] - n[2] * fj[1], n[2] * fj[0] - n[0] * fj[2], n[0] * fj[1] - n[1] * fj[0]};
+          double gn[3] = {gi[1] * n[2] - gi[2] * n[1], gi[2] * n[0] - gi[0] * n[2], gi[0] * n[1] - gi[1] * n[0]};
+          acc[0] += w * (gi[0] * fj[0] + gi[1] * fj[1] + gi[2] * fj[2]);
+          acc[1] += w * (gi[0] * nf[0] + gi[1] * nf[1] + gi[2] * nf[2]);
+          acc[2] += w * sg * (gn[0] * nf[0] + gn[1] * nf[1] + gn[2] * nf[2]);
+          acc[3] += w * sg * (gi[0] * nf[0] + gi[1] * nf[1] + gi[2] * nf[2]);
+        }
+        int ne_ = g.tedge[3 * T + i], me = g.tedge[3 * T + j];
+        auto &R = rows[ne_];
+        bool found = false;
+        for (auto &pr : R)
+          if (pr.first == me) {
+            for (int a = 0; a < 4; a++) pr.second[a] += acc[a];
+            found = true;
+          }
+        if (!found) R.push_back({me, acc});
+      }
+  }
+  lt.ptr.assign(g.ne + 1, 0);
+  for (int e = 0; e < g.ne; e++) lt.ptr[e + 1] = lt.ptr[e] + (int64_t)rows[e].size();
+  lt.col.resize(lt.ptr[g.ne]);
+  lt.val.resize(4 * lt.ptr[g.ne]);
+  for (int e = 0; e < g.ne; e++) {
+    std::sort(rows[e].begin(), rows[e].end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (size_t k = 0; k < rows[e].size(); k++) {
+      lt.col[lt.ptr[e] + k] = rows[e][k].first;
+      for (int a = 0; a < 4; a++) lt.val[4 * (lt.ptr[e] + k) + a] = rows[e][k].second[a];
+    }
+  }
 }
 
 }  // namespace scabs
