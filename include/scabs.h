@@ -60,8 +60,10 @@ typedef struct {
   void *stream;    /* hipStream_t; NULL = a stream created by the library */
   int precond;     /* 1: restricted additive Schwarz preconditioner on the exact
                       near-field matrix (boxes of side pc_cell grown by
-                      pc_overlap); 0: none */
-  double pc_cell;     /* <= 0 selects 1.5 r_near */
+                      pc_overlap); 0: none.  Where a grown box would hold
+                      more than 2048 unknowns, cell and overlap are scaled
+                      down together (factor 0.85 per try) until all fit */
+  double pc_cell;     /* <= 0 selects 2 r_near */
   double pc_overlap;  /* < 0 selects 0.75 r_near; must not exceed pc_cell */
 } scabs_opts;
 

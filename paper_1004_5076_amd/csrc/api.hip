@@ -77,9 +77,7 @@ template <typename T> struct PrecState {
   cx<T> *src = nullptr, *tri_out = nullptr;
   std::vector<DevGrid<T>> grids;   // host copies holding device pointers
   DevGrid<T> *grids_dev = nullptr;
-  Slab *slabs = nullptr;
-  int nslabs = 0;
-  size_t proj_lds = 0;
+  std::vector<GatherGrid<T>> gather;
   DevOperator<T> op;
   T inv_h = 0;
 };
@@ -108,7 +106,6 @@ struct scabs_ctx {
   // device state
   DevMem mem;
   EdgeRec *edges = nullptr;
-  int *plist = nullptr;
   int64_t *rowptr = nullptr;
   int *col = nullptr;
   int64_t nnz = 0;
@@ -178,11 +175,23 @@ static int hip_fail(scabs_ctx *c, const HipError &e) {
 // ---------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------
+// twiddle table length: a common multiple of the grid's FFT sizes (2^a or 3 2^a)
+static int twiddle_length(const GridDesc &d) {
+  int p2 = 1, three = 1;
+  for (int a = 0; a < 3; a++) {
+    int m = d.N[a];
+    if (m % 3 == 0) {
+      three = 3;
+      m /= 3;
+    }
+    p2 = std::max(p2, m);
+  }
+  return p2 * three;
+}
 template <typename T>
 static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<double>> &tw_host,
                             const std::vector<int> &tw_off, const std::vector<cx<double> *> &ghat64,
-                            const std::vector<cx<float> *> &ghat32, const std::vector<int> &plist_off,
-                            const std::vector<std::vector<int>> &plane_start, cx<T> *V4, cx<T> *S4) {
+                            const std::vector<cx<float> *> &ghat32, cx<T> *V4, cx<T> *S4) {
   const Geometry &g = c->geo;
   const Layout &L = c->lay;
   const size_t np = (size_t)g.nt * NQ;
@@ -230,8 +239,7 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   P.S4 = S4;
   // grids
   P.grids.clear();
-  std::vector<Slab> slabs;
-  size_t lds_max = 0;
+  P.gather.clear();
   for (size_t gi = 0; gi < c->grids.size(); gi++) {
     const GridDesc &d = c->grids[gi];
     DevGrid<T> G{};
@@ -246,39 +254,46 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
     size_t nphys = (size_t)d.n[0] * d.n[1] * d.n[2];
     G.phys = c->mem.alloc<cx<T>>(8 * nphys);
     G.spec = c->mem.alloc<cx<T>>(8 * (size_t)d.n[0] * d.N[1] * d.N[2]);
-    int twL = std::max(d.N[0], std::max(d.N[1], d.N[2]));
+    int twL = twiddle_length(d);
     G.twL = twL;
-    std::vector<cx<T>> tw(twL / 2);
-    for (int j = 0; j < twL / 2; j++) tw[j] = {(T)tw_host[tw_off[gi] + j].x, (T)tw_host[tw_off[gi] + j].y};
+    std::vector<cx<T>> tw(twL);
+    for (int j = 0; j < twL; j++) tw[j] = {(T)tw_host[tw_off[gi] + j].x, (T)tw_host[tw_off[gi] + j].y};
     G.tw = c->mem.upload(tw);
     if (sizeof(T) == sizeof(double))
       G.ghat = (const cx<T> *)ghat64[gi];
     else
       G.ghat = (const cx<T> *)ghat32[gi];
     P.grids.push_back(G);
-    // projection slabs: LDS holds nx planes of 8 fields
-    size_t plane_bytes = 8 * sizeof(cx<T>) * (size_t)d.n[1] * d.n[2];
-    size_t budget = 60 * 1024;
-    if (plane_bytes > budget) throw std::string("a grid plane does not fit the projection LDS tile");
-    int nxs = (int)std::min<size_t>(budget / plane_bytes, (size_t)d.n[0]);
-    nxs = std::max(1, std::min(nxs, 8));
-    lds_max = std::max(lds_max, plane_bytes * nxs);
-    const std::vector<int> &ps = plane_start[gi];   // size n0 + 1, anchors sorted by x
-    for (int x0 = 0; x0 < d.n[0]; x0 += nxs) {
-      Slab s;
-      s.grid = (int)gi;
-      s.x0 = x0;
-      s.nx = std::min(nxs, d.n[0] - x0);
-      int lo = std::max(0, x0 - 1), hi = std::min(d.n[0], x0 + s.nx + 1);
-      s.p0 = plist_off[gi] + ps[lo];
-      s.p1 = plist_off[gi] + ps[hi];
-      slabs.push_back(s);
+    // gather projection: the grid's points sorted by anchor cell
+    std::vector<std::pair<int64_t, int>> key;
+    for (int Tt = 0; Tt < g.nt; Tt++) {
+      if (d.which >= 0 && g.body[Tt] != d.which) continue;
+      for (int q = 0; q < NQ; q++) {
+        size_t ip = (size_t)Tt * NQ + q;
+        int ax = c->anchor[3 * ip] - d.o[0], ay = c->anchor[3 * ip + 1] - d.o[1], az = c->anchor[3 * ip + 2] - d.o[2];
+        key.push_back({((int64_t)ax * d.n[1] + ay) * d.n[2] + az, (int)ip});
+      }
     }
+    std::sort(key.begin(), key.end());
+    std::vector<int> perm(key.size());
+    std::vector<int64_t> cellptr(nphys + 1, 0);
+    std::vector<T> uu(3 * key.size());
+    for (size_t i = 0; i < key.size(); i++) {
+      perm[i] = key[i].second;
+      cellptr[key[i].first + 1]++;
+      for (int a = 0; a < 3; a++) uu[3 * i + a] = (T)c->u[3 * (size_t)key[i].second + a];
+    }
+    for (size_t k = 0; k < nphys; k++) cellptr[k + 1] += cellptr[k];
+    GatherGrid<T> GG{};
+    GG.np = (int)key.size();
+    GG.ncell = (int64_t)nphys;
+    GG.perm = c->mem.upload(perm);
+    GG.cellptr = c->mem.upload(cellptr);
+    GG.u = c->mem.upload(uu);
+    GG.src = c->mem.alloc<cx<T>>(8 * key.size());
+    P.gather.push_back(GG);
   }
   P.grids_dev = c->mem.upload(P.grids);
-  P.slabs = c->mem.upload(slabs);
-  P.nslabs = (int)slabs.size();
-  P.proj_lds = lds_max;
   P.inv_h = (T)(1.0 / c->opts.h);
   DevOperator<T> &op = P.op;
   op.np = (int)np;
@@ -305,9 +320,18 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   const Geometry &g = c->geo;
   const Layout &L = c->lay;
   hipStream_t s = c->stream;
-  double cell = c->opts.pc_cell > 0 ? c->opts.pc_cell : 1.5 * c->opts.r_near;
+  double cell = c->opts.pc_cell > 0 ? c->opts.pc_cell : 2.0 * c->opts.r_near;
   double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 0.75 * c->opts.r_near;
-  std::string e = build_clusters(g, L, cell, ov, c->cl);
+  // boxes that would hold more unknowns than one work-group inverts shrink
+  // the cell and overlap together until every cluster fits
+  std::string e;
+  for (int attempt = 0;; attempt++) {
+    bool too_large = false;
+    e = build_clusters(g, L, cell, ov, c->cl, &too_large);
+    if (!too_large || attempt == 30) break;
+    cell *= 0.85;
+    ov *= 0.85;
+  }
   if (!e.empty()) throw e;
   LocalTerms lt;
   build_local_terms(g, L, lt);
@@ -444,41 +468,23 @@ static int do_build(scabs_ctx *c) {
     if (L.isR[n]) c->nnzR += c->near.rowptr[n + 1] - c->near.rowptr[n];
   c->qp64 = c->mem.upload(g.qp);
   c->body_dev = c->mem.upload(g.body);
-  // ---- point lists per grid, sorted by anchor x ------------------------------
-  std::vector<int> plist_all, plist_off;
-  std::vector<std::vector<int>> plane_start;
-  for (const GridDesc &d : c->grids) {
-    std::vector<int> pl;
-    for (int T = 0; T < g.nt; T++) {
-      if (d.which >= 0 && g.body[T] != d.which) continue;
-      for (int q = 0; q < NQ; q++) pl.push_back(T * NQ + q);
-    }
-    std::stable_sort(pl.begin(), pl.end(), [&](int a, int b) { return c->anchor[3 * a] < c->anchor[3 * b]; });
-    std::vector<int> ps(d.n[0] + 1, 0);
-    for (int p : pl) ps[c->anchor[3 * p] - d.o[0] + 1]++;
-    for (int x = 0; x < d.n[0]; x++) ps[x + 1] += ps[x];
-    plist_off.push_back((int)plist_all.size());
-    plist_all.insert(plist_all.end(), pl.begin(), pl.end());
-    plane_start.push_back(ps);
-  }
-  c->plist = c->mem.upload(plist_all);
   // ---- twiddles and kernel spectra ---------------------------------------------
   std::vector<cx<double>> tw_all;
   std::vector<int> tw_off;
   std::vector<cx<double> *> ghat64;
   std::vector<cx<float> *> ghat32;
   for (const GridDesc &d : c->grids) {
-    int twL = std::max(d.N[0], std::max(d.N[1], d.N[2]));
+    int twL = twiddle_length(d);
     tw_off.push_back((int)tw_all.size());
-    for (int j = 0; j < twL / 2; j++) {
+    for (int j = 0; j < twL; j++) {
       double a = -2.0 * PI * j / twL;
       tw_all.push_back({std::cos(a), std::sin(a)});
     }
   }
   for (size_t gi = 0; gi < c->grids.size(); gi++) {
     const GridDesc &d = c->grids[gi];
-    int twL = std::max(d.N[0], std::max(d.N[1], d.N[2]));
-    std::vector<cx<double>> tw(tw_all.begin() + tw_off[gi], tw_all.begin() + tw_off[gi] + twL / 2);
+    int twL = twiddle_length(d);
+    std::vector<cx<double>> tw(tw_all.begin() + tw_off[gi], tw_all.begin() + tw_off[gi] + twL);
     cx<double> *tw64 = c->mem.upload(tw);
     size_t oct = (size_t)(d.N[0] / 2 + 1) * (d.N[1] / 2 + 1) * (d.N[2] / 2 + 1);
     cx<double> *g64 = c->mem.alloc<cx<double>>(oct);
@@ -543,8 +549,8 @@ static int do_build(scabs_ctx *c) {
     }
     HIPCHK(hipStreamSynchronize(s));
     tmp.release();
-    build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, plist_off, plane_start, V4, S4);
-    build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, plist_off, plane_start, V4f, S4f);
+    build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, V4, S4);
+    build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, V4f, S4f);
   }
   HIPCHK(hipStreamSynchronize(s));
   c->built = true;
@@ -563,7 +569,7 @@ template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const dou
   }
   {
     StageTimer t(c, SCABS_STAGE_PROJECT + off);
-    launch_project(P.op, P.grids_dev, P.slabs, P.nslabs, c->plist, P.proj_lds, s);
+    launch_project(P.op, P.grids, P.gather, s);
   }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);

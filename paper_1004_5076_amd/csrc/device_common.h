@@ -52,47 +52,132 @@ __device__ inline void unpack_anchor(int a, int &x, int &y, int &z) {
   z = (a >> 23) & 0x1ff;
 }
 
-// Radix-2 Stockham FFTs of `nlines` lines of length L (power of two) held in
-// LDS: element e of line l at buf[l * lstride + e * estride].  tw holds
-// exp(-2 pi i j / twL), j < twL / 2, twL >= L.  MAXB bounds the butterflies
-// per thread per stage (nlines * L / 2 <= MAXB * blockDim.x).  All threads of
-// the block must call it.
-template <typename T, int MAXB>
-__device__ void lds_fft(cx<T> *buf, int L, int nlines, int lstride, int estride, const cx<T> *tw, int twL,
-                        bool inverse) {
-  const int half = L >> 1;
-  const int nb = nlines * half;
-  int lgh = 0;
-  while ((1 << lgh) < half) lgh++;
-  for (int Ns = 1; Ns < L; Ns <<= 1) {
-    cx<T> ra[MAXB], rb[MAXB];
-    int ro[MAXB];
+// ---------------------------------------------------------------------------
+// Mixed-radix (8, 4, 2, 3) Stockham FFTs of lines held in LDS.
+// Line l (0 <= l < nlines) starts at logical index (l / nin) * lso + (l % nin) * lsi;
+// element e of a line is at + e * es; logical index a lives at buf[lpad(a)].  tw holds exp(-2 pi i j / twL) for
+// 0 <= j < twL, twL a multiple of L.  Stage with radix R and input stride
+// Ns: v_r = x[j + r L/R], v_r *= w^(r k), k = j mod Ns, w = exp(-+2 pi i/(Ns R)),
+// V = DFT_R(v), y[(j - k) R + k + r Ns] = V_r.  ELEMS bounds the elements per
+// thread (nlines * L <= ELEMS * blockDim.x).  All threads must call it.
+// ---------------------------------------------------------------------------
+template <typename T, int R> __device__ inline void dft_small(cx<T> *v, bool inv) {
+  if (R == 2) {
+    cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if (R == 3) {
+    const T h = T(0.86602540378443864676);   // sqrt(3)/2
+    cx<T> a = v[0], b = v[1], c = v[2];
+    cx<T> s = b + c, d = b - c;
+    cx<T> m = {a.x - T(0.5) * s.x, a.y - T(0.5) * s.y};
+    // i * (sign) * h * d ; forward sign -1
+    cx<T> rot = inv ? cx<T>{-h * d.y, h * d.x} : cx<T>{h * d.y, -h * d.x};
+    v[0] = a + s;
+    v[1] = m + rot;
+    v[2] = m - rot;
+  } else if (R == 4) {
+    cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3], t3 = v[1] - v[3];
+    // forward: X1 = t1 - i t3, X3 = t1 + i t3
+    cx<T> it3 = inv ? cx<T>{-t3.y, t3.x} : cx<T>{t3.y, -t3.x};
+    v[0] = t0 + t2;
+    v[2] = t0 - t2;
+    v[1] = t1 + it3;
+    v[3] = t1 - it3;
+  } else if (R == 8) {
+    const T c = T(0.70710678118654752440);
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft_small<T, 4>(e, inv);
+    dft_small<T, 4>(o, inv);
+    // twiddles W^m, W = exp(-+ 2 pi i / 8)
+    cx<T> w1 = inv ? cx<T>{c * (o[1].x - o[1].y), c * (o[1].x + o[1].y)}
+                   : cx<T>{c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)};
+    cx<T> w2 = inv ? cx<T>{-o[2].y, o[2].x} : cx<T>{o[2].y, -o[2].x};
+    cx<T> w3 = inv ? cx<T>{-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y)}
+                   : cx<T>{c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)};
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + w1;
+    v[5] = e[1] - w1;
+    v[2] = e[2] + w2;
+    v[6] = e[2] - w2;
+    v[3] = e[3] + w3;
+    v[7] = e[3] - w3;
+  }
+}
+
+// LDS address swizzle for the FFT buffers.  For 16-byte (FP64 complex)
+// elements one pad element every 16 breaks the power-of-two strides of
+// Stockham writes and of strided lines; 8-byte elements measured faster
+// unpadded, so the swizzle is the identity there.
+template <typename T> __device__ inline int lpad(int a) { return sizeof(T) == 8 ? a + (a >> 4) : a; }
+template <typename T> __host__ __device__ inline int lpad_size(int n) {
+  return sizeof(T) == 8 ? n + (n >> 4) + 1 : n;
+}
+
+template <typename T, int R, int NB>
+__device__ inline void stockham_stage(cx<T> *buf, int L, int nlines, int nin, int lso, int lsi, int es, int Ns,
+                                      const cx<T> *tw, int twL, bool inv) {
+  const int LR = L / R;
+  const int nb = nlines * LR;
+  cx<T> v[NB][R];
+  int ob[NB];
 #pragma unroll
-    for (int c = 0; c < MAXB; c++) {
-      int t = threadIdx.x + c * blockDim.x;
-      if (t < nb) {
-        int line = t >> lgh, j = t & (half - 1);
-        cx<T> *base = buf + line * lstride;
-        cx<T> a = base[j * estride], b = base[(j + half) * estride];
-        int k = j & (Ns - 1);
-        cx<T> w = tw[k * (twL / (2 * Ns))];
-        if (inverse) w.y = -w.y;
-        b = b * w;
-        ra[c] = a + b;
-        rb[c] = a - b;
-        ro[c] = line * lstride + ((j - k) * 2 + k) * estride;
-      }
-    }
-    __syncthreads();
+  for (int c = 0; c < NB; c++) {
+    const int b = threadIdx.x + c * blockDim.x;
+    if (b < nb) {
+      const int line = b / LR, j = b - line * LR;
+      const int base = (line / nin) * lso + (line % nin) * lsi;
+      const int k = j % Ns;
 #pragma unroll
-    for (int c = 0; c < MAXB; c++) {
-      int t = threadIdx.x + c * blockDim.x;
-      if (t < nb) {
-        buf[ro[c]] = ra[c];
-        buf[ro[c] + Ns * estride] = rb[c];
+      for (int r = 0; r < R; r++) v[c][r] = buf[lpad<T>(base + (j + r * LR) * es)];
+      if (k) {
+        const int step = (twL / (Ns * R)) * k;
+#pragma unroll
+        for (int r = 1; r < R; r++) {
+          cx<T> w = tw[r * step];
+          if (inv) w.y = -w.y;
+          v[c][r] = v[c][r] * w;
+        }
       }
+      dft_small<T, R>(v[c], inv);
+      ob[c] = base + ((j - k) * R + k) * es;
     }
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NB; c++) {
+    const int b = threadIdx.x + c * blockDim.x;
+    if (b < nb) {
+#pragma unroll
+      for (int r = 0; r < R; r++) buf[lpad<T>(ob[c] + r * Ns * es)] = v[c][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int ELEMS>
+__device__ void lds_fft_mr(cx<T> *buf, int L, int nlines, int nin, int lso, int lsi, int es, const cx<T> *tw, int twL,
+                           bool inv) {
+  int m = L, Ns = 1;
+  while (m > 1) {
+    if (m % 8 == 0) {
+      stockham_stage<T, 8, (ELEMS + 7) / 8>(buf, L, nlines, nin, lso, lsi, es, Ns, tw, twL, inv);
+      m /= 8;
+      Ns *= 8;
+    } else if (m % 4 == 0) {
+      stockham_stage<T, 4, (ELEMS + 3) / 4>(buf, L, nlines, nin, lso, lsi, es, Ns, tw, twL, inv);
+      m /= 4;
+      Ns *= 4;
+    } else if (m % 2 == 0) {
+      stockham_stage<T, 2, (ELEMS + 1) / 2>(buf, L, nlines, nin, lso, lsi, es, Ns, tw, twL, inv);
+      m /= 2;
+      Ns *= 2;
+    } else {
+      stockham_stage<T, 3, (ELEMS + 2) / 3>(buf, L, nlines, nin, lso, lsi, es, Ns, tw, twL, inv);
+      m /= 3;
+      Ns *= 3;
+    }
   }
 }
 

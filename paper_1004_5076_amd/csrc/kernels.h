@@ -1,5 +1,7 @@
 // Launch interfaces of the HIP kernels.
 #pragma once
+#include <vector>
+
 #include "internal.h"
 
 namespace scabs {
@@ -19,10 +21,16 @@ template <typename T> struct DevGrid {
   const cx<T> *tw;   // exp(-2 pi i j / twL), j < twL/2
 };
 
-// x-slab of a grid handled by one projection work-group
-struct Slab {
-  int grid, x0, nx;
-  int p0, p1;        // range in the grid's anchor-x-sorted point list
+// Per-grid point lists for the gather projection: the grid's points sorted by
+// anchor cell (x, y, z), cell ranges, and per sorted point its offset from
+// the anchor (grid units).
+template <typename T> struct GatherGrid {
+  int np;                  // points in this grid
+  int64_t ncell;           // n0 n1 n2
+  const int *perm;         // sorted index -> point id
+  const int64_t *cellptr;  // ncell + 1
+  const T *u;              // 3 per sorted point
+  cx<T> *src;              // 8 per sorted point (written each product)
 };
 
 template <typename T> struct DevOperator {
@@ -50,8 +58,8 @@ hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int t
 // ---- matvec steps ------------------------------------------------------------
 template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s);
 template <typename T>
-void launch_project(const DevOperator<T> &op, const DevGrid<T> *grids_dev, const Slab *slabs, int nslabs,
-                    const int *plist, size_t lds_bytes, hipStream_t s);
+void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids,
+                    const std::vector<GatherGrid<T>> &gg, hipStream_t s);
 template <typename T>
 void launch_interp_test(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, T inv_h,
                         hipStream_t s);

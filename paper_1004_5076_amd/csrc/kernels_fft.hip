@@ -10,110 +10,125 @@
 
 namespace scabs {
 
-constexpr int FFT_THREADS = 256;
 constexpr size_t LDS_BUDGET = 64 * 1024;
-// butterflies per thread per stage held in registers by the x-line kernel
-template <typename T> struct XStage { static constexpr int value = 16; };
-template <> struct XStage<double> { static constexpr int value = 8; };
+// threads per work-group and elements per thread held in registers by one
+// Stockham stage (measured: 256 x 32 for FP32, 512 x 8 for FP64)
+template <typename T> struct FftCfg {
+  static constexpr int threads = 256, elems = 32;
+};
+template <> struct FftCfg<double> {
+  static constexpr int threads = 512, elems = 8;
+};
 
+// P consecutive x planes of one field per work-group: y-z transforms.
+// Forward: physical n1 x n2 plane -> zero-padded N1 x N2 spectrum (z lines
+// with data first, then every y line).  Inverse: the reverse, keeping n1 x n2.
 template <typename T>
-__global__ void __launch_bounds__(FFT_THREADS)
+__global__ void __launch_bounds__(FftCfg<T>::threads)
 plane_fwd_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n0, int n1, int n2, int N1, int N2,
-                 const cx<T> *__restrict__ tw, int twL) {
+                 int P, const cx<T> *__restrict__ tw, int twL) {
   extern __shared__ unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
-  const int x = blockIdx.x, f = blockIdx.y;
+  const int f = blockIdx.y, x0 = blockIdx.x * P;
+  const int np = min(P, n0 - x0);
   const int M = N1 * N2;
-  const cx<T> *src = phys + ((size_t)f * n0 + x) * n1 * n2;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    int y = i / N2, z = i - y * N2;
-    buf[i] = (y < n1 && z < n2) ? src[y * n2 + z] : czero<T>();
+  const cx<T> *src = phys + ((size_t)f * n0 + x0) * n1 * n2;
+  for (int i = threadIdx.x; i < np * M; i += blockDim.x) {
+    const int pl = i / M, r = i - pl * M, y = r / N2, z = r - y * N2;
+    buf[lpad<T>(i)] = (y < n1 && z < n2) ? src[(size_t)pl * n1 * n2 + y * n2 + z] : czero<T>();
   }
   __syncthreads();
-  lds_fft<T, 8>(buf, N2, n1, N2, 1, tw, twL, false);   // z lines with data
-  lds_fft<T, 8>(buf, N1, N2, 1, N2, tw, twL, false);   // y lines
-  cx<T> *dst = spec + ((size_t)f * n0 + x) * M;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) dst[i] = buf[i];
+  lds_fft_mr<T, FftCfg<T>::elems>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, false);   // z lines with data
+  lds_fft_mr<T, FftCfg<T>::elems>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, false);   // y lines
+  cx<T> *dst = spec + ((size_t)f * n0 + x0) * M;
+  for (int i = threadIdx.x; i < np * M; i += blockDim.x) dst[i] = buf[lpad<T>(i)];
 }
 
 template <typename T>
-__global__ void __launch_bounds__(FFT_THREADS)
+__global__ void __launch_bounds__(FftCfg<T>::threads)
 plane_inv_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n0, int n1, int n2, int N1, int N2,
-                 const cx<T> *__restrict__ tw, int twL) {
+                 int P, const cx<T> *__restrict__ tw, int twL) {
   extern __shared__ unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
-  const int x = blockIdx.x, f = blockIdx.y;
+  const int f = blockIdx.y, x0 = blockIdx.x * P;
+  const int np = min(P, n0 - x0);
   const int M = N1 * N2;
-  const cx<T> *src = spec + ((size_t)f * n0 + x) * M;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) buf[i] = src[i];
+  const cx<T> *src = spec + ((size_t)f * n0 + x0) * M;
+  for (int i = threadIdx.x; i < np * M; i += blockDim.x) buf[lpad<T>(i)] = src[i];
   __syncthreads();
-  lds_fft<T, 8>(buf, N1, N2, 1, N2, tw, twL, true);    // y lines
-  lds_fft<T, 8>(buf, N2, n1, N2, 1, tw, twL, true);    // z lines that are kept
-  cx<T> *dst = phys + ((size_t)f * n0 + x) * n1 * n2;
-  for (int i = threadIdx.x; i < n1 * n2; i += blockDim.x) {
-    int y = i / n2, z = i - y * n2;
-    dst[i] = buf[y * N2 + z];
+  lds_fft_mr<T, FftCfg<T>::elems>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, true);    // y lines
+  lds_fft_mr<T, FftCfg<T>::elems>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, true);    // z lines that are kept
+  cx<T> *dst = phys + ((size_t)f * n0 + x0) * n1 * n2;
+  for (int i = threadIdx.x; i < np * n1 * n2; i += blockDim.x) {
+    const int pl = i / (n1 * n2), r = i - pl * n1 * n2, y = r / n2, z = r - y * n2;
+    dst[i] = buf[lpad<T>(pl * M + y * N2 + z)];
   }
 }
 
 // mode 0: forward x FFT, product with ghat, inverse; x < n0 kept.
 // mode 1: forward x FFT only over the full length (n0 == N0).
 template <typename T>
-__global__ void __launch_bounds__(FFT_THREADS)
+__global__ void __launch_bounds__(FftCfg<T>::threads)
 xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, const cx<T> *__restrict__ ghat,
              const cx<T> *__restrict__ tw, int twL, int mode) {
   extern __shared__ unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);   // [c][x]
   const int f = blockIdx.y, b0 = blockIdx.x * C;
   const int M = N1 * N2;
+  const int nl = min(C, M - b0);
   cx<T> *base = spec + (size_t)f * n0 * M;
-  for (int i = threadIdx.x; i < C * N0; i += blockDim.x) {
-    int x = i / C, c = i - x * C;
-    cx<T> v = czero<T>();
-    if (x < n0 && b0 + c < M) v = base[(size_t)x * M + b0 + c];
-    buf[c * N0 + x] = v;
+  const int LS = N0 + 1;   // odd line stride: the staging loop writes across lines
+  for (int i = threadIdx.x; i < nl * N0; i += blockDim.x) {
+    const int x = i / nl, c = i - x * nl;
+    buf[lpad<T>(c * LS + x)] = x < n0 ? base[(size_t)x * M + b0 + c] : czero<T>();
   }
   __syncthreads();
-  lds_fft<T, XStage<T>::value>(buf, N0, C, N0, 1, tw, twL, false);
+  lds_fft_mr<T, FftCfg<T>::elems>(buf, N0, nl, 1, LS, 0, 1, tw, twL, false);
   if (mode == 0) {
     const int h1 = N1 / 2 + 1, h2 = N2 / 2 + 1;
-    for (int i = threadIdx.x; i < C * N0; i += blockDim.x) {
-      int c = i / N0, kx = i - c * N0;
-      int b = b0 + c;
-      if (b >= M) continue;
-      int ky = b / N2, kz = b - ky * N2;
-      int ax = min(kx, N0 - kx), ay = min(ky, N1 - ky), az = min(kz, N2 - kz);
-      buf[i] = buf[i] * ghat[((size_t)ax * h1 + ay) * h2 + az];
+    for (int i = threadIdx.x; i < nl * N0; i += blockDim.x) {
+      const int c = i / N0, kx = i - c * N0;
+      const int b = b0 + c;
+      const int ky = b / N2, kz = b - ky * N2;
+      const int ax = min(kx, N0 - kx), ay = min(ky, N1 - ky), az = min(kz, N2 - kz);
+      const int a = lpad<T>(c * LS + kx);
+      buf[a] = buf[a] * ghat[((size_t)ax * h1 + ay) * h2 + az];
     }
     __syncthreads();
-    lds_fft<T, XStage<T>::value>(buf, N0, C, N0, 1, tw, twL, true);
+    lds_fft_mr<T, FftCfg<T>::elems>(buf, N0, nl, 1, LS, 0, 1, tw, twL, true);
   }
-  for (int i = threadIdx.x; i < C * n0; i += blockDim.x) {
-    int x = i / C, c = i - x * C;
-    if (b0 + c < M) base[(size_t)x * M + b0 + c] = buf[c * N0 + x];
+  for (int i = threadIdx.x; i < nl * n0; i += blockDim.x) {
+    const int x = i / nl, c = i - x * nl;
+    base[(size_t)x * M + b0 + c] = buf[lpad<T>(c * LS + x)];
   }
 }
 
 template <typename T> static int xline_lines(int N0) {
-  int C = (int)(LDS_BUDGET / (sizeof(cx<T>) * (size_t)N0));
-  C = std::max(1, std::min(C, 16));
-  // butterflies per thread per stage must fit the register staging
-  while (C > 1 && (size_t)C * N0 / 2 > (size_t)XStage<T>::value * FFT_THREADS) C /= 2;
-  return C;
+  int C = (int)std::min<size_t>(LDS_BUDGET / (sizeof(cx<T>) * (size_t)lpad_size<T>(N0 + 1)),
+                                (size_t)FftCfg<T>::elems * FftCfg<T>::threads / N0);
+  return std::max(1, std::min(C, 16));
+}
+template <typename T> static size_t xline_lds(int N0, int C) { return sizeof(cx<T>) * (size_t)lpad_size<T>(C * (N0 + 1)); }
+template <typename T> static int planes_per_group(int N1, int N2) {
+  int P = (int)std::min<size_t>(LDS_BUDGET / 2 / (sizeof(cx<T>) * (size_t)lpad_size<T>(N1 * N2)),
+                                (size_t)FftCfg<T>::elems * FftCfg<T>::threads / ((size_t)N1 * N2));
+  return std::max(1, P);
 }
 
 template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
-  size_t plane_lds = sizeof(cx<T>) * (size_t)N1 * N2;
-  hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3(n0, 8), dim3(FFT_THREADS), plane_lds, s, g.phys, g.spec, n0, n1, n2, N1,
-                     N2, g.tw, g.twL);
-  int C = xline_lines<T>(N0);
-  int nb = (N1 * N2 + C - 1) / C;
-  hipLaunchKernelGGL(xline_kernel<T>, dim3(nb, 8), dim3(FFT_THREADS), sizeof(cx<T>) * (size_t)C * N0, s, g.spec, n0,
-                     N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
-  hipLaunchKernelGGL(plane_inv_kernel<T>, dim3(n0, 8), dim3(FFT_THREADS), plane_lds, s, g.spec, g.phys, n0, n1, n2, N1,
-                     N2, g.tw, g.twL);
+  const int P = planes_per_group<T>(N1, N2);
+  const size_t plane_lds = sizeof(cx<T>) * (size_t)lpad_size<T>(P * N1 * N2);
+  const int npg = (n0 + P - 1) / P;
+  hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3(npg, 8), dim3(FftCfg<T>::threads), plane_lds, s, g.phys, g.spec, n0, n1, n2, N1,
+                     N2, P, g.tw, g.twL);
+  const int C = xline_lines<T>(N0);
+  const int nb = (N1 * N2 + C - 1) / C;
+  hipLaunchKernelGGL(xline_kernel<T>, dim3(nb, 8), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s, g.spec, n0, N0, N1, N2,
+                     C, g.ghat, g.tw, g.twL, 0);
+  hipLaunchKernelGGL(plane_inv_kernel<T>, dim3(npg, 8), dim3(FftCfg<T>::threads), plane_lds, s, g.spec, g.phys, n0, n1, n2, N1,
+                     N2, P, g.tw, g.twL);
 }
 template void launch_conv<float>(const DevGrid<float> &, hipStream_t);
 template void launch_conv<double>(const DevGrid<double> &, hipStream_t);
@@ -166,13 +181,14 @@ hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int t
   }
   hipLaunchKernelGGL(sample_kernel, dim3(1024), dim3(256), 0, s, full, N0, N1, N2, d.n[0], d.n[1], d.n[2], h, d.k);
   // forward 3-D FFT: y-z planes (full), then x lines (full length); one field
-  size_t plane_lds = sizeof(cx<double>) * (size_t)N1 * N2;
-  hipLaunchKernelGGL(plane_fwd_kernel<double>, dim3(N0, 1), dim3(FFT_THREADS), plane_lds, s, full, spec, N0, N1, N2, N1,
-                     N2, tw64, twL);
+  const int P = planes_per_group<double>(N1, N2);
+  const size_t plane_lds = sizeof(cx<double>) * (size_t)lpad_size<double>(P * N1 * N2);
+  hipLaunchKernelGGL(plane_fwd_kernel<double>, dim3((N0 + P - 1) / P, 1), dim3(FftCfg<double>::threads), plane_lds, s, full, spec,
+                     N0, N1, N2, N1, N2, P, tw64, twL);
   int C = xline_lines<double>(N0);
   int nb = (N1 * N2 + C - 1) / C;
-  hipLaunchKernelGGL(xline_kernel<double>, dim3(nb, 1), dim3(FFT_THREADS), sizeof(cx<double>) * (size_t)C * N0, s, spec,
-                     N0, N0, N1, N2, C, (const cx<double> *)nullptr, tw64, twL, 1);
+  hipLaunchKernelGGL(xline_kernel<double>, dim3(nb, 1), dim3(FftCfg<double>::threads), xline_lds<double>(N0, C), s, spec, N0, N0, N1,
+                     N2, C, (const cx<double> *)nullptr, tw64, twL, 1);
   hipLaunchKernelGGL(extract_octant, dim3(256), dim3(256), 0, s, spec, ghat64, ghat32, N0, N1, N2);
   e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(s);

@@ -42,89 +42,129 @@ template void launch_unpack<float>(const DevOperator<float> &, const double *, h
 template void launch_unpack<double>(const DevOperator<double> &, const double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// projection: every quadrature point spreads w_q * (J, div J, M, div M) of its
+// projection: every quadrature point spreads w_q (J, div J, M, div M) of its
 // medium onto the 27 nodes around its anchor with tensor Lagrange weights.
-// One work-group owns an x-slab of one grid in LDS and accumulates the points
-// anchored in the slab and its two neighbouring planes.
+// Gather form: (1) per point the 8 weighted source values, written in the
+// grid's cell-sorted order; (2) one thread per node sums the points of the 27
+// cells around it.  No atomics; the summation order is fixed.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
-project_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restrict__ tris, const cx<T> *__restrict__ src,
-               const DevGrid<T> *__restrict__ grids, const Slab *__restrict__ slabs, const int *__restrict__ plist) {
-  extern __shared__ unsigned char smem_raw[];
-  cx<T> *acc = reinterpret_cast<cx<T> *>(smem_raw);
-  const Slab sl = slabs[blockIdx.x];
-  const DevGrid<T> &g = grids[sl.grid];
-  const int n1 = g.n[1], n2 = g.n[2], plane = n1 * n2;
-  const int nxs = sl.nx;
-  const int fstride = nxs * plane;
-  for (int i = threadIdx.x; i < 8 * fstride; i += blockDim.x) acc[i] = czero<T>();
-  __syncthreads();
-  const bool ext = g.which < 0;
-  for (int pi = sl.p0 + threadIdx.x; pi < sl.p1; pi += blockDim.x) {
-    const int p = plist[pi];
-    const PointRec<T> P = pts[p];
-    const TriRec<T> tr = tris[P.tri];
-    cx<T> s[8];
+point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restrict__ tris,
+                     const cx<T> *__restrict__ esrc, GatherGrid<T> g, int interior) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.np) return;
+  const PointRec<T> P = pts[g.perm[i]];
+  const TriRec<T> tr = tris[P.tri];
+  cx<T> s[8];
 #pragma unroll
-    for (int f = 0; f < 8; f++) s[f] = czero<T>();
+  for (int f = 0; f < 8; f++) s[f] = czero<T>();
 #pragma unroll
-    for (int j = 0; j < 3; j++) {
-      const int e = tr.edge[j];
-      cx<T> J = ext ? src[3 * e] : src[3 * e + 1];
-      cx<T> M = src[3 * e + 2];
-      if (!ext) M = -M;
-      for (int a = 0; a < 3; a++) {
-        axpy(s[a], P.f[3 * j + a], J);
-        axpy(s[4 + a], P.f[3 * j + a], M);
-      }
-      axpy(s[3], tr.div[j], J);
-      axpy(s[7], tr.div[j], M);
+  for (int j = 0; j < 3; j++) {
+    const int e = tr.edge[j];
+    const cx<T> J = interior ? esrc[3 * e + 1] : esrc[3 * e];
+    const cx<T> M = interior ? -esrc[3 * e + 2] : esrc[3 * e + 2];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      axpy(s[a], P.f[3 * j + a], J);
+      axpy(s[4 + a], P.f[3 * j + a], M);
     }
+    axpy(s[3], tr.div[j], J);
+    axpy(s[7], tr.div[j], M);
+  }
+  cx<T> *o = g.src + (size_t)8 * i;
 #pragma unroll
-    for (int f = 0; f < 8; f++) s[f] = s[f] * P.w;
-    int ax, ay, az;
-    unpack_anchor(P.anc, ax, ay, az);
-    ax -= g.off[0] + sl.x0;
-    ay -= g.off[1];
-    az -= g.off[2];
-    T Lx[3], Ly[3], Lz[3], d[3];
-    lagr3(P.u[0], Lx, d);
-    lagr3(P.u[1], Ly, d);
-    lagr3(P.u[2], Lz, d);
-    for (int i = 0; i < 3; i++) {
-      const int gx = ax + i - 1;
-      if (gx < 0 || gx >= nxs) continue;
-      for (int j = 0; j < 3; j++)
-        for (int k = 0; k < 3; k++) {
-          const int node = (gx * n1 + ay + j - 1) * n2 + az + k - 1;
-          const T wgt = Lx[i] * Ly[j] * Lz[k];
+  for (int f = 0; f < 8; f++) o[f] = s[f] * P.w;
+}
+
+// One work-group per x plane of a grid: the points anchored in planes
+// x-1..x+1 (contiguous in the cell-sorted list) are staged through LDS in
+// chunks; each thread owns nodes (y, z) of the plane and sums the points of
+// its 27 neighbouring cells that fall in the chunk.
+constexpr int GA_THREADS = 256;
+constexpr int GA_CHUNK = 1024;
+template <typename T>
+__global__ void __launch_bounds__(GA_THREADS) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
+  __shared__ cx<T> s_src[GA_CHUNK * 8];
+  __shared__ T s_u[GA_CHUNK * 3];
+  const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
+  const int plane = n1 * n2;
+  const int x = blockIdx.x;
+  const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
+  const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
+  constexpr int MAXN = 4;   // nodes per thread (plane <= MAXN * GA_THREADS)
+  cx<T> acc[MAXN][8];
 #pragma unroll
-          for (int f = 0; f < 8; f++) {
-            atomicAdd(&acc[f * fstride + node].x, wgt * s[f].x);
-            atomicAdd(&acc[f * fstride + node].y, wgt * s[f].y);
+  for (int m = 0; m < MAXN; m++)
+#pragma unroll
+    for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
+  for (int64_t c0 = P0; c0 < P1; c0 += GA_CHUNK) {
+    const int64_t c1 = min(c0 + (int64_t)GA_CHUNK, P1);
+    const int cn = (int)(c1 - c0);
+    for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) s_src[i] = g.src[(size_t)8 * c0 + i];
+    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) s_u[i] = g.u[(size_t)3 * c0 + i];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXN; m++) {
+      const int nd = threadIdx.x + m * GA_THREADS;
+      if (nd >= plane) continue;
+      const int y = nd / n2, z = nd - y * n2;
+      for (int dx = -1; dx <= 1; dx++) {
+        const int ax = x + dx;
+        if (ax < 0 || ax >= n0) continue;
+        for (int dy = -1; dy <= 1; dy++) {
+          const int ay = y + dy;
+          if (ay < 0 || ay >= n1) continue;
+          const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
+          for (int dz = -1; dz <= 1; dz++) {
+            const int az = z + dz;
+            if (az < 0 || az >= n2) continue;
+            const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
+            for (int64_t p = p0; p < p1; p++) {
+              // the node sits at offset (-dx, -dy, -dz) from this point's anchor
+              const int lp = (int)(p - c0);
+              const T ux = s_u[3 * lp], uy = s_u[3 * lp + 1], uz = s_u[3 * lp + 2];
+              const T wx = dx == 1 ? T(0.5) * ux * (ux - T(1)) : (dx == 0 ? T(1) - ux * ux : T(0.5) * ux * (ux + T(1)));
+              const T wy = dy == 1 ? T(0.5) * uy * (uy - T(1)) : (dy == 0 ? T(1) - uy * uy : T(0.5) * uy * (uy + T(1)));
+              const T wz = dz == 1 ? T(0.5) * uz * (uz - T(1)) : (dz == 0 ? T(1) - uz * uz : T(0.5) * uz * (uz + T(1)));
+              const T wgt = wx * wy * wz;
+              const cx<T> *sp = s_src + 8 * lp;
+#pragma unroll
+              for (int f = 0; f < 8; f++) axpy(acc[m][f], wgt, sp[f]);
+            }
           }
         }
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  const size_t G = (size_t)g.n[0] * plane;
-  for (int i = threadIdx.x; i < 8 * fstride; i += blockDim.x) {
-    int f = i / fstride, r = i - f * fstride;
-    g.phys[f * G + (size_t)sl.x0 * plane + r] = acc[i];
+  const size_t G = (size_t)g.ncell;
+#pragma unroll
+  for (int m = 0; m < MAXN; m++) {
+    const int nd = threadIdx.x + m * GA_THREADS;
+    if (nd >= plane) continue;
+#pragma unroll
+    for (int f = 0; f < 8; f++) dg.phys[f * G + (size_t)x * plane + nd] = acc[m][f];
   }
 }
 
 template <typename T>
-void launch_project(const DevOperator<T> &op, const DevGrid<T> *grids_dev, const Slab *slabs, int nslabs,
-                    const int *plist, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(project_kernel<T>, dim3(nslabs), dim3(256), lds_bytes, s, op.pts, op.tris, op.src, grids_dev,
-                     slabs, plist);
+void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids,
+                    const std::vector<GatherGrid<T>> &gg, hipStream_t s) {
+  for (size_t k = 0; k < grids.size(); k++) {
+    const GatherGrid<T> &g = gg[k];
+    hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256), dim3(256), 0, s, op.pts, op.tris, op.src, g,
+                       grids[k].which >= 0 ? 1 : 0);
+  }
+  for (size_t k = 0; k < grids.size(); k++) {
+    const GatherGrid<T> &g = gg[k];
+    hipLaunchKernelGGL(gather_kernel<T>, dim3(grids[k].n[0]), dim3(GA_THREADS), 0, s, grids[k], g);
+  }
 }
-template void launch_project<float>(const DevOperator<float> &, const DevGrid<float> *, const Slab *, int, const int *,
-                                    size_t, hipStream_t);
-template void launch_project<double>(const DevOperator<double> &, const DevGrid<double> *, const Slab *, int,
-                                     const int *, size_t, hipStream_t);
+template void launch_project<float>(const DevOperator<float> &, const std::vector<DevGrid<float>> &,
+                                    const std::vector<GatherGrid<float>> &, hipStream_t);
+template void launch_project<double>(const DevOperator<double> &, const std::vector<DevGrid<double>> &,
+                                     const std::vector<GatherGrid<double>> &, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // interpolation at test points + row contributions + local terms, reduced to

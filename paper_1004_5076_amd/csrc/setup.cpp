@@ -178,10 +178,15 @@ void build_layout(const Geometry &g, Layout &L) {
   L.N = 2 * L.NL + 3 * L.NR;
 }
 
+// smallest 2^a or 3 * 2^a >= 2n - 1 (sizes the mixed-radix FFT handles)
 static int fft_size(int n) {
-  int m = 1;
-  while (m < 2 * n - 1) m *= 2;
-  return std::max(m, 2);
+  int need = std::max(2 * n - 1, 2), best = 1 << 30;
+  for (int m = 1; m < (1 << 30); m *= 2) {
+    if (m >= need) best = std::min(best, m);
+    if (3 * m >= need) best = std::min(best, 3 * m);
+    if (m >= need) break;
+  }
+  return best;
 }
 
 std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std::vector<GridDesc> &grids,
@@ -218,8 +223,9 @@ std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std
     }
     if (d.n[0] >= (1 << 14) || d.n[1] >= (1 << 9) || d.n[2] >= (1 << 9))
       return "grid too large for the anchor packing (x < 16384, y,z < 512 nodes)";
-    if (d.N[0] > 2048 || d.N[1] * d.N[2] > 4096 || d.N[1] > 1024 || d.N[2] > 1024)
-      return "FFT sizes beyond the supported range (N_x <= 2048, N_y N_z <= 4096)";
+    if (d.n[1] * d.n[2] > 1024) return "grid cross-section too large for the projection tile (n_y n_z <= 1024)";
+    if (d.N[0] > 4096 || d.N[1] * d.N[2] > 4096)
+      return "FFT sizes beyond the supported range (N_x <= 4096, N_y N_z <= 4096)";
     grids.push_back(d);
   }
   return "";
@@ -372,7 +378,9 @@ void edge_slots(const Layout &L, int e, int *slots, int *nslots) {
   }
 }
 
-std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl) {
+std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl,
+                           bool *too_large) {
+  *too_large = false;
   if (!(cell > 0) || overlap < 0 || overlap > cell) return "preconditioner cell must be > 0 and overlap in [0, cell]";
   const int ne = g.ne;
   std::vector<double> mid(3 * ne);
@@ -458,7 +466,10 @@ std::string build_clusters(const Geometry &g, const Layout &L, double cell, doub
     cl.a_off[c + 1] = cl.a_off[c] + (int64_t)(ne_c * ne_c);
     cl.r_off[c + 1] = cl.r_off[c] + (int64_t)(ne_c * nc_c);
   }
-  if (maxext > 2048) return "preconditioner cluster too large (> 2048 unknowns); reduce the cell size";
+  if (maxext > 2048) {
+    *too_large = true;
+    return "preconditioner cluster too large (> 2048 unknowns); reduce the cell size";
+  }
   cl.ext_slot.resize(cl.ext_ptr[cl.nc]);
   cl.core_pos.resize(cl.core_ptr[cl.nc]);
   cl.core_slot.resize(cl.core_ptr[cl.nc]);
