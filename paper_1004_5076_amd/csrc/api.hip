@@ -119,6 +119,8 @@ struct scabs_ctx {
   int64_t nnzR = 0;
   int64_t *pc_ext_ptr = nullptr, *pc_core_ptr = nullptr, *pc_r_off = nullptr;
   int *pc_ext_slot = nullptr, *pc_core_slot = nullptr;
+  int *pc_items = nullptr;   // (cluster, first core row) per apply work-group
+  int pc_n_items = 0;
   cx<float> *pc_Rt = nullptr;
   // solver workspace (grown on demand)
   DevMem work;
@@ -364,6 +366,17 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   c->pc_core_ptr = c->mem.upload(cl.core_ptr);
   c->pc_core_slot = c->mem.upload(cl.core_slot);
   c->pc_r_off = c->mem.upload(cl.r_off);
+  {
+    const int rows = precond_rows_per_item();
+    std::vector<int> items;
+    for (int k = 0; k < cl.nc; k++)
+      for (int64_t r0 = 0; r0 < cl.core_ptr[k + 1] - cl.core_ptr[k]; r0 += rows) {
+        items.push_back(k);
+        items.push_back((int)r0);
+      }
+    c->pc_n_items = (int)(items.size() / 2);
+    c->pc_items = c->mem.upload(items);
+  }
   p.ext_ptr = c->pc_ext_ptr;
   p.ext_slot = c->pc_ext_slot;
   p.a_off = tmp.upload(cl.a_off);
@@ -386,8 +399,8 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
 
 static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y) {
   StageTimer tm(c, SCABS_STAGE_PRECOND);
-  launch_precond_apply(c->cl.nc, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot, c->pc_r_off, c->pc_Rt,
-                       x, y, c->stream);
+  launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
+                       c->pc_r_off, c->pc_Rt, x, y, c->stream);
 }
 
 static int do_build(scabs_ctx *c) {

@@ -106,6 +106,22 @@ template <typename T, int R> __device__ inline void dft_small(cx<T> *v, bool inv
   }
 }
 
+// Division by a work-group-uniform divisor d >= 1 through a multiply-high
+// (round-up method of Granlund and Montgomery): for 0 <= n < 2^31,
+// n / d = (umulhi(n, m) + n) >> s with s = ceil(log2 d),
+// m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+  unsigned m, s, d;
+};
+__host__ __device__ inline FastDiv make_fastdiv(unsigned d) {
+  unsigned s = 0;
+  while ((1u << s) < d) s++;
+  const unsigned long long two32 = 1ull << 32;
+  const unsigned m = (unsigned)((two32 * ((1ull << s) - d)) / d + 1);
+  return {m, s, d};
+}
+__device__ inline int fdiv(int n, FastDiv f) { return (int)((__umulhi((unsigned)n, f.m) + (unsigned)n) >> f.s); }
+
 // LDS address swizzle for the FFT buffers.  For 16-byte (FP64 complex)
 // elements one pad element every 16 breaks the power-of-two strides of
 // Stockham writes and of strided lines; 8-byte elements measured faster
@@ -120,19 +136,22 @@ __device__ inline void stockham_stage(cx<T> *buf, int L, int nlines, int nin, in
                                       const cx<T> *tw, int twL, bool inv) {
   const int LR = L / R;
   const int nb = nlines * LR;
+  const FastDiv dLR = make_fastdiv(LR), dnin = make_fastdiv(nin), dNs = make_fastdiv(Ns);
+  const int tstep = twL / (Ns * R);
   cx<T> v[NB][R];
   int ob[NB];
 #pragma unroll
   for (int c = 0; c < NB; c++) {
     const int b = threadIdx.x + c * blockDim.x;
     if (b < nb) {
-      const int line = b / LR, j = b - line * LR;
-      const int base = (line / nin) * lso + (line % nin) * lsi;
-      const int k = j % Ns;
+      const int line = fdiv(b, dLR), j = b - line * LR;
+      const int lo = fdiv(line, dnin);
+      const int base = lo * lso + (line - lo * nin) * lsi;
+      const int k = j - fdiv(j, dNs) * Ns;
 #pragma unroll
       for (int r = 0; r < R; r++) v[c][r] = buf[lpad<T>(base + (j + r * LR) * es)];
       if (k) {
-        const int step = (twL / (Ns * R)) * k;
+        const int step = tstep * k;
 #pragma unroll
         for (int r = 1; r < R; r++) {
           cx<T> w = tw[r * step];

@@ -114,9 +114,12 @@ void launch_exact_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, c
                            const cx<double> *blocks, cx<double> *X8, hipStream_t s);
 void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
                           const int64_t *r_off, cx<float> *Rt, int *piv, int *status, hipStream_t s);
-void launch_precond_apply(int nc, const int64_t *ext_ptr, const int *ext_slot, const int64_t *core_ptr,
-                          const int *core_slot, const int64_t *r_off, const cx<float> *Rt, const cx<double> *x,
-                          cx<double> *y, hipStream_t s);
+// rows of one cluster's core handled by one work-group of the apply kernel
+int precond_rows_per_item();
+// items: n_items pairs (cluster, first core row), rows per item as above
+void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
+                          const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                          const cx<double> *x, cx<double> *y, hipStream_t s);
 
 // ---- misc --------------------------------------------------------------------
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,

@@ -33,8 +33,9 @@ plane_fwd_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n
   const int np = min(P, n0 - x0);
   const int M = N1 * N2;
   const cx<T> *src = phys + ((size_t)f * n0 + x0) * n1 * n2;
+  const FastDiv dM = make_fastdiv(M), dN2 = make_fastdiv(N2);
   for (int i = threadIdx.x; i < np * M; i += blockDim.x) {
-    const int pl = i / M, r = i - pl * M, y = r / N2, z = r - y * N2;
+    const int pl = fdiv(i, dM), r = i - pl * M, y = fdiv(r, dN2), z = r - y * N2;
     buf[lpad<T>(i)] = (y < n1 && z < n2) ? src[(size_t)pl * n1 * n2 + y * n2 + z] : czero<T>();
   }
   __syncthreads();
@@ -59,8 +60,9 @@ plane_inv_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n
   lds_fft_mr<T, FftCfg<T>::elems>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, true);    // y lines
   lds_fft_mr<T, FftCfg<T>::elems>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, true);    // z lines that are kept
   cx<T> *dst = phys + ((size_t)f * n0 + x0) * n1 * n2;
+  const FastDiv dP = make_fastdiv(n1 * n2), dn2 = make_fastdiv(n2);
   for (int i = threadIdx.x; i < np * n1 * n2; i += blockDim.x) {
-    const int pl = i / (n1 * n2), r = i - pl * n1 * n2, y = r / n2, z = r - y * n2;
+    const int pl = fdiv(i, dP), r = i - pl * n1 * n2, y = fdiv(r, dn2), z = r - y * n2;
     dst[i] = buf[lpad<T>(pl * M + y * N2 + z)];
   }
 }
@@ -78,8 +80,9 @@ xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, co
   const int nl = min(C, M - b0);
   cx<T> *base = spec + (size_t)f * n0 * M;
   const int LS = N0 + 1;   // odd line stride: the staging loop writes across lines
+  const FastDiv dnl = make_fastdiv(nl), dN0 = make_fastdiv(N0), dN2 = make_fastdiv(N2);
   for (int i = threadIdx.x; i < nl * N0; i += blockDim.x) {
-    const int x = i / nl, c = i - x * nl;
+    const int x = fdiv(i, dnl), c = i - x * nl;
     buf[lpad<T>(c * LS + x)] = x < n0 ? base[(size_t)x * M + b0 + c] : czero<T>();
   }
   __syncthreads();
@@ -87,9 +90,9 @@ xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, co
   if (mode == 0) {
     const int h1 = N1 / 2 + 1, h2 = N2 / 2 + 1;
     for (int i = threadIdx.x; i < nl * N0; i += blockDim.x) {
-      const int c = i / N0, kx = i - c * N0;
+      const int c = fdiv(i, dN0), kx = i - c * N0;
       const int b = b0 + c;
-      const int ky = b / N2, kz = b - ky * N2;
+      const int ky = fdiv(b, dN2), kz = b - ky * N2;
       const int ax = min(kx, N0 - kx), ay = min(ky, N1 - ky), az = min(kz, N2 - kz);
       const int a = lpad<T>(c * LS + kx);
       buf[a] = buf[a] * ghat[((size_t)ax * h1 + ay) * h2 + az];
@@ -98,7 +101,7 @@ xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, co
     lds_fft_mr<T, FftCfg<T>::elems>(buf, N0, nl, 1, LS, 0, 1, tw, twL, true);
   }
   for (int i = threadIdx.x; i < nl * n0; i += blockDim.x) {
-    const int x = i / nl, c = i - x * nl;
+    const int x = fdiv(i, dnl), c = i - x * nl;
     base[(size_t)x * M + b0 + c] = buf[lpad<T>(c * LS + x)];
   }
 }

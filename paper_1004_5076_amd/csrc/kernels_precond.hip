@@ -212,20 +212,20 @@ void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core
 }
 
 // y[core] = R_c x[ext] for every cluster; each unknown is in exactly one core.
-// One work-group per cluster: 256 rows at a time, the ext columns split in
-// PA_Q contiguous quarters (coalesced reads of the column-major block),
-// partial sums reduced in LDS in a fixed order.
-constexpr int PA_ROWS = 256;
+// One work-group per item (cluster c, PA_ROWS core rows from row0): the ext
+// columns split in PA_Q contiguous parts (coalesced reads of the
+// column-major block), partial sums reduced in LDS in a fixed order.
+constexpr int PA_ROWS = 64;
 constexpr int PA_Q = 4;
 constexpr int PA_THREADS = PA_ROWS * PA_Q;
 __global__ void __launch_bounds__(PA_THREADS)
-precond_apply_kernel(const int64_t *__restrict__ ext_ptr, const int *__restrict__ ext_slot,
-                     const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
-                     const int64_t *__restrict__ r_off, const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x,
-                     cx<double> *__restrict__ y) {
+precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
+                     const int *__restrict__ ext_slot, const int64_t *__restrict__ core_ptr,
+                     const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
+                     const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y) {
   __shared__ cx<double> xs[GJ_MAXN];
   __shared__ cx<double> red[PA_Q][PA_ROWS];
-  const int c = blockIdx.x;
+  const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
@@ -234,47 +234,46 @@ precond_apply_kernel(const int64_t *__restrict__ ext_ptr, const int *__restrict_
   const cx<float> *R = Rt + r_off[c];
   const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
   const int jb = (ne * q) / PA_Q, je = (ne * (q + 1)) / PA_Q;
-  for (int i0 = 0; i0 < nc; i0 += PA_ROWS) {
-    const int i = i0 + il;
-    double ar = 0, ai = 0;
-    if (i < nc) {
-      // four independent partial sums keep several loads in flight
-      double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
-      int j = jb;
-      for (; j + 4 <= je; j += 4) {
+  const int i = i0 + il;
+  double ar = 0, ai = 0;
+  if (i < nc) {
+    // four independent partial sums keep several loads in flight
+    double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
+    int j = jb;
+    for (; j + 4 <= je; j += 4) {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const cx<float> rv = R[(size_t)(j + u) * nc + i];
-          const cx<double> xv = xs[j + u];
-          pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-          pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
-        }
+      for (int u = 0; u < 4; u++) {
+        const cx<float> rv = R[(size_t)(j + u) * nc + i];
+        const cx<double> xv = xs[j + u];
+        pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
+        pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
       }
-      for (; j < je; j++) {
-        const cx<float> rv = R[(size_t)j * nc + i];
-        const cx<double> xv = xs[j];
-        pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-        pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
-      }
-      ar = (pr[0] + pr[1]) + (pr[2] + pr[3]);
-      ai = (pi[0] + pi[1]) + (pi[2] + pi[3]);
     }
-    red[q][il] = {ar, ai};
-    __syncthreads();
-    if (q == 0 && i < nc) {
-      cx<double> t = red[0][il];
-      for (int k = 1; k < PA_Q; k++) t += red[k][il];
-      y[core_slot[core_ptr[c] + i]] = t;
+    for (; j < je; j++) {
+      const cx<float> rv = R[(size_t)j * nc + i];
+      const cx<double> xv = xs[j];
+      pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
+      pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
     }
-    __syncthreads();
+    ar = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+    ai = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+  }
+  red[q][il] = {ar, ai};
+  __syncthreads();
+  if (q == 0 && i < nc) {
+    cx<double> t = red[0][il];
+    for (int k = 1; k < PA_Q; k++) t += red[k][il];
+    y[core_slot[core_ptr[c] + i]] = t;
   }
 }
 
-void launch_precond_apply(int nc, const int64_t *ext_ptr, const int *ext_slot, const int64_t *core_ptr,
-                          const int *core_slot, const int64_t *r_off, const cx<float> *Rt, const cx<double> *x,
-                          cx<double> *y, hipStream_t s) {
-  hipLaunchKernelGGL(precond_apply_kernel, dim3(nc), dim3(PA_THREADS), 0, s, ext_ptr, ext_slot, core_ptr, core_slot,
-                     r_off, Rt, x, y);
+int precond_rows_per_item() { return PA_ROWS; }
+
+void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
+                          const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                          const cx<double> *x, cx<double> *y, hipStream_t s) {
+  hipLaunchKernelGGL(precond_apply_kernel, dim3(n_items), dim3(PA_THREADS), 0, s, items, ext_ptr, ext_slot, core_ptr,
+                     core_slot, r_off, Rt, x, y);
 }
 
 }  // namespace scabs
