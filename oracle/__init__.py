@@ -100,6 +100,14 @@ def lib():
         L.or_grid_project.argtypes = [P, zp, C.c_int, ip, ip, zp]
         L.or_grid_interp_rows.restype = C.c_int
         L.or_grid_interp_rows.argtypes = [P, C.c_int, ip, ip, zp, zp]
+        L.or_grid_interp_rows_t.restype = C.c_int
+        L.or_grid_interp_rows_t.argtypes = [P, C.c_int, ip, ip, zp, zp]
+        L.or_grid_project_t.restype = C.c_int
+        L.or_grid_project_t.argtypes = [P, C.c_int, ip, ip, zp, zp]
+        L.or_grid_point_fields.restype = C.c_int
+        L.or_grid_point_fields.argtypes = [P, C.c_int, ip, ip, zp, zp]
+        L.or_point_near_corr.restype = C.c_int
+        L.or_point_near_corr.argtypes = [P, zp, ip, C.c_long, zp, zp]
         _lib = L
     return _lib
 
@@ -298,6 +306,50 @@ class Oracle:
         E, _ = self.fields_at(x, dip.pos[None, :], int(dip.body))
         return float(P0 - 0.5 * np.real(np.vdot(dip.moment, E[0])))
 
+    # -- sigma gradient (adjoint method) --------------------------------------
+    def edge_rows(self):
+        """(E, H, eq14) row of every edge; eq14 row -1 on sigma-free edges."""
+        NL, NR = self.NL, self.NR
+        r = self.isR != 0
+        rE = np.where(r, 2 * NL + self.eidx, self.eidx)
+        rH = np.where(r, 2 * NL + NR + self.eidx, NL + self.eidx)
+        r14 = np.where(r, 2 * NL + 2 * NR + self.eidx, -1)
+        return rE, rH, r14
+
+    def sigma_gradient_points(self, lam, Ee, Ei, Einc=None) -> np.ndarray:
+        """d f / d sigma_q = 2 Re[lam^T (db/dsigma_q - dA/dsigma_q x)] at every
+        quadrature point, for A^T lam = g.  sigma enters A only through the
+        absorber-edge tests at the points (eq13 rotated by n x and eq14, Appendix
+        A): row H_n carries w sigma (f_n x n).E_e^+(q) and row eq14_n carries
+        -w sigma f_n.E_i^-(q); b's eq14 row carries w sigma f_n.E_inc(q).  So the
+        derivative at q is w_q [t14.(E_inc + E_i^-) - (tH x n).E_e^+] with
+        tH = sum lam_H f, t14 = sum lam_14 f over the absorber edges at q."""
+        fv, _ = self.point_basis()
+        tri = np.repeat(np.arange(self.nt), NQ)
+        e = self.tedge[tri]
+        isr = (self.isR[e] != 0)
+        _, rH, r14 = self.edge_rows()
+        lh = np.where(isr, lam[rH[e]], 0)
+        l14 = np.where(isr, lam[np.maximum(r14[e], 0)], 0)
+        tH = np.einsum("pj,pja->pa", lh, fv)
+        t14 = np.einsum("pj,pja->pa", l14, fv)
+        n = np.repeat(self.nrm, NQ, axis=0)
+        Et = Ei if Einc is None else Ei + Einc
+        val = self.qw * (np.einsum("pa,pa->p", t14, Et) - np.einsum("pa,pa->p", np.cross(tH, n), Ee))
+        return 2.0 * np.real(val)
+
+    def field_matrix(self, pts, region: int) -> np.ndarray:
+        """Q with E(pts) = Q x (scattered field of `region`), rows (point, comp)."""
+        pts = np.asarray(pts, float).reshape(-1, 3)
+        Q = np.zeros((3 * pts.shape[0], self.N), complex)
+        e = np.zeros(self.N, complex)
+        for n in range(self.N):
+            e[n] = 1.0
+            E, _ = self.fields_at(e, pts, region)
+            Q[:, n] = E.ravel()
+            e[n] = 0.0
+        return Q
+
     # -- pFFT ----------------------------------------------------------------
     def pfft(self, h: float, r_near: float) -> "PFFT":
         return PFFT(self, h, r_near)
@@ -397,6 +449,72 @@ class PFFT:
     def matvec(self, x: np.ndarray) -> np.ndarray:
         return self.grid_apply(x) + self.C_near @ x
 
+    def _conv(self, Hhat, dims, Q):
+        n0, n1, n2 = dims
+        Phi = np.empty_like(Q)
+        for f in range(8):
+            Qp = np.zeros((2 * n0, 2 * n1, 2 * n2), complex)
+            Qp[:n0, :n1, :n2] = Q[f]
+            Phi[f] = np.fft.ifftn(np.fft.fftn(Qp) * Hhat)[:n0, :n1, :n2]
+        return Phi
+
+    def grid_apply_t(self, z: np.ndarray) -> np.ndarray:
+        """transpose of grid_apply: test-side sources (value and gradient
+        weights), the same symmetric lattice convolution, then the transposed
+        projection back to unknowns"""
+        o = self.o
+        L = lib()
+        z = np.ascontiguousarray(z, complex)
+        y = np.zeros(o.N, complex)
+        for which, lo, dims, k, Hhat in self.grids:
+            G = int(np.prod(dims))
+            S = np.zeros(8 * G, complex)
+            assert L.or_grid_interp_rows_t(o._c, which, lo, dims, z, S) == 0
+            Phi = self._conv(Hhat, dims, S.reshape(8, *dims))
+            assert L.or_grid_project_t(o._c, which, lo, dims, np.ascontiguousarray(Phi.ravel()), y) == 0
+        return y
+
+    def rmatvec(self, z: np.ndarray) -> np.ndarray:
+        """A~^T z"""
+        return self.grid_apply_t(z) + self.C_near.T @ z
+
+    def solve_t(self, g: np.ndarray, tol: float = 1e-12, restart: int = 200, maxiter: int = 50) -> np.ndarray:
+        """A~^T lam = g by GMRES, preconditioned by the transposed sparse LU of
+        the exact near-field part; true residual checked."""
+        N = self.o.N
+        near = self.o.pair_coo(self.pairs, 1) + self.o.local_coo()
+        lu = spla.splu(near.T.tocsc())
+        M = spla.LinearOperator((N, N), matvec=lu.solve, dtype=complex)
+        op = spla.LinearOperator((N, N), matvec=self.rmatvec, dtype=complex)
+        lam, info = spla.gmres(op, g, rtol=tol, atol=0.0, restart=restart, maxiter=maxiter, M=M)
+        res = np.linalg.norm(self.rmatvec(lam) - g) / np.linalg.norm(g)
+        if info != 0 or res > 100 * tol:
+            raise RuntimeError("oracle adjoint GMRES did not converge (info=%d, residual %.2e)" % (info, res))
+        return lam
+
+    def point_fields(self, x: np.ndarray):
+        """One-sided pointwise fields of this operator at every quadrature point:
+        grid interpolation, plus exact-minus-grid of the near triangle pairs,
+        plus the residue 1/2 n x M (exterior: E_e^+, interior: E_i^-)."""
+        o = self.o
+        L = lib()
+        x = np.ascontiguousarray(x, complex)
+        Ee = np.zeros((o.np_, 3), complex)
+        Ei = np.zeros((o.np_, 3), complex)
+        for which, lo, dims, k, Hhat in self.grids:
+            G = int(np.prod(dims))
+            Q = np.zeros(8 * G, complex)
+            assert L.or_grid_project(o._c, x, which, lo, dims, Q) == 0
+            Phi = self._conv(Hhat, dims, Q.reshape(8, *dims))
+            tgt = Ee if which < 0 else Ei
+            assert L.or_grid_point_fields(o._c, which, lo, dims, np.ascontiguousarray(Phi.ravel()), tgt.ravel()) == 0
+        pairs = np.ascontiguousarray(self.pairs, dtype=np.int32)
+        assert L.or_point_near_corr(o._c, x, pairs.ravel(), pairs.shape[0], Ee.ravel(), Ei.ravel()) == 0
+        _, _, Mq = o.surface_currents_at_points(x)
+        n = np.repeat(o.nrm, NQ, axis=0)
+        res = 0.5 * np.cross(n, Mq)
+        return Ee + res, Ei + res
+
     def solve(self, b: np.ndarray, tol: float = 1e-12, restart: int = 200, maxiter: int = 50) -> np.ndarray:
         """GMRES on A~ preconditioned by a sparse LU of its exact near-field
         part (the preconditioner changes the iteration path, not the answer);
@@ -440,3 +558,10 @@ def gmres_dense(A: np.ndarray, b: np.ndarray, tol: float = 1e-10) -> np.ndarray:
             return V[:, : j + 1] @ y
         V[:, j + 1] = w / Hm[j + 1, j]
     return V[:, : V.shape[1] - 1] @ y
+
+
+def monitor_weights(xs: np.ndarray, beta: float) -> np.ndarray:
+    """Least-squares fit of samples E(x_k) to a e^{-j beta x} + b e^{+j beta x}:
+    returns w with b = w . E (the reflected amplitude)."""
+    P = np.stack([np.exp(-1j * beta * xs), np.exp(1j * beta * xs)], axis=1)
+    return np.linalg.pinv(P)[1]

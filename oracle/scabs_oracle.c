@@ -1136,3 +1136,209 @@ int or_grid_interp_rows(Ctx *c, int which, const int *o, const int *n, const zc 
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Transposed pFFT pieces (adjoint system A~^T l = g) and pointwise    */
+/* one-sided fields of the pFFT operator (sigma derivative of A~ x).   */
+/* ------------------------------------------------------------------ */
+
+/* Transpose of or_grid_interp_rows.  Every tested quantity there is linear
+ * in the grid potentials through the value weights W (a_J, phi_J, a_M, phi_M)
+ * or the derivative weights grad W (curl a_J, curl a_M, grad phi_J).  Given a
+ * row-space vector z, Src gets, per field, W times the coefficient of that
+ * field's value plus grad W dotted with the coefficient of its gradient, so
+ * that sum_f <Src_f, Phi_f> = z^T (rows added for Phi).  The coefficient of
+ * grad A_c inside v . curl A is e_c x v. */
+int or_grid_interp_rows_t(Ctx *c, int which, const int *o, const int *n, const zc *z, zc *Src) {
+  double k = which < 0 ? c->k_e : c->k_i, Z = which < 0 ? c->Z_e : c->Z_i;
+  double sgn = which < 0 ? 1.0 : -1.0;
+  zc jk = I * k;
+  size_t G = (size_t)n[0] * n[1] * n[2];
+  memset(Src, 0, sizeof(zc) * 8 * G);
+  for (int T = 0; T < c->nt; T++) {
+    if (which >= 0 && c->body[T] != which) continue;
+    const double *nr = c->nrm + 3 * T;
+    for (int q = 0; q < NQ; q++) {
+      int it = T * NQ + q;
+      const double *r = c->qp + 3 * it;
+      double w = c->qw[it], sg = c->sigma[it];
+      zc tE[3] = {0, 0, 0}, tH[3] = {0, 0, 0}, sv[3] = {0, 0, 0}, dE = 0, dH = 0;
+      for (int i = 0; i < 3; i++) {
+        double g[3], dg, gxn[3];
+        half_rwg(c, T, i, r, g, &dg);
+        cross3(g, nr, gxn);
+        int rE, rH, r14; edge_slots(c, c->tedge[3 * T + i], &rE, &rH, &r14);
+        for (int a = 0; a < 3; a++) { tE[a] += z[rE] * g[a]; tH[a] += z[rH] * g[a]; }
+        dE += z[rE] * dg; dH += z[rH] * dg;
+        if (r14 >= 0) {
+          for (int a = 0; a < 3; a++) {
+            if (which < 0) sv[a] += w * sg * z[rH] * gxn[a];
+            else sv[a] += -w * sg * z[r14] * g[a];
+          }
+        }
+      }
+      zc cv[8], gc[8][3], vJ[3], vM[3], gp[3];
+      for (int a = 0; a < 3; a++) {
+        cv[a] = -Z * jk * (sgn * w * tE[a] + sv[a]);
+        cv[4 + a] = -(jk / Z) * sgn * w * tH[a];
+        vJ[a] = sgn * w * tH[a];
+        vM[a] = -(sgn * w * tE[a] + sv[a]);
+        gp[a] = -Z * jk * sv[a] / (k * k);
+      }
+      cv[3] = sgn * w * Z * jk * dE / (k * k);
+      cv[7] = (jk / Z) * sgn * w * dH / (k * k);
+      const zc *vv[2] = {vJ, vM};
+      for (int s = 0; s < 2; s++) {
+        const zc *v = vv[s];
+        int b = 4 * s;
+        gc[b + 0][0] = 0;     gc[b + 0][1] = -v[2]; gc[b + 0][2] = v[1];
+        gc[b + 1][0] = v[2];  gc[b + 1][1] = 0;     gc[b + 1][2] = -v[0];
+        gc[b + 2][0] = -v[1]; gc[b + 2][1] = v[0];  gc[b + 2][2] = 0;
+      }
+      for (int a = 0; a < 3; a++) { gc[3][a] = gp[a]; gc[7][a] = 0; }
+      const int *an = c->anchor + 3 * it;
+      const double *wt = c->gw + 27 * it, *gt = c->gd + 81 * it;
+      int ib = 0;
+      for (int i = -1; i <= 1; i++) for (int j = -1; j <= 1; j++) for (int kk = -1; kk <= 1; kk++, ib++) {
+        int gx = an[0] + i - o[0], gy = an[1] + j - o[1], gz = an[2] + kk - o[2];
+        if (gx < 0 || gy < 0 || gz < 0 || gx >= n[0] || gy >= n[1] || gz >= n[2]) return -1;
+        size_t gi = ((size_t)gx * n[1] + gy) * n[2] + gz;
+        for (int f = 0; f < 8; f++)
+          Src[f * G + gi] += wt[ib] * cv[f] + gt[3 * ib] * gc[f][0] + gt[3 * ib + 1] * gc[f][1] + gt[3 * ib + 2] * gc[f][2];
+      }
+    }
+  }
+  return 0;
+}
+
+/* transpose of edge_currents: adjoint currents per edge -> unknown space (adds) */
+static void edge_currents_t(const Ctx *c, const zc *aJe, const zc *aJi, const zc *aM, zc *y) {
+  for (int e = 0; e < c->ne; e++) {
+    int s0, s1, s2; edge_slots(c, e, &s0, &s1, &s2);
+    if (!c->isR[e]) { y[s0] += aJe[e] - aJi[e]; y[s1] += aM[e]; }
+    else { y[s0] += aJe[e]; y[s1] += aJi[e]; y[s2] += aM[e]; }
+  }
+}
+
+/* Transpose of or_grid_project: node values Phi (8 fields) -> unknown space
+ * (adds into y).  Each source point reads Phi with its value weights and
+ * hands w_s (f . Phi_vec + div f Phi_scalar) back to its half-RWG currents. */
+int or_grid_project_t(Ctx *c, int which, const int *o, const int *n, const zc *Phi, zc *y) {
+  zc *aJe = calloc(c->ne, sizeof(zc)), *aJi = calloc(c->ne, sizeof(zc)), *aM = calloc(c->ne, sizeof(zc));
+  size_t G = (size_t)n[0] * n[1] * n[2];
+  int bad = 0;
+  for (int T = 0; T < c->nt && !bad; T++) {
+    if (which >= 0 && c->body[T] != which) continue;
+    for (int q = 0; q < NQ; q++) {
+      int is = T * NQ + q;
+      const double *s = c->qp + 3 * is;
+      double w = c->qw[is];
+      const int *an = c->anchor + 3 * is;
+      const double *ws = c->gw + 27 * is;
+      zc P[8] = {0};
+      int ib = 0;
+      for (int i = -1; i <= 1; i++) for (int j = -1; j <= 1; j++) for (int k = -1; k <= 1; k++, ib++) {
+        int gx = an[0] + i - o[0], gy = an[1] + j - o[1], gz = an[2] + k - o[2];
+        if (gx < 0 || gy < 0 || gz < 0 || gx >= n[0] || gy >= n[1] || gz >= n[2]) { bad = 1; continue; }
+        size_t g = ((size_t)gx * n[1] + gy) * n[2] + gz;
+        for (int f = 0; f < 8; f++) P[f] += ws[ib] * Phi[f * G + g];
+      }
+      for (int j = 0; j < 3; j++) {
+        double f[3], df; half_rwg(c, T, j, s, f, &df);
+        int m = c->tedge[3 * T + j];
+        zc aj = w * (f[0] * P[0] + f[1] * P[1] + f[2] * P[2] + df * P[3]);
+        zc am = w * (f[0] * P[4] + f[1] * P[5] + f[2] * P[6] + df * P[7]);
+        if (which < 0) { aJe[m] += aj; aM[m] += am; }
+        else { aJi[m] += aj; aM[m] -= am; }
+      }
+    }
+  }
+  edge_currents_t(c, aJe, aJi, aM, y);
+  free(aJe); free(aJi); free(aM);
+  return bad ? -1 : 0;
+}
+
+/* Pointwise field of one medium's grid potentials at the selected test points
+ * (no residue): E = -Z jk (a_J + k^-2 grad phi_J) - curl a_M, added into Ep. */
+int or_grid_point_fields(Ctx *c, int which, const int *o, const int *n, const zc *Phi, zc *Ep) {
+  double k = which < 0 ? c->k_e : c->k_i, Z = which < 0 ? c->Z_e : c->Z_i;
+  size_t G = (size_t)n[0] * n[1] * n[2];
+  for (int T = 0; T < c->nt; T++) {
+    if (which >= 0 && c->body[T] != which) continue;
+    for (int q = 0; q < NQ; q++) {
+      int it = T * NQ + q;
+      const int *an = c->anchor + 3 * it;
+      const double *wt = c->gw + 27 * it, *gt = c->gd + 81 * it;
+      zc val[8] = {0}, grad[8][3];
+      memset(grad, 0, sizeof grad);
+      int ib = 0;
+      for (int i = -1; i <= 1; i++) for (int j = -1; j <= 1; j++) for (int kk = -1; kk <= 1; kk++, ib++) {
+        int gx = an[0] + i - o[0], gy = an[1] + j - o[1], gz = an[2] + kk - o[2];
+        if (gx < 0 || gy < 0 || gz < 0 || gx >= n[0] || gy >= n[1] || gz >= n[2]) return -1;
+        size_t g = ((size_t)gx * n[1] + gy) * n[2] + gz;
+        for (int f = 0; f < 8; f++) {
+          zc p = Phi[f * G + g];
+          val[f] += wt[ib] * p;
+          for (int a = 0; a < 3; a++) grad[f][a] += gt[3 * ib + a] * p;
+        }
+      }
+      zc cM[3] = {grad[6][1] - grad[5][2], grad[4][2] - grad[6][0], grad[5][0] - grad[4][1]};
+      for (int a = 0; a < 3; a++)
+        Ep[3 * it + a] += -Z * I * k * (val[a] + grad[3][a] / (k * k)) - cM[a];
+    }
+  }
+  return 0;
+}
+
+/* Near-pair correction of the pointwise fields: for every listed pair
+ * (T, T') and test point of T, (exact - grid) field of the currents of T'
+ * (exterior medium always, interior medium when both lie on one body) added
+ * into Ee / Ei.  Pairs must be grouped by test triangle. */
+int or_point_near_corr(Ctx *c, const zc *x, const int *pairs, long npairs, zc *Ee, zc *Ei) {
+  for (long p = 1; p < npairs; p++) if (pairs[2 * p] < pairs[2 * (p - 1)]) return -1;
+  zc *Je = malloc(sizeof(zc) * c->ne), *Ji = malloc(sizeof(zc) * c->ne), *M = malloc(sizeof(zc) * c->ne);
+  edge_currents(c, x, Je, Ji, M);
+  int D = 0;
+  for (long p = 0; p < npairs; p++)
+    for (int q1 = 0; q1 < NQ; q1++) for (int q2 = 0; q2 < NQ; q2++)
+      for (int a = 0; a < 3; a++) {
+        int d = abs(c->anchor[3 * (pairs[2 * p] * NQ + q1) + a] - c->anchor[3 * (pairs[2 * p + 1] * NQ + q2) + a]);
+        if (d > D) D = d;
+      }
+  D += 2;
+  HTab hte = make_htab(c->k_e, c->h, D), hti = make_htab(c->k_i, c->h, D);
+  long *start = malloc(sizeof(long) * (c->nt + 1));
+  for (int T = 0; T <= c->nt; T++) start[T] = 0;
+  for (long p = 0; p < npairs; p++) start[pairs[2 * p] + 1]++;
+  for (int T = 0; T < c->nt; T++) start[T + 1] += start[T];
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int T = 0; T < c->nt; T++) {
+    for (long p = start[T]; p < start[T + 1]; p++) {
+      int Tp = pairs[2 * p + 1];
+      int sing = or_singular_pair(c, T, Tp);
+      int same = c->body[T] == c->body[Tp];
+      for (int q = 0; q < NQ; q++) {
+        int iq = T * NQ + q;
+        const double *r = c->qp + 3 * iq;
+        for (int med = 0; med < (same ? 2 : 1); med++) {
+          double k = med ? c->k_i : c->k_e, Z = med ? c->Z_i : c->Z_e;
+          Inner ex, gr;
+          inner_exact(c, Tp, r, k, sing, &ex);
+          inner_grid(c, T, q, Tp, med ? &hti : &hte, &gr);
+          for (int j = 0; j < 3; j++) {
+            int m = c->tedge[3 * Tp + j];
+            zc J = med ? Ji[m] : Je[m], Mm = med ? -M[m] : M[m];
+            for (int a = 0; a < 3; a++) {
+              zc da = ex.a[j][a] - gr.a[j][a], dg = ex.gphi[j][a] - gr.gphi[j][a], dc = ex.c[j][a] - gr.c[j][a];
+              zc val = -Z * I * k * (da + dg / (k * k)) * J - dc * Mm;
+              if (med) Ei[3 * iq + a] += val; else Ee[3 * iq + a] += val;
+            }
+          }
+        }
+      }
+    }
+  }
+  free(start); free(hte.tab); free(hti.tab);
+  free(Je); free(Ji); free(M);
+  return 0;
+}

@@ -281,6 +281,27 @@ def workload_transition(L: float, degree: int, edge: float = 0.1, guide_len: flo
     return Workload("transition_L%g_d%d" % (L, degree), mesh, sig, [dip], h=h, r_near=r_near)
 
 
+def workload_gradient(guide_len: float = 20.0, absorber: float = 4.0, edge: float = 0.1, n_ctrl: int = 256,
+                      n_monitor: int = 16, h: float = 0.05, r_near: float = 0.3137, seed: int = 0,
+                      beta_frac: float = 0.9) -> Workload:
+    """Differentiation form: guide of length guide_len with an appended
+    absorber whose conductivity is piecewise linear with n_ctrl control values
+    drawn U[0, 2] from the seed; n_monitor field samples on the guide axis over
+    [2, guide_len - 2] (clamped to the guide); fitted propagation constant
+    frozen at beta_frac * k_i (notes: 'monitor_x', 'beta')."""
+    v, t = guide(guide_len + absorber, edge)
+    mesh = merge_bodies([(v, t)])
+    rng = SplitMix64(7000 + seed)
+    ctrl = np.array([rng.uniform_range(0.0, 2.0) for _ in range(n_ctrl)])
+    sig = [SigmaEnd(axis=0, x0=guide_len, length=absorber, direction=+1, ctrl=ctrl)]
+    dip = seeded_dipole(1000 * 4 + seed)
+    a, b = min(2.0, 0.25 * guide_len), max(guide_len - 2.0, 0.75 * guide_len)
+    xs = np.linspace(a, b, n_monitor)
+    k_i = OMEGA * math.sqrt(EPS_IN)
+    return Workload("gradient_W%g_L%g_edge%.3g" % (guide_len, absorber, edge), mesh, sig, [dip], h=h, r_near=r_near,
+                    notes={"monitor_x": xs, "beta": beta_frac * k_i})
+
+
 def workload_two_channel(edge: float = 0.072, length: float = 30.0, absorber: float = 4.0,
                          nx_target: int = 512, r_near: Optional[float] = None, seed: int = 0) -> Workload:
     """Two parallel 0.4 x 0.2 channels (gap 0.3, centres y = +-0.35), quartic
