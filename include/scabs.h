@@ -145,6 +145,63 @@ int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
 int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                 int mode, scabs_solve_info *info);
 
+/* Transposed system (adjoint method).  y = A^T x, same argument rules as
+ * scabs_matvec; the lattice convolution is symmetric, so the transpose runs
+ * the testing and projection steps in reverse (test-side sources with value
+ * and derivative stencil weights, convolution, values read at the source
+ * points) and the near correction through the mirrored pair entries. */
+int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
+
+/* Solve A^T x = b; arguments and precision modes as scabs_solve (the right
+ * preconditioner is the transposed Schwarz operator). */
+int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
+                          int mode, scabs_solve_info *info);
+
+/* Incident field of an electric dipole (as scabs_rhs_dipole) at every
+ * quadrature point (zero on other bodies).  E: device, n_points * 3 complex
+ * (6 n_points doubles), point-major. */
+int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double moment[6], int body, double *E);
+
+/* One-sided pointwise fields of the discrete operator at every quadrature
+ * point for currents x (device, 2N doubles): Ee = E_e^+ (exterior limit of the
+ * exterior-medium field of J_e, M_e) and Ei = E_i^- (interior limit of the
+ * interior-medium field of J_i, M_i, without the incident field), each
+ * n_points * 3 complex on the device.  These are the fields the sigma-weighted
+ * tests of eq13 (rotated by n x) and eq14 integrate (Appendix A).  Exact at
+ * the points of triangles carrying an absorber edge; elsewhere the near-pair
+ * correction is omitted. */
+int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei);
+
+/* Scattered fields at off-surface points pts (host, npts * 3) from currents x
+ * (device): region < 0 the exterior medium's field of (J_e, M); region = b the
+ * interior field of body b's currents (J_i, -M), without the incident field.
+ * E, H: device, npts * 3 complex.  Plain 7-point rule on every triangle, so
+ * the points must lie well away from the surface (several edge lengths). */
+int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E, double *H);
+
+/* Transpose of the E part of scabs_eval_field: y = Q^T wE where E = Q x;
+ * wE: device, npts * 3 complex; y: device, 2N doubles (overwritten). */
+int scabs_eval_field_transpose(scabs_ctx *c, const double *pts, int npts, int region, const double *wE, double *y);
+
+/* Number of profile parameters: per absorber in the order added, 1 (sigma0)
+ * for a monomial profile, n for a piecewise-linear one (its control values). */
+int scabs_sigma_params(const scabs_ctx *c, int64_t *n);
+
+/* Gradient of a real objective f(x), x = A^-1 b, with respect to sigma by the
+ * adjoint method: given x and lam solving A^T lam = g, g = df/dx in the sense
+ * df = 2 Re(g^T dx), returns
+ *   dfdsigma[q] = 2 Re[lam^T (db/dsigma_q - dA/dsigma_q x)]  (device, n_points;
+ *                 may be NULL)
+ *   dfdparam[k] = sum_q dsigma_q/dp_k dfdsigma[q]            (host,
+ *                 scabs_sigma_params entries; may be NULL)
+ * sigma enters A only through the sigma-weighted tests of eq13 and eq14 and b
+ * through eq14's incident-field term; einc (device, n_points * 3 complex, from
+ * scabs_incident_dipole_points; NULL for no incident field on the absorber)
+ * supplies the latter.  The layout (which edges are absorber edges) is held
+ * fixed. */
+int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const double *einc, double *dfdsigma,
+                         double *dfdparam);
+
 /* Stage timing (tracing): between scabs_profile_begin and scabs_profile_end
  * every stage of every product and solve is bracketed by HIP events on the
  * context stream.  scabs_profile_end synchronises the stream and returns, per

@@ -24,7 +24,9 @@ SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCO
 SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
-            "scabs_solve", "scabs_profile_begin", "scabs_profile_end", "scabs_last_error", "scabs_destroy"]
+            "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_incident_dipole_points",
+            "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
+            "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
           "near32", "precond", "ortho"]
 
@@ -87,6 +89,15 @@ def load() -> C.CDLL:
     L.scabs_rhs_dipole.argtypes = [P, dp, dp, C.c_int, P]
     L.scabs_matvec.argtypes = [P, P, P, C.c_int, C.c_int]
     L.scabs_solve.argtypes = [P, P, P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(SolveInfo)]
+    L.scabs_matvec_transpose.argtypes = [P, P, P, C.c_int, C.c_int]
+    L.scabs_solve_transpose.argtypes = [P, P, P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
+                                        C.POINTER(SolveInfo)]
+    L.scabs_incident_dipole_points.argtypes = [P, dp, dp, C.c_int, P]
+    L.scabs_point_fields.argtypes = [P, P, P, P]
+    L.scabs_eval_field.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
+    L.scabs_eval_field_transpose.argtypes = [P, dp, C.c_int, C.c_int, P, P]
+    L.scabs_sigma_params.argtypes = [P, C.POINTER(C.c_int64)]
+    L.scabs_sigma_gradient.argtypes = [P, P, P, P, P, dp]
     L.scabs_profile_begin.argtypes = [P]
     L.scabs_profile_end.argtypes = [P, dp, C.POINTER(C.c_int64)]
     L.scabs_last_error.restype = C.c_char_p
@@ -192,7 +203,8 @@ class Context:
             raise TypeError("expected a contiguous complex128 CUDA tensor")
         if t.shape[-1] != self.N:
             raise ValueError(f"last dimension must be N={self.N}")
-        return t
+        # a lazily conjugated view shares the unconjugated storage: materialise it
+        return t.resolve_conj() if t.is_conj() else t
 
     def rhs_dipole(self, pos, moment, body: int = 0):
         import torch
@@ -203,13 +215,76 @@ class Context:
         self._check(self._L.scabs_rhs_dipole(self._c, pp, mp, int(body), C.c_void_p(b.data_ptr())))
         return b
 
-    def matvec(self, x, prec: int = SCABS_FP64):
+    def matvec(self, x, prec: int = SCABS_FP64, transpose: bool = False):
         import torch
         x = self._dev(x)
         y = torch.empty_like(x)
         nrhs = 1 if x.dim() == 1 else x.shape[0]
-        self._check(self._L.scabs_matvec(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, prec))
+        fn = self._L.scabs_matvec_transpose if transpose else self._L.scabs_matvec
+        self._check(fn(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, prec))
         return y
+
+    def incident_dipole_points(self, pos, moment, body: int = 0):
+        import torch
+        npt = self.info()["n_points"]
+        E = torch.empty((npt, 3), dtype=torch.complex128, device=self.device)
+        p, pp = _f64(pos)
+        m = np.asarray(moment, dtype=np.complex128)
+        mm, mp = _f64(np.stack([m.real, m.imag], axis=1).ravel())
+        self._check(self._L.scabs_incident_dipole_points(self._c, pp, mp, int(body), C.c_void_p(E.data_ptr())))
+        return E
+
+    def point_fields(self, x):
+        import torch
+        x = self._dev(x)
+        npt = self.info()["n_points"]
+        Ee = torch.empty((npt, 3), dtype=torch.complex128, device=self.device)
+        Ei = torch.empty_like(Ee)
+        self._check(self._L.scabs_point_fields(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(Ee.data_ptr()),
+                                               C.c_void_p(Ei.data_ptr())))
+        return Ee, Ei
+
+    def eval_field(self, x, pts, region: int):
+        import torch
+        x = self._dev(x)
+        p, pp = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        E = torch.empty((p.shape[0], 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E)
+        self._check(self._L.scabs_eval_field(self._c, C.c_void_p(x.data_ptr()), pp, p.shape[0], int(region),
+                                             C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
+        return E, H
+
+    def eval_field_transpose(self, pts, region: int, wE):
+        import torch
+        p, pp = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        wE = wE.to(device=self.device, dtype=torch.complex128).resolve_conj().contiguous()
+        if tuple(wE.shape) != (p.shape[0], 3):
+            raise ValueError("wE must have shape (npts, 3)")
+        y = torch.empty(self.N, dtype=torch.complex128, device=self.device)
+        self._check(self._L.scabs_eval_field_transpose(self._c, pp, p.shape[0], int(region),
+                                                       C.c_void_p(wE.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    def sigma_params(self) -> int:
+        n = C.c_int64()
+        self._check(self._L.scabs_sigma_params(self._c, C.byref(n)))
+        return n.value
+
+    def sigma_gradient(self, x, lam, einc=None):
+        """(d f/d sigma per quadrature point [device], d f/d profile parameters [numpy])."""
+        import torch
+        x = self._dev(x)
+        lam = self._dev(lam)
+        npt = self.info()["n_points"]
+        dfds = torch.empty(npt, dtype=torch.float64, device=self.device)
+        dfdp = np.zeros(max(self.sigma_params(), 1))
+        if einc is not None:
+            einc = einc.resolve_conj().contiguous()
+        ep = C.c_void_p(einc.data_ptr()) if einc is not None else C.c_void_p()
+        self._check(self._L.scabs_sigma_gradient(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(lam.data_ptr()), ep,
+                                                 C.c_void_p(dfds.data_ptr()),
+                                                 dfdp.ctypes.data_as(C.POINTER(C.c_double))))
+        return dfds, dfdp[: self.sigma_params()]
 
     def profile_begin(self):
         self._check(self._L.scabs_profile_begin(self._c))
@@ -221,14 +296,15 @@ class Context:
         return {name: {"ms": ms[k], "count": cnt[k]} for k, name in enumerate(STAGES)}
 
     def solve(self, b, x0=None, tol: float = 1e-6, max_iter: int = 2000, restart: int = 60,
-              mode: int = SCABS_MIXED, raise_on_noconv: bool = False):
+              mode: int = SCABS_MIXED, raise_on_noconv: bool = False, transpose: bool = False):
         import torch
         b = self._dev(b)
         x = torch.zeros_like(b) if x0 is None else self._dev(x0).clone()
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         infos = (SolveInfo * nrhs)()
-        rc = self._L.scabs_solve(self._c, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, tol, max_iter,
-                                 restart, mode, infos)
+        fn = self._L.scabs_solve_transpose if transpose else self._L.scabs_solve
+        rc = fn(self._c, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, tol, max_iter, restart, mode,
+                infos)
         if rc != SCABS_OK and (rc != SCABS_E_NOCONV or raise_on_noconv):
             self._check(rc)
         out = [infos[k].as_dict() for k in range(nrhs)]
@@ -246,3 +322,81 @@ def context_for(workload, device: int = 0, kappa_s: float = 1.37, h: Optional[fl
     ctx.set_sigma(workload.sigma)
     ctx.build()
     return ctx
+
+
+# ---------------------------------------------------------------------------
+# differentiation: torch.autograd wrappers over the adjoint entry points
+# ---------------------------------------------------------------------------
+def _autograd_functions():
+    import torch
+
+    class SigmaSolve(torch.autograd.Function):
+        """x = A(p)^-1 b(p) for the profile parameters p of one context (the
+        context is rebuilt with p).  Backward: A^T lam = g by the transposed
+        solve, then d/dp = 2 Re[lam^T (db/dp - dA/dp x)] from the library.
+        PyTorch's gradient of a real loss for complex x is 2 conj(d loss/dx),
+        so g = conj(x.grad) / 2."""
+
+        @staticmethod
+        def forward(fctx, params, ctx, set_params, dipole, tol, restart, mode):
+            set_params(ctx, params.detach().cpu().numpy())
+            ctx.build()
+            d = dipole
+            b = ctx.rhs_dipole(d.pos, d.moment, d.body)
+            x, info = ctx.solve(b, tol=tol, restart=restart, mode=mode, max_iter=20000, raise_on_noconv=True)
+            einc = ctx.incident_dipole_points(d.pos, d.moment, d.body)
+            fctx.ctx, fctx.tol, fctx.restart, fctx.mode = ctx, tol, restart, mode
+            fctx.save_for_backward(x, einc)
+            return x
+
+        @staticmethod
+        def backward(fctx, gx):
+            x, einc = fctx.saved_tensors
+            ctx = fctx.ctx
+            g = (torch.conj(gx) * 0.5).resolve_conj().contiguous()
+            lam, _ = ctx.solve(g, tol=fctx.tol, restart=fctx.restart, mode=fctx.mode, max_iter=20000,
+                               raise_on_noconv=True, transpose=True)
+            _, dp = ctx.sigma_gradient(x, lam, einc)
+            return torch.from_numpy(dp), None, None, None, None, None, None
+
+    class FieldAt(torch.autograd.Function):
+        """E at off-surface points (scattered part) as a function of x."""
+
+        @staticmethod
+        def forward(fctx, x, ctx, pts, region):
+            E, _ = ctx.eval_field(x.detach(), pts, region)
+            fctx.ctx, fctx.pts, fctx.region = ctx, pts, region
+            return E
+
+        @staticmethod
+        def backward(fctx, gE):
+            # vector-Jacobian product of a complex-linear map: Q^H gE = conj(Q^T conj(gE))
+            y = fctx.ctx.eval_field_transpose(fctx.pts, fctx.region, torch.conj(gE).resolve_conj())
+            return torch.conj(y).resolve_conj(), None, None, None
+
+    return SigmaSolve, FieldAt
+
+
+def sigma_solve(params, ctx: Context, set_params, dipole, tol: float = 1e-10, restart: int = 200,
+                mode: int = SCABS_FP64):
+    """Differentiable solve: x(params) with d/dparams by the adjoint method.
+    set_params(ctx, values) must apply the profile parameters to ctx."""
+    SigmaSolve, _ = _autograd_functions()
+    return SigmaSolve.apply(params, ctx, set_params, dipole, tol, restart, mode)
+
+
+def field_at(x, ctx: Context, pts, region: int):
+    """Differentiable scattered field E at off-surface points."""
+    _, FieldAt = _autograd_functions()
+    return FieldAt.apply(x, ctx, pts, region)
+
+
+def reflected_amplitude(E_y, xs, beta: float):
+    """b of the least-squares fit E_y(x_k) = a e^{-j beta x} + b e^{+j beta x}
+    at monitor positions xs (torch, differentiable in E_y): b = w . E_y with w
+    the second row of the pseudo-inverse of the 2-column fit matrix."""
+    import torch
+    xs = np.asarray(xs, float)
+    P = np.stack([np.exp(-1j * beta * xs), np.exp(1j * beta * xs)], axis=1)
+    w = torch.as_tensor(np.linalg.pinv(P)[1], dtype=torch.complex128, device=E_y.device)
+    return (w * E_y).sum()

@@ -78,6 +78,7 @@ template <typename T> struct PrecState {
   std::vector<DevGrid<T>> grids;   // host copies holding device pointers
   DevGrid<T> *grids_dev = nullptr;
   std::vector<GatherGrid<T>> gather;
+  std::vector<cx<T> *> src4;       // per grid: 32 adjoint-source coefficients per sorted point
   DevOperator<T> op;
   T inv_h = 0;
 };
@@ -111,6 +112,9 @@ struct scabs_ctx {
   int64_t nnz = 0;
   double *qp64 = nullptr;
   int *body_dev = nullptr;
+  int64_t *tpos = nullptr;     // per near CSR entry (n, m): index of the entry (m, n)
+  NearSetupArgs nsa{};         // near-pair tables kept for the pointwise-field pass
+  uint8_t *tmask = nullptr;    // triangles with an absorber edge
   PrecState<float> p32;
   PrecState<double> p64;
   // preconditioner
@@ -122,6 +126,11 @@ struct scabs_ctx {
   int *pc_items = nullptr;   // (cluster, first core row) per apply work-group
   int pc_n_items = 0;
   cx<float> *pc_Rt = nullptr;
+  // transposed apply: cluster of every ext entry, and per unknown its ext entries
+  int64_t pc_n_ext = 0;
+  int *pc_ext_cluster = nullptr;
+  int64_t *pc_inv_ptr = nullptr, *pc_inv_pos = nullptr;
+  cx<double> *pc_tmp = nullptr;
   // solver workspace (grown on demand)
   DevMem work;
   int work_restart = -1;
@@ -242,6 +251,7 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   // grids
   P.grids.clear();
   P.gather.clear();
+  P.src4.clear();
   for (size_t gi = 0; gi < c->grids.size(); gi++) {
     const GridDesc &d = c->grids[gi];
     DevGrid<T> G{};
@@ -294,6 +304,7 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
     GG.u = c->mem.upload(uu);
     GG.src = c->mem.alloc<cx<T>>(8 * key.size());
     P.gather.push_back(GG);
+    P.src4.push_back(c->mem.alloc<cx<T>>(32 * key.size()));
   }
   P.grids_dev = c->mem.upload(P.grids);
   P.inv_h = (T)(1.0 / c->opts.h);
@@ -367,6 +378,26 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   c->pc_core_slot = c->mem.upload(cl.core_slot);
   c->pc_r_off = c->mem.upload(cl.r_off);
   {
+    // transposed apply: owning cluster of every ext entry; per unknown the
+    // ext entries that hold it (cluster order)
+    const int64_t n_ext = cl.ext_ptr[cl.nc];
+    std::vector<int> ext_cluster(n_ext);
+    std::vector<int64_t> inv_ptr(L.N + 1, 0), inv_pos(n_ext);
+    for (int k = 0; k < cl.nc; k++)
+      for (int64_t q = cl.ext_ptr[k]; q < cl.ext_ptr[k + 1]; q++) {
+        ext_cluster[q] = k;
+        inv_ptr[cl.ext_slot[q] + 1]++;
+      }
+    for (int64_t u = 0; u < L.N; u++) inv_ptr[u + 1] += inv_ptr[u];
+    std::vector<int64_t> fill(inv_ptr.begin(), inv_ptr.end() - 1);
+    for (int64_t q = 0; q < n_ext; q++) inv_pos[fill[cl.ext_slot[q]]++] = q;
+    c->pc_n_ext = n_ext;
+    c->pc_ext_cluster = c->mem.upload(ext_cluster);
+    c->pc_inv_ptr = c->mem.upload(inv_ptr);
+    c->pc_inv_pos = c->mem.upload(inv_pos);
+    c->pc_tmp = c->mem.alloc<cx<double>>(n_ext);
+  }
+  {
     const int rows = precond_rows_per_item();
     std::vector<int> items;
     for (int k = 0; k < cl.nc; k++)
@@ -397,10 +428,15 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   c->has_pc = true;
 }
 
-static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y) {
+static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool trans) {
   StageTimer tm(c, SCABS_STAGE_PRECOND);
-  launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
-                       c->pc_r_off, c->pc_Rt, x, y, c->stream);
+  if (!trans)
+    launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
+                         c->pc_r_off, c->pc_Rt, x, y, c->stream);
+  else
+    launch_precond_apply_t(c->cl.nc, c->pc_n_ext, c->lay.N, c->pc_ext_ptr, c->pc_ext_cluster, c->pc_core_ptr,
+                           c->pc_core_slot, c->pc_r_off, c->pc_Rt, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y,
+                           c->stream);
 }
 
 static int do_build(scabs_ctx *c) {
@@ -476,6 +512,25 @@ static int do_build(scabs_ctx *c) {
   c->rowptr = c->mem.upload(c->near.rowptr);
   c->col = c->mem.upload(c->near.col);
   c->nnz = c->near.rowptr[g.ne];
+  {
+    // mirrored entry of every near pair (the near list is symmetric)
+    std::vector<int64_t> tp(c->nnz);
+    const std::vector<int64_t> &rp = c->near.rowptr;
+    const std::vector<int> &cl = c->near.col;
+    for (int n = 0; n < g.ne; n++)
+      for (int64_t k = rp[n]; k < rp[n + 1]; k++) {
+        const int m = cl[k];
+        auto b = cl.begin() + rp[m], e = cl.begin() + rp[m + 1];
+        auto it = std::lower_bound(b, e, n);
+        if (it == e || *it != n) return fail(c, SCABS_E_ARG, "near list is not symmetric");
+        tp[k] = it - cl.begin();
+      }
+    c->tpos = c->mem.upload(tp);
+    std::vector<uint8_t> tm(g.nt, 0);
+    for (int T = 0; T < g.nt; T++)
+      for (int j = 0; j < 3; j++) tm[T] |= (uint8_t)(L.isR[g.tedge[3 * T + j]] != 0);
+    c->tmask = c->mem.upload(tm);
+  }
   c->nnzR = 0;
   for (int n = 0; n < g.ne; n++)
     if (L.isR[n]) c->nnzR += c->near.rowptr[n + 1] - c->near.rowptr[n];
@@ -515,25 +570,28 @@ static int do_build(scabs_ctx *c) {
     a.h = c->opts.h;
     a.k_e = c->k_e;
     a.k_i = c->k_i;
-    a.v = tmp.upload(g.v);
-    a.t = tmp.upload(g.t);
+    a.Z_e = c->Z_e;
+    a.Z_i = c->Z_i;
+    a.v = c->mem.upload(g.v);
+    a.t = c->mem.upload(g.t);
     a.body = c->body_dev;
-    a.tedge = tmp.upload(g.tedge);
-    a.tsign = tmp.upload(g.tsign);
-    a.elen = tmp.upload(g.elen);
-    a.area = tmp.upload(g.area);
-    a.nrm = tmp.upload(g.nrm);
+    a.tedge = c->mem.upload(g.tedge);
+    a.tsign = c->mem.upload(g.tsign);
+    a.elen = c->mem.upload(g.elen);
+    a.area = c->mem.upload(g.area);
+    a.nrm = c->mem.upload(g.nrm);
     a.qp = c->qp64;
-    a.qw = tmp.upload(g.qw);
-    a.sigma = tmp.upload(L.sigma);
-    a.anchor = tmp.upload(c->anchor);
-    a.u = tmp.upload(c->u);
-    a.tptr = tmp.upload(c->near.tptr);
-    a.src = tmp.upload(c->near.src);
-    a.sing = tmp.upload(c->near.sing);
+    a.qw = c->mem.upload(g.qw);
+    a.sigma = c->mem.upload(L.sigma);
+    a.anchor = c->mem.upload(c->anchor);
+    a.u = c->mem.upload(c->u);
+    a.tptr = c->mem.upload(c->near.tptr);
+    a.src = c->mem.upload(c->near.src);
+    a.sing = c->mem.upload(c->near.sing);
     a.D = D;
-    cx<double> *he = tmp.alloc<cx<double>>((size_t)(D + 1) * (D + 1) * (D + 1));
-    cx<double> *hi = tmp.alloc<cx<double>>((size_t)(D + 1) * (D + 1) * (D + 1));
+    a.tmask = c->tmask;
+    cx<double> *he = c->mem.alloc<cx<double>>((size_t)(D + 1) * (D + 1) * (D + 1));
+    cx<double> *hi = c->mem.alloc<cx<double>>((size_t)(D + 1) * (D + 1) * (D + 1));
     build_htab(c->k_e, c->opts.h, D, he, s);
     build_htab(c->k_i, c->opts.h, D, hi, s);
     a.htab_e = he;
@@ -542,6 +600,8 @@ static int do_build(scabs_ctx *c) {
     a.blocks_exact = tmp.alloc<cx<double>>((size_t)npairs * 72);
     launch_near_setup(a, s);
     HIPCHK(hipGetLastError());
+    c->nsa = a;
+    c->nsa.blocks = c->nsa.blocks_exact = nullptr;
     cx<double> *V4 = c->mem.alloc<cx<double>>(4 * (size_t)c->nnz);
     cx<double> *S4 = c->mem.alloc<cx<double>>(4 * (size_t)c->nnz);
     cx<float> *V4f = c->mem.alloc<cx<float>>(4 * (size_t)c->nnz);
@@ -598,7 +658,41 @@ template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const dou
   }
 }
 
-static void matvec_one(scabs_ctx *c, const double *x, double *y, int prec) {
+// y = A~^T z: row weights -> lattice sources (value and gradient weights),
+// the same convolution, transposed projection, then transposed near rows
+template <typename T> static void apply_t(scabs_ctx *c, PrecState<T> &P, const double *z, double *y) {
+  hipStream_t s = c->stream;
+  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
+  {
+    StageTimer t(c, SCABS_STAGE_UNPACK + off);
+    launch_unpack_rows(P.op, z, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_PROJECT + off);
+    launch_test_t(P.op, P.grids, P.gather, P.src4, P.inv_h, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_FFT + off);
+    for (const DevGrid<T> &g : P.grids) launch_conv(g, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_INTERP + off);
+    launch_interp_adj(P.op, P.grids[0], P.grids_dev + 1, s);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_NEAR + off);
+    launch_near_rows_t(P.op, c->tpos, y, s);
+  }
+}
+
+static void matvec_one(scabs_ctx *c, const double *x, double *y, int prec, bool trans = false) {
+  if (trans) {
+    if (prec == SCABS_FP32)
+      apply_t(c, c->p32, x, y);
+    else
+      apply_t(c, c->p64, x, y);
+    return;
+  }
   if (prec == SCABS_FP32)
     apply(c, c->p32, x, y);
   else
@@ -644,7 +738,7 @@ struct GmresResult {
 
 // Solve A_prec sol = rhs from sol = 0 to ||rhs - A sol|| <= tol ||rhs||.
 static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, int prec, double tol, int max_iter,
-                         int restart, int &nmv) {
+                         int restart, int &nmv, bool trans) {
   typedef std::complex<double> zd;
   hipStream_t s = c->stream;
   const int64_t N = c->lay.N;
@@ -677,10 +771,10 @@ static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, i
     while (j < m && res.iters < max_iter) {
       cx<double> *vj = c->V + (size_t)j * N;
       if (c->has_pc) {
-        apply_precond(c, vj, c->z);
-        matvec_one(c, (const double *)c->z, (double *)c->w, prec);
+        apply_precond(c, vj, c->z, trans);
+        matvec_one(c, (const double *)c->z, (double *)c->w, prec, trans);
       } else {
-        matvec_one(c, (const double *)vj, (double *)c->w, prec);
+        matvec_one(c, (const double *)vj, (double *)c->w, prec, trans);
       }
       nmv++;
       {
@@ -737,13 +831,13 @@ static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, i
       // sol += M (V y)
       HIPCHK(hipMemsetAsync(c->t, 0, sizeof(cx<double>) * N, s));
       kr_update(c->t, c->V, N, j, h1, N, +1.0, s);
-      apply_precond(c, c->t, c->z);
+      apply_precond(c, c->t, c->z, trans);
       kr_axpy(sol, c->z, N, s);
     } else {
       kr_update(sol, c->V, N, j, h1, N, +1.0, s);
     }
     // true residual
-    matvec_one(c, (const double *)sol, (double *)c->w, prec);
+    matvec_one(c, (const double *)sol, (double *)c->w, prec, trans);
     nmv++;
     HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
     kr_residual((const cx<double> *)c->r, c->w, N, s);   // w = rhs - A sol
@@ -755,7 +849,7 @@ static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, i
 
 // FP64 iterative refinement around GMRES on the operator of `inner` precision.
 static int solve_one(scabs_ctx *c, const cx<double> *b, cx<double> *x, double tol, int max_iter, int restart, int mode,
-                     scabs_solve_info *info) {
+                     scabs_solve_info *info, bool trans) {
   hipStream_t s = c->stream;
   const int64_t N = c->lay.N;
   ensure_work(c, restart);
@@ -773,7 +867,7 @@ static int solve_one(scabs_ctx *c, const cx<double> *b, cx<double> *x, double to
   double rel = 1.0;
   int status = SCABS_E_NOCONV;
   for (int outer = 0; outer < 50; outer++) {
-    matvec_one(c, (const double *)x, (double *)rr, SCABS_FP64);
+    matvec_one(c, (const double *)x, (double *)rr, SCABS_FP64, trans);
     loc.matvecs64++;
     kr_residual(b, rr, N, s);   // rr = b - A x
     double rn = dev_norm(c, rr);
@@ -785,7 +879,7 @@ static int solve_one(scabs_ctx *c, const cx<double> *b, cx<double> *x, double to
     if (loc.inner_iters >= max_iter) break;
     double tin = std::max(0.5 * tol / rel, floor_tol);
     int nmv = 0;
-    GmresResult g = gmres(c, rr, corr, inner_prec, tin, max_iter - loc.inner_iters, restart, nmv);
+    GmresResult g = gmres(c, rr, corr, inner_prec, tin, max_iter - loc.inner_iters, restart, nmv, trans);
     if (inner_prec == SCABS_FP32)
       loc.matvecs32 += nmv;
     else
@@ -948,13 +1042,13 @@ int scabs_rhs_dipole(scabs_ctx *c, const double pos[3], const double moment[6], 
   return SCABS_OK;
 }
 
-int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
+static int do_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec, bool trans) {
   if (!c || !x || !y || nrhs < 1) return SCABS_E_ARG;
   if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
   if (prec != SCABS_FP32 && prec != SCABS_FP64) return fail(c, SCABS_E_ARG, "prec must be SCABS_FP32 or SCABS_FP64");
   try {
     const size_t stride = 2 * (size_t)c->lay.N;
-    for (int k = 0; k < nrhs; k++) matvec_one(c, x + k * stride, y + k * stride, prec);
+    for (int k = 0; k < nrhs; k++) matvec_one(c, x + k * stride, y + k * stride, prec, trans);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
   } catch (const HipError &e) {
@@ -963,8 +1057,16 @@ int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
   return SCABS_OK;
 }
 
-int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart, int mode,
-                scabs_solve_info *info) {
+int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
+  return do_matvec(c, x, y, nrhs, prec, false);
+}
+
+int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
+  return do_matvec(c, x, y, nrhs, prec, true);
+}
+
+static int do_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
+                    int mode, scabs_solve_info *info, bool trans) {
   if (!c || !b || !x || nrhs < 1 || !(tol > 0) || max_iter < 1 || restart < 1) return SCABS_E_ARG;
   if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
   if (mode != SCABS_FP64 && mode != SCABS_MIXED) return fail(c, SCABS_E_ARG, "mode must be SCABS_FP64 or SCABS_MIXED");
@@ -982,7 +1084,7 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
     for (int k = 0; k < nrhs; k++) {
       scabs_solve_info loc{};
       int st = solve_one(c, (const cx<double> *)(b + k * stride), (cx<double> *)(x + k * stride), tol, max_iter, restart,
-                         mode, &loc);
+                         mode, &loc, trans);
       if (info) info[k] = loc;
       if (st != SCABS_OK) worst = st;
     }
@@ -991,6 +1093,141 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
   } catch (const HipError &e) {
     return hip_fail(c, e);
   }
+}
+
+int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart, int mode,
+                scabs_solve_info *info) {
+  return do_solve(c, b, x, nrhs, tol, max_iter, restart, mode, info, false);
+}
+
+int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
+                          int mode, scabs_solve_info *info) {
+  return do_solve(c, b, x, nrhs, tol, max_iter, restart, mode, info, true);
+}
+
+int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double moment[6], int body, double *E) {
+  if (!c || !pos || !moment || !E) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (body < 0 || body >= c->geo.nbody) return fail(c, SCABS_E_ARG, "body index out of range");
+  try {
+    launch_incident_points(c->p64.op.np, c->body_dev, c->p64.pts, c->qp64, c->k_i, c->Z_i, pos, moment, body,
+                           (cx<double> *)E, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
+}
+
+// one-sided pointwise fields of the operator (FP64) at every quadrature point:
+// grid part, near-pair (exact - grid) part on triangles with absorber edges,
+// and the 1/2 n x M residue
+static void point_fields(scabs_ctx *c, const double *x, cx<double> *Ee, cx<double> *Ei) {
+  PrecState<double> &P = c->p64;
+  hipStream_t s = c->stream;
+  launch_unpack(P.op, x, s);
+  launch_project(P.op, P.grids, P.gather, s);
+  for (const DevGrid<double> &g : P.grids) launch_conv(g, s);
+  launch_point_fields(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, Ee, Ei, s);
+  NearSetupArgs a = c->nsa;
+  a.cur = P.src;
+  a.Ee = Ee;
+  a.Ei = Ei;
+  launch_near_point_fields(a, s);
+  HIPCHK(hipGetLastError());
+}
+
+int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei) {
+  if (!c || !x || !Ee || !Ei) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  try {
+    point_fields(c, x, (cx<double> *)Ee, (cx<double> *)Ei);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
+}
+
+int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E, double *H) {
+  if (!c || !x || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (region >= c->geo.nbody) return fail(c, SCABS_E_ARG, "region out of range");
+  try {
+    DevMem tmp;
+    double *p = tmp.alloc<double>(3 * (size_t)npts);
+    HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
+    launch_unpack(c->p64.op, x, c->stream);
+    const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
+    launch_eval_field(c->p64.op, c->qp64, p, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
+}
+
+int scabs_eval_field_transpose(scabs_ctx *c, const double *pts, int npts, int region, const double *wE, double *y) {
+  if (!c || !pts || npts < 1 || !wE || !y) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (region >= c->geo.nbody) return fail(c, SCABS_E_ARG, "region out of range");
+  try {
+    DevMem tmp;
+    double *p = tmp.alloc<double>(3 * (size_t)npts);
+    HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
+    const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
+    launch_eval_field_t(c->p64.op, c->qp64, p, npts, region, k, Z, (const cx<double> *)wE, y, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
+}
+
+int scabs_sigma_params(const scabs_ctx *c, int64_t *n) {
+  if (!c || !n) return SCABS_E_ARG;
+  int64_t k = 0;
+  for (const SigmaEnd &e : c->ends) k += e.ctrl.empty() ? 1 : (int64_t)e.ctrl.size();
+  *n = k;
+  return SCABS_OK;
+}
+
+int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const double *einc, double *dfdsigma,
+                         double *dfdparam) {
+  if (!c || !x || !lam) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  try {
+    const size_t np = (size_t)c->p64.op.np;
+    DevMem tmp;
+    cx<double> *Ee = tmp.alloc<cx<double>>(3 * np), *Ei = tmp.alloc<cx<double>>(3 * np);
+    double *dfds = dfdsigma ? dfdsigma : tmp.alloc<double>(np);
+    point_fields(c, x, Ee, Ei);
+    launch_unpack_rows(c->p64.op, lam, c->stream);
+    launch_sigma_grad(c->p64.op, Ee, Ei, (const cx<double> *)einc, dfds, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(dfdparam ? np : 0);
+    if (dfdparam) HIPCHK(hipMemcpyAsync(h.data(), dfds, np * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    tmp.release();
+    if (dfdparam) {
+      // chain rule through the profile: d sigma_q / d p for every end's parameters
+      std::vector<int64_t> jp;
+      std::vector<int> jk;
+      std::vector<double> jv;
+      int64_t npar = 0;
+      sigma_param_jacobian(c->geo, c->ends, jp, jk, jv, &npar);
+      std::vector<double> g(npar, 0.0);
+      for (size_t q = 0; q < np; q++)
+        for (int64_t t = jp[q]; t < jp[q + 1]; t++) g[jk[t]] += jv[t] * h[q];
+      std::memcpy(dfdparam, g.data(), npar * sizeof(double));
+    }
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
 }
 
 int scabs_profile_begin(scabs_ctx *c) {

@@ -81,6 +81,8 @@ std::string build_geometry(const std::vector<double> &v, const std::vector<int> 
                            Geometry &g);
 void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<double> &sigma);
 void build_layout(const Geometry &g, Layout &L);
+void sigma_param_jacobian(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<int64_t> &ptr,
+                          std::vector<int> &idx, std::vector<double> &val, int64_t *npar);
 std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std::vector<GridDesc> &grids,
                         std::vector<int> &anchor /* np*3 absolute */, std::vector<double> &u /* np*3 */);
 std::string build_near(const Geometry &g, double r_near, double kappa_s, NearList &nl);

@@ -85,8 +85,15 @@ struct NearSetupArgs {
   const cx<double> *htab_e, *htab_i;   // (D+1)^3 each
   cx<double> *blocks;        // npairs * 8 * 9: exact - grid
   cx<double> *blocks_exact;  // npairs * 8 * 9: exact
+  // pointwise-field mode
+  double Z_e, Z_i;
+  const uint8_t *tmask;      // triangles whose test points are needed
+  const cx<double> *cur;     // per edge: J_e, J_i, M
+  cx<double> *Ee, *Ei;       // np * 3 each (added into)
 };
 void launch_near_setup(const NearSetupArgs &a, hipStream_t s);
+// (exact - grid) near-pair part of the one-sided pointwise fields, added
+void launch_near_point_fields(const NearSetupArgs &a, hipStream_t s);
 void build_htab(double k, double h, int D, cx<double> *tab, hipStream_t s);
 void launch_near_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
                           const cx<double> *blocks, cx<double> *V4, cx<double> *S4, cx<float> *V4f, cx<float> *S4f,
@@ -120,6 +127,34 @@ int precond_rows_per_item();
 void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
                           const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
                           const cx<double> *x, cx<double> *y, hipStream_t s);
+
+// ---- transposed product, adjoint gradient --------------------------------------
+template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s);
+// src4[k]: 32 coefficients per sorted point of grid k (work buffer)
+template <typename T>
+void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids, const std::vector<GatherGrid<T>> &gg,
+                   const std::vector<cx<T> *> &src4, T inv_h, hipStream_t s);
+template <typename T>
+void launch_interp_adj(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, hipStream_t s);
+template <typename T>
+void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y, hipStream_t s);
+void launch_precond_apply_t(int nc, int64_t n_ext, int64_t N, const int64_t *ext_ptr, const int *ext_cluster,
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                            const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
+                            cx<double> *y, hipStream_t s);
+void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &ext, const DevGrid<double> *ints_dev,
+                         double inv_h, cx<double> *Ee, cx<double> *Ei, hipStream_t s);
+void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, const cx<double> *Ei,
+                       const cx<double> *Einc, double *dfds, hipStream_t s);
+void launch_incident_points(int np, const int *body, const PointRec<double> *pts, const double *qp, double k, double Z,
+                            const double *pos, const double *mom, int bodyid, cx<double> *E, hipStream_t s);
+
+// fields at off-surface points (currents from op.src) and the transpose of
+// their E part (adjoint currents collected into y, unknown space)
+void launch_eval_field(const DevOperator<double> &op, const double *qp, const double *pts, int npts, int region,
+                       double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s);
+void launch_eval_field_t(const DevOperator<double> &op, const double *qp, const double *pts, int npts, int region,
+                         double k, double Z, const cx<double> *wE, double *y, hipStream_t s);
 
 // ---- misc --------------------------------------------------------------------
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,

@@ -1,0 +1,752 @@
+// Transposed product y = A~^T z of the precorrected-FFT operator, the
+// transposed Schwarz preconditioner, and the pointwise one-sided fields and
+// sigma derivative used by the adjoint gradient.
+//
+// A~ = (test) G (source) + (near correction) + (local terms).  The lattice
+// convolution G is symmetric (the sampled kernel is even), so
+//   A~^T z = source^T G test^T z + near^T z + local^T z,
+// where test^T turns the row weights z at every test point into lattice
+// sources with both value weights W and derivative weights grad W (the
+// forward testing reads potentials through both), and source^T reads the
+// convolved lattice with W at the source points and hands the result back to
+// the half-RWG currents.  The near transpose walks the same edge-pair CSR
+// (the near list is symmetric) reading the entry of the mirrored pair.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace scabs {
+
+// ---------------------------------------------------------------------------
+// row-space vector -> per-edge row weights (z_E, z_H, z_14); z_14 = 0 on
+// sigma-free edges
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void unpack_rows_kernel(const EdgeRec *__restrict__ edges, int ne, const double *__restrict__ z,
+                                   cx<T> *__restrict__ dst) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const EdgeRec r = edges[e];
+  dst[3 * e] = {(T)z[2 * r.row[0]], (T)z[2 * r.row[0] + 1]};
+  dst[3 * e + 1] = {(T)z[2 * r.row[1]], (T)z[2 * r.row[1] + 1]};
+  dst[3 * e + 2] = r.isR ? cx<T>{(T)z[2 * r.row[2]], (T)z[2 * r.row[2] + 1]} : czero<T>();
+}
+
+template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_rows_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op.edges, op.ne, z, op.src);
+}
+template void launch_unpack_rows<float>(const DevOperator<float> &, const double *, hipStream_t);
+template void launch_unpack_rows<double>(const DevOperator<double> &, const double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// test^T, step 1: per point (in the grid's cell-sorted order) the coefficients
+// that the forward rows give to each potential field's value and gradient.
+// With t_E = sum z_E f, t_H = sum z_H f, d_E = sum z_E div f, d_H = sum z_H div f
+// and the sigma vector s (exterior: w sigma sum z_H (f x n); interior:
+// -w sigma sum z_14 f), the rows read
+//   a_J: -Z jk (sgn w t_E + s)      phi_J: sgn w Z jk d_E / k^2
+//   a_M: -(jk/Z) sgn w t_H          phi_M: (jk/Z) sgn w d_H / k^2
+//   curl a_J . (sgn w t_H)           curl a_M . (-(sgn w t_E + s))
+//   grad phi_J . (-Z jk s / k^2)
+// and the gradient coefficient of component c inside v . curl a is e_c x v.
+// Output per point: 8 fields x (value, d/dx, d/dy, d/dz).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+adj_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restrict__ tris,
+                   const cx<T> *__restrict__ zr, GatherGrid<T> g, cx<T> *__restrict__ out, T k, T Z, int interior) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.np) return;
+  const PointRec<T> P = pts[g.perm[i]];
+  const TriRec<T> tr = tris[P.tri];
+  const T n[3] = {tr.nrm[0], tr.nrm[1], tr.nrm[2]};
+  const T w = P.w, ws = P.w * P.sigma, sgn = interior ? T(-1) : T(1);
+  cx<T> tE[3], tH[3], sv[3], dE = czero<T>(), dH = czero<T>();
+#pragma unroll
+  for (int a = 0; a < 3; a++) tE[a] = tH[a] = sv[a] = czero<T>();
+#pragma unroll
+  for (int j = 0; j < 3; j++) {
+    const int e = tr.edge[j];
+    const cx<T> zE = zr[3 * e], zH = zr[3 * e + 1], z14 = zr[3 * e + 2];
+    const T f[3] = {P.f[3 * j], P.f[3 * j + 1], P.f[3 * j + 2]};
+    const T fxn[3] = {f[1] * n[2] - f[2] * n[1], f[2] * n[0] - f[0] * n[2], f[0] * n[1] - f[1] * n[0]};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      axpy(tE[a], f[a], zE);
+      axpy(tH[a], f[a], zH);
+      if (interior)
+        axpy(sv[a], -ws * f[a], z14);
+      else
+        axpy(sv[a], ws * fxn[a], zH);
+    }
+    axpy(dE, tr.div[j], zE);
+    axpy(dH, tr.div[j], zH);
+  }
+  cx<T> cv[8], vJ[3], vM[3], gp[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    cx<T> te = sgn * w * tE[a] + sv[a];
+    cv[a] = mul_j(te) * (-Z * k);
+    cv[4 + a] = mul_j(tH[a]) * (-(k / Z) * sgn * w);
+    vJ[a] = (sgn * w) * tH[a];
+    vM[a] = -te;
+    gp[a] = mul_j(sv[a]) * (-Z / k);
+  }
+  cv[3] = mul_j(dE) * (sgn * w * Z / k);
+  cv[7] = mul_j(dH) * (sgn * w / (Z * k));
+  cx<T> *o = out + (size_t)32 * i;
+  const cx<T> zz = czero<T>();
+  const cx<T> gc[8][3] = {{zz, -vJ[2], vJ[1]}, {vJ[2], zz, -vJ[0]}, {-vJ[1], vJ[0], zz}, {gp[0], gp[1], gp[2]},
+                          {zz, -vM[2], vM[1]}, {vM[2], zz, -vM[0]}, {-vM[1], vM[0], zz}, {zz, zz, zz}};
+#pragma unroll
+  for (int f = 0; f < 8; f++) {
+    o[4 * f] = cv[f];
+    o[4 * f + 1] = gc[f][0];
+    o[4 * f + 2] = gc[f][1];
+    o[4 * f + 3] = gc[f][2];
+  }
+}
+
+// test^T, step 2: every node sums, over the points of its 27 neighbouring
+// cells, W c_value + W_x c_x + W_y c_y + W_z c_z per field (the layout and
+// LDS staging of the forward gather, with four coefficients per field).
+constexpr int GT_THREADS = 256;
+template <typename T> struct GtChunk { static constexpr int value = 256; };
+template <> struct GtChunk<double> { static constexpr int value = 128; };
+
+template <typename T> __device__ inline void lagr_pick(int i, T u, T &L, T &dL) {
+  // node at offset i (-1, 0, +1) from the anchor
+  if (i == -1) {
+    L = T(0.5) * u * (u - T(1));
+    dL = u - T(0.5);
+  } else if (i == 0) {
+    L = T(1) - u * u;
+    dL = T(-2) * u;
+  } else {
+    L = T(0.5) * u * (u + T(1));
+    dL = u + T(0.5);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(GT_THREADS)
+gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4, T inv_h) {
+  constexpr int CH = GtChunk<T>::value;
+  __shared__ cx<T> s_src[CH * 32];
+  __shared__ T s_u[CH * 3];
+  const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
+  const int plane = n1 * n2;
+  const int x = blockIdx.x;
+  const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
+  const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
+  constexpr int MAXN = 4;   // nodes per thread (plane <= MAXN * GT_THREADS)
+  cx<T> acc[MAXN][8];
+#pragma unroll
+  for (int m = 0; m < MAXN; m++)
+#pragma unroll
+    for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
+  for (int64_t c0 = P0; c0 < P1; c0 += CH) {
+    const int64_t c1 = min(c0 + (int64_t)CH, P1);
+    const int cn = (int)(c1 - c0);
+    for (int i = threadIdx.x; i < cn * 32; i += blockDim.x) s_src[i] = src4[(size_t)32 * c0 + i];
+    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) s_u[i] = g.u[(size_t)3 * c0 + i];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXN; m++) {
+      const int nd = threadIdx.x + m * GT_THREADS;
+      if (nd >= plane) continue;
+      const int y = nd / n2, z = nd - y * n2;
+      for (int dx = -1; dx <= 1; dx++) {
+        const int ax = x + dx;
+        if (ax < 0 || ax >= n0) continue;
+        for (int dy = -1; dy <= 1; dy++) {
+          const int ay = y + dy;
+          if (ay < 0 || ay >= n1) continue;
+          const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
+          for (int dz = -1; dz <= 1; dz++) {
+            const int az = z + dz;
+            if (az < 0 || az >= n2) continue;
+            const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
+            for (int64_t p = p0; p < p1; p++) {
+              const int lp = (int)(p - c0);
+              T Lx, Ly, Lz, dLx, dLy, dLz;
+              lagr_pick(-dx, s_u[3 * lp], Lx, dLx);
+              lagr_pick(-dy, s_u[3 * lp + 1], Ly, dLy);
+              lagr_pick(-dz, s_u[3 * lp + 2], Lz, dLz);
+              const T W = Lx * Ly * Lz, Wx = dLx * Ly * Lz * inv_h, Wy = Lx * dLy * Lz * inv_h,
+                      Wz = Lx * Ly * dLz * inv_h;
+              const cx<T> *sp = s_src + 32 * lp;
+#pragma unroll
+              for (int f = 0; f < 8; f++) {
+                axpy(acc[m][f], W, sp[4 * f]);
+                axpy(acc[m][f], Wx, sp[4 * f + 1]);
+                axpy(acc[m][f], Wy, sp[4 * f + 2]);
+                axpy(acc[m][f], Wz, sp[4 * f + 3]);
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const size_t G = (size_t)g.ncell;
+#pragma unroll
+  for (int m = 0; m < MAXN; m++) {
+    const int nd = threadIdx.x + m * GT_THREADS;
+    if (nd >= plane) continue;
+#pragma unroll
+    for (int f = 0; f < 8; f++) dg.phys[f * G + (size_t)x * plane + nd] = acc[m][f];
+  }
+}
+
+template <typename T>
+void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids, const std::vector<GatherGrid<T>> &gg,
+                   const std::vector<cx<T> *> &src4, T inv_h, hipStream_t s) {
+  for (size_t k = 0; k < grids.size(); k++) {
+    const GatherGrid<T> &g = gg[k];
+    hipLaunchKernelGGL(adj_sources_kernel<T>, dim3((g.np + 255) / 256), dim3(256), 0, s, op.pts, op.tris, op.src, g,
+                       src4[k], grids[k].k, grids[k].Z, grids[k].which >= 0 ? 1 : 0);
+  }
+  for (size_t k = 0; k < grids.size(); k++)
+    hipLaunchKernelGGL(gather_adj_kernel<T>, dim3(grids[k].n[0]), dim3(GT_THREADS), 0, s, grids[k], gg[k], src4[k],
+                       inv_h);
+}
+template void launch_test_t<float>(const DevOperator<float> &, const std::vector<DevGrid<float>> &,
+                                   const std::vector<GatherGrid<float>> &, const std::vector<cx<float> *> &, float,
+                                   hipStream_t);
+template void launch_test_t<double>(const DevOperator<double> &, const std::vector<DevGrid<double>> &,
+                                    const std::vector<GatherGrid<double>> &, const std::vector<cx<double> *> &, double,
+                                    hipStream_t);
+
+// ---------------------------------------------------------------------------
+// source^T and local^T: at every point the convolved lattice values of the
+// exterior grid and of the point's own interior grid (W only), handed to the
+// three half-RWG currents (J_e, J_i, M) of its triangle, plus the transposed
+// point-local terms:  H residue -1/2 <f, n x (J_e + J_i)>, Gram <f, J_e + J_i>
+// on eq14 rows, and the 1/2 n x M residue inside the sigma-weighted tests.
+// Per-triangle half-edge partials (3 currents per half-edge) in tri_out.
+// ---------------------------------------------------------------------------
+constexpr int IA_TRIS = 32;
+constexpr int IA_THREADS = IA_TRIS * NQ;
+
+template <typename T>
+__device__ inline void gather_vals(const DevGrid<T> &g, int ax, int ay, int az, const T *Lx, const T *Ly, const T *Lz,
+                                   cx<T> *val) {
+#pragma unroll
+  for (int f = 0; f < 8; f++) val[f] = czero<T>();
+  const int n1 = g.n[1], n2 = g.n[2];
+  const size_t G = (size_t)g.n[0] * n1 * n2;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      const size_t row = ((size_t)(ax + i - 1) * n1 + (ay + j - 1)) * n2 + (az - 1);
+      const T wxy = Lx[i] * Ly[j];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        const T w = wxy * Lz[k];
+#pragma unroll
+        for (int f = 0; f < 8; f++) axpy(val[f], w, g.phys[f * G + row + k]);
+      }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(IA_THREADS)
+interp_adj_kernel(DevOperator<T> op, DevGrid<T> ext, const DevGrid<T> *__restrict__ ints) {
+  __shared__ cx<T> part[IA_THREADS][9];
+  const int lt = threadIdx.x / NQ, q = threadIdx.x - lt * NQ;
+  const int tri = blockIdx.x * IA_TRIS + lt;
+  cx<T> out[9];
+#pragma unroll
+  for (int r = 0; r < 9; r++) out[r] = czero<T>();
+  if (tri < op.nt) {
+    const PointRec<T> P = op.pts[tri * NQ + q];
+    const TriRec<T> tr = op.tris[tri];
+    const T n[3] = {tr.nrm[0], tr.nrm[1], tr.nrm[2]};
+    const T w = P.w, ws = P.w * P.sigma;
+    cx<T> tH[3], tR[3];
+    for (int a = 0; a < 3; a++) tH[a] = tR[a] = czero<T>();
+    for (int j = 0; j < 3; j++) {
+      const int e = tr.edge[j];
+      const cx<T> zH = op.src[3 * e + 1], z14 = op.src[3 * e + 2];
+      for (int a = 0; a < 3; a++) {
+        axpy(tH[a], P.f[3 * j + a], zH);
+        axpy(tR[a], P.f[3 * j + a], z14);
+      }
+    }
+    // coefficient vectors of J_e + J_i and of M at the point
+    cx<T> hxn[3], rxn[3], aJs[3], aMq[3];
+    hxn[0] = tH[1] * n[2] - tH[2] * n[1];
+    hxn[1] = tH[2] * n[0] - tH[0] * n[2];
+    hxn[2] = tH[0] * n[1] - tH[1] * n[0];
+    rxn[0] = tR[1] * n[2] - tR[2] * n[1];
+    rxn[1] = tR[2] * n[0] - tR[0] * n[2];
+    rxn[2] = tR[0] * n[1] - tR[1] * n[0];
+    const cx<T> hxnxn[3] = {hxn[1] * n[2] - hxn[2] * n[1], hxn[2] * n[0] - hxn[0] * n[2],
+                            hxn[0] * n[1] - hxn[1] * n[0]};
+    for (int a = 0; a < 3; a++) {
+      aJs[a] = (T(-0.5) * w) * hxn[a] + w * tR[a];
+      aMq[a] = (T(0.5) * ws) * (hxnxn[a] - rxn[a]);
+    }
+    T Lx[3], Ly[3], Lz[3], dLx[3], dLy[3], dLz[3];
+    lagr3(P.u[0], Lx, dLx);
+    lagr3(P.u[1], Ly, dLy);
+    lagr3(P.u[2], Lz, dLz);
+    int ax, ay, az;
+    unpack_anchor(P.anc, ax, ay, az);
+    cx<T> ve[8], vi[8];
+    gather_vals(ext, ax - ext.off[0], ay - ext.off[1], az - ext.off[2], Lx, Ly, Lz, ve);
+    const DevGrid<T> &gi = ints[tr.body];
+    gather_vals(gi, ax - gi.off[0], ay - gi.off[1], az - gi.off[2], Lx, Ly, Lz, vi);
+    for (int j = 0; j < 3; j++) {
+      const T f[3] = {P.f[3 * j], P.f[3 * j + 1], P.f[3 * j + 2]};
+      const T dv = tr.div[j];
+      cx<T> fl = f[0] * aJs[0];
+      axpy(fl, f[1], aJs[1]);
+      axpy(fl, f[2], aJs[2]);
+      cx<T> fm = f[0] * aMq[0];
+      axpy(fm, f[1], aMq[1]);
+      axpy(fm, f[2], aMq[2]);
+      cx<T> je = dv * ve[3], ji = dv * vi[3], me = dv * ve[7], mi = dv * vi[7];
+      for (int a = 0; a < 3; a++) {
+        axpy(je, f[a], ve[a]);
+        axpy(ji, f[a], vi[a]);
+        axpy(me, f[a], ve[4 + a]);
+        axpy(mi, f[a], vi[4 + a]);
+      }
+      out[3 * j] = w * je + fl;
+      out[3 * j + 1] = w * ji + fl;
+      out[3 * j + 2] = w * (me - mi) + fm;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 9; r++) part[threadIdx.x][r] = out[r];
+  __syncthreads();
+  for (int it = threadIdx.x; it < IA_TRIS * 9; it += blockDim.x) {
+    const int l = it / 9, r = it - l * 9;
+    const int t2 = blockIdx.x * IA_TRIS + l;
+    if (t2 < op.nt) {
+      cx<T> s = czero<T>();
+      for (int qq = 0; qq < NQ; qq++) s += part[l * NQ + qq][r];
+      op.tri_out[(size_t)t2 * 9 + r] = s;
+    }
+  }
+}
+
+template <typename T>
+void launch_interp_adj(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, hipStream_t s) {
+  hipLaunchKernelGGL(interp_adj_kernel<T>, dim3((op.nt + IA_TRIS - 1) / IA_TRIS), dim3(IA_THREADS), 0, s, op, ext,
+                     ints_dev);
+}
+template void launch_interp_adj<float>(const DevOperator<float> &, const DevGrid<float> &, const DevGrid<float> *,
+                                       hipStream_t);
+template void launch_interp_adj<double>(const DevOperator<double> &, const DevGrid<double> &,
+                                        const DevGrid<double> *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// near^T: one wave per column edge m.  Row n of the forward correction adds
+//   E_n += Z_i L_i J_i - Z_e L_e J_e + (K_e + K_i) M
+//   H_n += K_i J_i - K_e J_e - (L_e/Z_e + L_i/Z_i) M + K_r M - Z_e L_r J_e
+//   14_n += Z_i L_s J_i + K_s M
+// (the last four values vanish on sigma-free rows), so m's currents collect
+// the same coefficients against (z_E, z_H, z_14) of every row n near m, read
+// at the mirrored CSR entry tpos.  Adds the two triangle halves of m and maps
+// (J_e, J_i, M) to m's unknowns (sigma-free: J_e = J, J_i = -J).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ inline T wsum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+near_rows_t_kernel(DevOperator<T> op, const int64_t *__restrict__ tpos, double *__restrict__ y) {
+  const int m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (m >= op.ne) return;
+  const EdgeRec r = op.edges[m];
+  const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
+  cx<T> aJe = czero<T>(), aJi = czero<T>(), aM = czero<T>();
+  const int64_t b = op.rowptr[m], e = op.rowptr[m + 1];
+  for (int64_t k = b + lane; k < e; k += 64) {
+    const int n = op.col[k];
+    const int64_t t = tpos[k];
+    const cx<T> zE = op.src[3 * n], zH = op.src[3 * n + 1], z14 = op.src[3 * n + 2];
+    const cx<T> Le = op.V4[4 * t], Ke = op.V4[4 * t + 1], Li = op.V4[4 * t + 2], Ki = op.V4[4 * t + 3];
+    const cx<T> Lr = op.S4[4 * t], Kr = op.S4[4 * t + 1], Ls = op.S4[4 * t + 2], Ks = op.S4[4 * t + 3];
+    aJe -= (Le * zE) * Ze + Ke * zH + (Lr * zH) * Ze;
+    aJi += (Li * zE) * Zi + Ki * zH + (Ls * z14) * Zi;
+    aM += (Ke + Ki) * zE - (Le * zH) * iZe - (Li * zH) * iZi + Kr * zH + Ks * z14;
+  }
+  aJe.x = wsum(aJe.x);
+  aJe.y = wsum(aJe.y);
+  aJi.x = wsum(aJi.x);
+  aJi.y = wsum(aJi.y);
+  aM.x = wsum(aM.x);
+  aM.y = wsum(aM.y);
+  if (lane == 0) {
+    const cx<T> *p0 = op.tri_out + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
+    const cx<T> *p1 = op.tri_out + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
+    aJe += p0[0] + p1[0];
+    aJi += p0[1] + p1[1];
+    aM += p0[2] + p1[2];
+    if (!r.isR) {
+      const cx<T> j = aJe - aJi;
+      y[2 * r.col[0]] = j.x;
+      y[2 * r.col[0] + 1] = j.y;
+      y[2 * r.col[1]] = aM.x;
+      y[2 * r.col[1] + 1] = aM.y;
+    } else {
+      y[2 * r.col[0]] = aJe.x;
+      y[2 * r.col[0] + 1] = aJe.y;
+      y[2 * r.col[1]] = aJi.x;
+      y[2 * r.col[1] + 1] = aJi.y;
+      y[2 * r.col[2]] = aM.x;
+      y[2 * r.col[2] + 1] = aM.y;
+    }
+  }
+}
+
+template <typename T>
+void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y, hipStream_t s) {
+  int blocks = (int)(((int64_t)op.ne * 64 + 255) / 256);
+  hipLaunchKernelGGL(near_rows_t_kernel<T>, dim3(blocks), dim3(256), 0, s, op, tpos, y);
+}
+template void launch_near_rows_t<float>(const DevOperator<float> &, const int64_t *, double *, hipStream_t);
+template void launch_near_rows_t<double>(const DevOperator<double> &, const int64_t *, double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// transposed Schwarz preconditioner: y = sum_c R_ext^T B_c^T P_core x with
+// B_c the stored core rows of cluster c's inverse.  Step 1: one wave per
+// (cluster, ext column j) forms dot(B_c[:, j], x[core_c]); step 2: every
+// unknown sums its entries over the clusters whose ext set holds it (fixed
+// order, no atomics).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+precond_t_dots_kernel(int nc, const int64_t *__restrict__ ext_ptr, const int *__restrict__ ext_cluster,
+                      const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
+                      const int64_t *__restrict__ r_off, const cx<float> *__restrict__ Rt,
+                      const cx<double> *__restrict__ x, cx<double> *__restrict__ tmp, int64_t n_ext) {
+  const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (it >= n_ext) return;
+  const int c = ext_cluster[it];
+  const int j = (int)(it - ext_ptr[c]);
+  const int ncore = (int)(core_ptr[c + 1] - core_ptr[c]);
+  const cx<float> *R = Rt + r_off[c] + (size_t)j * ncore;
+  const int *cs = core_slot + core_ptr[c];
+  double ar = 0, ai = 0;
+  for (int i = lane; i < ncore; i += 64) {
+    const cx<float> rv = R[i];
+    const cx<double> xv = x[cs[i]];
+    ar += (double)rv.x * xv.x - (double)rv.y * xv.y;
+    ai += (double)rv.x * xv.y + (double)rv.y * xv.x;
+  }
+  ar = wsum(ar);
+  ai = wsum(ai);
+  if (lane == 0) tmp[it] = {ar, ai};
+  (void)nc;
+}
+
+__global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_ptr, const int64_t *__restrict__ inv_pos,
+                                     const cx<double> *__restrict__ tmp, cx<double> *__restrict__ y) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x) {
+    cx<double> s = {0.0, 0.0};
+    for (int64_t p = inv_ptr[u]; p < inv_ptr[u + 1]; p++) s += tmp[inv_pos[p]];
+    y[u] = s;
+  }
+}
+
+void launch_precond_apply_t(int nc, int64_t n_ext, int64_t N, const int64_t *ext_ptr, const int *ext_cluster,
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                            const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
+                            cx<double> *y, hipStream_t s) {
+  const int64_t threads = n_ext * 64;
+  hipLaunchKernelGGL(precond_t_dots_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nc, ext_ptr,
+                     ext_cluster, core_ptr, core_slot, r_off, Rt, x, tmp, n_ext);
+  hipLaunchKernelGGL(precond_t_sum_kernel, dim3(1024), dim3(256), 0, s, N, inv_ptr, inv_pos, (const cx<double> *)tmp,
+                     y);
+}
+
+// ---------------------------------------------------------------------------
+// pointwise one-sided fields of the grid part (FP64) at every test point:
+//   E_e^+ = -Z_e jk_e (a_J + k_e^-2 grad phi_J) - curl a_M + 1/2 n x M
+//   E_i^- = the same with the interior potentials (J_i, -M) + 1/2 n x M
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+point_fields_kernel(DevOperator<double> op, DevGrid<double> ext, const DevGrid<double> *__restrict__ ints,
+                    double inv_h, cx<double> *__restrict__ Ee, cx<double> *__restrict__ Ei) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= op.np) return;
+  const PointRec<double> P = op.pts[p];
+  const TriRec<double> tr = op.tris[P.tri];
+  const double *n = tr.nrm;
+  cx<double> Mq[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int j = 0; j < 3; j++) {
+    const cx<double> M = op.src[3 * tr.edge[j] + 2];
+    for (int a = 0; a < 3; a++) axpy(Mq[a], P.f[3 * j + a], M);
+  }
+  cx<double> hnM[3];
+  hnM[0] = 0.5 * (n[1] * Mq[2] - n[2] * Mq[1]);
+  hnM[1] = 0.5 * (n[2] * Mq[0] - n[0] * Mq[2]);
+  hnM[2] = 0.5 * (n[0] * Mq[1] - n[1] * Mq[0]);
+  double L[3][3], dL[3][3];
+  for (int a = 0; a < 3; a++) lagr3(P.u[a], L[a], dL[a]);
+  int ax, ay, az;
+  unpack_anchor(P.anc, ax, ay, az);
+  for (int med = 0; med < 2; med++) {
+    const DevGrid<double> &g = med == 0 ? ext : ints[tr.body];
+    const int bx = ax - g.off[0], by = ay - g.off[1], bz = az - g.off[2];
+    const int n1 = g.n[1], n2 = g.n[2];
+    const size_t G = (size_t)g.n[0] * n1 * n2;
+    // values of a_J (0..2) and grad of phi_J (3) and of a_M (4..6)
+    cx<double> aJ[3] = {{0, 0}, {0, 0}, {0, 0}}, gphi[3] = {{0, 0}, {0, 0}, {0, 0}};
+    cx<double> gM[3][3] = {{{0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}}};
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++)
+        for (int k = 0; k < 3; k++) {
+          const size_t node = ((size_t)(bx + i - 1) * n1 + (by + j - 1)) * n2 + (bz + k - 1);
+          const double w = L[0][i] * L[1][j] * L[2][k];
+          const double gw[3] = {dL[0][i] * L[1][j] * L[2][k] * inv_h, L[0][i] * dL[1][j] * L[2][k] * inv_h,
+                                L[0][i] * L[1][j] * dL[2][k] * inv_h};
+          for (int a = 0; a < 3; a++) axpy(aJ[a], w, g.phys[a * G + node]);
+          const cx<double> ph = g.phys[3 * G + node];
+          for (int a = 0; a < 3; a++) axpy(gphi[a], gw[a], ph);
+          for (int c = 0; c < 3; c++) {
+            const cx<double> v = g.phys[(4 + c) * G + node];
+            for (int a = 0; a < 3; a++) axpy(gM[c][a], gw[a], v);
+          }
+        }
+    const cx<double> cM[3] = {gM[2][1] - gM[1][2], gM[0][2] - gM[2][0], gM[1][0] - gM[0][1]};
+    const double k = g.k, Z = g.Z;
+    cx<double> *dst = (med == 0 ? Ee : Ei) + 3 * (size_t)p;
+    for (int a = 0; a < 3; a++) {
+      cx<double> t = aJ[a];
+      axpy(t, 1.0 / (k * k), gphi[a]);
+      dst[a] = mul_j(t) * (-Z * k) - cM[a] + hnM[a];
+    }
+  }
+}
+
+void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &ext, const DevGrid<double> *ints_dev,
+                         double inv_h, cx<double> *Ee, cx<double> *Ei, hipStream_t s) {
+  hipLaunchKernelGGL(point_fields_kernel, dim3((op.np + 255) / 256), dim3(256), 0, s, op, ext, ints_dev, inv_h, Ee, Ei);
+}
+
+// ---------------------------------------------------------------------------
+// d f / d sigma_q = 2 Re{ w_q [ t_14 . (E_inc + E_i^-) - (t_H x n) . E_e^+ ] }
+// with t_H = sum lam_H f, t_14 = sum lam_14 f over the absorber edges of the
+// point's triangle (lam unpacked into op.src as row weights): the sigma-
+// weighted tests of eq13 (rotated by n x) and eq14 and the eq14 right-hand
+// side are the only places sigma enters (Appendix A).
+// ---------------------------------------------------------------------------
+__global__ void sigma_grad_kernel(DevOperator<double> op, const cx<double> *__restrict__ Ee,
+                                  const cx<double> *__restrict__ Ei, const cx<double> *__restrict__ Einc,
+                                  double *__restrict__ dfds) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= op.np) return;
+  const PointRec<double> P = op.pts[p];
+  const TriRec<double> tr = op.tris[P.tri];
+  const double *n = tr.nrm;
+  cx<double> tH[3] = {{0, 0}, {0, 0}, {0, 0}}, t14[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int j = 0; j < 3; j++) {
+    const int e = tr.edge[j];
+    if (!op.edges[e].isR) continue;
+    const cx<double> lH = op.src[3 * e + 1], l14 = op.src[3 * e + 2];
+    for (int a = 0; a < 3; a++) {
+      axpy(tH[a], P.f[3 * j + a], lH);
+      axpy(t14[a], P.f[3 * j + a], l14);
+    }
+  }
+  const cx<double> hxn[3] = {tH[1] * n[2] - tH[2] * n[1], tH[2] * n[0] - tH[0] * n[2], tH[0] * n[1] - tH[1] * n[0]};
+  cx<double> v = {0.0, 0.0};
+  for (int a = 0; a < 3; a++) {
+    cx<double> et = Ei[3 * (size_t)p + a];
+    if (Einc) et += Einc[3 * (size_t)p + a];
+    v += t14[a] * et - hxn[a] * Ee[3 * (size_t)p + a];
+  }
+  dfds[p] = 2.0 * P.w * v.x;
+}
+
+void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, const cx<double> *Ei,
+                       const cx<double> *Einc, double *dfds, hipStream_t s) {
+  hipLaunchKernelGGL(sigma_grad_kernel, dim3((op.np + 255) / 256), dim3(256), 0, s, op, Ee, Ei, Einc, dfds);
+}
+
+// ---------------------------------------------------------------------------
+// fields at off-surface points (plain 7-point rule over every source point;
+// targets must stay well away from the surface).  region < 0: exterior
+// medium, currents (J_e, M); region = b: interior medium of body b, currents
+// (J_i, -M) of its triangles.  E = -Z L(J) + K(M), H = -K(J) - L(M)/Z with
+// L(X) = jk [int X G + k^-2 int grad G div X], K(X) = -int grad G x X.
+// One work-group per target point.
+// ---------------------------------------------------------------------------
+constexpr int EF_THREADS = 256;
+__device__ inline void green_grad(double k, const double *r, const double *s, cx<double> &G, cx<double> *g) {
+  const double d[3] = {r[0] - s[0], r[1] - s[1], r[2] - s[2]};
+  const double R = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  const cx<double> e = {cs, -sn};
+  G = e * (1.0 / (4.0 * PI * R));
+  const cx<double> dG = (cx<double>{1.0, k * R} * e) * (-1.0 / (4.0 * PI * R * R));
+  for (int a = 0; a < 3; a++) g[a] = dG * (d[a] / R);
+}
+
+__global__ void __launch_bounds__(EF_THREADS)
+eval_field_kernel(DevOperator<double> op, const double *__restrict__ qp, const double *__restrict__ pts, int region,
+                  double k, double Z, cx<double> *__restrict__ E, cx<double> *__restrict__ H) {
+  const int t = blockIdx.x;
+  const double r[3] = {pts[3 * t], pts[3 * t + 1], pts[3 * t + 2]};
+  cx<double> e[3] = {{0, 0}, {0, 0}, {0, 0}}, h[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int p = threadIdx.x; p < op.np; p += blockDim.x) {
+    const PointRec<double> P = op.pts[p];
+    const TriRec<double> tr = op.tris[P.tri];
+    if (region >= 0 && tr.body != region) continue;
+    cx<double> Jq[3] = {{0, 0}, {0, 0}, {0, 0}}, Mq[3] = {{0, 0}, {0, 0}, {0, 0}}, rJ = {0, 0}, rM = {0, 0};
+    for (int j = 0; j < 3; j++) {
+      const int m = tr.edge[j];
+      const cx<double> J = op.src[3 * m + (region < 0 ? 0 : 1)];
+      const cx<double> M = region < 0 ? op.src[3 * m + 2] : -op.src[3 * m + 2];
+      for (int a = 0; a < 3; a++) {
+        axpy(Jq[a], P.f[3 * j + a], J);
+        axpy(Mq[a], P.f[3 * j + a], M);
+      }
+      axpy(rJ, tr.div[j], J);
+      axpy(rM, tr.div[j], M);
+    }
+    cx<double> G, g[3];
+    green_grad(k, r, qp + 3 * (size_t)p, G, g);
+    const cx<double> gJ[3] = {g[1] * Jq[2] - g[2] * Jq[1], g[2] * Jq[0] - g[0] * Jq[2], g[0] * Jq[1] - g[1] * Jq[0]};
+    const cx<double> gM[3] = {g[1] * Mq[2] - g[2] * Mq[1], g[2] * Mq[0] - g[0] * Mq[2], g[0] * Mq[1] - g[1] * Mq[0]};
+    for (int a = 0; a < 3; a++) {
+      const cx<double> LJ = mul_j(Jq[a] * G + g[a] * rJ * (1.0 / (k * k))) * k;
+      const cx<double> LM = mul_j(Mq[a] * G + g[a] * rM * (1.0 / (k * k))) * k;
+      e[a] += (LJ * (-Z) - gM[a]) * P.w;
+      h[a] += (gJ[a] - LM * (1.0 / Z)) * P.w;
+    }
+  }
+  __shared__ cx<double> red[EF_THREADS / 64][6];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = 0; a < 3; a++) {
+    e[a].x = wsum(e[a].x);
+    e[a].y = wsum(e[a].y);
+    h[a].x = wsum(h[a].x);
+    h[a].y = wsum(h[a].y);
+  }
+  if (lane == 0)
+    for (int a = 0; a < 3; a++) {
+      red[wv][a] = e[a];
+      red[wv][3 + a] = h[a];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    cx<double> s = {0, 0};
+    for (int w = 0; w < EF_THREADS / 64; w++) s += red[w][threadIdx.x];
+    if (threadIdx.x < 3)
+      E[3 * t + threadIdx.x] = s;
+    else
+      H[3 * t + threadIdx.x - 3] = s;
+  }
+}
+
+void launch_eval_field(const DevOperator<double> &op, const double *qp, const double *pts, int npts, int region,
+                       double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s) {
+  hipLaunchKernelGGL(eval_field_kernel, dim3(npts), dim3(EF_THREADS), 0, s, op, qp, pts, region, k, Z, E, H);
+}
+
+// Transpose of the E part: for weights wE (npts x 3) the per-point
+// coefficients of the half-RWG currents,
+//   J_j: w_p sum_t wE_t . (-Z jk (f_j G + k^-2 grad G div f_j))
+//   M_j: -w_p sum_t f_j . (wE_t x grad G)
+// summed over each triangle's points into tri_out (J_e or J_i, M slots).
+constexpr int ET_TRIS = 32;
+__global__ void __launch_bounds__(ET_TRIS * NQ)
+eval_field_t_kernel(DevOperator<double> op, const double *__restrict__ qp, const double *__restrict__ pts, int npts,
+                    int region, double k, double Z, const cx<double> *__restrict__ wE) {
+  __shared__ cx<double> part[ET_TRIS * NQ][9];
+  const int lt = threadIdx.x / NQ, q = threadIdx.x - lt * NQ;
+  const int tri = blockIdx.x * ET_TRIS + lt;
+  cx<double> out[9];
+  for (int r = 0; r < 9; r++) out[r] = {0, 0};
+  if (tri < op.nt && (region < 0 || op.tris[tri].body == region)) {
+    const int p = tri * NQ + q;
+    const PointRec<double> P = op.pts[p];
+    const TriRec<double> tr = op.tris[tri];
+    cx<double> sG[3] = {{0, 0}, {0, 0}, {0, 0}}, sg = {0, 0}, cr[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int t = 0; t < npts; t++) {
+      cx<double> G, g[3];
+      green_grad(k, pts + 3 * t, qp + 3 * (size_t)p, G, g);
+      const cx<double> *w = wE + 3 * t;
+      for (int a = 0; a < 3; a++) sG[a] += w[a] * G;          // sum_t wE G
+      sg += w[0] * g[0] + w[1] * g[1] + w[2] * g[2];          // sum_t wE . grad G
+      cr[0] += w[1] * g[2] - w[2] * g[1];                     // sum_t wE x grad G
+      cr[1] += w[2] * g[0] - w[0] * g[2];
+      cr[2] += w[0] * g[1] - w[1] * g[0];
+    }
+    for (int j = 0; j < 3; j++) {
+      const double *f = P.f + 3 * j;
+      cx<double> fv = f[0] * sG[0];
+      axpy(fv, f[1], sG[1]);
+      axpy(fv, f[2], sG[2]);
+      axpy(fv, tr.div[j] / (k * k), sg);
+      const cx<double> aj = mul_j(fv) * (-Z * k * P.w);
+      cx<double> am = f[0] * cr[0];
+      axpy(am, f[1], cr[1]);
+      axpy(am, f[2], cr[2]);
+      am = am * (-P.w);
+      if (region < 0) {
+        out[3 * j] = aj;
+        out[3 * j + 2] = am;
+      } else {
+        out[3 * j + 1] = aj;
+        out[3 * j + 2] = -am;
+      }
+    }
+  }
+  for (int r = 0; r < 9; r++) part[threadIdx.x][r] = out[r];
+  __syncthreads();
+  for (int it = threadIdx.x; it < ET_TRIS * 9; it += blockDim.x) {
+    const int l = it / 9, r = it - l * 9;
+    const int t2 = blockIdx.x * ET_TRIS + l;
+    if (t2 < op.nt) {
+      cx<double> s = {0, 0};
+      for (int qq = 0; qq < NQ; qq++) s += part[l * NQ + qq][r];
+      op.tri_out[(size_t)t2 * 9 + r] = s;
+    }
+  }
+}
+
+// per edge: sum of its two triangle halves of (J_e, J_i, M) adjoints mapped to
+// its unknowns (sigma-free edges: J_e = J, J_i = -J)
+__global__ void edge_collect_kernel(DevOperator<double> op, double *__restrict__ y) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= op.ne) return;
+  const EdgeRec r = op.edges[m];
+  const cx<double> *p0 = op.tri_out + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
+  const cx<double> *p1 = op.tri_out + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
+  const cx<double> aJe = p0[0] + p1[0], aJi = p0[1] + p1[1], aM = p0[2] + p1[2];
+  if (!r.isR) {
+    const cx<double> j = aJe - aJi;
+    y[2 * r.col[0]] = j.x;
+    y[2 * r.col[0] + 1] = j.y;
+    y[2 * r.col[1]] = aM.x;
+    y[2 * r.col[1] + 1] = aM.y;
+  } else {
+    y[2 * r.col[0]] = aJe.x;
+    y[2 * r.col[0] + 1] = aJe.y;
+    y[2 * r.col[1]] = aJi.x;
+    y[2 * r.col[1] + 1] = aJi.y;
+    y[2 * r.col[2]] = aM.x;
+    y[2 * r.col[2] + 1] = aM.y;
+  }
+}
+
+void launch_eval_field_t(const DevOperator<double> &op, const double *qp, const double *pts, int npts, int region,
+                         double k, double Z, const cx<double> *wE, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(eval_field_t_kernel, dim3((op.nt + ET_TRIS - 1) / ET_TRIS), dim3(ET_TRIS * NQ), 0, s, op, qp, pts,
+                     npts, region, k, Z, wE);
+  hipLaunchKernelGGL(edge_collect_kernel, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, y);
+}
+
+}  // namespace scabs

@@ -448,6 +448,30 @@ __global__ void rhs_dipole_kernel(int nt, const int *__restrict__ body, const Tr
   }
 }
 
+// incident field of the dipole at every quadrature point of its body (zero on
+// the other bodies)
+__global__ void incident_points_kernel(int np, const int *__restrict__ body, const PointRec<double> *__restrict__ pts,
+                                       const double *__restrict__ qp, double k, double Z, double px, double py,
+                                       double pz, cx<double> m0, cx<double> m1, cx<double> m2, int bodyid,
+                                       cx<double> *__restrict__ E) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  cx<double> e[3] = {{0, 0}, {0, 0}, {0, 0}}, h[3];
+  if (body[pts[p].tri] == bodyid) {
+    const double r0[3] = {px, py, pz};
+    const cx<double> mo[3] = {m0, m1, m2};
+    dipole_fields(k, Z, r0, mo, qp + 3 * (size_t)p, e, h);
+  }
+  for (int a = 0; a < 3; a++) E[3 * (size_t)p + a] = e[a];
+}
+
+void launch_incident_points(int np, const int *body, const PointRec<double> *pts, const double *qp, double k, double Z,
+                            const double *pos, const double *mom, int bodyid, cx<double> *E, hipStream_t s) {
+  hipLaunchKernelGGL(incident_points_kernel, dim3((np + 255) / 256), dim3(256), 0, s, np, body, pts, qp, k, Z, pos[0],
+                     pos[1], pos[2], cx<double>{mom[0], mom[1]}, cx<double>{mom[2], mom[3]},
+                     cx<double>{mom[4], mom[5]}, bodyid, E);
+}
+
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,
                        const TriRec<double> *tris, const PointRec<double> *pts, const EdgeRec *edges, double k, double Z,
                        const double *pos, const double *mom, int bodyid, double *b, hipStream_t s) {

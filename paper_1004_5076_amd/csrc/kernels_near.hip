@@ -116,9 +116,14 @@ __device__ inline void kernel_val(double k, double R, bool remainder, cx<double>
   }
 }
 
-__global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a) {
+// MODE 0: tested blocks of every near pair (exact - grid, and exact alone).
+// MODE 1: pointwise (exact - grid) one-sided fields at the test points of the
+//         masked triangles from the currents a.cur, added into a.Ee / a.Ei.
+template <int MODE> __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a) {
   const int T = blockIdx.x;
   const int tid = threadIdx.x;
+  if (MODE == 1 && !a.tmask[T]) return;   // uniform over the work-group
+  cx<double> fe[3] = {{0, 0}, {0, 0}, {0, 0}}, fi[3] = {{0, 0}, {0, 0}, {0, 0}};
   __shared__ double s_tp[NQ][3], s_tw[NQ], s_tsig[NQ];
   __shared__ double s_tg[NQ][3][3];
   __shared__ double s_tdiv[3], s_n[3];
@@ -206,7 +211,8 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
       s_sdiv[tid] = 2.0 * s_scoef[tid];
       for (int c = 0; c < 3; c++) s_sv[tid][c] = a.v[3 * a.t[3 * Tp + tid] + c];
     }
-    for (int i = tid; i < 2 * NQ * NTYPES * 9; i += NS_THREADS) (&s_part[0][0][0])[i] = cx<double>{0.0, 0.0};
+    if (MODE == 0)
+      for (int i = tid; i < 2 * NQ * NTYPES * 9; i += NS_THREADS) (&s_part[0][0][0])[i] = cx<double>{0.0, 0.0};
     __syncthreads();
 
     for (int med = 0; med < (same ? 2 : 1); med++) {
@@ -264,7 +270,7 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
       __syncthreads();
       // per test point: inner integrals, then its share of the tested blocks,
       // once for exact - grid (variant 0) and once for exact alone (variant 1)
-      if (tid < 2 * NQ) {
+      if (tid < (MODE == 0 ? 2 : 1) * NQ) {
         const int t = tid % NQ, var = tid / NQ;
         const D3 r = d3(s_tp[t]);
         cx<double> S0 = {0, 0};
@@ -306,6 +312,7 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
         }
         cx<double> *part = s_part[var][t];
         const double w = s_tw[t], sg = s_tsig[t], ik2 = 1.0 / (k * k);
+        const double Zm = med ? a.Z_i : a.Z_e;
         for (int j = 0; j < 3; j++) {
           const D3 rv = r - d3(s_sv[j]);
           // a_j = coef_j (S1 + (r - v_j) S0); phi_j = div_j S0; grad phi_j = div_j Sg; c_j = coef_j Sc_j
@@ -320,6 +327,17 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
           Lv.y = mul_j(aj.y + gpj.y * ik2) * k;
           Lv.z = mul_j(aj.z + gpj.z * ik2) * k;
           const Z3 Kv = {-cj.x, -cj.y, -cj.z};
+          if (MODE == 1) {
+            // E_e += -Z_e L(f_j) J_e + K(f_j) M ;  E_i += -Z_i L(f_j) J_i - K(f_j) M  (M_i = -M)
+            const int m = a.tedge[3 * Tp + j];
+            const cx<double> J = a.cur[3 * m + (med ? 1 : 0)], M = a.cur[3 * m + 2];
+            cx<double> *f = med ? fi : fe;
+            const double sm = med ? -1.0 : 1.0;
+            f[0] += (Lv.x * J) * (-Zm) + (Kv.x * M) * sm;
+            f[1] += (Lv.y * J) * (-Zm) + (Kv.y * M) * sm;
+            f[2] += (Lv.z * J) * (-Zm) + (Kv.z * M) * sm;
+            continue;
+          }
           for (int i = 0; i < 3; i++) {
             const D3 gi = d3(s_tg[t][i]);
             cx<double> tl = zdot(gi, aj);
@@ -342,19 +360,30 @@ __global__ void __launch_bounds__(NS_THREADS) near_setup_kernel(NearSetupArgs a)
       }
       __syncthreads();
     }
-    for (int e = tid; e < 2 * NTYPES * 9; e += NS_THREADS) {
-      const int var = e / (NTYPES * 9), ee = e - var * NTYPES * 9;
-      cx<double> s = {0, 0};
-      for (int t = 0; t < NQ; t++) s += s_part[var][t][ee];
-      (var ? a.blocks_exact : a.blocks)[(size_t)p * NTYPES * 9 + ee] = s;
-    }
+    if (MODE == 0)
+      for (int e = tid; e < 2 * NTYPES * 9; e += NS_THREADS) {
+        const int var = e / (NTYPES * 9), ee = e - var * NTYPES * 9;
+        cx<double> s = {0, 0};
+        for (int t = 0; t < NQ; t++) s += s_part[var][t][ee];
+        (var ? a.blocks_exact : a.blocks)[(size_t)p * NTYPES * 9 + ee] = s;
+      }
     __syncthreads();
+  }
+  if (MODE == 1 && tid < NQ) {
+    const size_t ip = (size_t)T * NQ + tid;
+    for (int c = 0; c < 3; c++) {
+      a.Ee[3 * ip + c] += fe[c];
+      a.Ei[3 * ip + c] += fi[c];
+    }
   }
   (void)tsig_any;
 }
 
 void launch_near_setup(const NearSetupArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(near_setup_kernel, dim3(a.nt), dim3(NS_THREADS), 0, s, a);
+  hipLaunchKernelGGL(near_setup_kernel<0>, dim3(a.nt), dim3(NS_THREADS), 0, s, a);
+}
+void launch_near_point_fields(const NearSetupArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(near_setup_kernel<1>, dim3(a.nt), dim3(NS_THREADS), 0, s, a);
 }
 
 __global__ void htab_kernel(double k, double h, int D, cx<double> *tab) {

@@ -164,6 +164,45 @@ void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vecto
   }
 }
 
+// d sigma_q / d p per quadrature point (CSR over points): parameters are, end
+// by end, sigma0 of a monomial end or the control values of a piecewise-linear
+// end, in the order the ends were added
+void sigma_param_jacobian(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<int64_t> &ptr,
+                          std::vector<int> &idx, std::vector<double> &val, int64_t *npar) {
+  size_t np = (size_t)g.nt * NQ;
+  std::vector<std::vector<std::pair<int, double>>> rows(np);
+  int base = 0;
+  for (const SigmaEnd &e : ends) {
+    const int n = e.ctrl.empty() ? 1 : (int)e.ctrl.size();
+    for (size_t i = 0; i < np; i++) {
+      double s = e.dir * (g.qp[3 * i + e.axis] - e.x0) / e.length;
+      if (s < 0) continue;
+      s = std::min(s, 1.0);
+      if (e.ctrl.empty()) {
+        rows[i].push_back({base, e.degree == 0 ? 1.0 : std::pow(s, e.degree)});
+      } else {
+        double step = 1.0 / (n - 1);
+        for (int k = 0; k < n; k++) {
+          double a = std::fabs(s - (double)k / (n - 1)) / step;
+          if (a < 1) rows[i].push_back({base + k, 1 - a});
+        }
+      }
+    }
+    base += n;
+  }
+  *npar = base;
+  ptr.assign(np + 1, 0);
+  idx.clear();
+  val.clear();
+  for (size_t i = 0; i < np; i++) {
+    for (auto &pr : rows[i]) {
+      idx.push_back(pr.first);
+      val.push_back(pr.second);
+    }
+    ptr[i + 1] = (int64_t)idx.size();
+  }
+}
+
 void build_layout(const Geometry &g, Layout &L) {
   L.isR.assign(g.ne, 0);
   L.eidx.assign(g.ne, 0);
