@@ -79,6 +79,7 @@ template <typename T> struct PrecState {
   DevGrid<T> *grids_dev = nullptr;
   std::vector<GatherGrid<T>> gather;
   std::vector<cx<T> *> src4;       // per grid: 32 adjoint-source coefficients per sorted point
+  int bcap = 1;                    // vectors the per-vector buffers hold
   DevOperator<T> op;
   T inv_h = 0;
 };
@@ -133,7 +134,7 @@ struct scabs_ctx {
   cx<double> *pc_tmp = nullptr;
   // solver workspace (grown on demand)
   DevMem work;
-  int work_restart = -1;
+  int work_restart = -1, work_nb = 0;
   int64_t work_N = -1;
   cx<double> *V = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *hcol = nullptr, *part = nullptr;
   cx<double> *z = nullptr, *t = nullptr;
@@ -446,6 +447,8 @@ static int do_build(scabs_ctx *c) {
   c->work.release();
   c->work_restart = -1;
   c->work_N = -1;
+  c->work_nb = 0;
+  c->p32.bcap = c->p64.bcap = 1;
   if (c->verts.empty() || c->tris.empty()) return fail(c, SCABS_E_STATE, "mesh not set");
   if (!(c->omega > 0)) return fail(c, SCABS_E_STATE, "media not set");
   std::string e = build_geometry(c->verts, c->tris, c->body, c->geo);
@@ -633,28 +636,53 @@ static int do_build(scabs_ctx *c) {
 // ---------------------------------------------------------------------------
 // products
 // ---------------------------------------------------------------------------
-template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const double *x, double *y) {
+// Grow the per-vector buffers of one precision to hold nb vectors.
+template <typename T> static void ensure_batch(scabs_ctx *c, PrecState<T> &P, int nb) {
+  if (nb <= P.bcap) return;
+  const Geometry &g = c->geo;
+  c->mem.free_one(P.src);
+  c->mem.free_one(P.tri_out);
+  P.src = c->mem.alloc<cx<T>>((size_t)g.ne * 3 * nb);
+  P.tri_out = c->mem.alloc<cx<T>>((size_t)g.nt * 9 * nb);
+  for (size_t k = 0; k < P.grids.size(); k++) {
+    DevGrid<T> &G = P.grids[k];
+    c->mem.free_one(G.phys);
+    c->mem.free_one(G.spec);
+    c->mem.free_one(P.gather[k].src);
+    G.phys = c->mem.alloc<cx<T>>(8 * (size_t)G.n[0] * G.n[1] * G.n[2] * nb);
+    G.spec = c->mem.alloc<cx<T>>(8 * (size_t)G.n[0] * G.N[1] * G.N[2] * nb);
+    P.gather[k].src = c->mem.alloc<cx<T>>(8 * (size_t)P.gather[k].np * nb);
+  }
+  c->mem.free_one(P.grids_dev);
+  P.grids_dev = c->mem.upload(P.grids);
+  P.op.src = P.src;
+  P.op.tri_out = P.tri_out;
+  P.bcap = nb;
+}
+
+// y = A x for nb vectors (nb <= near_rows_max_batch(), within the capacity)
+template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const double *x, double *y, int nb) {
   hipStream_t s = c->stream;
   const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
   {
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
-    launch_unpack(P.op, x, s);
+    launch_unpack(P.op, x, s, nb);
   }
   {
     StageTimer t(c, SCABS_STAGE_PROJECT + off);
-    launch_project(P.op, P.grids, P.gather, s);
+    launch_project(P.op, P.grids, P.gather, s, nb);
   }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
-    for (const DevGrid<T> &g : P.grids) launch_conv(g, s);
+    for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb);
   }
   {
     StageTimer t(c, SCABS_STAGE_INTERP + off);
-    launch_interp_test(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, s);
+    launch_interp_test(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, s, nb);
   }
   {
     StageTimer t(c, SCABS_STAGE_NEAR + off);
-    launch_near_rows(P.op, y, s);
+    launch_near_rows(P.op, y, s, nb);
   }
 }
 
@@ -685,49 +713,68 @@ template <typename T> static void apply_t(scabs_ctx *c, PrecState<T> &P, const d
   }
 }
 
-static void matvec_one(scabs_ctx *c, const double *x, double *y, int prec, bool trans = false) {
+// nb products (vectors stored one after another, 2N doubles each)
+static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec, bool trans = false) {
+  const size_t stride = 2 * (size_t)c->lay.N;
   if (trans) {
-    if (prec == SCABS_FP32)
-      apply_t(c, c->p32, x, y);
-    else
-      apply_t(c, c->p64, x, y);
+    for (int k = 0; k < nb; k++) {
+      if (prec == SCABS_FP32)
+        apply_t(c, c->p32, x + k * stride, y + k * stride);
+      else
+        apply_t(c, c->p64, x + k * stride, y + k * stride);
+    }
     return;
   }
-  if (prec == SCABS_FP32)
-    apply(c, c->p32, x, y);
-  else
-    apply(c, c->p64, x, y);
+  const int B = near_rows_max_batch();
+  for (int k0 = 0; k0 < nb; k0 += B) {
+    const int m = std::min(B, nb - k0);
+    if (prec == SCABS_FP32) {
+      ensure_batch(c, c->p32, m);
+      apply(c, c->p32, x + k0 * stride, y + k0 * stride, m);
+    } else {
+      ensure_batch(c, c->p64, m);
+      apply(c, c->p64, x + k0 * stride, y + k0 * stride, m);
+    }
+  }
+}
+
+static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, int nb, bool trans) {
+  const size_t N = (size_t)c->lay.N;
+  for (int k = 0; k < nb; k++) apply_precond(c, x + k * N, y + k * N, trans);
 }
 
 // ---------------------------------------------------------------------------
-// GMRES (restarted; two-pass classical Gram-Schmidt and Givens rotations in
-// FP64; one host synchronisation per Arnoldi step)
+// GMRES on a batch of right-hand sides (restarted; two-pass classical
+// Gram-Schmidt and Givens rotations in FP64).  The nb systems step together:
+// one batched preconditioner + product per Arnoldi step, per-system
+// orthogonalisation, one host synchronisation per step for all of them.
 // ---------------------------------------------------------------------------
-static void ensure_work(scabs_ctx *c, int restart) {
+static void ensure_work(scabs_ctx *c, int restart, int nb) {
   int64_t N = c->lay.N;
-  if (c->work_restart >= restart && c->work_N == N) return;
+  if (c->work_restart >= restart && c->work_N == N && c->work_nb >= nb) return;
   c->work.release();
-  c->V = c->work.alloc<cx<double>>((size_t)(restart + 1) * N);
-  c->w = c->work.alloc<cx<double>>(N);
-  c->r = c->work.alloc<cx<double>>(N);
-  c->d = c->work.alloc<cx<double>>(N);
-  c->z = c->work.alloc<cx<double>>(N);
-  c->t = c->work.alloc<cx<double>>(N);
-  c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2));
+  c->V = c->work.alloc<cx<double>>((size_t)(restart + 1) * N * nb);
+  c->w = c->work.alloc<cx<double>>(N * nb);
+  c->r = c->work.alloc<cx<double>>(N * nb);
+  c->d = c->work.alloc<cx<double>>(N * nb);
+  c->z = c->work.alloc<cx<double>>(N * nb);
+  c->t = c->work.alloc<cx<double>>(N * nb);
+  c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2) * nb);
   c->part = c->work.alloc<cx<double>>((size_t)256 * (restart + 2));
-  c->nrm = c->work.alloc<double>(4);
+  c->nrm = c->work.alloc<double>(nb + 4);
   c->nrm_part = c->work.alloc<double>(1024);
   c->flag = c->work.alloc<int>(1);
   c->work_restart = restart;
   c->work_N = N;
+  c->work_nb = nb;
 }
 
-static double dev_norm(scabs_ctx *c, const cx<double> *v) {
-  double n;
-  kr_norm(v, c->lay.N, c->nrm_part, c->nrm + 1, c->stream);
-  HIPCHK(hipMemcpyAsync(&n, c->nrm + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+// norms of nb vectors (one synchronisation)
+static void dev_norms(scabs_ctx *c, const cx<double> *v, int nb, double *out) {
+  const int64_t N = c->lay.N;
+  for (int b = 0; b < nb; b++) kr_norm(v + b * N, N, c->nrm_part, c->nrm + b, c->stream);
+  HIPCHK(hipMemcpyAsync(out, c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  return n;
 }
 
 struct GmresResult {
@@ -736,165 +783,212 @@ struct GmresResult {
   bool converged = false;
 };
 
-// Solve A_prec sol = rhs from sol = 0 to ||rhs - A sol|| <= tol ||rhs||.
-static GmresResult gmres(scabs_ctx *c, const cx<double> *rhs, cx<double> *sol, int prec, double tol, int max_iter,
-                         int restart, int &nmv, bool trans) {
+// Solve A sol_b = rhs_b (b < nb, vectors one after another) from sol = 0 to
+// ||rhs_b - A sol_b|| <= tol[b] ||rhs_b||.
+static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> *sol, int prec, const double *tol,
+                        int max_iter, int restart, int &nmv, bool trans, std::vector<GmresResult> &res) {
   typedef std::complex<double> zd;
   hipStream_t s = c->stream;
   const int64_t N = c->lay.N;
-  GmresResult res;
-  HIPCHK(hipMemsetAsync(sol, 0, sizeof(cx<double>) * N, s));
-  HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
-  const double bn = dev_norm(c, rhs);
-  if (bn == 0) {
-    res.rel = 0;
-    res.converged = true;
-    return res;
-  }
   const int m = restart;
-  std::vector<zd> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
-  std::vector<cx<double>> hb(2 * (m + 2));
-  cx<double> *h1 = c->hcol, *h2 = c->hcol + (m + 2);
-  double beta = bn;
+  const int64_t ldv = N * nb;   // V[j][b] at V + (j nb + b) N
+  res.assign(nb, GmresResult());
+  HIPCHK(hipMemsetAsync(sol, 0, sizeof(cx<double>) * N * nb, s));
+  HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N * nb, hipMemcpyDeviceToDevice, s));
+  std::vector<double> bn(nb), beta(nb), hn(nb);
+  dev_norms(c, rhs, nb, bn.data());
+  beta = bn;
+  std::vector<std::vector<zd>> H(nb, std::vector<zd>((size_t)(m + 1) * m)), g(nb, std::vector<zd>(m + 1)),
+      cs(nb, std::vector<zd>(m)), sn(nb, std::vector<zd>(m));
+  std::vector<int> jb(nb);
+  std::vector<cx<double>> hb(2 * (size_t)(m + 2) * nb);
   while (true) {
-    res.rel = beta / bn;
-    if (res.rel <= tol) {
-      res.converged = true;
-      break;
-    }
-    if (res.iters >= max_iter) break;
-    kr_norm(c->r, N, c->nrm_part, c->nrm, s);
-    kr_scale(c->V, c->r, c->nrm, N, s);
-    std::fill(g.begin(), g.end(), zd(0));
-    g[0] = beta;
-    int j = 0;
-    while (j < m && res.iters < max_iter) {
-      cx<double> *vj = c->V + (size_t)j * N;
-      if (c->has_pc) {
-        apply_precond(c, vj, c->z, trans);
-        matvec_one(c, (const double *)c->z, (double *)c->w, prec, trans);
-      } else {
-        matvec_one(c, (const double *)vj, (double *)c->w, prec, trans);
+    std::vector<int> act;
+    for (int b = 0; b < nb; b++) {
+      res[b].rel = bn[b] > 0 ? beta[b] / bn[b] : 0.0;
+      if (res[b].rel <= tol[b]) {
+        res[b].converged = true;
+        continue;
       }
-      nmv++;
+      if (res[b].iters < max_iter) act.push_back(b);
+    }
+    if (act.empty()) break;
+    for (int b : act) {
+      kr_norm(c->r + b * N, N, c->nrm_part, c->nrm + b, s);
+      kr_scale(c->V + b * N, c->r + b * N, c->nrm + b, N, s);
+      std::fill(g[b].begin(), g[b].end(), zd(0));
+      g[b][0] = beta[b];
+      jb[b] = 0;
+    }
+    std::vector<int> run = act;
+    int j = 0;
+    while (j < m && !run.empty()) {
+      cx<double> *vj = c->V + (size_t)j * ldv;
+      if (c->has_pc) {
+        apply_precond_n(c, vj, c->z, nb, trans);
+        matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
+      } else {
+        matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
+      }
+      nmv += (int)run.size();
       {
         StageTimer tm(c, SCABS_STAGE_ORTHO);
-        kr_dots(c->V, N, j + 1, c->w, N, c->part, h1, 0, s);
-        kr_update(c->w, c->V, N, j + 1, h1, N, -1.0, s);
-        kr_dots(c->V, N, j + 1, c->w, N, c->part, h2, 0, s);
-        kr_update(c->w, c->V, N, j + 1, h2, N, -1.0, s);
-        kr_norm(c->w, N, c->nrm_part, c->nrm, s);
-        kr_scale(c->V + (size_t)(j + 1) * N, c->w, c->nrm, N, s);
+        for (int b : run) {
+          cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
+          cx<double> *wb = c->w + b * N;
+          const cx<double> *Vb = c->V + b * N;
+          kr_dots(Vb, ldv, j + 1, wb, N, c->part, h1, 0, s);
+          kr_update(wb, Vb, ldv, j + 1, h1, N, -1.0, s);
+          kr_dots(Vb, ldv, j + 1, wb, N, c->part, h2, 0, s);
+          kr_update(wb, Vb, ldv, j + 1, h2, N, -1.0, s);
+          kr_norm(wb, N, c->nrm_part, c->nrm + b, s);
+          kr_scale(c->V + (size_t)(j + 1) * ldv + b * N, wb, c->nrm + b, N, s);
+        }
       }
-      double hn;
-      HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * 2 * (m + 2), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(&hn, c->nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      zd *col = &H[(size_t)j * (m + 1)];
-      for (int i = 0; i <= j; i++) col[i] = zd(hb[i].x + hb[m + 2 + i].x, hb[i].y + hb[m + 2 + i].y);
-      col[j + 1] = hn;
-      for (int i = 0; i < j; i++) {
-        zd a = col[i], b = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * b;
-        col[i + 1] = -std::conj(sn[i]) * a + cs[i] * b;
+      std::vector<int> next;
+      for (int b : run) {
+        const cx<double> *h1 = hb.data() + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
+        zd *col = &H[b][(size_t)j * (m + 1)];
+        for (int i = 0; i <= j; i++) col[i] = zd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+        col[j + 1] = hn[b];
+        for (int i = 0; i < j; i++) {
+          zd a = col[i], bb = col[i + 1];
+          col[i] = cs[b][i] * a + sn[b][i] * bb;
+          col[i + 1] = -std::conj(sn[b][i]) * a + cs[b][i] * bb;
+        }
+        double an = std::abs(col[j]), bnrm = std::abs(col[j + 1]);
+        if (bnrm == 0) {
+          cs[b][j] = 1;
+          sn[b][j] = 0;
+        } else if (an == 0) {
+          cs[b][j] = 0;
+          sn[b][j] = std::conj(col[j + 1]) / bnrm;
+        } else {
+          double t = std::hypot(an, bnrm);
+          cs[b][j] = an / t;
+          sn[b][j] = (col[j] / an) * std::conj(col[j + 1]) / t;
+        }
+        col[j] = cs[b][j] * col[j] + sn[b][j] * col[j + 1];
+        col[j + 1] = 0;
+        g[b][j + 1] = -std::conj(sn[b][j]) * g[b][j];
+        g[b][j] = cs[b][j] * g[b][j];
+        jb[b] = j + 1;
+        res[b].iters++;
+        const bool done = std::abs(g[b][j + 1]) <= tol[b] * bn[b] || hn[b] == 0 || res[b].iters >= max_iter;
+        if (!done) next.push_back(b);
       }
-      double an = std::abs(col[j]), bnrm = std::abs(col[j + 1]);
-      if (bnrm == 0) {
-        cs[j] = 1;
-        sn[j] = 0;
-      } else if (an == 0) {
-        cs[j] = 0;
-        sn[j] = std::conj(col[j + 1]) / bnrm;
-      } else {
-        double t = std::hypot(an, bnrm);
-        cs[j] = an / t;
-        sn[j] = (col[j] / an) * std::conj(col[j + 1]) / t;
-      }
-      col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
-      col[j + 1] = 0;
-      g[j + 1] = -std::conj(sn[j]) * g[j];
-      g[j] = cs[j] * g[j];
+      run.swap(next);
       j++;
-      res.iters++;
-      if (std::abs(g[j]) <= tol * bn || hn == 0) break;
     }
-    // y = H^-1 g (upper triangular), sol += V y
-    for (int i = j - 1; i >= 0; i--) {
-      zd acc = g[i];
-      for (int k = i + 1; k < j; k++) acc -= H[(size_t)k * (m + 1) + i] * y[k];
-      y[i] = acc / H[(size_t)i * (m + 1) + i];
+    // y = H^-1 g (upper triangular); sol += M (V y)
+    HIPCHK(hipMemsetAsync(c->t, 0, sizeof(cx<double>) * N * nb, s));
+    for (int b : act) {
+      const int jj = jb[b];
+      std::vector<zd> y(jj);
+      for (int i = jj - 1; i >= 0; i--) {
+        zd acc = g[b][i];
+        for (int k = i + 1; k < jj; k++) acc -= H[b][(size_t)k * (m + 1) + i] * y[k];
+        y[i] = acc / H[b][(size_t)i * (m + 1) + i];
+      }
+      std::vector<cx<double>> yb(jj);
+      for (int i = 0; i < jj; i++) yb[i] = {y[i].real(), y[i].imag()};
+      cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b;
+      HIPCHK(hipMemcpyAsync(h1, yb.data(), sizeof(cx<double>) * jj, hipMemcpyHostToDevice, s));
+      kr_update(c->t + b * N, c->V + b * N, ldv, jj, h1, N, +1.0, s);
+      // the host vector yb must outlive the copy
+      HIPCHK(hipStreamSynchronize(s));
     }
-    std::vector<cx<double>> yb(j);
-    for (int i = 0; i < j; i++) yb[i] = {y[i].real(), y[i].imag()};
-    HIPCHK(hipMemcpyAsync(h1, yb.data(), sizeof(cx<double>) * j, hipMemcpyHostToDevice, s));
     if (c->has_pc) {
-      // sol += M (V y)
-      HIPCHK(hipMemsetAsync(c->t, 0, sizeof(cx<double>) * N, s));
-      kr_update(c->t, c->V, N, j, h1, N, +1.0, s);
-      apply_precond(c, c->t, c->z, trans);
-      kr_axpy(sol, c->z, N, s);
+      apply_precond_n(c, c->t, c->z, nb, trans);
+      for (int b : act) kr_axpy(sol + b * N, c->z + b * N, N, s);
     } else {
-      kr_update(sol, c->V, N, j, h1, N, +1.0, s);
+      for (int b : act) kr_axpy(sol + b * N, c->t + b * N, N, s);
     }
-    // true residual
-    matvec_one(c, (const double *)sol, (double *)c->w, prec, trans);
-    nmv++;
-    HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
-    kr_residual((const cx<double> *)c->r, c->w, N, s);   // w = rhs - A sol
-    HIPCHK(hipMemcpyAsync(c->r, c->w, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
-    beta = dev_norm(c, c->r);
+    // true residuals
+    matvec_n(c, (const double *)sol, (double *)c->w, nb, prec, trans);
+    nmv += (int)act.size();
+    for (int b : act) {
+      HIPCHK(hipMemcpyAsync(c->r + b * N, rhs + b * N, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+      kr_residual((const cx<double> *)(c->r + b * N), c->w + b * N, N, s);   // w = rhs - A sol
+      HIPCHK(hipMemcpyAsync(c->r + b * N, c->w + b * N, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+    }
+    std::vector<double> nr(nb);
+    dev_norms(c, c->r, nb, nr.data());
+    for (int b : act) beta[b] = nr[b];
   }
-  return res;
 }
 
-// FP64 iterative refinement around GMRES on the operator of `inner` precision.
-static int solve_one(scabs_ctx *c, const cx<double> *b, cx<double> *x, double tol, int max_iter, int restart, int mode,
-                     scabs_solve_info *info, bool trans) {
+// FP64 iterative refinement around batched GMRES on the operator of the inner
+// precision; nb right-hand sides (vectors one after another).
+static int solve_batch(scabs_ctx *c, int nb, const cx<double> *b, cx<double> *x, double tol, int max_iter,
+                       int restart, int mode, scabs_solve_info *info, bool trans) {
   hipStream_t s = c->stream;
   const int64_t N = c->lay.N;
-  ensure_work(c, restart);
-  scabs_solve_info loc{};
+  ensure_work(c, restart, nb);
+  std::vector<scabs_solve_info> loc(nb);
   const int inner_prec = mode == SCABS_MIXED ? SCABS_FP32 : SCABS_FP64;
   const double floor_tol = mode == SCABS_MIXED ? 1e-5 : 1e-14;
-  const double bn = dev_norm(c, b);
-  cx<double> *r64 = c->d;   // refinement residual, reused as correction below
-  std::vector<cx<double>> dummy;
-  cx<double> *corr = nullptr;
+  std::vector<double> bn(nb), rn(nb), rel(nb, 1.0);
+  dev_norms(c, b, nb, bn.data());
   DevMem tmp;
-  corr = tmp.alloc<cx<double>>(N);
-  cx<double> *rr = tmp.alloc<cx<double>>(N);
-  (void)r64;
-  double rel = 1.0;
-  int status = SCABS_E_NOCONV;
+  cx<double> *rr = tmp.alloc<cx<double>>(N * nb);     // residuals
+  cx<double> *rhs = tmp.alloc<cx<double>>(N * nb);    // compacted residuals of the active systems
+  cx<double> *corr = tmp.alloc<cx<double>>(N * nb);
+  std::vector<int> status(nb, SCABS_E_NOCONV), stalled(nb, 0);
   for (int outer = 0; outer < 50; outer++) {
-    matvec_one(c, (const double *)x, (double *)rr, SCABS_FP64, trans);
-    loc.matvecs64++;
-    kr_residual(b, rr, N, s);   // rr = b - A x
-    double rn = dev_norm(c, rr);
-    rel = bn > 0 ? rn / bn : 0.0;
-    if (rel <= tol) {
-      status = SCABS_OK;
-      break;
+    matvec_n(c, (const double *)x, (double *)rr, nb, SCABS_FP64, trans);
+    for (int k = 0; k < nb; k++) kr_residual(b + k * N, rr + k * N, N, s);   // rr = b - A x
+    dev_norms(c, rr, nb, rn.data());
+    std::vector<int> act;
+    for (int k = 0; k < nb; k++) {
+      loc[k].matvecs64 += status[k] == SCABS_E_NOCONV && !stalled[k] ? 1 : 0;
+      if (status[k] == SCABS_OK || stalled[k]) continue;
+      rel[k] = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+      if (rel[k] <= tol) {
+        status[k] = SCABS_OK;
+        continue;
+      }
+      if (loc[k].inner_iters >= max_iter) continue;
+      act.push_back(k);
     }
-    if (loc.inner_iters >= max_iter) break;
-    double tin = std::max(0.5 * tol / rel, floor_tol);
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    std::vector<double> tin(na);
+    int min_left = max_iter;
+    for (int a = 0; a < na; a++) {
+      const int k = act[a];
+      tin[a] = std::max(0.5 * tol / rel[k], floor_tol);
+      min_left = std::min(min_left, max_iter - loc[k].inner_iters);
+      HIPCHK(hipMemcpyAsync(rhs + a * N, rr + k * N, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+    }
     int nmv = 0;
-    GmresResult g = gmres(c, rr, corr, inner_prec, tin, max_iter - loc.inner_iters, restart, nmv, trans);
-    if (inner_prec == SCABS_FP32)
-      loc.matvecs32 += nmv;
-    else
-      loc.matvecs64 += nmv;
-    loc.inner_iters += g.iters;
-    loc.outer_iters++;
-    kr_axpy(x, corr, N, s);
-    if (g.iters == 0 && !g.converged) break;
+    std::vector<GmresResult> g;
+    gmres_batch(c, na, rhs, corr, inner_prec, tin.data(), min_left, restart, nmv, trans, g);
+    for (int a = 0; a < na; a++) {
+      const int k = act[a];
+      if (inner_prec == SCABS_FP32)
+        loc[k].matvecs32 += nmv / na;
+      else
+        loc[k].matvecs64 += nmv / na;
+      loc[k].inner_iters += g[a].iters;
+      loc[k].outer_iters++;
+      kr_axpy(x + k * N, corr + a * N, N, s);
+      if (g[a].iters == 0 && !g[a].converged) stalled[k] = 1;
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
   tmp.release();
-  loc.rel_residual = rel;
-  loc.status = status;
-  if (info) *info = loc;
-  return status;
+  int worst = SCABS_OK;
+  for (int k = 0; k < nb; k++) {
+    loc[k].rel_residual = rel[k];
+    loc[k].status = status[k];
+    if (info) info[k] = loc[k];
+    if (status[k] != SCABS_OK) worst = status[k];
+  }
+  return worst;
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,8 +1141,7 @@ static int do_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int pre
   if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
   if (prec != SCABS_FP32 && prec != SCABS_FP64) return fail(c, SCABS_E_ARG, "prec must be SCABS_FP32 or SCABS_FP64");
   try {
-    const size_t stride = 2 * (size_t)c->lay.N;
-    for (int k = 0; k < nrhs; k++) matvec_one(c, x + k * stride, y + k * stride, prec, trans);
+    matvec_n(c, x, y, nrhs, prec, trans);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
   } catch (const HipError &e) {
@@ -1072,7 +1165,8 @@ static int do_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double t
   if (mode != SCABS_FP64 && mode != SCABS_MIXED) return fail(c, SCABS_E_ARG, "mode must be SCABS_FP64 or SCABS_MIXED");
   try {
     const size_t stride = 2 * (size_t)c->lay.N;
-    ensure_work(c, restart);
+    const int B = std::min(nrhs, near_rows_max_batch());
+    ensure_work(c, restart, B);
     HIPCHK(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
     kr_finite(b, (int64_t)stride * nrhs, c->flag, c->stream);
     kr_finite(x, (int64_t)stride * nrhs, c->flag, c->stream);
@@ -1081,11 +1175,10 @@ static int do_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double t
     HIPCHK(hipStreamSynchronize(c->stream));
     if (bad) return fail(c, SCABS_E_NAN, "non-finite value in b or x");
     int worst = SCABS_OK;
-    for (int k = 0; k < nrhs; k++) {
-      scabs_solve_info loc{};
-      int st = solve_one(c, (const cx<double> *)(b + k * stride), (cx<double> *)(x + k * stride), tol, max_iter, restart,
-                         mode, &loc, trans);
-      if (info) info[k] = loc;
+    for (int k0 = 0; k0 < nrhs; k0 += B) {
+      const int m = std::min(B, nrhs - k0);
+      int st = solve_batch(c, m, (const cx<double> *)(b + k0 * stride), (cx<double> *)(x + k0 * stride), tol,
+                           max_iter, restart, mode, info ? info + k0 : nullptr, trans);
       if (st != SCABS_OK) worst = st;
     }
     if (worst != SCABS_OK) c->err = "GMRES did not reach the tolerance within max_iter";

@@ -50,20 +50,25 @@ template <typename T> struct DevOperator {
 };
 
 // ---- FFT convolution -------------------------------------------------------
-template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s);
+// nb vectors: phys/spec hold nb consecutive 8-field blocks
+template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb = 1);
 // FFT of the circulant-embedded grid kernel; writes the scaled octant in both precisions
 hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int twL, cx<double> *ghat64,
                       cx<float> *ghat32, hipStream_t s);
 
 // ---- matvec steps ------------------------------------------------------------
-template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s);
+// Batched steps: nb vectors at once; every per-vector buffer (x, y, op.src,
+// op.tri_out, gather sources, grid fields) holds nb consecutive copies.
+template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s, int nb = 1);
 template <typename T>
 void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids,
-                    const std::vector<GatherGrid<T>> &gg, hipStream_t s);
+                    const std::vector<GatherGrid<T>> &gg, hipStream_t s, int nb = 1);
 template <typename T>
 void launch_interp_test(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, T inv_h,
-                        hipStream_t s);
-template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s);
+                        hipStream_t s, int nb = 1);
+// nb <= near_rows_max_batch()
+template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s, int nb = 1);
+int near_rows_max_batch();
 
 // ---- setup (FP64) ------------------------------------------------------------
 struct NearSetupArgs {

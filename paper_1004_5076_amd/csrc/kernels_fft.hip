@@ -118,23 +118,23 @@ template <typename T> static int planes_per_group(int N1, int N2) {
   return std::max(1, P);
 }
 
-template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s) {
+template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
   const int P = planes_per_group<T>(N1, N2);
   const size_t plane_lds = sizeof(cx<T>) * (size_t)lpad_size<T>(P * N1 * N2);
   const int npg = (n0 + P - 1) / P;
-  hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3(npg, 8), dim3(FftCfg<T>::threads), plane_lds, s, g.phys, g.spec, n0, n1, n2, N1,
+  hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.phys, g.spec, n0, n1, n2, N1,
                      N2, P, g.tw, g.twL);
   const int C = xline_lines<T>(N0);
-  const int nb = (N1 * N2 + C - 1) / C;
-  hipLaunchKernelGGL(xline_kernel<T>, dim3(nb, 8), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s, g.spec, n0, N0, N1, N2,
+  const int nlb = (N1 * N2 + C - 1) / C;
+  hipLaunchKernelGGL(xline_kernel<T>, dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s, g.spec, n0, N0, N1, N2,
                      C, g.ghat, g.tw, g.twL, 0);
-  hipLaunchKernelGGL(plane_inv_kernel<T>, dim3(npg, 8), dim3(FftCfg<T>::threads), plane_lds, s, g.spec, g.phys, n0, n1, n2, N1,
+  hipLaunchKernelGGL(plane_inv_kernel<T>, dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.spec, g.phys, n0, n1, n2, N1,
                      N2, P, g.tw, g.twL);
 }
-template void launch_conv<float>(const DevGrid<float> &, hipStream_t);
-template void launch_conv<double>(const DevGrid<double> &, hipStream_t);
+template void launch_conv<float>(const DevGrid<float> &, hipStream_t, int);
+template void launch_conv<double>(const DevGrid<double> &, hipStream_t, int);
 
 // ---- kernel spectrum -----------------------------------------------------------
 // circulant embedding of H(d) = G(h |d|) (H(0) = 0) on N0 x N1 x N2, offsets

@@ -15,11 +15,14 @@ namespace scabs {
 // ---------------------------------------------------------------------------
 // unknown vector -> per-edge currents (J_e, J_i, M)
 // ---------------------------------------------------------------------------
+// batch index blockIdx.y: x + b * 2N, src + b * 3 ne
 template <typename T>
-__global__ void unpack_kernel(const EdgeRec *__restrict__ edges, int ne, const double *__restrict__ x,
+__global__ void unpack_kernel(const EdgeRec *__restrict__ edges, int ne, int N, const double *__restrict__ x,
                               cx<T> *__restrict__ src) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
+  x += (size_t)blockIdx.y * 2 * N;
+  src += (size_t)blockIdx.y * 3 * ne;
   EdgeRec r = edges[e];
   cx<T> a = {(T)x[2 * r.col[0]], (T)x[2 * r.col[0] + 1]};
   cx<T> b = {(T)x[2 * r.col[1]], (T)x[2 * r.col[1] + 1]};
@@ -35,11 +38,12 @@ __global__ void unpack_kernel(const EdgeRec *__restrict__ edges, int ne, const d
   }
 }
 
-template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s) {
-  hipLaunchKernelGGL(unpack_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op.edges, op.ne, x, op.src);
+template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s, int nb) {
+  hipLaunchKernelGGL(unpack_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op.edges, op.ne, op.N, x,
+                     op.src);
 }
-template void launch_unpack<float>(const DevOperator<float> &, const double *, hipStream_t);
-template void launch_unpack<double>(const DevOperator<double> &, const double *, hipStream_t);
+template void launch_unpack<float>(const DevOperator<float> &, const double *, hipStream_t, int);
+template void launch_unpack<double>(const DevOperator<double> &, const double *, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // projection: every quadrature point spreads w_q (J, div J, M, div M) of its
@@ -51,9 +55,10 @@ template void launch_unpack<double>(const DevOperator<double> &, const double *,
 template <typename T>
 __global__ void __launch_bounds__(256)
 point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restrict__ tris,
-                     const cx<T> *__restrict__ esrc, GatherGrid<T> g, int interior) {
+                     const cx<T> *__restrict__ esrc, GatherGrid<T> g, int interior, int ne) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.np) return;
+  esrc += (size_t)blockIdx.y * 3 * ne;   // batch index blockIdx.y
   const PointRec<T> P = pts[g.perm[i]];
   const TriRec<T> tr = tris[P.tri];
   cx<T> s[8];
@@ -72,7 +77,7 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
     axpy(s[3], tr.div[j], J);
     axpy(s[7], tr.div[j], M);
   }
-  cx<T> *o = g.src + (size_t)8 * i;
+  cx<T> *o = g.src + (size_t)8 * g.np * blockIdx.y + (size_t)8 * i;
 #pragma unroll
   for (int f = 0; f < 8; f++) o[f] = s[f] * P.w;
 }
@@ -88,6 +93,9 @@ __global__ void __launch_bounds__(GA_THREADS) gather_kernel(DevGrid<T> dg, Gathe
   __shared__ cx<T> s_src[GA_CHUNK * 8];
   __shared__ T s_u[GA_CHUNK * 3];
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
+  // batch index blockIdx.y
+  const cx<T> *gsrc = g.src + (size_t)8 * g.np * blockIdx.y;
+  cx<T> *phys = dg.phys + (size_t)8 * g.ncell * blockIdx.y;
   const int plane = n1 * n2;
   const int x = blockIdx.x;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
@@ -101,7 +109,7 @@ __global__ void __launch_bounds__(GA_THREADS) gather_kernel(DevGrid<T> dg, Gathe
   for (int64_t c0 = P0; c0 < P1; c0 += GA_CHUNK) {
     const int64_t c1 = min(c0 + (int64_t)GA_CHUNK, P1);
     const int cn = (int)(c1 - c0);
-    for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) s_src[i] = g.src[(size_t)8 * c0 + i];
+    for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) s_src[i] = gsrc[(size_t)8 * c0 + i];
     for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) s_u[i] = g.u[(size_t)3 * c0 + i];
     __syncthreads();
 #pragma unroll
@@ -144,27 +152,27 @@ __global__ void __launch_bounds__(GA_THREADS) gather_kernel(DevGrid<T> dg, Gathe
     const int nd = threadIdx.x + m * GA_THREADS;
     if (nd >= plane) continue;
 #pragma unroll
-    for (int f = 0; f < 8; f++) dg.phys[f * G + (size_t)x * plane + nd] = acc[m][f];
+    for (int f = 0; f < 8; f++) phys[f * G + (size_t)x * plane + nd] = acc[m][f];
   }
 }
 
 template <typename T>
 void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids,
-                    const std::vector<GatherGrid<T>> &gg, hipStream_t s) {
+                    const std::vector<GatherGrid<T>> &gg, hipStream_t s, int nb) {
   for (size_t k = 0; k < grids.size(); k++) {
     const GatherGrid<T> &g = gg[k];
-    hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256), dim3(256), 0, s, op.pts, op.tris, op.src, g,
-                       grids[k].which >= 0 ? 1 : 0);
+    hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256, nb), dim3(256), 0, s, op.pts, op.tris, op.src,
+                       g, grids[k].which >= 0 ? 1 : 0, op.ne);
   }
   for (size_t k = 0; k < grids.size(); k++) {
     const GatherGrid<T> &g = gg[k];
-    hipLaunchKernelGGL(gather_kernel<T>, dim3(grids[k].n[0]), dim3(GA_THREADS), 0, s, grids[k], g);
+    hipLaunchKernelGGL(gather_kernel<T>, dim3(grids[k].n[0], nb), dim3(GA_THREADS), 0, s, grids[k], g);
   }
 }
 template void launch_project<float>(const DevOperator<float> &, const std::vector<DevGrid<float>> &,
-                                    const std::vector<GatherGrid<float>> &, hipStream_t);
+                                    const std::vector<GatherGrid<float>> &, hipStream_t, int);
 template void launch_project<double>(const DevOperator<double> &, const std::vector<DevGrid<double>> &,
-                                     const std::vector<GatherGrid<double>> &, hipStream_t);
+                                     const std::vector<GatherGrid<double>> &, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // interpolation at test points + row contributions + local terms, reduced to
@@ -181,7 +189,7 @@ template <typename T> struct Pot {
 
 template <typename T>
 __device__ inline void gather(const DevGrid<T> &g, int ax, int ay, int az, const T *Lx, const T *Ly, const T *Lz,
-                              const T *dLx, const T *dLy, const T *dLz, T inv_h, Pot<T> &p) {
+                              const T *dLx, const T *dLy, const T *dLz, T inv_h, Pot<T> &p, int b) {
 #pragma unroll
   for (int f = 0; f < 8; f++) {
     p.val[f] = czero<T>();
@@ -189,6 +197,7 @@ __device__ inline void gather(const DevGrid<T> &g, int ax, int ay, int az, const
   }
   const int n1 = g.n[1], n2 = g.n[2];
   const size_t G = (size_t)g.n[0] * n1 * n2;
+  const cx<T> *phys = g.phys + (size_t)8 * G * b;
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
       const size_t row = ((size_t)(ax + i - 1) * n1 + (ay + j - 1)) * n2 + (az - 1);
@@ -198,7 +207,7 @@ __device__ inline void gather(const DevGrid<T> &g, int ax, int ay, int az, const
         const T w = wxy * Lz[k], gx = dxy * Lz[k] * inv_h, gy = xdy * Lz[k] * inv_h, gz = wxy * dLz[k] * inv_h;
 #pragma unroll
         for (int f = 0; f < 8; f++) {
-          const cx<T> v = g.phys[f * G + row + k];
+          const cx<T> v = phys[f * G + row + k];
           axpy(p.val[f], w, v);
           axpy(p.grad[f][0], gx, v);
           axpy(p.grad[f][1], gy, v);
@@ -221,6 +230,8 @@ interp_test_kernel(DevOperator<T> op, DevGrid<T> ext, const DevGrid<T> *__restri
   __shared__ cx<T> part[IT_THREADS][9];
   const int lt = threadIdx.x / NQ, q = threadIdx.x - lt * NQ;
   const int tri = blockIdx.x * IT_TRIS + lt;
+  const int bb = blockIdx.y;   // batch index
+  const cx<T> *esrc = op.src + (size_t)3 * op.ne * bb;
   cx<T> out[9];
 #pragma unroll
   for (int r = 0; r < 9; r++) out[r] = czero<T>();
@@ -233,7 +244,7 @@ interp_test_kernel(DevOperator<T> op, DevGrid<T> ext, const DevGrid<T> *__restri
     for (int a = 0; a < 3; a++) Jsum[a] = Mq[a] = czero<T>();
     for (int j = 0; j < 3; j++) {
       const int e = tr.edge[j];
-      const cx<T> Je = op.src[3 * e], Ji = op.src[3 * e + 1], M = op.src[3 * e + 2];
+      const cx<T> Je = esrc[3 * e], Ji = esrc[3 * e + 1], M = esrc[3 * e + 2];
       for (int a = 0; a < 3; a++) {
         axpy(Jsum[a], P.f[3 * j + a], Je + Ji);
         axpy(Mq[a], P.f[3 * j + a], M);
@@ -257,7 +268,7 @@ interp_test_kernel(DevOperator<T> op, DevGrid<T> ext, const DevGrid<T> *__restri
     Pot<T> pot;
     for (int med = 0; med < 2; med++) {
       const DevGrid<T> &g = med == 0 ? ext : ints[tr.body];
-      gather(g, ax - g.off[0], ay - g.off[1], az - g.off[2], Lx, Ly, Lz, dLx, dLy, dLz, inv_h, pot);
+      gather(g, ax - g.off[0], ay - g.off[1], az - g.off[2], Lx, Ly, Lz, dLx, dLy, dLz, inv_h, pot, bb);
       const T k = g.k, Z = g.Z, ik2 = T(1) / (k * k);
       const T sgn = med == 0 ? T(1) : T(-1);
       cx<T> aJ[3] = {pot.val[0], pot.val[1], pot.val[2]};
@@ -311,21 +322,21 @@ interp_test_kernel(DevOperator<T> op, DevGrid<T> ext, const DevGrid<T> *__restri
     if (t2 < op.nt) {
       cx<T> s = czero<T>();
       for (int qq = 0; qq < NQ; qq++) s += part[l * NQ + qq][r];
-      op.tri_out[(size_t)t2 * 9 + r] = s;
+      op.tri_out[(size_t)9 * op.nt * bb + (size_t)t2 * 9 + r] = s;
     }
   }
 }
 
 template <typename T>
 void launch_interp_test(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, T inv_h,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(interp_test_kernel<T>, dim3((op.nt + IT_TRIS - 1) / IT_TRIS), dim3(IT_THREADS), 0, s, op, ext,
+                        hipStream_t s, int nb) {
+  hipLaunchKernelGGL(interp_test_kernel<T>, dim3((op.nt + IT_TRIS - 1) / IT_TRIS, nb), dim3(IT_THREADS), 0, s, op, ext,
                      ints_dev, inv_h);
 }
 template void launch_interp_test<float>(const DevOperator<float> &, const DevGrid<float> &, const DevGrid<float> *,
-                                          float, hipStream_t);
+                                        float, hipStream_t, int);
 template void launch_interp_test<double>(const DevOperator<double> &, const DevGrid<double> &,
-                                           const DevGrid<double> *, double, hipStream_t);
+                                         const DevGrid<double> *, double, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // near correction (exact - grid) rows, plus the two triangle halves of every
@@ -337,56 +348,83 @@ template <typename T> __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Up to NR_MAXB vectors per launch: every CSR entry's values are read once
+// and applied to all of them.
+constexpr int NR_MAXB = 8;
 template <typename T>
-__global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, double *__restrict__ y) {
+__global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, double *__restrict__ y, int nb) {
   const int n = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (n >= op.ne) return;
   const EdgeRec r = op.edges[n];
   const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
-  cx<T> E = czero<T>(), H = czero<T>(), R = czero<T>();
-  const int64_t b = op.rowptr[n], e = op.rowptr[n + 1];
-  for (int64_t k = b + lane; k < e; k += 64) {
+  const size_t bs = (size_t)3 * op.ne;
+  cx<T> E[NR_MAXB], H[NR_MAXB], R[NR_MAXB];
+#pragma unroll
+  for (int b = 0; b < NR_MAXB; b++) E[b] = H[b] = R[b] = czero<T>();
+  const int64_t kb = op.rowptr[n], ke = op.rowptr[n + 1];
+  for (int64_t k = kb + lane; k < ke; k += 64) {
     const int m = op.col[k];
-    const cx<T> Je = op.src[3 * m], Ji = op.src[3 * m + 1], M = op.src[3 * m + 2];
     const cx<T> Le = op.V4[4 * k], Ke = op.V4[4 * k + 1], Li = op.V4[4 * k + 2], Ki = op.V4[4 * k + 3];
-    E += (Li * Ji) * Zi - (Le * Je) * Ze + (Ke + Ki) * M;
-    H += Ki * Ji - Ke * Je - (Le * M) * iZe - (Li * M) * iZi;
+    cx<T> Lr = czero<T>(), Kr = czero<T>(), Ls = czero<T>(), Ks = czero<T>();
     if (r.isR) {
-      const cx<T> Lr = op.S4[4 * k], Kr = op.S4[4 * k + 1], Ls = op.S4[4 * k + 2], Ks = op.S4[4 * k + 3];
-      H += Kr * M - (Lr * Je) * Ze;
-      R += (Ls * Ji) * Zi + Ks * M;
+      Lr = op.S4[4 * k];
+      Kr = op.S4[4 * k + 1];
+      Ls = op.S4[4 * k + 2];
+      Ks = op.S4[4 * k + 3];
+    }
+    const cx<T> KeKi = Ke + Ki;
+#pragma unroll
+    for (int b = 0; b < NR_MAXB; b++) {
+      if (b >= nb) break;
+      const cx<T> *src = op.src + bs * b + 3 * m;
+      const cx<T> Je = src[0], Ji = src[1], M = src[2];
+      E[b] += (Li * Ji) * Zi - (Le * Je) * Ze + KeKi * M;
+      H[b] += Ki * Ji - Ke * Je - (Le * M) * iZe - (Li * M) * iZi;
+      if (r.isR) {
+        H[b] += Kr * M - (Lr * Je) * Ze;
+        R[b] += (Ls * Ji) * Zi + Ks * M;
+      }
     }
   }
-  E.x = wave_sum(E.x);
-  E.y = wave_sum(E.y);
-  H.x = wave_sum(H.x);
-  H.y = wave_sum(H.y);
-  R.x = wave_sum(R.x);
-  R.y = wave_sum(R.y);
-  if (lane == 0) {
-    const cx<T> *p0 = op.tri_out + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
-    const cx<T> *p1 = op.tri_out + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
-    E += p0[0] + p1[0];
-    H += p0[1] + p1[1];
-    R += p0[2] + p1[2];
-    y[2 * r.row[0]] = E.x;
-    y[2 * r.row[0] + 1] = E.y;
-    y[2 * r.row[1]] = H.x;
-    y[2 * r.row[1] + 1] = H.y;
-    if (r.isR) {
-      y[2 * r.row[2]] = R.x;
-      y[2 * r.row[2] + 1] = R.y;
+#pragma unroll
+  for (int b = 0; b < NR_MAXB; b++) {
+    if (b >= nb) break;
+    cx<T> e = E[b], h = H[b], rr = R[b];
+    e.x = wave_sum(e.x);
+    e.y = wave_sum(e.y);
+    h.x = wave_sum(h.x);
+    h.y = wave_sum(h.y);
+    rr.x = wave_sum(rr.x);
+    rr.y = wave_sum(rr.y);
+    if (lane == 0) {
+      const cx<T> *to = op.tri_out + (size_t)9 * op.nt * b;
+      const cx<T> *p0 = to + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
+      const cx<T> *p1 = to + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
+      e += p0[0] + p1[0];
+      h += p0[1] + p1[1];
+      rr += p0[2] + p1[2];
+      double *yb = y + (size_t)2 * op.N * b;
+      yb[2 * r.row[0]] = e.x;
+      yb[2 * r.row[0] + 1] = e.y;
+      yb[2 * r.row[1]] = h.x;
+      yb[2 * r.row[1] + 1] = h.y;
+      if (r.isR) {
+        yb[2 * r.row[2]] = rr.x;
+        yb[2 * r.row[2] + 1] = rr.y;
+      }
     }
   }
 }
 
-template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s) {
+int near_rows_max_batch() { return NR_MAXB; }
+
+template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s, int nb) {
   int blocks = (int)(((int64_t)op.ne * 64 + 255) / 256);
-  hipLaunchKernelGGL(near_rows_kernel<T>, dim3(blocks), dim3(256), 0, s, op, y);
+  hipLaunchKernelGGL(near_rows_kernel<T>, dim3(blocks), dim3(256), 0, s, op, y, nb);
 }
-template void launch_near_rows<float>(const DevOperator<float> &, double *, hipStream_t);
-template void launch_near_rows<double>(const DevOperator<double> &, double *, hipStream_t);
+template void launch_near_rows<float>(const DevOperator<float> &, double *, hipStream_t, int);
+template void launch_near_rows<double>(const DevOperator<double> &, double *, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // right-hand side of an electric dipole in the interior medium of one body
