@@ -122,14 +122,11 @@ __host__ __device__ inline FastDiv make_fastdiv(unsigned d) {
 }
 __device__ inline int fdiv(int n, FastDiv f) { return (int)((__umulhi((unsigned)n, f.m) + (unsigned)n) >> f.s); }
 
-// LDS address swizzle for the FFT buffers.  For 16-byte (FP64 complex)
-// elements one pad element every 16 breaks the power-of-two strides of
-// Stockham writes and of strided lines; 8-byte elements measured faster
-// unpadded, so the swizzle is the identity there.
-template <typename T> __device__ inline int lpad(int a) { return sizeof(T) == 8 ? a + (a >> 4) : a; }
-template <typename T> __host__ __device__ inline int lpad_size(int n) {
-  return sizeof(T) == 8 ? n + (n >> 4) + 1 : n;
-}
+// LDS address swizzle for the FFT buffers: one pad element every 16 breaks
+// the power-of-two strides of Stockham writes (outputs of a radix-R stage
+// land R elements apart) and of strided lines.
+template <typename T> __device__ inline int lpad(int a) { return a + (a >> 4); }
+template <typename T> __host__ __device__ inline int lpad_size(int n) { return n + (n >> 4) + 1; }
 
 template <typename T, int R, int NB>
 __device__ inline void stockham_stage(cx<T> *buf, int L, int nlines, int nin, int lso, int lsi, int es, int Ns,

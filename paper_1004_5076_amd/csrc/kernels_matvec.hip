@@ -7,6 +7,8 @@
 //   eq14   <X_n, J_e + J_i> - sum_q w sigma X_n.E_i^-(q)
 // with per-edge currents J_e, J_i, M_e = M, M_i = -M (eq10-eq12) and one-sided
 // limits E^+/- = PV +/- 1/2 n x M, H^+/- = PV -/+ 1/2 n x J.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -82,64 +84,77 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
   for (int f = 0; f < 8; f++) o[f] = s[f] * P.w;
 }
 
-// One work-group per x plane of a grid: the points anchored in planes
-// x-1..x+1 (contiguous in the cell-sorted list) are staged through LDS in
-// chunks; each thread owns nodes (y, z) of the plane and sums the points of
-// its 27 neighbouring cells that fall in the chunk.
-constexpr int GA_THREADS = 256;
-constexpr int GA_CHUNK = 1024;
-template <typename T>
-__global__ void __launch_bounds__(GA_THREADS) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
-  __shared__ cx<T> s_src[GA_CHUNK * 8];
-  __shared__ T s_u[GA_CHUNK * 3];
+// One work-group per x plane of a grid (and vector of the batch).  Work items
+// are (node (y, z) of the plane, x offset dx of the source cells): item
+// dxi * plane + node, dx = dxi - 1, so neighbouring lanes own neighbouring
+// nodes.  The points anchored in planes x-1..x+1 (contiguous in the
+// cell-sorted list) are staged through LDS in chunks, field-major so that
+// lanes reading different points hit different banks; each item sums the
+// points of its 9 cells (x+dx, y+dy, z+dz) that fall in the chunk, and the
+// three dx partials of a node are added in LDS at the end, field by field.
+// points per staged chunk (measured: 1024 for FP32, 512 for FP64)
+template <typename T> struct GaChunk { static constexpr int value = 1024; };
+template <> struct GaChunk<double> { static constexpr int value = 512; };
+template <typename T, int MAXI>
+__global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
+  constexpr int GA_CHUNK = GaChunk<T>::value;
+  __shared__ cx<T> s_src[8][GA_CHUNK];
+  __shared__ T s_u[3][GA_CHUNK];
+  extern __shared__ unsigned char smem_raw[];
+  cx<T> *s_red = reinterpret_cast<cx<T> *>(smem_raw);   // 3 * plane
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
+  const int plane = n1 * n2;
+  const int x = blockIdx.x;
   // batch index blockIdx.y
   const cx<T> *gsrc = g.src + (size_t)8 * g.np * blockIdx.y;
   cx<T> *phys = dg.phys + (size_t)8 * g.ncell * blockIdx.y;
-  const int plane = n1 * n2;
-  const int x = blockIdx.x;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
   const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
-  constexpr int MAXN = 4;   // nodes per thread (plane <= MAXN * GA_THREADS)
-  cx<T> acc[MAXN][8];
+  const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane);
+  cx<T> acc[MAXI][8];
 #pragma unroll
-  for (int m = 0; m < MAXN; m++)
+  for (int m = 0; m < MAXI; m++)
 #pragma unroll
     for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
   for (int64_t c0 = P0; c0 < P1; c0 += GA_CHUNK) {
     const int64_t c1 = min(c0 + (int64_t)GA_CHUNK, P1);
     const int cn = (int)(c1 - c0);
-    for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) s_src[i] = gsrc[(size_t)8 * c0 + i];
-    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) s_u[i] = g.u[(size_t)3 * c0 + i];
+    for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) {
+      const int lp = i >> 3, f = i & 7;
+      s_src[f][lp] = gsrc[(size_t)8 * c0 + i];
+    }
+    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) {
+      const int lp = fdiv(i, make_fastdiv(3)), a = i - 3 * lp;
+      s_u[a][lp] = g.u[(size_t)3 * c0 + i];
+    }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MAXN; m++) {
-      const int nd = threadIdx.x + m * GA_THREADS;
-      if (nd >= plane) continue;
-      const int y = nd / n2, z = nd - y * n2;
-      for (int dx = -1; dx <= 1; dx++) {
-        const int ax = x + dx;
-        if (ax < 0 || ax >= n0) continue;
-        for (int dy = -1; dy <= 1; dy++) {
-          const int ay = y + dy;
-          if (ay < 0 || ay >= n1) continue;
-          const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
-          for (int dz = -1; dz <= 1; dz++) {
-            const int az = z + dz;
-            if (az < 0 || az >= n2) continue;
-            const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
-            for (int64_t p = p0; p < p1; p++) {
-              // the node sits at offset (-dx, -dy, -dz) from this point's anchor
-              const int lp = (int)(p - c0);
-              const T ux = s_u[3 * lp], uy = s_u[3 * lp + 1], uz = s_u[3 * lp + 2];
-              const T wx = dx == 1 ? T(0.5) * ux * (ux - T(1)) : (dx == 0 ? T(1) - ux * ux : T(0.5) * ux * (ux + T(1)));
-              const T wy = dy == 1 ? T(0.5) * uy * (uy - T(1)) : (dy == 0 ? T(1) - uy * uy : T(0.5) * uy * (uy + T(1)));
-              const T wz = dz == 1 ? T(0.5) * uz * (uz - T(1)) : (dz == 0 ? T(1) - uz * uz : T(0.5) * uz * (uz + T(1)));
-              const T wgt = wx * wy * wz;
-              const cx<T> *sp = s_src + 8 * lp;
+    for (int m = 0; m < MAXI; m++) {
+      const int it = threadIdx.x + m * blockDim.x;
+      if (it >= 3 * plane) continue;
+      const int dxi = fdiv(it, dpl), nd = it - dxi * plane;
+      const int dx = dxi - 1;
+      const int ax = x + dx;
+      if (ax < 0 || ax >= n0) continue;
+      const int y = fdiv(nd, dn2), z = nd - y * n2;
+      for (int dy = -1; dy <= 1; dy++) {
+        const int ay = y + dy;
+        if (ay < 0 || ay >= n1) continue;
+        const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
+        for (int dz = -1; dz <= 1; dz++) {
+          const int az = z + dz;
+          if (az < 0 || az >= n2) continue;
+          const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
+          for (int64_t p = p0; p < p1; p++) {
+            // the node sits at offset (-dx, -dy, -dz) from this point's anchor
+            const int lp = (int)(p - c0);
+            const T ux = s_u[0][lp], uy = s_u[1][lp], uz = s_u[2][lp];
+            const T wx = dx == 1 ? T(0.5) * ux * (ux - T(1)) : (dx == 0 ? T(1) - ux * ux : T(0.5) * ux * (ux + T(1)));
+            const T wy = dy == 1 ? T(0.5) * uy * (uy - T(1)) : (dy == 0 ? T(1) - uy * uy : T(0.5) * uy * (uy + T(1)));
+            const T wz = dz == 1 ? T(0.5) * uz * (uz - T(1)) : (dz == 0 ? T(1) - uz * uz : T(0.5) * uz * (uz + T(1)));
+            const T wgt = wx * wy * wz;
 #pragma unroll
-              for (int f = 0; f < 8; f++) axpy(acc[m][f], wgt, sp[f]);
-            }
+            for (int f = 0; f < 8; f++) axpy(acc[m][f], wgt, s_src[f][lp]);
           }
         }
       }
@@ -147,12 +162,16 @@ __global__ void __launch_bounds__(GA_THREADS) gather_kernel(DevGrid<T> dg, Gathe
     __syncthreads();
   }
   const size_t G = (size_t)g.ncell;
+  for (int f = 0; f < 8; f++) {
 #pragma unroll
-  for (int m = 0; m < MAXN; m++) {
-    const int nd = threadIdx.x + m * GA_THREADS;
-    if (nd >= plane) continue;
-#pragma unroll
-    for (int f = 0; f < 8; f++) phys[f * G + (size_t)x * plane + nd] = acc[m][f];
+    for (int m = 0; m < MAXI; m++) {
+      const int it = threadIdx.x + m * blockDim.x;
+      if (it < 3 * plane) s_red[it] = acc[m][f];
+    }
+    __syncthreads();
+    for (int nd = threadIdx.x; nd < plane; nd += blockDim.x)
+      phys[f * G + (size_t)x * plane + nd] = s_red[nd] + s_red[plane + nd] + s_red[2 * plane + nd];
+    __syncthreads();
   }
 }
 
@@ -166,7 +185,18 @@ void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &gri
   }
   for (size_t k = 0; k < grids.size(); k++) {
     const GatherGrid<T> &g = gg[k];
-    hipLaunchKernelGGL(gather_kernel<T>, dim3(grids[k].n[0], nb), dim3(GA_THREADS), 0, s, grids[k], g);
+    const int plane = grids[k].n[1] * grids[k].n[2];
+    const int items = 3 * plane;
+    const int threads = std::min(1024, (items + 63) / 64 * 64);
+    const int maxi = (items + threads - 1) / threads;
+    const size_t lds = sizeof(cx<T>) * (size_t)items;
+    const dim3 grid(grids[k].n[0], nb);
+    if (maxi == 1)
+      hipLaunchKernelGGL((gather_kernel<T, 1>), grid, dim3(threads), lds, s, grids[k], g);
+    else if (maxi == 2)
+      hipLaunchKernelGGL((gather_kernel<T, 2>), grid, dim3(threads), lds, s, grids[k], g);
+    else
+      hipLaunchKernelGGL((gather_kernel<T, 3>), grid, dim3(threads), lds, s, grids[k], g);
   }
 }
 template void launch_project<float>(const DevOperator<float> &, const std::vector<DevGrid<float>> &,
@@ -351,7 +381,7 @@ template <typename T> __device__ inline T wave_sum(T v) {
 // Up to NR_MAXB vectors per launch: every CSR entry's values are read once
 // and applied to all of them.
 constexpr int NR_MAXB = 8;
-template <typename T>
+template <typename T, int NRB>
 __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, double *__restrict__ y, int nb) {
   const int n = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -359,9 +389,9 @@ __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, doubl
   const EdgeRec r = op.edges[n];
   const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
   const size_t bs = (size_t)3 * op.ne;
-  cx<T> E[NR_MAXB], H[NR_MAXB], R[NR_MAXB];
+  cx<T> E[NRB], H[NRB], R[NRB];
 #pragma unroll
-  for (int b = 0; b < NR_MAXB; b++) E[b] = H[b] = R[b] = czero<T>();
+  for (int b = 0; b < NRB; b++) E[b] = H[b] = R[b] = czero<T>();
   const int64_t kb = op.rowptr[n], ke = op.rowptr[n + 1];
   for (int64_t k = kb + lane; k < ke; k += 64) {
     const int m = op.col[k];
@@ -375,7 +405,7 @@ __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, doubl
     }
     const cx<T> KeKi = Ke + Ki;
 #pragma unroll
-    for (int b = 0; b < NR_MAXB; b++) {
+    for (int b = 0; b < NRB; b++) {
       if (b >= nb) break;
       const cx<T> *src = op.src + bs * b + 3 * m;
       const cx<T> Je = src[0], Ji = src[1], M = src[2];
@@ -388,7 +418,7 @@ __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, doubl
     }
   }
 #pragma unroll
-  for (int b = 0; b < NR_MAXB; b++) {
+  for (int b = 0; b < NRB; b++) {
     if (b >= nb) break;
     cx<T> e = E[b], h = H[b], rr = R[b];
     e.x = wave_sum(e.x);
@@ -421,7 +451,14 @@ int near_rows_max_batch() { return NR_MAXB; }
 
 template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s, int nb) {
   int blocks = (int)(((int64_t)op.ne * 64 + 255) / 256);
-  hipLaunchKernelGGL(near_rows_kernel<T>, dim3(blocks), dim3(256), 0, s, op, y, nb);
+  if (nb == 1)
+    hipLaunchKernelGGL((near_rows_kernel<T, 1>), dim3(blocks), dim3(256), 0, s, op, y, nb);
+  else if (nb == 2)
+    hipLaunchKernelGGL((near_rows_kernel<T, 2>), dim3(blocks), dim3(256), 0, s, op, y, nb);
+  else if (nb <= 4)
+    hipLaunchKernelGGL((near_rows_kernel<T, 4>), dim3(blocks), dim3(256), 0, s, op, y, nb);
+  else
+    hipLaunchKernelGGL((near_rows_kernel<T, NR_MAXB>), dim3(blocks), dim3(256), 0, s, op, y, nb);
 }
 template void launch_near_rows<float>(const DevOperator<float> &, double *, hipStream_t, int);
 template void launch_near_rows<double>(const DevOperator<double> &, double *, hipStream_t, int);
