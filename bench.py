@@ -1,17 +1,25 @@
-"""Benchmark: precorrected-FFT PMCHW products and mixed-precision solves.
+"""Benchmark: precorrected-FFT PMCHW products, mixed-precision batched solves
+and the adjoint sigma gradient on one GPU.
 
-Workload: two parallel 0.4 x 0.2 dielectric channels (eps 12.25 in air),
-30 long, quartic surface-conductivity absorbers of length 4 at both ends,
-mesh edge 0.072 (N ~ 1e5 unknowns), one seeded dipole in channel 0; lengths in
-wavelengths inside the guide.  Synthetic, seeded inputs (synth.py).
+Workload: two parallel 0.4 x 0.2 dielectric channels (eps 12.25 in air, gap
+0.3), 30 long, quartic surface-conductivity absorbers of length 4 at both
+ends, mesh edge 0.072 (N = 102,852 unknowns), exterior grid 511 x 21 x 7
+(FFT 1024 x 48 x 16); lengths in wavelengths inside the guide.  Synthetic,
+seeded inputs (synth package).
 
-One step = one mixed-precision solve of A x = b to relative residual 1e-6
-(FP32 products inside GMRES, FP64 orthogonalisation and refinement residual,
-right preconditioner), i.e. one pass of every stage of the hot path.
-value = operator products per second over the timed steps (the solve's
-products, FP32 and FP64).  Also reported: standalone FP32/FP64 product rates,
-the FP64-only solve time, the roofline of the dominant kernel measured with
-HIP events over the timed region, and the oracle timed on the host.
+One step = one pass of the whole hot path: a batched mixed-precision solve of
+B = 8 seeded dipoles in channel 0 to relative residual 1e-6 (FP32 products
+inside GMRES, FP64 orthogonalisation and refinement residual, right Schwarz
+preconditioner), then, for dipole 0, the reflected amplitude at 16 monitor
+points on the channel axis, its adjoint (transposed) mixed solve and the sigma
+gradient.  value = operator products per second over the timed steps
+(forward and transposed, FP32 and FP64, all right-hand sides).
+
+Also reported: single-dipole mixed and FP64 solve times (the mixed/FP64
+comparison), standalone product rates (1 and 8 vectors), per-stage averages
+from HIP events, the roofline of the dominant kernel (the Schwarz
+preconditioner apply, HBM-bound) measured with HIP events on the library
+stream over the timed region, and the oracle timed on the host.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -29,42 +37,58 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BATCH = 8
 
 
-def near_rows_bytes(info: dict, real_bytes: int) -> float:
-    """Algorithmic bytes of one near-correction-row launch (the dominant
-    kernel): CSR row pointers and columns, four complex exact-minus-grid values
-    per entry (eight on absorber rows), per-edge currents and triangle partial
-    rows read once, edge records, and the FP64 output rows written."""
-    cplx = 2 * real_bytes
-    ne, nt, N = info["n_edges"], info["n_tris"], info["N"]
-    nnz, nnzr = info["nnz_near"], info["nnz_near_r"]
-    return ((ne + 1) * 8 + nnz * 4 + nnz * 4 * cplx + nnzr * 4 * cplx + ne * 3 * cplx + ne * 56
-            + nt * 9 * cplx + N * 16)
+def precond_bytes(info: dict, m: int) -> float:
+    """Algorithmic bytes of one preconditioner apply to m vectors (the dominant
+    kernel): every stored FP32 complex coefficient once (8 B), per
+    extended-set entry its unknown index (4 B) and m FP64 complex inputs
+    (16 B each), per unknown its core index (4 B) and m FP64 complex outputs."""
+    return 8.0 * info["precond_entries"] + (4.0 + 16.0 * m) * (info["precond_ext_entries"] + info["N"])
 
 
-def kernel_src_sha() -> str:
-    p = os.path.join(ROOT, "paper_1004_5076_amd", "csrc", "kernels_matvec.hip")
+def kernel_src_sha(name: str) -> str:
+    p = os.path.join(ROOT, "paper_1004_5076_amd", "csrc", name)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(bytes_alg: float):
-    """HBM bytes per launch from committed rocprofv3 counter runs, only if they
-    were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "near_rows_two_channel_traffic.json")
+def measured_traffic():
+    """HBM bytes per launch of the preconditioner apply from committed
+    rocprofv3 counter runs, only if they were taken on the current source."""
+    p = os.path.join(ROOT, "profiles", "precond_apply_two_channel_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_src_sha") != kernel_src_sha():
+    if d.get("kernel_src_sha") != kernel_src_sha("kernels_precond.hip"):
         return None
     return d.get("bytes_per_launch")
 
 
+def dipole_field_y(w, d, p):
+    """E_y of the source dipole in the interior medium at p (closed form): the
+    incident part of the monitored field."""
+    import numpy as np
+    k = w.omega * math.sqrt(w.eps_in)
+    Z = 1.0 / math.sqrt(w.eps_in)
+    r = np.asarray(p, float) - np.asarray(d.pos, float)
+    R = float(np.linalg.norm(r))
+    u = r / R
+    m = np.asarray(d.moment, complex)
+    e = np.exp(-1j * k * R)
+    G = e / (4 * math.pi * R)
+    G1 = -(1 + 1j * k * R) * e / (4 * math.pi * R * R)
+    G2 = (2 - k * k * R * R + 2j * k * R) * e / (4 * math.pi * R ** 3)
+    up = u @ m
+    hp = G2 * up * u + (G1 / R) * (m - up * u)
+    E = -1j * k * Z * (m * G + hp / (k * k))
+    return E[1]
+
+
 def cpu_baseline(w_full_N: int, budget_s: float = 20.0) -> dict:
     """The oracle's precorrected-FFT product (numpy FFT + plain C loops) on a
-    1-long two-channel section of the same geometry, mesh and grid; scaled
+    0.6-long two-channel section of the same geometry, mesh and grid; scaled
     linearly in N to the benchmark size (the product's cost is ~linear)."""
-    import numpy as np
     import oracle
     import synth
     w = synth.workload_two_channel(length=0.6, absorber=0.3, edge=0.072)
@@ -95,14 +119,16 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=240)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-solve", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the untimed single-solve and product-rate runs")
     ap.add_argument("--products-only", type=int, default=0,
-                    help="run this many FP32 products, then a device copy of known size (counter calibration)")
+                    help="run this many FP32 products and preconditioner applies, then a device copy of known "
+                         "size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    import numpy as np
     import torch
     import paper_1004_5076_amd as pk
     import synth
@@ -117,78 +143,114 @@ def main():
     info = ctx.info()
     log("setup", f"{setup_s:.2f}s", info)
     N = ctx.N
-    d = w.dipoles[0]
-    b = ctx.rhs_dipole(d.pos, d.moment, d.body)
+    d0 = w.dipoles[0]
 
     if args.products_only:
         x = torch.from_numpy(synth.random_complex(3, N)).to(dev)
         for _ in range(args.products_only):
             ctx.matvec(x, prec=pk.SCABS_FP32)
+        b = ctx.rhs_dipole(d0.pos, d0.moment, d0.body)
+        b4 = torch.stack([b] * 4).contiguous()
+        for _ in range(args.products_only):   # one GMRES step: one FP32 apply to 4 vectors
+            ctx.solve(b4, tol=0.5, max_iter=1, restart=1, mode=pk.SCABS_MIXED)
         torch.cuda.synchronize()
-        # calibration copy: 2^28 bytes read and 2^28 bytes written
-        a = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        a = torch.ones(1 << 26, dtype=torch.float32, device=dev)   # 2^28 bytes read, 2^28 written
         c = torch.empty_like(a)
         c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"products": args.products_only, "N": N, "copy_bytes": 1 << 28, "info": info,
-                          "near_rows_alg_bytes": near_rows_bytes(info, 4), "kernel_src_sha": kernel_src_sha()}))
+                          "precond_alg_bytes": precond_bytes(info, 4),
+                          "kernel_src_sha": kernel_src_sha("kernels_precond.hip")}))
         ctx.close()
         return
 
-    # standalone product rates
-    x = torch.from_numpy(synth.random_complex(3, N)).to(dev)
-    rates = {}
-    for prec, name in ((pk.SCABS_FP32, "fp32"), (pk.SCABS_FP64, "fp64")):
-        for _ in range(3):
-            ctx.matvec(x, prec=prec)
-        torch.cuda.synchronize()
-        n = 30
-        t1 = time.perf_counter()
-        for _ in range(n):
-            ctx.matvec(x, prec=prec)
-        torch.cuda.synchronize()
-        rates[name] = n / (time.perf_counter() - t1)
-    log("product rates /s", rates)
+    # seeded dipoles in channel 0 within its first wavelength; monitor points on its axis
+    dips = [d0] + [synth.seeded_dipole(600 + k, base=(0.5, float(d0.pos[1]), 0.0), body=d0.body)
+                   for k in range(BATCH - 1)]
+    B = torch.stack([ctx.rhs_dipole(d.pos, d.moment, d.body) for d in dips]).contiguous()
+    xs_m = np.linspace(6.0, 24.0, 16)
+    pts = np.stack([xs_m, np.full_like(xs_m, float(d0.pos[1])), np.zeros_like(xs_m)], 1)
+    beta = 0.9 * w.omega * math.sqrt(w.eps_in)
+    fit = np.stack([np.exp(-1j * beta * xs_m), np.exp(1j * beta * xs_m)], axis=1)
+    wE = np.zeros((len(xs_m), 3), complex)
+    wE[:, 1] = np.linalg.pinv(fit)[1]
+    wE_t = torch.from_numpy(wE).to(dev)
+    Einc_y = torch.from_numpy(np.array([dipole_field_y(w, d0, p) for p in pts])).to(dev)
+    einc = ctx.incident_dipole_points(d0.pos, d0.moment, d0.body)
+    region = int(d0.body)
 
-    # warmup solves
+    def step():
+        X, infos = ctx.solve(B, tol=args.tol, restart=args.restart, mode=pk.SCABS_MIXED, max_iter=6000)
+        x0 = X[0].contiguous()
+        E, _ = ctx.eval_field(x0, pts, region)
+        bh = (wE_t[:, 1] * (Einc_y + E[:, 1])).sum()
+        q = ctx.eval_field_transpose(pts, region, wE_t)
+        g = (torch.conj(bh) * q).contiguous()
+        lam, ia = ctx.solve(g, tol=args.tol, restart=args.restart, mode=pk.SCABS_MIXED, max_iter=6000,
+                            transpose=True)
+        _, dpar = ctx.sigma_gradient(x0, lam, einc)
+        return infos, ia, dpar
+
     for _ in range(args.warmup):
-        ctx.solve(b, tol=args.tol, restart=args.restart, mode=pk.SCABS_MIXED)
+        step()
     torch.cuda.synchronize()
-    # timed steps, stage events recorded on the library stream
     ctx.profile_begin()
-    infos = []
+    all_infos, adj_infos = [], []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
-        xs, si = ctx.solve(b, tol=args.tol, restart=args.restart, mode=pk.SCABS_MIXED)
-        infos.append(si)
+        infos, ia, dpar = step()
+        all_infos += infos
+        adj_infos.append(ia)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     prof = ctx.profile_end()
-    nprod = sum(i["matvecs32"] + i["matvecs64"] for i in infos)
-    ok = all(i["status"] == 0 for i in infos)
-    log("mixed solves", infos, f"{dt / args.steps:.4f}s per solve")
-    log("stages", prof)
-
-    fp64_solve = None
-    if not args.no_fp64_solve:
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        x64, si64 = ctx.solve(b, tol=args.tol, restart=args.restart, mode=pk.SCABS_FP64)
-        torch.cuda.synchronize()
-        fp64_solve = {"seconds": time.perf_counter() - t2, **si64}
-        rel = (torch.linalg.norm(xs - x64) / torch.linalg.norm(x64)).item()
-        fp64_solve["mixed_vs_fp64_rel_diff"] = rel
-        log("fp64 solve", fp64_solve)
-
-    # dominant kernel: near-correction rows of the FP32 product
-    near = prof["near32"]
-    avg_s = near["ms"] / max(near["count"], 1) * 1e-3
-    bytes_alg = near_rows_bytes(info, 4)
-    achieved = bytes_alg / avg_s / 1e9 if avg_s > 0 else 0.0
-    tr = measured_traffic(bytes_alg)
+    nprod = sum(i["matvecs32"] + i["matvecs64"] for i in all_infos + adj_infos)
+    ok = all(i["status"] == 0 for i in all_infos + adj_infos)
+    log("batched solves", all_infos[:BATCH], "adjoint", adj_infos[0], "gradient", list(dpar),
+        f"{dt / args.steps:.3f}s per step")
     stage_avg_us = {k: (v["ms"] / v["count"] * 1e3 if v["count"] else 0.0) for k, v in prof.items()}
+    stage_total_ms = {k: v["ms"] for k, v in prof.items()}
+    log("stages avg us", stage_avg_us)
 
+    extras = {}
+    if not args.no_extras:
+        b0 = B[0].clone()
+        xsol = {}
+        for mode, name in ((pk.SCABS_MIXED, "mixed"), (pk.SCABS_FP64, "fp64")):
+            ctx.solve(b0, tol=args.tol, restart=args.restart, mode=mode, max_iter=6000)   # warm
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            x1, si = ctx.solve(b0, tol=args.tol, restart=args.restart, mode=mode, max_iter=6000)
+            torch.cuda.synchronize()
+            extras[f"solve_single_{name}"] = {"seconds": time.perf_counter() - t2, **si}
+            xsol[name] = x1
+        extras["mixed_vs_fp64_rel_diff"] = (torch.linalg.norm(xsol["mixed"] - xsol["fp64"]) /
+                                            torch.linalg.norm(xsol["fp64"])).item()
+        x8 = torch.from_numpy(np.stack([synth.random_complex(3 + k, N) for k in range(BATCH)])).to(dev)
+        rates = {}
+        for prec, name in ((pk.SCABS_FP32, "fp32"), (pk.SCABS_FP64, "fp64")):
+            for nb in (1, BATCH):
+                xb = x8[:nb].contiguous()
+                for _ in range(2):
+                    ctx.matvec(xb, prec=prec)
+                torch.cuda.synchronize()
+                n = 10
+                t3 = time.perf_counter()
+                for _ in range(n):
+                    ctx.matvec(xb, prec=prec)
+                torch.cuda.synchronize()
+                rates[f"{name}_x{nb}"] = n * nb / (time.perf_counter() - t3)
+        extras["product_rates_per_s"] = rates
+        log("extras", extras)
+
+    # dominant kernel: the FP32 Schwarz preconditioner apply to 4 vectors (one kernel per stage event)
+    pc = prof["precond"]
+    avg_s = pc["ms"] / max(pc["count"], 1) * 1e-3
+    bytes_alg = precond_bytes(info, 4)   # the timed batch of 8 applies in launches of 4 vectors
+    achieved = bytes_alg / avg_s / 1e9 if avg_s > 0 else 0.0
+    single_m = extras.get("solve_single_mixed", {}).get("seconds")
+    single_d = extras.get("solve_single_fp64", {}).get("seconds")
     out = {
         "metric": "PMCHW matvecs/s + solve time @1e-6 resid, N~100k: mixed/batched vs FP64, 1 GPU",
         "value": nprod / dt,
@@ -204,18 +266,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": "two_channel_30x0.4x0.2_quartic_absorbers_edge%.3g" % args.edge, "N": N,
                    "grid_phys": info["grid_phys"], "grid_fft": info["grid_fft"], "h": w.h, "r_near": w.r_near,
-                   "tol": args.tol, "restart": args.restart},
-        "solve_mixed_s": dt / args.steps,
-        "solve_mixed_iters": infos[0]["inner_iters"],
+                   "tol": args.tol, "restart": args.restart, "batch_rhs": BATCH,
+                   "step": "batched mixed solve of 8 dipoles + adjoint solve + sigma gradient"},
         "solve_converged": ok,
-        "solve_fp64": fp64_solve,
-        "matvec_fp32_per_s": rates["fp32"],
-        "matvec_fp64_per_s": rates["fp64"],
+        "step_s_per_rhs": dt / args.steps / BATCH,
+        "solve_single_mixed_s": single_m,
+        "solve_single_fp64_s": single_d,
+        "mixed_speedup_vs_fp64": (single_d / single_m) if single_m and single_d else None,
+        "iters_mixed": all_infos[0]["inner_iters"],
+        "adjoint_iters": adj_infos[0]["inner_iters"],
+        "extras": extras,
         "setup_s": setup_s,
         "stage_avg_us": stage_avg_us,
-        "roofline": {"kernel": "near_rows_kernel<float>", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": tr, "bytes_per_launch": bytes_alg, "avg_launch_us": avg_s * 1e6},
+        "stage_total_ms": stage_total_ms,
+        "roofline": {"kernel": "precond_apply32_kernel<4>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "bytes_per_launch": bytes_alg, "avg_launch_us": avg_s * 1e6},
     }
     if not args.no_cpu_baseline:
         try:

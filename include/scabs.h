@@ -78,6 +78,7 @@ typedef struct {
   int64_t n_clusters;      /* preconditioner clusters (0 without) */
   int64_t precond_entries; /* stored preconditioner coefficients */
   int64_t device_bytes;    /* device memory held by the context */
+  int64_t precond_ext_entries; /* sum over clusters of their extended sets */
 } scabs_info_t;
 
 typedef struct {
@@ -215,7 +216,8 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
 #define SCABS_STAGE_FP32_OFFSET 5  /* add to stages 0-4 for the FP32 product */
 #define SCABS_STAGE_PRECOND 10   /* preconditioner application */
 #define SCABS_STAGE_ORTHO 11     /* Gram-Schmidt, norms (FP64) */
-#define SCABS_NSTAGES 12
+#define SCABS_STAGE_PRECOND_T 12 /* transposed preconditioner application */
+#define SCABS_NSTAGES 13
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
 

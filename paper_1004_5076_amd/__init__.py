@@ -28,7 +28,7 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
-          "near32", "precond", "ortho"]
+          "near32", "precond", "ortho", "precond_t"]
 
 
 class ScabsError(RuntimeError):
@@ -47,7 +47,7 @@ class Info(C.Structure):
                 ("n_tris", C.c_int64), ("n_points", C.c_int64), ("n_bodies", C.c_int64),
                 ("n_near_pairs", C.c_int64), ("nnz_near", C.c_int64), ("grid_phys", C.c_int64 * 3),
                 ("grid_fft", C.c_int64 * 3), ("nnz_near_r", C.c_int64), ("n_clusters", C.c_int64),
-                ("precond_entries", C.c_int64), ("device_bytes", C.c_int64)]
+                ("precond_entries", C.c_int64), ("device_bytes", C.c_int64), ("precond_ext_entries", C.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -126,6 +126,7 @@ struct scabs_ctx {
   int *pc_ext_slot = nullptr, *pc_core_slot = nullptr;
   int *pc_items = nullptr;   // (cluster, first core row) per apply work-group
   int pc_n_items = 0;
+  int pc_max_ext = 0;        // largest extended set
   cx<float> *pc_Rt = nullptr;
   // transposed apply: cluster of every ext entry, and per unknown its ext entries
   int64_t pc_n_ext = 0;
@@ -420,6 +421,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   c->pc_Rt = c->mem.alloc<cx<float>>((size_t)cl.r_off[cl.nc]);
   int max_ext = 0;
   for (int k = 0; k < cl.nc; k++) max_ext = std::max(max_ext, (int)(cl.ext_ptr[k + 1] - cl.ext_ptr[k]));
+  c->pc_max_ext = max_ext;
   launch_precond_build(p, max_ext, c->pc_core_ptr, core_pos, c->pc_r_off, c->pc_Rt, piv, status, s);
   HIPCHK(hipGetLastError());
   int st = 0;
@@ -430,7 +432,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
 }
 
 static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool trans) {
-  StageTimer tm(c, SCABS_STAGE_PRECOND);
+  StageTimer tm(c, trans ? SCABS_STAGE_PRECOND_T : SCABS_STAGE_PRECOND);
   if (!trans)
     launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
                          c->pc_r_off, c->pc_Rt, x, y, c->stream);
@@ -738,8 +740,20 @@ static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec,
   }
 }
 
-static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, int nb, bool trans) {
+// prec: precision of the products the preconditioner feeds (FP32 inner solves
+// use the batched single-precision apply)
+static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, int nb, bool trans, int prec) {
   const size_t N = (size_t)c->lay.N;
+  if (!trans && prec == SCABS_FP32) {
+    const int B = precond_apply32_max_batch();
+    for (int b0 = 0; b0 < nb; b0 += B) {
+      StageTimer tm(c, SCABS_STAGE_PRECOND);
+      launch_precond_apply32(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr,
+                             c->pc_core_slot, c->pc_r_off, c->pc_Rt, x + b0 * N, y + b0 * N, (int64_t)N,
+                             std::min(B, nb - b0), c->pc_max_ext, c->stream);
+    }
+    return;
+  }
   for (int k = 0; k < nb; k++) apply_precond(c, x + k * N, y + k * N, trans);
 }
 
@@ -825,7 +839,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     while (j < m && !run.empty()) {
       cx<double> *vj = c->V + (size_t)j * ldv;
       if (c->has_pc) {
-        apply_precond_n(c, vj, c->z, nb, trans);
+        apply_precond_n(c, vj, c->z, nb, trans, prec);
         matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
       } else {
         matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
@@ -902,7 +916,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       HIPCHK(hipStreamSynchronize(s));
     }
     if (c->has_pc) {
-      apply_precond_n(c, c->t, c->z, nb, trans);
+      apply_precond_n(c, c->t, c->z, nb, trans, prec);
       for (int b : act) kr_axpy(sol + b * N, c->z + b * N, N, s);
     } else {
       for (int b : act) kr_axpy(sol + b * N, c->t + b * N, N, s);
@@ -1105,8 +1119,12 @@ int scabs_info(const scabs_ctx *c, scabs_info_t *info) {
   }
   info->nnz_near_r = c->nnzR;
   info->n_clusters = c->has_pc ? c->cl.nc : 0;
-  info->precond_entries = c->has_pc ? c->cl.r_off[c->cl.nc] : 0;
+  info->precond_entries = 0;
+  if (c->has_pc)
+    for (int k = 0; k < c->cl.nc; k++)
+      info->precond_entries += (c->cl.ext_ptr[k + 1] - c->cl.ext_ptr[k]) * (c->cl.core_ptr[k + 1] - c->cl.core_ptr[k]);
   info->device_bytes = (int64_t)(c->mem.bytes + c->work.bytes);
+  info->precond_ext_entries = c->has_pc ? c->cl.ext_ptr[c->cl.nc] : 0;
   return SCABS_OK;
 }
 

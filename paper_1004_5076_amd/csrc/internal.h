@@ -58,6 +58,10 @@ struct NearList {
   std::vector<uint8_t> cij;       // i*3 + j
 };
 
+// Column stride of a cluster's stored core rows: a multiple of 16 FP32
+// complex values (128 bytes), so every column segment starts on a cache line.
+__host__ __device__ inline int64_t rt_stride(int64_t nc) { return (nc + 15) / 16 * 16; }
+
 // Overlapping box clusters of edges (restricted additive Schwarz on the
 // near-field matrix): core = edges whose midpoint lies in a cubic cell,
 // ext = edges whose midpoint lies in the cell grown by the overlap.

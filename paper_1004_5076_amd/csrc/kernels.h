@@ -133,6 +133,14 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
                           const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
                           const cx<double> *x, cx<double> *y, hipStream_t s);
 
+// FP32 batched apply (inner solves of the mixed mode): m vectors of N,
+// m <= precond_apply32_max_batch()
+int precond_apply32_max_batch();
+void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off,
+                            const cx<float> *Rt, const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext,
+                            hipStream_t s);
+
 // ---- transposed product, adjoint gradient --------------------------------------
 template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s);
 // src4[k]: 32 coefficients per sorted point of grid k (work buffer)

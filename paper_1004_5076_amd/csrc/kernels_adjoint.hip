@@ -11,6 +11,8 @@
 // convolved lattice with W at the source points and hands the result back to
 // the half-RWG currents.  The near transpose walks the same edge-pair CSR
 // (the near list is symmetric) reading the entry of the mirrored pair.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -107,9 +109,9 @@ adj_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restr
 }
 
 // test^T, step 2: every node sums, over the points of its 27 neighbouring
-// cells, W c_value + W_x c_x + W_y c_y + W_z c_z per field (the layout and
-// LDS staging of the forward gather, with four coefficients per field).
-constexpr int GT_THREADS = 256;
+// cells, W c_value + W_x c_x + W_y c_y + W_z c_z per field.  Same organisation
+// as the forward gather: one work-group per x plane, work items (node, dx),
+// coefficients staged field-major in LDS, dx partials added at the end.
 template <typename T> struct GtChunk { static constexpr int value = 256; };
 template <> struct GtChunk<double> { static constexpr int value = 128; };
 
@@ -127,61 +129,68 @@ template <typename T> __device__ inline void lagr_pick(int i, T u, T &L, T &dL) 
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(GT_THREADS)
+template <typename T, int MAXI>
+__global__ void __launch_bounds__(1024)
 gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4, T inv_h) {
   constexpr int CH = GtChunk<T>::value;
-  __shared__ cx<T> s_src[CH * 32];
-  __shared__ T s_u[CH * 3];
+  __shared__ cx<T> s_src[32][CH];
+  __shared__ T s_u[3][CH];
+  extern __shared__ unsigned char smem_raw[];
+  cx<T> *s_red = reinterpret_cast<cx<T> *>(smem_raw);   // 3 * plane
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   const int x = blockIdx.x;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
   const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
-  constexpr int MAXN = 4;   // nodes per thread (plane <= MAXN * GT_THREADS)
-  cx<T> acc[MAXN][8];
+  const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane);
+  cx<T> acc[MAXI][8];
 #pragma unroll
-  for (int m = 0; m < MAXN; m++)
+  for (int m = 0; m < MAXI; m++)
 #pragma unroll
     for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
   for (int64_t c0 = P0; c0 < P1; c0 += CH) {
     const int64_t c1 = min(c0 + (int64_t)CH, P1);
     const int cn = (int)(c1 - c0);
-    for (int i = threadIdx.x; i < cn * 32; i += blockDim.x) s_src[i] = src4[(size_t)32 * c0 + i];
-    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) s_u[i] = g.u[(size_t)3 * c0 + i];
+    for (int i = threadIdx.x; i < cn * 32; i += blockDim.x) {
+      const int lp = i >> 5, f = i & 31;
+      s_src[f][lp] = src4[(size_t)32 * c0 + i];
+    }
+    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) {
+      const int lp = i / 3, a = i - 3 * lp;
+      s_u[a][lp] = g.u[(size_t)3 * c0 + i];
+    }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MAXN; m++) {
-      const int nd = threadIdx.x + m * GT_THREADS;
-      if (nd >= plane) continue;
-      const int y = nd / n2, z = nd - y * n2;
-      for (int dx = -1; dx <= 1; dx++) {
-        const int ax = x + dx;
-        if (ax < 0 || ax >= n0) continue;
-        for (int dy = -1; dy <= 1; dy++) {
-          const int ay = y + dy;
-          if (ay < 0 || ay >= n1) continue;
-          const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
-          for (int dz = -1; dz <= 1; dz++) {
-            const int az = z + dz;
-            if (az < 0 || az >= n2) continue;
-            const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
-            for (int64_t p = p0; p < p1; p++) {
-              const int lp = (int)(p - c0);
-              T Lx, Ly, Lz, dLx, dLy, dLz;
-              lagr_pick(-dx, s_u[3 * lp], Lx, dLx);
-              lagr_pick(-dy, s_u[3 * lp + 1], Ly, dLy);
-              lagr_pick(-dz, s_u[3 * lp + 2], Lz, dLz);
-              const T W = Lx * Ly * Lz, Wx = dLx * Ly * Lz * inv_h, Wy = Lx * dLy * Lz * inv_h,
-                      Wz = Lx * Ly * dLz * inv_h;
-              const cx<T> *sp = s_src + 32 * lp;
+    for (int m = 0; m < MAXI; m++) {
+      const int it = threadIdx.x + m * blockDim.x;
+      if (it >= 3 * plane) continue;
+      const int dxi = fdiv(it, dpl), nd = it - dxi * plane;
+      const int dx = dxi - 1;
+      const int ax = x + dx;
+      if (ax < 0 || ax >= n0) continue;
+      const int y = fdiv(nd, dn2), z = nd - y * n2;
+      for (int dy = -1; dy <= 1; dy++) {
+        const int ay = y + dy;
+        if (ay < 0 || ay >= n1) continue;
+        const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
+        for (int dz = -1; dz <= 1; dz++) {
+          const int az = z + dz;
+          if (az < 0 || az >= n2) continue;
+          const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
+          for (int64_t p = p0; p < p1; p++) {
+            const int lp = (int)(p - c0);
+            T Lx, Ly, Lz, dLx, dLy, dLz;
+            lagr_pick(-dx, s_u[0][lp], Lx, dLx);
+            lagr_pick(-dy, s_u[1][lp], Ly, dLy);
+            lagr_pick(-dz, s_u[2][lp], Lz, dLz);
+            const T W = Lx * Ly * Lz, Wx = dLx * Ly * Lz * inv_h, Wy = Lx * dLy * Lz * inv_h,
+                    Wz = Lx * Ly * dLz * inv_h;
 #pragma unroll
-              for (int f = 0; f < 8; f++) {
-                axpy(acc[m][f], W, sp[4 * f]);
-                axpy(acc[m][f], Wx, sp[4 * f + 1]);
-                axpy(acc[m][f], Wy, sp[4 * f + 2]);
-                axpy(acc[m][f], Wz, sp[4 * f + 3]);
-              }
+            for (int f = 0; f < 8; f++) {
+              axpy(acc[m][f], W, s_src[4 * f][lp]);
+              axpy(acc[m][f], Wx, s_src[4 * f + 1][lp]);
+              axpy(acc[m][f], Wy, s_src[4 * f + 2][lp]);
+              axpy(acc[m][f], Wz, s_src[4 * f + 3][lp]);
             }
           }
         }
@@ -190,12 +199,16 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
     __syncthreads();
   }
   const size_t G = (size_t)g.ncell;
+  for (int f = 0; f < 8; f++) {
 #pragma unroll
-  for (int m = 0; m < MAXN; m++) {
-    const int nd = threadIdx.x + m * GT_THREADS;
-    if (nd >= plane) continue;
-#pragma unroll
-    for (int f = 0; f < 8; f++) dg.phys[f * G + (size_t)x * plane + nd] = acc[m][f];
+    for (int m = 0; m < MAXI; m++) {
+      const int it = threadIdx.x + m * blockDim.x;
+      if (it < 3 * plane) s_red[it] = acc[m][f];
+    }
+    __syncthreads();
+    for (int nd = threadIdx.x; nd < plane; nd += blockDim.x)
+      dg.phys[f * G + (size_t)x * plane + nd] = s_red[nd] + s_red[plane + nd] + s_red[2 * plane + nd];
+    __syncthreads();
   }
 }
 
@@ -207,9 +220,22 @@ void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grid
     hipLaunchKernelGGL(adj_sources_kernel<T>, dim3((g.np + 255) / 256), dim3(256), 0, s, op.pts, op.tris, op.src, g,
                        src4[k], grids[k].k, grids[k].Z, grids[k].which >= 0 ? 1 : 0);
   }
-  for (size_t k = 0; k < grids.size(); k++)
-    hipLaunchKernelGGL(gather_adj_kernel<T>, dim3(grids[k].n[0]), dim3(GT_THREADS), 0, s, grids[k], gg[k], src4[k],
-                       inv_h);
+  for (size_t k = 0; k < grids.size(); k++) {
+    const int plane = grids[k].n[1] * grids[k].n[2];
+    const int items = 3 * plane;
+    const int threads = std::min(1024, (items + 63) / 64 * 64);
+    const int maxi = (items + threads - 1) / threads;
+    const size_t lds = sizeof(cx<T>) * (size_t)items;
+    if (maxi == 1)
+      hipLaunchKernelGGL((gather_adj_kernel<T, 1>), dim3(grids[k].n[0]), dim3(threads), lds, s, grids[k], gg[k],
+                         src4[k], inv_h);
+    else if (maxi == 2)
+      hipLaunchKernelGGL((gather_adj_kernel<T, 2>), dim3(grids[k].n[0]), dim3(threads), lds, s, grids[k], gg[k],
+                         src4[k], inv_h);
+    else
+      hipLaunchKernelGGL((gather_adj_kernel<T, 3>), dim3(grids[k].n[0]), dim3(threads), lds, s, grids[k], gg[k],
+                         src4[k], inv_h);
+  }
 }
 template void launch_test_t<float>(const DevOperator<float> &, const std::vector<DevGrid<float>> &,
                                    const std::vector<GatherGrid<float>> &, const std::vector<cx<float> *> &, float,
@@ -433,7 +459,7 @@ precond_t_dots_kernel(int nc, const int64_t *__restrict__ ext_ptr, const int *__
   const int c = ext_cluster[it];
   const int j = (int)(it - ext_ptr[c]);
   const int ncore = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const cx<float> *R = Rt + r_off[c] + (size_t)j * ncore;
+  const cx<float> *R = Rt + r_off[c] + (size_t)j * rt_stride(ncore);
   const int *cs = core_slot + core_ptr[c];
   double ar = 0, ai = 0;
   for (int i = lane; i < ncore; i += 64) {

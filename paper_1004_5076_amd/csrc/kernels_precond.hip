@@ -187,7 +187,8 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ab
   }
 }
 
-// Rt[j][i] = inverse[core_pos[i]][j], FP32 (column-major over the core rows)
+// Rt[j][i] = inverse[core_pos[i]][j], FP32 (column-major over the core rows,
+// column stride rt_stride(nc))
 __global__ void extract_kernel(const cx<double> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr,
                                const int64_t *core_ptr, const int *core_pos, const int64_t *r_off, cx<float> *Rt) {
   const int c = blockIdx.y;
@@ -198,7 +199,7 @@ __global__ void extract_kernel(const cx<double> *Ablocks, const int64_t *a_off, 
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(idx / nc), i = (int)(idx - (int64_t)j * nc);
     const cx<double> v = A[(size_t)core_pos[core_ptr[c] + i] * ne + j];
-    Rt[r_off[c] + idx] = {(float)v.x, (float)v.y};
+    Rt[r_off[c] + (int64_t)j * rt_stride(nc) + i] = {(float)v.x, (float)v.y};
   }
 }
 
@@ -232,6 +233,7 @@ precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ 
   for (int j = threadIdx.x; j < ne; j += blockDim.x) xs[j] = x[ext_slot[e0 + j]];
   __syncthreads();
   const cx<float> *R = Rt + r_off[c];
+  const int64_t ncp = rt_stride(nc);
   const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
   const int jb = (ne * q) / PA_Q, je = (ne * (q + 1)) / PA_Q;
   const int i = i0 + il;
@@ -243,14 +245,14 @@ precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ 
     for (; j + 4 <= je; j += 4) {
 #pragma unroll
       for (int u = 0; u < 4; u++) {
-        const cx<float> rv = R[(size_t)(j + u) * nc + i];
+        const cx<float> rv = R[(j + u) * ncp + i];
         const cx<double> xv = xs[j + u];
         pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
         pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
       }
     }
     for (; j < je; j++) {
-      const cx<float> rv = R[(size_t)j * nc + i];
+      const cx<float> rv = R[j * ncp + i];
       const cx<double> xv = xs[j];
       pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
       pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
@@ -274,6 +276,97 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
                           const cx<double> *x, cx<double> *y, hipStream_t s) {
   hipLaunchKernelGGL(precond_apply_kernel, dim3(n_items), dim3(PA_THREADS), 0, s, items, ext_ptr, ext_slot, core_ptr,
                      core_slot, r_off, Rt, x, y);
+}
+
+// Batched apply in single precision for the FP32 inner solves: nb <= 4
+// vectors per launch, their ext entries staged in LDS as FP32 (all lanes of a
+// wave read the same column: broadcast), each coefficient read once for all
+// of them, FP32 accumulation.  Inner solves stop at relative residuals of
+// 1e-5 or more and an FP64 refinement follows, so the rounding of x and of
+// the sums only perturbs the preconditioner, not the solution.
+constexpr int PA32_Q = 8;
+constexpr int PA32_THREADS = PA_ROWS * PA32_Q;
+template <int NB>
+__global__ void __launch_bounds__(PA32_THREADS)
+precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
+                       const int *__restrict__ ext_slot, const int64_t *__restrict__ core_ptr,
+                       const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
+                       const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y,
+                       int64_t N, int nb) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);   // [nb][ne]
+  __shared__ cx<float> red[PA32_Q][PA_ROWS][NB];
+  const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
+  const int64_t e0 = ext_ptr[c];
+  const int ne = (int)(ext_ptr[c + 1] - e0);
+  const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
+  for (int t = threadIdx.x; t < nb * ne; t += blockDim.x) {
+    const int b = t / ne, j = t - b * ne;
+    const cx<double> v = x[(size_t)b * N + ext_slot[e0 + j]];
+    xs[t] = {(float)v.x, (float)v.y};
+  }
+  __syncthreads();
+  const cx<float> *R = Rt + r_off[c];
+  const int64_t ncp = rt_stride(nc);
+  const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
+  const int jb = (ne * q) / PA32_Q, je = (ne * (q + 1)) / PA32_Q;
+  const int i = i0 + il;
+  cx<float> acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; b++) acc[b] = czero<float>();
+  if (i < nc) {
+    // eight coefficient loads in flight per thread
+    int j = jb;
+    for (; j + 8 <= je; j += 8) {
+      cx<float> rv[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) rv[u] = R[(j + u) * ncp + i];
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+          if (b < nb) acc[b] += rv[u] * xs[b * ne + j + u];
+    }
+    for (; j < je; j++) {
+      const cx<float> rv = R[j * ncp + i];
+#pragma unroll
+      for (int b = 0; b < NB; b++)
+        if (b < nb) acc[b] += rv * xs[b * ne + j];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; b++) red[q][il][b] = acc[b];
+  __syncthreads();
+  if (q == 0 && i < nc) {
+    const int slot = core_slot[core_ptr[c] + i];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      if (b >= nb) break;
+      cx<float> t = red[0][il][b];
+      for (int k = 1; k < PA32_Q; k++) t += red[k][il][b];
+      y[(size_t)b * N + slot] = {(double)t.x, (double)t.y};
+    }
+  }
+}
+
+int precond_apply32_max_batch() { return 4; }
+
+// m <= precond_apply32_max_batch() vectors; max_ext (largest extended set)
+// sizes the LDS staging
+void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off,
+                            const cx<float> *Rt, const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext,
+                            hipStream_t s) {
+  const size_t lds = sizeof(cx<float>) * (size_t)m * max_ext;
+  if (m == 1)
+    hipLaunchKernelGGL((precond_apply32_kernel<1>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
+                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+  else if (m == 2)
+    hipLaunchKernelGGL((precond_apply32_kernel<2>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
+                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+  else
+    hipLaunchKernelGGL((precond_apply32_kernel<4>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
+                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
 }
 
 }  // namespace scabs

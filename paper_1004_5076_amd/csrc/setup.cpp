@@ -503,7 +503,7 @@ std::string build_clusters(const Geometry &g, const Layout &L, double cell, doub
     cl.ext_ptr[c + 1] = cl.ext_ptr[c] + ne_c;
     cl.core_ptr[c + 1] = cl.core_ptr[c] + nc_c;
     cl.a_off[c + 1] = cl.a_off[c] + (int64_t)(ne_c * ne_c);
-    cl.r_off[c + 1] = cl.r_off[c] + (int64_t)(ne_c * nc_c);
+    cl.r_off[c + 1] = cl.r_off[c] + (int64_t)ne_c * rt_stride((int64_t)nc_c);
   }
   if (maxext > 2048) {
     *too_large = true;
