@@ -336,7 +336,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   const Layout &L = c->lay;
   hipStream_t s = c->stream;
   double cell = c->opts.pc_cell > 0 ? c->opts.pc_cell : 2.0 * c->opts.r_near;
-  double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 0.75 * c->opts.r_near;
+  double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 1.0 * c->opts.r_near;
   // boxes that would hold more unknowns than one work-group inverts shrink
   // the cell and overlap together until every cluster fits
   std::string e;
@@ -435,7 +435,7 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
   StageTimer tm(c, trans ? SCABS_STAGE_PRECOND_T : SCABS_STAGE_PRECOND);
   if (!trans)
     launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
-                         c->pc_r_off, c->pc_Rt, x, y, c->stream);
+                         c->pc_r_off, c->pc_Rt, x, y, c->pc_max_ext, c->stream);
   else
     launch_precond_apply_t(c->cl.nc, c->pc_n_ext, c->lay.N, c->pc_ext_ptr, c->pc_ext_cluster, c->pc_core_ptr,
                            c->pc_core_slot, c->pc_r_off, c->pc_Rt, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y,

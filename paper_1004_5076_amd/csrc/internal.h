@@ -91,7 +91,7 @@ std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std
                         std::vector<int> &anchor /* np*3 absolute */, std::vector<double> &u /* np*3 */);
 std::string build_near(const Geometry &g, double r_near, double kappa_s, NearList &nl);
 // Box clusters of side `cell` grown by `overlap`; sets *too_large when a
-// grown box holds more than 2048 unknowns.
+// grown box holds more than 4096 unknowns.
 std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl,
                            bool *too_large);
 void build_local_terms(const Geometry &g, const Layout &L, LocalTerms &lt);

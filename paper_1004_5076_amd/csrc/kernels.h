@@ -131,7 +131,7 @@ int precond_rows_per_item();
 // items: n_items pairs (cluster, first core row), rows per item as above
 void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
                           const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
-                          const cx<double> *x, cx<double> *y, hipStream_t s);
+                          const cx<double> *x, cx<double> *y, int max_ext, hipStream_t s);
 
 // FP32 batched apply (inner solves of the mixed mode): m vectors of N,
 // m <= precond_apply32_max_batch()

@@ -92,7 +92,7 @@ __global__ void block_assemble_kernel(PrecondArgs p) {
 // elimination with partial pivoting; the row interchanges are undone as
 // column interchanges at the end.  One work-group per cluster.
 constexpr int GJ_THREADS = 1024;
-constexpr int GJ_MAXN = 2048;
+constexpr int GJ_MAXN = 4096;   // largest cluster (extended set) the inversion handles
 
 __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ablocks, const int64_t *a_off,
                                                                   const int64_t *ext_ptr, int *piv_all, int *status) {
@@ -219,48 +219,51 @@ void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core
 constexpr int PA_ROWS = 64;
 constexpr int PA_Q = 4;
 constexpr int PA_THREADS = PA_ROWS * PA_Q;
+constexpr int PA_CW = 512;   // ext columns staged per pass
 __global__ void __launch_bounds__(PA_THREADS)
 precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                      const int *__restrict__ ext_slot, const int64_t *__restrict__ core_ptr,
                      const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
                      const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y) {
-  __shared__ cx<double> xs[GJ_MAXN];
+  __shared__ cx<double> xs[PA_CW];
   __shared__ cx<double> red[PA_Q][PA_ROWS];
   const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
-  for (int j = threadIdx.x; j < ne; j += blockDim.x) xs[j] = x[ext_slot[e0 + j]];
-  __syncthreads();
   const cx<float> *R = Rt + r_off[c];
   const int64_t ncp = rt_stride(nc);
   const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
-  const int jb = (ne * q) / PA_Q, je = (ne * (q + 1)) / PA_Q;
   const int i = i0 + il;
-  double ar = 0, ai = 0;
-  if (i < nc) {
-    // four independent partial sums keep several loads in flight
-    double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
-    int j = jb;
-    for (; j + 4 <= je; j += 4) {
+  // four independent partial sums keep several loads in flight
+  double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
+  for (int cb = 0; cb < ne; cb += PA_CW) {
+    const int cw = min(PA_CW, ne - cb);
+    __syncthreads();   // the previous pass is done with xs
+    for (int jj = threadIdx.x; jj < cw; jj += blockDim.x) xs[jj] = x[ext_slot[e0 + cb + jj]];
+    __syncthreads();
+    const int jb = (cw * q) / PA_Q, je = (cw * (q + 1)) / PA_Q;
+    if (i < nc) {
+      const cx<float> *Rc = R + (int64_t)cb * ncp + i;
+      int j = jb;
+      for (; j + 4 <= je; j += 4) {
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const cx<float> rv = R[(j + u) * ncp + i];
-        const cx<double> xv = xs[j + u];
-        pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-        pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
+        for (int u = 0; u < 4; u++) {
+          const cx<float> rv = Rc[(j + u) * ncp];
+          const cx<double> xv = xs[j + u];
+          pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
+          pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
+        }
+      }
+      for (; j < je; j++) {
+        const cx<float> rv = Rc[j * ncp];
+        const cx<double> xv = xs[j];
+        pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
+        pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
       }
     }
-    for (; j < je; j++) {
-      const cx<float> rv = R[j * ncp + i];
-      const cx<double> xv = xs[j];
-      pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-      pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
-    }
-    ar = (pr[0] + pr[1]) + (pr[2] + pr[3]);
-    ai = (pi[0] + pi[1]) + (pi[2] + pi[3]);
   }
-  red[q][il] = {ar, ai};
+  red[q][il] = {(pr[0] + pr[1]) + (pr[2] + pr[3]), (pi[0] + pi[1]) + (pi[2] + pi[3])};
   __syncthreads();
   if (q == 0 && i < nc) {
     cx<double> t = red[0][il];
@@ -273,7 +276,8 @@ int precond_rows_per_item() { return PA_ROWS; }
 
 void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
                           const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
-                          const cx<double> *x, cx<double> *y, hipStream_t s) {
+                          const cx<double> *x, cx<double> *y, int max_ext, hipStream_t s) {
+  (void)max_ext;
   hipLaunchKernelGGL(precond_apply_kernel, dim3(n_items), dim3(PA_THREADS), 0, s, items, ext_ptr, ext_slot, core_ptr,
                      core_slot, r_off, Rt, x, y);
 }
@@ -286,6 +290,7 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
 // the sums only perturbs the preconditioner, not the solution.
 constexpr int PA32_Q = 8;
 constexpr int PA32_THREADS = PA_ROWS * PA32_Q;
+constexpr int PA32_CW = 512;   // ext columns staged per pass
 template <int NB>
 __global__ void __launch_bounds__(PA32_THREADS)
 precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
@@ -293,45 +298,49 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
                        const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
                        const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y,
                        int64_t N, int nb) {
-  extern __shared__ unsigned char smem_raw[];
-  cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);   // [nb][ne]
+  __shared__ cx<float> xs[NB][PA32_CW];
   __shared__ cx<float> red[PA32_Q][PA_ROWS][NB];
   const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
-  for (int t = threadIdx.x; t < nb * ne; t += blockDim.x) {
-    const int b = t / ne, j = t - b * ne;
-    const cx<double> v = x[(size_t)b * N + ext_slot[e0 + j]];
-    xs[t] = {(float)v.x, (float)v.y};
-  }
-  __syncthreads();
   const cx<float> *R = Rt + r_off[c];
   const int64_t ncp = rt_stride(nc);
   const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
-  const int jb = (ne * q) / PA32_Q, je = (ne * (q + 1)) / PA32_Q;
   const int i = i0 + il;
   cx<float> acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; b++) acc[b] = czero<float>();
-  if (i < nc) {
-    // eight coefficient loads in flight per thread
-    int j = jb;
-    for (; j + 8 <= je; j += 8) {
-      cx<float> rv[8];
+  for (int cb = 0; cb < ne; cb += PA32_CW) {
+    const int cw = min(PA32_CW, ne - cb);
+    __syncthreads();   // the previous pass is done with xs
+    for (int t = threadIdx.x; t < nb * cw; t += blockDim.x) {
+      const int b = t / cw, jj = t - b * cw;
+      const cx<double> v = x[(size_t)b * N + ext_slot[e0 + cb + jj]];
+      xs[b][jj] = {(float)v.x, (float)v.y};
+    }
+    __syncthreads();
+    const int jb = (cw * q) / PA32_Q, je = (cw * (q + 1)) / PA32_Q;
+    if (i < nc) {
+      // eight coefficient loads in flight per thread
+      const cx<float> *Rc = R + (int64_t)cb * ncp + i;
+      int j = jb;
+      for (; j + 8 <= je; j += 8) {
+        cx<float> rv[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) rv[u] = R[(j + u) * ncp + i];
+        for (int u = 0; u < 8; u++) rv[u] = Rc[(j + u) * ncp];
 #pragma unroll
-      for (int u = 0; u < 8; u++)
+        for (int u = 0; u < 8; u++)
+#pragma unroll
+          for (int b = 0; b < NB; b++)
+            if (b < nb) acc[b] += rv[u] * xs[b][j + u];
+      }
+      for (; j < je; j++) {
+        const cx<float> rv = Rc[j * ncp];
 #pragma unroll
         for (int b = 0; b < NB; b++)
-          if (b < nb) acc[b] += rv[u] * xs[b * ne + j + u];
-    }
-    for (; j < je; j++) {
-      const cx<float> rv = R[j * ncp + i];
-#pragma unroll
-      for (int b = 0; b < NB; b++)
-        if (b < nb) acc[b] += rv * xs[b * ne + j];
+          if (b < nb) acc[b] += rv * xs[b][j];
+      }
     }
   }
 #pragma unroll
@@ -357,7 +366,8 @@ void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_pt
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off,
                             const cx<float> *Rt, const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext,
                             hipStream_t s) {
-  const size_t lds = sizeof(cx<float>) * (size_t)m * max_ext;
+  const size_t lds = 0;
+  (void)max_ext;
   if (m == 1)
     hipLaunchKernelGGL((precond_apply32_kernel<1>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
                        core_ptr, core_slot, r_off, Rt, x, y, N, m);

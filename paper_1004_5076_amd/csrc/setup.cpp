@@ -505,9 +505,9 @@ std::string build_clusters(const Geometry &g, const Layout &L, double cell, doub
     cl.a_off[c + 1] = cl.a_off[c] + (int64_t)(ne_c * ne_c);
     cl.r_off[c + 1] = cl.r_off[c] + (int64_t)ne_c * rt_stride((int64_t)nc_c);
   }
-  if (maxext > 2048) {
+  if (maxext > 4096) {
     *too_large = true;
-    return "preconditioner cluster too large (> 2048 unknowns); reduce the cell size";
+    return "preconditioner cluster too large (> 4096 unknowns); reduce the cell size";
   }
   cl.ext_slot.resize(cl.ext_ptr[cl.nc]);
   cl.core_pos.resize(cl.core_ptr[cl.nc]);
