@@ -413,7 +413,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   p.ext_ptr = c->pc_ext_ptr;
   p.ext_slot = c->pc_ext_slot;
   p.a_off = tmp.upload(cl.a_off);
-  p.A = tmp.alloc<cx<double>>((size_t)cl.a_off[cl.nc]);
+  p.A = tmp.alloc<cx<float>>((size_t)cl.a_off[cl.nc]);
   int *core_pos = tmp.upload(cl.core_pos);
   int *piv = tmp.alloc<int>((size_t)cl.ext_ptr[cl.nc]);
   int *status = tmp.alloc<int>(1);

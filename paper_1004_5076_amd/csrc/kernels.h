@@ -120,7 +120,7 @@ struct PrecondArgs {
   const int64_t *ext_ptr;
   const int *ext_slot;
   const int64_t *a_off;
-  cx<double> *A;             // dense cluster blocks
+  cx<float> *A;              // dense cluster blocks (FP32)
 };
 void launch_exact_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
                            const cx<double> *blocks, cx<double> *X8, hipStream_t s);

@@ -76,50 +76,54 @@ __device__ cx<double> near_entry(const PrecondArgs &p, int a, int b) {
   return cc == 0 ? cJe - cJi : cM;
 }
 
+// Dense cluster blocks, assembled in FP64 and stored in FP32 for the
+// inversion (the preconditioner only needs an approximate inverse; its rows
+// are kept in FP32 anyway).
 __global__ void block_assemble_kernel(PrecondArgs p) {
   const int c = blockIdx.y;
   const int64_t e0 = p.ext_ptr[c];
   const int ne = (int)(p.ext_ptr[c + 1] - e0);
-  cx<double> *A = p.A + p.a_off[c];
+  cx<float> *A = p.A + p.a_off[c];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)ne * ne;
        i += (int64_t)gridDim.x * blockDim.x) {
     int a = (int)(i / ne), b = (int)(i - (int64_t)a * ne);
-    A[i] = near_entry(p, p.ext_slot[e0 + a], p.ext_slot[e0 + b]);
+    const cx<double> v = near_entry(p, p.ext_slot[e0 + a], p.ext_slot[e0 + b]);
+    A[i] = {(float)v.x, (float)v.y};
   }
 }
 
-// In-place inverse of each cluster block (row-major n x n) by Gauss-Jordan
-// elimination with partial pivoting; the row interchanges are undone as
-// column interchanges at the end.  One work-group per cluster.
+// In-place inverse of each cluster block (row-major n x n, FP32) by
+// Gauss-Jordan elimination with partial pivoting; the row interchanges are
+// undone as column interchanges at the end.  One work-group per cluster.
 constexpr int GJ_THREADS = 1024;
 constexpr int GJ_MAXN = 4096;   // largest cluster (extended set) the inversion handles
 
-__global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ablocks, const int64_t *a_off,
+__global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<float> *Ablocks, const int64_t *a_off,
                                                                   const int64_t *ext_ptr, int *piv_all, int *status) {
   const int c = blockIdx.x;
   const int n = (int)(ext_ptr[c + 1] - ext_ptr[c]);
-  cx<double> *A = Ablocks + a_off[c];
+  cx<float> *A = Ablocks + a_off[c];
   int *piv = piv_all + ext_ptr[c];
-  __shared__ cx<double> rowk[GJ_MAXN];
-  __shared__ cx<double> colk[GJ_MAXN];
-  __shared__ double red_v[GJ_THREADS / 64];
+  __shared__ cx<float> rowk[GJ_MAXN];
+  __shared__ cx<float> colk[GJ_MAXN];
+  __shared__ float red_v[GJ_THREADS / 64];
   __shared__ int red_i[GJ_THREADS / 64];
   __shared__ int s_p;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = GJ_THREADS / 64;
   for (int k = 0; k < n; k++) {
     // pivot: largest |A[i][k]|, i >= k
-    double best = -1.0;
+    float best = -1.0f;
     int bi = k;
     for (int i = k + tid; i < n; i += blockDim.x) {
-      cx<double> v = A[(size_t)i * n + k];
-      double m = v.x * v.x + v.y * v.y;
+      cx<float> v = A[(size_t)i * n + k];
+      float m = v.x * v.x + v.y * v.y;
       if (m > best) {
         best = m;
         bi = i;
       }
     }
     for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(best, o, 64);
+      float ov = __shfl_xor(best, o, 64);
       int oi = __shfl_xor(bi, o, 64);
       if (ov > best || (ov == best && oi < bi)) {
         best = ov;
@@ -132,9 +136,9 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ab
     }
     __syncthreads();
     if (tid == 0) {
-      double bv = red_v[0];
+      float bv = red_v[0];
       int bb = red_i[0];
-      for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+      for (int w = 1; w < nw; w++)
         if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bb)) {
           bv = red_v[w];
           bb = red_i[w];
@@ -147,30 +151,33 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ab
     const int pr = s_p;
     if (pr != k)
       for (int j = tid; j < n; j += blockDim.x) {
-        cx<double> t = A[(size_t)k * n + j];
+        cx<float> t = A[(size_t)k * n + j];
         A[(size_t)k * n + j] = A[(size_t)pr * n + j];
         A[(size_t)pr * n + j] = t;
       }
     __syncthreads();
     // pivot row scaled by 1/d, pivot column saved
-    const cx<double> d = A[(size_t)k * n + k];
-    const double dn = d.x * d.x + d.y * d.y;
-    const cx<double> inv = dn > 0 ? cx<double>{d.x / dn, -d.y / dn} : cx<double>{0.0, 0.0};
+    const cx<float> d = A[(size_t)k * n + k];
+    const float dn = d.x * d.x + d.y * d.y;
+    const cx<float> inv = dn > 0 ? cx<float>{d.x / dn, -d.y / dn} : cx<float>{0.0f, 0.0f};
     for (int j = tid; j < n; j += blockDim.x) {
-      cx<double> v = j == k ? cx<double>{1.0, 0.0} : A[(size_t)k * n + j];
+      cx<float> v = j == k ? cx<float>{1.0f, 0.0f} : A[(size_t)k * n + j];
       rowk[j] = v * inv;
       colk[j] = A[(size_t)j * n + k];
     }
     __syncthreads();
     for (int j = tid; j < n; j += blockDim.x) A[(size_t)k * n + j] = rowk[j];
-    for (int64_t idx = tid; idx < (int64_t)n * n; idx += blockDim.x) {
-      const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    // every other row: one wave per row, lanes along the (contiguous) columns
+    for (int i = wid; i < n; i += nw) {
       if (i == k) continue;
-      const cx<double> f = colk[i];
-      if (j == k)
-        A[idx] = -(f * inv);
-      else
-        A[idx] -= f * rowk[j];
+      const cx<float> f = colk[i];
+      cx<float> *Ai = A + (size_t)i * n;
+      for (int j = lane; j < n; j += 64) {
+        if (j == k)
+          Ai[j] = -(f * inv);
+        else
+          Ai[j] -= f * rowk[j];
+      }
     }
     __syncthreads();
   }
@@ -179,7 +186,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ab
     const int pr = piv[k];
     if (pr != k)
       for (int i = tid; i < n; i += blockDim.x) {
-        cx<double> t = A[(size_t)i * n + k];
+        cx<float> t = A[(size_t)i * n + k];
         A[(size_t)i * n + k] = A[(size_t)i * n + pr];
         A[(size_t)i * n + pr] = t;
       }
@@ -189,17 +196,16 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<double> *Ab
 
 // Rt[j][i] = inverse[core_pos[i]][j], FP32 (column-major over the core rows,
 // column stride rt_stride(nc))
-__global__ void extract_kernel(const cx<double> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr,
+__global__ void extract_kernel(const cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr,
                                const int64_t *core_ptr, const int *core_pos, const int64_t *r_off, cx<float> *Rt) {
   const int c = blockIdx.y;
   const int ne = (int)(ext_ptr[c + 1] - ext_ptr[c]);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const cx<double> *A = Ablocks + a_off[c];
+  const cx<float> *A = Ablocks + a_off[c];
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)ne * nc;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(idx / nc), i = (int)(idx - (int64_t)j * nc);
-    const cx<double> v = A[(size_t)core_pos[core_ptr[c] + i] * ne + j];
-    Rt[r_off[c] + (int64_t)j * rt_stride(nc) + i] = {(float)v.x, (float)v.y};
+    Rt[r_off[c] + (int64_t)j * rt_stride(nc) + i] = A[(size_t)core_pos[core_ptr[c] + i] * ne + j];
   }
 }
 
@@ -208,7 +214,7 @@ void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core
   (void)max_ext;
   hipLaunchKernelGGL(block_assemble_kernel, dim3(64, p.nc), dim3(256), 0, s, p);
   hipLaunchKernelGGL(gauss_jordan_kernel, dim3(p.nc), dim3(GJ_THREADS), 0, s, p.A, p.a_off, p.ext_ptr, piv, status);
-  hipLaunchKernelGGL(extract_kernel, dim3(32, p.nc), dim3(256), 0, s, (const cx<double> *)p.A, p.a_off, p.ext_ptr,
+  hipLaunchKernelGGL(extract_kernel, dim3(32, p.nc), dim3(256), 0, s, (const cx<float> *)p.A, p.a_off, p.ext_ptr,
                      core_ptr, core_pos, r_off, Rt);
 }
 
