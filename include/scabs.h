@@ -138,7 +138,8 @@ int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
 /* Solve A x = b (device vectors, nrhs of them).  x holds the initial guess
  * on entry.  mode: SCABS_FP64 (restarted GMRES on the FP64 operator) or
  * SCABS_MIXED (FP64 refinement around FP32-operator GMRES).  Orthogonalisation
- * (two-pass classical Gram-Schmidt) and the Hessenberg least squares are FP64;
+ * (classical Gram-Schmidt, repeated where the first pass lost more than
+ * 1 - 1/sqrt(2) of the norm) and the Hessenberg least squares are FP64;
  * the preconditioner (if enabled) is applied on the right.
  * tol: relative residual with the FP64 operator.  info may be NULL.
  * Returns SCABS_E_NOCONV (x holds the last iterate) if max_iter Arnoldi

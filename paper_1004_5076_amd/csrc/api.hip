@@ -758,10 +758,12 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
 }
 
 // ---------------------------------------------------------------------------
-// GMRES on a batch of right-hand sides (restarted; two-pass classical
-// Gram-Schmidt and Givens rotations in FP64).  The nb systems step together:
-// one batched preconditioner + product per Arnoldi step, per-system
-// orthogonalisation, one host synchronisation per step for all of them.
+// GMRES on a batch of right-hand sides (restarted; classical Gram-Schmidt
+// with a second pass where the first lost more than 1 - 1/sqrt(2) of the
+// vector's norm, Givens rotations, all in FP64).  The nb systems step
+// together: one batched preconditioner + product per Arnoldi step,
+// per-system orthogonalisation, one host synchronisation per step for all of
+// them (two when a system needs the second pass).
 // ---------------------------------------------------------------------------
 static void ensure_work(scabs_ctx *c, int restart, int nb) {
   int64_t N = c->lay.N;
@@ -775,7 +777,7 @@ static void ensure_work(scabs_ctx *c, int restart, int nb) {
   c->t = c->work.alloc<cx<double>>(N * nb);
   c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2) * nb);
   c->part = c->work.alloc<cx<double>>((size_t)256 * (restart + 2));
-  c->nrm = c->work.alloc<double>(nb + 4);
+  c->nrm = c->work.alloc<double>(2 * nb + 4);
   c->nrm_part = c->work.alloc<double>(1024);
   c->flag = c->work.alloc<int>(1);
   c->work_restart = restart;
@@ -809,7 +811,8 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
   res.assign(nb, GmresResult());
   HIPCHK(hipMemsetAsync(sol, 0, sizeof(cx<double>) * N * nb, s));
   HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N * nb, hipMemcpyDeviceToDevice, s));
-  std::vector<double> bn(nb), beta(nb), hn(nb);
+  std::vector<double> bn(nb), beta(nb), hn(2 * nb);
+  std::vector<int> reo2(nb, 0);
   dev_norms(c, rhs, nb, bn.data());
   beta = bn;
   std::vector<std::vector<zd>> H(nb, std::vector<zd>((size_t)(m + 1) * m)), g(nb, std::vector<zd>(m + 1)),
@@ -845,28 +848,54 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
       }
       nmv += (int)run.size();
+      // classical Gram-Schmidt, repeated only where it lost too much of w
+      // (Daniel-Gragg-Kaufman-Stewart test ||w1|| < ||w|| / sqrt(2))
       {
         StageTimer tm(c, SCABS_STAGE_ORTHO);
         for (int b : run) {
-          cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
+          cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b;
           cx<double> *wb = c->w + b * N;
           const cx<double> *Vb = c->V + b * N;
+          kr_norm(wb, N, c->nrm_part, c->nrm + nb + b, s);
           kr_dots(Vb, ldv, j + 1, wb, N, c->part, h1, 0, s);
           kr_update(wb, Vb, ldv, j + 1, h1, N, -1.0, s);
-          kr_dots(Vb, ldv, j + 1, wb, N, c->part, h2, 0, s);
-          kr_update(wb, Vb, ldv, j + 1, h2, N, -1.0, s);
           kr_norm(wb, N, c->nrm_part, c->nrm + b, s);
-          kr_scale(c->V + (size_t)(j + 1) * ldv + b * N, wb, c->nrm + b, N, s);
         }
       }
       HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      std::vector<int> reo;
+      for (int b : run) {
+        reo2[b] = 0;
+        if (hn[b] < 0.7071067811865476 * hn[nb + b]) reo.push_back(b);
+      }
+      if (!reo.empty()) {
+        StageTimer tm(c, SCABS_STAGE_ORTHO);
+        for (int b : reo) {
+          cx<double> *h2 = c->hcol + 2 * (size_t)(m + 2) * b + (m + 2);
+          cx<double> *wb = c->w + b * N;
+          const cx<double> *Vb = c->V + b * N;
+          kr_dots(Vb, ldv, j + 1, wb, N, c->part, h2, 0, s);
+          kr_update(wb, Vb, ldv, j + 1, h2, N, -1.0, s);
+          kr_norm(wb, N, c->nrm_part, c->nrm + b, s);
+          reo2[b] = 1;
+        }
+        std::vector<cx<double>> hb2(hb.size());
+        HIPCHK(hipMemcpyAsync(hb2.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int b : reo)
+          std::copy(hb2.begin() + 2 * (size_t)(m + 2) * b + (m + 2), hb2.begin() + 2 * (size_t)(m + 2) * (b + 1),
+                    hb.begin() + 2 * (size_t)(m + 2) * b + (m + 2));
+      }
+      for (int b : run) kr_scale(c->V + (size_t)(j + 1) * ldv + b * N, c->w + b * N, c->nrm + b, N, s);
       std::vector<int> next;
       for (int b : run) {
         const cx<double> *h1 = hb.data() + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
         zd *col = &H[b][(size_t)j * (m + 1)];
-        for (int i = 0; i <= j; i++) col[i] = zd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+        for (int i = 0; i <= j; i++)
+          col[i] = reo2[b] ? zd(h1[i].x + h2[i].x, h1[i].y + h2[i].y) : zd(h1[i].x, h1[i].y);
         col[j + 1] = hn[b];
         for (int i = 0; i < j; i++) {
           zd a = col[i], bb = col[i + 1];
