@@ -197,4 +197,106 @@ __device__ void lds_fft_mr(cx<T> *buf, int L, int nlines, int nin, int lso, int 
   }
 }
 
+// Wave-owned variant: the lines [0, nlines) are split into contiguous groups,
+// one per wave of the work-group; each wave runs every stage on its own group
+// with only wave-level ordering between stages (no work-group barrier).  The
+// caller synchronises the work-group before (data loaded) and after (data
+// consumed by other waves).  Requires ceil(nlines / waves) * L <= ELEMS * 64.
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int R, int NB>
+__device__ inline void stockham_stage_w(cx<T> *buf, int L, int l0, int l1, int nin, int lso, int lsi, int es, int Ns,
+                                        const cx<T> *tw, int twL, bool inv, int lane) {
+  const int LR = L / R;
+  const int nb = (l1 - l0) * LR;
+  const FastDiv dLR = make_fastdiv(LR), dnin = make_fastdiv(nin), dNs = make_fastdiv(Ns);
+  const int tstep = twL / (Ns * R);
+  cx<T> v[NB][R];
+  int ob[NB];
+#pragma unroll
+  for (int c = 0; c < NB; c++) {
+    const int b = lane + c * 64;
+    if (b < nb) {
+      const int lr = fdiv(b, dLR), j = b - lr * LR;
+      const int line = l0 + lr;
+      const int lo = fdiv(line, dnin);
+      const int base = lo * lso + (line - lo * nin) * lsi;
+      const int k = j - fdiv(j, dNs) * Ns;
+#pragma unroll
+      for (int r = 0; r < R; r++) v[c][r] = buf[lpad<T>(base + (j + r * LR) * es)];
+      if (k) {
+        const int step = tstep * k;
+#pragma unroll
+        for (int r = 1; r < R; r++) {
+          cx<T> w = tw[r * step];
+          if (inv) w.y = -w.y;
+          v[c][r] = v[c][r] * w;
+        }
+      }
+      dft_small<T, R>(v[c], inv);
+      ob[c] = base + ((j - k) * R + k) * es;
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int c = 0; c < NB; c++) {
+    const int b = lane + c * 64;
+    if (b < nb) {
+#pragma unroll
+      for (int r = 0; r < R; r++) buf[lpad<T>(ob[c] + r * Ns * es)] = v[c][r];
+    }
+  }
+  wave_lds_fence();
+}
+
+template <typename T, int ELEMS>
+__device__ void lds_fft_wave(cx<T> *buf, int L, int nlines, int nin, int lso, int lsi, int es, const cx<T> *tw,
+                             int twL, bool inv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int G = (nlines + nw - 1) / nw;
+  const int l0 = min(nlines, wave * G), l1 = min(nlines, l0 + G);
+  int m = L, Ns = 1;
+  while (m > 1) {
+    if (m % 8 == 0) {
+      stockham_stage_w<T, 8, (ELEMS + 7) / 8>(buf, L, l0, l1, nin, lso, lsi, es, Ns, tw, twL, inv, lane);
+      m /= 8;
+      Ns *= 8;
+    } else if (m % 4 == 0) {
+      stockham_stage_w<T, 4, (ELEMS + 3) / 4>(buf, L, l0, l1, nin, lso, lsi, es, Ns, tw, twL, inv, lane);
+      m /= 4;
+      Ns *= 4;
+    } else if (m % 2 == 0) {
+      stockham_stage_w<T, 2, (ELEMS + 1) / 2>(buf, L, l0, l1, nin, lso, lsi, es, Ns, tw, twL, inv, lane);
+      m /= 2;
+      Ns *= 2;
+    } else {
+      stockham_stage_w<T, 3, (ELEMS + 2) / 3>(buf, L, l0, l1, nin, lso, lsi, es, Ns, tw, twL, inv, lane);
+      m /= 3;
+      Ns *= 3;
+    }
+  }
+}
+
+// Transforms of nlines lines: wave-owned (WAVE, the caller guarantees a
+// wave's share fits EW elements per lane) or work-group-wide; the data is
+// visible to the whole work-group on return.
+template <typename T, int ELEMS, int EW, bool WAVE>
+__device__ inline void lds_fft(cx<T> *buf, int L, int nlines, int nin, int lso, int lsi, int es, const cx<T> *tw,
+                               int twL, bool inv) {
+  if (WAVE) {
+    lds_fft_wave<T, EW>(buf, L, nlines, nin, lso, lsi, es, tw, twL, inv);
+    __syncthreads();
+  } else {
+    lds_fft_mr<T, ELEMS>(buf, L, nlines, nin, lso, lsi, es, tw, twL, inv);
+  }
+}
+// whether nlines lines of length L split over nw waves fit EW elements per lane
+__host__ __device__ inline bool wave_fits(int L, int nlines, int nw, int EW) {
+  return ((nlines + nw - 1) / nw) * L <= EW * 64;
+}
+
 }  // namespace scabs

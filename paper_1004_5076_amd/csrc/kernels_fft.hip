@@ -11,20 +11,24 @@
 namespace scabs {
 
 constexpr size_t LDS_BUDGET = 64 * 1024;
-// threads per work-group and elements per thread held in registers by one
-// Stockham stage (measured: 256 x 32 for FP32, 512 x 8 for FP64)
+// threads per work-group, elements per thread held in registers by one
+// work-group-wide Stockham stage, elements per lane of a wave-owned pass,
+// minimum waves per SIMD (occupancy), and whether wave-owned passes are used
+// (measured: wave-owned at 4 waves per SIMD for FP32, work-group-wide for FP64)
 template <typename T> struct FftCfg {
-  static constexpr int threads = 256, elems = 32;
+  static constexpr int threads = 512, elems = 16, wave_elems = 16, min_waves = 4;
+  static constexpr bool wave = true;
 };
 template <> struct FftCfg<double> {
-  static constexpr int threads = 512, elems = 8;
+  static constexpr int threads = 512, elems = 8, wave_elems = 16, min_waves = 4;
+  static constexpr bool wave = false;
 };
 
 // P consecutive x planes of one field per work-group: y-z transforms.
 // Forward: physical n1 x n2 plane -> zero-padded N1 x N2 spectrum (z lines
 // with data first, then every y line).  Inverse: the reverse, keeping n1 x n2.
-template <typename T>
-__global__ void __launch_bounds__(FftCfg<T>::threads)
+template <typename T, bool WAVE>
+__global__ void __launch_bounds__(FftCfg<T>::threads, FftCfg<T>::min_waves)
 plane_fwd_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n0, int n1, int n2, int N1, int N2,
                  int P, const cx<T> *__restrict__ tw, int twL) {
   extern __shared__ unsigned char smem_raw[];
@@ -39,14 +43,14 @@ plane_fwd_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n
     buf[lpad<T>(i)] = (y < n1 && z < n2) ? src[(size_t)pl * n1 * n2 + y * n2 + z] : czero<T>();
   }
   __syncthreads();
-  lds_fft_mr<T, FftCfg<T>::elems>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, false);   // z lines with data
-  lds_fft_mr<T, FftCfg<T>::elems>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, false);   // y lines
+  lds_fft<T, FftCfg<T>::elems, FftCfg<T>::wave_elems, WAVE>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, false);   // z lines with data
+  lds_fft<T, FftCfg<T>::elems, FftCfg<T>::wave_elems, WAVE>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, false);   // y lines
   cx<T> *dst = spec + ((size_t)f * n0 + x0) * M;
   for (int i = threadIdx.x; i < np * M; i += blockDim.x) dst[i] = buf[lpad<T>(i)];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(FftCfg<T>::threads)
+template <typename T, bool WAVE>
+__global__ void __launch_bounds__(FftCfg<T>::threads, FftCfg<T>::min_waves)
 plane_inv_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n0, int n1, int n2, int N1, int N2,
                  int P, const cx<T> *__restrict__ tw, int twL) {
   extern __shared__ unsigned char smem_raw[];
@@ -57,8 +61,8 @@ plane_inv_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n
   const cx<T> *src = spec + ((size_t)f * n0 + x0) * M;
   for (int i = threadIdx.x; i < np * M; i += blockDim.x) buf[lpad<T>(i)] = src[i];
   __syncthreads();
-  lds_fft_mr<T, FftCfg<T>::elems>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, true);    // y lines
-  lds_fft_mr<T, FftCfg<T>::elems>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, true);    // z lines that are kept
+  lds_fft<T, FftCfg<T>::elems, FftCfg<T>::wave_elems, WAVE>(buf, N1, np * N2, N2, M, 1, N2, tw, twL, true);    // y lines
+  lds_fft<T, FftCfg<T>::elems, FftCfg<T>::wave_elems, WAVE>(buf, N2, np * n1, n1, M, N2, 1, tw, twL, true);    // z lines that are kept
   cx<T> *dst = phys + ((size_t)f * n0 + x0) * n1 * n2;
   const FastDiv dP = make_fastdiv(n1 * n2), dn2 = make_fastdiv(n2);
   for (int i = threadIdx.x; i < np * n1 * n2; i += blockDim.x) {
@@ -69,8 +73,8 @@ plane_inv_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n
 
 // mode 0: forward x FFT, product with ghat, inverse; x < n0 kept.
 // mode 1: forward x FFT only over the full length (n0 == N0).
-template <typename T>
-__global__ void __launch_bounds__(FftCfg<T>::threads)
+template <typename T, bool WAVE>
+__global__ void __launch_bounds__(FftCfg<T>::threads, FftCfg<T>::min_waves)
 xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, const cx<T> *__restrict__ ghat,
              const cx<T> *__restrict__ tw, int twL, int mode) {
   extern __shared__ unsigned char smem_raw[];
@@ -86,7 +90,7 @@ xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, co
     buf[lpad<T>(c * LS + x)] = x < n0 ? base[(size_t)x * M + b0 + c] : czero<T>();
   }
   __syncthreads();
-  lds_fft_mr<T, FftCfg<T>::elems>(buf, N0, nl, 1, LS, 0, 1, tw, twL, false);
+  lds_fft<T, FftCfg<T>::elems, FftCfg<T>::wave_elems, WAVE>(buf, N0, nl, 1, LS, 0, 1, tw, twL, false);
   if (mode == 0) {
     const int h1 = N1 / 2 + 1, h2 = N2 / 2 + 1;
     for (int i = threadIdx.x; i < nl * N0; i += blockDim.x) {
@@ -98,7 +102,7 @@ xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, co
       buf[a] = buf[a] * ghat[((size_t)ax * h1 + ay) * h2 + az];
     }
     __syncthreads();
-    lds_fft_mr<T, FftCfg<T>::elems>(buf, N0, nl, 1, LS, 0, 1, tw, twL, true);
+    lds_fft<T, FftCfg<T>::elems, FftCfg<T>::wave_elems, WAVE>(buf, N0, nl, 1, LS, 0, 1, tw, twL, true);
   }
   for (int i = threadIdx.x; i < nl * n0; i += blockDim.x) {
     const int x = fdiv(i, dnl), c = i - x * nl;
@@ -124,14 +128,29 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
   const int P = planes_per_group<T>(N1, N2);
   const size_t plane_lds = sizeof(cx<T>) * (size_t)lpad_size<T>(P * N1 * N2);
   const int npg = (n0 + P - 1) / P;
-  hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.phys, g.spec, n0, n1, n2, N1,
-                     N2, P, g.tw, g.twL);
+  const int nw = FftCfg<T>::threads / 64, EW = FftCfg<T>::wave_elems;
+  // wave-owned passes measured faster in FP32 only (FP64 needs too many registers)
+  const bool pw = FftCfg<T>::wave && wave_fits(N2, P * n1, nw, EW) && wave_fits(N1, P * N2, nw, EW);
+  if (pw)
+    hipLaunchKernelGGL((plane_fwd_kernel<T, true>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.phys,
+                       g.spec, n0, n1, n2, N1, N2, P, g.tw, g.twL);
+  else
+    hipLaunchKernelGGL((plane_fwd_kernel<T, false>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.phys,
+                       g.spec, n0, n1, n2, N1, N2, P, g.tw, g.twL);
   const int C = xline_lines<T>(N0);
   const int nlb = (N1 * N2 + C - 1) / C;
-  hipLaunchKernelGGL(xline_kernel<T>, dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s, g.spec, n0, N0, N1, N2,
-                     C, g.ghat, g.tw, g.twL, 0);
-  hipLaunchKernelGGL(plane_inv_kernel<T>, dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.spec, g.phys, n0, n1, n2, N1,
-                     N2, P, g.tw, g.twL);
+  if (FftCfg<T>::wave && wave_fits(N0, C, nw, EW))
+    hipLaunchKernelGGL((xline_kernel<T, true>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
+                       g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
+  else
+    hipLaunchKernelGGL((xline_kernel<T, false>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
+                       g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
+  if (pw)
+    hipLaunchKernelGGL((plane_inv_kernel<T, true>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.spec,
+                       g.phys, n0, n1, n2, N1, N2, P, g.tw, g.twL);
+  else
+    hipLaunchKernelGGL((plane_inv_kernel<T, false>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.spec,
+                       g.phys, n0, n1, n2, N1, N2, P, g.tw, g.twL);
 }
 template void launch_conv<float>(const DevGrid<float> &, hipStream_t, int);
 template void launch_conv<double>(const DevGrid<double> &, hipStream_t, int);
@@ -186,11 +205,11 @@ hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int t
   // forward 3-D FFT: y-z planes (full), then x lines (full length); one field
   const int P = planes_per_group<double>(N1, N2);
   const size_t plane_lds = sizeof(cx<double>) * (size_t)lpad_size<double>(P * N1 * N2);
-  hipLaunchKernelGGL(plane_fwd_kernel<double>, dim3((N0 + P - 1) / P, 1), dim3(FftCfg<double>::threads), plane_lds, s, full, spec,
+  hipLaunchKernelGGL((plane_fwd_kernel<double, false>), dim3((N0 + P - 1) / P, 1), dim3(FftCfg<double>::threads), plane_lds, s, full, spec,
                      N0, N1, N2, N1, N2, P, tw64, twL);
   int C = xline_lines<double>(N0);
   int nb = (N1 * N2 + C - 1) / C;
-  hipLaunchKernelGGL(xline_kernel<double>, dim3(nb, 1), dim3(FftCfg<double>::threads), xline_lds<double>(N0, C), s, spec, N0, N0, N1,
+  hipLaunchKernelGGL((xline_kernel<double, false>), dim3(nb, 1), dim3(FftCfg<double>::threads), xline_lds<double>(N0, C), s, spec, N0, N0, N1,
                      N2, C, (const cx<double> *)nullptr, tw64, twL, 1);
   hipLaunchKernelGGL(extract_octant, dim3(256), dim3(256), 0, s, spec, ghat64, ghat32, N0, N1, N2);
   e = hipGetLastError();
