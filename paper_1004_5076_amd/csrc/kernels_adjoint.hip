@@ -137,11 +137,15 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
   __shared__ T s_u[3][CH];
   extern __shared__ unsigned char smem_raw[];
   cx<T> *s_red = reinterpret_cast<cx<T> *>(smem_raw);   // 3 * plane
+  int *s_cell = reinterpret_cast<int *>(s_red + 3 * dg.n[1] * dg.n[2]);   // cell starts of planes x-1..x+1
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   const int x = blockIdx.x;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
   const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
+  // cell pointers of the (up to) three planes, relative to P0, staged once
+  const int ncl = (xh - xl + 1) * plane;
+  for (int t = threadIdx.x; t <= ncl; t += blockDim.x) s_cell[t] = (int)(g.cellptr[(int64_t)xl * plane + t] - P0);
   const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane);
   cx<T> acc[MAXI][8];
 #pragma unroll
@@ -151,6 +155,7 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
   for (int64_t c0 = P0; c0 < P1; c0 += CH) {
     const int64_t c1 = min(c0 + (int64_t)CH, P1);
     const int cn = (int)(c1 - c0);
+    const int cr0 = (int)(c0 - P0), cr1 = (int)(c1 - P0);
     for (int i = threadIdx.x; i < cn * 32; i += blockDim.x) {
       const int lp = i >> 5, f = i & 31;
       s_src[f][lp] = src4[(size_t)32 * c0 + i];
@@ -172,13 +177,13 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
       for (int dy = -1; dy <= 1; dy++) {
         const int ay = y + dy;
         if (ay < 0 || ay >= n1) continue;
-        const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
+        const int rowc = ((ax - xl) * n1 + ay) * n2;
         for (int dz = -1; dz <= 1; dz++) {
           const int az = z + dz;
           if (az < 0 || az >= n2) continue;
-          const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
-          for (int64_t p = p0; p < p1; p++) {
-            const int lp = (int)(p - c0);
+          const int p0 = max(s_cell[rowc + az], cr0), p1 = min(s_cell[rowc + az + 1], cr1);
+          for (int p = p0; p < p1; p++) {
+            const int lp = p - cr0;
             T Lx, Ly, Lz, dLx, dLy, dLz;
             lagr_pick(-dx, s_u[0][lp], Lx, dLx);
             lagr_pick(-dy, s_u[1][lp], Ly, dLy);
@@ -225,7 +230,7 @@ void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grid
     const int items = 3 * plane;
     const int threads = std::min(1024, (items + 63) / 64 * 64);
     const int maxi = (items + threads - 1) / threads;
-    const size_t lds = sizeof(cx<T>) * (size_t)items;
+    const size_t lds = sizeof(cx<T>) * (size_t)items + sizeof(int) * (size_t)(items + 1);
     if (maxi == 1)
       hipLaunchKernelGGL((gather_adj_kernel<T, 1>), dim3(grids[k].n[0]), dim3(threads), lds, s, grids[k], gg[k],
                          src4[k], inv_h);

@@ -92,8 +92,8 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
 // lanes reading different points hit different banks; each item sums the
 // points of its 9 cells (x+dx, y+dy, z+dz) that fall in the chunk, and the
 // three dx partials of a node are added in LDS at the end, field by field.
-// points per staged chunk (measured: 1024 for FP32, 512 for FP64)
-template <typename T> struct GaChunk { static constexpr int value = 1024; };
+// points per staged chunk (measured; FP32 sized so two work-groups fit in LDS)
+template <typename T> struct GaChunk { static constexpr int value = 960; };
 template <> struct GaChunk<double> { static constexpr int value = 512; };
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
   __shared__ T s_u[3][GA_CHUNK];
   extern __shared__ unsigned char smem_raw[];
   cx<T> *s_red = reinterpret_cast<cx<T> *>(smem_raw);   // 3 * plane
+  int *s_cell = reinterpret_cast<int *>(s_red + 3 * dg.n[1] * dg.n[2]);   // cell starts of planes x-1..x+1
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   const int x = blockIdx.x;
@@ -110,6 +111,9 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
   cx<T> *phys = dg.phys + (size_t)8 * g.ncell * blockIdx.y;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
   const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
+  // cell pointers of the (up to) three planes, relative to P0, staged once
+  const int ncl = (xh - xl + 1) * plane;
+  for (int t = threadIdx.x; t <= ncl; t += blockDim.x) s_cell[t] = (int)(g.cellptr[(int64_t)xl * plane + t] - P0);
   const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane);
   cx<T> acc[MAXI][8];
 #pragma unroll
@@ -119,6 +123,7 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
   for (int64_t c0 = P0; c0 < P1; c0 += GA_CHUNK) {
     const int64_t c1 = min(c0 + (int64_t)GA_CHUNK, P1);
     const int cn = (int)(c1 - c0);
+    const int cr0 = (int)(c0 - P0), cr1 = (int)(c1 - P0);
     for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) {
       const int lp = i >> 3, f = i & 7;
       s_src[f][lp] = gsrc[(size_t)8 * c0 + i];
@@ -140,14 +145,14 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
       for (int dy = -1; dy <= 1; dy++) {
         const int ay = y + dy;
         if (ay < 0 || ay >= n1) continue;
-        const int64_t rowc = ((int64_t)ax * n1 + ay) * n2;
+        const int rowc = ((ax - xl) * n1 + ay) * n2;
         for (int dz = -1; dz <= 1; dz++) {
           const int az = z + dz;
           if (az < 0 || az >= n2) continue;
-          const int64_t p0 = max(g.cellptr[rowc + az], c0), p1 = min(g.cellptr[rowc + az + 1], c1);
-          for (int64_t p = p0; p < p1; p++) {
+          const int p0 = max(s_cell[rowc + az], cr0), p1 = min(s_cell[rowc + az + 1], cr1);
+          for (int p = p0; p < p1; p++) {
             // the node sits at offset (-dx, -dy, -dz) from this point's anchor
-            const int lp = (int)(p - c0);
+            const int lp = p - cr0;
             const T ux = s_u[0][lp], uy = s_u[1][lp], uz = s_u[2][lp];
             const T wx = dx == 1 ? T(0.5) * ux * (ux - T(1)) : (dx == 0 ? T(1) - ux * ux : T(0.5) * ux * (ux + T(1)));
             const T wy = dy == 1 ? T(0.5) * uy * (uy - T(1)) : (dy == 0 ? T(1) - uy * uy : T(0.5) * uy * (uy + T(1)));
@@ -189,7 +194,7 @@ void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &gri
     const int items = 3 * plane;
     const int threads = std::min(1024, (items + 63) / 64 * 64);
     const int maxi = (items + threads - 1) / threads;
-    const size_t lds = sizeof(cx<T>) * (size_t)items;
+    const size_t lds = sizeof(cx<T>) * (size_t)items + sizeof(int) * (size_t)(items + 1);
     const dim3 grid(grids[k].n[0], nb);
     if (maxi == 1)
       hipLaunchKernelGGL((gather_kernel<T, 1>), grid, dim3(threads), lds, s, grids[k], g);
