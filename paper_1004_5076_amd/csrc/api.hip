@@ -273,6 +273,25 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
     std::vector<cx<T>> tw(twL);
     for (int j = 0; j < twL; j++) tw[j] = {(T)tw_host[tw_off[gi] + j].x, (T)tw_host[tw_off[gi] + j].y};
     G.tw = c->mem.upload(tw);
+    G.twx = nullptr;
+    if (d.N[0] == XLINE_REG_LEN) {
+      std::vector<cx<T>> tx(XLINE_REG_LEN + 64);
+      auto root = [](long e, long n) {
+        const double a = -2.0 * PI * (double)(e % n) / (double)n;
+        return cx<double>{std::cos(a), std::sin(a)};
+      };
+      for (int a = 0; a < 16; a++)
+        for (int l = 0; l < 64; l++) {
+          const cx<double> w = root((long)a * l, XLINE_REG_LEN);
+          tx[a * 64 + l] = {(T)w.x, (T)w.y};
+        }
+      for (int cc = 0; cc < 16; cc++)
+        for (int p = 0; p < 4; p++) {
+          const cx<double> w = root((long)p * cc, 64);
+          tx[XLINE_REG_LEN + cc * 4 + p] = {(T)w.x, (T)w.y};
+        }
+      G.twx = c->mem.upload(tx);
+    }
     if (sizeof(T) == sizeof(double))
       G.ghat = (const cx<T> *)ghat64[gi];
     else

@@ -8,29 +8,29 @@
 namespace scabs {
 
 template <typename T> __host__ __device__ inline cx<T> mk(T a, T b) { return cx<T>{a, b}; }
-template <typename T> __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
-template <typename T> __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
-template <typename T> __device__ inline cx<T> operator-(cx<T> a) { return {-a.x, -a.y}; }
-template <typename T> __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+template <typename T> __host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a) { return {-a.x, -a.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-template <typename T> __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.x, s * a.y}; }
-template <typename T> __device__ inline cx<T> operator*(cx<T> a, T s) { return {s * a.x, s * a.y}; }
-template <typename T> __device__ inline cx<T> &operator+=(cx<T> &a, cx<T> b) {
+template <typename T> __host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, T s) { return {s * a.x, s * a.y}; }
+template <typename T> __host__ __device__ inline cx<T> &operator+=(cx<T> &a, cx<T> b) {
   a.x += b.x;
   a.y += b.y;
   return a;
 }
-template <typename T> __device__ inline cx<T> &operator-=(cx<T> &a, cx<T> b) {
+template <typename T> __host__ __device__ inline cx<T> &operator-=(cx<T> &a, cx<T> b) {
   a.x -= b.x;
   a.y -= b.y;
   return a;
 }
-template <typename T> __device__ inline cx<T> czero() { return {T(0), T(0)}; }
-template <typename T> __device__ inline cx<T> mul_j(cx<T> a) { return {-a.y, a.x}; }   // j * a
-template <typename T> __device__ inline cx<T> conjc(cx<T> a) { return {a.x, -a.y}; }
+template <typename T> __host__ __device__ inline cx<T> czero() { return {T(0), T(0)}; }
+template <typename T> __host__ __device__ inline cx<T> mul_j(cx<T> a) { return {-a.y, a.x}; }   // j * a
+template <typename T> __host__ __device__ inline cx<T> conjc(cx<T> a) { return {a.x, -a.y}; }
 // a += s * b (s real)
-template <typename T> __device__ inline void axpy(cx<T> &a, T s, cx<T> b) {
+template <typename T> __host__ __device__ inline void axpy(cx<T> &a, T s, cx<T> b) {
   a.x += s * b.x;
   a.y += s * b.y;
 }
@@ -61,7 +61,7 @@ __device__ inline void unpack_anchor(int a, int &x, int &y, int &z) {
 // V = DFT_R(v), y[(j - k) R + k + r Ns] = V_r.  ELEMS bounds the elements per
 // thread (nlines * L <= ELEMS * blockDim.x).  All threads must call it.
 // ---------------------------------------------------------------------------
-template <typename T, int R> __device__ inline void dft_small(cx<T> *v, bool inv) {
+template <typename T, int R> __host__ __device__ inline void dft_small(cx<T> *v, bool inv) {
   if (R == 2) {
     cx<T> a = v[0], b = v[1];
     v[0] = a + b;

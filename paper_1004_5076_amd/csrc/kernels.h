@@ -18,7 +18,10 @@ template <typename T> struct DevGrid {
   cx<T> *phys;       // 8 * n0 n1 n2
   cx<T> *spec;       // 8 * n0 N1 N2 (y-z transformed planes)
   const cx<T> *ghat; // (N0/2+1)(N1/2+1)(N2/2+1): FFT of the embedded kernel / (N0 N1 N2)
-  const cx<T> *tw;   // exp(-2 pi i j / twL), j < twL/2
+  const cx<T> *tw;   // exp(-2 pi i j / twL), j < twL
+  // x lines of length 1024 only (else null): exp(-2 pi i a l / 1024) at
+  // [a * 64 + l] (a < 16, l < 64), then exp(-2 pi i p c / 64) at [1024 + c * 4 + p]
+  const cx<T> *twx;
 };
 
 // Per-grid point lists for the gather projection: the grid's points sorted by
@@ -51,6 +54,7 @@ template <typename T> struct DevOperator {
 
 // ---- FFT convolution -------------------------------------------------------
 // nb vectors: phys/spec hold nb consecutive 8-field blocks
+constexpr int XLINE_REG_LEN = 1024;   // x length with the wave-per-line register transform
 template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb = 1);
 // FFT of the circulant-embedded grid kernel; writes the scaled octant in both precisions
 hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int twL, cx<double> *ghat64,

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "device_common.h"
+#include "fft_reg.h"
 #include "kernels.h"
 
 namespace scabs {
@@ -110,6 +111,200 @@ xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, co
   }
 }
 
+// ---- register-resident transforms ---------------------------------------------
+// y-z planes: a lane holds one whole z line, then one whole y line, in its
+// registers and transforms it there (lengths in reg_line_ok); the planes of
+// a work-group meet in LDS between the two directions.
+__host__ __device__ constexpr bool reg_line_ok(int n) {
+  return n == 4 || n == 6 || n == 8 || n == 12 || n == 16 || n == 24 || n == 32 || n == 48;
+}
+
+// out[i os] = (DFT of in[0..nin) zero-padded to NN)[i] for i < nout
+template <typename T, int NN, bool INV>
+__device__ __forceinline__ void line_dft(const cx<T> *in, int is, int nin, cx<T> *out, int os, int nout) {
+  cx<T> v[NN];
+#pragma unroll
+  for (int i = 0; i < NN; i++) v[i] = i < nin ? in[i * is] : czero<T>();
+  rdft<T, NN, INV>(v);
+#pragma unroll
+  for (int i = 0; i < NN; i++)
+    if (i < nout) out[i * os] = v[i];
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void line_dft_n(int NN, const cx<T> *in, int is, int nin, cx<T> *out, int os, int nout) {
+  switch (NN) {
+    case 4: line_dft<T, 4, INV>(in, is, nin, out, os, nout); break;
+    case 6: line_dft<T, 6, INV>(in, is, nin, out, os, nout); break;
+    case 8: line_dft<T, 8, INV>(in, is, nin, out, os, nout); break;
+    case 12: line_dft<T, 12, INV>(in, is, nin, out, os, nout); break;
+    case 16: line_dft<T, 16, INV>(in, is, nin, out, os, nout); break;
+    case 24: line_dft<T, 24, INV>(in, is, nin, out, os, nout); break;
+    case 32: line_dft<T, 32, INV>(in, is, nin, out, os, nout); break;
+    default: line_dft<T, 48, INV>(in, is, nin, out, os, nout); break;
+  }
+}
+
+constexpr int PLANE_REG_THREADS = 256;
+// Forward: z lines y < n1 of P physical planes (zero-padded n2 -> N2) into LDS
+// rows of stride N2 + 1, then every y line (n1 -> N1) out to the spectrum.
+template <typename T>
+__global__ void __launch_bounds__(PLANE_REG_THREADS)
+plane_fwd_reg_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n0, int n1, int n2, int N1,
+                     int N2, int P) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int f = blockIdx.y, x0 = blockIdx.x * P;
+  const int np = min(P, n0 - x0), S = N2 + 1;
+  const cx<T> *src = phys + ((size_t)f * n0 + x0) * n1 * n2;
+  for (int i = threadIdx.x; i < np * n1; i += blockDim.x)
+    line_dft_n<T, false>(N2, src + (size_t)i * n2, 1, n2, buf + i * S, 1, N2);
+  __syncthreads();
+  cx<T> *dst = spec + ((size_t)f * n0 + x0) * N1 * N2;
+  for (int i = threadIdx.x; i < np * N2; i += blockDim.x) {
+    const int pl = i / N2, kz = i - pl * N2;
+    line_dft_n<T, false>(N1, buf + pl * n1 * S + kz, S, n1, dst + (size_t)pl * N1 * N2 + kz, N2, N1);
+  }
+}
+// Inverse: every y line (N1, kept y < n1) into LDS, then the z lines (kept z < n2).
+template <typename T>
+__global__ void __launch_bounds__(PLANE_REG_THREADS)
+plane_inv_reg_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n0, int n1, int n2, int N1,
+                     int N2, int P) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int f = blockIdx.y, x0 = blockIdx.x * P;
+  const int np = min(P, n0 - x0), S = N2 + 1;
+  const cx<T> *src = spec + ((size_t)f * n0 + x0) * N1 * N2;
+  for (int i = threadIdx.x; i < np * N2; i += blockDim.x) {
+    const int pl = i / N2, kz = i - pl * N2;
+    line_dft_n<T, true>(N1, src + (size_t)pl * N1 * N2 + kz, N2, N1, buf + pl * n1 * S + kz, S, n1);
+  }
+  __syncthreads();
+  cx<T> *dst = phys + ((size_t)f * n0 + x0) * n1 * n2;
+  for (int i = threadIdx.x; i < np * n1; i += blockDim.x)
+    line_dft_n<T, true>(N2, buf + i * S, 1, N2, dst + (size_t)i * n2, 1, n2);
+}
+static int reg_planes(int n1, int N2) { return std::max(1, PLANE_REG_THREADS / std::max(n1, N2)); }
+
+// x lines of length 1024: one wave per (k_y, k_z) column, 16 elements per
+// lane.  1024 = 16 x 64: a 16-point transform in each lane's registers over
+// x = l + 64 r, twiddles exp(-2 pi i l a / 1024), an exchange through LDS to
+// lane 4 a + p holding l = p + 4 s, a 16-point transform over s, twiddles
+// exp(-2 pi i p c / 64) and a 4-point transform across the lane quad: lane
+// 4 a + p then holds k_x = a + 16 c + 256 d(p) in register c.  The product
+// with the kernel spectrum is taken there, and the inverse runs the adjoint
+// steps in reverse order back to x = l + 64 r.  The columns of a work-group
+// are staged through LDS (row-major global rows, one LDS line per column);
+// the exchange reuses the wave's own line.
+template <typename T> struct XRegCfg { static constexpr int threads = 512; };
+template <> struct XRegCfg<double> { static constexpr int threads = 256; };
+constexpr int XR_LS = 1096;   // LDS line stride: >= 16 x 68 exchange slots, = 8 (mod 64)
+constexpr int XR_XS = 68;     // exchange row stride
+
+template <typename T>
+__global__ void __launch_bounds__(XRegCfg<T>::threads)
+xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *__restrict__ ghat,
+                 const cx<T> *__restrict__ twx) {
+  constexpr int C = XRegCfg<T>::threads / 64;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int f = blockIdx.y, b0 = blockIdx.x * C;
+  const int M = N1 * N2;
+  const int nl = min(C, M - b0);
+  cx<T> *base = spec + (size_t)f * n0 * M + b0;
+  {
+    const int c = threadIdx.x % C, xr = threadIdx.x / C;   // 64 rows per pass
+    for (int xb = 0; xb < n0; xb += 8 * 64) {
+      cx<T> t[8];
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const int x = xb + xr + 64 * k;
+        t[k] = (x < n0 && c < nl) ? base[(size_t)x * M + c] : czero<T>();
+      }
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const int x = xb + xr + 64 * k;
+        if (x < n0) buf[c * XR_LS + x] = t[k];
+      }
+    }
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (w < nl) {   // wave-uniform: every lane of the wave takes part below
+    cx<T> *ln = buf + w * XR_LS;
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int x = lane + 64 * r;
+      v[r] = x < n0 ? ln[x] : czero<T>();
+    }
+    rdft<T, 16, false>(v);
+#pragma unroll
+    for (int a = 1; a < 16; a++) v[a] = v[a] * twx[a * 64 + lane];
+    wave_lds_fence();
+#pragma unroll
+    for (int a = 0; a < 16; a++) ln[a * XR_XS + lane] = v[a];
+    wave_lds_fence();
+    const int qa = lane >> 2, p = lane & 3;
+#pragma unroll
+    for (int s = 0; s < 16; s++) v[s] = ln[qa * XR_XS + p + 4 * s];
+    rdft<T, 16, false>(v);
+#pragma unroll
+    for (int c = 1; c < 16; c++) v[c] = v[c] * twx[XLINE_REG_LEN + c * 4 + p];
+#pragma unroll
+    for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, false>(v[c], p);
+    // product with the kernel spectrum (octant storage, mirrored indices)
+    const int b = b0 + w, ky = b / N2, kz = b - ky * N2;
+    const int h1 = N1 / 2 + 1, h2 = N2 / 2 + 1;
+    const cx<T> *gl = ghat + (size_t)min(ky, N1 - ky) * h2 + min(kz, N2 - kz);
+    const size_t gs = (size_t)h1 * h2;
+    const int d = 2 * (p & 1) + (p >> 1);
+#pragma unroll
+    for (int c = 0; c < 16; c++) {
+      const int kx = qa + 16 * c + 256 * d;
+      v[c] = v[c] * gl[(size_t)min(kx, XLINE_REG_LEN - kx) * gs];
+    }
+#pragma unroll
+    for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, true>(v[c], p);
+#pragma unroll
+    for (int c = 1; c < 16; c++) v[c] = twm<T, true>(v[c], twx[XLINE_REG_LEN + c * 4 + p]);
+    rdft<T, 16, true>(v);
+    wave_lds_fence();
+#pragma unroll
+    for (int s = 0; s < 16; s++) ln[qa * XR_XS + p + 4 * s] = v[s];
+    wave_lds_fence();
+#pragma unroll
+    for (int a = 0; a < 16; a++) v[a] = ln[a * XR_XS + lane];
+#pragma unroll
+    for (int a = 1; a < 16; a++) v[a] = twm<T, true>(v[a], twx[a * 64 + lane]);
+    rdft<T, 16, true>(v);
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int x = lane + 64 * r;
+      if (x < n0) ln[x] = v[r];
+    }
+  }
+  __syncthreads();
+  {
+    const int c = threadIdx.x % C, xr = threadIdx.x / C;
+    if (c < nl)
+      for (int xb = 0; xb < n0; xb += 8 * 64) {
+        cx<T> t[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const int x = xb + xr + 64 * k;
+          t[k] = x < n0 ? buf[c * XR_LS + x] : czero<T>();
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const int x = xb + xr + 64 * k;
+          if (x < n0) base[(size_t)x * M + c] = t[k];
+        }
+      }
+  }
+}
+
 template <typename T> static int xline_lines(int N0) {
   int C = (int)std::min<size_t>(LDS_BUDGET / (sizeof(cx<T>) * (size_t)lpad_size<T>(N0 + 1)),
                                 (size_t)FftCfg<T>::elems * FftCfg<T>::threads / N0);
@@ -131,7 +326,15 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
   const int nw = FftCfg<T>::threads / 64, EW = FftCfg<T>::wave_elems;
   // wave-owned passes measured faster in FP32 only (FP64 needs too many registers)
   const bool pw = FftCfg<T>::wave && wave_fits(N2, P * n1, nw, EW) && wave_fits(N1, P * N2, nw, EW);
-  if (pw)
+  // register-resident y-z transforms where both lengths are supported
+  const int Pr = std::min(reg_planes(n1, N2), (int)(LDS_BUDGET / (sizeof(cx<T>) * (size_t)n1 * (N2 + 1))));
+  const bool preg = reg_line_ok(N1) && reg_line_ok(N2) && Pr >= 1;
+  const size_t preg_lds = sizeof(cx<T>) * (size_t)Pr * n1 * (N2 + 1);
+  const int npr = (n0 + Pr - 1) / Pr;
+  if (preg)
+    hipLaunchKernelGGL(plane_fwd_reg_kernel<T>, dim3(npr, 8 * nb), dim3(PLANE_REG_THREADS), preg_lds, s, g.phys,
+                       g.spec, n0, n1, n2, N1, N2, Pr);
+  else if (pw)
     hipLaunchKernelGGL((plane_fwd_kernel<T, true>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.phys,
                        g.spec, n0, n1, n2, N1, N2, P, g.tw, g.twL);
   else
@@ -139,13 +342,20 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
                        g.spec, n0, n1, n2, N1, N2, P, g.tw, g.twL);
   const int C = xline_lines<T>(N0);
   const int nlb = (N1 * N2 + C - 1) / C;
-  if (FftCfg<T>::wave && wave_fits(N0, C, nw, EW))
+  constexpr int CR = XRegCfg<T>::threads / 64;
+  if (g.twx && N0 == XLINE_REG_LEN && n0 <= XLINE_REG_LEN / 2)
+    hipLaunchKernelGGL(xline_reg_kernel<T>, dim3((N1 * N2 + CR - 1) / CR, 8 * nb), dim3(XRegCfg<T>::threads),
+                       sizeof(cx<T>) * (size_t)CR * XR_LS, s, g.spec, n0, N1, N2, g.ghat, g.twx);
+  else if (FftCfg<T>::wave && wave_fits(N0, C, nw, EW))
     hipLaunchKernelGGL((xline_kernel<T, true>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
                        g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
   else
     hipLaunchKernelGGL((xline_kernel<T, false>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
                        g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
-  if (pw)
+  if (preg)
+    hipLaunchKernelGGL(plane_inv_reg_kernel<T>, dim3(npr, 8 * nb), dim3(PLANE_REG_THREADS), preg_lds, s, g.spec,
+                       g.phys, n0, n1, n2, N1, N2, Pr);
+  else if (pw)
     hipLaunchKernelGGL((plane_inv_kernel<T, true>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.spec,
                        g.phys, n0, n1, n2, N1, N2, P, g.tw, g.twL);
   else

@@ -215,3 +215,34 @@ def test_errors_are_reported():
     with pytest.raises(pk.ScabsError) as e:
         ctx3.solve(b, mode=0, raise_on_noconv=True)
     assert e.value.code == pk.SCABS_E_NAN
+
+
+@pytest.fixture(scope="module")
+def apart():
+    """Two short guides 24 apart along x: the exterior lattice is 427 nodes
+    long (1024-point x transforms) while the unknown count stays small."""
+    h = 25.0 / 424
+    parts = [synth.guide(1.0, 0.1, x0=0.0), synth.guide(1.0, 0.1, x0=24.0, yc=0.05)]
+    mesh = synth.merge_bodies(parts)
+    sig = [synth.SigmaEnd(0, 24.5, 0.5, +1, 2, 1.0)]
+    w = synth.Workload("apart", mesh, sig, [synth.seeded_dipole(7, base=(0.5, 0, 0), body=0)], h=h,
+                       r_near=3.61 * h)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    P = o.pfft(w.h, w.r_near)
+    assert int(P.grids[0][2][0]) > 384   # x length of the embedding is 1024
+    return w, o, P, _ctx(w)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_long_lattice_matvec(apart, prec, tol, transpose):
+    torch = _torch()
+    w, o, P, ctx = apart
+    X = np.stack([synth.random_complex(500 + k, o.N) for k in range(3)])
+    Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=prec, transpose=transpose).cpu().numpy()
+    for k in range(3):
+        ref = P.rmatvec(X[k]) if transpose else P.matvec(X[k])
+        err = _rel(Y[k], ref)
+        print("long lattice prec", prec, "transpose", transpose, "rel", err, flush=True)
+        assert err < tol
