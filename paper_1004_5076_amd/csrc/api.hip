@@ -78,7 +78,7 @@ template <typename T> struct PrecState {
   std::vector<DevGrid<T>> grids;   // host copies holding device pointers
   DevGrid<T> *grids_dev = nullptr;
   std::vector<GatherGrid<T>> gather;
-  std::vector<cx<T> *> src4;       // per grid: 32 adjoint-source coefficients per sorted point
+  std::vector<cx<T> *> src4;       // per grid: ADJ_COEF adjoint-source coefficients per sorted point
   int bcap = 1;                    // vectors the per-vector buffers hold
   DevOperator<T> op;
   T inv_h = 0;
@@ -324,8 +324,18 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
     GG.cellptr = c->mem.upload(cellptr);
     GG.u = c->mem.upload(uu);
     GG.src = c->mem.alloc<cx<T>>(8 * key.size());
+    std::vector<int> nz_ptr(d.n[0] + 1, 0), nz_yz;
+    const size_t plane = (size_t)d.n[1] * d.n[2];
+    for (int xx = 0; xx < d.n[0]; xx++) {
+      for (size_t yz = 0; yz < plane; yz++)
+        if (cellptr[xx * plane + yz + 1] > cellptr[xx * plane + yz]) nz_yz.push_back((int)yz);
+      nz_ptr[xx + 1] = (int)nz_yz.size();
+    }
+    if (nz_yz.empty()) nz_yz.push_back(0);
+    GG.nz_ptr = c->mem.upload(nz_ptr);
+    GG.nz_yz = c->mem.upload(nz_yz);
     P.gather.push_back(GG);
-    P.src4.push_back(c->mem.alloc<cx<T>>(32 * key.size()));
+    P.src4.push_back(c->mem.alloc<cx<T>>((size_t)ADJ_COEF * key.size()));
   }
   P.grids_dev = c->mem.upload(P.grids);
   P.inv_h = (T)(1.0 / c->opts.h);

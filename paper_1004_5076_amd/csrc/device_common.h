@@ -46,6 +46,13 @@ template <typename T> __device__ inline void lagr3(T u, T *L, T *dL) {
   dL[2] = u + T(0.5);
 }
 
+// the same weights for a node at offset o (-1, 0, 1) from the anchor:
+// (1 - u^2) at o = 0, u (u + o) / 2 otherwise; and d/du of it
+template <typename T> __device__ __forceinline__ T lag_w(int o, T u) {
+  return o == 0 ? T(1) - u * u : T(0.5) * u * (u + T(o));
+}
+template <typename T> __device__ __forceinline__ T lag_d(int o, T u) { return o == 0 ? T(-2) * u : u + T(0.5) * T(o); }
+
 __device__ inline void unpack_anchor(int a, int &x, int &y, int &z) {
   x = a & 0x3fff;
   y = (a >> 14) & 0x1ff;

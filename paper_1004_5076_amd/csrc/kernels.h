@@ -34,7 +34,12 @@ template <typename T> struct GatherGrid {
   const int64_t *cellptr;  // ncell + 1
   const T *u;              // 3 per sorted point
   cx<T> *src;              // 8 per sorted point (written each product)
+  const int *nz_ptr;       // n0 + 1: cells holding points, listed plane by plane
+  const int *nz_yz;        // their (y, z) index y n2 + z within the plane
 };
+// coefficients per point of the transposed testing (lattice sources of test^T):
+// 8 value coefficients, then the three vectors whose curls and gradient enter
+constexpr int ADJ_COEF = 17;
 
 template <typename T> struct DevOperator {
   int np, nt, ne, N;
@@ -147,7 +152,7 @@ void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_pt
 
 // ---- transposed product, adjoint gradient --------------------------------------
 template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s);
-// src4[k]: 32 coefficients per sorted point of grid k (work buffer)
+// src4[k]: ADJ_COEF coefficients per sorted point of grid k (work buffer)
 template <typename T>
 void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids, const std::vector<GatherGrid<T>> &gg,
                    const std::vector<cx<T> *> &src4, T inv_h, hipStream_t s);

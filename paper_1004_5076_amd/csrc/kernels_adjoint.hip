@@ -50,7 +50,10 @@ template void launch_unpack_rows<double>(const DevOperator<double> &, const doub
 //   curl a_J . (sgn w t_H)           curl a_M . (-(sgn w t_E + s))
 //   grad phi_J . (-Z jk s / k^2)
 // and the gradient coefficient of component c inside v . curl a is e_c x v.
-// Output per point: 8 fields x (value, d/dx, d/dy, d/dz).
+// Output per point (ADJ_COEF): the 8 value coefficients, then vJ, vM and the
+// gradient vector of phi_J; the lattice node at weight W then receives
+// W c + (grad W) . (gradient coefficients), i.e. -(grad W x vJ) on a_J,
+// grad W . gp on phi_J and -(grad W x vM) on a_M.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -95,114 +98,124 @@ adj_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restr
   }
   cv[3] = mul_j(dE) * (sgn * w * Z / k);
   cv[7] = mul_j(dH) * (sgn * w / (Z * k));
-  cx<T> *o = out + (size_t)32 * i;
-  const cx<T> zz = czero<T>();
-  const cx<T> gc[8][3] = {{zz, -vJ[2], vJ[1]}, {vJ[2], zz, -vJ[0]}, {-vJ[1], vJ[0], zz}, {gp[0], gp[1], gp[2]},
-                          {zz, -vM[2], vM[1]}, {vM[2], zz, -vM[0]}, {-vM[1], vM[0], zz}, {zz, zz, zz}};
+  cx<T> *o = out + (size_t)ADJ_COEF * i;
 #pragma unroll
-  for (int f = 0; f < 8; f++) {
-    o[4 * f] = cv[f];
-    o[4 * f + 1] = gc[f][0];
-    o[4 * f + 2] = gc[f][1];
-    o[4 * f + 3] = gc[f][2];
+  for (int f = 0; f < 8; f++) o[f] = cv[f];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    o[8 + a] = vJ[a];
+    o[11 + a] = vM[a];
+    o[14 + a] = gp[a];
   }
 }
 
 // test^T, step 2: every node sums, over the points of its 27 neighbouring
-// cells, W c_value + W_x c_x + W_y c_y + W_z c_z per field.  Same organisation
-// as the forward gather: one work-group per x plane, work items (node, dx),
-// coefficients staged field-major in LDS, dx partials added at the end.
-template <typename T> struct GtChunk { static constexpr int value = 256; };
-template <> struct GtChunk<double> { static constexpr int value = 128; };
-
-template <typename T> __device__ inline void lagr_pick(int i, T u, T &L, T &dL) {
-  // node at offset i (-1, 0, +1) from the anchor
-  if (i == -1) {
-    L = T(0.5) * u * (u - T(1));
-    dL = u - T(0.5);
-  } else if (i == 0) {
-    L = T(1) - u * u;
-    dL = T(-2) * u;
-  } else {
-    L = T(0.5) * u * (u + T(1));
-    dL = u + T(0.5);
-  }
-}
+// cells, W c_value + grad W . (gradient coefficients) per field.  Same
+// organisation as the forward projection: per x plane, phase A over (cell,
+// node offset) items of the nonempty cells of planes x-1..x+1, phase B over
+// (node, x offset) items through the cell -> slot map, x partials added last.
+template <typename T> struct CellChunkT { static constexpr int value = 96; };
+template <> struct CellChunkT<double> { static constexpr int value = 48; };
 
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024)
 gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4, T inv_h) {
-  constexpr int CH = GtChunk<T>::value;
-  __shared__ cx<T> s_src[32][CH];
-  __shared__ T s_u[3][CH];
-  extern __shared__ unsigned char smem_raw[];
-  cx<T> *s_red = reinterpret_cast<cx<T> *>(smem_raw);   // 3 * plane
-  int *s_cell = reinterpret_cast<int *>(s_red + 3 * dg.n[1] * dg.n[2]);   // cell starts of planes x-1..x+1
+  constexpr int SC = CellChunkT<T>::value, SQ = 9 * SC;
+  static_assert(8 * SQ >= 3 * 1024, "the final reduction reuses s_q for 3 planes of at most 1024 nodes");
+  __shared__ cx<T> s_q[8][SQ];
+  extern __shared__ int s_map[];
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   const int x = blockIdx.x;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
-  const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
-  // cell pointers of the (up to) three planes, relative to P0, staged once
-  const int ncl = (xh - xl + 1) * plane;
-  for (int t = threadIdx.x; t <= ncl; t += blockDim.x) s_cell[t] = (int)(g.cellptr[(int64_t)xl * plane + t] - P0);
-  const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane);
+  const int K0 = g.nz_ptr[xl], K = g.nz_ptr[xh + 1] - K0;
+  const int B1 = g.nz_ptr[min(xl + 1, xh + 1)] - K0, B2 = g.nz_ptr[min(xl + 2, xh + 1)] - K0;
+  for (int t = threadIdx.x; t < (xh - xl + 1) * plane; t += blockDim.x) s_map[t] = -1;
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) s_map[((k >= B1) + (k >= B2)) * plane + g.nz_yz[K0 + k]] = k;
+  __syncthreads();
+  const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane), d9 = make_fastdiv(9), d3 = make_fastdiv(3);
   cx<T> acc[MAXI][8];
 #pragma unroll
   for (int m = 0; m < MAXI; m++)
 #pragma unroll
     for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
-  for (int64_t c0 = P0; c0 < P1; c0 += CH) {
-    const int64_t c1 = min(c0 + (int64_t)CH, P1);
-    const int cn = (int)(c1 - c0);
-    const int cr0 = (int)(c0 - P0), cr1 = (int)(c1 - P0);
-    for (int i = threadIdx.x; i < cn * 32; i += blockDim.x) {
-      const int lp = i >> 5, f = i & 31;
-      s_src[f][lp] = src4[(size_t)32 * c0 + i];
-    }
-    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) {
-      const int lp = i / 3, a = i - 3 * lp;
-      s_u[a][lp] = g.u[(size_t)3 * c0 + i];
+  for (int c0 = 0; c0 < K; c0 += SC) {
+    const int cn = min(SC, K - c0);
+    for (int it = threadIdx.x; it < 9 * cn; it += blockDim.x) {
+      const int kk = fdiv(it, d9), off = it - 9 * kk;
+      const int k = c0 + kk;
+      const int cxo = (k >= B1) + (k >= B2);
+      const int yz = g.nz_yz[K0 + k];
+      const int cy = fdiv(yz, dn2), cz = yz - cy * n2;
+      const int oyi = fdiv(off, d3);
+      const int ox = x - (xl + cxo), oy = oyi - 1, oz = off - 3 * oyi - 1;
+      cx<T> a[8];
+#pragma unroll
+      for (int f = 0; f < 8; f++) a[f] = czero<T>();
+      if (cy + oy >= 0 && cy + oy < n1 && cz + oz >= 0 && cz + oz < n2) {
+        const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
+        const int64_t p1 = g.cellptr[cell + 1];
+        for (int64_t p = g.cellptr[cell]; p < p1; p++) {
+          const T ux = g.u[3 * p], uy = g.u[3 * p + 1], uz = g.u[3 * p + 2];
+          const T Lx = lag_w(ox, ux), Ly = lag_w(oy, uy), Lz = lag_w(oz, uz);
+          const T W = Lx * Ly * Lz, Wx = lag_d(ox, ux) * Ly * Lz * inv_h, Wy = Lx * lag_d(oy, uy) * Lz * inv_h,
+                  Wz = Lx * Ly * lag_d(oz, uz) * inv_h;
+          const cx<T> *c = src4 + (size_t)ADJ_COEF * p;
+#pragma unroll
+          for (int f = 0; f < 8; f++) axpy(a[f], W, c[f]);
+          const cx<T> vJ0 = c[8], vJ1 = c[9], vJ2 = c[10], vM0 = c[11], vM1 = c[12], vM2 = c[13];
+          // -(grad W x vJ) on a_J, -(grad W x vM) on a_M
+          axpy(a[0], -Wy, vJ2);
+          axpy(a[0], Wz, vJ1);
+          axpy(a[1], -Wz, vJ0);
+          axpy(a[1], Wx, vJ2);
+          axpy(a[2], -Wx, vJ1);
+          axpy(a[2], Wy, vJ0);
+          axpy(a[4], -Wy, vM2);
+          axpy(a[4], Wz, vM1);
+          axpy(a[5], -Wz, vM0);
+          axpy(a[5], Wx, vM2);
+          axpy(a[6], -Wx, vM1);
+          axpy(a[6], Wy, vM0);
+          axpy(a[3], Wx, c[14]);
+          axpy(a[3], Wy, c[15]);
+          axpy(a[3], Wz, c[16]);
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < 8; f++) s_q[f][it] = a[f];
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MAXI; m++) {
       const int it = threadIdx.x + m * blockDim.x;
       if (it >= 3 * plane) continue;
-      const int dxi = fdiv(it, dpl), nd = it - dxi * plane;
-      const int dx = dxi - 1;
-      const int ax = x + dx;
-      if (ax < 0 || ax >= n0) continue;
+      const int oxi = fdiv(it, dpl), nd = it - oxi * plane;
+      const int cxp = x - (oxi - 1);
+      if (cxp < xl || cxp > xh) continue;
       const int y = fdiv(nd, dn2), z = nd - y * n2;
-      for (int dy = -1; dy <= 1; dy++) {
-        const int ay = y + dy;
-        if (ay < 0 || ay >= n1) continue;
-        const int rowc = ((ax - xl) * n1 + ay) * n2;
-        for (int dz = -1; dz <= 1; dz++) {
-          const int az = z + dz;
-          if (az < 0 || az >= n2) continue;
-          const int p0 = max(s_cell[rowc + az], cr0), p1 = min(s_cell[rowc + az + 1], cr1);
-          for (int p = p0; p < p1; p++) {
-            const int lp = p - cr0;
-            T Lx, Ly, Lz, dLx, dLy, dLz;
-            lagr_pick(-dx, s_u[0][lp], Lx, dLx);
-            lagr_pick(-dy, s_u[1][lp], Ly, dLy);
-            lagr_pick(-dz, s_u[2][lp], Lz, dLz);
-            const T W = Lx * Ly * Lz, Wx = dLx * Ly * Lz * inv_h, Wy = Lx * dLy * Lz * inv_h,
-                    Wz = Lx * Ly * dLz * inv_h;
+      const int *mp = s_map + (cxp - xl) * plane;
 #pragma unroll
-            for (int f = 0; f < 8; f++) {
-              axpy(acc[m][f], W, s_src[4 * f][lp]);
-              axpy(acc[m][f], Wx, s_src[4 * f + 1][lp]);
-              axpy(acc[m][f], Wy, s_src[4 * f + 2][lp]);
-              axpy(acc[m][f], Wz, s_src[4 * f + 3][lp]);
-            }
+      for (int oy = -1; oy <= 1; oy++) {
+        const int cy = y - oy;
+        if (cy < 0 || cy >= n1) continue;
+#pragma unroll
+        for (int oz = -1; oz <= 1; oz++) {
+          const int cz = z - oz;
+          if (cz < 0 || cz >= n2) continue;
+          const int k = mp[cy * n2 + cz] - c0;
+          if ((unsigned)k < (unsigned)cn) {
+            const int q = 9 * k + 3 * (oy + 1) + oz + 1;
+#pragma unroll
+            for (int f = 0; f < 8; f++) acc[m][f] += s_q[f][q];
           }
         }
       }
     }
     __syncthreads();
   }
+  cx<T> *s_red = &s_q[0][0];
   const size_t G = (size_t)g.ncell;
   for (int f = 0; f < 8; f++) {
 #pragma unroll
@@ -230,7 +243,7 @@ void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grid
     const int items = 3 * plane;
     const int threads = std::min(1024, (items + 63) / 64 * 64);
     const int maxi = (items + threads - 1) / threads;
-    const size_t lds = sizeof(cx<T>) * (size_t)items + sizeof(int) * (size_t)(items + 1);
+    const size_t lds = sizeof(int) * (size_t)items;   // cell -> slot map of three planes
     if (maxi == 1)
       hipLaunchKernelGGL((gather_adj_kernel<T, 1>), dim3(grids[k].n[0]), dim3(threads), lds, s, grids[k], gg[k],
                          src4[k], inv_h);

@@ -84,25 +84,24 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
   for (int f = 0; f < 8; f++) o[f] = s[f] * P.w;
 }
 
-// One work-group per x plane of a grid (and vector of the batch).  Work items
-// are (node (y, z) of the plane, x offset dx of the source cells): item
-// dxi * plane + node, dx = dxi - 1, so neighbouring lanes own neighbouring
-// nodes.  The points anchored in planes x-1..x+1 (contiguous in the
-// cell-sorted list) are staged through LDS in chunks, field-major so that
-// lanes reading different points hit different banks; each item sums the
-// points of its 9 cells (x+dx, y+dy, z+dz) that fall in the chunk, and the
-// three dx partials of a node are added in LDS at the end, field by field.
-// points per staged chunk (measured; FP32 sized so two work-groups fit in LDS)
-template <typename T> struct GaChunk { static constexpr int value = 960; };
-template <> struct GaChunk<double> { static constexpr int value = 512; };
+// One work-group per x plane of a grid (and vector of the batch), in chunks
+// of the cells that hold points among the planes x-1..x+1 (listed per plane
+// at setup).  Phase A, work item (cell, node offset (oy, oz)): the cell's
+// points, in sorted order, summed into the contribution to the node of plane x
+// at that offset (the x offset is fixed by the cell's plane); nine lanes share
+// a cell and so the same loop length, and empty cells cost nothing.  Phase B,
+// work item (node, x offset): the contributions of the 9 cells around the
+// node in that offset's plane, read through a cell -> slot map in LDS.  The
+// three x partials of a node are added at the end.  No atomics; the
+// summation order is fixed.
+template <typename T> struct CellChunk { static constexpr int value = 96; };
+template <> struct CellChunk<double> { static constexpr int value = 48; };
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
-  constexpr int GA_CHUNK = GaChunk<T>::value;
-  __shared__ cx<T> s_src[8][GA_CHUNK];
-  __shared__ T s_u[3][GA_CHUNK];
-  extern __shared__ unsigned char smem_raw[];
-  cx<T> *s_red = reinterpret_cast<cx<T> *>(smem_raw);   // 3 * plane
-  int *s_cell = reinterpret_cast<int *>(s_red + 3 * dg.n[1] * dg.n[2]);   // cell starts of planes x-1..x+1
+  constexpr int SC = CellChunk<T>::value, SQ = 9 * SC;
+  static_assert(8 * SQ >= 3 * 1024, "the final reduction reuses s_q for 3 planes of at most 1024 nodes");
+  __shared__ cx<T> s_q[8][SQ];
+  extern __shared__ int s_map[];   // (plane - xl) * plane + yz -> slot, or -1
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   const int x = blockIdx.x;
@@ -110,62 +109,73 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
   const cx<T> *gsrc = g.src + (size_t)8 * g.np * blockIdx.y;
   cx<T> *phys = dg.phys + (size_t)8 * g.ncell * blockIdx.y;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
-  const int64_t P0 = g.cellptr[(int64_t)xl * plane], P1 = g.cellptr[(int64_t)(xh + 1) * plane];
-  // cell pointers of the (up to) three planes, relative to P0, staged once
-  const int ncl = (xh - xl + 1) * plane;
-  for (int t = threadIdx.x; t <= ncl; t += blockDim.x) s_cell[t] = (int)(g.cellptr[(int64_t)xl * plane + t] - P0);
-  const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane);
+  const int K0 = g.nz_ptr[xl], K = g.nz_ptr[xh + 1] - K0;
+  const int B1 = g.nz_ptr[min(xl + 1, xh + 1)] - K0, B2 = g.nz_ptr[min(xl + 2, xh + 1)] - K0;
+  for (int t = threadIdx.x; t < (xh - xl + 1) * plane; t += blockDim.x) s_map[t] = -1;
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) s_map[((k >= B1) + (k >= B2)) * plane + g.nz_yz[K0 + k]] = k;
+  __syncthreads();
+  const FastDiv dn2 = make_fastdiv(n2), dpl = make_fastdiv(plane), d9 = make_fastdiv(9), d3 = make_fastdiv(3);
   cx<T> acc[MAXI][8];
 #pragma unroll
   for (int m = 0; m < MAXI; m++)
 #pragma unroll
     for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
-  for (int64_t c0 = P0; c0 < P1; c0 += GA_CHUNK) {
-    const int64_t c1 = min(c0 + (int64_t)GA_CHUNK, P1);
-    const int cn = (int)(c1 - c0);
-    const int cr0 = (int)(c0 - P0), cr1 = (int)(c1 - P0);
-    for (int i = threadIdx.x; i < cn * 8; i += blockDim.x) {
-      const int lp = i >> 3, f = i & 7;
-      s_src[f][lp] = gsrc[(size_t)8 * c0 + i];
-    }
-    for (int i = threadIdx.x; i < cn * 3; i += blockDim.x) {
-      const int lp = fdiv(i, make_fastdiv(3)), a = i - 3 * lp;
-      s_u[a][lp] = g.u[(size_t)3 * c0 + i];
+  for (int c0 = 0; c0 < K; c0 += SC) {
+    const int cn = min(SC, K - c0);
+    for (int it = threadIdx.x; it < 9 * cn; it += blockDim.x) {
+      const int kk = fdiv(it, d9), off = it - 9 * kk;
+      const int k = c0 + kk;
+      const int cxo = (k >= B1) + (k >= B2);
+      const int yz = g.nz_yz[K0 + k];
+      const int cy = fdiv(yz, dn2), cz = yz - cy * n2;
+      const int oyi = fdiv(off, d3);
+      const int ox = x - (xl + cxo), oy = oyi - 1, oz = off - 3 * oyi - 1;
+      cx<T> a[8];
+#pragma unroll
+      for (int f = 0; f < 8; f++) a[f] = czero<T>();
+      if (cy + oy >= 0 && cy + oy < n1 && cz + oz >= 0 && cz + oz < n2) {
+        const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
+        const int64_t p1 = g.cellptr[cell + 1];
+        for (int64_t p = g.cellptr[cell]; p < p1; p++) {
+          const T w = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]) * lag_w(oz, g.u[3 * p + 2]);
+#pragma unroll
+          for (int f = 0; f < 8; f++) axpy(a[f], w, gsrc[8 * p + f]);
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < 8; f++) s_q[f][it] = a[f];
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MAXI; m++) {
       const int it = threadIdx.x + m * blockDim.x;
       if (it >= 3 * plane) continue;
-      const int dxi = fdiv(it, dpl), nd = it - dxi * plane;
-      const int dx = dxi - 1;
-      const int ax = x + dx;
-      if (ax < 0 || ax >= n0) continue;
+      const int oxi = fdiv(it, dpl), nd = it - oxi * plane;
+      const int cxp = x - (oxi - 1);   // the cells' plane: node offset oxi - 1 from their anchors
+      if (cxp < xl || cxp > xh) continue;
       const int y = fdiv(nd, dn2), z = nd - y * n2;
-      for (int dy = -1; dy <= 1; dy++) {
-        const int ay = y + dy;
-        if (ay < 0 || ay >= n1) continue;
-        const int rowc = ((ax - xl) * n1 + ay) * n2;
-        for (int dz = -1; dz <= 1; dz++) {
-          const int az = z + dz;
-          if (az < 0 || az >= n2) continue;
-          const int p0 = max(s_cell[rowc + az], cr0), p1 = min(s_cell[rowc + az + 1], cr1);
-          for (int p = p0; p < p1; p++) {
-            // the node sits at offset (-dx, -dy, -dz) from this point's anchor
-            const int lp = p - cr0;
-            const T ux = s_u[0][lp], uy = s_u[1][lp], uz = s_u[2][lp];
-            const T wx = dx == 1 ? T(0.5) * ux * (ux - T(1)) : (dx == 0 ? T(1) - ux * ux : T(0.5) * ux * (ux + T(1)));
-            const T wy = dy == 1 ? T(0.5) * uy * (uy - T(1)) : (dy == 0 ? T(1) - uy * uy : T(0.5) * uy * (uy + T(1)));
-            const T wz = dz == 1 ? T(0.5) * uz * (uz - T(1)) : (dz == 0 ? T(1) - uz * uz : T(0.5) * uz * (uz + T(1)));
-            const T wgt = wx * wy * wz;
+      const int *mp = s_map + (cxp - xl) * plane;
 #pragma unroll
-            for (int f = 0; f < 8; f++) axpy(acc[m][f], wgt, s_src[f][lp]);
+      for (int oy = -1; oy <= 1; oy++) {
+        const int cy = y - oy;
+        if (cy < 0 || cy >= n1) continue;
+#pragma unroll
+        for (int oz = -1; oz <= 1; oz++) {
+          const int cz = z - oz;
+          if (cz < 0 || cz >= n2) continue;
+          const int k = mp[cy * n2 + cz] - c0;
+          if ((unsigned)k < (unsigned)cn) {
+            const int q = 9 * k + 3 * (oy + 1) + oz + 1;
+#pragma unroll
+            for (int f = 0; f < 8; f++) acc[m][f] += s_q[f][q];
           }
         }
       }
     }
     __syncthreads();
   }
+  cx<T> *s_red = &s_q[0][0];   // 3 * plane <= 8 * SQ
   const size_t G = (size_t)g.ncell;
   for (int f = 0; f < 8; f++) {
 #pragma unroll
@@ -194,7 +204,7 @@ void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &gri
     const int items = 3 * plane;
     const int threads = std::min(1024, (items + 63) / 64 * 64);
     const int maxi = (items + threads - 1) / threads;
-    const size_t lds = sizeof(cx<T>) * (size_t)items + sizeof(int) * (size_t)(items + 1);
+    const size_t lds = sizeof(int) * (size_t)items;   // cell -> slot map of three planes
     const dim3 grid(grids[k].n[0], nb);
     if (maxi == 1)
       hipLaunchKernelGGL((gather_kernel<T, 1>), grid, dim3(threads), lds, s, grids[k], g);
