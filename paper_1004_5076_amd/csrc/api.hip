@@ -130,7 +130,8 @@ struct scabs_ctx {
   cx<float> *pc_Rt = nullptr;
   // transposed apply: cluster of every ext entry, and per unknown its ext entries
   int64_t pc_n_ext = 0;
-  int *pc_ext_cluster = nullptr;
+  int *pc_t_items = nullptr;   // (cluster, first ext column) per transposed-apply work-group
+  int pc_n_t_items = 0;
   int64_t *pc_inv_ptr = nullptr, *pc_inv_pos = nullptr;
   cx<double> *pc_tmp = nullptr;
   // solver workspace (grown on demand)
@@ -369,14 +370,16 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   // boxes that would hold more unknowns than one work-group inverts shrink
   // the cell and overlap together until every cluster fits
   std::string e;
+  bool too_large = false;
   for (int attempt = 0;; attempt++) {
-    bool too_large = false;
+    too_large = false;
     e = build_clusters(g, L, cell, ov, c->cl, &too_large);
     if (!too_large || attempt == 30) break;
     cell *= 0.85;
     ov *= 0.85;
   }
   if (!e.empty()) throw e;
+  if (too_large) throw std::string("preconditioner clusters above the largest invertible block remain");
   LocalTerms lt;
   build_local_terms(g, L, lt);
   const Clusters &cl = c->cl;
@@ -409,21 +412,25 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   c->pc_core_slot = c->mem.upload(cl.core_slot);
   c->pc_r_off = c->mem.upload(cl.r_off);
   {
-    // transposed apply: owning cluster of every ext entry; per unknown the
-    // ext entries that hold it (cluster order)
+    // transposed apply: (cluster, first ext column) per work-group; per
+    // unknown the ext entries that hold it (cluster order)
     const int64_t n_ext = cl.ext_ptr[cl.nc];
-    std::vector<int> ext_cluster(n_ext);
+    std::vector<int> t_items;
     std::vector<int64_t> inv_ptr(L.N + 1, 0), inv_pos(n_ext);
-    for (int k = 0; k < cl.nc; k++)
-      for (int64_t q = cl.ext_ptr[k]; q < cl.ext_ptr[k + 1]; q++) {
-        ext_cluster[q] = k;
-        inv_ptr[cl.ext_slot[q] + 1]++;
+    const int tcols = precond_t_cols_per_item();
+    for (int k = 0; k < cl.nc; k++) {
+      for (int64_t j0 = 0; j0 < cl.ext_ptr[k + 1] - cl.ext_ptr[k]; j0 += tcols) {
+        t_items.push_back(k);
+        t_items.push_back((int)j0);
       }
+      for (int64_t q = cl.ext_ptr[k]; q < cl.ext_ptr[k + 1]; q++) inv_ptr[cl.ext_slot[q] + 1]++;
+    }
     for (int64_t u = 0; u < L.N; u++) inv_ptr[u + 1] += inv_ptr[u];
     std::vector<int64_t> fill(inv_ptr.begin(), inv_ptr.end() - 1);
     for (int64_t q = 0; q < n_ext; q++) inv_pos[fill[cl.ext_slot[q]]++] = q;
     c->pc_n_ext = n_ext;
-    c->pc_ext_cluster = c->mem.upload(ext_cluster);
+    c->pc_n_t_items = (int)(t_items.size() / 2);
+    c->pc_t_items = c->mem.upload(t_items);
     c->pc_inv_ptr = c->mem.upload(inv_ptr);
     c->pc_inv_pos = c->mem.upload(inv_pos);
     c->pc_tmp = c->mem.alloc<cx<double>>(n_ext);
@@ -466,9 +473,8 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
     launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
                          c->pc_r_off, c->pc_Rt, x, y, c->pc_max_ext, c->stream);
   else
-    launch_precond_apply_t(c->cl.nc, c->pc_n_ext, c->lay.N, c->pc_ext_ptr, c->pc_ext_cluster, c->pc_core_ptr,
-                           c->pc_core_slot, c->pc_r_off, c->pc_Rt, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y,
-                           c->stream);
+    launch_precond_apply_t(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
+                           c->pc_r_off, c->pc_Rt, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y, c->stream);
 }
 
 static int do_build(scabs_ctx *c) {

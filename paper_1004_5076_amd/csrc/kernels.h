@@ -160,7 +160,9 @@ template <typename T>
 void launch_interp_adj(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, hipStream_t s);
 template <typename T>
 void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y, hipStream_t s);
-void launch_precond_apply_t(int nc, int64_t n_ext, int64_t N, const int64_t *ext_ptr, const int *ext_cluster,
+// items: (cluster, first ext column) per work-group, precond_t_cols_per_item() columns each
+int precond_t_cols_per_item();
+void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
                             cx<double> *y, hipStream_t s);

@@ -461,35 +461,58 @@ template void launch_near_rows_t<double>(const DevOperator<double> &, const int6
 
 // ---------------------------------------------------------------------------
 // transposed Schwarz preconditioner: y = sum_c R_ext^T B_c^T P_core x with
-// B_c the stored core rows of cluster c's inverse.  Step 1: one wave per
-// (cluster, ext column j) forms dot(B_c[:, j], x[core_c]); step 2: every
-// unknown sums its entries over the clusters whose ext set holds it (fixed
-// order, no atomics).
+// B_c the stored core rows of cluster c's inverse.  Step 1: one work-group per
+// (cluster, block of PT_COLS ext columns) stages x on the cluster's core in
+// LDS; each wave then forms dot(B_c[:, j], x[core_c]) for its columns j,
+// reading each stored column once, contiguously.  Step 2: every unknown sums
+// its entries over the clusters whose ext set holds it (fixed order, no
+// atomics).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-precond_t_dots_kernel(int nc, const int64_t *__restrict__ ext_ptr, const int *__restrict__ ext_cluster,
+constexpr int PT_COLS = 64;
+constexpr int PT_THREADS = 512;
+constexpr int PT_MAXCORE = 4096;   // the largest cluster the Gauss-Jordan kernel inverts
+int precond_t_cols_per_item() { return PT_COLS; }
+
+__global__ void __launch_bounds__(PT_THREADS)
+precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                       const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
                       const int64_t *__restrict__ r_off, const cx<float> *__restrict__ Rt,
-                      const cx<double> *__restrict__ x, cx<double> *__restrict__ tmp, int64_t n_ext) {
-  const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (it >= n_ext) return;
-  const int c = ext_cluster[it];
-  const int j = (int)(it - ext_ptr[c]);
+                      const cx<double> *__restrict__ x, cx<double> *__restrict__ tmp) {
+  __shared__ cx<double> xs[PT_MAXCORE];
+  const int c = items[2 * blockIdx.x], j0 = items[2 * blockIdx.x + 1];
+  const int64_t e0 = ext_ptr[c];
+  const int ne = (int)(ext_ptr[c + 1] - e0);
   const int ncore = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const cx<float> *R = Rt + r_off[c] + (size_t)j * rt_stride(ncore);
   const int *cs = core_slot + core_ptr[c];
-  double ar = 0, ai = 0;
-  for (int i = lane; i < ncore; i += 64) {
-    const cx<float> rv = R[i];
-    const cx<double> xv = x[cs[i]];
-    ar += (double)rv.x * xv.x - (double)rv.y * xv.y;
-    ai += (double)rv.x * xv.y + (double)rv.y * xv.x;
+  for (int i = threadIdx.x; i < ncore; i += blockDim.x) xs[i] = x[cs[i]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t ncp = rt_stride(ncore);
+  const int j1 = min(j0 + PT_COLS, ne);
+  for (int j = j0 + w; j < j1; j += nw) {
+    const cx<float> *R = Rt + r_off[c] + (int64_t)j * ncp;
+    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    int i = lane;
+    for (; i + 192 < ncore; i += 256) {
+      cx<float> rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) rv[u] = R[i + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const cx<double> xv = xs[i + 64 * u];
+        ar[u] += (double)rv[u].x * xv.x - (double)rv[u].y * xv.y;
+        ai[u] += (double)rv[u].x * xv.y + (double)rv[u].y * xv.x;
+      }
+    }
+    for (; i < ncore; i += 64) {
+      const cx<float> rv = R[i];
+      const cx<double> xv = xs[i];
+      ar[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
+      ai[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
+    }
+    const double sr = wsum((ar[0] + ar[1]) + (ar[2] + ar[3])), si = wsum((ai[0] + ai[1]) + (ai[2] + ai[3]));
+    if (lane == 0) tmp[e0 + j] = {sr, si};
   }
-  ar = wsum(ar);
-  ai = wsum(ai);
-  if (lane == 0) tmp[it] = {ar, ai};
-  (void)nc;
 }
 
 __global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_ptr, const int64_t *__restrict__ inv_pos,
@@ -501,13 +524,12 @@ __global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_
   }
 }
 
-void launch_precond_apply_t(int nc, int64_t n_ext, int64_t N, const int64_t *ext_ptr, const int *ext_cluster,
+void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
                             cx<double> *y, hipStream_t s) {
-  const int64_t threads = n_ext * 64;
-  hipLaunchKernelGGL(precond_t_dots_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nc, ext_ptr,
-                     ext_cluster, core_ptr, core_slot, r_off, Rt, x, tmp, n_ext);
+  hipLaunchKernelGGL(precond_t_dots_kernel, dim3(n_items), dim3(PT_THREADS), 0, s, items, ext_ptr, core_ptr, core_slot,
+                     r_off, Rt, x, tmp);
   hipLaunchKernelGGL(precond_t_sum_kernel, dim3(1024), dim3(256), 0, s, N, inv_ptr, inv_pos, (const cx<double> *)tmp,
                      y);
 }

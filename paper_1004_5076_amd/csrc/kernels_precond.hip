@@ -288,7 +288,7 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
                      core_slot, r_off, Rt, x, y);
 }
 
-// Batched apply in single precision for the FP32 inner solves: nb <= 4
+// Batched apply in single precision for the FP32 inner solves: nb <= 8
 // vectors per launch, their ext entries staged in LDS as FP32 (all lanes of a
 // wave read the same column: broadcast), each coefficient read once for all
 // of them, FP32 accumulation.  Inner solves stop at relative residuals of
@@ -304,8 +304,10 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
                        const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
                        const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y,
                        int64_t N, int nb) {
+  // the column staging and, after the last pass, the partial sums share LDS
+  static_assert(PA32_Q * PA_ROWS <= PA32_CW, "partial sums must fit the staging buffer");
   __shared__ cx<float> xs[NB][PA32_CW];
-  __shared__ cx<float> red[PA32_Q][PA_ROWS][NB];
+  cx<float>(*red)[PA_ROWS][NB] = reinterpret_cast<cx<float>(*)[PA_ROWS][NB]>(&xs[0][0]);
   const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
@@ -349,6 +351,7 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
       }
     }
   }
+  __syncthreads();   // every wave is done with xs
 #pragma unroll
   for (int b = 0; b < NB; b++) red[q][il][b] = acc[b];
   __syncthreads();
@@ -364,7 +367,7 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
   }
 }
 
-int precond_apply32_max_batch() { return 4; }
+int precond_apply32_max_batch() { return 8; }
 
 // m <= precond_apply32_max_batch() vectors; max_ext (largest extended set)
 // sizes the LDS staging
@@ -380,8 +383,11 @@ void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_pt
   else if (m == 2)
     hipLaunchKernelGGL((precond_apply32_kernel<2>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
                        core_ptr, core_slot, r_off, Rt, x, y, N, m);
-  else
+  else if (m <= 4)
     hipLaunchKernelGGL((precond_apply32_kernel<4>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
+                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+  else
+    hipLaunchKernelGGL((precond_apply32_kernel<8>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
                        core_ptr, core_slot, r_off, Rt, x, y, N, m);
 }
 
