@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--edge", type=float, default=0.072)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--restart", type=int, default=240)
+    ap.add_argument("--restart", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the untimed single-solve and product-rate runs")
     ap.add_argument("--products-only", type=int, default=0,

@@ -12,12 +12,15 @@
 #include "kernels.h"
 
 namespace scabs {
-void kr_dots(const cx<double> *V, int64_t ldv, int jn, const cx<double> *w, int64_t N, cx<double> *part,
+template <typename VT>
+void kr_dots(const cx<VT> *V, int64_t ldv, int jn, const cx<double> *w, int64_t N, cx<double> *part,
              cx<double> *out, int accumulate, hipStream_t s);
-void kr_update(cx<double> *w, const cx<double> *V, int64_t ldv, int jn, const cx<double> *c, int64_t N, double sgn,
+template <typename VT>
+void kr_update(cx<double> *w, const cx<VT> *V, int64_t ldv, int jn, const cx<double> *c, int64_t N, double sgn,
                hipStream_t s);
 void kr_norm(const cx<double> *w, int64_t N, double *part, double *out, hipStream_t s);
-void kr_scale(cx<double> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s);
+template <typename VT> void kr_scale(cx<VT> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s);
+void kr_widen(const cx<float> *src, cx<double> *dst, int64_t n, hipStream_t s);
 void kr_residual(const cx<double> *b, cx<double> *r, int64_t N, hipStream_t s);
 void kr_axpy(cx<double> *x, const cx<double> *d, int64_t N, hipStream_t s);
 void kr_finite(const double *v, int64_t n, int *bad, hipStream_t s);
@@ -138,8 +141,14 @@ struct scabs_ctx {
   DevMem work;
   int work_restart = -1, work_nb = 0;
   int64_t work_N = -1;
-  cx<double> *V = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *hcol = nullptr, *part = nullptr;
+  cx<double> *w = nullptr, *r = nullptr, *d = nullptr, *hcol = nullptr, *part = nullptr;
   cx<double> *z = nullptr, *t = nullptr;
+  // Krylov bases: FP64 for FP64 solves, FP32 for the single-precision inner
+  // solves of the mixed mode (each grown on demand)
+  DevMem workV64, workV32;
+  int64_t cap_V64 = 0, cap_V32 = 0;   // complex entries
+  cx<double> *V64 = nullptr;
+  cx<float> *V32 = nullptr;
   // stage timing with HIP events on the context stream
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
@@ -297,6 +306,13 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
       G.ghat = (const cx<T> *)ghat64[gi];
     else
       G.ghat = (const cx<T> *)ghat32[gi];
+    G.ghx = nullptr;
+    if (G.twx) {
+      const int h0 = d.N[0] / 2 + 1, h1 = d.N[1] / 2 + 1, h2 = d.N[2] / 2 + 1;
+      cx<T> *ghx = c->mem.alloc<cx<T>>((size_t)h0 * h1 * h2);
+      launch_ghat_xfast<T>(G.ghat, ghx, h0, h1, h2, c->stream);
+      G.ghx = ghx;
+    }
     P.grids.push_back(G);
     // gather projection: the grid's points sorted by anchor cell
     std::vector<std::pair<int64_t, int>> key;
@@ -795,7 +811,9 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
 // ---------------------------------------------------------------------------
 // GMRES on a batch of right-hand sides (restarted; classical Gram-Schmidt
 // with a second pass where the first lost more than 1 - 1/sqrt(2) of the
-// vector's norm, Givens rotations, all in FP64).  The nb systems step
+// vector's norm, Givens rotations; sums and rotations in FP64, the basis
+// stored in FP64, or in FP32 for the single-precision inner solves, whose
+// tolerance is 1e-5 or looser and whose correction an FP64 residual checks).  The nb systems step
 // together: one batched preconditioner + product per Arnoldi step,
 // per-system orthogonalisation, one host synchronisation per step for all of
 // them (two when a system needs the second pass).
@@ -804,7 +822,6 @@ static void ensure_work(scabs_ctx *c, int restart, int nb) {
   int64_t N = c->lay.N;
   if (c->work_restart >= restart && c->work_N == N && c->work_nb >= nb) return;
   c->work.release();
-  c->V = c->work.alloc<cx<double>>((size_t)(restart + 1) * N * nb);
   c->w = c->work.alloc<cx<double>>(N * nb);
   c->r = c->work.alloc<cx<double>>(N * nb);
   c->d = c->work.alloc<cx<double>>(N * nb);
@@ -836,12 +853,44 @@ struct GmresResult {
 
 // Solve A sol_b = rhs_b (b < nb, vectors one after another) from sol = 0 to
 // ||rhs_b - A sol_b|| <= tol[b] ||rhs_b||.
+// the Krylov basis of restart + 1 vectors for nb systems, in FP64 or FP32
+static cx<double> *basis(scabs_ctx *c, int restart, int nb, cx<double> *) {
+  const int64_t need = (int64_t)(restart + 1) * c->lay.N * nb;
+  if (c->cap_V64 < need) {
+    c->workV64.release();
+    c->V64 = c->workV64.alloc<cx<double>>((size_t)need);
+    c->cap_V64 = need;
+  }
+  return c->V64;
+}
+static cx<float> *basis(scabs_ctx *c, int restart, int nb, cx<float> *) {
+  const int64_t need = (int64_t)(restart + 1) * c->lay.N * nb;
+  if (c->cap_V32 < need) {
+    c->workV32.release();
+    c->V32 = c->workV32.alloc<cx<float>>((size_t)need);
+    c->cap_V32 = need;
+  }
+  return c->V32;
+}
+// FP64 view of nb basis vectors for the operator (FP32 ones widened into t)
+static const cx<double> *operator_input(scabs_ctx *c, const cx<double> *v, int64_t n) {
+  (void)c;
+  (void)n;
+  return v;
+}
+static const cx<double> *operator_input(scabs_ctx *c, const cx<float> *v, int64_t n) {
+  kr_widen(v, c->t, n, c->stream);
+  return c->t;
+}
+
+template <typename VT>
 static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> *sol, int prec, const double *tol,
                         int max_iter, int restart, int &nmv, bool trans, std::vector<GmresResult> &res) {
   typedef std::complex<double> zd;
   hipStream_t s = c->stream;
   const int64_t N = c->lay.N;
   const int m = restart;
+  cx<VT> *const V = basis(c, restart, nb, (cx<VT> *)nullptr);
   const int64_t ldv = N * nb;   // V[j][b] at V + (j nb + b) N
   res.assign(nb, GmresResult());
   HIPCHK(hipMemsetAsync(sol, 0, sizeof(cx<double>) * N * nb, s));
@@ -867,7 +916,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     if (act.empty()) break;
     for (int b : act) {
       kr_norm(c->r + b * N, N, c->nrm_part, c->nrm + b, s);
-      kr_scale(c->V + b * N, c->r + b * N, c->nrm + b, N, s);
+      kr_scale(V + b * N, c->r + b * N, c->nrm + b, N, s);
       std::fill(g[b].begin(), g[b].end(), zd(0));
       g[b][0] = beta[b];
       jb[b] = 0;
@@ -875,7 +924,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     std::vector<int> run = act;
     int j = 0;
     while (j < m && !run.empty()) {
-      cx<double> *vj = c->V + (size_t)j * ldv;
+      const cx<double> *vj = operator_input(c, V + (size_t)j * ldv, ldv);
       if (c->has_pc) {
         apply_precond_n(c, vj, c->z, nb, trans, prec);
         matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
@@ -890,7 +939,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         for (int b : run) {
           cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b;
           cx<double> *wb = c->w + b * N;
-          const cx<double> *Vb = c->V + b * N;
+          const cx<VT> *Vb = V + b * N;
           kr_norm(wb, N, c->nrm_part, c->nrm + nb + b, s);
           kr_dots(Vb, ldv, j + 1, wb, N, c->part, h1, 0, s);
           kr_update(wb, Vb, ldv, j + 1, h1, N, -1.0, s);
@@ -910,7 +959,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         for (int b : reo) {
           cx<double> *h2 = c->hcol + 2 * (size_t)(m + 2) * b + (m + 2);
           cx<double> *wb = c->w + b * N;
-          const cx<double> *Vb = c->V + b * N;
+          const cx<VT> *Vb = V + b * N;
           kr_dots(Vb, ldv, j + 1, wb, N, c->part, h2, 0, s);
           kr_update(wb, Vb, ldv, j + 1, h2, N, -1.0, s);
           kr_norm(wb, N, c->nrm_part, c->nrm + b, s);
@@ -924,7 +973,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
           std::copy(hb2.begin() + 2 * (size_t)(m + 2) * b + (m + 2), hb2.begin() + 2 * (size_t)(m + 2) * (b + 1),
                     hb.begin() + 2 * (size_t)(m + 2) * b + (m + 2));
       }
-      for (int b : run) kr_scale(c->V + (size_t)(j + 1) * ldv + b * N, c->w + b * N, c->nrm + b, N, s);
+      for (int b : run) kr_scale(V + (size_t)(j + 1) * ldv + b * N, c->w + b * N, c->nrm + b, N, s);
       std::vector<int> next;
       for (int b : run) {
         const cx<double> *h1 = hb.data() + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
@@ -975,7 +1024,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       for (int i = 0; i < jj; i++) yb[i] = {y[i].real(), y[i].imag()};
       cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b;
       HIPCHK(hipMemcpyAsync(h1, yb.data(), sizeof(cx<double>) * jj, hipMemcpyHostToDevice, s));
-      kr_update(c->t + b * N, c->V + b * N, ldv, jj, h1, N, +1.0, s);
+      kr_update(c->t + b * N, V + b * N, ldv, jj, h1, N, +1.0, s);
       // the host vector yb must outlive the copy
       HIPCHK(hipStreamSynchronize(s));
     }
@@ -1044,7 +1093,10 @@ static int solve_batch(scabs_ctx *c, int nb, const cx<double> *b, cx<double> *x,
     }
     int nmv = 0;
     std::vector<GmresResult> g;
-    gmres_batch(c, na, rhs, corr, inner_prec, tin.data(), min_left, restart, nmv, trans, g);
+    if (inner_prec == SCABS_FP32)
+      gmres_batch<float>(c, na, rhs, corr, inner_prec, tin.data(), min_left, restart, nmv, trans, g);
+    else
+      gmres_batch<double>(c, na, rhs, corr, inner_prec, tin.data(), min_left, restart, nmv, trans, g);
     for (int a = 0; a < na; a++) {
       const int k = act[a];
       if (inner_prec == SCABS_FP32)

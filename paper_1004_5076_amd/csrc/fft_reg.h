@@ -139,24 +139,30 @@ template <int CTRL> __device__ __forceinline__ double dpp_mov(double x) {
 template <int CTRL, typename T> __device__ __forceinline__ cx<T> dpp_mov(cx<T> v) {
   return {dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y)};
 }
-// (this lane, partner) -> sum on the lower lane of the pair, partner - this on the upper
-template <int CTRL, typename T> __device__ __forceinline__ cx<T> quad_bfly(cx<T> v, bool upper) {
+// (this lane, partner) -> partner + sgn * this: the sum on the lower lane of
+// the pair (sgn = 1), partner - this on the upper (sgn = -1); one exact FMA
+template <int CTRL, typename T> __device__ __forceinline__ cx<T> quad_bfly(cx<T> v, T sgn) {
   const cx<T> o = dpp_mov<CTRL>(v);
-  return upper ? o - v : v + o;
+  return {fma(sgn, v.x, o.x), fma(sgn, v.y, o.y)};
 }
+// Lane signs of the two butterflies for lane p of a quad
+template <typename T> struct QuadSigns {
+  T s1, s2;   // -1 on the upper lane of the xor-1 / xor-2 pairs
+  __device__ explicit QuadSigns(int p) : s1((p & 1) ? T(-1) : T(1)), s2((p >= 2) ? T(-1) : T(1)) {}
+};
 // Forward: lane p (= lane & 3) holds z_p; afterwards lane p holds Z_{d(p)}
 // with d(p) = 2 (p & 1) + (p >> 1), Z_d = sum_p z_p exp(-2 pi i p d / 4).
 // Inverse (INV): the adjoint, from that order back to natural order with
 // exp(+2 pi i p d / 4).  Every lane of the wave must take part.
-template <typename T, bool INV> __device__ __forceinline__ cx<T> quad_dft4(cx<T> v, int p) {
+template <typename T, bool INV> __device__ __forceinline__ cx<T> quad_dft4(cx<T> v, int p, const QuadSigns<T> &q) {
   if (!INV) {
-    v = quad_bfly<DPP_XOR2>(v, p >= 2);
+    v = quad_bfly<DPP_XOR2>(v, q.s2);
     if (p == 3) v = cx<T>{v.y, -v.x};   // * (-i)
-    return quad_bfly<DPP_XOR1>(v, p & 1);
+    return quad_bfly<DPP_XOR1>(v, q.s1);
   }
-  v = quad_bfly<DPP_XOR1>(v, p & 1);
+  v = quad_bfly<DPP_XOR1>(v, q.s1);
   if (p == 3) v = cx<T>{-v.y, v.x};     // * (+i)
-  return quad_bfly<DPP_XOR2>(v, p >= 2);
+  return quad_bfly<DPP_XOR2>(v, q.s2);
 }
 
 }  // namespace scabs

@@ -22,6 +22,9 @@ template <typename T> struct DevGrid {
   // x lines of length 1024 only (else null): exp(-2 pi i a l / 1024) at
   // [a * 64 + l] (a < 16, l < 64), then exp(-2 pi i p c / 64) at [1024 + c * 4 + p]
   const cx<T> *twx;
+  // with twx: the kernel spectrum octant again, x fastest:
+  // [(k_y' (N2/2+1) + k_z') (N0/2+1) + k_x'] (null otherwise)
+  const cx<T> *ghx;
 };
 
 // Per-grid point lists for the gather projection: the grid's points sorted by
@@ -61,6 +64,8 @@ template <typename T> struct DevOperator {
 // nb vectors: phys/spec hold nb consecutive 8-field blocks
 constexpr int XLINE_REG_LEN = 1024;   // x length with the wave-per-line register transform
 template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb = 1);
+// ghx[(y h2 + z) h0 + x] = ghat[(x h1 + y) h2 + z]
+template <typename T> void launch_ghat_xfast(const cx<T> *ghat, cx<T> *ghx, int h0, int h1, int h2, hipStream_t s);
 // FFT of the circulant-embedded grid kernel; writes the scaled octant in both precisions
 hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int twL, cx<double> *ghat64,
                       cx<float> *ghat32, hipStream_t s);

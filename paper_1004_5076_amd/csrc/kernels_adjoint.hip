@@ -117,6 +117,33 @@ adj_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restr
 template <typename T> struct CellChunkT { static constexpr int value = 96; };
 template <> struct CellChunkT<double> { static constexpr int value = 48; };
 
+// one point's contribution to the node at offset (ox, oy, oz) from its anchor:
+// W c_value, -(grad W x vJ) on a_J, grad W . gp on phi_J, -(grad W x vM) on a_M
+template <typename T>
+__device__ __forceinline__ void adj_point(cx<T> *a, const cx<T> *c, const T *u, int ox, int oy, int oz, T inv_h) {
+  const T ux = u[0], uy = u[1], uz = u[2];
+  const T Lx = lag_w(ox, ux), Ly = lag_w(oy, uy), Lz = lag_w(oz, uz);
+  const T W = Lx * Ly * Lz, Wx = lag_d(ox, ux) * Ly * Lz * inv_h, Wy = Lx * lag_d(oy, uy) * Lz * inv_h,
+          Wz = Lx * Ly * lag_d(oz, uz) * inv_h;
+#pragma unroll
+  for (int f = 0; f < 8; f++) axpy(a[f], W, c[f]);
+  axpy(a[0], -Wy, c[10]);
+  axpy(a[0], Wz, c[9]);
+  axpy(a[1], -Wz, c[8]);
+  axpy(a[1], Wx, c[10]);
+  axpy(a[2], -Wx, c[9]);
+  axpy(a[2], Wy, c[8]);
+  axpy(a[4], -Wy, c[13]);
+  axpy(a[4], Wz, c[12]);
+  axpy(a[5], -Wz, c[11]);
+  axpy(a[5], Wx, c[13]);
+  axpy(a[6], -Wx, c[12]);
+  axpy(a[6], Wy, c[11]);
+  axpy(a[3], Wx, c[14]);
+  axpy(a[3], Wy, c[15]);
+  axpy(a[3], Wz, c[16]);
+}
+
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024)
 gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4, T inv_h) {
@@ -156,32 +183,19 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
       if (cy + oy >= 0 && cy + oy < n1 && cz + oz >= 0 && cz + oz < n2) {
         const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
         const int64_t p1 = g.cellptr[cell + 1];
-        for (int64_t p = g.cellptr[cell]; p < p1; p++) {
-          const T ux = g.u[3 * p], uy = g.u[3 * p + 1], uz = g.u[3 * p + 2];
-          const T Lx = lag_w(ox, ux), Ly = lag_w(oy, uy), Lz = lag_w(oz, uz);
-          const T W = Lx * Ly * Lz, Wx = lag_d(ox, ux) * Ly * Lz * inv_h, Wy = Lx * lag_d(oy, uy) * Lz * inv_h,
-                  Wz = Lx * Ly * lag_d(oz, uz) * inv_h;
-          const cx<T> *c = src4 + (size_t)ADJ_COEF * p;
+        int64_t p = g.cellptr[cell];
+        // two points' loads in flight (FP32; FP64 would spill)
+        for (; sizeof(T) == 4 && p + 2 <= p1; p += 2) {
+          cx<T> c0[ADJ_COEF], c1[ADJ_COEF];
 #pragma unroll
-          for (int f = 0; f < 8; f++) axpy(a[f], W, c[f]);
-          const cx<T> vJ0 = c[8], vJ1 = c[9], vJ2 = c[10], vM0 = c[11], vM1 = c[12], vM2 = c[13];
-          // -(grad W x vJ) on a_J, -(grad W x vM) on a_M
-          axpy(a[0], -Wy, vJ2);
-          axpy(a[0], Wz, vJ1);
-          axpy(a[1], -Wz, vJ0);
-          axpy(a[1], Wx, vJ2);
-          axpy(a[2], -Wx, vJ1);
-          axpy(a[2], Wy, vJ0);
-          axpy(a[4], -Wy, vM2);
-          axpy(a[4], Wz, vM1);
-          axpy(a[5], -Wz, vM0);
-          axpy(a[5], Wx, vM2);
-          axpy(a[6], -Wx, vM1);
-          axpy(a[6], Wy, vM0);
-          axpy(a[3], Wx, c[14]);
-          axpy(a[3], Wy, c[15]);
-          axpy(a[3], Wz, c[16]);
+          for (int f = 0; f < ADJ_COEF; f++) {
+            c0[f] = src4[(size_t)ADJ_COEF * p + f];
+            c1[f] = src4[(size_t)ADJ_COEF * (p + 1) + f];
+          }
+          adj_point(a, c0, g.u + 3 * p, ox, oy, oz, inv_h);
+          adj_point(a, c1, g.u + 3 * p + 3, ox, oy, oz, inv_h);
         }
+        for (; p < p1; p++) adj_point(a, src4 + (size_t)ADJ_COEF * p, g.u + 3 * p, ox, oy, oz, inv_h);
       }
 #pragma unroll
       for (int f = 0; f < 8; f++) s_q[f][it] = a[f];

@@ -196,14 +196,16 @@ static int reg_planes(int n1, int N2) { return std::max(1, PLANE_REG_THREADS / s
 // steps in reverse order back to x = l + 64 r.  The columns of a work-group
 // are staged through LDS (row-major global rows, one LDS line per column);
 // the exchange reuses the wave's own line.
-template <typename T> struct XRegCfg { static constexpr int threads = 512; };
-template <> struct XRegCfg<double> { static constexpr int threads = 256; };
+// minimum waves per SIMD the register budget is sized for (LDS allows two
+// work-groups per CU: 4 waves per SIMD in FP32)
+template <typename T> struct XRegCfg { static constexpr int threads = 512, min_waves = 4; };
+template <> struct XRegCfg<double> { static constexpr int threads = 256, min_waves = 2; };
 constexpr int XR_LS = 1096;   // LDS line stride: >= 16 x 68 exchange slots, = 8 (mod 64)
 constexpr int XR_XS = 68;     // exchange row stride
 
 template <typename T>
-__global__ void __launch_bounds__(XRegCfg<T>::threads)
-xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *__restrict__ ghat,
+__global__ void __launch_bounds__(XRegCfg<T>::threads, XRegCfg<T>::min_waves)
+xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *__restrict__ ghx,
                  const cx<T> *__restrict__ twx) {
   constexpr int C = XRegCfg<T>::threads / 64;
   extern __shared__ unsigned char smem_raw[];
@@ -246,26 +248,27 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
     for (int a = 0; a < 16; a++) ln[a * XR_XS + lane] = v[a];
     wave_lds_fence();
     const int qa = lane >> 2, p = lane & 3;
+    const QuadSigns<T> qs(p);
 #pragma unroll
     for (int s = 0; s < 16; s++) v[s] = ln[qa * XR_XS + p + 4 * s];
     rdft<T, 16, false>(v);
 #pragma unroll
     for (int c = 1; c < 16; c++) v[c] = v[c] * twx[XLINE_REG_LEN + c * 4 + p];
 #pragma unroll
-    for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, false>(v[c], p);
-    // product with the kernel spectrum (octant storage, mirrored indices)
+    for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, false>(v[c], p, qs);
+    // product with the kernel spectrum (octant storage with k_x fastest,
+    // mirrored indices: the 16 lanes of one d read 16 neighbouring entries)
     const int b = b0 + w, ky = b / N2, kz = b - ky * N2;
-    const int h1 = N1 / 2 + 1, h2 = N2 / 2 + 1;
-    const cx<T> *gl = ghat + (size_t)min(ky, N1 - ky) * h2 + min(kz, N2 - kz);
-    const size_t gs = (size_t)h1 * h2;
+    const int h2 = N2 / 2 + 1, h0 = XLINE_REG_LEN / 2 + 1;
+    const cx<T> *gl = ghx + ((size_t)min(ky, N1 - ky) * h2 + min(kz, N2 - kz)) * h0;
     const int d = 2 * (p & 1) + (p >> 1);
 #pragma unroll
     for (int c = 0; c < 16; c++) {
       const int kx = qa + 16 * c + 256 * d;
-      v[c] = v[c] * gl[(size_t)min(kx, XLINE_REG_LEN - kx) * gs];
+      v[c] = v[c] * gl[min(kx, XLINE_REG_LEN - kx)];
     }
 #pragma unroll
-    for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, true>(v[c], p);
+    for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, true>(v[c], p, qs);
 #pragma unroll
     for (int c = 1; c < 16; c++) v[c] = twm<T, true>(v[c], twx[XLINE_REG_LEN + c * 4 + p]);
     rdft<T, 16, true>(v);
@@ -343,9 +346,9 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
   const int C = xline_lines<T>(N0);
   const int nlb = (N1 * N2 + C - 1) / C;
   constexpr int CR = XRegCfg<T>::threads / 64;
-  if (g.twx && N0 == XLINE_REG_LEN && n0 <= XLINE_REG_LEN / 2)
+  if (g.twx && g.ghx && N0 == XLINE_REG_LEN && n0 <= XLINE_REG_LEN / 2)
     hipLaunchKernelGGL(xline_reg_kernel<T>, dim3((N1 * N2 + CR - 1) / CR, 8 * nb), dim3(XRegCfg<T>::threads),
-                       sizeof(cx<T>) * (size_t)CR * XR_LS, s, g.spec, n0, N1, N2, g.ghat, g.twx);
+                       sizeof(cx<T>) * (size_t)CR * XR_LS, s, g.spec, n0, N1, N2, g.ghx, g.twx);
   else if (FftCfg<T>::wave && wave_fits(N0, C, nw, EW))
     hipLaunchKernelGGL((xline_kernel<T, true>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
                        g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
@@ -364,6 +367,22 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
 }
 template void launch_conv<float>(const DevGrid<float> &, hipStream_t, int);
 template void launch_conv<double>(const DevGrid<double> &, hipStream_t, int);
+
+template <typename T>
+__global__ void ghat_xfast_kernel(const cx<T> *__restrict__ ghat, cx<T> *__restrict__ ghx, int h0, int h1, int h2) {
+  const size_t total = (size_t)h0 * h1 * h2;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % h0);
+    const size_t yz = i / h0;
+    const int z = (int)(yz % h2), y = (int)(yz / h2);
+    ghx[i] = ghat[((size_t)x * h1 + y) * h2 + z];
+  }
+}
+template <typename T> void launch_ghat_xfast(const cx<T> *ghat, cx<T> *ghx, int h0, int h1, int h2, hipStream_t s) {
+  hipLaunchKernelGGL(ghat_xfast_kernel<T>, dim3(256), dim3(256), 0, s, ghat, ghx, h0, h1, h2);
+}
+template void launch_ghat_xfast<float>(const cx<float> *, cx<float> *, int, int, int, hipStream_t);
+template void launch_ghat_xfast<double>(const cx<double> *, cx<double> *, int, int, int, hipStream_t);
 
 // ---- kernel spectrum -----------------------------------------------------------
 // circulant embedding of H(d) = G(h |d|) (H(0) = 0) on N0 x N1 x N2, offsets

@@ -18,18 +18,21 @@ __device__ inline double block_sum(double v, double *sh) {
   return r;
 }
 
-// part[j * nb + b] = sum over rows of chunk b of conj(V_j) w
+// part[j * nb + b] = sum over rows of chunk b of conj(V_j) w (V in FP64, or
+// FP32 for the basis of the single-precision inner solves; FP64 sums)
+template <typename VT>
 __global__ void __launch_bounds__(KR_THREADS)
-dots_partial(const cx<double> *__restrict__ V, int64_t ldv, const cx<double> *__restrict__ w, int64_t N,
+dots_partial(const cx<VT> *__restrict__ V, int64_t ldv, const cx<double> *__restrict__ w, int64_t N,
              cx<double> *__restrict__ part) {
   __shared__ double sh[2][KR_THREADS / 64];
   const int j = blockIdx.y, nb = gridDim.x;
-  const cx<double> *v = V + (size_t)j * ldv;
+  const cx<VT> *v = V + (size_t)j * ldv;
   double re = 0, im = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)nb * blockDim.x) {
-    cx<double> a = v[i], b = w[i];
-    re += a.x * b.x + a.y * b.y;
-    im += a.x * b.y - a.y * b.x;
+    const cx<VT> a = v[i];
+    const cx<double> b = w[i];
+    re += (double)a.x * b.x + (double)a.y * b.y;
+    im += (double)a.x * b.y - (double)a.y * b.x;
   }
   re = block_sum(re, sh[0]);
   im = block_sum(im, sh[1]);
@@ -59,13 +62,15 @@ __global__ void reduce_parts(const cx<double> *__restrict__ part, int nb, int jn
 }
 
 // w += sgn * sum_{j < jn} V_j c_j
+template <typename VT>
 __global__ void __launch_bounds__(KR_THREADS)
-basis_update(cx<double> *__restrict__ w, const cx<double> *__restrict__ V, int64_t ldv, int jn,
+basis_update(cx<double> *__restrict__ w, const cx<VT> *__restrict__ V, int64_t ldv, int jn,
              const cx<double> *__restrict__ c, int64_t N, double sgn) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     cx<double> acc = w[i];
     for (int j = 0; j < jn; j++) {
-      cx<double> t = V[(size_t)j * ldv + i] * c[j];
+      const cx<VT> v = V[(size_t)j * ldv + i];
+      const cx<double> t = cx<double>{(double)v.x, (double)v.y} * c[j];
       acc.x += sgn * t.x;
       acc.y += sgn * t.y;
     }
@@ -93,13 +98,20 @@ __global__ void reduce_norm(const double *__restrict__ part, int nb, double *out
   if (threadIdx.x == 0) *out = sqrt(s);
 }
 
-// dst = src / *nrm (nrm > 0), else dst = 0
-__global__ void scale_by_inv(cx<double> *__restrict__ dst, const cx<double> *__restrict__ src, const double *nrm,
+// dst = src / *nrm (nrm > 0), else dst = 0; dst in FP64 or FP32
+template <typename VT>
+__global__ void scale_by_inv(cx<VT> *__restrict__ dst, const cx<double> *__restrict__ src, const double *nrm,
                              int64_t N) {
   const double n = *nrm;
   const double s = n > 0 ? 1.0 / n : 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i] * s;
+    dst[i] = {(VT)(src[i].x * s), (VT)(src[i].y * s)};
+}
+
+// FP32 basis vectors -> FP64 operator input
+__global__ void widen_kernel(const cx<float> *__restrict__ src, cx<double> *__restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = {(double)src[i].x, (double)src[i].y};
 }
 
 // r = b - r (in place on r, which holds A x)
@@ -124,24 +136,39 @@ static int reduce_blocks(int64_t N) {
   return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
-void kr_dots(const cx<double> *V, int64_t ldv, int jn, const cx<double> *w, int64_t N, cx<double> *part,
+template <typename VT>
+void kr_dots(const cx<VT> *V, int64_t ldv, int jn, const cx<double> *w, int64_t N, cx<double> *part,
              cx<double> *out, int accumulate, hipStream_t s) {
   int nb = reduce_blocks(N);
   if (nb > 256) nb = 256;
-  hipLaunchKernelGGL(dots_partial, dim3(nb, jn), dim3(KR_THREADS), 0, s, V, ldv, w, N, part);
+  hipLaunchKernelGGL(dots_partial<VT>, dim3(nb, jn), dim3(KR_THREADS), 0, s, V, ldv, w, N, part);
   hipLaunchKernelGGL(reduce_parts, dim3(jn), dim3(KR_THREADS), 0, s, part, nb, jn, out, accumulate);
 }
-void kr_update(cx<double> *w, const cx<double> *V, int64_t ldv, int jn, const cx<double> *c, int64_t N, double sgn,
+template <typename VT>
+void kr_update(cx<double> *w, const cx<VT> *V, int64_t ldv, int jn, const cx<double> *c, int64_t N, double sgn,
                hipStream_t s) {
-  hipLaunchKernelGGL(basis_update, dim3(reduce_blocks(N)), dim3(KR_THREADS), 0, s, w, V, ldv, jn, c, N, sgn);
+  hipLaunchKernelGGL(basis_update<VT>, dim3(reduce_blocks(N)), dim3(KR_THREADS), 0, s, w, V, ldv, jn, c, N, sgn);
+}
+template <typename VT> void kr_scale(cx<VT> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(scale_by_inv<VT>, dim3(reduce_blocks(N)), dim3(KR_THREADS), 0, s, dst, src, nrm, N);
+}
+template void kr_dots<double>(const cx<double> *, int64_t, int, const cx<double> *, int64_t, cx<double> *,
+                              cx<double> *, int, hipStream_t);
+template void kr_dots<float>(const cx<float> *, int64_t, int, const cx<double> *, int64_t, cx<double> *,
+                             cx<double> *, int, hipStream_t);
+template void kr_update<double>(cx<double> *, const cx<double> *, int64_t, int, const cx<double> *, int64_t, double,
+                                hipStream_t);
+template void kr_update<float>(cx<double> *, const cx<float> *, int64_t, int, const cx<double> *, int64_t, double,
+                               hipStream_t);
+template void kr_scale<double>(cx<double> *, const cx<double> *, const double *, int64_t, hipStream_t);
+template void kr_scale<float>(cx<float> *, const cx<double> *, const double *, int64_t, hipStream_t);
+void kr_widen(const cx<float> *src, cx<double> *dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(widen_kernel, dim3(reduce_blocks(n)), dim3(KR_THREADS), 0, s, src, dst, n);
 }
 void kr_norm(const cx<double> *w, int64_t N, double *part, double *out, hipStream_t s) {
   int nb = reduce_blocks(N);
   hipLaunchKernelGGL(norm2_partial, dim3(nb), dim3(KR_THREADS), 0, s, w, N, part);
   hipLaunchKernelGGL(reduce_norm, dim3(1), dim3(KR_THREADS), 0, s, part, nb, out);
-}
-void kr_scale(cx<double> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s) {
-  hipLaunchKernelGGL(scale_by_inv, dim3(reduce_blocks(N)), dim3(KR_THREADS), 0, s, dst, src, nrm, N);
 }
 void kr_residual(const cx<double> *b, cx<double> *r, int64_t N, hipStream_t s) {
   hipLaunchKernelGGL(residual_kernel, dim3(reduce_blocks(N)), dim3(KR_THREADS), 0, s, b, r, N);

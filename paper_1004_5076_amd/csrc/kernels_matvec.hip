@@ -137,7 +137,23 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
       if (cy + oy >= 0 && cy + oy < n1 && cz + oz >= 0 && cz + oz < n2) {
         const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
         const int64_t p1 = g.cellptr[cell + 1];
-        for (int64_t p = g.cellptr[cell]; p < p1; p++) {
+        int64_t p = g.cellptr[cell];
+        // two points' loads in flight (FP32; FP64 would spill)
+        for (; sizeof(T) == 4 && p + 2 <= p1; p += 2) {
+          cx<T> s0[8], s1[8];
+#pragma unroll
+          for (int f = 0; f < 8; f++) {
+            s0[f] = gsrc[8 * p + f];
+            s1[f] = gsrc[8 * p + 8 + f];
+          }
+          const T w0 = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]) * lag_w(oz, g.u[3 * p + 2]);
+          const T w1 = lag_w(ox, g.u[3 * p + 3]) * lag_w(oy, g.u[3 * p + 4]) * lag_w(oz, g.u[3 * p + 5]);
+#pragma unroll
+          for (int f = 0; f < 8; f++) axpy(a[f], w0, s0[f]);
+#pragma unroll
+          for (int f = 0; f < 8; f++) axpy(a[f], w1, s1[f]);
+        }
+        for (; p < p1; p++) {
           const T w = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]) * lag_w(oz, g.u[3 * p + 2]);
 #pragma unroll
           for (int f = 0; f < 8; f++) axpy(a[f], w, gsrc[8 * p + f]);
