@@ -21,6 +21,14 @@ void kr_update(cx<double> *w, const cx<VT> *V, int64_t ldv, int jn, const cx<dou
 void kr_norm(const cx<double> *w, int64_t N, double *part, double *out, hipStream_t s);
 template <typename VT> void kr_scale(cx<VT> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s);
 void kr_widen(const cx<float> *src, cx<double> *dst, int64_t n, hipStream_t s);
+template <typename VT>
+void kr_ortho_pass(const cx<VT> *V, int64_t ldv, int jn, cx<double> *w, int64_t N, const KrRun &run, int with_norm,
+                   cx<double> *part, double *npart, cx<double> *hcol, int64_t hstride, int64_t hoff,
+                   double *nrm_before, double *nrm_after, hipStream_t s);
+template <typename VT>
+void kr_scale_run(cx<VT> *Vdst, const cx<double> *w, const double *nrm, int64_t N, const KrRun &run, hipStream_t s);
+size_t kr_ortho_part_entries(int jn_max, int nsys);
+size_t kr_ortho_npart_entries(int64_t N, int nsys);
 void kr_residual(const cx<double> *b, cx<double> *r, int64_t N, hipStream_t s);
 void kr_axpy(cx<double> *x, const cx<double> *d, int64_t N, hipStream_t s);
 void kr_finite(const double *v, int64_t n, int *bad, hipStream_t s);
@@ -154,7 +162,7 @@ struct scabs_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_recs;
-  double *nrm = nullptr, *nrm_part = nullptr;
+  double *nrm = nullptr, *nrm_part = nullptr, *npart = nullptr;
   int *flag = nullptr;
 };
 
@@ -828,7 +836,8 @@ static void ensure_work(scabs_ctx *c, int restart, int nb) {
   c->z = c->work.alloc<cx<double>>(N * nb);
   c->t = c->work.alloc<cx<double>>(N * nb);
   c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2) * nb);
-  c->part = c->work.alloc<cx<double>>((size_t)256 * (restart + 2));
+  c->part = c->work.alloc<cx<double>>(std::max((size_t)256 * (restart + 2), kr_ortho_part_entries(restart + 1, nb)));
+  c->npart = c->work.alloc<double>(kr_ortho_npart_entries(N, nb));
   c->nrm = c->work.alloc<double>(2 * nb + 4);
   c->nrm_part = c->work.alloc<double>(1024);
   c->flag = c->work.alloc<int>(1);
@@ -933,18 +942,19 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       }
       nmv += (int)run.size();
       // classical Gram-Schmidt, repeated only where it lost too much of w
-      // (Daniel-Gragg-Kaufman-Stewart test ||w1|| < ||w|| / sqrt(2))
+      // (Daniel-Gragg-Kaufman-Stewart test ||w1|| < ||w|| / sqrt(2)); one
+      // set of launches for all running systems
+      const int64_t hstride = 2 * (int64_t)(m + 2);
+      auto to_run = [](const std::vector<int> &v) {
+        KrRun r{};
+        r.n = (int)v.size();
+        for (size_t i = 0; i < v.size(); i++) r.b[i] = v[i];
+        return r;
+      };
       {
         StageTimer tm(c, SCABS_STAGE_ORTHO);
-        for (int b : run) {
-          cx<double> *h1 = c->hcol + 2 * (size_t)(m + 2) * b;
-          cx<double> *wb = c->w + b * N;
-          const cx<VT> *Vb = V + b * N;
-          kr_norm(wb, N, c->nrm_part, c->nrm + nb + b, s);
-          kr_dots(Vb, ldv, j + 1, wb, N, c->part, h1, 0, s);
-          kr_update(wb, Vb, ldv, j + 1, h1, N, -1.0, s);
-          kr_norm(wb, N, c->nrm_part, c->nrm + b, s);
-        }
+        kr_ortho_pass(V, ldv, j + 1, c->w, N, to_run(run), 1, c->part, c->npart, c->hcol, hstride, 0, c->nrm + nb,
+                      c->nrm, s);
       }
       HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
@@ -955,16 +965,12 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         if (hn[b] < 0.7071067811865476 * hn[nb + b]) reo.push_back(b);
       }
       if (!reo.empty()) {
-        StageTimer tm(c, SCABS_STAGE_ORTHO);
-        for (int b : reo) {
-          cx<double> *h2 = c->hcol + 2 * (size_t)(m + 2) * b + (m + 2);
-          cx<double> *wb = c->w + b * N;
-          const cx<VT> *Vb = V + b * N;
-          kr_dots(Vb, ldv, j + 1, wb, N, c->part, h2, 0, s);
-          kr_update(wb, Vb, ldv, j + 1, h2, N, -1.0, s);
-          kr_norm(wb, N, c->nrm_part, c->nrm + b, s);
-          reo2[b] = 1;
+        {
+          StageTimer tm(c, SCABS_STAGE_ORTHO);
+          kr_ortho_pass(V, ldv, j + 1, c->w, N, to_run(reo), 0, c->part, c->npart, c->hcol, hstride, m + 2,
+                        c->nrm + nb, c->nrm, s);
         }
+        for (int b : reo) reo2[b] = 1;
         std::vector<cx<double>> hb2(hb.size());
         HIPCHK(hipMemcpyAsync(hb2.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
@@ -973,7 +979,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
           std::copy(hb2.begin() + 2 * (size_t)(m + 2) * b + (m + 2), hb2.begin() + 2 * (size_t)(m + 2) * (b + 1),
                     hb.begin() + 2 * (size_t)(m + 2) * b + (m + 2));
       }
-      for (int b : run) kr_scale(V + (size_t)(j + 1) * ldv + b * N, c->w + b * N, c->nrm + b, N, s);
+      kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(run), s);
       std::vector<int> next;
       for (int b : run) {
         const cx<double> *h1 = hb.data() + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
@@ -1493,6 +1499,8 @@ void scabs_destroy(scabs_ctx *c) {
   hipSetDevice(c->opts.device);
   if (c->stream) hipStreamSynchronize(c->stream);
   c->work.release();
+  c->workV64.release();
+  c->workV32.release();
   c->mem.release();
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);

@@ -133,4 +133,11 @@ struct EdgeRec {
 
 inline int pack_anchor(int x, int y, int z) { return x | (y << 14) | (z << 23); }
 
+// the systems of a GMRES batch taking part in one step (kernel argument)
+constexpr int KR_MAX_SYSTEMS = 8;
+struct KrRun {
+  int n;
+  int b[KR_MAX_SYSTEMS];
+};
+
 }  // namespace scabs
