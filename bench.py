@@ -17,9 +17,12 @@ gradient.  value = operator products per second over the timed steps
 
 Also reported: single-dipole mixed and FP64 solve times (the mixed/FP64
 comparison), standalone product rates (1 and 8 vectors), per-stage averages
-from HIP events, the roofline of the dominant kernel (the Schwarz
-preconditioner apply, HBM-bound) measured with HIP events on the library
-stream over the timed region, and the oracle timed on the host.
+from HIP events, the rooflines of the x-line transforms of the FP32
+convolution, the FP32 projection gather and the FP32 Schwarz apply (the
+kernels with the largest shares of a step; "roofline" is the one with the
+largest measured total),
+measured with HIP events on the library stream over the timed region, and
+the oracle timed on the host.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -40,29 +43,47 @@ HBM_PEAK_GBS = 8000.0
 BATCH = 8
 
 
-def precond_bytes(info: dict, m: int) -> float:
-    """Algorithmic bytes of one preconditioner apply to m vectors (the dominant
-    kernel): every stored FP32 complex coefficient once (8 B), per
-    extended-set entry its unknown index (4 B) and m FP64 complex inputs
-    (16 B each), per unknown its core index (4 B) and m FP64 complex outputs."""
-    return 8.0 * info["precond_entries"] + (4.0 + 16.0 * m) * (info["precond_ext_entries"] + info["N"])
-
-
 def kernel_src_sha(name: str) -> str:
     p = os.path.join(ROOT, "paper_1004_5076_amd", "csrc", name)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the preconditioner apply from committed
-    rocprofv3 counter runs, only if they were taken on the current source."""
-    p = os.path.join(ROOT, "profiles", "precond_apply_two_channel_traffic.json")
+# kernels whose roofline is reported: stage record, kernel name, source file
+ROOFLINE_KERNELS = {
+    "xline32": ("xline_reg_kernel<float>", "kernels_fft.hip"),
+    "gather32": ("gather_kernel<float, 1>", "kernels_matvec.hip"),
+    "precond": ("precond_apply32_kernel<8>", "kernels_precond.hip"),
+}
+
+
+def measured_ratio(stage: str):
+    """HBM bytes over algorithmic bytes of a kernel from committed rocprofv3
+    counter runs (FETCH_SIZE and WRITE_SIZE, calibrated on a device copy),
+    only if they were taken on the current source of the kernel."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s_two_channel.json" % stage)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_src_sha") != kernel_src_sha("kernels_precond.hip"):
+    if d.get("kernel_src_sha") != kernel_src_sha(ROOFLINE_KERNELS[stage][1]):
         return None
-    return d.get("bytes_per_launch")
+    return d.get("ratio")
+
+
+def roofline(prof: dict, stage: str) -> dict:
+    """Roofline of one kernel from the stage records of the timed region:
+    algorithmic bytes per launch (summed by the library per record) over the
+    average launch time from HIP events on the library stream."""
+    rec = prof[stage]
+    n = max(rec["count"], 1)
+    avg_s = rec["ms"] / n * 1e-3
+    bytes_launch = rec["bytes"] / n
+    achieved = bytes_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    ratio = measured_ratio(stage)
+    return {"kernel": ROOFLINE_KERNELS[stage][0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": ratio * bytes_launch if ratio is not None else None,
+            "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6, "launches": rec["count"],
+            "total_ms": rec["ms"]}
 
 
 def dipole_field_y(w, d, p):
@@ -146,21 +167,27 @@ def main():
     d0 = w.dipoles[0]
 
     if args.products_only:
-        x = torch.from_numpy(synth.random_complex(3, N)).to(dev)
-        for _ in range(args.products_only):
-            ctx.matvec(x, prec=pk.SCABS_FP32)
+        # the roofline kernels alone, for counter runs: batched FP32 products
+        # and one GMRES step of the batch (one FP32 Schwarz apply to 8 vectors)
+        X = torch.from_numpy(np.stack([synth.random_complex(3 + k, N) for k in range(BATCH)])).to(dev)
         b = ctx.rhs_dipole(d0.pos, d0.moment, d0.body)
         bb = torch.stack([b] * BATCH).contiguous()
-        for _ in range(args.products_only):   # one GMRES step: one FP32 apply to the batch
-            ctx.solve(bb, tol=0.5, max_iter=1, restart=1, mode=pk.SCABS_MIXED)
+        ctx.matvec(X, prec=pk.SCABS_FP32)
         torch.cuda.synchronize()
+        ctx.profile_begin()
+        for _ in range(args.products_only):
+            ctx.matvec(X, prec=pk.SCABS_FP32)
+        for _ in range(args.products_only):
+            ctx.solve(bb, tol=0.5, max_iter=1, restart=1, mode=pk.SCABS_MIXED)
+        prof = ctx.profile_end()
         a = torch.ones(1 << 26, dtype=torch.float32, device=dev)   # 2^28 bytes read, 2^28 written
         c = torch.empty_like(a)
         c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"products": args.products_only, "N": N, "copy_bytes": 1 << 28, "info": info,
-                          "precond_alg_bytes": precond_bytes(info, BATCH),
-                          "kernel_src_sha": kernel_src_sha("kernels_precond.hip")}))
+                          "stages": {k: prof[k] for k in ROOFLINE_KERNELS},
+                          "kernels": {k: v[0] for k, v in ROOFLINE_KERNELS.items()},
+                          "kernel_src_sha": {k: kernel_src_sha(v[1]) for k, v in ROOFLINE_KERNELS.items()}}))
         ctx.close()
         return
 
@@ -244,14 +271,12 @@ def main():
         extras["product_rates_per_s"] = rates
         log("extras", extras)
 
-    # the FP32 Schwarz preconditioner apply to the batch (one kernel per stage
-    # event; launches after some systems converged carry fewer vectors and
-    # are counted at the full batch, an overestimate of at most 16 B per
-    # missing vector and extended entry)
-    pc = prof["precond"]
-    avg_s = pc["ms"] / max(pc["count"], 1) * 1e-3
-    bytes_alg = precond_bytes(info, BATCH)
-    achieved = bytes_alg / avg_s / 1e9 if avg_s > 0 else 0.0
+    # rooflines of the three kernels with the largest share of the step in
+    # the kernel trace: the x-line transforms of the FP32 convolution, the
+    # FP32 projection gather and the FP32 Schwarz apply; "roofline" is the one
+    # with the largest measured total
+    roofs = {k: roofline(prof, k) for k in ROOFLINE_KERNELS}
+    top = max(roofs, key=lambda k: roofs[k]["total_ms"])
     single_m = extras.get("solve_single_mixed", {}).get("seconds")
     single_d = extras.get("solve_single_fp64", {}).get("seconds")
     out = {
@@ -282,9 +307,8 @@ def main():
         "setup_s": setup_s,
         "stage_avg_us": stage_avg_us,
         "stage_total_ms": stage_total_ms,
-        "roofline": {"kernel": "precond_apply32_kernel<8>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "bytes_per_launch": bytes_alg, "avg_launch_us": avg_s * 1e6},
+        "roofline": roofs[top],
+        "rooflines": roofs,
     }
     if not args.no_cpu_baseline:
         try:

@@ -218,9 +218,26 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
 #define SCABS_STAGE_PRECOND 10   /* preconditioner application */
 #define SCABS_STAGE_ORTHO 11     /* Gram-Schmidt, norms (FP64) */
 #define SCABS_STAGE_PRECOND_T 12 /* transposed preconditioner application */
-#define SCABS_NSTAGES 13
+#define SCABS_STAGE_XLINE32 13   /* x-line transforms and kernel product of the FP32
+                                    convolution, one record per grid (inside stage
+                                    SCABS_STAGE_FFT + SCABS_STAGE_FP32_OFFSET) */
+#define SCABS_STAGE_GATHER32 14  /* lattice gather of the FP32 projection, one record
+                                    per grid (inside stage SCABS_STAGE_PROJECT +
+                                    SCABS_STAGE_FP32_OFFSET) */
+#define SCABS_NSTAGES 15
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
+/* Algorithmic HBM bytes of the records of each stage of the last finished
+ * profiling session (SCABS_NSTAGES entries, written to the caller's host
+ * array; 0 for stages that do not define them).  SCABS_STAGE_XLINE32: the
+ * physical x range of every transformed line read and written once;
+ * SCABS_STAGE_GATHER32: the 8 weighted sources of every point read once and
+ * the 8 fields of every lattice node written once;
+ * SCABS_STAGE_PRECOND (FP32 inner solves): every stored coefficient once, per
+ * extended-set entry its index and the FP64 inputs of the vectors applied, per
+ * unknown its index and FP64 outputs.  Returns SCABS_E_ARG for null
+ * arguments. */
+int scabs_profile_bytes(const scabs_ctx *c, double *bytes);
 
 const char *scabs_last_error(const scabs_ctx *c);
 void scabs_destroy(scabs_ctx *c);

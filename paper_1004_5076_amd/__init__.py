@@ -26,9 +26,10 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_incident_dipole_points",
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
-            "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_last_error", "scabs_destroy"]
+            "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_bytes",
+            "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
-          "near32", "precond", "ortho", "precond_t"]
+          "near32", "precond", "ortho", "precond_t", "xline32", "gather32"]
 
 
 class ScabsError(RuntimeError):
@@ -100,6 +101,7 @@ def load() -> C.CDLL:
     L.scabs_sigma_gradient.argtypes = [P, P, P, P, P, dp]
     L.scabs_profile_begin.argtypes = [P]
     L.scabs_profile_end.argtypes = [P, dp, C.POINTER(C.c_int64)]
+    L.scabs_profile_bytes.argtypes = [P, dp]
     L.scabs_last_error.restype = C.c_char_p
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
@@ -293,7 +295,9 @@ class Context:
         ms = (C.c_double * len(STAGES))()
         cnt = (C.c_int64 * len(STAGES))()
         self._check(self._L.scabs_profile_end(self._c, ms, cnt))
-        return {name: {"ms": ms[k], "count": cnt[k]} for k, name in enumerate(STAGES)}
+        nbytes = (C.c_double * len(STAGES))()
+        self._check(self._L.scabs_profile_bytes(self._c, nbytes))
+        return {name: {"ms": ms[k], "count": cnt[k], "bytes": nbytes[k]} for k, name in enumerate(STAGES)}
 
     def solve(self, b, x0=None, tol: float = 1e-6, max_iter: int = 2000, restart: int = 60,
               mode: int = SCABS_MIXED, raise_on_noconv: bool = False, transpose: bool = False):

@@ -141,6 +141,7 @@ struct scabs_ctx {
   cx<float> *pc_Rt = nullptr;
   // transposed apply: cluster of every ext entry, and per unknown its ext entries
   int64_t pc_n_ext = 0;
+  int64_t pc_coef = 0;   // stored preconditioner coefficients (core rows x ext columns, unpadded)
   int *pc_t_items = nullptr;   // (cluster, first ext column) per transposed-apply work-group
   int pc_n_t_items = 0;
   int64_t *pc_inv_ptr = nullptr, *pc_inv_pos = nullptr;
@@ -161,7 +162,13 @@ struct scabs_ctx {
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_recs;
+  struct ProfRec {
+    int stage;
+    hipEvent_t e0, e1;
+    double bytes;   // algorithmic HBM bytes of the bracketed work (0: not defined)
+  };
+  std::vector<ProfRec> prof_recs;
+  double prof_bytes[SCABS_NSTAGES] = {};   // per stage, last finished session
   double *nrm = nullptr, *nrm_part = nullptr, *npart = nullptr;
   int *flag = nullptr;
 };
@@ -170,8 +177,9 @@ struct scabs_ctx {
 struct StageTimer {
   scabs_ctx *c;
   int stage;
+  double bytes;
   hipEvent_t e0 = nullptr;
-  StageTimer(scabs_ctx *cc, int st);
+  StageTimer(scabs_ctx *cc, int st, double b = 0);
   ~StageTimer();
 };
 
@@ -183,7 +191,7 @@ static hipEvent_t next_event(scabs_ctx *c) {
   }
   return c->ev_pool[c->ev_used++];
 }
-StageTimer::StageTimer(scabs_ctx *cc, int st) : c(cc), stage(st) {
+StageTimer::StageTimer(scabs_ctx *cc, int st, double b) : c(cc), stage(st), bytes(b) {
   if (c->prof_on && (e0 = next_event(c))) hipEventRecord(e0, c->stream);
 }
 StageTimer::~StageTimer() {
@@ -191,7 +199,7 @@ StageTimer::~StageTimer() {
   hipEvent_t e1 = next_event(c);
   if (!e1) return;
   hipEventRecord(e1, c->stream);
-  c->prof_recs.push_back({stage, {e0, e1}});
+  c->prof_recs.push_back({stage, e0, e1, bytes});
 }
 
 static int fail(scabs_ctx *c, int code, const std::string &m) {
@@ -453,6 +461,9 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
     std::vector<int64_t> fill(inv_ptr.begin(), inv_ptr.end() - 1);
     for (int64_t q = 0; q < n_ext; q++) inv_pos[fill[cl.ext_slot[q]]++] = q;
     c->pc_n_ext = n_ext;
+    c->pc_coef = 0;
+    for (int k = 0; k < cl.nc; k++)
+      c->pc_coef += (cl.ext_ptr[k + 1] - cl.ext_ptr[k]) * (cl.core_ptr[k + 1] - cl.core_ptr[k]);
     c->pc_n_t_items = (int)(t_items.size() / 2);
     c->pc_t_items = c->mem.upload(t_items);
     c->pc_inv_ptr = c->mem.upload(inv_ptr);
@@ -721,6 +732,26 @@ template <typename T> static void ensure_batch(scabs_ctx *c, PrecState<T> &P, in
   P.bcap = nb;
 }
 
+// lattice convolutions of all grids; in FP32 the x-line transforms of each
+// grid also get a record of their own (algorithmic bytes: the physical x range
+// of every transformed line read and written once)
+template <typename T> static void conv_timed(scabs_ctx *c, PrecState<T> &P, int nb) {
+  hipStream_t s = c->stream;
+  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
+  StageTimer t(c, SCABS_STAGE_FFT + off);
+  for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb, CONV_PLANES_FWD);
+  for (const DevGrid<T> &g : P.grids) {
+    if (sizeof(T) == sizeof(float)) {
+      const double bytes = 2.0 * sizeof(cx<T>) * g.n[0] * (8.0 * nb * g.N[1] * g.N[2]);
+      StageTimer tx(c, SCABS_STAGE_XLINE32, bytes);
+      launch_conv(g, s, nb, CONV_XLINES);
+    } else {
+      launch_conv(g, s, nb, CONV_XLINES);
+    }
+  }
+  for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb, CONV_PLANES_INV);
+}
+
 // y = A x for nb vectors (nb <= near_rows_max_batch(), within the capacity)
 template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const double *x, double *y, int nb) {
   hipStream_t s = c->stream;
@@ -731,12 +762,22 @@ template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const dou
   }
   {
     StageTimer t(c, SCABS_STAGE_PROJECT + off);
-    launch_project(P.op, P.grids, P.gather, s, nb);
+    if (sizeof(T) == sizeof(float)) {
+      // point sources of every grid, then each grid's gather with a record of
+      // its own (algorithmic bytes: the 8 sources of every point read once,
+      // the 8 fields of every node written once)
+      launch_project(P.op, P.grids, P.gather, s, nb, -2);
+      for (size_t k = 0; k < P.grids.size(); k++) {
+        const DevGrid<T> &g = P.grids[k];
+        const double bytes = 8.0 * sizeof(cx<T>) * nb * ((double)P.gather[k].np + (double)g.n[0] * g.n[1] * g.n[2]);
+        StageTimer tg(c, SCABS_STAGE_GATHER32, bytes);
+        launch_project(P.op, P.grids, P.gather, s, nb, (int)k);
+      }
+    } else {
+      launch_project(P.op, P.grids, P.gather, s, nb);
+    }
   }
-  {
-    StageTimer t(c, SCABS_STAGE_FFT + off);
-    for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb);
-  }
+  conv_timed(c, P, nb);
   {
     StageTimer t(c, SCABS_STAGE_INTERP + off);
     launch_interp_test(P.op, P.grids[0], P.grids_dev + 1, P.inv_h, s, nb);
@@ -760,10 +801,7 @@ template <typename T> static void apply_t(scabs_ctx *c, PrecState<T> &P, const d
     StageTimer t(c, SCABS_STAGE_PROJECT + off);
     launch_test_t(P.op, P.grids, P.gather, P.src4, P.inv_h, s);
   }
-  {
-    StageTimer t(c, SCABS_STAGE_FFT + off);
-    for (const DevGrid<T> &g : P.grids) launch_conv(g, s);
-  }
+  conv_timed(c, P, 1);
   {
     StageTimer t(c, SCABS_STAGE_INTERP + off);
     launch_interp_adj(P.op, P.grids[0], P.grids_dev + 1, s);
@@ -806,10 +844,13 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
   if (!trans && prec == SCABS_FP32) {
     const int B = precond_apply32_max_batch();
     for (int b0 = 0; b0 < nb; b0 += B) {
-      StageTimer tm(c, SCABS_STAGE_PRECOND);
+      const int m = std::min(B, nb - b0);
+      // coefficients once; per ext entry its index and m FP64 inputs; per unknown its index and m outputs
+      const double bytes = 8.0 * (double)c->pc_coef + (4.0 + 16.0 * m) * (double)(c->pc_n_ext + c->lay.N);
+      StageTimer tm(c, SCABS_STAGE_PRECOND, bytes);
       launch_precond_apply32(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr,
                              c->pc_core_slot, c->pc_r_off, c->pc_Rt, x + b0 * N, y + b0 * N, (int64_t)N,
-                             std::min(B, nb - b0), c->pc_max_ext, c->stream);
+                             m, c->pc_max_ext, c->stream);
     }
     return;
   }
@@ -1478,17 +1519,25 @@ int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count) {
   for (int k = 0; k < SCABS_NSTAGES; k++) {
     if (ms) ms[k] = 0;
     if (count) count[k] = 0;
+    c->prof_bytes[k] = 0;
   }
   for (auto &r : c->prof_recs) {
     float t = 0;
-    if (hipEventElapsedTime(&t, r.second.first, r.second.second) != hipSuccess) continue;
-    if (r.first >= 0 && r.first < SCABS_NSTAGES) {
-      if (ms) ms[r.first] += t;
-      if (count) count[r.first] += 1;
+    if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) continue;
+    if (r.stage >= 0 && r.stage < SCABS_NSTAGES) {
+      if (ms) ms[r.stage] += t;
+      if (count) count[r.stage] += 1;
+      c->prof_bytes[r.stage] += r.bytes;
     }
   }
   c->prof_recs.clear();
   c->ev_used = 0;
+  return SCABS_OK;
+}
+
+int scabs_profile_bytes(const scabs_ctx *c, double *bytes) {
+  if (!c || !bytes) return SCABS_E_ARG;
+  for (int k = 0; k < SCABS_NSTAGES; k++) bytes[k] = c->prof_bytes[k];
   return SCABS_OK;
 }
 

@@ -113,6 +113,17 @@ template <typename T, int R> __host__ __device__ inline void dft_small(cx<T> *v,
   }
 }
 
+// XCD-aware work-group order.  Work-groups are dealt round-robin to the 8
+// XCDs (each with its own L2) in linear order, so ids lin and lin + 8 run on
+// the same XCD at about the same time.  Renumbering so that every XCD takes a
+// contiguous range of logical ids gives those two neighbouring logical ids:
+// work that shares lines with its neighbour (the next column block, the next
+// lattice plane) then finds them in the same L2.  A bijection of [0, total).
+__device__ inline int xcd_remap(int lin, int total) {
+  const int q = total >> 3, rem = total & 7, i = lin & 7, k = lin >> 3;
+  return i * q + min(i, rem) + k;
+}
+
 // Division by a work-group-uniform divisor d >= 1 through a multiply-high
 // (round-up method of Granlund and Montgomery): for 0 <= n < 2^31,
 // n / d = (umulhi(n, m) + n) >> s with s = ceil(log2 d),

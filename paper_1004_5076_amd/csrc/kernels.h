@@ -63,7 +63,10 @@ template <typename T> struct DevOperator {
 // ---- FFT convolution -------------------------------------------------------
 // nb vectors: phys/spec hold nb consecutive 8-field blocks
 constexpr int XLINE_REG_LEN = 1024;   // x length with the wave-per-line register transform
-template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb = 1);
+// parts of the convolution (bit flags): forward y-z transforms, x lines with
+// the kernel product, inverse y-z transforms
+enum ConvPart { CONV_PLANES_FWD = 1, CONV_XLINES = 2, CONV_PLANES_INV = 4, CONV_ALL = 7 };
+template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb = 1, int parts = CONV_ALL);
 // ghx[(y h2 + z) h0 + x] = ghat[(x h1 + y) h2 + z]
 template <typename T> void launch_ghat_xfast(const cx<T> *ghat, cx<T> *ghx, int h0, int h1, int h2, hipStream_t s);
 // FFT of the circulant-embedded grid kernel; writes the scaled octant in both precisions
@@ -74,9 +77,10 @@ hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int t
 // Batched steps: nb vectors at once; every per-vector buffer (x, y, op.src,
 // op.tri_out, gather sources, grid fields) holds nb consecutive copies.
 template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s, int nb = 1);
+// part < 0: point sources and gathers of every grid; part = k: grid k's gather only
 template <typename T>
 void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids,
-                    const std::vector<GatherGrid<T>> &gg, hipStream_t s, int nb = 1);
+                    const std::vector<GatherGrid<T>> &gg, hipStream_t s, int nb = 1, int part = -1);
 template <typename T>
 void launch_interp_test(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, T inv_h,
                         hipStream_t s, int nb = 1);

@@ -153,7 +153,7 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
   extern __shared__ int s_map[];
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
-  const int x = blockIdx.x;
+  const int x = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring planes on one XCD
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
   const int K0 = g.nz_ptr[xl], K = g.nz_ptr[xh + 1] - K0;
   const int B1 = g.nz_ptr[min(xl + 1, xh + 1)] - K0, B2 = g.nz_ptr[min(xl + 2, xh + 1)] - K0;

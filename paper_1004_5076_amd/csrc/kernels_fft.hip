@@ -198,8 +198,15 @@ static int reg_planes(int n1, int N2) { return std::max(1, PLANE_REG_THREADS / s
 // the exchange reuses the wave's own line.
 // minimum waves per SIMD the register budget is sized for (LDS allows two
 // work-groups per CU: 4 waves per SIMD in FP32)
-template <typename T> struct XRegCfg { static constexpr int threads = 512, min_waves = 4; };
-template <> struct XRegCfg<double> { static constexpr int threads = 256, min_waves = 2; };
+template <typename T> struct XRegCfg {
+  static constexpr int threads = 512, min_waves = 4;
+  static constexpr bool lds_twiddles = true;   // twiddle table copied to LDS (fits beside two work-groups)
+};
+template <> struct XRegCfg<double> {
+  static constexpr int threads = 256, min_waves = 2;
+  static constexpr bool lds_twiddles = false;
+};
+constexpr int XR_TW = XLINE_REG_LEN + 64;   // twiddle table entries
 constexpr int XR_LS = 1096;   // LDS line stride: >= 16 x 68 exchange slots, = 8 (mod 64)
 constexpr int XR_XS = 68;     // exchange row stride
 
@@ -210,10 +217,20 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
   constexpr int C = XRegCfg<T>::threads / 64;
   extern __shared__ unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
-  const int f = blockIdx.y, b0 = blockIdx.x * C;
+  // XCD-aware order: neighbouring column blocks, whose 64-byte row segments
+  // share 128-byte lines, run on one XCD at about the same time
+  const int nbx = gridDim.x;
+  const int lb = xcd_remap(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+  const int f = lb / nbx, b0 = (lb - f * nbx) * C;
   const int M = N1 * N2;
   const int nl = min(C, M - b0);
   cx<T> *base = spec + (size_t)f * n0 * M + b0;
+  const cx<T> *tw = twx;
+  if (XRegCfg<T>::lds_twiddles) {
+    cx<T> *tw_s = buf + C * XR_LS;
+    for (int i = threadIdx.x; i < XR_TW; i += blockDim.x) tw_s[i] = twx[i];
+    tw = tw_s;
+  }
   {
     const int c = threadIdx.x % C, xr = threadIdx.x / C;   // 64 rows per pass
     for (int xb = 0; xb < n0; xb += 8 * 64) {
@@ -242,7 +259,7 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
     }
     rdft<T, 16, false>(v);
 #pragma unroll
-    for (int a = 1; a < 16; a++) v[a] = v[a] * twx[a * 64 + lane];
+    for (int a = 1; a < 16; a++) v[a] = v[a] * tw[a * 64 + lane];
     wave_lds_fence();
 #pragma unroll
     for (int a = 0; a < 16; a++) ln[a * XR_XS + lane] = v[a];
@@ -253,7 +270,7 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
     for (int s = 0; s < 16; s++) v[s] = ln[qa * XR_XS + p + 4 * s];
     rdft<T, 16, false>(v);
 #pragma unroll
-    for (int c = 1; c < 16; c++) v[c] = v[c] * twx[XLINE_REG_LEN + c * 4 + p];
+    for (int c = 1; c < 16; c++) v[c] = v[c] * tw[XLINE_REG_LEN + c * 4 + p];
 #pragma unroll
     for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, false>(v[c], p, qs);
     // product with the kernel spectrum (octant storage with k_x fastest,
@@ -270,7 +287,7 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
 #pragma unroll
     for (int c = 0; c < 16; c++) v[c] = quad_dft4<T, true>(v[c], p, qs);
 #pragma unroll
-    for (int c = 1; c < 16; c++) v[c] = twm<T, true>(v[c], twx[XLINE_REG_LEN + c * 4 + p]);
+    for (int c = 1; c < 16; c++) v[c] = twm<T, true>(v[c], tw[XLINE_REG_LEN + c * 4 + p]);
     rdft<T, 16, true>(v);
     wave_lds_fence();
 #pragma unroll
@@ -279,7 +296,7 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
 #pragma unroll
     for (int a = 0; a < 16; a++) v[a] = ln[a * XR_XS + lane];
 #pragma unroll
-    for (int a = 1; a < 16; a++) v[a] = twm<T, true>(v[a], twx[a * 64 + lane]);
+    for (int a = 1; a < 16; a++) v[a] = twm<T, true>(v[a], tw[a * 64 + lane]);
     rdft<T, 16, true>(v);
     wave_lds_fence();
 #pragma unroll
@@ -320,7 +337,7 @@ template <typename T> static int planes_per_group(int N1, int N2) {
   return std::max(1, P);
 }
 
-template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb) {
+template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int nb, int parts) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
   const int P = planes_per_group<T>(N1, N2);
@@ -334,7 +351,8 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
   const bool preg = reg_line_ok(N1) && reg_line_ok(N2) && Pr >= 1;
   const size_t preg_lds = sizeof(cx<T>) * (size_t)Pr * n1 * (N2 + 1);
   const int npr = (n0 + Pr - 1) / Pr;
-  if (preg)
+  if (!(parts & CONV_PLANES_FWD)) {
+  } else if (preg)
     hipLaunchKernelGGL(plane_fwd_reg_kernel<T>, dim3(npr, 8 * nb), dim3(PLANE_REG_THREADS), preg_lds, s, g.phys,
                        g.spec, n0, n1, n2, N1, N2, Pr);
   else if (pw)
@@ -346,16 +364,19 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
   const int C = xline_lines<T>(N0);
   const int nlb = (N1 * N2 + C - 1) / C;
   constexpr int CR = XRegCfg<T>::threads / 64;
-  if (g.twx && g.ghx && N0 == XLINE_REG_LEN && n0 <= XLINE_REG_LEN / 2)
+  if (!(parts & CONV_XLINES)) {
+  } else if (g.twx && g.ghx && N0 == XLINE_REG_LEN && n0 <= XLINE_REG_LEN / 2)
     hipLaunchKernelGGL(xline_reg_kernel<T>, dim3((N1 * N2 + CR - 1) / CR, 8 * nb), dim3(XRegCfg<T>::threads),
-                       sizeof(cx<T>) * (size_t)CR * XR_LS, s, g.spec, n0, N1, N2, g.ghx, g.twx);
+                       sizeof(cx<T>) * ((size_t)CR * XR_LS + (XRegCfg<T>::lds_twiddles ? XR_TW : 0)), s, g.spec,
+                       n0, N1, N2, g.ghx, g.twx);
   else if (FftCfg<T>::wave && wave_fits(N0, C, nw, EW))
     hipLaunchKernelGGL((xline_kernel<T, true>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
                        g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
   else
     hipLaunchKernelGGL((xline_kernel<T, false>), dim3(nlb, 8 * nb), dim3(FftCfg<T>::threads), xline_lds<T>(N0, C), s,
                        g.spec, n0, N0, N1, N2, C, g.ghat, g.tw, g.twL, 0);
-  if (preg)
+  if (!(parts & CONV_PLANES_INV)) {
+  } else if (preg)
     hipLaunchKernelGGL(plane_inv_reg_kernel<T>, dim3(npr, 8 * nb), dim3(PLANE_REG_THREADS), preg_lds, s, g.spec,
                        g.phys, n0, n1, n2, N1, N2, Pr);
   else if (pw)
@@ -365,8 +386,8 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
     hipLaunchKernelGGL((plane_inv_kernel<T, false>), dim3(npg, 8 * nb), dim3(FftCfg<T>::threads), plane_lds, s, g.spec,
                        g.phys, n0, n1, n2, N1, N2, P, g.tw, g.twL);
 }
-template void launch_conv<float>(const DevGrid<float> &, hipStream_t, int);
-template void launch_conv<double>(const DevGrid<double> &, hipStream_t, int);
+template void launch_conv<float>(const DevGrid<float> &, hipStream_t, int, int);
+template void launch_conv<double>(const DevGrid<double> &, hipStream_t, int, int);
 
 template <typename T>
 __global__ void ghat_xfast_kernel(const cx<T> *__restrict__ ghat, cx<T> *__restrict__ ghx, int h0, int h1, int h2) {

@@ -104,10 +104,11 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
   extern __shared__ int s_map[];   // (plane - xl) * plane + yz -> slot, or -1
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
-  const int x = blockIdx.x;
-  // batch index blockIdx.y
-  const cx<T> *gsrc = g.src + (size_t)8 * g.np * blockIdx.y;
-  cx<T> *phys = dg.phys + (size_t)8 * g.ncell * blockIdx.y;
+  // XCD-aware order: neighbouring planes (which read the same points) on one XCD
+  const int lb = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bb = lb / gridDim.x, x = lb - bb * gridDim.x;   // batch index, plane
+  const cx<T> *gsrc = g.src + (size_t)8 * g.np * bb;
+  cx<T> *phys = dg.phys + (size_t)8 * g.ncell * bb;
   const int xl = max(x - 1, 0), xh = min(x + 1, n0 - 1);
   const int K0 = g.nz_ptr[xl], K = g.nz_ptr[xh + 1] - K0;
   const int B1 = g.nz_ptr[min(xl + 1, xh + 1)] - K0, B2 = g.nz_ptr[min(xl + 2, xh + 1)] - K0;
@@ -208,13 +209,15 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
 
 template <typename T>
 void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids,
-                    const std::vector<GatherGrid<T>> &gg, hipStream_t s, int nb) {
+                    const std::vector<GatherGrid<T>> &gg, hipStream_t s, int nb, int part) {
+  if (part < 0)   // -1: sources and gathers; -2: sources only
+    for (size_t k = 0; k < grids.size(); k++) {
+      const GatherGrid<T> &g = gg[k];
+      hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256, nb), dim3(256), 0, s, op.pts, op.tris,
+                         op.src, g, grids[k].which >= 0 ? 1 : 0, op.ne);
+    }
   for (size_t k = 0; k < grids.size(); k++) {
-    const GatherGrid<T> &g = gg[k];
-    hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256, nb), dim3(256), 0, s, op.pts, op.tris, op.src,
-                       g, grids[k].which >= 0 ? 1 : 0, op.ne);
-  }
-  for (size_t k = 0; k < grids.size(); k++) {
+    if (part == -2 || (part >= 0 && (int)k != part)) continue;
     const GatherGrid<T> &g = gg[k];
     const int plane = grids[k].n[1] * grids[k].n[2];
     const int items = 3 * plane;
@@ -231,9 +234,9 @@ void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &gri
   }
 }
 template void launch_project<float>(const DevOperator<float> &, const std::vector<DevGrid<float>> &,
-                                    const std::vector<GatherGrid<float>> &, hipStream_t, int);
+                                    const std::vector<GatherGrid<float>> &, hipStream_t, int, int);
 template void launch_project<double>(const DevOperator<double> &, const std::vector<DevGrid<double>> &,
-                                     const std::vector<GatherGrid<double>> &, hipStream_t, int);
+                                     const std::vector<GatherGrid<double>> &, hipStream_t, int, int);
 
 // ---------------------------------------------------------------------------
 // interpolation at test points + row contributions + local terms, reduced to
