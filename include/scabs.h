@@ -62,7 +62,10 @@ typedef struct {
                       near-field matrix (boxes of side pc_cell grown by
                       pc_overlap); 0: none.  Where a grown box would hold
                       more than 4096 unknowns, cell and overlap are scaled
-                      down together (factor 0.85 per try) until all fit */
+                      down together (factor 0.85 per try) until all fit.
+                      The block inverses (FP32 Gauss-Jordan) are stored as
+                      FP16 pairs scaled per column; the preconditioner only
+                      steers convergence, not the solution's accuracy */
   double pc_cell;     /* <= 0 selects 2 r_near */
   double pc_overlap;  /* < 0 selects r_near; must not exceed pc_cell */
 } scabs_opts;
@@ -139,8 +142,9 @@ int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
  * on entry.  mode: SCABS_FP64 (restarted GMRES on the FP64 operator) or
  * SCABS_MIXED (FP64 refinement around FP32-operator GMRES).  Orthogonalisation
  * (classical Gram-Schmidt, repeated where the first pass lost more than
- * 1 - 1/sqrt(2) of the norm) and the Hessenberg least squares are FP64;
- * the preconditioner (if enabled) is applied on the right.
+ * 1 - 1/sqrt(2) of the norm) and the Hessenberg least squares are FP64 (the
+ * basis of the FP32 inner solves is stored in FP32); the preconditioner (if
+ * enabled) is applied on the right.
  * tol: relative residual with the FP64 operator.  info may be NULL.
  * Returns SCABS_E_NOCONV (x holds the last iterate) if max_iter Arnoldi
  * steps do not reach tol. */
@@ -233,9 +237,9 @@ int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
  * physical x range of every transformed line read and written once;
  * SCABS_STAGE_GATHER32: the 8 weighted sources of every point read once and
  * the 8 fields of every lattice node written once;
- * SCABS_STAGE_PRECOND (FP32 inner solves): every stored coefficient once, per
- * extended-set entry its index and the FP64 inputs of the vectors applied, per
- * unknown its index and FP64 outputs.  Returns SCABS_E_ARG for null
+ * SCABS_STAGE_PRECOND (FP32 inner solves): every stored coefficient once (4
+ * bytes), per extended-set entry its index, its column scale and the FP64
+ * inputs of the vectors applied, per unknown its index and FP64 outputs.  Returns SCABS_E_ARG for null
  * arguments. */
 int scabs_profile_bytes(const scabs_ctx *c, double *bytes);
 

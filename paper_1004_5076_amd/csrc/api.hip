@@ -138,7 +138,8 @@ struct scabs_ctx {
   int *pc_items = nullptr;   // (cluster, first core row) per apply work-group
   int pc_n_items = 0;
   int pc_max_ext = 0;        // largest extended set
-  cx<float> *pc_Rt = nullptr;
+  uint32_t *pc_Rt = nullptr;   // stored rows (FP16 pairs), see PcStore
+  float *pc_Rs = nullptr;      // column scales, one per ext entry
   // transposed apply: cluster of every ext entry, and per unknown its ext entries
   int64_t pc_n_ext = 0;
   int64_t pc_coef = 0;   // stored preconditioner coefficients (core rows x ext columns, unpadded)
@@ -489,11 +490,13 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   int *piv = tmp.alloc<int>((size_t)cl.ext_ptr[cl.nc]);
   int *status = tmp.alloc<int>(1);
   HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
-  c->pc_Rt = c->mem.alloc<cx<float>>((size_t)cl.r_off[cl.nc]);
+  c->pc_Rt = c->mem.alloc<uint32_t>((size_t)cl.r_off[cl.nc]);
+  c->pc_Rs = c->mem.alloc<float>((size_t)cl.ext_ptr[cl.nc]);
+  p.n_ext = cl.ext_ptr[cl.nc];
   int max_ext = 0;
   for (int k = 0; k < cl.nc; k++) max_ext = std::max(max_ext, (int)(cl.ext_ptr[k + 1] - cl.ext_ptr[k]));
   c->pc_max_ext = max_ext;
-  launch_precond_build(p, max_ext, c->pc_core_ptr, core_pos, c->pc_r_off, c->pc_Rt, piv, status, s);
+  launch_precond_build(p, max_ext, c->pc_core_ptr, core_pos, c->pc_r_off, c->pc_Rt, c->pc_Rs, piv, status, s);
   HIPCHK(hipGetLastError());
   int st = 0;
   HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -506,10 +509,11 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
   StageTimer tm(c, trans ? SCABS_STAGE_PRECOND_T : SCABS_STAGE_PRECOND);
   if (!trans)
     launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
-                         c->pc_r_off, c->pc_Rt, x, y, c->pc_max_ext, c->stream);
+                         c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, x, y, c->pc_max_ext, c->stream);
   else
     launch_precond_apply_t(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
-                           c->pc_r_off, c->pc_Rt, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y, c->stream);
+                           c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y,
+                           c->stream);
 }
 
 static int do_build(scabs_ctx *c) {
@@ -845,11 +849,14 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
     const int B = precond_apply32_max_batch();
     for (int b0 = 0; b0 < nb; b0 += B) {
       const int m = std::min(B, nb - b0);
-      // coefficients once; per ext entry its index and m FP64 inputs; per unknown its index and m outputs
-      const double bytes = 8.0 * (double)c->pc_coef + (4.0 + 16.0 * m) * (double)(c->pc_n_ext + c->lay.N);
+      // coefficients once (4 B); per ext entry its index, its column scale and
+      // m FP64 inputs; per unknown its index and m FP64 outputs
+      const double bytes = 4.0 * (double)c->pc_coef + (8.0 + 16.0 * m) * (double)c->pc_n_ext +
+                           (4.0 + 16.0 * m) * (double)c->lay.N;
       StageTimer tm(c, SCABS_STAGE_PRECOND, bytes);
       launch_precond_apply32(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr,
-                             c->pc_core_slot, c->pc_r_off, c->pc_Rt, x + b0 * N, y + b0 * N, (int64_t)N,
+                             c->pc_core_slot, c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, x + b0 * N, y + b0 * N,
+                             (int64_t)N,
                              m, c->pc_max_ext, c->stream);
     }
     return;

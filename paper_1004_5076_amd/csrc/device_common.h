@@ -1,6 +1,7 @@
 // Device helpers shared by the HIP kernels: complex arithmetic, Lagrange
 // stencils and an in-LDS radix-2 Stockham FFT.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -111,6 +112,15 @@ template <typename T, int R> __host__ __device__ inline void dft_small(cx<T> *v,
     v[3] = e[3] + w3;
     v[7] = e[3] - w3;
   }
+}
+
+// complex coefficient stored as two FP16 halves (real in the low 16 bits)
+__device__ inline cx<float> unpack_h2(uint32_t v) {
+  return {__half2float(__ushort_as_half((unsigned short)(v & 0xffffu))),
+          __half2float(__ushort_as_half((unsigned short)(v >> 16)))};
+}
+__device__ inline uint32_t pack_h2(float re, float im) {
+  return (uint32_t)__half_as_ushort(__float2half_rn(re)) | ((uint32_t)__half_as_ushort(__float2half_rn(im)) << 16);
 }
 
 // XCD-aware work-group order.  Work-groups are dealt round-robin to the 8

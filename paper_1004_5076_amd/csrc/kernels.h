@@ -138,26 +138,34 @@ struct PrecondArgs {
   const int64_t *ext_ptr;
   const int *ext_slot;
   const int64_t *a_off;
+  int64_t n_ext;             // ext entries of all clusters
   cx<float> *A;              // dense cluster blocks (FP32)
 };
 void launch_exact_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
                            const cx<double> *blocks, cx<double> *X8, hipStream_t s);
+// Stored Schwarz rows: per cluster the core rows x ext columns of the block
+// inverse, column-major (column stride rt_stride(nc)), each complex entry as two
+// FP16 halves (real in the low 16 bits) divided by its column's scale (the
+// largest |re|, |im| of the column, FP32, one per ext entry).
+struct PcStore {
+  const uint32_t *R;
+  const float *scale;
+};
 void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
-                          const int64_t *r_off, cx<float> *Rt, int *piv, int *status, hipStream_t s);
+                          const int64_t *r_off, uint32_t *Rt, float *Rs, int *piv, int *status, hipStream_t s);
 // rows of one cluster's core handled by one work-group of the apply kernel
 int precond_rows_per_item();
 // items: n_items pairs (cluster, first core row), rows per item as above
 void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
-                          const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                          const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                           const cx<double> *x, cx<double> *y, int max_ext, hipStream_t s);
 
 // FP32 batched apply (inner solves of the mixed mode): m vectors of N,
 // m <= precond_apply32_max_batch()
 int precond_apply32_max_batch();
 void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
-                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off,
-                            const cx<float> *Rt, const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext,
-                            hipStream_t s);
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
+                            const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext, hipStream_t s);
 
 // ---- transposed product, adjoint gradient --------------------------------------
 template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s);
@@ -172,7 +180,7 @@ void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y
 // items: (cluster, first ext column) per work-group, precond_t_cols_per_item() columns each
 int precond_t_cols_per_item();
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
-                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
                             cx<double> *y, hipStream_t s);
 void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &ext, const DevGrid<double> *ints_dev,

@@ -490,8 +490,8 @@ int precond_t_cols_per_item() { return PT_COLS; }
 __global__ void __launch_bounds__(PT_THREADS)
 precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                       const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
-                      const int64_t *__restrict__ r_off, const cx<float> *__restrict__ Rt,
-                      const cx<double> *__restrict__ x, cx<double> *__restrict__ tmp) {
+                      const int64_t *__restrict__ r_off, PcStore pc, const cx<double> *__restrict__ x,
+                      cx<double> *__restrict__ tmp) {
   __shared__ cx<double> xs[PT_MAXCORE];
   const int c = items[2 * blockIdx.x], j0 = items[2 * blockIdx.x + 1];
   const int64_t e0 = ext_ptr[c];
@@ -504,13 +504,13 @@ precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__
   const int64_t ncp = rt_stride(ncore);
   const int j1 = min(j0 + PT_COLS, ne);
   for (int j = j0 + w; j < j1; j += nw) {
-    const cx<float> *R = Rt + r_off[c] + (int64_t)j * ncp;
+    const uint32_t *R = pc.R + r_off[c] + (int64_t)j * ncp;
     double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
     int i = lane;
     for (; i + 192 < ncore; i += 256) {
       cx<float> rv[4];
 #pragma unroll
-      for (int u = 0; u < 4; u++) rv[u] = R[i + 64 * u];
+      for (int u = 0; u < 4; u++) rv[u] = unpack_h2(R[i + 64 * u]);
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const cx<double> xv = xs[i + 64 * u];
@@ -519,13 +519,14 @@ precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__
       }
     }
     for (; i < ncore; i += 64) {
-      const cx<float> rv = R[i];
+      const cx<float> rv = unpack_h2(R[i]);
       const cx<double> xv = xs[i];
       ar[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
       ai[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
     }
     const double sr = wsum((ar[0] + ar[1]) + (ar[2] + ar[3])), si = wsum((ai[0] + ai[1]) + (ai[2] + ai[3]));
-    if (lane == 0) tmp[e0 + j] = {sr, si};
+    const double sc = pc.scale[e0 + j];
+    if (lane == 0) tmp[e0 + j] = {sr * sc, si * sc};
   }
 }
 
@@ -539,11 +540,11 @@ __global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_
 }
 
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
-                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
                             cx<double> *y, hipStream_t s) {
   hipLaunchKernelGGL(precond_t_dots_kernel, dim3(n_items), dim3(PT_THREADS), 0, s, items, ext_ptr, core_ptr, core_slot,
-                     r_off, Rt, x, tmp);
+                     r_off, pc, x, tmp);
   hipLaunchKernelGGL(precond_t_sum_kernel, dim3(1024), dim3(256), 0, s, N, inv_ptr, inv_pos, (const cx<double> *)tmp,
                      y);
 }

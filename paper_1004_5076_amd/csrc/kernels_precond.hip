@@ -194,30 +194,51 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<float> *Abl
   }
 }
 
-// Rt[j][i] = inverse[core_pos[i]][j], FP32 (column-major over the core rows,
-// column stride rt_stride(nc))
-__global__ void extract_kernel(const cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr,
-                               const int64_t *core_ptr, const int *core_pos, const int64_t *r_off, cx<float> *Rt) {
-  const int c = blockIdx.y;
+// Stored rows: for ext column j of cluster c, Rt[j][i] = inverse[core_pos[i]][j]
+// over the core rows i (column-major, column stride rt_stride(nc)), as FP16
+// halves divided by the column's scale Rs = max |re|, |im| (1 for a zero
+// column).  One wave per column: the maximum, then the scaled entries.
+__global__ void __launch_bounds__(256)
+extract_kernel(const cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr, const int64_t *core_ptr,
+               const int *core_pos, const int64_t *r_off, int nclust, uint32_t *Rt, float *Rs) {
+  const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (col >= ext_ptr[nclust]) return;
+  int lo = 0, hi = nclust;   // owning cluster: ext_ptr[c] <= col < ext_ptr[c + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ext_ptr[mid] <= col) lo = mid;
+    else hi = mid;
+  }
+  const int c = lo;
   const int ne = (int)(ext_ptr[c + 1] - ext_ptr[c]);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
+  const int j = (int)(col - ext_ptr[c]);
   const cx<float> *A = Ablocks + a_off[c];
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)ne * nc;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(idx / nc), i = (int)(idx - (int64_t)j * nc);
-    Rt[r_off[c] + (int64_t)j * rt_stride(nc) + i] = A[(size_t)core_pos[core_ptr[c] + i] * ne + j];
+  const int *cp = core_pos + core_ptr[c];
+  float m = 0;
+  for (int i = lane; i < nc; i += 64) {
+    const cx<float> v = A[(size_t)cp[i] * ne + j];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
   }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  const float sc = m > 0 ? m : 1.0f, inv = 1.0f / sc;
+  uint32_t *R = Rt + r_off[c] + (int64_t)j * rt_stride(nc);
+  for (int i = lane; i < nc; i += 64) {
+    const cx<float> v = A[(size_t)cp[i] * ne + j];
+    R[i] = pack_h2(v.x * inv, v.y * inv);
+  }
+  if (lane == 0) Rs[col] = sc;
 }
 
 void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
-                          const int64_t *r_off, cx<float> *Rt, int *piv, int *status, hipStream_t s) {
+                          const int64_t *r_off, uint32_t *Rt, float *Rs, int *piv, int *status, hipStream_t s) {
   (void)max_ext;
   hipLaunchKernelGGL(block_assemble_kernel, dim3(64, p.nc), dim3(256), 0, s, p);
   hipLaunchKernelGGL(gauss_jordan_kernel, dim3(p.nc), dim3(GJ_THREADS), 0, s, p.A, p.a_off, p.ext_ptr, piv, status);
-  hipLaunchKernelGGL(extract_kernel, dim3(32, p.nc), dim3(256), 0, s, (const cx<float> *)p.A, p.a_off, p.ext_ptr,
-                     core_ptr, core_pos, r_off, Rt);
+  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((p.n_ext * 64 + 255) / 256)), dim3(256), 0, s,
+                     (const cx<float> *)p.A, p.a_off, p.ext_ptr, core_ptr, core_pos, r_off, p.nc, Rt, Rs);
 }
-
 // y[core] = R_c x[ext] for every cluster; each unknown is in exactly one core.
 // One work-group per item (cluster c, PA_ROWS core rows from row0): the ext
 // columns split in PA_Q contiguous parts (coalesced reads of the
@@ -229,15 +250,15 @@ constexpr int PA_CW = 512;   // ext columns staged per pass
 __global__ void __launch_bounds__(PA_THREADS)
 precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                      const int *__restrict__ ext_slot, const int64_t *__restrict__ core_ptr,
-                     const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
-                     const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y) {
+                     const int *__restrict__ core_slot, const int64_t *__restrict__ r_off, PcStore pc,
+                     const cx<double> *__restrict__ x, cx<double> *__restrict__ y) {
   __shared__ cx<double> xs[PA_CW];
   __shared__ cx<double> red[PA_Q][PA_ROWS];
   const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const cx<float> *R = Rt + r_off[c];
+  const uint32_t *R = pc.R + r_off[c];
   const int64_t ncp = rt_stride(nc);
   const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
   const int i = i0 + il;
@@ -246,23 +267,25 @@ precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ 
   for (int cb = 0; cb < ne; cb += PA_CW) {
     const int cw = min(PA_CW, ne - cb);
     __syncthreads();   // the previous pass is done with xs
-    for (int jj = threadIdx.x; jj < cw; jj += blockDim.x) xs[jj] = x[ext_slot[e0 + cb + jj]];
+    // the column scales fold into the staged inputs
+    for (int jj = threadIdx.x; jj < cw; jj += blockDim.x)
+      xs[jj] = x[ext_slot[e0 + cb + jj]] * (double)pc.scale[e0 + cb + jj];
     __syncthreads();
     const int jb = (cw * q) / PA_Q, je = (cw * (q + 1)) / PA_Q;
     if (i < nc) {
-      const cx<float> *Rc = R + (int64_t)cb * ncp + i;
+      const uint32_t *Rc = R + (int64_t)cb * ncp + i;
       int j = jb;
       for (; j + 4 <= je; j += 4) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          const cx<float> rv = Rc[(j + u) * ncp];
+          const cx<float> rv = unpack_h2(Rc[(j + u) * ncp]);
           const cx<double> xv = xs[j + u];
           pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
           pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
         }
       }
       for (; j < je; j++) {
-        const cx<float> rv = Rc[j * ncp];
+        const cx<float> rv = unpack_h2(Rc[j * ncp]);
         const cx<double> xv = xs[j];
         pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
         pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
@@ -281,11 +304,11 @@ precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ 
 int precond_rows_per_item() { return PA_ROWS; }
 
 void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
-                          const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, const cx<float> *Rt,
+                          const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                           const cx<double> *x, cx<double> *y, int max_ext, hipStream_t s) {
   (void)max_ext;
   hipLaunchKernelGGL(precond_apply_kernel, dim3(n_items), dim3(PA_THREADS), 0, s, items, ext_ptr, ext_slot, core_ptr,
-                     core_slot, r_off, Rt, x, y);
+                     core_slot, r_off, pc, x, y);
 }
 
 // Batched apply in single precision for the FP32 inner solves: nb <= 8
@@ -301,9 +324,8 @@ template <int NB>
 __global__ void __launch_bounds__(PA32_THREADS)
 precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                        const int *__restrict__ ext_slot, const int64_t *__restrict__ core_ptr,
-                       const int *__restrict__ core_slot, const int64_t *__restrict__ r_off,
-                       const cx<float> *__restrict__ Rt, const cx<double> *__restrict__ x, cx<double> *__restrict__ y,
-                       int64_t N, int nb) {
+                       const int *__restrict__ core_slot, const int64_t *__restrict__ r_off, PcStore pc,
+                       const cx<double> *__restrict__ x, cx<double> *__restrict__ y, int64_t N, int nb) {
   // the column staging and, after the last pass, the partial sums share LDS
   static_assert(PA32_Q * PA_ROWS <= PA32_CW, "partial sums must fit the staging buffer");
   __shared__ cx<float> xs[NB][PA32_CW];
@@ -312,7 +334,7 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const cx<float> *R = Rt + r_off[c];
+  const uint32_t *R = pc.R + r_off[c];
   const int64_t ncp = rt_stride(nc);
   const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
   const int i = i0 + il;
@@ -325,18 +347,19 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
     for (int t = threadIdx.x; t < nb * cw; t += blockDim.x) {
       const int b = t / cw, jj = t - b * cw;
       const cx<double> v = x[(size_t)b * N + ext_slot[e0 + cb + jj]];
-      xs[b][jj] = {(float)v.x, (float)v.y};
+      const float sc = pc.scale[e0 + cb + jj];   // the column scale folds into the staged input
+      xs[b][jj] = {(float)v.x * sc, (float)v.y * sc};
     }
     __syncthreads();
     const int jb = (cw * q) / PA32_Q, je = (cw * (q + 1)) / PA32_Q;
     if (i < nc) {
       // eight coefficient loads in flight per thread
-      const cx<float> *Rc = R + (int64_t)cb * ncp + i;
+      const uint32_t *Rc = R + (int64_t)cb * ncp + i;
       int j = jb;
       for (; j + 8 <= je; j += 8) {
         cx<float> rv[8];
 #pragma unroll
-        for (int u = 0; u < 8; u++) rv[u] = Rc[(j + u) * ncp];
+        for (int u = 0; u < 8; u++) rv[u] = unpack_h2(Rc[(j + u) * ncp]);
 #pragma unroll
         for (int u = 0; u < 8; u++)
 #pragma unroll
@@ -344,7 +367,7 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
             if (b < nb) acc[b] += rv[u] * xs[b][j + u];
       }
       for (; j < je; j++) {
-        const cx<float> rv = Rc[j * ncp];
+        const cx<float> rv = unpack_h2(Rc[j * ncp]);
 #pragma unroll
         for (int b = 0; b < NB; b++)
           if (b < nb) acc[b] += rv * xs[b][j];
@@ -372,23 +395,22 @@ int precond_apply32_max_batch() { return 8; }
 // m <= precond_apply32_max_batch() vectors; max_ext (largest extended set)
 // sizes the LDS staging
 void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
-                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off,
-                            const cx<float> *Rt, const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext,
-                            hipStream_t s) {
+                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
+                            const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext, hipStream_t s) {
   const size_t lds = 0;
   (void)max_ext;
   if (m == 1)
     hipLaunchKernelGGL((precond_apply32_kernel<1>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+                       core_ptr, core_slot, r_off, pc, x, y, N, m);
   else if (m == 2)
     hipLaunchKernelGGL((precond_apply32_kernel<2>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+                       core_ptr, core_slot, r_off, pc, x, y, N, m);
   else if (m <= 4)
     hipLaunchKernelGGL((precond_apply32_kernel<4>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+                       core_ptr, core_slot, r_off, pc, x, y, N, m);
   else
     hipLaunchKernelGGL((precond_apply32_kernel<8>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, Rt, x, y, N, m);
+                       core_ptr, core_slot, r_off, pc, x, y, N, m);
 }
 
 }  // namespace scabs
