@@ -496,7 +496,12 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   int max_ext = 0;
   for (int k = 0; k < cl.nc; k++) max_ext = std::max(max_ext, (int)(cl.ext_ptr[k + 1] - cl.ext_ptr[k]));
   c->pc_max_ext = max_ext;
-  launch_precond_build(p, max_ext, c->pc_core_ptr, core_pos, c->pc_r_off, c->pc_Rt, c->pc_Rs, piv, status, s);
+  int npanels = 0;
+  const std::vector<int> tiles = gj_tile_table(cl.ext_ptr, npanels);
+  const int *tiles_dev = tmp.upload(tiles);
+  cx<float> *gj_tmp = tmp.alloc<cx<float>>(gj_scratch_entries(cl.ext_ptr));
+  launch_precond_build(p, cl.ext_ptr, tiles_dev, tiles, npanels, gj_tmp, c->pc_core_ptr, core_pos, c->pc_r_off,
+                       c->pc_Rt, c->pc_Rs, piv, status, s);
   HIPCHK(hipGetLastError());
   int st = 0;
   HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -151,8 +151,14 @@ struct PcStore {
   const uint32_t *R;
   const float *scale;
 };
-void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
-                          const int64_t *r_off, uint32_t *Rt, float *Rs, int *piv, int *status, hipStream_t s);
+// blocked Gauss-Jordan: per panel the prefix sums over clusters of their
+// update tiles (npanels x (nclusters + 1)), and the pivot-row scratch size
+std::vector<int> gj_tile_table(const std::vector<int64_t> &ext_ptr, int &npanels);
+size_t gj_scratch_entries(const std::vector<int64_t> &ext_ptr);
+void launch_precond_build(const PrecondArgs &p, const std::vector<int64_t> &ext_ptr_h, const int *tiles_dev,
+                          const std::vector<int> &tiles_h, int npanels, cx<float> *gj_tmp, const int64_t *core_ptr,
+                          const int *core_pos, const int64_t *r_off, uint32_t *Rt, float *Rs, int *piv, int *status,
+                          hipStream_t s);
 // rows of one cluster's core handled by one work-group of the apply kernel
 int precond_rows_per_item();
 // items: n_items pairs (cluster, first core row), rows per item as above

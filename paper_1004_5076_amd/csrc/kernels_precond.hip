@@ -3,6 +3,9 @@
 // (overlapping) unknown set is assembled in FP64, inverted by Gauss-Jordan
 // elimination with partial pivoting, and the rows of its core unknowns are
 // kept (FP32).  Applying it is one dense block product per cluster.
+#include <algorithm>
+#include <vector>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -92,39 +95,52 @@ __global__ void block_assemble_kernel(PrecondArgs p) {
   }
 }
 
-// In-place inverse of each cluster block (row-major n x n, FP32) by
-// Gauss-Jordan elimination with partial pivoting; the row interchanges are
-// undone as column interchanges at the end.  One work-group per cluster.
+// In-place inverse of each cluster block (row-major n x n, FP32) by blocked
+// Gauss-Jordan elimination with partial pivoting.  Panels of GJ_B columns:
+// the panel kernel (one work-group per cluster) runs the GJ_B elimination
+// steps on the panel columns of every row only (pivot search, full-row
+// interchange, panel update); the b steps compose to T = I + (P - E) E^T
+// with P the panel columns afterwards and E the pivot rows' unit vectors, so
+// every other column v becomes v + (P - E) v_E: a rank-GJ_B update of the
+// remaining columns (update kernel, 64 x 64 tiles of all clusters) from a
+// snapshot of the pivot rows.  The row interchanges are undone as column
+// interchanges at the end.
 constexpr int GJ_THREADS = 1024;
 constexpr int GJ_MAXN = 4096;   // largest cluster (extended set) the inversion handles
+constexpr int GJ_B = 32;        // panel width
+constexpr int GJ_TILE = 64;     // update tile (rows x columns)
 
-__global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<float> *Ablocks, const int64_t *a_off,
-                                                                  const int64_t *ext_ptr, int *piv_all, int *status) {
+__global__ void __launch_bounds__(GJ_THREADS)
+gj_panel_kernel(cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr, int *piv_all, int *status,
+                int k0) {
   const int c = blockIdx.x;
   const int n = (int)(ext_ptr[c + 1] - ext_ptr[c]);
+  if (n <= k0) return;
   cx<float> *A = Ablocks + a_off[c];
   int *piv = piv_all + ext_ptr[c];
-  __shared__ cx<float> rowk[GJ_MAXN];
+  const int kb = min(k0 + GJ_B, n), bw = kb - k0;
   __shared__ cx<float> colk[GJ_MAXN];
+  __shared__ cx<float> rowp[GJ_B];
   __shared__ float red_v[GJ_THREADS / 64];
   __shared__ int red_i[GJ_THREADS / 64];
   __shared__ int s_p;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = GJ_THREADS / 64;
-  for (int k = 0; k < n; k++) {
+  const FastDiv dbw = make_fastdiv(bw);
+  for (int k = k0; k < kb; k++) {
     // pivot: largest |A[i][k]|, i >= k
     float best = -1.0f;
     int bi = k;
     for (int i = k + tid; i < n; i += blockDim.x) {
-      cx<float> v = A[(size_t)i * n + k];
-      float m = v.x * v.x + v.y * v.y;
+      const cx<float> v = A[(size_t)i * n + k];
+      const float m = v.x * v.x + v.y * v.y;
       if (m > best) {
         best = m;
         bi = i;
       }
     }
     for (int o = 32; o > 0; o >>= 1) {
-      float ov = __shfl_xor(best, o, 64);
-      int oi = __shfl_xor(bi, o, 64);
+      const float ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
       if (ov > best || (ov == best && oi < bi)) {
         best = ov;
         bi = oi;
@@ -149,50 +165,145 @@ __global__ void __launch_bounds__(GJ_THREADS) gauss_jordan_kernel(cx<float> *Abl
     }
     __syncthreads();
     const int pr = s_p;
-    if (pr != k)
+    if (pr != k)   // whole rows: the deferred update reads the pivot rows
       for (int j = tid; j < n; j += blockDim.x) {
-        cx<float> t = A[(size_t)k * n + j];
+        const cx<float> t = A[(size_t)k * n + j];
         A[(size_t)k * n + j] = A[(size_t)pr * n + j];
         A[(size_t)pr * n + j] = t;
       }
     __syncthreads();
-    // pivot row scaled by 1/d, pivot column saved
     const cx<float> d = A[(size_t)k * n + k];
     const float dn = d.x * d.x + d.y * d.y;
     const cx<float> inv = dn > 0 ? cx<float>{d.x / dn, -d.y / dn} : cx<float>{0.0f, 0.0f};
-    for (int j = tid; j < n; j += blockDim.x) {
-      cx<float> v = j == k ? cx<float>{1.0f, 0.0f} : A[(size_t)k * n + j];
-      rowk[j] = v * inv;
-      colk[j] = A[(size_t)j * n + k];
-    }
+    for (int q = tid; q < bw; q += blockDim.x)
+      rowp[q] = (k0 + q == k ? cx<float>{1.0f, 0.0f} : A[(size_t)k * n + k0 + q]) * inv;
+    for (int i = tid; i < n; i += blockDim.x) colk[i] = A[(size_t)i * n + k];
     __syncthreads();
-    for (int j = tid; j < n; j += blockDim.x) A[(size_t)k * n + j] = rowk[j];
-    // every other row: one wave per row, lanes along the (contiguous) columns
-    for (int i = wid; i < n; i += nw) {
-      if (i == k) continue;
-      const cx<float> f = colk[i];
-      cx<float> *Ai = A + (size_t)i * n;
-      for (int j = lane; j < n; j += 64) {
-        if (j == k)
-          Ai[j] = -(f * inv);
-        else
-          Ai[j] -= f * rowk[j];
-      }
+    // panel columns of every row (the pivot row takes the scaled row)
+    for (int idx = tid; idx < n * bw; idx += blockDim.x) {
+      const int i = fdiv(idx, dbw), q = idx - i * bw, j = k0 + q;
+      cx<float> *a = A + (size_t)i * n + j;
+      if (i == k)
+        *a = rowp[q];
+      else
+        *a = (j == k ? czero<float>() : *a) - colk[i] * rowp[q];
     }
     __syncthreads();
   }
-  // undo row interchanges as column interchanges, last first
+}
+
+// snapshot of the panel's pivot rows: tmp[q][j] = A[k0 + q][j]
+__global__ void gj_pivot_rows_kernel(const cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr,
+                                     cx<float> *tmp_all, int k0) {
+  const int c = blockIdx.y;
+  const int n = (int)(ext_ptr[c + 1] - ext_ptr[c]);
+  if (n <= k0) return;
+  const int bw = min(GJ_B, n - k0);
+  const cx<float> *A = Ablocks + a_off[c] + (size_t)k0 * n;
+  cx<float> *tmp = tmp_all + (size_t)GJ_B * ext_ptr[c];
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)bw * n;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    tmp[idx] = A[idx];
+}
+
+// A[i][j] += sum_q (P - E)[i][q] tmp[q][j] for every j outside the panel;
+// work-group = (cluster, 64 x 64 tile) from the per-panel tile prefix sums
+__global__ void __launch_bounds__(256)
+gj_update_kernel(cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr, const cx<float> *tmp_all,
+                 const int *tiles, int nclust, int k0) {
+  __shared__ cx<float> sP[GJ_TILE][GJ_B + 1];
+  __shared__ cx<float> sT[GJ_B][GJ_TILE + 1];
+  const int t = blockIdx.x;
+  int lo = 0, hi = nclust;   // tiles[c] <= t < tiles[c + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tiles[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  const int c = lo;
+  const int n = (int)(ext_ptr[c + 1] - ext_ptr[c]);
+  const int bw = min(GJ_B, n - k0);
+  const int nt = (n + GJ_TILE - 1) / GJ_TILE, tl = t - tiles[c];
+  const int i0 = (tl / nt) * GJ_TILE, j0 = (tl % nt) * GJ_TILE;
+  cx<float> *A = Ablocks + a_off[c];
+  const cx<float> *tmp = tmp_all + (size_t)GJ_B * ext_ptr[c];
+  for (int e = threadIdx.x; e < GJ_TILE * GJ_B; e += blockDim.x) {
+    const int r = e / GJ_B, q = e - r * GJ_B, i = i0 + r;
+    cx<float> v = czero<float>();
+    if (i < n && q < bw) {
+      v = A[(size_t)i * n + k0 + q];
+      if (i == k0 + q) v.x -= 1.0f;
+    }
+    sP[r][q] = v;
+  }
+  for (int e = threadIdx.x; e < GJ_B * GJ_TILE; e += blockDim.x) {
+    const int q = e / GJ_TILE, cc = e - q * GJ_TILE, j = j0 + cc;
+    sT[q][cc] = (q < bw && j < n) ? tmp[(size_t)q * n + j] : czero<float>();
+  }
+  __syncthreads();
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  cx<float> acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = czero<float>();
+  for (int q = 0; q < bw; q++) {
+    cx<float> pv[4], tv[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) pv[a] = sP[tr + 16 * a][q];
+#pragma unroll
+    for (int b = 0; b < 4; b++) tv[b] = sT[q][tc + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) acc[a][b] += pv[a] * tv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    const int i = i0 + tr + 16 * a;
+    if (i >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int j = j0 + tc + 16 * b;
+      if (j < n && (j < k0 || j >= k0 + bw)) A[(size_t)i * n + j] += acc[a][b];
+    }
+  }
+}
+
+// undo the row interchanges as column interchanges, last first
+__global__ void __launch_bounds__(GJ_THREADS)
+gj_unswap_kernel(cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_ptr, const int *piv_all) {
+  const int c = blockIdx.x;
+  const int n = (int)(ext_ptr[c + 1] - ext_ptr[c]);
+  cx<float> *A = Ablocks + a_off[c];
+  const int *piv = piv_all + ext_ptr[c];
   for (int k = n - 1; k >= 0; k--) {
     const int pr = piv[k];
     if (pr != k)
-      for (int i = tid; i < n; i += blockDim.x) {
-        cx<float> t = A[(size_t)i * n + k];
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const cx<float> t = A[(size_t)i * n + k];
         A[(size_t)i * n + k] = A[(size_t)i * n + pr];
         A[(size_t)i * n + pr] = t;
       }
     __syncthreads();
   }
 }
+
+std::vector<int> gj_tile_table(const std::vector<int64_t> &ext_ptr, int &npanels) {
+  const int nc = (int)ext_ptr.size() - 1;
+  int64_t maxn = 0;
+  for (int c = 0; c < nc; c++) maxn = std::max(maxn, ext_ptr[c + 1] - ext_ptr[c]);
+  npanels = (int)((maxn + GJ_B - 1) / GJ_B);
+  std::vector<int> t((size_t)npanels * (nc + 1), 0);
+  for (int p = 0; p < npanels; p++)
+    for (int c = 0; c < nc; c++) {
+      const int64_t n = ext_ptr[c + 1] - ext_ptr[c];
+      const int64_t nt = n > (int64_t)p * GJ_B ? (n + GJ_TILE - 1) / GJ_TILE : 0;
+      t[(size_t)p * (nc + 1) + c + 1] = t[(size_t)p * (nc + 1) + c] + (int)(nt * nt);
+    }
+  return t;
+}
+size_t gj_scratch_entries(const std::vector<int64_t> &ext_ptr) { return (size_t)GJ_B * ext_ptr.back(); }
 
 // Stored rows: for ext column j of cluster c, Rt[j][i] = inverse[core_pos[i]][j]
 // over the core rows i (column-major, column stride rt_stride(nc)), as FP16
@@ -231,14 +342,27 @@ extract_kernel(const cx<float> *Ablocks, const int64_t *a_off, const int64_t *ex
   if (lane == 0) Rs[col] = sc;
 }
 
-void launch_precond_build(const PrecondArgs &p, int max_ext, const int64_t *core_ptr, const int *core_pos,
-                          const int64_t *r_off, uint32_t *Rt, float *Rs, int *piv, int *status, hipStream_t s) {
-  (void)max_ext;
+void launch_precond_build(const PrecondArgs &p, const std::vector<int64_t> &ext_ptr_h, const int *tiles_dev,
+                          const std::vector<int> &tiles_h, int npanels, cx<float> *gj_tmp, const int64_t *core_ptr,
+                          const int *core_pos, const int64_t *r_off, uint32_t *Rt, float *Rs, int *piv, int *status,
+                          hipStream_t s) {
+  (void)ext_ptr_h;
   hipLaunchKernelGGL(block_assemble_kernel, dim3(64, p.nc), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(p.nc), dim3(GJ_THREADS), 0, s, p.A, p.a_off, p.ext_ptr, piv, status);
+  for (int pn = 0; pn < npanels; pn++) {
+    const int k0 = pn * GJ_B;
+    hipLaunchKernelGGL(gj_panel_kernel, dim3(p.nc), dim3(GJ_THREADS), 0, s, p.A, p.a_off, p.ext_ptr, piv, status, k0);
+    hipLaunchKernelGGL(gj_pivot_rows_kernel, dim3(16, p.nc), dim3(256), 0, s, (const cx<float> *)p.A, p.a_off,
+                       p.ext_ptr, gj_tmp, k0);
+    const int ntiles = tiles_h[(size_t)pn * (p.nc + 1) + p.nc];
+    if (ntiles > 0)
+      hipLaunchKernelGGL(gj_update_kernel, dim3(ntiles), dim3(256), 0, s, p.A, p.a_off, p.ext_ptr,
+                         (const cx<float> *)gj_tmp, tiles_dev + (size_t)pn * (p.nc + 1), p.nc, k0);
+  }
+  hipLaunchKernelGGL(gj_unswap_kernel, dim3(p.nc), dim3(GJ_THREADS), 0, s, p.A, p.a_off, p.ext_ptr, piv);
   hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((p.n_ext * 64 + 255) / 256)), dim3(256), 0, s,
                      (const cx<float> *)p.A, p.a_off, p.ext_ptr, core_ptr, core_pos, r_off, p.nc, Rt, Rs);
 }
+
 // y[core] = R_c x[ext] for every cluster; each unknown is in exactly one core.
 // One work-group per item (cluster c, PA_ROWS core rows from row0): the ext
 // columns split in PA_Q contiguous parts (coalesced reads of the
