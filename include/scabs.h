@@ -61,13 +61,14 @@ typedef struct {
   int precond;     /* 1: restricted additive Schwarz preconditioner on the exact
                       near-field matrix (boxes of side pc_cell grown by
                       pc_overlap); 0: none.  Where a grown box would hold
-                      more than 4096 unknowns, cell and overlap are scaled
-                      down together (factor 0.85 per try) until all fit.
+                      more than 8192 unknowns (or its core more than 4096),
+                      cell and overlap are scaled down together (factor
+                      0.85 per try) until all fit.
                       The block inverses (FP32 Gauss-Jordan) are stored as
                       FP16 pairs scaled per column; the preconditioner only
                       steers convergence, not the solution's accuracy */
   double pc_cell;     /* <= 0 selects 2 r_near */
-  double pc_overlap;  /* < 0 selects r_near; must not exceed pc_cell */
+  double pc_overlap;  /* < 0 selects 1.5 r_near; must not exceed pc_cell */
 } scabs_opts;
 
 typedef struct {

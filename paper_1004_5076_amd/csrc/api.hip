@@ -399,7 +399,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   const Layout &L = c->lay;
   hipStream_t s = c->stream;
   double cell = c->opts.pc_cell > 0 ? c->opts.pc_cell : 2.0 * c->opts.r_near;
-  double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 1.0 * c->opts.r_near;
+  double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 1.5 * c->opts.r_near;
   // boxes that would hold more unknowns than one work-group inverts shrink
   // the cell and overlap together until every cluster fits
   std::string e;

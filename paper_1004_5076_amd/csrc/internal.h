@@ -90,8 +90,13 @@ void sigma_param_jacobian(const Geometry &g, const std::vector<SigmaEnd> &ends, 
 std::string build_grids(const Geometry &g, double h, double k_e, double k_i, std::vector<GridDesc> &grids,
                         std::vector<int> &anchor /* np*3 absolute */, std::vector<double> &u /* np*3 */);
 std::string build_near(const Geometry &g, double r_near, double kappa_s, NearList &nl);
+// Largest preconditioner cluster: extended set (the block the Gauss-Jordan
+// kernels invert) and core (staged whole in LDS by the transposed apply).
+constexpr int PC_MAX_EXT = 8192;
+constexpr int PC_MAX_CORE = 4096;
 // Box clusters of side `cell` grown by `overlap`; sets *too_large when a
-// grown box holds more than 4096 unknowns.
+// grown box holds more than PC_MAX_EXT unknowns or its core more than
+// PC_MAX_CORE.
 std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl,
                            bool *too_large);
 void build_local_terms(const Geometry &g, const Layout &L, LocalTerms &lt);

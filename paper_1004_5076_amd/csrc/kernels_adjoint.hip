@@ -484,7 +484,7 @@ template void launch_near_rows_t<double>(const DevOperator<double> &, const int6
 // ---------------------------------------------------------------------------
 constexpr int PT_COLS = 64;
 constexpr int PT_THREADS = 512;
-constexpr int PT_MAXCORE = 4096;   // the largest cluster the Gauss-Jordan kernel inverts
+constexpr int PT_MAXCORE = PC_MAX_CORE;   // largest core of a cluster
 int precond_t_cols_per_item() { return PT_COLS; }
 
 __global__ void __launch_bounds__(PT_THREADS)

@@ -106,7 +106,7 @@ __global__ void block_assemble_kernel(PrecondArgs p) {
 // snapshot of the pivot rows.  The row interchanges are undone as column
 // interchanges at the end.
 constexpr int GJ_THREADS = 1024;
-constexpr int GJ_MAXN = 4096;   // largest cluster (extended set) the inversion handles
+constexpr int GJ_MAXN = PC_MAX_EXT;   // largest cluster (extended set) the inversion handles
 constexpr int GJ_B = 32;        // panel width
 constexpr int GJ_TILE = 64;     // update tile (rows x columns)
 

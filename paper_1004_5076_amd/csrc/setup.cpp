@@ -496,18 +496,19 @@ std::string build_clusters(const Geometry &g, const Layout &L, double cell, doub
   cl.core_ptr.assign(cl.nc + 1, 0);
   cl.a_off.assign(cl.nc + 1, 0);
   cl.r_off.assign(cl.nc + 1, 0);
-  size_t maxext = 0;
+  size_t maxext = 0, maxcore = 0;
   for (int c = 0; c < cl.nc; c++) {
     size_t ne_c = ext[c].size(), nc_c = core[c].size();
     maxext = std::max(maxext, ne_c);
+    maxcore = std::max(maxcore, nc_c);
     cl.ext_ptr[c + 1] = cl.ext_ptr[c] + ne_c;
     cl.core_ptr[c + 1] = cl.core_ptr[c] + nc_c;
     cl.a_off[c + 1] = cl.a_off[c] + (int64_t)(ne_c * ne_c);
     cl.r_off[c + 1] = cl.r_off[c] + (int64_t)ne_c * rt_stride((int64_t)nc_c);
   }
-  if (maxext > 4096) {
+  if (maxext > (size_t)PC_MAX_EXT || maxcore > (size_t)PC_MAX_CORE) {
     *too_large = true;
-    return "preconditioner cluster too large (> 4096 unknowns); reduce the cell size";
+    return "preconditioner cluster too large (extended set > 8192 or core > 4096 unknowns); reduce the cell size";
   }
   cl.ext_slot.resize(cl.ext_ptr[cl.nc]);
   cl.core_pos.resize(cl.core_ptr[cl.nc]);
