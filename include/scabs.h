@@ -164,6 +164,16 @@ int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, i
 int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                           int mode, scabs_solve_info *info);
 
+/* The right preconditioner of the solves on its own: y = M x (transpose = 0)
+ * or y = M^T x (transpose = 1), M the restricted additive Schwarz operator
+ * (the stored core rows of each cluster's inverted exact near-field block,
+ * see scabs_opts.precond), for nrhs device vectors of 2N doubles stored one
+ * after another (x and y must not overlap).  prec: SCABS_FP64, or SCABS_FP32
+ * for the arithmetic of the FP32 inner solves (vectors stay FP64; the
+ * transposed apply is FP64 either way).  SCABS_E_STATE when the context was
+ * built without a preconditioner. */
+int scabs_precond_apply(scabs_ctx *c, const double *x, double *y, int nrhs, int prec, int transpose);
+
 /* Incident field of an electric dipole (as scabs_rhs_dipole) at every
  * quadrature point (zero on other bodies).  E: device, n_points * 3 complex
  * (6 n_points doubles), point-major. */
@@ -229,7 +239,11 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
 #define SCABS_STAGE_GATHER32 14  /* lattice gather of the FP32 projection, one record
                                     per grid (inside stage SCABS_STAGE_PROJECT +
                                     SCABS_STAGE_FP32_OFFSET) */
-#define SCABS_NSTAGES 15
+#define SCABS_STAGE_PCGATHER32 15 /* FP32 inner solves: the inputs of the Schwarz
+                                     blocks gathered once per application into an
+                                     ext-ordered FP32 copy (before each
+                                     SCABS_STAGE_PRECOND record) */
+#define SCABS_NSTAGES 16
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
 /* Algorithmic HBM bytes of the records of each stage of the last finished
@@ -239,9 +253,11 @@ int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
  * SCABS_STAGE_GATHER32: the 8 weighted sources of every point read once and
  * the 8 fields of every lattice node written once;
  * SCABS_STAGE_PRECOND (FP32 inner solves): every stored coefficient once (4
- * bytes), per extended-set entry its index, its column scale and the FP64
- * inputs of the vectors applied, per unknown its index and FP64 outputs.  Returns SCABS_E_ARG for null
- * arguments. */
+ * bytes), per extended-set entry the FP32 gathered inputs of the vectors
+ * applied, per unknown its index and FP64 outputs;
+ * SCABS_STAGE_PCGATHER32: per extended-set entry its index, its column scale,
+ * the FP64 inputs read and the FP32 copies written.  Returns SCABS_E_ARG for
+ * null arguments. */
 int scabs_profile_bytes(const scabs_ctx *c, double *bytes);
 
 const char *scabs_last_error(const scabs_ctx *c);

@@ -24,12 +24,12 @@ SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCO
 SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
-            "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_incident_dipole_points",
+            "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
-          "near32", "precond", "ortho", "precond_t", "xline32", "gather32"]
+          "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32"]
 
 
 class ScabsError(RuntimeError):
@@ -93,6 +93,7 @@ def load() -> C.CDLL:
     L.scabs_matvec_transpose.argtypes = [P, P, P, C.c_int, C.c_int]
     L.scabs_solve_transpose.argtypes = [P, P, P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
                                         C.POINTER(SolveInfo)]
+    L.scabs_precond_apply.argtypes = [P, P, P, C.c_int, C.c_int, C.c_int]
     L.scabs_incident_dipole_points.argtypes = [P, dp, dp, C.c_int, P]
     L.scabs_point_fields.argtypes = [P, P, P, P]
     L.scabs_eval_field.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
@@ -224,6 +225,16 @@ class Context:
         nrhs = 1 if x.dim() == 1 else x.shape[0]
         fn = self._L.scabs_matvec_transpose if transpose else self._L.scabs_matvec
         self._check(fn(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, prec))
+        return y
+
+    def precond_apply(self, x, prec: int = SCABS_FP64, transpose: bool = False):
+        """y = M x or M^T x with the Schwarz preconditioner (one or a stack of vectors)."""
+        import torch
+        x = self._dev(x)
+        y = torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        self._check(self._L.scabs_precond_apply(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs,
+                                                prec, int(bool(transpose))))
         return y
 
     def incident_dipole_points(self, pos, moment, body: int = 0):

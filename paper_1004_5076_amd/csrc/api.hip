@@ -140,6 +140,7 @@ struct scabs_ctx {
   int pc_max_ext = 0;        // largest extended set
   uint32_t *pc_Rt = nullptr;   // stored rows (FP16 pairs), see PcStore
   float *pc_Rs = nullptr;      // column scales, one per ext entry
+  cx<float> *pc_xe = nullptr;  // FP32 ext-ordered inputs of the batched apply (n_ext x max batch)
   // transposed apply: cluster of every ext entry, and per unknown its ext entries
   int64_t pc_n_ext = 0;
   int64_t pc_coef = 0;   // stored preconditioner coefficients (core rows x ext columns, unpadded)
@@ -147,6 +148,7 @@ struct scabs_ctx {
   int pc_n_t_items = 0;
   int64_t *pc_inv_ptr = nullptr, *pc_inv_pos = nullptr;
   cx<double> *pc_tmp = nullptr;
+  cx<double> *pc_xc = nullptr;   // x in core order (N entries)
   // solver workspace (grown on demand)
   DevMem work;
   int work_restart = -1, work_nb = 0;
@@ -413,6 +415,9 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   }
   if (!e.empty()) throw e;
   if (too_large) throw std::string("preconditioner clusters above the largest invertible block remain");
+  // the cores must partition the unknowns (the applies write every unknown
+  // once and the transposed apply permutes x into core order)
+  if (c->cl.core_ptr[c->cl.nc] != L.N) throw std::string("preconditioner cores do not cover every unknown once");
   LocalTerms lt;
   build_local_terms(g, L, lt);
   const Clusters &cl = c->cl;
@@ -470,6 +475,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
     c->pc_inv_ptr = c->mem.upload(inv_ptr);
     c->pc_inv_pos = c->mem.upload(inv_pos);
     c->pc_tmp = c->mem.alloc<cx<double>>(n_ext);
+    c->pc_xc = c->mem.alloc<cx<double>>((size_t)L.N);
   }
   {
     const int rows = precond_rows_per_item();
@@ -492,6 +498,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
   c->pc_Rt = c->mem.alloc<uint32_t>((size_t)cl.r_off[cl.nc]);
   c->pc_Rs = c->mem.alloc<float>((size_t)cl.ext_ptr[cl.nc]);
+  c->pc_xe = c->mem.alloc<cx<float>>((size_t)cl.ext_ptr[cl.nc] * precond_apply32_max_batch());
   p.n_ext = cl.ext_ptr[cl.nc];
   int max_ext = 0;
   for (int k = 0; k < cl.nc; k++) max_ext = std::max(max_ext, (int)(cl.ext_ptr[k + 1] - cl.ext_ptr[k]));
@@ -517,7 +524,7 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
                          c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, x, y, c->pc_max_ext, c->stream);
   else
     launch_precond_apply_t(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
-                           c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, x, y,
+                           c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, c->pc_xc, x, y,
                            c->stream);
 }
 
@@ -854,15 +861,20 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
     const int B = precond_apply32_max_batch();
     for (int b0 = 0; b0 < nb; b0 += B) {
       const int m = std::min(B, nb - b0);
-      // coefficients once (4 B); per ext entry its index, its column scale and
-      // m FP64 inputs; per unknown its index and m FP64 outputs
-      const double bytes = 4.0 * (double)c->pc_coef + (8.0 + 16.0 * m) * (double)c->pc_n_ext +
-                           (4.0 + 16.0 * m) * (double)c->lay.N;
+      {
+        // per ext entry its index and column scale, m FP64 inputs read and m
+        // FP32 copies written
+        StageTimer tm(c, SCABS_STAGE_PCGATHER32, (8.0 + 24.0 * m) * (double)c->pc_n_ext);
+        launch_precond_gather32(c->pc_n_ext, c->pc_ext_slot, c->pc_Rs, x + b0 * N, (int64_t)N, m, c->pc_xe,
+                                c->stream);
+      }
+      // coefficients once (4 B); per ext entry the m FP32 gathered inputs;
+      // per unknown its index and m FP64 outputs
+      const double bytes =
+          4.0 * (double)c->pc_coef + 8.0 * m * (double)c->pc_n_ext + (4.0 + 16.0 * m) * (double)c->lay.N;
       StageTimer tm(c, SCABS_STAGE_PRECOND, bytes);
-      launch_precond_apply32(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr,
-                             c->pc_core_slot, c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, x + b0 * N, y + b0 * N,
-                             (int64_t)N,
-                             m, c->pc_max_ext, c->stream);
+      launch_precond_apply32(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot, c->pc_r_off,
+                             c->pc_Rt, c->pc_xe, y + b0 * N, (int64_t)N, m, c->stream);
     }
     return;
   }
@@ -1349,6 +1361,22 @@ int scabs_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
 
 int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, int prec) {
   return do_matvec(c, x, y, nrhs, prec, true);
+}
+
+int scabs_precond_apply(scabs_ctx *c, const double *x, double *y, int nrhs, int prec, int transpose) {
+  if (!c || !x || !y || nrhs < 1) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (!c->has_pc) return fail(c, SCABS_E_STATE, "the context was built without a preconditioner");
+  if (prec != SCABS_FP32 && prec != SCABS_FP64) return fail(c, SCABS_E_ARG, "prec must be SCABS_FP32 or SCABS_FP64");
+  if (transpose != 0 && transpose != 1) return fail(c, SCABS_E_ARG, "transpose must be 0 or 1");
+  try {
+    apply_precond_n(c, (const cx<double> *)x, (cx<double> *)y, nrhs, transpose != 0, prec);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const HipError &e) {
+    return hip_fail(c, e);
+  }
+  return SCABS_OK;
 }
 
 static int do_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,

@@ -30,6 +30,14 @@ template <typename T> __host__ __device__ inline cx<T> &operator-=(cx<T> &a, cx<
 template <typename T> __host__ __device__ inline cx<T> czero() { return {T(0), T(0)}; }
 template <typename T> __host__ __device__ inline cx<T> mul_j(cx<T> a) { return {-a.y, a.x}; }   // j * a
 template <typename T> __host__ __device__ inline cx<T> conjc(cx<T> a) { return {a.x, -a.y}; }
+// acc += a * b in four FMAs (complex multiply-accumulate; written out so the
+// accumulation fuses instead of a product followed by an add)
+template <typename T> __host__ __device__ inline void cmac(cx<T> &acc, cx<T> a, cx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
 // a += s * b (s real)
 template <typename T> __host__ __device__ inline void axpy(cx<T> &a, T s, cx<T> b) {
   a.x += s * b.x;

@@ -167,11 +167,15 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
                           const cx<double> *x, cx<double> *y, int max_ext, hipStream_t s);
 
 // FP32 batched apply (inner solves of the mixed mode): m vectors of N,
-// m <= precond_apply32_max_batch()
+// m <= precond_apply32_max_batch().  First the inputs are gathered into an
+// ext-ordered copy xe[e m + b] = scale_e x_b[ext_slot_e] (FP32, n_ext m
+// entries), then every work-group stages its cluster's part of xe.
 int precond_apply32_max_batch();
-void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
-                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
-                            const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext, hipStream_t s);
+void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<double> *x, int64_t N,
+                             int m, cx<float> *xe, hipStream_t s);
+void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int64_t *core_ptr,
+                            const int *core_slot, const int64_t *r_off, const uint32_t *R, const cx<float> *xe,
+                            cx<double> *y, int64_t N, int m, hipStream_t s);
 
 // ---- transposed product, adjoint gradient --------------------------------------
 template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s);
@@ -187,8 +191,8 @@ void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y
 int precond_t_cols_per_item();
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
-                            const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
-                            cx<double> *y, hipStream_t s);
+                            const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, cx<double> *xc,
+                            const cx<double> *x, cx<double> *y, hipStream_t s);
 void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &ext, const DevGrid<double> *ints_dev,
                          double inv_h, cx<double> *Ee, cx<double> *Ei, hipStream_t s);
 void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, const cx<double> *Ei,

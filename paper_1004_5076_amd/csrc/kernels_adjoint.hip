@@ -475,58 +475,100 @@ template void launch_near_rows_t<double>(const DevOperator<double> &, const int6
 
 // ---------------------------------------------------------------------------
 // transposed Schwarz preconditioner: y = sum_c R_ext^T B_c^T P_core x with
-// B_c the stored core rows of cluster c's inverse.  Step 1: one work-group per
-// (cluster, block of PT_COLS ext columns) stages x on the cluster's core in
-// LDS; each wave then forms dot(B_c[:, j], x[core_c]) for its columns j,
-// reading each stored column once, contiguously.  Step 2: every unknown sums
-// its entries over the clusters whose ext set holds it (fixed order, no
-// atomics).
+// B_c the stored core rows of cluster c's inverse.  Step 1: x is copied into
+// core order (the cores partition the unknowns, so this is a permutation).
+// Step 2: one work-group per (cluster, block of PT_COLS ext columns); each
+// wave forms dot(B_c[:, j], x[core_c]) for PT_WCOLS columns j at once, lanes
+// over rows (every stored column read once, contiguously, PT_WCOLS loads in
+// flight per row block, the core-ordered x read from L2), then reduces the
+// 2 PT_WCOLS partial sums across the wave in one halving exchange.  Step 3:
+// every unknown sums its entries over the clusters whose ext set holds it
+// (fixed order, no atomics).
 // ---------------------------------------------------------------------------
 constexpr int PT_COLS = 64;
 constexpr int PT_THREADS = 512;
-constexpr int PT_MAXCORE = PC_MAX_CORE;   // largest core of a cluster
+constexpr int PT_WCOLS = PT_COLS / (PT_THREADS / 64);   // columns per wave
+static_assert(PT_WCOLS == 8, "the wave reduction below is written for 8 columns (16 values)");
 int precond_t_cols_per_item() { return PT_COLS; }
+
+__global__ void precond_t_gather_kernel(int64_t n, const int *__restrict__ core_slot, const cx<double> *__restrict__ x,
+                                        cx<double> *__restrict__ xc) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) xc[p] = x[core_slot[p]];
+}
+
+// One halving exchange: lanes whose bit (lane & MASK) is set keep the upper
+// HALF values, the others the lower HALF; each adds its partner's copy of the
+// kept values (partner = lane ^ MASK).  Kept values move to v[0, HALF).
+template <int HALF, int MASK> __device__ inline void halve_exchange(double *v, int lane) {
+  const bool up = (lane & MASK) != 0;
+#pragma unroll
+  for (int k = 0; k < HALF; k++) {
+    const double send = up ? v[k] : v[k + HALF];
+    const double keep = up ? v[k + HALF] : v[k];
+    v[k] = keep + __shfl_xor(send, MASK, 64);
+  }
+}
+
+// Sum over the 64 lanes of 16 values at once: four halving exchanges leave
+// lane L with a 16-lane partial of value (L >> 2) & 15, two more exchanges
+// finish it.  Returns, on every lane, the full sum of value (L >> 2) & 15.
+__device__ inline double wsum16_scatter(double v[16]) {
+  const int lane = threadIdx.x & 63;
+  halve_exchange<8, 32>(v, lane);
+  halve_exchange<4, 16>(v, lane);
+  halve_exchange<2, 8>(v, lane);
+  halve_exchange<1, 4>(v, lane);
+  double t = v[0];
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  return t;
+}
 
 __global__ void __launch_bounds__(PT_THREADS)
 precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
-                      const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
-                      const int64_t *__restrict__ r_off, PcStore pc, const cx<double> *__restrict__ x,
-                      cx<double> *__restrict__ tmp) {
-  __shared__ cx<double> xs[PT_MAXCORE];
-  const int c = items[2 * blockIdx.x], j0 = items[2 * blockIdx.x + 1];
+                      const int64_t *__restrict__ core_ptr, const int64_t *__restrict__ r_off, PcStore pc,
+                      const cx<double> *__restrict__ xc, cx<double> *__restrict__ tmp) {
+  // the items of one cluster are consecutive: keep them on one XCD (its L2
+  // then serves the cluster's core-ordered x to all of them)
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int c = items[2 * item], j0 = items[2 * item + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int ncore = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const int *cs = core_slot + core_ptr[c];
-  for (int i = threadIdx.x; i < ncore; i += blockDim.x) xs[i] = x[cs[i]];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int jw = j0 + w * PT_WCOLS;
+  const int nj = min(PT_WCOLS, ne - jw);   // wave-uniform
+  if (nj <= 0) return;
   const int64_t ncp = rt_stride(ncore);
-  const int j1 = min(j0 + PT_COLS, ne);
-  for (int j = j0 + w; j < j1; j += nw) {
-    const uint32_t *R = pc.R + r_off[c] + (int64_t)j * ncp;
-    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    int i = lane;
-    for (; i + 192 < ncore; i += 256) {
-      cx<float> rv[4];
+  const cx<double> *xcc = xc + core_ptr[c];
+  // columns past the last one repeat it (read, never written)
+  const uint32_t *Rcol[PT_WCOLS];
 #pragma unroll
-      for (int u = 0; u < 4; u++) rv[u] = unpack_h2(R[i + 64 * u]);
+  for (int u = 0; u < PT_WCOLS; u++) Rcol[u] = pc.R + r_off[c] + (int64_t)(jw + min(u, nj - 1)) * ncp;
+  double v[2 * PT_WCOLS];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const cx<double> xv = xs[i + 64 * u];
-        ar[u] += (double)rv[u].x * xv.x - (double)rv[u].y * xv.y;
-        ai[u] += (double)rv[u].x * xv.y + (double)rv[u].y * xv.x;
-      }
+  for (int k = 0; k < 2 * PT_WCOLS; k++) v[k] = 0.0;
+  for (int i = lane; i < ncore; i += 64) {
+    cx<float> rv[PT_WCOLS];
+#pragma unroll
+    for (int u = 0; u < PT_WCOLS; u++) rv[u] = unpack_h2(Rcol[u][i]);
+    const cx<double> xv = xcc[i];
+#pragma unroll
+    for (int u = 0; u < PT_WCOLS; u++) {
+      v[2 * u] = fma((double)rv[u].x, xv.x, v[2 * u]);
+      v[2 * u] = fma(-(double)rv[u].y, xv.y, v[2 * u]);
+      v[2 * u + 1] = fma((double)rv[u].x, xv.y, v[2 * u + 1]);
+      v[2 * u + 1] = fma((double)rv[u].y, xv.x, v[2 * u + 1]);
     }
-    for (; i < ncore; i += 64) {
-      const cx<float> rv = unpack_h2(R[i]);
-      const cx<double> xv = xs[i];
-      ar[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-      ai[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
-    }
-    const double sr = wsum((ar[0] + ar[1]) + (ar[2] + ar[3])), si = wsum((ai[0] + ai[1]) + (ai[2] + ai[3]));
-    const double sc = pc.scale[e0 + j];
-    if (lane == 0) tmp[e0 + j] = {sr * sc, si * sc};
+  }
+  const double t = wsum16_scatter(v);
+  const int k = (lane >> 2) & 15, u = k >> 1;
+  // lanes 0, 8, 16, ... hold the real parts, lanes 4, 12, ... the imaginary parts
+  const double other = __shfl_down(t, 4, 64);
+  if ((lane & 7) == 0 && u < nj) {
+    const double sc = pc.scale[e0 + jw + u];
+    tmp[e0 + jw + u] = {t * sc, other * sc};
   }
 }
 
@@ -539,12 +581,16 @@ __global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_
   }
 }
 
+// xc: N entries of work space (x in core order)
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
-                            const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, const cx<double> *x,
-                            cx<double> *y, hipStream_t s) {
-  hipLaunchKernelGGL(precond_t_dots_kernel, dim3(n_items), dim3(PT_THREADS), 0, s, items, ext_ptr, core_ptr, core_slot,
-                     r_off, pc, x, tmp);
+                            const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, cx<double> *xc,
+                            const cx<double> *x, cx<double> *y, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(precond_t_gather_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, core_slot, x, xc);
+  if (n_items > 0)
+    hipLaunchKernelGGL(precond_t_dots_kernel, dim3(n_items), dim3(PT_THREADS), 0, s, items, ext_ptr, core_ptr, r_off,
+                       pc, (const cx<double> *)xc, tmp);
   hipLaunchKernelGGL(precond_t_sum_kernel, dim3(1024), dim3(256), 0, s, N, inv_ptr, inv_pos, (const cx<double> *)tmp,
                      y);
 }

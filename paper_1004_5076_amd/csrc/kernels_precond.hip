@@ -256,7 +256,7 @@ gj_update_kernel(cx<float> *Ablocks, const int64_t *a_off, const int64_t *ext_pt
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-      for (int b = 0; b < 4; b++) acc[a][b] += pv[a] * tv[b];
+      for (int b = 0; b < 4; b++) cmac(acc[a][b], pv[a], tv[b]);
   }
 #pragma unroll
   for (int a = 0; a < 4; a++) {
@@ -435,70 +435,76 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
                      core_slot, r_off, pc, x, y);
 }
 
-// Batched apply in single precision for the FP32 inner solves: nb <= 8
-// vectors per launch, their ext entries staged in LDS as FP32 (all lanes of a
-// wave read the same column: broadcast), each coefficient read once for all
-// of them, FP32 accumulation.  Inner solves stop at relative residuals of
-// 1e-5 or more and an FP64 refinement follows, so the rounding of x and of
-// the sums only perturbs the preconditioner, not the solution.
+// Batched apply in single precision for the FP32 inner solves: NB <= 8
+// vectors per launch (a compile-time count, so the inner loop has no
+// per-vector branches).  The inputs are first gathered once into an
+// ext-ordered FP32 copy with the column scale folded in (NB values per
+// column, contiguous).  Work-group = PA_ROWS core rows of one cluster, its
+// PA32_Q waves split the cluster's columns; within a wave every lane reads
+// the same column's NB inputs, so these are wave-uniform (scalar) loads fed
+// straight into the FMAs, and each coefficient is read once for all vectors;
+// FP32 sums, combined across the waves in LDS at the end.  Inner solves stop
+// at relative residuals of 1e-5 or more and an FP64 refinement follows, so
+// the rounding of x and of the sums only perturbs the preconditioner, not
+// the solution.
 constexpr int PA32_Q = 8;
 constexpr int PA32_THREADS = PA_ROWS * PA32_Q;
-constexpr int PA32_CW = 512;   // ext columns staged per pass
+
+__global__ void precond_gather32_kernel(int64_t n_ext, int m, const int *__restrict__ ext_slot,
+                                        const float *__restrict__ scale, const cx<double> *__restrict__ x, int64_t N,
+                                        cx<float> *__restrict__ xe) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_ext * m) return;
+  const int64_t e = t / m;
+  const int b = (int)(t - e * m);
+  const cx<double> v = x[(size_t)b * N + ext_slot[e]];
+  const float sc = scale[e];
+  xe[t] = {(float)v.x * sc, (float)v.y * sc};
+}
+
 template <int NB>
 __global__ void __launch_bounds__(PA32_THREADS)
 precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
-                       const int *__restrict__ ext_slot, const int64_t *__restrict__ core_ptr,
-                       const int *__restrict__ core_slot, const int64_t *__restrict__ r_off, PcStore pc,
-                       const cx<double> *__restrict__ x, cx<double> *__restrict__ y, int64_t N, int nb) {
-  // the column staging and, after the last pass, the partial sums share LDS
-  static_assert(PA32_Q * PA_ROWS <= PA32_CW, "partial sums must fit the staging buffer");
-  __shared__ cx<float> xs[NB][PA32_CW];
-  cx<float>(*red)[PA_ROWS][NB] = reinterpret_cast<cx<float>(*)[PA_ROWS][NB]>(&xs[0][0]);
-  const int c = items[2 * blockIdx.x], i0 = items[2 * blockIdx.x + 1];
+                       const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
+                       const int64_t *__restrict__ r_off, const uint32_t *__restrict__ Rst,
+                       const cx<float> *__restrict__ xe, cx<double> *__restrict__ y, int64_t N) {
+  __shared__ cx<float> red[PA32_Q][PA_ROWS][NB];
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int c = items[2 * item], i0 = items[2 * item + 1];
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
-  const uint32_t *R = pc.R + r_off[c];
+  const uint32_t *R = Rst + r_off[c];
   const int64_t ncp = rt_stride(nc);
-  const int q = threadIdx.x / PA_ROWS, il = threadIdx.x - q * PA_ROWS;
+  // q is uniform within a wave (PA_ROWS is the wave size); saying so lets the
+  // column loads below be scalar loads
+  static_assert(PA_ROWS == 64, "one wave per row block");
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / PA_ROWS);
+  const int il = threadIdx.x - q * PA_ROWS;
   const int i = i0 + il;
   cx<float> acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; b++) acc[b] = czero<float>();
-  for (int cb = 0; cb < ne; cb += PA32_CW) {
-    const int cw = min(PA32_CW, ne - cb);
-    __syncthreads();   // the previous pass is done with xs
-    for (int t = threadIdx.x; t < nb * cw; t += blockDim.x) {
-      const int b = t / cw, jj = t - b * cw;
-      const cx<double> v = x[(size_t)b * N + ext_slot[e0 + cb + jj]];
-      const float sc = pc.scale[e0 + cb + jj];   // the column scale folds into the staged input
-      xs[b][jj] = {(float)v.x * sc, (float)v.y * sc};
+  const int jb = (int)(((int64_t)ne * q) / PA32_Q), je = (int)(((int64_t)ne * (q + 1)) / PA32_Q);
+  if (i < nc) {
+    const uint32_t *Rc = R + i;
+    const cx<float> *xc = xe + e0 * NB;
+    int j = jb;
+    for (; j + 8 <= je; j += 8) {
+      cx<float> rv[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) rv[u] = unpack_h2(Rc[(int64_t)(j + u) * ncp]);
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) cmac(acc[b], rv[u], xc[(j + u) * NB + b]);
     }
-    __syncthreads();
-    const int jb = (cw * q) / PA32_Q, je = (cw * (q + 1)) / PA32_Q;
-    if (i < nc) {
-      // eight coefficient loads in flight per thread
-      const uint32_t *Rc = R + (int64_t)cb * ncp + i;
-      int j = jb;
-      for (; j + 8 <= je; j += 8) {
-        cx<float> rv[8];
+    for (; j < je; j++) {
+      const cx<float> rv = unpack_h2(Rc[(int64_t)j * ncp]);
 #pragma unroll
-        for (int u = 0; u < 8; u++) rv[u] = unpack_h2(Rc[(j + u) * ncp]);
-#pragma unroll
-        for (int u = 0; u < 8; u++)
-#pragma unroll
-          for (int b = 0; b < NB; b++)
-            if (b < nb) acc[b] += rv[u] * xs[b][j + u];
-      }
-      for (; j < je; j++) {
-        const cx<float> rv = unpack_h2(Rc[j * ncp]);
-#pragma unroll
-        for (int b = 0; b < NB; b++)
-          if (b < nb) acc[b] += rv * xs[b][j];
-      }
+      for (int b = 0; b < NB; b++) cmac(acc[b], rv, xc[j * NB + b]);
     }
   }
-  __syncthreads();   // every wave is done with xs
 #pragma unroll
   for (int b = 0; b < NB; b++) red[q][il][b] = acc[b];
   __syncthreads();
@@ -506,7 +512,6 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
     const int slot = core_slot[core_ptr[c] + i];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-      if (b >= nb) break;
       cx<float> t = red[0][il][b];
       for (int k = 1; k < PA32_Q; k++) t += red[k][il][b];
       y[(size_t)b * N + slot] = {(double)t.x, (double)t.y};
@@ -516,25 +521,41 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
 
 int precond_apply32_max_batch() { return 8; }
 
-// m <= precond_apply32_max_batch() vectors; max_ext (largest extended set)
-// sizes the LDS staging
-void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int *ext_slot,
-                            const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
-                            const cx<double> *x, cx<double> *y, int64_t N, int m, int max_ext, hipStream_t s) {
-  const size_t lds = 0;
-  (void)max_ext;
-  if (m == 1)
-    hipLaunchKernelGGL((precond_apply32_kernel<1>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, pc, x, y, N, m);
-  else if (m == 2)
-    hipLaunchKernelGGL((precond_apply32_kernel<2>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, pc, x, y, N, m);
-  else if (m <= 4)
-    hipLaunchKernelGGL((precond_apply32_kernel<4>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, pc, x, y, N, m);
-  else
-    hipLaunchKernelGGL((precond_apply32_kernel<8>), dim3(n_items), dim3(PA32_THREADS), lds, s, items, ext_ptr, ext_slot,
-                       core_ptr, core_slot, r_off, pc, x, y, N, m);
+void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<double> *x, int64_t N,
+                             int m, cx<float> *xe, hipStream_t s) {
+  const int64_t total = n_ext * m;
+  if (total == 0) return;
+  const int threads = 256;
+  hipLaunchKernelGGL(precond_gather32_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s,
+                     n_ext, m, ext_slot, scale, x, N, xe);
+}
+
+template <int NB>
+static void apply32_launch(int n_items, const int *items, const int64_t *ext_ptr, const int64_t *core_ptr,
+                           const int *core_slot, const int64_t *r_off, const uint32_t *R, const cx<float> *xe,
+                           cx<double> *y, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL((precond_apply32_kernel<NB>), dim3(n_items), dim3(PA32_THREADS), 0, s, items, ext_ptr, core_ptr,
+                     core_slot, r_off, R, xe, y, N);
+}
+
+// m <= precond_apply32_max_batch() vectors (one kernel instance per count);
+// xe as written by launch_precond_gather32 with the same m
+void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int64_t *core_ptr,
+                            const int *core_slot, const int64_t *r_off, const uint32_t *R, const cx<float> *xe,
+                            cx<double> *y, int64_t N, int m, hipStream_t s) {
+  if (n_items == 0) return;
+#define SCABS_APPLY32(NB) apply32_launch<NB>(n_items, items, ext_ptr, core_ptr, core_slot, r_off, R, xe, y, N, s)
+  switch (m) {
+    case 1: SCABS_APPLY32(1); break;
+    case 2: SCABS_APPLY32(2); break;
+    case 3: SCABS_APPLY32(3); break;
+    case 4: SCABS_APPLY32(4); break;
+    case 5: SCABS_APPLY32(5); break;
+    case 6: SCABS_APPLY32(6); break;
+    case 7: SCABS_APPLY32(7); break;
+    default: SCABS_APPLY32(8); break;
+  }
+#undef SCABS_APPLY32
 }
 
 }  // namespace scabs

@@ -49,6 +49,14 @@ def test_batched_products_equal_single(big):
             assert _rel(Y[k], ctx.matvec(X[k].clone(), prec=prec)) < 1e-13
 
 
+def test_precond_apply_at_benchmark_size(big):
+    """The Schwarz operator at full size (clusters up to 8192 ext / 4096 core
+    unknowns): transpose identity, FP32 against FP64, batch against single."""
+    from test_gpu_parity import _precond_checks
+    w, ctx = big
+    _precond_checks(ctx, 960, (8,))
+
+
 def test_transpose_bilinear_identity(big):
     import torch
     w, ctx = big

@@ -246,3 +246,46 @@ def test_long_lattice_matvec(apart, prec, tol, transpose):
         err = _rel(Y[k], ref)
         print("long lattice prec", prec, "transpose", transpose, "rel", err, flush=True)
         assert err < tol
+
+
+def _precond_checks(ctx, seed, batch_sizes):
+    """The Schwarz operator through its own entry point: the transposed apply
+    is the transpose of the forward one (unconjugated bilinear identity, FP64);
+    the FP32 apply of the inner solves agrees with the FP64 apply, and a
+    batch of vectors gives each vector the result of its own apply."""
+    torch = _torch()
+    import paper_1004_5076_amd as pk
+    N = ctx.N
+    x = torch.from_numpy(synth.random_complex(seed, N)).cuda()
+    z = torch.from_numpy(synth.random_complex(seed + 1, N)).cuda()
+    Mx = ctx.precond_apply(x)
+    Mtz = ctx.precond_apply(z, transpose=True)
+    a = (z * Mx).sum().item()
+    b = (Mtz * x).sum().item()
+    scale = (torch.linalg.norm(z) * torch.linalg.norm(Mx)).item()
+    print("precond bilinear", a, b, abs(a - b) / scale, flush=True)
+    assert abs(a - b) <= 1e-12 * scale
+    for nb in batch_sizes:
+        X = torch.from_numpy(np.stack([synth.random_complex(seed + 10 + k, N) for k in range(nb)])).cuda()
+        Y32 = ctx.precond_apply(X, prec=pk.SCABS_FP32)
+        Y64 = ctx.precond_apply(X, prec=pk.SCABS_FP64)
+        Yt = ctx.precond_apply(X, transpose=True)
+        for k in range(nb):
+            e32 = float(torch.linalg.norm(Y32[k] - Y64[k]) / torch.linalg.norm(Y64[k]))
+            s32 = ctx.precond_apply(X[k].clone(), prec=pk.SCABS_FP32)
+            st = ctx.precond_apply(X[k].clone(), transpose=True)
+            d32 = float(torch.linalg.norm(Y32[k] - s32) / torch.linalg.norm(s32))
+            dt = float(torch.linalg.norm(Yt[k] - st) / torch.linalg.norm(st))
+            print("precond nb", nb, "vector", k, "fp32 vs fp64", e32, "batch vs single", d32, dt, flush=True)
+            assert e32 < 1e-4
+            assert d32 < 1e-6 and dt < 1e-14
+
+
+def test_precond_apply_consistency(small):
+    w, o, P, ctx = small
+    _precond_checks(ctx, 900, (8, 3))
+
+
+def test_precond_apply_two_bodies(apart):
+    _precond_checks(apart[3], 950, (5,))
+
