@@ -497,34 +497,6 @@ __global__ void precond_t_gather_kernel(int64_t n, const int *__restrict__ core_
   if (p < n) xc[p] = x[core_slot[p]];
 }
 
-// One halving exchange: lanes whose bit (lane & MASK) is set keep the upper
-// HALF values, the others the lower HALF; each adds its partner's copy of the
-// kept values (partner = lane ^ MASK).  Kept values move to v[0, HALF).
-template <int HALF, int MASK> __device__ inline void halve_exchange(double *v, int lane) {
-  const bool up = (lane & MASK) != 0;
-#pragma unroll
-  for (int k = 0; k < HALF; k++) {
-    const double send = up ? v[k] : v[k + HALF];
-    const double keep = up ? v[k + HALF] : v[k];
-    v[k] = keep + __shfl_xor(send, MASK, 64);
-  }
-}
-
-// Sum over the 64 lanes of 16 values at once: four halving exchanges leave
-// lane L with a 16-lane partial of value (L >> 2) & 15, two more exchanges
-// finish it.  Returns, on every lane, the full sum of value (L >> 2) & 15.
-__device__ inline double wsum16_scatter(double v[16]) {
-  const int lane = threadIdx.x & 63;
-  halve_exchange<8, 32>(v, lane);
-  halve_exchange<4, 16>(v, lane);
-  halve_exchange<2, 8>(v, lane);
-  halve_exchange<1, 4>(v, lane);
-  double t = v[0];
-  t += __shfl_xor(t, 2, 64);
-  t += __shfl_xor(t, 1, 64);
-  return t;
-}
-
 __global__ void __launch_bounds__(PT_THREADS)
 precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                       const int64_t *__restrict__ core_ptr, const int64_t *__restrict__ r_off, PcStore pc,

@@ -166,7 +166,8 @@ __global__ void finite_check(const double *__restrict__ v, int64_t n, int *bad) 
 //   (2) the partials summed in a fixed order into h_j (and ||w||);
 //   (3) w -= sum_j V_j h_j with ||w||^2 partials of the result, summed by (4).
 // ---------------------------------------------------------------------------
-constexpr int OG_BLOCKS = 256;   // row chunks of the dot pass
+constexpr int OG_BLOCKS = 64;   // row chunks of the dot pass (several rows per thread)
+static_assert(KD_J == 8, "the wave reduction of og_dots is written for 8 columns (16 values)");
 template <typename VT>
 __global__ void __launch_bounds__(KR_THREADS)
 og_dots(const cx<VT> *__restrict__ V, int64_t ldv, int jn, const cx<double> *__restrict__ w, int64_t N, KrRun run,
@@ -177,33 +178,31 @@ og_dots(const cx<VT> *__restrict__ V, int64_t ldv, int jn, const cx<double> *__r
   const int nj = min(KD_J, jn - j0);
   const cx<VT> *Vb = V + (size_t)b * N;
   const cx<double> *wb = w + (size_t)b * N;
-  double re[KD_J], im[KD_J], nn = 0;
+  // columns past the group's last one repeat it (their sums are never stored),
+  // so the loop has no per-column branches
+  const cx<VT> *Vq[KD_J];
 #pragma unroll
-  for (int q = 0; q < KD_J; q++) re[q] = im[q] = 0;
+  for (int q = 0; q < KD_J; q++) Vq[q] = Vb + (size_t)(j0 + min(q, nj - 1)) * ldv;
+  double v[2 * KD_J], nn = 0;
+#pragma unroll
+  for (int q = 0; q < 2 * KD_J; q++) v[q] = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)nblk * blockDim.x) {
     const cx<double> x = wb[i];
-    nn += x.x * x.x + x.y * x.y;
+    nn = fma(x.x, x.x, nn);
+    nn = fma(x.y, x.y, nn);
 #pragma unroll
     for (int q = 0; q < KD_J; q++) {
-      if (q < nj) {
-        const cx<VT> a = Vb[(size_t)(j0 + q) * ldv + i];
-        re[q] += (double)a.x * x.x + (double)a.y * x.y;
-        im[q] += (double)a.x * x.y - (double)a.y * x.x;
-      }
+      const cx<VT> a = Vq[q][i];
+      v[2 * q] = fma((double)a.x, x.x, v[2 * q]);
+      v[2 * q] = fma((double)a.y, x.y, v[2 * q]);
+      v[2 * q + 1] = fma((double)a.x, x.y, v[2 * q + 1]);
+      v[2 * q + 1] = fma(-(double)a.y, x.x, v[2 * q + 1]);
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < KD_J; q++) {
-    for (int o = 32; o > 0; o >>= 1) {
-      re[q] += __shfl_xor(re[q], o, 64);
-      im[q] += __shfl_xor(im[q], o, 64);
-    }
-    if (lane == 0) {
-      sh[2 * q][wid] = re[q];
-      sh[2 * q + 1][wid] = im[q];
-    }
-  }
+  // lane L ends with the wave sum of value (L >> 2) & 15
+  const double t = wsum16_scatter(v);
+  if ((lane & 3) == 0) sh[(lane >> 2) & 15][wid] = t;
   for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
   if (lane == 0) sh[2 * KD_J][wid] = nn;
   __syncthreads();

@@ -124,44 +124,92 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
     for (int f = 0; f < 8; f++) acc[m][f] = czero<T>();
   for (int c0 = 0; c0 < K; c0 += SC) {
     const int cn = min(SC, K - c0);
-    for (int it = threadIdx.x; it < 9 * cn; it += blockDim.x) {
-      const int kk = fdiv(it, d9), off = it - 9 * kk;
-      const int k = c0 + kk;
-      const int cxo = (k >= B1) + (k >= B2);
-      const int yz = g.nz_yz[K0 + k];
-      const int cy = fdiv(yz, dn2), cz = yz - cy * n2;
-      const int oyi = fdiv(off, d3);
-      const int ox = x - (xl + cxo), oy = oyi - 1, oz = off - 3 * oyi - 1;
-      cx<T> a[8];
+    if constexpr (sizeof(T) == 4 && MAXI == 1) {
+      // FP32, at most one node per thread: one item per (cell, y offset)
+      // producing the three z offsets, so a point's loads and its x-y weight
+      // serve three node sums (same products and order as one item per
+      // offset; with more nodes per thread, or in FP64, the registers of the
+      // three sums would spill)
+      for (int it = threadIdx.x; it < 3 * cn; it += blockDim.x) {
+        const int kk = fdiv(it, d3), oyi = it - 3 * kk;
+        const int k = c0 + kk;
+        const int cxo = (k >= B1) + (k >= B2);
+        const int yz = g.nz_yz[K0 + k];
+        const int cy = fdiv(yz, dn2);
+        const int ox = x - (xl + cxo), oy = oyi - 1;
+        cx<T> a[3][8];
 #pragma unroll
-      for (int f = 0; f < 8; f++) a[f] = czero<T>();
-      if (cy + oy >= 0 && cy + oy < n1 && cz + oz >= 0 && cz + oz < n2) {
-        const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
-        const int64_t p1 = g.cellptr[cell + 1];
-        int64_t p = g.cellptr[cell];
-        // two points' loads in flight (FP32; FP64 would spill)
-        for (; sizeof(T) == 4 && p + 2 <= p1; p += 2) {
-          cx<T> s0[8], s1[8];
+        for (int r = 0; r < 3; r++)
 #pragma unroll
-          for (int f = 0; f < 8; f++) {
-            s0[f] = gsrc[8 * p + f];
-            s1[f] = gsrc[8 * p + 8 + f];
+          for (int f = 0; f < 8; f++) a[r][f] = czero<T>();
+        if (cy + oy >= 0 && cy + oy < n1) {
+          const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
+          const int64_t p1 = g.cellptr[cell + 1];
+          int64_t p = g.cellptr[cell];
+          for (; p + 2 <= p1; p += 2) {
+            cx<T> s0[8], s1[8];
+#pragma unroll
+            for (int f = 0; f < 8; f++) {
+              s0[f] = gsrc[8 * p + f];
+              s1[f] = gsrc[8 * p + 8 + f];
+            }
+            const T w0 = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]);
+            const T w1 = lag_w(ox, g.u[3 * p + 3]) * lag_w(oy, g.u[3 * p + 4]);
+            const T uz0 = g.u[3 * p + 2], uz1 = g.u[3 * p + 5];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+              const T wr0 = w0 * lag_w(r - 1, uz0), wr1 = w1 * lag_w(r - 1, uz1);
+#pragma unroll
+              for (int f = 0; f < 8; f++) axpy(a[r][f], wr0, s0[f]);
+#pragma unroll
+              for (int f = 0; f < 8; f++) axpy(a[r][f], wr1, s1[f]);
+            }
           }
-          const T w0 = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]) * lag_w(oz, g.u[3 * p + 2]);
-          const T w1 = lag_w(ox, g.u[3 * p + 3]) * lag_w(oy, g.u[3 * p + 4]) * lag_w(oz, g.u[3 * p + 5]);
+          for (; p < p1; p++) {
+            const T w = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]);
+            const T uz = g.u[3 * p + 2];
+            cx<T> s0[8];
 #pragma unroll
-          for (int f = 0; f < 8; f++) axpy(a[f], w0, s0[f]);
+            for (int f = 0; f < 8; f++) s0[f] = gsrc[8 * p + f];
 #pragma unroll
-          for (int f = 0; f < 8; f++) axpy(a[f], w1, s1[f]);
+            for (int r = 0; r < 3; r++) {
+              const T wr = w * lag_w(r - 1, uz);
+#pragma unroll
+              for (int f = 0; f < 8; f++) axpy(a[r][f], wr, s0[f]);
+            }
+          }
         }
-        for (; p < p1; p++) {
-          const T w = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]) * lag_w(oz, g.u[3 * p + 2]);
+        // z offsets whose node lies outside the lattice are never read back
 #pragma unroll
-          for (int f = 0; f < 8; f++) axpy(a[f], w, gsrc[8 * p + f]);
-        }
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+          for (int f = 0; f < 8; f++) s_q[f][9 * kk + 3 * oyi + r] = a[r][f];
       }
+    } else {
+      for (int it = threadIdx.x; it < 9 * cn; it += blockDim.x) {
+        const int kk = fdiv(it, d9), off = it - 9 * kk;
+        const int k = c0 + kk;
+        const int cxo = (k >= B1) + (k >= B2);
+        const int yz = g.nz_yz[K0 + k];
+        const int cy = fdiv(yz, dn2), cz = yz - cy * n2;
+        const int oyi = fdiv(off, d3);
+        const int ox = x - (xl + cxo), oy = oyi - 1, oz = off - 3 * oyi - 1;
+        cx<T> a[8];
 #pragma unroll
-      for (int f = 0; f < 8; f++) s_q[f][it] = a[f];
+        for (int f = 0; f < 8; f++) a[f] = czero<T>();
+        if (cy + oy >= 0 && cy + oy < n1 && cz + oz >= 0 && cz + oz < n2) {
+          const int64_t cell = (int64_t)(xl + cxo) * plane + yz;
+          const int64_t p1 = g.cellptr[cell + 1];
+          int64_t p = g.cellptr[cell];
+          for (; p < p1; p++) {
+            const T w = lag_w(ox, g.u[3 * p]) * lag_w(oy, g.u[3 * p + 1]) * lag_w(oz, g.u[3 * p + 2]);
+#pragma unroll
+            for (int f = 0; f < 8; f++) axpy(a[f], w, gsrc[8 * p + f]);
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < 8; f++) s_q[f][it] = a[f];
+      }
     }
     __syncthreads();
 #pragma unroll
