@@ -246,6 +246,11 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
 #define SCABS_NSTAGES 16
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
+/* Restrict the stages that profiling sessions record to those whose bit
+ * (1u << stage) is set in mask (0: every stage, the default); unrecorded
+ * stages add no events to the stream.  SCABS_E_ARG for bits beyond
+ * SCABS_NSTAGES. */
+int scabs_profile_mask(scabs_ctx *c, uint32_t mask);
 /* Algorithmic HBM bytes of the records of each stage of the last finished
  * profiling session (SCABS_NSTAGES entries, written to the caller's host
  * array; 0 for stages that do not define them).  SCABS_STAGE_XLINE32: the

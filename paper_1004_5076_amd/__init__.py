@@ -26,7 +26,7 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
-            "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_bytes",
+            "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
           "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32"]
@@ -103,6 +103,7 @@ def load() -> C.CDLL:
     L.scabs_profile_begin.argtypes = [P]
     L.scabs_profile_end.argtypes = [P, dp, C.POINTER(C.c_int64)]
     L.scabs_profile_bytes.argtypes = [P, dp]
+    L.scabs_profile_mask.argtypes = [P, C.c_uint32]
     L.scabs_last_error.restype = C.c_char_p
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
@@ -301,6 +302,11 @@ class Context:
 
     def profile_begin(self):
         self._check(self._L.scabs_profile_begin(self._c))
+
+    def profile_mask(self, stages=None):
+        """Record only the named stages in later sessions (None: all stages)."""
+        mask = 0 if not stages else sum(1 << STAGES.index(k) for k in stages)
+        self._check(self._L.scabs_profile_mask(self._c, mask))
 
     def profile_end(self) -> dict:
         ms = (C.c_double * len(STAGES))()

@@ -163,6 +163,7 @@ struct scabs_ctx {
   cx<float> *V32 = nullptr;
   // stage timing with HIP events on the context stream
   bool prof_on = false;
+  uint32_t prof_mask = ~0u;   // stages recorded by profiling sessions (bit k: stage k)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   struct ProfRec {
@@ -195,7 +196,7 @@ static hipEvent_t next_event(scabs_ctx *c) {
   return c->ev_pool[c->ev_used++];
 }
 StageTimer::StageTimer(scabs_ctx *cc, int st, double b) : c(cc), stage(st), bytes(b) {
-  if (c->prof_on && (e0 = next_event(c))) hipEventRecord(e0, c->stream);
+  if (c->prof_on && ((c->prof_mask >> st) & 1u) && (e0 = next_event(c))) hipEventRecord(e0, c->stream);
 }
 StageTimer::~StageTimer() {
   if (!e0) return;
@@ -1549,6 +1550,13 @@ int scabs_profile_begin(scabs_ctx *c) {
   c->prof_recs.clear();
   c->ev_used = 0;
   c->prof_on = true;
+  return SCABS_OK;
+}
+
+int scabs_profile_mask(scabs_ctx *c, uint32_t mask) {
+  if (!c) return SCABS_E_ARG;
+  if (mask >> SCABS_NSTAGES) return fail(c, SCABS_E_ARG, "mask names a stage that does not exist");
+  c->prof_mask = mask ? mask : ~0u;
   return SCABS_OK;
 }
 

@@ -44,6 +44,10 @@ def test_argument_errors_without_gpu():
     assert lib.scabs_create(None, None) == -1
     lib.scabs_matvec.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int, ctypes.c_int]
     assert lib.scabs_matvec(None, None, None, 1, 0) == -1
+    lib.scabs_precond_apply.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int] * 3
+    assert lib.scabs_precond_apply(None, None, None, 1, 0, 0) == -1
+    lib.scabs_profile_mask.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    assert lib.scabs_profile_mask(None, 1) == -1
     lib.scabs_last_error.restype = ctypes.c_char_p
     lib.scabs_last_error.argtypes = [ctypes.c_void_p]
     assert lib.scabs_last_error(None) == b"null context"

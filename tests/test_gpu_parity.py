@@ -289,3 +289,21 @@ def test_precond_apply_consistency(small):
 def test_precond_apply_two_bodies(apart):
     _precond_checks(apart[3], 950, (5,))
 
+
+def test_profile_mask_records_only_selected_stages(small):
+    """A stage mask limits the event records of a profiling session."""
+    torch = _torch()
+    w, o, P, ctx = small
+    x = torch.from_numpy(synth.random_complex(990, ctx.N)).cuda()
+    ctx.profile_mask(["fft32", "near32"])
+    ctx.profile_begin()
+    ctx.matvec(x, prec=1)
+    pr = ctx.profile_end()
+    ctx.profile_mask(None)
+    assert pr["fft32"]["count"] == 1 and pr["near32"]["count"] == 1
+    assert all(v["count"] == 0 for k, v in pr.items() if k not in ("fft32", "near32"))
+    ctx.profile_begin()
+    ctx.matvec(x, prec=1)
+    pr = ctx.profile_end()
+    assert pr["project32"]["count"] == 1 and pr["interp32"]["count"] == 1
+
