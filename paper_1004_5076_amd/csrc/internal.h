@@ -105,7 +105,9 @@ void edge_slots(const Layout &L, int e, int *slots, int *nslots);
 // ---------------------------------------------------------------------------
 // device-side records
 // ---------------------------------------------------------------------------
-template <typename T> struct cx { T x, y; };
+// aligned to its size, so that LDS and global accesses of one value are single
+// 8-byte (FP32) or 16-byte (FP64) instructions
+template <typename T> struct alignas(2 * sizeof(T)) cx { T x, y; };
 
 // per quadrature point (also a test point: the rule is shared)
 template <typename T> struct PointRec {

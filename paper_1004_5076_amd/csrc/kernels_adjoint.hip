@@ -150,7 +150,7 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
   constexpr int SC = CellChunkT<T>::value, SQ = 9 * SC;
   static_assert(8 * SQ >= 3 * 1024, "the final reduction reuses s_q for 3 planes of at most 1024 nodes");
   __shared__ cx<T> s_q[8][SQ];
-  extern __shared__ int s_map[];
+  extern __shared__ __align__(16) int s_map[];
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   const int x = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring planes on one XCD

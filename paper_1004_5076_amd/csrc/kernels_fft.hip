@@ -32,7 +32,7 @@ template <typename T, bool WAVE>
 __global__ void __launch_bounds__(FftCfg<T>::threads, FftCfg<T>::min_waves)
 plane_fwd_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n0, int n1, int n2, int N1, int N2,
                  int P, const cx<T> *__restrict__ tw, int twL) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   const int f = blockIdx.y, x0 = blockIdx.x * P;
   const int np = min(P, n0 - x0);
@@ -54,7 +54,7 @@ template <typename T, bool WAVE>
 __global__ void __launch_bounds__(FftCfg<T>::threads, FftCfg<T>::min_waves)
 plane_inv_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n0, int n1, int n2, int N1, int N2,
                  int P, const cx<T> *__restrict__ tw, int twL) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   const int f = blockIdx.y, x0 = blockIdx.x * P;
   const int np = min(P, n0 - x0);
@@ -78,7 +78,7 @@ template <typename T, bool WAVE>
 __global__ void __launch_bounds__(FftCfg<T>::threads, FftCfg<T>::min_waves)
 xline_kernel(cx<T> *__restrict__ spec, int n0, int N0, int N1, int N2, int C, const cx<T> *__restrict__ ghat,
              const cx<T> *__restrict__ tw, int twL, int mode) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);   // [c][x]
   const int f = blockIdx.y, b0 = blockIdx.x * C;
   const int M = N1 * N2;
@@ -151,7 +151,7 @@ template <typename T>
 __global__ void __launch_bounds__(PLANE_REG_THREADS)
 plane_fwd_reg_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, int n0, int n1, int n2, int N1,
                      int N2, int P) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   const int f = blockIdx.y, x0 = blockIdx.x * P;
   const int np = min(P, n0 - x0), S = N2 + 1;
@@ -170,7 +170,7 @@ template <typename T>
 __global__ void __launch_bounds__(PLANE_REG_THREADS)
 plane_inv_reg_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, int n0, int n1, int n2, int N1,
                      int N2, int P) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   const int f = blockIdx.y, x0 = blockIdx.x * P;
   const int np = min(P, n0 - x0), S = N2 + 1;
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(XRegCfg<T>::threads, XRegCfg<T>::min_waves)
 xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *__restrict__ ghx,
                  const cx<T> *__restrict__ twx) {
   constexpr int C = XRegCfg<T>::threads / 64;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   // XCD-aware order: neighbouring column blocks, whose 64-byte row segments
   // share 128-byte lines, run on one XCD at about the same time

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
   constexpr int SC = CellChunk<T>::value, SQ = 9 * SC;
   static_assert(8 * SQ >= 3 * 1024, "the final reduction reuses s_q for 3 planes of at most 1024 nodes");
   __shared__ cx<T> s_q[8][SQ];
-  extern __shared__ int s_map[];   // (plane - xl) * plane + yz -> slot, or -1
+  extern __shared__ __align__(16) int s_map[];   // (plane - xl) * plane + yz -> slot, or -1
   const int n0 = dg.n[0], n1 = dg.n[1], n2 = dg.n[2];
   const int plane = n1 * n2;
   // XCD-aware order: neighbouring planes (which read the same points) on one XCD
