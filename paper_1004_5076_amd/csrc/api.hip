@@ -86,6 +86,7 @@ template <typename T> struct PrecState {
   TriRec<T> *tris = nullptr;
   cx<T> *V4 = nullptr, *S4 = nullptr;
   cx<T> *src = nullptr, *tri_out = nullptr;
+  cx<T> *srcI = nullptr;           // edge-major currents of a batch (nb > 1)
   std::vector<DevGrid<T>> grids;   // host copies holding device pointers
   DevGrid<T> *grids_dev = nullptr;
   std::vector<GatherGrid<T>> gather;
@@ -393,6 +394,7 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   op.V4 = P.V4;
   op.S4 = P.S4;
   op.src = P.src;
+  op.srcI = nullptr;
   op.tri_out = P.tri_out;
 }
 
@@ -731,7 +733,9 @@ template <typename T> static void ensure_batch(scabs_ctx *c, PrecState<T> &P, in
   const Geometry &g = c->geo;
   c->mem.free_one(P.src);
   c->mem.free_one(P.tri_out);
+  if (P.srcI) c->mem.free_one(P.srcI);
   P.src = c->mem.alloc<cx<T>>((size_t)g.ne * 3 * nb);
+  P.srcI = c->mem.alloc<cx<T>>((size_t)g.ne * 3 * nb);
   P.tri_out = c->mem.alloc<cx<T>>((size_t)g.nt * 9 * nb);
   for (size_t k = 0; k < P.grids.size(); k++) {
     DevGrid<T> &G = P.grids[k];
@@ -745,6 +749,7 @@ template <typename T> static void ensure_batch(scabs_ctx *c, PrecState<T> &P, in
   c->mem.free_one(P.grids_dev);
   P.grids_dev = c->mem.upload(P.grids);
   P.op.src = P.src;
+  P.op.srcI = P.srcI;
   P.op.tri_out = P.tri_out;
   P.bcap = nb;
 }

@@ -142,6 +142,20 @@ __device__ inline int xcd_remap(int lin, int total) {
   return i * q + min(i, rem) + k;
 }
 
+// One halving exchange of a per-lane array (any arithmetic type): lanes whose
+// bit (lane & MASK) is set keep the upper HALF values, the others the lower
+// HALF; each adds its partner's copy of the kept values (partner = lane ^
+// MASK).  Kept values move to v[0, HALF).
+template <typename T, int HALF, int MASK> __device__ inline void halve_exchange_t(T *v, int lane) {
+  const bool up = (lane & MASK) != 0;
+#pragma unroll
+  for (int k = 0; k < HALF; k++) {
+    const T send = up ? v[k] : v[k + HALF];
+    const T keep = up ? v[k + HALF] : v[k];
+    v[k] = keep + __shfl_xor(send, MASK, 64);
+  }
+}
+
 // One halving exchange: lanes whose bit (lane & MASK) is set keep the upper
 // HALF values, the others the lower HALF; each adds its partner's copy of the
 // kept values (partner = lane ^ MASK).  Kept values move to v[0, HALF).

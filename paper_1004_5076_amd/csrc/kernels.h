@@ -57,6 +57,9 @@ template <typename T> struct DevOperator {
   const cx<T> *S4;   // per entry: Lrot_e, Krot_e, Lsig_i, Ksig_i (R rows only)
   // work buffers
   cx<T> *src;        // ne * 3: J_e, J_i, M
+  // batches of nb > 1 vectors: the same currents per edge for all vectors,
+  // [e][b][3] (written by the unpack step; null until a batch is used)
+  cx<T> *srcI;
   cx<T> *tri_out;    // nt * 3 (half-edge) * 3 (E, H, eq14 rows)
 };
 

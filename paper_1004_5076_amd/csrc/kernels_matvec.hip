@@ -17,32 +17,41 @@ namespace scabs {
 // ---------------------------------------------------------------------------
 // unknown vector -> per-edge currents (J_e, J_i, M)
 // ---------------------------------------------------------------------------
-// batch index blockIdx.y: x + b * 2N, src + b * 3 ne
+// batch index blockIdx.y: x + b * 2N, src + b * 3 ne; with srcI (nb > 1) the
+// same currents also edge-major, srcI[(e nb + b) 3 + j]
 template <typename T>
 __global__ void unpack_kernel(const EdgeRec *__restrict__ edges, int ne, int N, const double *__restrict__ x,
-                              cx<T> *__restrict__ src) {
+                              cx<T> *__restrict__ src, cx<T> *__restrict__ srcI, int nb) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
-  x += (size_t)blockIdx.y * 2 * N;
-  src += (size_t)blockIdx.y * 3 * ne;
+  const int bb = blockIdx.y;
+  x += (size_t)bb * 2 * N;
+  src += (size_t)bb * 3 * ne;
   EdgeRec r = edges[e];
-  cx<T> a = {(T)x[2 * r.col[0]], (T)x[2 * r.col[0] + 1]};
-  cx<T> b = {(T)x[2 * r.col[1]], (T)x[2 * r.col[1] + 1]};
+  const cx<T> a = {(T)x[2 * r.col[0]], (T)x[2 * r.col[0] + 1]};
+  const cx<T> b = {(T)x[2 * r.col[1]], (T)x[2 * r.col[1] + 1]};
+  cx<T> v[3];
   if (!r.isR) {
-    src[3 * e] = a;
-    src[3 * e + 1] = -a;
-    src[3 * e + 2] = b;
+    v[0] = a;
+    v[1] = -a;
+    v[2] = b;
   } else {
-    cx<T> c = {(T)x[2 * r.col[2]], (T)x[2 * r.col[2] + 1]};
-    src[3 * e] = a;
-    src[3 * e + 1] = b;
-    src[3 * e + 2] = c;
+    v[0] = a;
+    v[1] = b;
+    v[2] = cx<T>{(T)x[2 * r.col[2]], (T)x[2 * r.col[2] + 1]};
+  }
+#pragma unroll
+  for (int j = 0; j < 3; j++) src[3 * e + j] = v[j];
+  if (srcI) {
+    cx<T> *o = srcI + ((size_t)e * nb + bb) * 3;
+#pragma unroll
+    for (int j = 0; j < 3; j++) o[j] = v[j];
   }
 }
 
 template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s, int nb) {
   hipLaunchKernelGGL(unpack_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op.edges, op.ne, op.N, x,
-                     op.src);
+                     op.src, nb > 1 ? op.srcI : (cx<T> *)nullptr, nb);
 }
 template void launch_unpack<float>(const DevOperator<float> &, const double *, hipStream_t, int);
 template void launch_unpack<double>(const DevOperator<double> &, const double *, hipStream_t, int);
@@ -460,71 +469,112 @@ template <typename T> __device__ inline T wave_sum(T v) {
   return v;
 }
 
-// Up to NR_MAXB vectors per launch: every CSR entry's values are read once
-// and applied to all of them.
+// Up to NR_MAXB vectors per launch, NRB = their count (no per-vector
+// branches): every CSR entry's values are read once, combined into the
+// coefficients of J_i, J_e and M of each output row, and applied to all
+// vectors, whose currents at the column edge are contiguous (edge-major
+// batch copy); the 6 NRB sums are reduced across the wave together.
 constexpr int NR_MAXB = 8;
 template <typename T, int NRB>
-__global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, double *__restrict__ y, int nb) {
+__global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, double *__restrict__ y) {
   const int n = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (n >= op.ne) return;
+  if (n >= op.ne) return;   // wave-uniform
   const EdgeRec r = op.edges[n];
   const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
-  const size_t bs = (size_t)3 * op.ne;
-  cx<T> E[NRB], H[NRB], R[NRB];
+  const cx<T> *cur = NRB > 1 ? op.srcI : op.src;   // [m][b][3]
+  // v[6 b + (0, 1 | 2, 3 | 4, 5)] = (E | H | eq14 row) of vector b, re and im
+  T v[6 * NRB];
 #pragma unroll
-  for (int b = 0; b < NRB; b++) E[b] = H[b] = R[b] = czero<T>();
+  for (int q = 0; q < 6 * NRB; q++) v[q] = T(0);
   const int64_t kb = op.rowptr[n], ke = op.rowptr[n + 1];
   for (int64_t k = kb + lane; k < ke; k += 64) {
     const int m = op.col[k];
     const cx<T> Le = op.V4[4 * k], Ke = op.V4[4 * k + 1], Li = op.V4[4 * k + 2], Ki = op.V4[4 * k + 3];
-    cx<T> Lr = czero<T>(), Kr = czero<T>(), Ls = czero<T>(), Ks = czero<T>();
+    //   E += Zi Li Ji - Ze Le Je + (Ke + Ki) M
+    //   H += Ki Ji - (Ke + Ze Lr) Je + (Kr - Le / Ze - Li / Zi) M
+    //   R += Zi Ls Ji + Ks M          (Lr, Kr, Ls, Ks on absorber rows only)
+    cx<T> eJi = Li * Zi, eJe = Le * (-Ze), eM = Ke + Ki;
+    cx<T> hJi = Ki, hJe = -Ke, hM = Le * (-iZe) - Li * iZi;
+    cx<T> rJi = czero<T>(), rM = czero<T>();
     if (r.isR) {
-      Lr = op.S4[4 * k];
-      Kr = op.S4[4 * k + 1];
-      Ls = op.S4[4 * k + 2];
-      Ks = op.S4[4 * k + 3];
+      const cx<T> Lr = op.S4[4 * k], Kr = op.S4[4 * k + 1], Ls = op.S4[4 * k + 2], Ks = op.S4[4 * k + 3];
+      hJe = hJe - Lr * Ze;
+      hM = hM + Kr;
+      rJi = Ls * Zi;
+      rM = Ks;
     }
-    const cx<T> KeKi = Ke + Ki;
+    const cx<T> *cm = cur + (size_t)m * NRB * 3;
 #pragma unroll
     for (int b = 0; b < NRB; b++) {
-      if (b >= nb) break;
-      const cx<T> *src = op.src + bs * b + 3 * m;
-      const cx<T> Je = src[0], Ji = src[1], M = src[2];
-      E[b] += (Li * Ji) * Zi - (Le * Je) * Ze + KeKi * M;
-      H[b] += Ki * Ji - Ke * Je - (Le * M) * iZe - (Li * M) * iZi;
-      if (r.isR) {
-        H[b] += Kr * M - (Lr * Je) * Ze;
-        R[b] += (Ls * Ji) * Zi + Ks * M;
-      }
+      const cx<T> Je = cm[3 * b], Ji = cm[3 * b + 1], M = cm[3 * b + 2];
+      cx<T> e = {v[6 * b], v[6 * b + 1]}, h = {v[6 * b + 2], v[6 * b + 3]}, q = {v[6 * b + 4], v[6 * b + 5]};
+      cmac(e, eJi, Ji);
+      cmac(e, eJe, Je);
+      cmac(e, eM, M);
+      cmac(h, hJi, Ji);
+      cmac(h, hJe, Je);
+      cmac(h, hM, M);
+      cmac(q, rJi, Ji);
+      cmac(q, rM, M);
+      v[6 * b] = e.x;
+      v[6 * b + 1] = e.y;
+      v[6 * b + 2] = h.x;
+      v[6 * b + 3] = h.y;
+      v[6 * b + 4] = q.x;
+      v[6 * b + 5] = q.y;
     }
   }
+  // lane b (b < NRB) ends with the 6 sums of vector b
+  T s6[6];
+  if constexpr (NRB == 8) {
+    // halving exchanges: 48 values -> 3 per lane (values 3 ((L >> 2) & 15) + t
+    // summed over the 16 lanes that share L & 3), then the last two lane bits
+    halve_exchange_t<T, 24, 32>(v, lane);
+    halve_exchange_t<T, 12, 16>(v, lane);
+    halve_exchange_t<T, 6, 8>(v, lane);
+    halve_exchange_t<T, 3, 4>(v, lane);
 #pragma unroll
-  for (int b = 0; b < NRB; b++) {
-    if (b >= nb) break;
-    cx<T> e = E[b], h = H[b], rr = R[b];
-    e.x = wave_sum(e.x);
-    e.y = wave_sum(e.y);
-    h.x = wave_sum(h.x);
-    h.y = wave_sum(h.y);
-    rr.x = wave_sum(rr.x);
-    rr.y = wave_sum(rr.y);
-    if (lane == 0) {
-      const cx<T> *to = op.tri_out + (size_t)9 * op.nt * b;
-      const cx<T> *p0 = to + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
-      const cx<T> *p1 = to + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
-      e += p0[0] + p1[0];
-      h += p0[1] + p1[1];
-      rr += p0[2] + p1[2];
-      double *yb = y + (size_t)2 * op.N * b;
-      yb[2 * r.row[0]] = e.x;
-      yb[2 * r.row[0] + 1] = e.y;
-      yb[2 * r.row[1]] = h.x;
-      yb[2 * r.row[1] + 1] = h.y;
-      if (r.isR) {
-        yb[2 * r.row[2]] = rr.x;
-        yb[2 * r.row[2] + 1] = rr.y;
-      }
+    for (int t = 0; t < 3; t++) {
+      v[t] += __shfl_xor(v[t], 2, 64);
+      v[t] += __shfl_xor(v[t], 1, 64);
+    }
+    // lane 8 b holds values 6 b .. 6 b + 2, lane 8 b + 4 values 6 b + 3 .. 6 b + 5
+    const int src_lane = 8 * lane;
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+      s6[t] = __shfl(v[t], src_lane, 64);
+      s6[3 + t] = __shfl(v[t], src_lane + 4, 64);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 6 * NRB; q++) v[q] = wave_sum(v[q]);
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+      T sel = v[t];
+#pragma unroll
+      for (int b = 1; b < NRB; b++)
+        if (lane == b) sel = v[6 * b + t];
+      s6[t] = sel;
+    }
+  }
+  if (lane < NRB) {
+    const int b = lane;
+    cx<T> e = {s6[0], s6[1]}, h = {s6[2], s6[3]}, rr = {s6[4], s6[5]};
+    const cx<T> *to = op.tri_out + (size_t)9 * op.nt * b;
+    const cx<T> *p0 = to + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
+    const cx<T> *p1 = to + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
+    e += p0[0] + p1[0];
+    h += p0[1] + p1[1];
+    rr += p0[2] + p1[2];
+    double *yb = y + (size_t)2 * op.N * b;
+    yb[2 * r.row[0]] = e.x;
+    yb[2 * r.row[0] + 1] = e.y;
+    yb[2 * r.row[1]] = h.x;
+    yb[2 * r.row[1] + 1] = h.y;
+    if (r.isR) {
+      yb[2 * r.row[2]] = rr.x;
+      yb[2 * r.row[2] + 1] = rr.y;
     }
   }
 }
@@ -532,15 +582,20 @@ __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, doubl
 int near_rows_max_batch() { return NR_MAXB; }
 
 template <typename T> void launch_near_rows(const DevOperator<T> &op, double *y, hipStream_t s, int nb) {
-  int blocks = (int)(((int64_t)op.ne * 64 + 255) / 256);
-  if (nb == 1)
-    hipLaunchKernelGGL((near_rows_kernel<T, 1>), dim3(blocks), dim3(256), 0, s, op, y, nb);
-  else if (nb == 2)
-    hipLaunchKernelGGL((near_rows_kernel<T, 2>), dim3(blocks), dim3(256), 0, s, op, y, nb);
-  else if (nb <= 4)
-    hipLaunchKernelGGL((near_rows_kernel<T, 4>), dim3(blocks), dim3(256), 0, s, op, y, nb);
-  else
-    hipLaunchKernelGGL((near_rows_kernel<T, NR_MAXB>), dim3(blocks), dim3(256), 0, s, op, y, nb);
+  const int blocks = (int)(((int64_t)op.ne * 64 + 255) / 256);
+#define SCABS_NEAR_ROWS(NB) \
+  hipLaunchKernelGGL((near_rows_kernel<T, NB>), dim3(blocks), dim3(256), 0, s, op, y)
+  switch (nb) {
+    case 1: SCABS_NEAR_ROWS(1); break;
+    case 2: SCABS_NEAR_ROWS(2); break;
+    case 3: SCABS_NEAR_ROWS(3); break;
+    case 4: SCABS_NEAR_ROWS(4); break;
+    case 5: SCABS_NEAR_ROWS(5); break;
+    case 6: SCABS_NEAR_ROWS(6); break;
+    case 7: SCABS_NEAR_ROWS(7); break;
+    default: SCABS_NEAR_ROWS(8); break;
+  }
+#undef SCABS_NEAR_ROWS
 }
 template void launch_near_rows<float>(const DevOperator<float> &, double *, hipStream_t, int);
 template void launch_near_rows<double>(const DevOperator<double> &, double *, hipStream_t, int);
