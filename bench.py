@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--restart", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the untimed single-solve and product-rate runs")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the untimed step with every stage recorded (the roofline kernel is then the "
+                         "largest of the roofline kernels over the timed steps)")
     ap.add_argument("--products-only", type=int, default=0,
                     help="run this many FP32 products and preconditioner applies, then a device copy of known "
                          "size (counter calibration)")
@@ -221,19 +224,24 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # one untimed step with every stage recorded: the per-stage breakdown and
-    # the choice of the roofline kernel (largest total among ROOFLINE_KERNELS)
-    ctx.profile_mask(None)
-    ctx.profile_begin()
-    step()
-    full = ctx.profile_end()
-    stage_avg_us = {k: (v["ms"] / v["count"] * 1e3 if v["count"] else 0.0) for k, v in full.items()}
-    stage_total_ms = {k: v["ms"] for k, v in full.items()}
-    log("stages avg us (profiled step)", stage_avg_us)
-    top = max(ROOFLINE_KERNELS, key=lambda k: full[k]["ms"])
+    full = None
+    if not args.no_breakdown:
+        # one untimed step with every stage recorded: the per-stage breakdown
+        # and the choice of the roofline kernel (largest total among
+        # ROOFLINE_KERNELS)
+        ctx.profile_mask(None)
+        ctx.profile_begin()
+        step()
+        full = ctx.profile_end()
+        log("stages avg us (profiled step)",
+            {k: (v["ms"] / v["count"] * 1e3 if v["count"] else 0.0) for k, v in full.items()})
+        top = max(ROOFLINE_KERNELS, key=lambda k: full[k]["ms"])
+        timed_stages = [top]
+    else:
+        timed_stages = list(ROOFLINE_KERNELS)
     # timed steps: only the roofline kernel's stage records events (the
     # others would add events to every Arnoldi step)
-    ctx.profile_mask([top])
+    ctx.profile_mask(timed_stages)
     torch.cuda.synchronize()
     ctx.profile_begin()
     all_infos, adj_infos = [], []
@@ -247,6 +255,11 @@ def main():
     dt = time.perf_counter() - t1
     prof = ctx.profile_end()
     ctx.profile_mask(None)
+    if full is None:
+        top = max(ROOFLINE_KERNELS, key=lambda k: prof[k]["ms"])
+        full = prof
+    stage_avg_us = {k: (v["ms"] / v["count"] * 1e3 if v["count"] else 0.0) for k, v in full.items()}
+    stage_total_ms = {k: v["ms"] for k, v in full.items()}
     nprod = sum(i["matvecs32"] + i["matvecs64"] for i in all_infos + adj_infos)
     ok = all(i["status"] == 0 for i in all_infos + adj_infos)
     log("batched solves", all_infos[:BATCH], "adjoint", adj_infos[0], "gradient", list(dpar),
@@ -321,7 +334,8 @@ def main():
         "stage_total_ms": stage_total_ms,
         "roofline": roofline(prof, top),
         "rooflines": roofs,
-        "rooflines_source": "one untimed step with every stage recorded",
+        "rooflines_source": ("the timed steps (roofline kernels only)" if args.no_breakdown
+                             else "one untimed step with every stage recorded"),
     }
     if not args.no_cpu_baseline:
         try:

@@ -235,7 +235,8 @@ static int twiddle_length(const GridDesc &d) {
 template <typename T>
 static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<double>> &tw_host,
                             const std::vector<int> &tw_off, const std::vector<cx<double> *> &ghat64,
-                            const std::vector<cx<float> *> &ghat32, cx<T> *V4, cx<T> *S4) {
+                            const std::vector<cx<float> *> &ghat32, cx<T> *V4, cx<T> *S4, const cx<T> *V4T,
+                            const cx<T> *S4T) {
   const Geometry &g = c->geo;
   const Layout &L = c->lay;
   const size_t np = (size_t)g.nt * NQ;
@@ -393,6 +394,8 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   op.col = c->col;
   op.V4 = P.V4;
   op.S4 = P.S4;
+  op.V4T = V4T;
+  op.S4T = S4T;
   op.src = P.src;
   op.srcI = nullptr;
   op.tri_out = P.tri_out;
@@ -716,8 +719,14 @@ static int do_build(scabs_ctx *c) {
     }
     HIPCHK(hipStreamSynchronize(s));
     tmp.release();
-    build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, V4, S4);
-    build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, V4f, S4f);
+    // FP32 transposed product: mirrored copies of the near values, read in row order
+    cx<float> *V4fT = c->mem.alloc<cx<float>>(4 * (size_t)c->nnz);
+    cx<float> *S4fT = c->mem.alloc<cx<float>>(4 * (size_t)c->nnz);
+    launch_mirror4(c->nnz, c->tpos, V4f, V4fT, s);
+    launch_mirror4(c->nnz, c->tpos, S4f, S4fT, s);
+    HIPCHK(hipGetLastError());
+    build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, V4, S4, nullptr, nullptr);
+    build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, V4f, S4f, V4fT, S4fT);
   }
   HIPCHK(hipStreamSynchronize(s));
   c->built = true;

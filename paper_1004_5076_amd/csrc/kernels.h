@@ -55,6 +55,9 @@ template <typename T> struct DevOperator {
   const int *col;
   const cx<T> *V4;   // per entry: L_e, K_e, L_i, K_i   (exact - grid)
   const cx<T> *S4;   // per entry: Lrot_e, Krot_e, Lsig_i, Ksig_i (R rows only)
+  // the same values at the mirrored entry: V4T[4 k + j] = V4[4 tpos[k] + j]
+  // (row-ordered reads for the transposed product; null: read through tpos)
+  const cx<T> *V4T, *S4T;
   // work buffers
   cx<T> *src;        // ne * 3: J_e, J_i, M
   // batches of nb > 1 vectors: the same currents per edge for all vectors,
@@ -182,6 +185,8 @@ void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_pt
 
 // ---- transposed product, adjoint gradient --------------------------------------
 template <typename T> void launch_unpack_rows(const DevOperator<T> &op, const double *z, hipStream_t s);
+// dst[4 k + j] = src[4 tpos[k] + j] for k < nnz (mirrored-entry copy)
+void launch_mirror4(int64_t nnz, const int64_t *tpos, const cx<float> *src, cx<float> *dst, hipStream_t s);
 // src4[k]: ADJ_COEF coefficients per sorted point of grid k (work buffer)
 template <typename T>
 void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grids, const std::vector<GatherGrid<T>> &gg,

@@ -426,12 +426,15 @@ near_rows_t_kernel(DevOperator<T> op, const int64_t *__restrict__ tpos, double *
   const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
   cx<T> aJe = czero<T>(), aJi = czero<T>(), aM = czero<T>();
   const int64_t b = op.rowptr[m], e = op.rowptr[m + 1];
+  // mirrored values: row-ordered copies where they exist, else through tpos
+  const bool mirrored = op.V4T != nullptr;
+  const cx<T> *V4 = mirrored ? op.V4T : op.V4, *S4 = mirrored ? op.S4T : op.S4;
   for (int64_t k = b + lane; k < e; k += 64) {
     const int n = op.col[k];
-    const int64_t t = tpos[k];
+    const int64_t t = mirrored ? k : tpos[k];
     const cx<T> zE = op.src[3 * n], zH = op.src[3 * n + 1], z14 = op.src[3 * n + 2];
-    const cx<T> Le = op.V4[4 * t], Ke = op.V4[4 * t + 1], Li = op.V4[4 * t + 2], Ki = op.V4[4 * t + 3];
-    const cx<T> Lr = op.S4[4 * t], Kr = op.S4[4 * t + 1], Ls = op.S4[4 * t + 2], Ks = op.S4[4 * t + 3];
+    const cx<T> Le = V4[4 * t], Ke = V4[4 * t + 1], Li = V4[4 * t + 2], Ki = V4[4 * t + 3];
+    const cx<T> Lr = S4[4 * t], Kr = S4[4 * t + 1], Ls = S4[4 * t + 2], Ks = S4[4 * t + 3];
     aJe -= (Le * zE) * Ze + Ke * zH + (Lr * zH) * Ze;
     aJi += (Li * zE) * Zi + Ki * zH + (Ls * z14) * Zi;
     aM += (Ke + Ki) * zE - (Le * zH) * iZe - (Li * zH) * iZi + Kr * zH + Ks * z14;
@@ -471,6 +474,19 @@ void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y
   hipLaunchKernelGGL(near_rows_t_kernel<T>, dim3(blocks), dim3(256), 0, s, op, tpos, y);
 }
 template void launch_near_rows_t<float>(const DevOperator<float> &, const int64_t *, double *, hipStream_t);
+
+__global__ void mirror4_kernel(int64_t nnz, const int64_t *__restrict__ tpos, const cx<float> *__restrict__ src,
+                               cx<float> *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * nnz) return;
+  const int64_t k = i >> 2;
+  dst[i] = src[4 * tpos[k] + (i & 3)];
+}
+
+void launch_mirror4(int64_t nnz, const int64_t *tpos, const cx<float> *src, cx<float> *dst, hipStream_t s) {
+  if (nnz == 0) return;
+  hipLaunchKernelGGL(mirror4_kernel, dim3((unsigned)((4 * nnz + 255) / 256)), dim3(256), 0, s, nnz, tpos, src, dst);
+}
 template void launch_near_rows_t<double>(const DevOperator<double> &, const int64_t *, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
