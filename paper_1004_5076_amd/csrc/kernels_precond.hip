@@ -490,14 +490,26 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
     const uint32_t *Rc = R + i;
     const cx<float> *xc = xe + e0 * NB;
     int j = jb;
+    // the next block's eight coefficient loads are issued before this
+    // block's products
+    uint32_t cur[8];
+    if (j + 8 <= je) {
+#pragma unroll
+      for (int u = 0; u < 8; u++) cur[u] = Rc[(int64_t)(j + u) * ncp];
+    }
     for (; j + 8 <= je; j += 8) {
-      cx<float> rv[8];
+      uint32_t nxt[8];
+      const int jn = j + 16 <= je ? j + 8 : j;   // without a next block, reload this one (in bounds)
 #pragma unroll
-      for (int u = 0; u < 8; u++) rv[u] = unpack_h2(Rc[(int64_t)(j + u) * ncp]);
+      for (int u = 0; u < 8; u++) nxt[u] = Rc[(int64_t)(jn + u) * ncp];
 #pragma unroll
-      for (int u = 0; u < 8; u++)
+      for (int u = 0; u < 8; u++) {
+        const cx<float> rv = unpack_h2(cur[u]);
 #pragma unroll
-        for (int b = 0; b < NB; b++) cmac(acc[b], rv[u], xc[(j + u) * NB + b]);
+        for (int b = 0; b < NB; b++) cmac(acc[b], rv, xc[(j + u) * NB + b]);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++) cur[u] = nxt[u];
     }
     for (; j < je; j++) {
       const cx<float> rv = unpack_h2(Rc[(int64_t)j * ncp]);
