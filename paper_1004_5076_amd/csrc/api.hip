@@ -175,6 +175,11 @@ struct scabs_ctx {
   std::vector<ProfRec> prof_recs;
   double prof_bytes[SCABS_NSTAGES] = {};   // per stage, last finished session
   double *nrm = nullptr, *nrm_part = nullptr, *npart = nullptr;
+  // nrm (KR_NRM entries) followed by hcol in one device block, mirrored in
+  // pinned host memory, so each Arnoldi step reads both back in one copy
+  cx<double> *hblock = nullptr;
+  cx<double> *hpin = nullptr;
+  size_t hpin_entries = 0;
   int *flag = nullptr;
 };
 
@@ -906,6 +911,9 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
 // per-system orthogonalisation, one host synchronisation per step for all of
 // them (two when a system needs the second pass).
 // ---------------------------------------------------------------------------
+// complex entries in front of the Hessenberg columns that hold the norms
+// (2 nb + 4 doubles for nb <= KR_MAX_SYSTEMS)
+constexpr size_t KR_NRM = KR_MAX_SYSTEMS + 2;
 static void ensure_work(scabs_ctx *c, int restart, int nb) {
   int64_t N = c->lay.N;
   if (c->work_restart >= restart && c->work_N == N && c->work_nb >= nb) return;
@@ -915,10 +923,16 @@ static void ensure_work(scabs_ctx *c, int restart, int nb) {
   c->d = c->work.alloc<cx<double>>(N * nb);
   c->z = c->work.alloc<cx<double>>(N * nb);
   c->t = c->work.alloc<cx<double>>(N * nb);
-  c->hcol = c->work.alloc<cx<double>>(2 * (size_t)(restart + 2) * nb);
+  const size_t hentries = KR_NRM + 2 * (size_t)(restart + 2) * nb;
+  c->hblock = c->work.alloc<cx<double>>(hentries);
+  c->nrm = reinterpret_cast<double *>(c->hblock);
+  c->hcol = c->hblock + KR_NRM;
+  if (c->hpin) HIPCHK(hipHostFree(c->hpin));
+  c->hpin = nullptr;
+  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(cx<double>) * hentries, hipHostMallocDefault));
+  c->hpin_entries = hentries;
   c->part = c->work.alloc<cx<double>>(std::max((size_t)256 * (restart + 2), kr_ortho_part_entries(restart + 1, nb)));
   c->npart = c->work.alloc<double>(kr_ortho_npart_entries(N, nb));
-  c->nrm = c->work.alloc<double>(2 * nb + 4);
   c->nrm_part = c->work.alloc<double>(1024);
   c->flag = c->work.alloc<int>(1);
   c->work_restart = restart;
@@ -1012,14 +1026,23 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     }
     std::vector<int> run = act;
     int j = 0;
-    while (j < m && !run.empty()) {
-      const cx<double> *vj = operator_input(c, V + (size_t)j * ldv, ldv);
+    // w = A M v_j for every vector of the batch (the batched stages take all
+    // nb vectors; only the orthogonalisation is restricted to running systems)
+    auto enqueue_product = [&](int jj) {
+      const cx<double> *vj = operator_input(c, V + (size_t)jj * ldv, ldv);
       if (c->has_pc) {
         apply_precond_n(c, vj, c->z, nb, trans, prec);
         matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
       } else {
         matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
       }
+    };
+    // the product of step j is already in the stream (enqueued during step
+    // j - 1, before the host's Givens update; unused if the cycle ends there)
+    bool pending = false;
+    while (j < m && !run.empty()) {
+      if (!pending) enqueue_product(j);
+      pending = false;
       nmv += (int)run.size();
       // classical Gram-Schmidt, repeated only where it lost too much of w
       // (Daniel-Gragg-Kaufman-Stewart test ||w1|| < ||w|| / sqrt(2)); one
@@ -1036,9 +1059,15 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         kr_ortho_pass(V, ldv, j + 1, c->w, N, to_run(run), 1, c->part, c->npart, c->hcol, hstride, 0, c->nrm + nb,
                       c->nrm, s);
       }
-      HIPCHK(hipMemcpyAsync(hb.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
+      // v_{j+1} = w / ||w|| before the read-back (redone below for systems
+      // that take a second pass)
+      kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(run), s);
+      // norms and Hessenberg columns in one copy to pinned memory
+      HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb.size()), hipMemcpyDeviceToHost,
+                            s));
       HIPCHK(hipStreamSynchronize(s));
+      std::copy(c->hpin + KR_NRM, c->hpin + KR_NRM + hb.size(), hb.begin());
+      std::copy((const double *)c->hpin, (const double *)c->hpin + 2 * nb, hn.begin());
       std::vector<int> reo;
       for (int b : run) {
         reo2[b] = 0;
@@ -1052,14 +1081,22 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         }
         for (int b : reo) reo2[b] = 1;
         std::vector<cx<double>> hb2(hb.size());
-        HIPCHK(hipMemcpyAsync(hb2.data(), c->hcol, sizeof(cx<double>) * hb.size(), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(hn.data(), c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb.size()),
+                              hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        std::copy(c->hpin + KR_NRM, c->hpin + KR_NRM + hb.size(), hb2.begin());
+        std::copy((const double *)c->hpin, (const double *)c->hpin + nb, hn.begin());
         for (int b : reo)
           std::copy(hb2.begin() + 2 * (size_t)(m + 2) * b + (m + 2), hb2.begin() + 2 * (size_t)(m + 2) * (b + 1),
                     hb.begin() + 2 * (size_t)(m + 2) * b + (m + 2));
+        kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(reo), s);
       }
-      kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(run), s);
+      // the next step's product goes into the stream now, so the GPU works
+      // while the host updates the rotations
+      if (j + 1 < m) {
+        enqueue_product(j + 1);
+        pending = true;
+      }
       std::vector<int> next;
       for (int b : run) {
         const cx<double> *h1 = hb.data() + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
@@ -1613,6 +1650,7 @@ void scabs_destroy(scabs_ctx *c) {
   c->workV64.release();
   c->workV32.release();
   c->mem.release();
+  if (c->hpin) hipHostFree(c->hpin);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
