@@ -508,8 +508,13 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   int *status = tmp.alloc<int>(1);
   HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
   c->pc_Rt = c->mem.alloc<uint32_t>((size_t)cl.r_off[cl.nc]);
+  HIPCHK(hipMemsetAsync(c->pc_Rt, 0, sizeof(uint32_t) * (size_t)cl.r_off[cl.nc], s));   // padding stays zero
   c->pc_Rs = c->mem.alloc<float>((size_t)cl.ext_ptr[cl.nc]);
-  c->pc_xe = c->mem.alloc<cx<float>>((size_t)cl.ext_ptr[cl.nc] * precond_apply32_max_batch());
+  // gathered inputs of the batched apply, with a zeroed tail for the padding
+  // columns of the last cluster
+  const size_t xe_n = ((size_t)cl.ext_ptr[cl.nc] + RT_CB) * precond_apply32_max_batch();
+  c->pc_xe = c->mem.alloc<cx<float>>(xe_n);
+  HIPCHK(hipMemsetAsync(c->pc_xe, 0, sizeof(cx<float>) * xe_n, s));
   p.n_ext = cl.ext_ptr[cl.nc];
   int max_ext = 0;
   for (int k = 0; k < cl.nc; k++) max_ext = std::max(max_ext, (int)(cl.ext_ptr[k + 1] - cl.ext_ptr[k]));

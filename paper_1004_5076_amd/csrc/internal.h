@@ -61,6 +61,16 @@ struct NearList {
 // Column stride of a cluster's stored core rows: a multiple of 16 FP32
 // complex values (128 bytes), so every column segment starts on a cache line.
 __host__ __device__ inline int64_t rt_stride(int64_t nc) { return (nc + 15) / 16 * 16; }
+// Stored Schwarz rows of a cluster (nc core rows, ne ext columns): the columns
+// in blocks of RT_CB, each block row-major (RT_CB consecutive entries per core
+// row), rows padded to ncp = rt_stride(nc), columns to rt_cols(ne) (padding
+// zero); entry (i, j) at rt_index(i, j, ncp).  A wave reading RT_CB columns of
+// 64 rows reads one contiguous 2 KB run.
+constexpr int RT_CB = 8;
+__host__ __device__ inline int64_t rt_cols(int64_t ne) { return (ne + RT_CB - 1) / RT_CB * RT_CB; }
+__host__ __device__ inline int64_t rt_index(int64_t i, int64_t j, int64_t ncp) {
+  return (j / RT_CB) * (ncp * RT_CB) + i * RT_CB + (j % RT_CB);
+}
 
 // Overlapping box clusters of edges (restricted additive Schwarz on the
 // near-field matrix): core = edges whose midpoint lies in a cubic cell,

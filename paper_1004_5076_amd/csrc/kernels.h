@@ -150,7 +150,7 @@ struct PrecondArgs {
 void launch_exact_assemble(int64_t nnz, const int64_t *cptr, const int *cpair, const uint8_t *cij,
                            const cx<double> *blocks, cx<double> *X8, hipStream_t s);
 // Stored Schwarz rows: per cluster the core rows x ext columns of the block
-// inverse, column-major (column stride rt_stride(nc)), each complex entry as two
+// inverse in 8-column row-major blocks (rt_index), each complex entry as two
 // FP16 halves (real in the low 16 bits) divided by its column's scale (the
 // largest |re|, |im| of the column, FP32, one per ext entry).
 struct PcStore {

@@ -530,17 +530,20 @@ precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__
   if (nj <= 0) return;
   const int64_t ncp = rt_stride(ncore);
   const cx<double> *xcc = xc + core_ptr[c];
-  // columns past the last one repeat it (read, never written)
-  const uint32_t *Rcol[PT_WCOLS];
-#pragma unroll
-  for (int u = 0; u < PT_WCOLS; u++) Rcol[u] = pc.R + r_off[c] + (int64_t)(jw + min(u, nj - 1)) * ncp;
+  // the wave's 8 columns are one stored block (jw is a multiple of 8): each
+  // lane reads its row's 8 coefficients, 32 contiguous bytes (padding columns
+  // past the last hold zeros and are never written)
+  static_assert(PT_WCOLS == RT_CB, "one stored column block per wave");
+  const uint4 *Rb = reinterpret_cast<const uint4 *>(pc.R + r_off[c] + (int64_t)(jw / RT_CB) * (ncp * RT_CB));
   double v[2 * PT_WCOLS];
 #pragma unroll
   for (int k = 0; k < 2 * PT_WCOLS; k++) v[k] = 0.0;
   for (int i = lane; i < ncore; i += 64) {
+    const uint4 c0 = Rb[2 * i], c1 = Rb[2 * i + 1];
+    const uint32_t wd[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
     cx<float> rv[PT_WCOLS];
 #pragma unroll
-    for (int u = 0; u < PT_WCOLS; u++) rv[u] = unpack_h2(Rcol[u][i]);
+    for (int u = 0; u < PT_WCOLS; u++) rv[u] = unpack_h2(wd[u]);
     const cx<double> xv = xcc[i];
 #pragma unroll
     for (int u = 0; u < PT_WCOLS; u++) {

@@ -305,8 +305,8 @@ std::vector<int> gj_tile_table(const std::vector<int64_t> &ext_ptr, int &npanels
 }
 size_t gj_scratch_entries(const std::vector<int64_t> &ext_ptr) { return (size_t)GJ_B * ext_ptr.back(); }
 
-// Stored rows: for ext column j of cluster c, Rt[j][i] = inverse[core_pos[i]][j]
-// over the core rows i (column-major, column stride rt_stride(nc)), as FP16
+// Stored rows: for ext column j of cluster c, entry (i, j) = inverse[core_pos[i]][j]
+// over the core rows i (8-column row-major blocks, rt_index), as FP16
 // halves divided by the column's scale Rs = max |re|, |im| (1 for a zero
 // column).  One wave per column: the maximum, then the scaled entries.
 __global__ void __launch_bounds__(256)
@@ -334,10 +334,11 @@ extract_kernel(const cx<float> *Ablocks, const int64_t *a_off, const int64_t *ex
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   const float sc = m > 0 ? m : 1.0f, inv = 1.0f / sc;
-  uint32_t *R = Rt + r_off[c] + (int64_t)j * rt_stride(nc);
+  uint32_t *R = Rt + r_off[c];
+  const int64_t ncp = rt_stride(nc);
   for (int i = lane; i < nc; i += 64) {
     const cx<float> v = A[(size_t)cp[i] * ne + j];
-    R[i] = pack_h2(v.x * inv, v.y * inv);
+    R[rt_index(i, j, ncp)] = pack_h2(v.x * inv, v.y * inv);
   }
   if (lane == 0) Rs[col] = sc;
 }
@@ -388,31 +389,29 @@ precond_apply_kernel(const int *__restrict__ items, const int64_t *__restrict__ 
   const int i = i0 + il;
   // four independent partial sums keep several loads in flight
   double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
+  static_assert(PA_CW % RT_CB == 0, "passes start on a stored column block");
   for (int cb = 0; cb < ne; cb += PA_CW) {
     const int cw = min(PA_CW, ne - cb);
+    const int cwp = (int)rt_cols(cw);
     __syncthreads();   // the previous pass is done with xs
-    // the column scales fold into the staged inputs
-    for (int jj = threadIdx.x; jj < cw; jj += blockDim.x)
-      xs[jj] = x[ext_slot[e0 + cb + jj]] * (double)pc.scale[e0 + cb + jj];
+    // the column scales fold into the staged inputs; padding columns get 0
+    for (int jj = threadIdx.x; jj < cwp; jj += blockDim.x)
+      xs[jj] = jj < cw ? x[ext_slot[e0 + cb + jj]] * (double)pc.scale[e0 + cb + jj] : cx<double>{0.0, 0.0};
     __syncthreads();
-    const int jb = (cw * q) / PA_Q, je = (cw * (q + 1)) / PA_Q;
+    // this quarter's 8-column blocks; each lane reads its row's 8 coefficients
+    const int nbk = cwp / RT_CB, kb = (nbk * q) / PA_Q, ke = (nbk * (q + 1)) / PA_Q;
     if (i < nc) {
-      const uint32_t *Rc = R + (int64_t)cb * ncp + i;
-      int j = jb;
-      for (; j + 4 <= je; j += 4) {
+      for (int k = kb; k < ke; k++) {
+        const uint4 *Rb = reinterpret_cast<const uint4 *>(R + rt_index(i, cb + k * RT_CB, ncp));
+        const uint4 c0 = Rb[0], c1 = Rb[1];
+        const uint32_t wd[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const cx<float> rv = unpack_h2(Rc[(j + u) * ncp]);
-          const cx<double> xv = xs[j + u];
-          pr[u] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-          pi[u] += (double)rv.x * xv.y + (double)rv.y * xv.x;
+        for (int u = 0; u < 8; u++) {
+          const cx<float> rv = unpack_h2(wd[u]);
+          const cx<double> xv = xs[k * RT_CB + u];
+          pr[u & 3] += (double)rv.x * xv.x - (double)rv.y * xv.y;
+          pi[u & 3] += (double)rv.x * xv.y + (double)rv.y * xv.x;
         }
-      }
-      for (; j < je; j++) {
-        const cx<float> rv = unpack_h2(Rc[j * ncp]);
-        const cx<double> xv = xs[j];
-        pr[0] += (double)rv.x * xv.x - (double)rv.y * xv.y;
-        pi[0] += (double)rv.x * xv.y + (double)rv.y * xv.x;
       }
     }
   }
@@ -485,36 +484,31 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
   cx<float> acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; b++) acc[b] = czero<float>();
-  const int jb = (int)(((int64_t)ne * q) / PA32_Q), je = (int)(((int64_t)ne * (q + 1)) / PA32_Q);
-  if (i < nc) {
-    const uint32_t *Rc = R + i;
+  // the wave's share of the cluster's 8-column blocks; per block each lane
+  // reads its row's 8 coefficients (32 contiguous bytes; the wave: 2 KB).
+  // Padding columns hold zero coefficients and their inputs are finite (the
+  // next cluster's, or the zeroed tail of the gathered copy): they add nothing.
+  const int nblk = (int)(rt_cols(ne) / RT_CB);
+  const int kb = (nblk * q) / PA32_Q, ke = (nblk * (q + 1)) / PA32_Q;
+  if (i < nc && kb < ke) {
+    const int64_t bstride = ncp * RT_CB / 4;   // uint4 per block
+    const uint4 *Rb = reinterpret_cast<const uint4 *>(R + (int64_t)i * RT_CB);
     const cx<float> *xc = xe + e0 * NB;
-    int j = jb;
-    // the next block's eight coefficient loads are issued before this
-    // block's products
-    uint32_t cur[8];
-    if (j + 8 <= je) {
-#pragma unroll
-      for (int u = 0; u < 8; u++) cur[u] = Rc[(int64_t)(j + u) * ncp];
-    }
-    for (; j + 8 <= je; j += 8) {
-      uint32_t nxt[8];
-      const int jn = j + 16 <= je ? j + 8 : j;   // without a next block, reload this one (in bounds)
-#pragma unroll
-      for (int u = 0; u < 8; u++) nxt[u] = Rc[(int64_t)(jn + u) * ncp];
+    // the next block's loads are issued before this block's products
+    uint4 c0 = Rb[kb * bstride], c1 = Rb[kb * bstride + 1];
+    for (int k = kb; k < ke; k++) {
+      const int kn = k + 1 < ke ? k + 1 : k;
+      const uint4 n0 = Rb[kn * bstride], n1 = Rb[kn * bstride + 1];
+      const uint32_t wd[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+      const cx<float> *xk = xc + (int64_t)k * RT_CB * NB;
 #pragma unroll
       for (int u = 0; u < 8; u++) {
-        const cx<float> rv = unpack_h2(cur[u]);
+        const cx<float> rv = unpack_h2(wd[u]);
 #pragma unroll
-        for (int b = 0; b < NB; b++) cmac(acc[b], rv, xc[(j + u) * NB + b]);
+        for (int b = 0; b < NB; b++) cmac(acc[b], rv, xk[u * NB + b]);
       }
-#pragma unroll
-      for (int u = 0; u < 8; u++) cur[u] = nxt[u];
-    }
-    for (; j < je; j++) {
-      const cx<float> rv = unpack_h2(Rc[(int64_t)j * ncp]);
-#pragma unroll
-      for (int b = 0; b < NB; b++) cmac(acc[b], rv, xc[j * NB + b]);
+      c0 = n0;
+      c1 = n1;
     }
   }
 #pragma unroll

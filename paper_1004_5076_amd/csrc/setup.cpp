@@ -504,7 +504,7 @@ std::string build_clusters(const Geometry &g, const Layout &L, double cell, doub
     cl.ext_ptr[c + 1] = cl.ext_ptr[c] + ne_c;
     cl.core_ptr[c + 1] = cl.core_ptr[c] + nc_c;
     cl.a_off[c + 1] = cl.a_off[c] + (int64_t)(ne_c * ne_c);
-    cl.r_off[c + 1] = cl.r_off[c] + (int64_t)ne_c * rt_stride((int64_t)nc_c);
+    cl.r_off[c + 1] = cl.r_off[c] + rt_cols((int64_t)ne_c) * rt_stride((int64_t)nc_c);
   }
   if (maxext > (size_t)PC_MAX_EXT || maxcore > (size_t)PC_MAX_CORE) {
     *too_large = true;
