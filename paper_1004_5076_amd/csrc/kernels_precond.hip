@@ -366,8 +366,9 @@ void launch_precond_build(const PrecondArgs &p, const std::vector<int64_t> &ext_
 
 // y[core] = R_c x[ext] for every cluster; each unknown is in exactly one core.
 // One work-group per item (cluster c, PA_ROWS core rows from row0): the ext
-// columns split in PA_Q contiguous parts (coalesced reads of the
-// column-major block), partial sums reduced in LDS in a fixed order.
+// columns are staged in LDS per pass and their 8-column stored blocks split
+// in PA_Q contiguous parts (each lane reads its row's 8 coefficients of a
+// block at once), partial sums reduced in LDS in a fixed order.
 constexpr int PA_ROWS = 64;
 constexpr int PA_Q = 4;
 constexpr int PA_THREADS = PA_ROWS * PA_Q;
@@ -439,10 +440,13 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
 // per-vector branches).  The inputs are first gathered once into an
 // ext-ordered FP32 copy with the column scale folded in (NB values per
 // column, contiguous).  Work-group = PA_ROWS core rows of one cluster, its
-// PA32_Q waves split the cluster's columns; within a wave every lane reads
-// the same column's NB inputs, so these are wave-uniform (scalar) loads fed
+// PA32_Q waves split the cluster's 8-column stored blocks; per block each lane
+// reads its row's 8 coefficients (32 contiguous bytes), every lane needs the
+// same columns' NB inputs, so these are wave-uniform (scalar) loads fed
 // straight into the FMAs, and each coefficient is read once for all vectors;
-// FP32 sums, combined across the waves in LDS at the end.  Inner solves stop
+// FP32 sums, combined across the waves in LDS at the end.  (A matrix-core
+// form, 16x16x4 FP32 steps over (column, re/im) x (vector, re/im), measured
+// slower: the product is bound by the coefficient stream, not by FMAs.)  Inner solves stop
 // at relative residuals of 1e-5 or more and an FP64 refinement follows, so
 // the rounding of x and of the sums only perturbs the preconditioner, not
 // the solution.
