@@ -104,6 +104,8 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
 // three x partials of a node are added at the end.  No atomics; the
 // summation order is fixed.
 template <typename T> struct CellChunk { static constexpr int value = 96; };
+// phase-B layout with one node per thread triple: 21 nodes (63 lanes) per wave
+constexpr int GB_NODES_PER_WAVE = 21;
 template <> struct CellChunk<double> { static constexpr int value = 48; };
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
@@ -223,9 +225,18 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MAXI; m++) {
-      const int it = threadIdx.x + m * blockDim.x;
-      if (it >= 3 * plane) continue;
-      const int oxi = fdiv(it, dpl), nd = it - oxi * plane;
+      int it = threadIdx.x + m * blockDim.x, oxi, nd;
+      if constexpr (MAXI == 1) {
+        // 21 nodes per wave, their three x offsets in neighbouring lanes
+        const int ln = threadIdx.x & 63;
+        oxi = ln % 3;
+        nd = (threadIdx.x >> 6) * GB_NODES_PER_WAVE + ln / 3;
+        if (ln >= 3 * GB_NODES_PER_WAVE || nd >= plane) continue;
+      } else {
+        if (it >= 3 * plane) continue;
+        oxi = fdiv(it, dpl);
+        nd = it - oxi * plane;
+      }
       const int cxp = x - (oxi - 1);   // the cells' plane: node offset oxi - 1 from their anchors
       if (cxp < xl || cxp > xh) continue;
       const int y = fdiv(nd, dn2), z = nd - y * n2;
@@ -249,8 +260,22 @@ __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<
     }
     __syncthreads();
   }
-  cx<T> *s_red = &s_q[0][0];   // 3 * plane <= 8 * SQ
   const size_t G = (size_t)g.ncell;
+  if constexpr (MAXI == 1) {
+    // the three x-offset sums of a node meet across neighbouring lanes
+    const int ln = threadIdx.x & 63;
+    const int nd = (threadIdx.x >> 6) * GB_NODES_PER_WAVE + ln / 3;
+    const bool own = ln < 3 * GB_NODES_PER_WAVE && ln % 3 == 0 && nd < plane;
+#pragma unroll
+    for (int f = 0; f < 8; f++) {
+      const cx<T> v = acc[0][f];
+      const cx<T> v1 = {__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64)};
+      const cx<T> v2 = {__shfl_down(v.x, 2, 64), __shfl_down(v.y, 2, 64)};
+      if (own) phys[f * G + (size_t)x * plane + nd] = v + v1 + v2;
+    }
+    return;
+  }
+  cx<T> *s_red = &s_q[0][0];   // 3 * plane <= 8 * SQ
   for (int f = 0; f < 8; f++) {
 #pragma unroll
     for (int m = 0; m < MAXI; m++) {
@@ -278,8 +303,19 @@ void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &gri
     const GatherGrid<T> &g = gg[k];
     const int plane = grids[k].n[1] * grids[k].n[2];
     const int items = 3 * plane;
-    const int threads = std::min(1024, (items + 63) / 64 * 64);
-    const int maxi = (items + threads - 1) / threads;
+    int threads = std::min(1024, (items + 63) / 64 * 64);
+    int maxi = (items + threads - 1) / threads;
+    // one pass over the nodes: waves of 21 nodes (their 3 x offsets in lane
+    // triples), when they fit one work-group
+    const int triple_threads = (plane + GB_NODES_PER_WAVE - 1) / GB_NODES_PER_WAVE * 64;
+    if (maxi == 1) {
+      if (triple_threads <= 1024) {
+        threads = std::max(threads, triple_threads);
+      } else {
+        threads = 1024;
+        maxi = 2;
+      }
+    }
     const size_t lds = sizeof(int) * (size_t)items;   // cell -> slot map of three planes
     const dim3 grid(grids[k].n[0], nb);
     if (maxi == 1)
