@@ -66,43 +66,49 @@ template void launch_unpack<double>(const DevOperator<double> &, const double *,
 template <typename T>
 __global__ void __launch_bounds__(256)
 point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__restrict__ tris,
-                     const cx<T> *__restrict__ esrc, GatherGrid<T> g, int interior, int ne) {
+                     const cx<T> *__restrict__ esrc, const cx<T> *__restrict__ esrcI, GatherGrid<T> g, int interior,
+                     int ne, int nb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.np) return;
-  esrc += (size_t)blockIdx.y * 3 * ne;   // batch index blockIdx.y
+  // the point's records once for all vectors of the batch; batch currents
+  // edge-major ([e][b][3]) when there are several
   const PointRec<T> P = pts[g.perm[i]];
   const TriRec<T> tr = tris[P.tri];
-  cx<T> s[8];
+  for (int b = 0; b < nb; b++) {
+    cx<T> s[8];
 #pragma unroll
-  for (int f = 0; f < 8; f++) s[f] = czero<T>();
+    for (int f = 0; f < 8; f++) s[f] = czero<T>();
 #pragma unroll
-  for (int j = 0; j < 3; j++) {
-    const int e = tr.edge[j];
-    const cx<T> J = interior ? esrc[3 * e + 1] : esrc[3 * e];
-    const cx<T> M = interior ? -esrc[3 * e + 2] : esrc[3 * e + 2];
+    for (int j = 0; j < 3; j++) {
+      const int e = tr.edge[j];
+      const cx<T> *c = nb > 1 ? esrcI + ((size_t)e * nb + b) * 3 : esrc + (size_t)3 * e;
+      const cx<T> J = interior ? c[1] : c[0];
+      const cx<T> M = interior ? -c[2] : c[2];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-      axpy(s[a], P.f[3 * j + a], J);
-      axpy(s[4 + a], P.f[3 * j + a], M);
+      for (int a = 0; a < 3; a++) {
+        axpy(s[a], P.f[3 * j + a], J);
+        axpy(s[4 + a], P.f[3 * j + a], M);
+      }
+      axpy(s[3], tr.div[j], J);
+      axpy(s[7], tr.div[j], M);
     }
-    axpy(s[3], tr.div[j], J);
-    axpy(s[7], tr.div[j], M);
-  }
-  cx<T> *o = g.src + (size_t)8 * g.np * blockIdx.y + (size_t)8 * i;
+    cx<T> *o = g.src + (size_t)8 * g.np * b + (size_t)8 * i;
 #pragma unroll
-  for (int f = 0; f < 8; f++) o[f] = s[f] * P.w;
+    for (int f = 0; f < 8; f++) o[f] = s[f] * P.w;
+  }
 }
 
 // One work-group per x plane of a grid (and vector of the batch), in chunks
 // of the cells that hold points among the planes x-1..x+1 (listed per plane
-// at setup).  Phase A, work item (cell, node offset (oy, oz)): the cell's
-// points, in sorted order, summed into the contribution to the node of plane x
-// at that offset (the x offset is fixed by the cell's plane); nine lanes share
-// a cell and so the same loop length, and empty cells cost nothing.  Phase B,
-// work item (node, x offset): the contributions of the 9 cells around the
-// node in that offset's plane, read through a cell -> slot map in LDS.  The
-// three x partials of a node are added at the end.  No atomics; the
-// summation order is fixed.
+// at setup).  Phase A, work item (cell, y offset oy) (FP32; (cell, (oy, oz))
+// otherwise): the cell's points, in sorted order, summed into the
+// contributions to the nodes of plane x at offsets (oy, -1..1) (the x offset
+// is fixed by the cell's plane); the lanes of a cell share its loop length,
+// and empty cells cost nothing.  Phase B, work item (node, x offset): the
+// contributions of the 9 cells around the node in that offset's plane, read
+// through a cell -> slot map in LDS; the three x partials of a node sit in
+// neighbouring lanes and are added by shuffles.  No atomics; the summation
+// order is fixed.
 template <typename T> struct CellChunk { static constexpr int value = 96; };
 // phase-B layout with one node per thread triple: 21 nodes (63 lanes) per wave
 constexpr int GB_NODES_PER_WAVE = 21;
@@ -295,8 +301,8 @@ void launch_project(const DevOperator<T> &op, const std::vector<DevGrid<T>> &gri
   if (part < 0)   // -1: sources and gathers; -2: sources only
     for (size_t k = 0; k < grids.size(); k++) {
       const GatherGrid<T> &g = gg[k];
-      hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256, nb), dim3(256), 0, s, op.pts, op.tris,
-                         op.src, g, grids[k].which >= 0 ? 1 : 0, op.ne);
+      hipLaunchKernelGGL(point_sources_kernel<T>, dim3((g.np + 255) / 256), dim3(256), 0, s, op.pts, op.tris,
+                         op.src, op.srcI, g, grids[k].which >= 0 ? 1 : 0, op.ne, nb);
     }
   for (size_t k = 0; k < grids.size(); k++) {
     if (part == -2 || (part >= 0 && (int)k != part)) continue;
