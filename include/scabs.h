@@ -222,7 +222,8 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
 /* Stage timing (tracing): between scabs_profile_begin and scabs_profile_end
  * every stage of every product and solve is bracketed by HIP events on the
  * context stream.  scabs_profile_end synchronises the stream and returns, per
- * stage, the summed duration in milliseconds and the number of launches
+ * stage, the summed duration in milliseconds and the number of kernel launches
+ * (one per record, or the launch count of a record that spans several)
  * (arrays of SCABS_NSTAGES entries; either may be NULL). */
 #define SCABS_STAGE_UNPACK 0     /* unknowns -> per-edge currents */
 #define SCABS_STAGE_PROJECT 1    /* sources -> grid */
@@ -234,11 +235,13 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
 #define SCABS_STAGE_ORTHO 11     /* Gram-Schmidt, norms (FP64) */
 #define SCABS_STAGE_PRECOND_T 12 /* transposed preconditioner application */
 #define SCABS_STAGE_XLINE32 13   /* x-line transforms and kernel product of the FP32
-                                    convolution, one record per grid (inside stage
-                                    SCABS_STAGE_FFT + SCABS_STAGE_FP32_OFFSET) */
-#define SCABS_STAGE_GATHER32 14  /* lattice gather of the FP32 projection, one record
-                                    per grid (inside stage SCABS_STAGE_PROJECT +
+                                    convolution: one record per product over the
+                                    grids' back-to-back launches, counted as one
+                                    launch per grid (inside stage SCABS_STAGE_FFT +
                                     SCABS_STAGE_FP32_OFFSET) */
+#define SCABS_STAGE_GATHER32 14  /* lattice gather of the FP32 projection, recorded
+                                    as SCABS_STAGE_XLINE32 (inside stage
+                                    SCABS_STAGE_PROJECT + SCABS_STAGE_FP32_OFFSET) */
 #define SCABS_STAGE_PCGATHER32 15 /* FP32 inner solves: the inputs of the Schwarz
                                      blocks gathered once per application into an
                                      ext-ordered FP32 copy (before each

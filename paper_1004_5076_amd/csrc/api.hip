@@ -171,6 +171,7 @@ struct scabs_ctx {
     int stage;
     hipEvent_t e0, e1;
     double bytes;   // algorithmic HBM bytes of the bracketed work (0: not defined)
+    int launches;   // kernel launches of the stage inside the record
   };
   std::vector<ProfRec> prof_recs;
   double prof_bytes[SCABS_NSTAGES] = {};   // per stage, last finished session
@@ -180,6 +181,7 @@ struct scabs_ctx {
   cx<double> *hblock = nullptr;
   cx<double> *hpin = nullptr;
   size_t hpin_entries = 0;
+  hipEvent_t ev_read = nullptr;   // end of a step's read-back (no timing)
   int *flag = nullptr;
 };
 
@@ -188,8 +190,9 @@ struct StageTimer {
   scabs_ctx *c;
   int stage;
   double bytes;
+  int launches;
   hipEvent_t e0 = nullptr;
-  StageTimer(scabs_ctx *cc, int st, double b = 0);
+  StageTimer(scabs_ctx *cc, int st, double b = 0, int n = 1);
   ~StageTimer();
 };
 
@@ -201,7 +204,7 @@ static hipEvent_t next_event(scabs_ctx *c) {
   }
   return c->ev_pool[c->ev_used++];
 }
-StageTimer::StageTimer(scabs_ctx *cc, int st, double b) : c(cc), stage(st), bytes(b) {
+StageTimer::StageTimer(scabs_ctx *cc, int st, double b, int n) : c(cc), stage(st), bytes(b), launches(n) {
   if (c->prof_on && ((c->prof_mask >> st) & 1u) && (e0 = next_event(c))) hipEventRecord(e0, c->stream);
 }
 StageTimer::~StageTimer() {
@@ -209,7 +212,7 @@ StageTimer::~StageTimer() {
   hipEvent_t e1 = next_event(c);
   if (!e1) return;
   hipEventRecord(e1, c->stream);
-  c->prof_recs.push_back({stage, e0, e1, bytes});
+  c->prof_recs.push_back({stage, e0, e1, bytes, launches});
 }
 
 static int fail(scabs_ctx *c, int code, const std::string &m) {
@@ -781,14 +784,15 @@ template <typename T> static void conv_timed(scabs_ctx *c, PrecState<T> &P, int 
   const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
   StageTimer t(c, SCABS_STAGE_FFT + off);
   for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb, CONV_PLANES_FWD);
-  for (const DevGrid<T> &g : P.grids) {
-    if (sizeof(T) == sizeof(float)) {
-      const double bytes = 2.0 * sizeof(cx<T>) * g.n[0] * (8.0 * nb * g.N[1] * g.N[2]);
-      StageTimer tx(c, SCABS_STAGE_XLINE32, bytes);
-      launch_conv(g, s, nb, CONV_XLINES);
-    } else {
-      launch_conv(g, s, nb, CONV_XLINES);
-    }
+  if (sizeof(T) == sizeof(float)) {
+    // one record over the grids' back-to-back launches (events between them
+    // would stall the stream), counted as one launch per grid
+    double bytes = 0;
+    for (const DevGrid<T> &g : P.grids) bytes += 2.0 * sizeof(cx<T>) * g.n[0] * (8.0 * nb * g.N[1] * g.N[2]);
+    StageTimer tx(c, SCABS_STAGE_XLINE32, bytes, (int)P.grids.size());
+    for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb, CONV_XLINES);
+  } else {
+    for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb, CONV_XLINES);
   }
   for (const DevGrid<T> &g : P.grids) launch_conv(g, s, nb, CONV_PLANES_INV);
 }
@@ -808,12 +812,13 @@ template <typename T> static void apply(scabs_ctx *c, PrecState<T> &P, const dou
       // its own (algorithmic bytes: the 8 sources of every point read once,
       // the 8 fields of every node written once)
       launch_project(P.op, P.grids, P.gather, s, nb, -2);
+      double bytes = 0;
       for (size_t k = 0; k < P.grids.size(); k++) {
         const DevGrid<T> &g = P.grids[k];
-        const double bytes = 8.0 * sizeof(cx<T>) * nb * ((double)P.gather[k].np + (double)g.n[0] * g.n[1] * g.n[2]);
-        StageTimer tg(c, SCABS_STAGE_GATHER32, bytes);
-        launch_project(P.op, P.grids, P.gather, s, nb, (int)k);
+        bytes += 8.0 * sizeof(cx<T>) * nb * ((double)P.gather[k].np + (double)g.n[0] * g.n[1] * g.n[2]);
       }
+      StageTimer tg(c, SCABS_STAGE_GATHER32, bytes, (int)P.grids.size());
+      for (size_t k = 0; k < P.grids.size(); k++) launch_project(P.op, P.grids, P.gather, s, nb, (int)k);
     } else {
       launch_project(P.op, P.grids, P.gather, s, nb);
     }
@@ -916,6 +921,17 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
 // per-system orthogonalisation, one host synchronisation per step for all of
 // them (two when a system needs the second pass).
 // ---------------------------------------------------------------------------
+// Wait for the work enqueued so far on s by polling an event (the host
+// spins instead of sleeping; used once per Arnoldi step)
+static void wait_polling(scabs_ctx *c, hipStream_t s) {
+  if (!c->ev_read) HIPCHK(hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(c->ev_read, s));
+  hipError_t e;
+  while ((e = hipEventQuery(c->ev_read)) == hipErrorNotReady) {
+  }
+  if (e != hipSuccess) throw HipError{e, "hipEventQuery"};
+}
+
 // complex entries in front of the Hessenberg columns that hold the norms
 // (2 nb + 4 doubles for nb <= KR_MAX_SYSTEMS)
 constexpr size_t KR_NRM = KR_MAX_SYSTEMS + 2;
@@ -1067,10 +1083,11 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       // v_{j+1} = w / ||w|| before the read-back (redone below for systems
       // that take a second pass)
       kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(run), s);
-      // norms and Hessenberg columns in one copy to pinned memory
+      // norms and Hessenberg columns in one copy to pinned memory, waited for
+      // by polling its event (a blocking wait wakes the host up later)
       HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb.size()), hipMemcpyDeviceToHost,
                             s));
-      HIPCHK(hipStreamSynchronize(s));
+      wait_polling(c, s);
       std::copy(c->hpin + KR_NRM, c->hpin + KR_NRM + hb.size(), hb.begin());
       std::copy((const double *)c->hpin, (const double *)c->hpin + 2 * nb, hn.begin());
       std::vector<int> reo;
@@ -1630,7 +1647,7 @@ int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count) {
     if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) continue;
     if (r.stage >= 0 && r.stage < SCABS_NSTAGES) {
       if (ms) ms[r.stage] += t;
-      if (count) count[r.stage] += 1;
+      if (count) count[r.stage] += r.launches;
       c->prof_bytes[r.stage] += r.bytes;
     }
   }
@@ -1656,6 +1673,7 @@ void scabs_destroy(scabs_ctx *c) {
   c->workV32.release();
   c->mem.release();
   if (c->hpin) hipHostFree(c->hpin);
+  if (c->ev_read) hipEventDestroy(c->ev_read);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
