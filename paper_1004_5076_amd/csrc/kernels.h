@@ -80,6 +80,9 @@ hipError_t build_ghat(const GridDesc &d, double h, const cx<double> *tw64, int t
                       cx<float> *ghat32, hipStream_t s);
 
 // ---- matvec steps ------------------------------------------------------------
+// lattice gathers (projection and transposed testing): phase-B layout with one
+// node per lane triple (its three x offsets), 21 nodes (63 lanes) per wave
+constexpr int GB_NODES_PER_WAVE = 21;
 // Batched steps: nb vectors at once; every per-vector buffer (x, y, op.src,
 // op.tri_out, gather sources, grid fields) holds nb consecutive copies.
 template <typename T> void launch_unpack(const DevOperator<T> &op, const double *x, hipStream_t s, int nb = 1);

@@ -203,9 +203,19 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MAXI; m++) {
-      const int it = threadIdx.x + m * blockDim.x;
-      if (it >= 3 * plane) continue;
-      const int oxi = fdiv(it, dpl), nd = it - oxi * plane;
+      int oxi, nd;
+      if constexpr (MAXI == 1) {
+        // 21 nodes per wave, their three x offsets in neighbouring lanes
+        const int ln = threadIdx.x & 63;
+        oxi = ln % 3;
+        nd = (threadIdx.x >> 6) * GB_NODES_PER_WAVE + ln / 3;
+        if (ln >= 3 * GB_NODES_PER_WAVE || nd >= plane) continue;
+      } else {
+        const int it = threadIdx.x + m * blockDim.x;
+        if (it >= 3 * plane) continue;
+        oxi = fdiv(it, dpl);
+        nd = it - oxi * plane;
+      }
       const int cxp = x - (oxi - 1);
       if (cxp < xl || cxp > xh) continue;
       const int y = fdiv(nd, dn2), z = nd - y * n2;
@@ -229,8 +239,22 @@ gather_adj_kernel(DevGrid<T> dg, GatherGrid<T> g, const cx<T> *__restrict__ src4
     }
     __syncthreads();
   }
-  cx<T> *s_red = &s_q[0][0];
   const size_t G = (size_t)g.ncell;
+  if constexpr (MAXI == 1) {
+    // the three x-offset sums of a node meet across neighbouring lanes
+    const int ln = threadIdx.x & 63;
+    const int nd = (threadIdx.x >> 6) * GB_NODES_PER_WAVE + ln / 3;
+    const bool own = ln < 3 * GB_NODES_PER_WAVE && ln % 3 == 0 && nd < plane;
+#pragma unroll
+    for (int f = 0; f < 8; f++) {
+      const cx<T> v = acc[0][f];
+      const cx<T> v1 = {__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64)};
+      const cx<T> v2 = {__shfl_down(v.x, 2, 64), __shfl_down(v.y, 2, 64)};
+      if (own) dg.phys[f * G + (size_t)x * plane + nd] = v + v1 + v2;
+    }
+    return;
+  }
+  cx<T> *s_red = &s_q[0][0];
   for (int f = 0; f < 8; f++) {
 #pragma unroll
     for (int m = 0; m < MAXI; m++) {
@@ -255,8 +279,18 @@ void launch_test_t(const DevOperator<T> &op, const std::vector<DevGrid<T>> &grid
   for (size_t k = 0; k < grids.size(); k++) {
     const int plane = grids[k].n[1] * grids[k].n[2];
     const int items = 3 * plane;
-    const int threads = std::min(1024, (items + 63) / 64 * 64);
-    const int maxi = (items + threads - 1) / threads;
+    int threads = std::min(1024, (items + 63) / 64 * 64);
+    int maxi = (items + threads - 1) / threads;
+    // one pass over the nodes in lane triples when they fit one work-group
+    const int triple_threads = (plane + GB_NODES_PER_WAVE - 1) / GB_NODES_PER_WAVE * 64;
+    if (maxi == 1) {
+      if (triple_threads <= 1024) {
+        threads = std::max(threads, triple_threads);
+      } else {
+        threads = 1024;
+        maxi = 2;
+      }
+    }
     const size_t lds = sizeof(int) * (size_t)items;   // cell -> slot map of three planes
     if (maxi == 1)
       hipLaunchKernelGGL((gather_adj_kernel<T, 1>), dim3(grids[k].n[0]), dim3(threads), lds, s, grids[k], gg[k],
@@ -538,21 +572,26 @@ precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__
   double v[2 * PT_WCOLS];
 #pragma unroll
   for (int k = 0; k < 2 * PT_WCOLS; k++) v[k] = 0.0;
-  for (int i = lane; i < ncore; i += 64) {
-    const uint4 c0 = Rb[2 * i], c1 = Rb[2 * i + 1];
+  auto row = [&](const uint4 c0, const uint4 c1, const cx<double> xv) {
     const uint32_t wd[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    cx<float> rv[PT_WCOLS];
-#pragma unroll
-    for (int u = 0; u < PT_WCOLS; u++) rv[u] = unpack_h2(wd[u]);
-    const cx<double> xv = xcc[i];
 #pragma unroll
     for (int u = 0; u < PT_WCOLS; u++) {
-      v[2 * u] = fma((double)rv[u].x, xv.x, v[2 * u]);
-      v[2 * u] = fma(-(double)rv[u].y, xv.y, v[2 * u]);
-      v[2 * u + 1] = fma((double)rv[u].x, xv.y, v[2 * u + 1]);
-      v[2 * u + 1] = fma((double)rv[u].y, xv.x, v[2 * u + 1]);
+      const cx<float> rv = unpack_h2(wd[u]);
+      v[2 * u] = fma((double)rv.x, xv.x, v[2 * u]);
+      v[2 * u] = fma(-(double)rv.y, xv.y, v[2 * u]);
+      v[2 * u + 1] = fma((double)rv.x, xv.y, v[2 * u + 1]);
+      v[2 * u + 1] = fma((double)rv.y, xv.x, v[2 * u + 1]);
     }
+  };
+  // two row blocks per step: 64 bytes of coefficients in flight per lane
+  int i = lane;
+  for (; i + 64 < ncore; i += 128) {
+    const uint4 a0 = Rb[2 * i], a1 = Rb[2 * i + 1], b0 = Rb[2 * (i + 64)], b1 = Rb[2 * (i + 64) + 1];
+    const cx<double> xa = xcc[i], xb = xcc[i + 64];
+    row(a0, a1, xa);
+    row(b0, b1, xb);
   }
+  if (i < ncore) row(Rb[2 * i], Rb[2 * i + 1], xcc[i]);
   const double t = wsum16_scatter(v);
   const int k = (lane >> 2) & 15, u = k >> 1;
   // lanes 0, 8, 16, ... hold the real parts, lanes 4, 12, ... the imaginary parts

@@ -110,8 +110,6 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
 // neighbouring lanes and are added by shuffles.  No atomics; the summation
 // order is fixed.
 template <typename T> struct CellChunk { static constexpr int value = 96; };
-// phase-B layout with one node per thread triple: 21 nodes (63 lanes) per wave
-constexpr int GB_NODES_PER_WAVE = 21;
 template <> struct CellChunk<double> { static constexpr int value = 48; };
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
