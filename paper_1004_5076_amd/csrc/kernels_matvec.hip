@@ -528,8 +528,16 @@ __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, doubl
 #pragma unroll
   for (int q = 0; q < 6 * NRB; q++) v[q] = T(0);
   const int64_t kb = op.rowptr[n], ke = op.rowptr[n + 1];
-  for (int64_t k = kb + lane; k < ke; k += 64) {
-    const int m = op.col[k];
+  // the column indices of this lane's first NR_PRE entries are loaded up
+  // front, so only the first entry waits for its index before its currents
+  constexpr int NR_PRE = 4;
+  int mpre[NR_PRE];
+#pragma unroll
+  for (int u = 0; u < NR_PRE; u++) mpre[u] = kb + lane + 64 * u < ke ? op.col[kb + lane + 64 * u] : 0;
+  int u = 0;
+  for (int64_t k = kb + lane; k < ke; k += 64, u++) {
+    const int m = u == 0 ? mpre[0] : u == 1 ? mpre[1] : u == 2 ? mpre[2] : u == 3 ? mpre[3] : op.col[k];
+    static_assert(NR_PRE == 4, "the selection above names the four prefetched indices");
     const cx<T> Le = op.V4[4 * k], Ke = op.V4[4 * k + 1], Li = op.V4[4 * k + 2], Ki = op.V4[4 * k + 3];
     //   E += Zi Li Ji - Ze Le Je + (Ke + Ki) M
     //   H += Ki Ji - (Ke + Ze Lr) Je + (Kr - Le / Ze - Li / Zi) M
