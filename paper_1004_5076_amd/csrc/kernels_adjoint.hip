@@ -463,8 +463,13 @@ near_rows_t_kernel(DevOperator<T> op, const int64_t *__restrict__ tpos, double *
   // mirrored values: row-ordered copies where they exist, else through tpos
   const bool mirrored = op.V4T != nullptr;
   const cx<T> *V4 = mirrored ? op.V4T : op.V4, *S4 = mirrored ? op.S4T : op.S4;
-  for (int64_t k = b + lane; k < e; k += 64) {
-    const int n = op.col[k];
+  // the column indices of this lane's first four entries are loaded up front
+  int npre[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) npre[u] = b + lane + 64 * u < e ? op.col[b + lane + 64 * u] : 0;
+  int u = 0;
+  for (int64_t k = b + lane; k < e; k += 64, u++) {
+    const int n = u == 0 ? npre[0] : u == 1 ? npre[1] : u == 2 ? npre[2] : u == 3 ? npre[3] : op.col[k];
     const int64_t t = mirrored ? k : tpos[k];
     const cx<T> zE = op.src[3 * n], zH = op.src[3 * n + 1], z14 = op.src[3 * n + 2];
     const cx<T> Le = V4[4 * t], Ke = V4[4 * t + 1], Li = V4[4 * t + 2], Ki = V4[4 * t + 3];
