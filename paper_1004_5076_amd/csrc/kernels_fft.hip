@@ -251,12 +251,16 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (w < nl) {   // wave-uniform: every lane of the wave takes part below
     cx<T> *ln = buf + w * XR_LS;
+    // n0 <= 512 (launch condition): elements 8..15 of every lane are the
+    // zero padding, known zero here so the first 16-point transform folds them
     cx<T> v[16];
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
+    for (int r = 0; r < 8; r++) {
       const int x = lane + 64 * r;
       v[r] = x < n0 ? ln[x] : czero<T>();
     }
+#pragma unroll
+    for (int r = 8; r < 16; r++) v[r] = czero<T>();
     rdft<T, 16, false>(v);
 #pragma unroll
     for (int a = 1; a < 16; a++) v[a] = v[a] * tw[a * 64 + lane];
@@ -299,8 +303,9 @@ xline_reg_kernel(cx<T> *__restrict__ spec, int n0, int N1, int N2, const cx<T> *
     for (int a = 1; a < 16; a++) v[a] = twm<T, true>(v[a], tw[a * 64 + lane]);
     rdft<T, 16, true>(v);
     wave_lds_fence();
+    // only the physical range x < n0 <= 512 is kept: elements 0..7
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
+    for (int r = 0; r < 8; r++) {
       const int x = lane + 64 * r;
       if (x < n0) ln[x] = v[r];
     }
