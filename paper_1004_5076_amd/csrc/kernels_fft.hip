@@ -119,28 +119,31 @@ __host__ __device__ constexpr bool reg_line_ok(int n) {
   return n == 4 || n == 6 || n == 8 || n == 12 || n == 16 || n == 24 || n == 32 || n == 48;
 }
 
-// out[i os] = (DFT of in[0..nin) zero-padded to NN)[i] for i < nout
-template <typename T, int NN, bool INV>
+// out[i os] = (DFT of in[0..nin) zero-padded to NN)[i] for i < nout.  The
+// embedding has NN >= 2 n - 1, so a forward line's input (HALF_IN) and an
+// inverse line's kept output (HALF_OUT) lie in the lower half: the upper
+// half is known zero, or not computed back.
+template <typename T, int NN, bool INV, bool HALF_IN, bool HALF_OUT>
 __device__ __forceinline__ void line_dft(const cx<T> *in, int is, int nin, cx<T> *out, int os, int nout) {
   cx<T> v[NN];
 #pragma unroll
-  for (int i = 0; i < NN; i++) v[i] = i < nin ? in[i * is] : czero<T>();
+  for (int i = 0; i < NN; i++) v[i] = (HALF_IN && i >= NN / 2) || i >= nin ? czero<T>() : in[i * is];
   rdft<T, NN, INV>(v);
 #pragma unroll
   for (int i = 0; i < NN; i++)
-    if (i < nout) out[i * os] = v[i];
+    if ((!HALF_OUT || i < NN / 2) && i < nout) out[i * os] = v[i];
 }
-template <typename T, bool INV>
+template <typename T, bool INV, bool HALF_IN, bool HALF_OUT>
 __device__ __forceinline__ void line_dft_n(int NN, const cx<T> *in, int is, int nin, cx<T> *out, int os, int nout) {
   switch (NN) {
-    case 4: line_dft<T, 4, INV>(in, is, nin, out, os, nout); break;
-    case 6: line_dft<T, 6, INV>(in, is, nin, out, os, nout); break;
-    case 8: line_dft<T, 8, INV>(in, is, nin, out, os, nout); break;
-    case 12: line_dft<T, 12, INV>(in, is, nin, out, os, nout); break;
-    case 16: line_dft<T, 16, INV>(in, is, nin, out, os, nout); break;
-    case 24: line_dft<T, 24, INV>(in, is, nin, out, os, nout); break;
-    case 32: line_dft<T, 32, INV>(in, is, nin, out, os, nout); break;
-    default: line_dft<T, 48, INV>(in, is, nin, out, os, nout); break;
+    case 4: line_dft<T, 4, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    case 6: line_dft<T, 6, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    case 8: line_dft<T, 8, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    case 12: line_dft<T, 12, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    case 16: line_dft<T, 16, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    case 24: line_dft<T, 24, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    case 32: line_dft<T, 32, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
+    default: line_dft<T, 48, INV, HALF_IN, HALF_OUT>(in, is, nin, out, os, nout); break;
   }
 }
 
@@ -157,12 +160,12 @@ plane_fwd_reg_kernel(const cx<T> *__restrict__ phys, cx<T> *__restrict__ spec, i
   const int np = min(P, n0 - x0), S = N2 + 1;
   const cx<T> *src = phys + ((size_t)f * n0 + x0) * n1 * n2;
   for (int i = threadIdx.x; i < np * n1; i += blockDim.x)
-    line_dft_n<T, false>(N2, src + (size_t)i * n2, 1, n2, buf + i * S, 1, N2);
+    line_dft_n<T, false, true, false>(N2, src + (size_t)i * n2, 1, n2, buf + i * S, 1, N2);
   __syncthreads();
   cx<T> *dst = spec + ((size_t)f * n0 + x0) * N1 * N2;
   for (int i = threadIdx.x; i < np * N2; i += blockDim.x) {
     const int pl = i / N2, kz = i - pl * N2;
-    line_dft_n<T, false>(N1, buf + pl * n1 * S + kz, S, n1, dst + (size_t)pl * N1 * N2 + kz, N2, N1);
+    line_dft_n<T, false, true, false>(N1, buf + pl * n1 * S + kz, S, n1, dst + (size_t)pl * N1 * N2 + kz, N2, N1);
   }
 }
 // Inverse: every y line (N1, kept y < n1) into LDS, then the z lines (kept z < n2).
@@ -177,12 +180,12 @@ plane_inv_reg_kernel(const cx<T> *__restrict__ spec, cx<T> *__restrict__ phys, i
   const cx<T> *src = spec + ((size_t)f * n0 + x0) * N1 * N2;
   for (int i = threadIdx.x; i < np * N2; i += blockDim.x) {
     const int pl = i / N2, kz = i - pl * N2;
-    line_dft_n<T, true>(N1, src + (size_t)pl * N1 * N2 + kz, N2, N1, buf + pl * n1 * S + kz, S, n1);
+    line_dft_n<T, true, false, true>(N1, src + (size_t)pl * N1 * N2 + kz, N2, N1, buf + pl * n1 * S + kz, S, n1);
   }
   __syncthreads();
   cx<T> *dst = phys + ((size_t)f * n0 + x0) * n1 * n2;
   for (int i = threadIdx.x; i < np * n1; i += blockDim.x)
-    line_dft_n<T, true>(N2, buf + i * S, 1, N2, dst + (size_t)i * n2, 1, n2);
+    line_dft_n<T, true, false, true>(N2, buf + i * S, 1, N2, dst + (size_t)i * n2, 1, n2);
 }
 static int reg_planes(int n1, int N2) { return std::max(1, PLANE_REG_THREADS / std::max(n1, N2)); }
 
@@ -353,7 +356,9 @@ template <typename T> void launch_conv(const DevGrid<T> &g, hipStream_t s, int n
   const bool pw = FftCfg<T>::wave && wave_fits(N2, P * n1, nw, EW) && wave_fits(N1, P * N2, nw, EW);
   // register-resident y-z transforms where both lengths are supported
   const int Pr = std::min(reg_planes(n1, N2), (int)(LDS_BUDGET / (sizeof(cx<T>) * (size_t)n1 * (N2 + 1))));
-  const bool preg = reg_line_ok(N1) && reg_line_ok(N2) && Pr >= 1;
+  // (the register kernels assume the physical lengths fill at most half of
+  // the transform lengths, which the embedding size guarantees)
+  const bool preg = reg_line_ok(N1) && reg_line_ok(N2) && Pr >= 1 && 2 * n1 <= N1 && 2 * n2 <= N2;
   const size_t preg_lds = sizeof(cx<T>) * (size_t)Pr * n1 * (N2 + 1);
   const int npr = (n0 + Pr - 1) / Pr;
   if (!(parts & CONV_PLANES_FWD)) {
