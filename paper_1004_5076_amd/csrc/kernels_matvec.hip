@@ -109,7 +109,10 @@ point_sources_kernel(const PointRec<T> *__restrict__ pts, const TriRec<T> *__res
 // through a cell -> slot map in LDS; the three x partials of a node sit in
 // neighbouring lanes and are added by shuffles.  No atomics; the summation
 // order is fixed.
-template <typename T> struct CellChunk { static constexpr int value = 96; };
+// cells per pass: FP32 64 (measured best of 48-160 for batches: less LDS,
+// more resident work-groups), FP64 48; the same for every batch size, so a
+// batch gives each vector the sums of its own product
+template <typename T> struct CellChunk { static constexpr int value = 64; };
 template <> struct CellChunk<double> { static constexpr int value = 48; };
 template <typename T, int MAXI>
 __global__ void __launch_bounds__(1024) gather_kernel(DevGrid<T> dg, GatherGrid<T> g) {
