@@ -1026,7 +1026,10 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
   std::vector<std::vector<zd>> H(nb, std::vector<zd>((size_t)(m + 1) * m)), g(nb, std::vector<zd>(m + 1)),
       cs(nb, std::vector<zd>(m)), sn(nb, std::vector<zd>(m));
   std::vector<int> jb(nb);
-  std::vector<cx<double>> hb(2 * (size_t)(m + 2) * nb);
+  // Hessenberg columns of the running step (both passes), read in place in
+  // the pinned copy of the device block: system b's at hb + 2 (m + 2) b
+  const size_t hb_size = 2 * (size_t)(m + 2) * nb;
+  const cx<double> *const hb = c->hpin + KR_NRM;
   while (true) {
     std::vector<int> act;
     for (int b = 0; b < nb; b++) {
@@ -1085,10 +1088,8 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(run), s);
       // norms and Hessenberg columns in one copy to pinned memory, waited for
       // by polling its event (a blocking wait wakes the host up later)
-      HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb.size()), hipMemcpyDeviceToHost,
-                            s));
+      HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb_size), hipMemcpyDeviceToHost, s));
       wait_polling(c, s);
-      std::copy(c->hpin + KR_NRM, c->hpin + KR_NRM + hb.size(), hb.begin());
       std::copy((const double *)c->hpin, (const double *)c->hpin + 2 * nb, hn.begin());
       std::vector<int> reo;
       for (int b : run) {
@@ -1102,15 +1103,11 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
                         c->nrm + nb, c->nrm, s);
         }
         for (int b : reo) reo2[b] = 1;
-        std::vector<cx<double>> hb2(hb.size());
-        HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb.size()),
-                              hipMemcpyDeviceToHost, s));
+        // the block again: the second pass's columns beside the unchanged first ones
+        HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb_size), hipMemcpyDeviceToHost,
+                              s));
         HIPCHK(hipStreamSynchronize(s));
-        std::copy(c->hpin + KR_NRM, c->hpin + KR_NRM + hb.size(), hb2.begin());
         std::copy((const double *)c->hpin, (const double *)c->hpin + nb, hn.begin());
-        for (int b : reo)
-          std::copy(hb2.begin() + 2 * (size_t)(m + 2) * b + (m + 2), hb2.begin() + 2 * (size_t)(m + 2) * (b + 1),
-                    hb.begin() + 2 * (size_t)(m + 2) * b + (m + 2));
         kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(reo), s);
       }
       // the next step's product goes into the stream now, so the GPU works
@@ -1121,7 +1118,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       }
       std::vector<int> next;
       for (int b : run) {
-        const cx<double> *h1 = hb.data() + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
+        const cx<double> *h1 = hb + 2 * (size_t)(m + 2) * b, *h2 = h1 + (m + 2);
         zd *col = &H[b][(size_t)j * (m + 1)];
         for (int i = 0; i <= j; i++)
           col[i] = reo2[b] ? zd(h1[i].x + h2[i].x, h1[i].y + h2[i].y) : zd(h1[i].x, h1[i].y);
