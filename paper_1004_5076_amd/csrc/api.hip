@@ -138,6 +138,8 @@ struct scabs_ctx {
   int *pc_ext_slot = nullptr, *pc_core_slot = nullptr;
   int *pc_items = nullptr;   // (cluster, first core row) per apply work-group
   int pc_n_items = 0;
+  int *pc_items32 = nullptr;   // the same work-groups in the FP32 apply's dispatch order (cluster -1: empty)
+  int pc_n_items32 = 0;
   int pc_max_ext = 0;        // largest extended set
   uint32_t *pc_Rt = nullptr;   // stored rows (FP16 pairs), see PcStore
   float *pc_Rs = nullptr;      // column scales, one per ext entry
@@ -501,6 +503,56 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
       }
     c->pc_n_items = (int)(items.size() / 2);
     c->pc_items = c->mem.upload(items);
+    // the FP32 batched apply's work-groups run in one and a half waves of
+    // residency and differ up to threefold in length (a work-group's time
+    // follows its cluster's column count), so their order is planned: whole
+    // clusters go to the eight XCDs longest first, each to the least loaded
+    // (a cluster's gathered inputs then stay in one L2), and each XCD takes
+    // its work-groups longest first.  Work-groups are dispatched to the XCDs
+    // in turn, so XCD x runs list entries x, x + 8, ...; shorter lists are
+    // padded with empty entries (cluster -1).
+    std::vector<double> work(cl.nc);
+    for (int k = 0; k < cl.nc; k++) {
+      const double nblk = (double)((cl.ext_ptr[k + 1] - cl.ext_ptr[k] + RT_CB - 1) / RT_CB);
+      work[k] = nblk * (double)((cl.core_ptr[k + 1] - cl.core_ptr[k] + rows - 1) / rows);
+    }
+    std::vector<int> by_work(cl.nc);
+    std::iota(by_work.begin(), by_work.end(), 0);
+    std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work[a] > work[b]; });
+    constexpr int NXCD = 8;
+    std::vector<double> load(NXCD, 0.0);
+    std::vector<std::vector<int>> xcd(NXCD);
+    for (int k : by_work) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[x] += work[k];
+      xcd[x].push_back(k);
+    }
+    size_t len = 0;
+    std::vector<std::vector<std::pair<int, int>>> lists(NXCD);
+    for (int x = 0; x < NXCD; x++) {
+      // clusters already in decreasing total work; per work-group the column
+      // count decides, so sort by it (stable: a cluster's rows stay together)
+      std::vector<int> ks = xcd[x];
+      std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) {
+        return cl.ext_ptr[a + 1] - cl.ext_ptr[a] > cl.ext_ptr[b + 1] - cl.ext_ptr[b];
+      });
+      for (int k : ks)
+        for (int64_t r0 = 0; r0 < cl.core_ptr[k + 1] - cl.core_ptr[k]; r0 += rows) lists[x].push_back({k, (int)r0});
+      len = std::max(len, lists[x].size());
+    }
+    std::vector<int> items32(2 * NXCD * len, 0);
+    for (size_t j = 0; j < len; j++)
+      for (int x = 0; x < NXCD; x++) {
+        const size_t at = 2 * (j * NXCD + x);
+        if (j < lists[x].size()) {
+          items32[at] = lists[x][j].first;
+          items32[at + 1] = lists[x][j].second;
+        } else {
+          items32[at] = -1;
+        }
+      }
+    c->pc_n_items32 = (int)(items32.size() / 2);
+    c->pc_items32 = c->mem.upload(items32);
   }
   p.ext_ptr = c->pc_ext_ptr;
   p.ext_slot = c->pc_ext_slot;
@@ -903,7 +955,7 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
       const double bytes =
           4.0 * (double)c->pc_coef + 8.0 * m * (double)c->pc_n_ext + (4.0 + 16.0 * m) * (double)c->lay.N;
       StageTimer tm(c, SCABS_STAGE_PRECOND, bytes);
-      launch_precond_apply32(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot, c->pc_r_off,
+      launch_precond_apply32(c->pc_n_items32, c->pc_items32, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot, c->pc_r_off,
                              c->pc_Rt, c->pc_xe, y + b0 * N, (int64_t)N, m, c->stream);
     }
     return;

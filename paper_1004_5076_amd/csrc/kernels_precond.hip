@@ -472,8 +472,10 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
                        const int64_t *__restrict__ r_off, const uint32_t *__restrict__ Rst,
                        const cx<float> *__restrict__ xe, cx<double> *__restrict__ y, int64_t N) {
   __shared__ cx<float> red[PA32_Q][PA_ROWS][NB];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  // items are listed in dispatch order (see launch_precond_apply32)
+  const int item = blockIdx.x;
   const int c = items[2 * item], i0 = items[2 * item + 1];
+  if (c < 0) return;   // padding entry: the whole work-group leaves
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
@@ -549,7 +551,10 @@ static void apply32_launch(int n_items, const int *items, const int64_t *ext_ptr
 }
 
 // m <= precond_apply32_max_batch() vectors (one kernel instance per count);
-// xe as written by launch_precond_gather32 with the same m
+// xe as written by launch_precond_gather32 with the same m.  items: n_items
+// (cluster, first core row) pairs, one work-group each in list order, so the
+// list fixes which XCD runs what (work-group i goes to XCD i mod 8); entries
+// with cluster -1 are empty.
 void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int64_t *core_ptr,
                             const int *core_slot, const int64_t *r_off, const uint32_t *R, const cx<float> *xe,
                             cx<double> *y, int64_t N, int m, hipStream_t s) {
