@@ -411,6 +411,53 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   op.tri_out = P.tri_out;
 }
 
+// Dispatch order of per-cluster work-groups: items holds (cluster, offset)
+// pairs, a cluster's consecutive; len[k] is the run time of one of cluster
+// k's work-groups (any unit).  Work-groups go to the eight XCDs in turn (work-
+// group i to XCD i mod 8), so the returned list is read as eight interleaved
+// lists: whole clusters go to the XCDs longest total first, each to the least
+// loaded (longest-processing-time rule; a cluster's shared inputs then stay
+// in one L2), and each XCD takes its work-groups longest first, so that the
+// short ones fill the gaps at the end.  Shorter lists are padded with empty
+// entries (cluster -1), which the kernels skip.
+static std::vector<int> xcd_dispatch_order(const std::vector<int> &items, const std::vector<double> &len) {
+  constexpr int NXCD = 8;
+  const int nc = (int)len.size();
+  std::vector<std::vector<int>> offs(nc);
+  for (size_t i = 0; i + 1 < items.size(); i += 2) offs[items[i]].push_back(items[i + 1]);
+  std::vector<double> work(nc);
+  for (int k = 0; k < nc; k++) work[k] = len[k] * (double)offs[k].size();
+  std::vector<int> by_work(nc);
+  std::iota(by_work.begin(), by_work.end(), 0);
+  std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<double> load(NXCD, 0.0);
+  std::vector<std::vector<int>> xcd(NXCD);
+  for (int k : by_work) {
+    if (offs[k].empty()) continue;
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += work[k];
+    xcd[x].push_back(k);
+  }
+  size_t n = 0;
+  for (int x = 0; x < NXCD; x++) {
+    std::stable_sort(xcd[x].begin(), xcd[x].end(), [&](int a, int b) { return len[a] > len[b]; });
+    size_t cnt = 0;
+    for (int k : xcd[x]) cnt += offs[k].size();
+    n = std::max(n, cnt);
+  }
+  std::vector<int> out(2 * NXCD * n, -1);
+  for (int x = 0; x < NXCD; x++) {
+    size_t j = 0;
+    for (int k : xcd[x])
+      for (int o : offs[k]) {
+        out[2 * (j * NXCD + x)] = k;
+        out[2 * (j * NXCD + x) + 1] = o;
+        j++;
+      }
+  }
+  return out;
+}
+
 // Restricted additive Schwarz preconditioner from the exact near-field values
 static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp) {
   const Geometry &g = c->geo;
@@ -486,6 +533,11 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
     c->pc_coef = 0;
     for (int k = 0; k < cl.nc; k++)
       c->pc_coef += (cl.ext_ptr[k + 1] - cl.ext_ptr[k]) * (cl.core_ptr[k + 1] - cl.core_ptr[k]);
+    // the transposed apply's work-groups take time in proportion to their
+    // cluster's core size (a fivefold range)
+    std::vector<double> len_t(cl.nc);
+    for (int k = 0; k < cl.nc; k++) len_t[k] = (double)(cl.core_ptr[k + 1] - cl.core_ptr[k]);
+    t_items = xcd_dispatch_order(t_items, len_t);
     c->pc_n_t_items = (int)(t_items.size() / 2);
     c->pc_t_items = c->mem.upload(t_items);
     c->pc_inv_ptr = c->mem.upload(inv_ptr);
@@ -505,52 +557,10 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
     c->pc_items = c->mem.upload(items);
     // the FP32 batched apply's work-groups run in one and a half waves of
     // residency and differ up to threefold in length (a work-group's time
-    // follows its cluster's column count), so their order is planned: whole
-    // clusters go to the eight XCDs longest first, each to the least loaded
-    // (a cluster's gathered inputs then stay in one L2), and each XCD takes
-    // its work-groups longest first.  Work-groups are dispatched to the XCDs
-    // in turn, so XCD x runs list entries x, x + 8, ...; shorter lists are
-    // padded with empty entries (cluster -1).
-    std::vector<double> work(cl.nc);
-    for (int k = 0; k < cl.nc; k++) {
-      const double nblk = (double)((cl.ext_ptr[k + 1] - cl.ext_ptr[k] + RT_CB - 1) / RT_CB);
-      work[k] = nblk * (double)((cl.core_ptr[k + 1] - cl.core_ptr[k] + rows - 1) / rows);
-    }
-    std::vector<int> by_work(cl.nc);
-    std::iota(by_work.begin(), by_work.end(), 0);
-    std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work[a] > work[b]; });
-    constexpr int NXCD = 8;
-    std::vector<double> load(NXCD, 0.0);
-    std::vector<std::vector<int>> xcd(NXCD);
-    for (int k : by_work) {
-      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      load[x] += work[k];
-      xcd[x].push_back(k);
-    }
-    size_t len = 0;
-    std::vector<std::vector<std::pair<int, int>>> lists(NXCD);
-    for (int x = 0; x < NXCD; x++) {
-      // clusters already in decreasing total work; per work-group the column
-      // count decides, so sort by it (stable: a cluster's rows stay together)
-      std::vector<int> ks = xcd[x];
-      std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) {
-        return cl.ext_ptr[a + 1] - cl.ext_ptr[a] > cl.ext_ptr[b + 1] - cl.ext_ptr[b];
-      });
-      for (int k : ks)
-        for (int64_t r0 = 0; r0 < cl.core_ptr[k + 1] - cl.core_ptr[k]; r0 += rows) lists[x].push_back({k, (int)r0});
-      len = std::max(len, lists[x].size());
-    }
-    std::vector<int> items32(2 * NXCD * len, 0);
-    for (size_t j = 0; j < len; j++)
-      for (int x = 0; x < NXCD; x++) {
-        const size_t at = 2 * (j * NXCD + x);
-        if (j < lists[x].size()) {
-          items32[at] = lists[x][j].first;
-          items32[at + 1] = lists[x][j].second;
-        } else {
-          items32[at] = -1;
-        }
-      }
+    // follows its cluster's column count)
+    std::vector<double> len32(cl.nc);
+    for (int k = 0; k < cl.nc; k++) len32[k] = (double)((cl.ext_ptr[k + 1] - cl.ext_ptr[k] + RT_CB - 1) / RT_CB);
+    const std::vector<int> items32 = xcd_dispatch_order(items, len32);
     c->pc_n_items32 = (int)(items32.size() / 2);
     c->pc_items32 = c->mem.upload(items32);
   }

@@ -178,7 +178,9 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
 // FP32 batched apply (inner solves of the mixed mode): m vectors of N,
 // m <= precond_apply32_max_batch().  First the inputs are gathered into an
 // ext-ordered copy xe[e m + b] = scale_e x_b[ext_slot_e] (FP32, n_ext m
-// entries), then every work-group stages its cluster's part of xe.
+// entries), then every work-group reads its cluster's part of xe.  items:
+// (cluster, first core row) pairs in dispatch order (work-group i runs entry
+// i; cluster -1 marks an empty entry).
 int precond_apply32_max_batch();
 void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<double> *x, int64_t N,
                              int m, cx<float> *xe, hipStream_t s);
@@ -198,7 +200,8 @@ template <typename T>
 void launch_interp_adj(const DevOperator<T> &op, const DevGrid<T> &ext, const DevGrid<T> *ints_dev, hipStream_t s);
 template <typename T>
 void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y, hipStream_t s);
-// items: (cluster, first ext column) per work-group, precond_t_cols_per_item() columns each
+// items: (cluster, first ext column) per work-group, precond_t_cols_per_item() columns each, in
+// dispatch order (work-group i runs entry i; cluster -1 marks an empty entry)
 int precond_t_cols_per_item();
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,

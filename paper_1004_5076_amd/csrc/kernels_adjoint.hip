@@ -556,10 +556,11 @@ __global__ void __launch_bounds__(PT_THREADS)
 precond_t_dots_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
                       const int64_t *__restrict__ core_ptr, const int64_t *__restrict__ r_off, PcStore pc,
                       const cx<double> *__restrict__ xc, cx<double> *__restrict__ tmp) {
-  // the items of one cluster are consecutive: keep them on one XCD (its L2
-  // then serves the cluster's core-ordered x to all of them)
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  // items are listed in dispatch order: the host keeps a cluster's items on
+  // one XCD (its L2 then serves the cluster's core-ordered x to all of them)
+  const int item = blockIdx.x;
   const int c = items[2 * item], j0 = items[2 * item + 1];
+  if (c < 0) return;   // padding entry
   const int64_t e0 = ext_ptr[c];
   const int ne = (int)(ext_ptr[c + 1] - e0);
   const int ncore = (int)(core_ptr[c + 1] - core_ptr[c]);
