@@ -531,6 +531,109 @@ precond_apply32_kernel(const int *__restrict__ items, const int64_t *__restrict_
   }
 }
 
+// The 8-vector apply on the matrix cores.  Per stored 8-column block the
+// product Y[rows, 8 vectors] += R[rows, 8 columns] X[8 columns, 8 vectors] is
+// taken in real form: K = 16 (column, re/im of R) and N = 16 (vector, re/im
+// of the result), with B[(u, re)][(b, .)] = (Re x, Im x) and
+// B[(u, im)][(b, .)] = (-Im x, Re x), so that D = Re(R x), Im(R x) side by
+// side; four 16x16x4 FP32 steps per block and 16-row tile.  Lane (m, kq),
+// m = lane % 16, kq = lane / 16, supplies in step s the (column 2 kq + s / 2,
+// part s % 2) entries: of row m of the tile for A (one 8-byte read of two
+// coefficients per tile) and of vector m / 2 for B (two gathered inputs, the
+// component picked by m % 2).  A wave covers 64 rows as four tiles that share
+// B; the waves split the blocks as in the vector-ALU form above.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(PA32_THREADS)
+precond_apply32_mfma_kernel(const int *__restrict__ items, const int64_t *__restrict__ ext_ptr,
+                            const int64_t *__restrict__ core_ptr, const int *__restrict__ core_slot,
+                            const int64_t *__restrict__ r_off, const uint32_t *__restrict__ Rst,
+                            const cx<float> *__restrict__ xe, cx<double> *__restrict__ y, int64_t N) {
+  constexpr int NB = 8;
+  __shared__ float red[PA32_Q][PA_ROWS][2 * NB];
+  const int item = blockIdx.x;
+  const int c = items[2 * item], i0 = items[2 * item + 1];
+  if (c < 0) return;   // padding entry: the whole work-group leaves
+  const int64_t e0 = ext_ptr[c];
+  const int ne = (int)(ext_ptr[c + 1] - e0);
+  const int nc = (int)(core_ptr[c + 1] - core_ptr[c]);
+  const uint32_t *R = Rst + r_off[c];
+  const int64_t ncp = rt_stride(nc);
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / PA_ROWS);
+  const int lane = threadIdx.x - q * PA_ROWS;
+  const int m = lane & 15, kq = lane >> 4;
+  const bool odd = (m & 1) != 0;
+  mf4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc[t] = mf4{0.f, 0.f, 0.f, 0.f};
+  const int nblk = (int)(rt_cols(ne) / RT_CB);
+  const int kb = (nblk * q) / PA32_Q, ke = (nblk * (q + 1)) / PA32_Q;
+  if (kb < ke) {   // wave-uniform
+    // row i0 + 16 t + m of the tiles; rows past the core read as zero
+    bool live[4];
+    const uint2 *Ra[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int i = i0 + 16 * t + m;
+      live[t] = i < nc;
+      Ra[t] = reinterpret_cast<const uint2 *>(R + (int64_t)(live[t] ? i : 0) * RT_CB + 2 * kq);
+    }
+    const int64_t bstride = ncp * RT_CB / 2;   // uint2 per block
+    // inputs of columns 2 kq, 2 kq + 1 of block k for vector m / 2
+    const cx<float> *xl = xe + e0 * NB + (2 * kq) * NB + (m >> 1);
+    auto load = [&](int k, uint2 *a, cx<float> *xv) {
+#pragma unroll
+      for (int t = 0; t < 4; t++) a[t] = live[t] ? Ra[t][k * bstride] : make_uint2(0u, 0u);
+      xv[0] = xl[(int64_t)k * RT_CB * NB];
+      xv[1] = xl[(int64_t)k * RT_CB * NB + NB];
+    };
+    uint2 a[4], an[4];
+    cx<float> xv[2], xn[2];
+    load(kb, a, xv);
+    for (int k = kb; k < ke; k++) {
+      load(k + 1 < ke ? k + 1 : k, an, xn);
+      float b[4];
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        b[2 * u] = odd ? xv[u].y : xv[u].x;
+        b[2 * u + 1] = odd ? xv[u].x : -xv[u].y;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const cx<float> r0 = unpack_h2(a[t].x), r1 = unpack_h2(a[t].y);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(r0.x, b[0], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(r0.y, b[1], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(r1.x, b[2], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(r1.y, b[3], acc[t], 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; t++) a[t] = an[t];
+      xv[0] = xn[0];
+      xv[1] = xn[1];
+    }
+  }
+  // lane (m, kq) holds D[4 kq + r][m] of each tile: row 16 t + 4 kq + r,
+  // vector m / 2, real part for even m
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) red[q][16 * t + 4 * kq + r][m] = acc[t][r];
+  __syncthreads();
+  const int i = i0 + lane;
+  if (q == 0 && i < nc) {
+    const int slot = core_slot[core_ptr[c] + i];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      float tr = red[0][lane][2 * b], ti = red[0][lane][2 * b + 1];
+      for (int k = 1; k < PA32_Q; k++) {
+        tr += red[k][lane][2 * b];
+        ti += red[k][lane][2 * b + 1];
+      }
+      y[(size_t)b * N + slot] = {(double)tr, (double)ti};
+    }
+  }
+}
+
 int precond_apply32_max_batch() { return 8; }
 
 void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<double> *x, int64_t N,
@@ -568,7 +671,10 @@ void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_pt
     case 5: SCABS_APPLY32(5); break;
     case 6: SCABS_APPLY32(6); break;
     case 7: SCABS_APPLY32(7); break;
-    default: SCABS_APPLY32(8); break;
+    default:
+      hipLaunchKernelGGL(precond_apply32_mfma_kernel, dim3(n_items), dim3(PA32_THREADS), 0, s, items, ext_ptr,
+                         core_ptr, core_slot, r_off, R, xe, y, N);
+      break;
   }
 #undef SCABS_APPLY32
 }
