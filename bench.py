@@ -52,7 +52,7 @@ def kernel_src_sha(name: str) -> str:
 ROOFLINE_KERNELS = {
     "xline32": ("xline_reg_kernel<float>", "kernels_fft.hip"),
     "gather32": ("gather_kernel<float, 1>", "kernels_matvec.hip"),
-    "precond": ("precond_apply32_kernel<8>", "kernels_precond.hip"),
+    "precond": ("precond_apply32_mfma_kernel", "kernels_precond.hip"),
 }
 
 

@@ -444,9 +444,9 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
 // reads its row's 8 coefficients (32 contiguous bytes), every lane needs the
 // same columns' NB inputs, so these are wave-uniform (scalar) loads fed
 // straight into the FMAs, and each coefficient is read once for all vectors;
-// FP32 sums, combined across the waves in LDS at the end.  (A matrix-core
-// form, 16x16x4 FP32 steps over (column, re/im) x (vector, re/im), measured
-// slower: the product is bound by the coefficient stream, not by FMAs.)  Inner solves stop
+// FP32 sums, combined across the waves in LDS at the end.  This vector-ALU
+// form serves 1 to 7 vectors; 8 vectors take the matrix-core form below
+// (the same work split, a quarter of the issue slots per coefficient).  Inner solves stop
 // at relative residuals of 1e-5 or more and an FP64 refinement follows, so
 // the rounding of x and of the sums only perturbs the preconditioner, not
 // the solution.
