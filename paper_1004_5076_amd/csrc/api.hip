@@ -1,5 +1,6 @@
 // C ABI of the library: context, setup orchestration, products and solves.
 #include <algorithm>
+#include <atomic>
 #include <complex>
 #include <cmath>
 #include <cstdio>
@@ -29,6 +30,8 @@ template <typename VT>
 void kr_scale_run(cx<VT> *Vdst, const cx<double> *w, const double *nrm, int64_t N, const KrRun &run, hipStream_t s);
 size_t kr_ortho_part_entries(int jn_max, int nsys);
 size_t kr_ortho_npart_entries(int64_t N, int nsys);
+void kr_publish(const cx<double> *src, cx<double> *dst, int nnrm, int ncol, int stride, int rows, unsigned *flag,
+                unsigned seq, hipStream_t s);
 void kr_residual(const cx<double> *b, cx<double> *r, int64_t N, hipStream_t s);
 void kr_axpy(cx<double> *x, const cx<double> *d, int64_t N, hipStream_t s);
 void kr_finite(const double *v, int64_t n, int *bad, hipStream_t s);
@@ -179,10 +182,13 @@ struct scabs_ctx {
   double prof_bytes[SCABS_NSTAGES] = {};   // per stage, last finished session
   double *nrm = nullptr, *nrm_part = nullptr, *npart = nullptr;
   // nrm (KR_NRM entries) followed by hcol in one device block, mirrored in
-  // pinned host memory, so each Arnoldi step reads both back in one copy
+  // mapped, coherent host memory that a kernel writes at the end of each
+  // Arnoldi step, followed by a sequence number the host waits for
   cx<double> *hblock = nullptr;
-  cx<double> *hpin = nullptr;
+  cx<double> *hpin = nullptr, *hpin_dev = nullptr;
   size_t hpin_entries = 0;
+  unsigned *hflag = nullptr, *hflag_dev = nullptr;
+  unsigned hseq = 0;
   hipEvent_t ev_read = nullptr;   // end of a step's read-back (no timing)
   int *flag = nullptr;
 };
@@ -982,16 +988,29 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
 // together: one batched preconditioner + product per Arnoldi step,
 // per-system orthogonalisation, one host synchronisation per step for all of
 // them (two when a system needs the second pass).
-// ---------------------------------------------------------------------------
-// Wait for the work enqueued so far on s by polling an event (the host
-// spins instead of sleeping; used once per Arnoldi step)
-static void wait_polling(scabs_ctx *c, hipStream_t s) {
+// Read back the norms and the first `rows` entries of every Hessenberg column
+// block (2 nb blocks of `stride` entries) into the mapped host copy and wait
+// for them: the publishing kernel sets the host flag to a new sequence
+// number after its stores.  The host spins on the flag; an event after the
+// kernel bounds the wait (a finished or failed stream ends it).
+static void read_back(scabs_ctx *c, hipStream_t s, size_t nnrm, int nb, int stride, int rows) {
+  const unsigned seq = ++c->hseq;
+  kr_publish(c->hblock, c->hpin_dev, (int)nnrm, 2 * nb, stride, rows, c->hflag_dev, seq, s);
   if (!c->ev_read) HIPCHK(hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
   HIPCHK(hipEventRecord(c->ev_read, s));
-  hipError_t e;
-  while ((e = hipEventQuery(c->ev_read)) == hipErrorNotReady) {
+  const volatile unsigned *f = c->hflag;
+  for (unsigned spin = 1;; spin++) {
+    if (*f == seq) break;
+    if ((spin & 16383) == 0) {
+      const hipError_t e = hipEventQuery(c->ev_read);
+      if (e == hipSuccess) {
+        if (*f == seq) break;
+        throw std::string("Arnoldi read-back: the stream finished without setting the host flag");
+      }
+      if (e != hipErrorNotReady) throw HipError{e, "hipEventQuery"};
+    }
   }
-  if (e != hipSuccess) throw HipError{e, "hipEventQuery"};
+  std::atomic_thread_fence(std::memory_order_acquire);
 }
 
 // complex entries in front of the Hessenberg columns that hold the norms
@@ -1012,8 +1031,15 @@ static void ensure_work(scabs_ctx *c, int restart, int nb) {
   c->hcol = c->hblock + KR_NRM;
   if (c->hpin) HIPCHK(hipHostFree(c->hpin));
   c->hpin = nullptr;
-  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(cx<double>) * hentries, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(cx<double>) * hentries, hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCHK(hipHostGetDevicePointer((void **)&c->hpin_dev, c->hpin, 0));
   c->hpin_entries = hentries;
+  if (!c->hflag) {
+    HIPCHK(hipHostMalloc((void **)&c->hflag, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&c->hflag_dev, c->hflag, 0));
+    *(volatile unsigned *)c->hflag = 0;
+    c->hseq = 0;
+  }
   c->part = c->work.alloc<cx<double>>(std::max((size_t)256 * (restart + 2), kr_ortho_part_entries(restart + 1, nb)));
   c->npart = c->work.alloc<double>(kr_ortho_npart_entries(N, nb));
   c->nrm_part = c->work.alloc<double>(1024);
@@ -1089,8 +1115,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       cs(nb, std::vector<zd>(m)), sn(nb, std::vector<zd>(m));
   std::vector<int> jb(nb);
   // Hessenberg columns of the running step (both passes), read in place in
-  // the pinned copy of the device block: system b's at hb + 2 (m + 2) b
-  const size_t hb_size = 2 * (size_t)(m + 2) * nb;
+  // the mapped host copy of the device block: system b's at hb + 2 (m + 2) b
   const cx<double> *const hb = c->hpin + KR_NRM;
   while (true) {
     std::vector<int> act;
@@ -1148,10 +1173,10 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       // v_{j+1} = w / ||w|| before the read-back (redone below for systems
       // that take a second pass)
       kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(run), s);
-      // norms and Hessenberg columns in one copy to pinned memory, waited for
-      // by polling its event (a blocking wait wakes the host up later)
-      HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb_size), hipMemcpyDeviceToHost, s));
-      wait_polling(c, s);
+      // norms and Hessenberg columns written into mapped host memory by one
+      // kernel, waited for by spinning on its flag (a blocking wait wakes the
+      // host up later, a copy adds a blit and its own latency)
+      read_back(c, s, KR_NRM, nb, m + 2, j + 1);
       std::copy((const double *)c->hpin, (const double *)c->hpin + 2 * nb, hn.begin());
       std::vector<int> reo;
       for (int b : run) {
@@ -1166,9 +1191,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
         }
         for (int b : reo) reo2[b] = 1;
         // the block again: the second pass's columns beside the unchanged first ones
-        HIPCHK(hipMemcpyAsync(c->hpin, c->hblock, sizeof(cx<double>) * (KR_NRM + hb_size), hipMemcpyDeviceToHost,
-                              s));
-        HIPCHK(hipStreamSynchronize(s));
+        read_back(c, s, KR_NRM, nb, m + 2, j + 1);
         std::copy((const double *)c->hpin, (const double *)c->hpin + nb, hn.begin());
         kr_scale_run(V + (size_t)(j + 1) * ldv, c->w, c->nrm, N, to_run(reo), s);
       }
@@ -1732,6 +1755,7 @@ void scabs_destroy(scabs_ctx *c) {
   c->workV32.release();
   c->mem.release();
   if (c->hpin) hipHostFree(c->hpin);
+  if (c->hflag) hipHostFree(c->hflag);
   if (c->ev_read) hipEventDestroy(c->ev_read);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);

@@ -352,6 +352,28 @@ void kr_scale_run(cx<VT> *Vdst, const cx<double> *w, const double *nrm, int64_t 
   if (run.n == 0) return;
   hipLaunchKernelGGL(og_scale<VT>, dim3(reduce_blocks(N), run.n), dim3(KR_THREADS), 0, s, Vdst, w, nrm, N, run);
 }
+// Read-back of one Arnoldi step into mapped, coherent host memory: the norm
+// entries [0, nnrm) and, per column block k < ncol (stride entries apart,
+// after the norms), its first rows entries; then, once every thread's stores
+// are visible system-wide, flag = seq.  One work-group.
+__global__ void kr_publish_kernel(const cx<double> *__restrict__ src, cx<double> *dst, int nnrm, int ncol,
+                                  int stride, int rows, unsigned *flag, unsigned seq) {
+  for (int t = threadIdx.x; t < nnrm; t += blockDim.x) dst[t] = src[t];
+  const int total = ncol * rows;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int k = t / rows, i = t - k * rows;
+    const size_t at = (size_t)nnrm + (size_t)k * stride + i;
+    dst[at] = src[at];
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+void kr_publish(const cx<double> *src, cx<double> *dst, int nnrm, int ncol, int stride, int rows, unsigned *flag,
+                unsigned seq, hipStream_t s) {
+  hipLaunchKernelGGL(kr_publish_kernel, dim3(1), dim3(256), 0, s, src, dst, nnrm, ncol, stride, rows, flag, seq);
+}
+
 size_t kr_ortho_part_entries(int jn_max, int nsys) { return (size_t)OG_BLOCKS * (jn_max + 1) * nsys; }
 size_t kr_ortho_npart_entries(int64_t N, int nsys) { return (size_t)reduce_blocks(N) * nsys; }
 template void kr_ortho_pass<float>(const cx<float> *, int64_t, int, cx<double> *, int64_t, const KrRun &, int,
