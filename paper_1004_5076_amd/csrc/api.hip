@@ -8,6 +8,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -610,7 +611,7 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
     launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
                          c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, x, y, c->pc_max_ext, c->stream);
   else
-    launch_precond_apply_t(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
+    launch_precond_apply_t<double>(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
                            c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, c->pc_xc, x, y,
                            c->stream);
 }
@@ -953,16 +954,19 @@ static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec,
 
 // prec: precision of the products the preconditioner feeds (FP32 inner solves
 // use the batched single-precision apply)
-static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, int nb, bool trans, int prec) {
+// x: nb vectors of N, FP64, or FP32 (the inner solves' basis, read directly
+// by the gathers of the FP32 apply and of the transposed apply)
+template <typename TI>
+static void apply_precond_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb, bool trans, int prec) {
   const size_t N = (size_t)c->lay.N;
   if (!trans && prec == SCABS_FP32) {
     const int B = precond_apply32_max_batch();
     for (int b0 = 0; b0 < nb; b0 += B) {
       const int m = std::min(B, nb - b0);
       {
-        // per ext entry its index and column scale, m FP64 inputs read and m
-        // FP32 copies written
-        StageTimer tm(c, SCABS_STAGE_PCGATHER32, (8.0 + 24.0 * m) * (double)c->pc_n_ext);
+        // per ext entry its index and column scale, m inputs read and m FP32
+        // copies written
+        StageTimer tm(c, SCABS_STAGE_PCGATHER32, (8.0 + (2.0 * sizeof(TI) + 8.0) * m) * (double)c->pc_n_ext);
         launch_precond_gather32(c->pc_n_ext, c->pc_ext_slot, c->pc_Rs, x + b0 * N, (int64_t)N, m, c->pc_xe,
                                 c->stream);
       }
@@ -976,18 +980,19 @@ static void apply_precond_n(scabs_ctx *c, const cx<double> *x, cx<double> *y, in
     }
     return;
   }
-  for (int k = 0; k < nb; k++) apply_precond(c, x + k * N, y + k * N, trans);
+  if constexpr (std::is_same<TI, double>::value) {
+    for (int k = 0; k < nb; k++) apply_precond(c, x + k * N, y + k * N, trans);
+  } else {
+    if (!trans) throw std::string("the FP64 Schwarz apply takes FP64 inputs");
+    for (int k = 0; k < nb; k++) {
+      StageTimer tm(c, SCABS_STAGE_PRECOND_T);
+      launch_precond_apply_t<TI>(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr,
+                                 c->pc_core_slot, c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr,
+                                 c->pc_inv_pos, c->pc_tmp, c->pc_xc, x + k * N, y + k * N, c->stream);
+    }
+  }
 }
 
-// ---------------------------------------------------------------------------
-// GMRES on a batch of right-hand sides (restarted; classical Gram-Schmidt
-// with a second pass where the first lost more than 1 - 1/sqrt(2) of the
-// vector's norm, Givens rotations; sums and rotations in FP64, the basis
-// stored in FP64, or in FP32 for the single-precision inner solves, whose
-// tolerance is 1e-5 or looser and whose correction an FP64 residual checks).  The nb systems step
-// together: one batched preconditioner + product per Arnoldi step,
-// per-system orthogonalisation, one host synchronisation per step for all of
-// them (two when a system needs the second pass).
 // Read back the norms and the first `rows` entries of every Hessenberg column
 // block (2 nb blocks of `stride` entries) into the mapped host copy and wait
 // for them: the publishing kernel sets the host flag to a new sequence
@@ -1095,6 +1100,15 @@ static const cx<double> *operator_input(scabs_ctx *c, const cx<float> *v, int64_
   return c->t;
 }
 
+// ---------------------------------------------------------------------------
+// GMRES on a batch of right-hand sides (restarted; classical Gram-Schmidt
+// with a second pass where the first lost more than 1 - 1/sqrt(2) of the
+// vector's norm, Givens rotations; sums and rotations in FP64, the basis
+// stored in FP64, or in FP32 for the single-precision inner solves, whose
+// tolerance is 1e-5 or looser and whose correction an FP64 residual checks).  The nb systems step
+// together: one batched preconditioner + product per Arnoldi step,
+// per-system orthogonalisation, one host synchronisation per step for all of
+// them (two when a system needs the second pass).
 template <typename VT>
 static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> *sol, int prec, const double *tol,
                         int max_iter, int restart, int &nmv, bool trans, std::vector<GmresResult> &res) {
@@ -1140,11 +1154,13 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     // w = A M v_j for every vector of the batch (the batched stages take all
     // nb vectors; only the orthogonalisation is restricted to running systems)
     auto enqueue_product = [&](int jj) {
-      const cx<double> *vj = operator_input(c, V + (size_t)jj * ldv, ldv);
       if (c->has_pc) {
-        apply_precond_n(c, vj, c->z, nb, trans, prec);
+        // the preconditioner's gathers read the basis vectors in their own
+        // precision (no widened copy)
+        apply_precond_n(c, V + (size_t)jj * ldv, c->z, nb, trans, prec);
         matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
       } else {
+        const cx<double> *vj = operator_input(c, V + (size_t)jj * ldv, ldv);
         matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
       }
     };

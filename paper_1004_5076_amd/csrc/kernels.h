@@ -182,7 +182,8 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
 // (cluster, first core row) pairs in dispatch order (work-group i runs entry
 // i; cluster -1 marks an empty entry).
 int precond_apply32_max_batch();
-void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<double> *x, int64_t N,
+template <typename TI>   // double or float inputs
+void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<TI> *x, int64_t N,
                              int m, cx<float> *xe, hipStream_t s);
 void launch_precond_apply32(int n_items, const int *items, const int64_t *ext_ptr, const int64_t *core_ptr,
                             const int *core_slot, const int64_t *r_off, const uint32_t *R, const cx<float> *xe,
@@ -203,10 +204,11 @@ void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y
 // items: (cluster, first ext column) per work-group, precond_t_cols_per_item() columns each, in
 // dispatch order (work-group i runs entry i; cluster -1 marks an empty entry)
 int precond_t_cols_per_item();
+template <typename TI>   // double or float inputs x
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, cx<double> *xc,
-                            const cx<double> *x, cx<double> *y, hipStream_t s);
+                            const cx<TI> *x, cx<double> *y, hipStream_t s);
 void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &ext, const DevGrid<double> *ints_dev,
                          double inv_h, cx<double> *Ee, cx<double> *Ei, hipStream_t s);
 void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, const cx<double> *Ei,

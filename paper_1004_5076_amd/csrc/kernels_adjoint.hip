@@ -546,10 +546,15 @@ constexpr int PT_WCOLS = PT_COLS / (PT_THREADS / 64);   // columns per wave
 static_assert(PT_WCOLS == 8, "the wave reduction below is written for 8 columns (16 values)");
 int precond_t_cols_per_item() { return PT_COLS; }
 
-__global__ void precond_t_gather_kernel(int64_t n, const int *__restrict__ core_slot, const cx<double> *__restrict__ x,
+// x in FP64, or in FP32 straight from the inner solves' basis (widened here)
+template <typename TI>
+__global__ void precond_t_gather_kernel(int64_t n, const int *__restrict__ core_slot, const cx<TI> *__restrict__ x,
                                         cx<double> *__restrict__ xc) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) xc[p] = x[core_slot[p]];
+  if (p < n) {
+    const cx<TI> v = x[core_slot[p]];
+    xc[p] = {(double)v.x, (double)v.y};
+  }
 }
 
 __global__ void __launch_bounds__(PT_THREADS)
@@ -618,18 +623,27 @@ __global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_
 }
 
 // xc: N entries of work space (x in core order)
+template <typename TI>
 void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, cx<double> *xc,
-                            const cx<double> *x, cx<double> *y, hipStream_t s) {
+                            const cx<TI> *x, cx<double> *y, hipStream_t s) {
   if (N == 0) return;
-  hipLaunchKernelGGL(precond_t_gather_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, core_slot, x, xc);
+  hipLaunchKernelGGL(precond_t_gather_kernel<TI>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, core_slot, x,
+                     xc);
   if (n_items > 0)
     hipLaunchKernelGGL(precond_t_dots_kernel, dim3(n_items), dim3(PT_THREADS), 0, s, items, ext_ptr, core_ptr, r_off,
                        pc, (const cx<double> *)xc, tmp);
   hipLaunchKernelGGL(precond_t_sum_kernel, dim3(1024), dim3(256), 0, s, N, inv_ptr, inv_pos, (const cx<double> *)tmp,
                      y);
 }
+#define SCABS_APPLY_T(TI)                                                                                         \
+  template void launch_precond_apply_t<TI>(int, const int *, int64_t, const int64_t *, const int64_t *, const int *, \
+                                           const int64_t *, PcStore, const int64_t *, const int64_t *, cx<double> *,  \
+                                           cx<double> *, const cx<TI> *, cx<double> *, hipStream_t);
+SCABS_APPLY_T(double)
+SCABS_APPLY_T(float)
+#undef SCABS_APPLY_T
 
 // ---------------------------------------------------------------------------
 // pointwise one-sided fields of the grid part (FP64) at every test point:

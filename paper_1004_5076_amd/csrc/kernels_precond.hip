@@ -453,14 +453,17 @@ void launch_precond_apply(int n_items, const int *items, const int64_t *ext_ptr,
 constexpr int PA32_Q = 8;
 constexpr int PA32_THREADS = PA_ROWS * PA32_Q;
 
+// inputs in FP64, or in FP32 straight from the inner solves' basis (the same
+// values: FP32 to FP64 is exact)
+template <typename TI>
 __global__ void precond_gather32_kernel(int64_t n_ext, int m, const int *__restrict__ ext_slot,
-                                        const float *__restrict__ scale, const cx<double> *__restrict__ x, int64_t N,
+                                        const float *__restrict__ scale, const cx<TI> *__restrict__ x, int64_t N,
                                         cx<float> *__restrict__ xe) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_ext * m) return;
   const int64_t e = t / m;
   const int b = (int)(t - e * m);
-  const cx<double> v = x[(size_t)b * N + ext_slot[e]];
+  const cx<TI> v = x[(size_t)b * N + ext_slot[e]];
   const float sc = scale[e];
   xe[t] = {(float)v.x * sc, (float)v.y * sc};
 }
@@ -636,14 +639,19 @@ precond_apply32_mfma_kernel(const int *__restrict__ items, const int64_t *__rest
 
 int precond_apply32_max_batch() { return 8; }
 
-void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<double> *x, int64_t N,
+template <typename TI>
+void launch_precond_gather32(int64_t n_ext, const int *ext_slot, const float *scale, const cx<TI> *x, int64_t N,
                              int m, cx<float> *xe, hipStream_t s) {
   const int64_t total = n_ext * m;
   if (total == 0) return;
   const int threads = 256;
-  hipLaunchKernelGGL(precond_gather32_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s,
-                     n_ext, m, ext_slot, scale, x, N, xe);
+  hipLaunchKernelGGL(precond_gather32_kernel<TI>, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0,
+                     s, n_ext, m, ext_slot, scale, x, N, xe);
 }
+template void launch_precond_gather32<double>(int64_t, const int *, const float *, const cx<double> *, int64_t, int,
+                                              cx<float> *, hipStream_t);
+template void launch_precond_gather32<float>(int64_t, const int *, const float *, const cx<float> *, int64_t, int,
+                                             cx<float> *, hipStream_t);
 
 template <int NB>
 static void apply32_launch(int n_items, const int *items, const int64_t *ext_ptr, const int64_t *core_ptr,
