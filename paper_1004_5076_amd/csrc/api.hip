@@ -190,7 +190,6 @@ struct scabs_ctx {
   size_t hpin_entries = 0;
   unsigned *hflag = nullptr, *hflag_dev = nullptr;
   unsigned hseq = 0;
-  hipEvent_t ev_read = nullptr;   // end of a step's read-back (no timing)
   int *flag = nullptr;
 };
 
@@ -996,23 +995,22 @@ static void apply_precond_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb
 // Read back the norms and the first `rows` entries of every Hessenberg column
 // block (2 nb blocks of `stride` entries) into the mapped host copy and wait
 // for them: the publishing kernel sets the host flag to a new sequence
-// number after its stores.  The host spins on the flag; an event after the
-// kernel bounds the wait (a finished or failed stream ends it).
+// number after its stores.  The host spins on the flag; nothing is enqueued
+// behind the publishing kernel before the flag is seen, so an idle stream
+// without the flag (or a stream error) ends the wait with an error.
 static void read_back(scabs_ctx *c, hipStream_t s, size_t nnrm, int nb, int stride, int rows) {
   const unsigned seq = ++c->hseq;
   kr_publish(c->hblock, c->hpin_dev, (int)nnrm, 2 * nb, stride, rows, c->hflag_dev, seq, s);
-  if (!c->ev_read) HIPCHK(hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(c->ev_read, s));
   const volatile unsigned *f = c->hflag;
   for (unsigned spin = 1;; spin++) {
     if (*f == seq) break;
     if ((spin & 16383) == 0) {
-      const hipError_t e = hipEventQuery(c->ev_read);
+      const hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
         if (*f == seq) break;
         throw std::string("Arnoldi read-back: the stream finished without setting the host flag");
       }
-      if (e != hipErrorNotReady) throw HipError{e, "hipEventQuery"};
+      if (e != hipErrorNotReady) throw HipError{e, "hipStreamQuery"};
     }
   }
   std::atomic_thread_fence(std::memory_order_acquire);
@@ -1772,7 +1770,6 @@ void scabs_destroy(scabs_ctx *c) {
   c->mem.release();
   if (c->hpin) hipHostFree(c->hpin);
   if (c->hflag) hipHostFree(c->hflag);
-  if (c->ev_read) hipEventDestroy(c->ev_read);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
