@@ -149,7 +149,7 @@ def main():
                          "size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; runs on several GPUs are not supported", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

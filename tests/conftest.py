@@ -13,7 +13,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests are skipped (not failed) where no GPU is visible; on a GPU machine a
+    # GPU tests are skipped (not failed) where no GPU is visible; with a GPU a
     # missing library fails loudly inside the tests themselves.
     try:
         import torch
