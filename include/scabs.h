@@ -89,7 +89,9 @@ typedef struct {
   int status;              /* SCABS_OK or SCABS_E_NOCONV */
   int outer_iters;         /* refinement steps (MIXED) or restart cycles (FP64) */
   int inner_iters;         /* total Arnoldi steps */
-  int matvecs64, matvecs32;
+  int matvecs64, matvecs32; /* operator products this system's iteration used (the
+                              batched launches compute every vector of the batch,
+                              including systems that have already converged) */
   double rel_residual;     /* final ||b - A x|| / ||b|| with the FP64 operator */
 } scabs_solve_info;
 

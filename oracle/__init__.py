@@ -536,28 +536,55 @@ def lu_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     return sla.lu_solve((lu, piv), b)
 
 
-def gmres_dense(A: np.ndarray, b: np.ndarray, tol: float = 1e-10) -> np.ndarray:
-    """Full (unrestarted) GMRES on the dense matrix, Arnoldi with modified
-    Gram-Schmidt and a least-squares solve of the Hessenberg system."""
+def gmres_dense(A: np.ndarray, b: np.ndarray, tol: float = 1e-10, max_steps: Optional[int] = None) -> np.ndarray:
+    """Full (unrestarted) GMRES on the dense matrix (the solver the paper
+    names for eq19): Arnoldi with classical Gram-Schmidt applied twice,
+    Givens rotations on the Hessenberg matrix, stop when the updated residual
+    norm is at most tol ||b||, then solve the triangular system."""
     n = A.shape[0]
+    m = n if max_steps is None else min(n, max_steps)
     beta = np.linalg.norm(b)
-    V = np.zeros((n, min(n, 2000) + 1), complex)
-    Hm = np.zeros((V.shape[1], V.shape[1] - 1), complex)
+    V = np.zeros((n, m + 1), complex)
+    R = np.zeros((m + 1, m), complex)
+    cs = np.zeros(m, complex)
+    sn = np.zeros(m, complex)
+    g = np.zeros(m + 1, complex)
+    g[0] = beta
     V[:, 0] = b / beta
-    for j in range(V.shape[1] - 1):
+    j = 0
+    for j in range(m):
         w = A @ V[:, j]
-        for i in range(j + 1):
-            Hm[i, j] = np.vdot(V[:, i], w)
-            w = w - Hm[i, j] * V[:, i]
-        Hm[j + 1, j] = np.linalg.norm(w)
-        e1 = np.zeros(j + 2, complex)
-        e1[0] = beta
-        y, *_ = np.linalg.lstsq(Hm[: j + 2, : j + 1], e1, rcond=None)
-        res = np.linalg.norm(Hm[: j + 2, : j + 1] @ y - e1) / beta
-        if res < tol or Hm[j + 1, j] == 0:
-            return V[:, : j + 1] @ y
-        V[:, j + 1] = w / Hm[j + 1, j]
-    return V[:, : V.shape[1] - 1] @ y
+        h = V[:, : j + 1].conj().T @ w
+        w = w - V[:, : j + 1] @ h
+        h2 = V[:, : j + 1].conj().T @ w
+        w = w - V[:, : j + 1] @ h2
+        col = np.zeros(j + 2, complex)
+        col[: j + 1] = h + h2
+        col[j + 1] = np.linalg.norm(w)
+        for i in range(j):
+            a, c = col[i], col[i + 1]
+            col[i] = cs[i] * a + sn[i] * c
+            col[i + 1] = -np.conj(sn[i]) * a + cs[i] * c
+        den = math.hypot(abs(col[j]), abs(col[j + 1]))
+        if den == 0:
+            cs[j], sn[j] = 1.0, 0.0
+        elif col[j] == 0:
+            cs[j], sn[j] = 0.0, np.conj(col[j + 1]) / abs(col[j + 1])
+        else:
+            cs[j] = abs(col[j]) / den
+            sn[j] = (col[j] / abs(col[j])) * np.conj(col[j + 1]) / den
+        hn = col[j + 1]
+        col[j] = cs[j] * col[j] + sn[j] * col[j + 1]
+        col[j + 1] = 0
+        R[: j + 2, j] = col
+        g[j + 1] = -np.conj(sn[j]) * g[j]
+        g[j] = cs[j] * g[j]
+        if abs(g[j + 1]) <= tol * beta or hn == 0:
+            break
+        V[:, j + 1] = w / hn
+    k = j + 1
+    y = sla.solve_triangular(R[:k, :k], g[:k])
+    return V[:, :k] @ y
 
 
 def monitor_weights(xs: np.ndarray, beta: float) -> np.ndarray:

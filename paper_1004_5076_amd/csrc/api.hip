@@ -232,6 +232,25 @@ static int hip_fail(scabs_ctx *c, const HipError &e) {
   return fail(c, SCABS_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
 }
 
+// every exception a call can raise becomes a status code: none crosses the ABI
+#define SCABS_CATCH(c)                                                             \
+  catch (const HipError &e) {                                                      \
+    if (e.e == hipErrorOutOfMemory) return fail(c, SCABS_E_OOM, "device allocation failed"); \
+    return hip_fail(c, e);                                                         \
+  }                                                                                \
+  catch (const std::bad_alloc &) {                                                 \
+    return fail(c, SCABS_E_OOM, "host allocation failed");                         \
+  }                                                                                \
+  catch (const std::exception &e) {                                                \
+    return fail(c, SCABS_E_HIP, e.what());                                         \
+  }                                                                                \
+  catch (const std::string &m) {                                                   \
+    return fail(c, SCABS_E_STATE, m);                                              \
+  }                                                                                \
+  catch (...) {                                                                    \
+    return fail(c, SCABS_E_HIP, "unexpected exception");                           \
+  }
+
 // ---------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------
@@ -1008,7 +1027,7 @@ static void read_back(scabs_ctx *c, hipStream_t s, size_t nnrm, int nb, int stri
       const hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
         if (*f == seq) break;
-        throw std::string("Arnoldi read-back: the stream finished without setting the host flag");
+        throw HipError{hipErrorLaunchFailure, "Arnoldi read-back: the stream finished without setting the host flag"};
       }
       if (e != hipErrorNotReady) throw HipError{e, "hipStreamQuery"};
     }
@@ -1109,7 +1128,7 @@ static const cx<double> *operator_input(scabs_ctx *c, const cx<float> *v, int64_
 // them (two when a system needs the second pass).
 template <typename VT>
 static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> *sol, int prec, const double *tol,
-                        int max_iter, int restart, int &nmv, bool trans, std::vector<GmresResult> &res) {
+                        int max_iter, int restart, std::vector<int> &nmv, bool trans, std::vector<GmresResult> &res) {
   typedef std::complex<double> zd;
   hipStream_t s = c->stream;
   const int64_t N = c->lay.N;
@@ -1117,6 +1136,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
   cx<VT> *const V = basis(c, restart, nb, (cx<VT> *)nullptr);
   const int64_t ldv = N * nb;   // V[j][b] at V + (j nb + b) N
   res.assign(nb, GmresResult());
+  nmv.assign(nb, 0);
   HIPCHK(hipMemsetAsync(sol, 0, sizeof(cx<double>) * N * nb, s));
   HIPCHK(hipMemcpyAsync(c->r, rhs, sizeof(cx<double>) * N * nb, hipMemcpyDeviceToDevice, s));
   std::vector<double> bn(nb), beta(nb), hn(2 * nb);
@@ -1168,7 +1188,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     while (j < m && !run.empty()) {
       if (!pending) enqueue_product(j);
       pending = false;
-      nmv += (int)run.size();
+      for (int b : run) nmv[b]++;
       // classical Gram-Schmidt, repeated only where it lost too much of w
       // (Daniel-Gragg-Kaufman-Stewart test ||w1|| < ||w|| / sqrt(2)); one
       // set of launches for all running systems
@@ -1277,7 +1297,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     }
     // true residuals
     matvec_n(c, (const double *)sol, (double *)c->w, nb, prec, trans);
-    nmv += (int)act.size();
+    for (int b : act) nmv[b]++;
     for (int b : act) {
       HIPCHK(hipMemcpyAsync(c->r + b * N, rhs + b * N, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
       kr_residual((const cx<double> *)(c->r + b * N), c->w + b * N, N, s);   // w = rhs - A sol
@@ -1332,7 +1352,7 @@ static int solve_batch(scabs_ctx *c, int nb, const cx<double> *b, cx<double> *x,
       min_left = std::min(min_left, max_iter - loc[k].inner_iters);
       HIPCHK(hipMemcpyAsync(rhs + a * N, rr + k * N, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
     }
-    int nmv = 0;
+    std::vector<int> nmv;
     std::vector<GmresResult> g;
     if (inner_prec == SCABS_FP32)
       gmres_batch<float>(c, na, rhs, corr, inner_prec, tin.data(), min_left, restart, nmv, trans, g);
@@ -1341,9 +1361,9 @@ static int solve_batch(scabs_ctx *c, int nb, const cx<double> *b, cx<double> *x,
     for (int a = 0; a < na; a++) {
       const int k = act[a];
       if (inner_prec == SCABS_FP32)
-        loc[k].matvecs32 += nmv / na;
+        loc[k].matvecs32 += nmv[a];
       else
-        loc[k].matvecs64 += nmv / na;
+        loc[k].matvecs64 += nmv[a];
       loc[k].inner_iters += g[a].iters;
       loc[k].outer_iters++;
       kr_axpy(x + k * N, corr + a * N, N, s);
@@ -1505,9 +1525,8 @@ int scabs_rhs_dipole(scabs_ctx *c, const double pos[3], const double moment[6], 
                       c->Z_i, pos, moment, body, b, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1519,9 +1538,8 @@ static int do_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int pre
     matvec_n(c, x, y, nrhs, prec, trans);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1543,9 +1561,8 @@ int scabs_precond_apply(scabs_ctx *c, const double *x, double *y, int nrhs, int 
     apply_precond_n(c, (const cx<double> *)x, (cx<double> *)y, nrhs, transpose != 0, prec);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1574,9 +1591,8 @@ static int do_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double t
     }
     if (worst != SCABS_OK) c->err = "GMRES did not reach the tolerance within max_iter";
     return worst;
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
 }
 
 int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart, int mode,
@@ -1598,9 +1614,8 @@ int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double
                            (cx<double> *)E, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1628,9 +1643,8 @@ int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei) {
   try {
     point_fields(c, x, (cx<double> *)Ee, (cx<double> *)Ei);
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1647,9 +1661,8 @@ int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts,
     launch_eval_field(c->p64.op, c->qp64, p, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1665,9 +1678,8 @@ int scabs_eval_field_transpose(scabs_ctx *c, const double *pts, int npts, int re
     launch_eval_field_t(c->p64.op, c->qp64, p, npts, region, k, Z, (const cx<double> *)wE, y, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 
@@ -1708,9 +1720,8 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
         for (int64_t t = jp[q]; t < jp[q + 1]; t++) g[jk[t]] += jv[t] * h[q];
       std::memcpy(dfdparam, g.data(), npar * sizeof(double));
     }
-  } catch (const HipError &e) {
-    return hip_fail(c, e);
   }
+  SCABS_CATCH(c)
   return SCABS_OK;
 }
 

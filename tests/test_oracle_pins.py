@@ -366,3 +366,71 @@ def test_pfft_rejects_small_near_radius(small):
     w, o = small
     with pytest.raises(ValueError):
         o.pfft(0.05, 0.5 * o.singular_radius())
+
+
+# ---------------------------------------------------------------------------
+# the absorber profile (Sec. IV, eq60) and the dense GMRES solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 4])
+def test_sigma_monomial_profile(degree):
+    """sigma = sigma0 s^d with s = dir (x - x0)/L: zero before the absorber,
+    sigma0 beyond its end, and inside exactly the monomial of degree d
+    (a least-squares polynomial fit in s recovers sigma0 at degree d and
+    nothing else); both directions."""
+    w = synth.workload_small(edge=0.2, length=3.0)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    x = o.qp[:, 0]
+    for direction, x0 in ((+1, 1.7), (-1, 1.3)):
+        sig0, L = 0.83, 0.9
+        o.set_sigma([synth.SigmaEnd(axis=0, x0=x0, length=L, direction=direction, degree=degree, sigma0=sig0)])
+        s = direction * (x - x0) / L
+        before, inside, after = s < 0, (s > 0) & (s < 1), s > 1
+        assert np.all(o.sigma[before] == 0)
+        assert np.allclose(o.sigma[after], sig0, rtol=0, atol=1e-15)
+        coef = np.polynomial.polynomial.polyfit(s[inside], o.sigma[inside], 5)
+        want = np.zeros(6)
+        want[degree] = sig0
+        assert np.allclose(coef, want, atol=1e-9), coef
+        assert inside.sum() > 20
+
+
+def test_sigma_piecewise_linear_profile():
+    """Piecewise-linear profile: the hat-function interpolant of the control
+    values at s_k = k/(n-1), i.e. numpy's linear interpolation; held at the
+    last control value beyond the end, zero before the start; two absorbers
+    add."""
+    w = synth.workload_small(edge=0.2, length=3.0)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    x = o.qp[:, 0]
+    ctrl = synth.random_uniform(31, 9, 0.0, 2.0)
+    ctrl2 = synth.random_uniform(32, 5, 0.0, 1.0)
+    e1 = synth.SigmaEnd(axis=0, x0=2.0, length=0.8, direction=+1, ctrl=ctrl)
+    e2 = synth.SigmaEnd(axis=0, x0=1.2, length=1.0, direction=-1, ctrl=ctrl2)
+    o.set_sigma([e1, e2])
+    s1 = (x - 2.0) / 0.8
+    s2 = -(x - 1.2) / 1.0
+    ref = np.where(s1 >= 0, np.interp(np.clip(s1, 0, 1), np.linspace(0, 1, 9), ctrl), 0.0)
+    ref += np.where(s2 >= 0, np.interp(np.clip(s2, 0, 1), np.linspace(0, 1, 5), ctrl2), 0.0)
+    assert np.allclose(o.sigma, ref, rtol=0, atol=1e-14)
+    # its Jacobian with respect to the control values is the hat basis
+    J = o.pwl_jacobian(e1)
+    for k in range(9):
+        e = np.zeros(9)
+        e[k] = 1.0
+        hat = np.where(s1 >= 0, np.interp(np.clip(s1, 0, 1), np.linspace(0, 1, 9), e), 0.0)
+        assert np.allclose(J[:, k], hat, rtol=0, atol=1e-14)
+
+
+def test_gmres_dense_matches_lu():
+    """Unrestarted GMRES on the dense matrix (configuration 0's solver)
+    reaches the LU solution: residual 1e-11, solution to 1e-7."""
+    w = synth.workload_small(length=2.0, absorber=1.0)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    A = o.dense()
+    b = o.rhs_dipole(w.dipoles[0])
+    x_lu = oracle.lu_solve(A, b)
+    x_g = oracle.gmres_dense(A, b, tol=1e-11)
+    assert np.linalg.norm(A @ x_g - b) < 2e-11 * np.linalg.norm(b)
+    assert np.linalg.norm(x_g - x_lu) < 1e-7 * np.linalg.norm(x_lu)
