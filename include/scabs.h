@@ -119,6 +119,13 @@ int scabs_sigma_clear(scabs_ctx *c);
 int scabs_sigma_add_monomial(scabs_ctx *c, int axis, double x0, double length, int dir, int degree,
                              double sigma0);
 int scabs_sigma_add_pwl(scabs_ctx *c, int axis, double x0, double length, int dir, int n, const double *ctrl);
+/* Raw conductivity at every quadrature point (host array, copied): nq must be
+ * 7 n_tris of the mesh set before (points triangle by triangle, in the order
+ * of the seven-point rule: centroid, then the two orbits of three), values
+ * >= 0, added to the profile ends.  A later call replaces the earlier values;
+ * scabs_sigma_clear removes them.  For scabs_sigma_gradient the nq values are
+ * nq parameters, placed in the order the call was made among the ends. */
+int scabs_set_sigma_points(scabs_ctx *c, const double *sigma_q, int64_t nq);
 
 /* Build everything the products need: RWG edges, quadrature points, unknown
  * layout, grids, near list, exact and grid near-pair interactions (FP64 on the

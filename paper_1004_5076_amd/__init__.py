@@ -23,7 +23,7 @@ SCABS_OK = 0
 SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCONV, SCABS_E_NAN = -1, -2, -3, -4, -5, -6, -7
 SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
-            "scabs_sigma_add_pwl", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
+            "scabs_sigma_add_pwl", "scabs_set_sigma_points", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
@@ -97,6 +97,7 @@ def load() -> C.CDLL:
     L.scabs_incident_dipole_points.argtypes = [P, dp, dp, C.c_int, P]
     L.scabs_point_fields.argtypes = [P, P, P, P]
     L.scabs_eval_field.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
+    L.scabs_set_sigma_points.argtypes = [P, dp, C.c_int64]
     L.scabs_eval_field_transpose.argtypes = [P, dp, C.c_int, C.c_int, P, P]
     L.scabs_sigma_params.argtypes = [P, C.POINTER(C.c_int64)]
     L.scabs_sigma_gradient.argtypes = [P, P, P, P, P, dp]
@@ -173,6 +174,11 @@ class Context:
     def sigma_add_pwl(self, axis, x0, length, direction, ctrl):
         c, cp = _f64(ctrl)
         self._check(self._L.scabs_sigma_add_pwl(self._c, axis, x0, length, direction, c.shape[0], cp))
+
+    def set_sigma_points(self, sigma_q):
+        """Raw conductivity per quadrature point (7 per triangle, rule order)."""
+        a, ap = _f64(sigma_q)
+        self._check(self._L.scabs_set_sigma_points(self._c, ap, a.shape[0]))
 
     def set_sigma(self, ends: Iterable):
         self.sigma_clear()

@@ -1459,6 +1459,23 @@ int scabs_sigma_add_pwl(scabs_ctx *c, int axis, double x0, double length, int di
   return SCABS_OK;
 }
 
+int scabs_set_sigma_points(scabs_ctx *c, const double *sigma_q, int64_t nq) {
+  if (!c) return SCABS_E_ARG;
+  if (!sigma_q || nq != (int64_t)(c->tris.size() / 3) * NQ)
+    return fail(c, SCABS_E_ARG, "scabs_set_sigma_points needs 7 values per triangle of the mesh set before");
+  for (int64_t i = 0; i < nq; i++)
+    if (!(sigma_q[i] >= 0)) return fail(c, SCABS_E_ARG, "conductivity values must be >= 0");
+  for (size_t k = 0; k < c->ends.size(); k++)
+    if (!c->ends[k].pts.empty()) {
+      c->ends.erase(c->ends.begin() + k);
+      break;
+    }
+  SigmaEnd e{0, 1, 0, 0.0, 1.0, 0.0, {}, std::vector<double>(sigma_q, sigma_q + nq)};
+  c->ends.push_back(e);
+  c->built = false;
+  return SCABS_OK;
+}
+
 int scabs_build(scabs_ctx *c) {
   if (!c) return SCABS_E_ARG;
   try {
@@ -1686,7 +1703,7 @@ int scabs_eval_field_transpose(scabs_ctx *c, const double *pts, int npts, int re
 int scabs_sigma_params(const scabs_ctx *c, int64_t *n) {
   if (!c || !n) return SCABS_E_ARG;
   int64_t k = 0;
-  for (const SigmaEnd &e : c->ends) k += e.ctrl.empty() ? 1 : (int64_t)e.ctrl.size();
+  for (const SigmaEnd &e : c->ends) k += !e.pts.empty() ? (int64_t)e.pts.size() : e.ctrl.empty() ? 1 : (int64_t)e.ctrl.size();
   *n = k;
   return SCABS_OK;
 }

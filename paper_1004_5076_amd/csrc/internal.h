@@ -31,6 +31,7 @@ struct SigmaEnd {
   int axis, dir, degree;
   double x0, length, sigma0;
   std::vector<double> ctrl;       // piecewise-linear control values (empty: monomial)
+  std::vector<double> pts;        // raw values per quadrature point (non-empty: neither profile)
 };
 
 struct Layout {

@@ -145,6 +145,10 @@ void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vecto
   size_t np = (size_t)g.nt * NQ;
   sigma.assign(np, 0.0);
   for (const SigmaEnd &e : ends) {
+    if (!e.pts.empty()) {
+      for (size_t i = 0; i < np; i++) sigma[i] += e.pts[i];
+      continue;
+    }
     for (size_t i = 0; i < np; i++) {
       double s = e.dir * (g.qp[3 * i + e.axis] - e.x0) / e.length;
       if (s < 0) continue;
@@ -173,6 +177,11 @@ void sigma_param_jacobian(const Geometry &g, const std::vector<SigmaEnd> &ends, 
   std::vector<std::vector<std::pair<int, double>>> rows(np);
   int base = 0;
   for (const SigmaEnd &e : ends) {
+    if (!e.pts.empty()) {
+      for (size_t i = 0; i < np; i++) rows[i].push_back({base + (int)i, 1.0});
+      base += (int)np;
+      continue;
+    }
     const int n = e.ctrl.empty() ? 1 : (int)e.ctrl.size();
     for (size_t i = 0; i < np; i++) {
       double s = e.dir * (g.qp[3 * i + e.axis] - e.x0) / e.length;

@@ -69,7 +69,11 @@ def test_matvec_matches_oracle(small, prec, tol):
     NL, NR = o.NL, o.NR
     blocks = [(0, NL), (NL, 2 * NL), (2 * NL, 2 * NL + NR), (2 * NL + NR, 2 * NL + 2 * NR), (2 * NL + 2 * NR, o.N)]
     for a, b in blocks:
-        print("  block", a, b, _rel(y[a:b], y_or[a:b]), flush=True)
+        eb = _rel(y[a:b], y_or[a:b])
+        print("  block", a, b, eb, flush=True)
+        # every row block on its own (an error confined to the small eq14
+        # block would hide under the whole-vector norm)
+        assert eb < (tol if prec == 0 else 5 * tol), (a, b)
     assert err < tol
 
 
@@ -307,3 +311,40 @@ def test_profile_mask_records_only_selected_stages(small):
     pr = ctx.profile_end()
     assert pr["project32"]["count"] == 1 and pr["interp32"]["count"] == 1
 
+
+
+def test_sigma_points_matches_oracle():
+    """Raw per-point conductivity (scabs_set_sigma_points): the profile plus a
+    seeded perturbation on a band of triangles; layout and FP64 product match
+    the oracle given the same point values, and the gradient parameters are
+    the points themselves."""
+    torch = _torch()
+    import paper_1004_5076_amd as pk
+    w = synth.workload_small(length=2.0, absorber=1.0)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    sig = o.sigma.copy()
+    band = (o.qp[:, 0] > 0.6) & (o.qp[:, 0] < 0.9)
+    sig[band] += synth.random_uniform(41, int(band.sum()), 0.0, 0.5)
+    o.set_sigma_points(sig)
+    P = o.pfft(w.h, w.r_near)
+    ctx = pk.Context(w.h, w.r_near)
+    ctx.set_mesh(w.mesh.verts, w.mesh.tris, w.mesh.body)
+    ctx.set_media(w.omega, w.eps_out, w.eps_in)
+    ctx.sigma_clear()
+    ctx.set_sigma_points(sig)
+    ctx.build()
+    assert ctx.info()["N"] == o.N and ctx.info()["NR"] == o.NR
+    isr, idx = ctx.layout()
+    assert np.array_equal(isr, o.isR) and np.array_equal(idx, o.eidx)
+    assert ctx.sigma_params() == o.np_
+    x = synth.random_complex(102, o.N)
+    y = ctx.matvec(torch.from_numpy(x).cuda(), prec=0).cpu().numpy()
+    assert _rel(y, P.matvec(x)) < 1e-10
+    # per-point parameters: d f / d param = d f / d sigma_q
+    lam = torch.from_numpy(synth.random_complex(103, o.N)).cuda()
+    dfds, dfdp = ctx.sigma_gradient(torch.from_numpy(x).cuda(), lam)
+    assert np.allclose(dfdp, dfds.cpu().numpy(), rtol=0, atol=1e-14 * np.max(np.abs(dfdp)))
+    with pytest.raises(pk.ScabsError):
+        ctx.set_sigma_points(sig[:-1])
+    ctx.close()
