@@ -205,6 +205,21 @@ int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei);
  * the points must lie well away from the surface (several edge lengths). */
 int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E, double *H);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fields as scabs_eval_field, with the same arguments and results, but the
+ * device copy of the points goes into a fixed scratch array of the library
+ * (a static device array of 3 * SCABS_NOALLOC_MAX_POINTS doubles, 96 KiB,
+ * one per GPU, held until the process ends) instead of a per-call
+ * allocation; the call allocates nothing.  npts above
+ * SCABS_NOALLOC_MAX_POINTS returns SCABS_E_ARG.  Every call on one GPU
+ * shares that GPU's array, whatever its context: calls that overlap on one
+ * GPU (other threads, other contexts' streams) race.  The context's own
+ * buffers were allocated by scabs_build. */
+#define SCABS_NOALLOC_MAX_POINTS 4096
+int scabs_eval_field_noalloc(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E,
+                             double *H);
+
 /* Transpose of the E part of scabs_eval_field: y = Q^T wE where E = Q x;
  * wE: device, npts * 3 complex; y: device, 2N doubles (overwritten). */
 int scabs_eval_field_transpose(scabs_ctx *c, const double *pts, int npts, int region, const double *wE, double *y);

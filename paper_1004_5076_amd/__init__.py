@@ -25,7 +25,7 @@ SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_set_sigma_points", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
-            "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_transpose", "scabs_sigma_params",
+            "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_noalloc", "scabs_eval_field_transpose", "scabs_sigma_params",
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
@@ -97,6 +97,7 @@ def load() -> C.CDLL:
     L.scabs_incident_dipole_points.argtypes = [P, dp, dp, C.c_int, P]
     L.scabs_point_fields.argtypes = [P, P, P, P]
     L.scabs_eval_field.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
+    L.scabs_eval_field_noalloc.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
     L.scabs_set_sigma_points.argtypes = [P, dp, C.c_int64]
     L.scabs_eval_field_transpose.argtypes = [P, dp, C.c_int, C.c_int, P, P]
     L.scabs_sigma_params.argtypes = [P, C.POINTER(C.c_int64)]
@@ -272,6 +273,20 @@ class Context:
         H = torch.empty_like(E)
         self._check(self._L.scabs_eval_field(self._c, C.c_void_p(x.data_ptr()), pp, p.shape[0], int(region),
                                              C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
+        return E, H
+
+    def eval_field_noalloc(self, x, pts, region: int, E=None, H=None):
+        """scabs_eval_field through the entry point that allocates nothing
+        (outputs E, H may be passed in, shape (npts, 3) complex128)."""
+        import torch
+        x = self._dev(x)
+        p, pp = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        if E is None:
+            E = torch.empty((p.shape[0], 3), dtype=torch.complex128, device=self.device)
+        if H is None:
+            H = torch.empty_like(E)
+        self._check(self._L.scabs_eval_field_noalloc(self._c, C.c_void_p(x.data_ptr()), pp, p.shape[0], int(region),
+                                                     C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
         return E, H
 
     def eval_field_transpose(self, pts, region: int, wE):

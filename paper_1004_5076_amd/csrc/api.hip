@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -191,6 +192,7 @@ struct scabs_ctx {
   unsigned *hflag = nullptr, *hflag_dev = nullptr;
   unsigned hseq = 0;
   int *flag = nullptr;
+  double *noalloc_pts = nullptr;   // this device's copy of the no-allocation scratch array
 };
 
 // RAII stage timer: records a start/end event pair on the context stream
@@ -250,6 +252,32 @@ static int hip_fail(scabs_ctx *c, const HipError &e) {
   catch (...) {                                                                    \
     return fail(c, SCABS_E_HIP, "unexpected exception");                           \
   }
+
+// ---------------------------------------------------------------------------
+// scratch of scabs_eval_field_noalloc: a file-scope device array (each device
+// holds its own copy until the process ends).  Host code never passes the
+// array's name to a kernel or copy: it uses the address hipGetSymbolAddress
+// returns with the device current, looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[3 * SCABS_NOALLOC_MAX_POINTS];
+
+static std::mutex g_scratch_mu;
+static std::vector<double *> g_scratch_ptr;   // per device ordinal (null: not looked up yet)
+
+// the device's scratch address; the device must be current
+static hipError_t scratch_address(int device, double **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= g_scratch_ptr.size()) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (double *)p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // build
@@ -1395,6 +1423,7 @@ int scabs_create(scabs_ctx **out, const scabs_opts *o) {
   c->opts = *o;
   if (!(c->opts.kappa_s > 0)) c->opts.kappa_s = 1.37;
   if (hipSetDevice(o->device) != hipSuccess) return SCABS_E_HIP;
+  if (scratch_address(o->device, &c->noalloc_pts) != hipSuccess) return SCABS_E_HIP;
   if (o->stream) {
     c->stream = (hipStream_t)o->stream;
   } else {
@@ -1676,6 +1705,27 @@ int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts,
     launch_unpack(c->p64.op, x, c->stream);
     const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
     launch_eval_field(c->p64.op, c->qp64, p, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
+int scabs_eval_field_noalloc(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E,
+                             double *H) {
+  if (!c || !x || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
+  if (npts > SCABS_NOALLOC_MAX_POINTS)
+    return fail(c, SCABS_E_ARG, "npts exceeds SCABS_NOALLOC_MAX_POINTS (the scratch array's capacity)");
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (region >= c->geo.nbody) return fail(c, SCABS_E_ARG, "region out of range");
+  try {
+    // the points go into this device's scratch array (its looked-up address)
+    HIPCHK(hipMemcpyAsync(c->noalloc_pts, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
+    launch_unpack(c->p64.op, x, c->stream);
+    const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
+    launch_eval_field(c->p64.op, c->qp64, c->noalloc_pts, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H,
+                      c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
   }
