@@ -86,49 +86,89 @@ def roofline(prof: dict, stage: str) -> dict:
             "total_ms": rec["ms"]}
 
 
-def dipole_field_y(w, d, p):
-    """E_y of the source dipole in the interior medium at p (closed form): the
-    incident part of the monitored field."""
+def _host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w_full_N: int, budget_s: float = 12.0) -> dict:
+    """The oracle on the host cores, unscaled, on two bounded cases: the
+    4-long single guide (configuration 0, N = 2135) and a one-wavelength
+    section of the benchmark geometry (two channels, quartic absorber on
+    x in [0.5, 1], N = 4338).  Timed: dense Galerkin assembly (OpenMP C),
+    LU factorisation (zgetrf) and solve (zgetrs), the dense product (zgemv),
+    and the oracle's precorrected-FFT product (numpy FFT + C loops), on all
+    host cores and (configuration 0 only, plus the section's product) on one
+    core.  value: the dense product rate on all cores extrapolated O(N^2) to
+    the benchmark's N (labelled as an extrapolation; the dense matrix would
+    need 170 GB there)."""
     import numpy as np
-    k = w.omega * math.sqrt(w.eps_in)
-    Z = 1.0 / math.sqrt(w.eps_in)
-    r = np.asarray(p, float) - np.asarray(d.pos, float)
-    R = float(np.linalg.norm(r))
-    u = r / R
-    m = np.asarray(d.moment, complex)
-    e = np.exp(-1j * k * R)
-    G = e / (4 * math.pi * R)
-    G1 = -(1 + 1j * k * R) * e / (4 * math.pi * R * R)
-    G2 = (2 - k * k * R * R + 2j * k * R) * e / (4 * math.pi * R ** 3)
-    up = u @ m
-    hp = G2 * up * u + (G1 / R) * (m - up * u)
-    E = -1j * k * Z * (m * G + hp / (k * k))
-    return E[1]
-
-
-def cpu_baseline(w_full_N: int, budget_s: float = 20.0) -> dict:
-    """The oracle's precorrected-FFT product (numpy FFT + plain C loops) on a
-    0.6-long two-channel section of the same geometry, mesh and grid; scaled
-    linearly in N to the benchmark size (the product's cost is ~linear)."""
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_limits
     import oracle
     import synth
-    w = synth.workload_two_channel(length=0.6, absorber=0.3, edge=0.072)
-    wf = synth.workload_two_channel(edge=0.072)
-    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
-    o.set_sigma(w.sigma)
-    P = o.pfft(wf.h, wf.r_near)
-    x = synth.random_complex(77, o.N)
-    P.matvec(x)
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s or n < 2:
-        P.matvec(x)
-        n += 1
-    dt = (time.perf_counter() - t0) / n
-    rate = 1.0 / dt * (o.N / w_full_N)
-    return {"value": rate, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle pFFT product, two-channel 0.6-long section N={o.N}, {n} products "
-                      f"({dt * 1e3:.1f} ms each), rate scaled by N_sample/N={o.N}/{w_full_N}"}
+    cores = _host_cores()
+    L = oracle.lib()
+
+    def section():
+        w = synth.workload_two_channel(length=1.0, absorber=0.5, edge=0.072)
+        w.sigma = [synth.SigmaEnd(axis=0, x0=0.5, length=0.5, direction=+1, degree=4, sigma0=1.0)]
+        w.dipoles = [synth.seeded_dipole(2000, base=(0.25, -0.35, 0.0), jitter=(0.05, 0.02, 0.02), body=0)]
+        w.h, w.r_near = 30.0 / 508, 3.61 * 30.0 / 508
+        return w
+
+    def timed(fn, min_s=0.3):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s or n >= 50:
+                return dt / n
+
+    cases = {}
+    for name, wf, one_core in (("config0_guide4", synth.workload_small, True), ("section_1lambda", section, False)):
+        w = wf()
+        o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+        o.set_sigma(w.sigma)
+        rec = {"N": o.N}
+        for nthreads in ([cores, 1] if one_core else [cores]):
+            L.or_set_threads(nthreads)
+            with threadpool_limits(nthreads):
+                t0 = time.perf_counter()
+                A = o.dense()
+                ta = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                lu = sla.lu_factor(A)
+                tf = time.perf_counter() - t0
+                b = o.rhs_dipole(w.dipoles[0])
+                ts = timed(lambda: sla.lu_solve(lu, b), 0.1)
+                x = synth.random_complex(77, o.N)
+                tm = timed(lambda: A @ x)
+            rec[f"threads{nthreads}"] = {"assembly_s": ta, "zgetrf_s": tf, "zgetrs_s": ts, "zgemv_s": tm,
+                                         "dense_matvecs_per_s": 1.0 / tm}
+            del A, lu
+        # the oracle's precorrected product (one thread: numpy FFT, C loops)
+        L.or_set_threads(1)
+        with threadpool_limits(1):
+            P = o.pfft(w.h, w.r_near)
+            x = synth.random_complex(78, o.N)
+            tp = timed(lambda: P.matvec(x), 1.0)
+        rec["pfft_product_s_1thread"] = tp
+        cases[name] = rec
+    L.or_set_threads(cores)
+    ref = cases["section_1lambda"]
+    rate_ext = ref[f"threads{cores}"]["dense_matvecs_per_s"] * (ref["N"] / w_full_N) ** 2
+    pfft_ext = 1.0 / ref["pfft_product_s_1thread"] * (ref["N"] / w_full_N)
+    return {"value": rate_ext, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+            "extrapolated": True,
+            "sample": (f"dense Galerkin oracle (zgemv) on a one-wavelength two-channel section, N={ref['N']}, "
+                       f"{cores} threads; value extrapolated O(N^2) to N={w_full_N}"),
+            "cases": cases,
+            "pfft_oracle_matvecs_per_s_1thread_extrapolated_linear": pfft_ext,
+            "lu_extrapolated_s": ref[f"threads{cores}"]["zgetrf_s"] * (w_full_N / ref["N"]) ** 3}
 
 
 def main():
@@ -205,7 +245,7 @@ def main():
     wE = np.zeros((len(xs_m), 3), complex)
     wE[:, 1] = np.linalg.pinv(fit)[1]
     wE_t = torch.from_numpy(wE).to(dev)
-    Einc_y = torch.from_numpy(np.array([dipole_field_y(w, d0, p) for p in pts])).to(dev)
+    Einc_y = ctx.dipole_field(d0.pos, d0.moment, d0.body, pts, int(d0.body))[0][:, 1].contiguous()
     einc = ctx.incident_dipole_points(d0.pos, d0.moment, d0.body)
     region = int(d0.body)
 
@@ -315,7 +355,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 products / f64 Krylov",
+        "dtype": "c64 products and inner Krylov basis / f64 sums, rotations, refinement",
         "data": "synthetic",
         "config": {"workload": "two_channel_30x0.4x0.2_quartic_absorbers_edge%.3g" % args.edge, "N": N,
                    "grid_phys": info["grid_phys"], "grid_fft": info["grid_fft"], "h": w.h, "r_near": w.r_near,

@@ -205,6 +205,16 @@ int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei);
  * the points must lie well away from the surface (several edge lengths). */
 int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E, double *H);
 
+/* Fields of an electric dipole (as scabs_rhs_dipole: current moment p = I l,
+ * moment[6] re/im pairs, at pos inside body `body`) at points pts (host,
+ * npts * 3) of region `region` (< 0 exterior, b >= 0 interior of body b):
+ * the closed-form dipole fields of the interior medium (Sec. II; the
+ * incident field of the rows) when region == body, zero otherwise.  E, H:
+ * device, npts * 3 complex.  Added to scabs_eval_field's scattered fields
+ * this gives the total field at monitor points. */
+int scabs_dipole_field(scabs_ctx *c, const double pos[3], const double moment[6], int body, const double *pts,
+                       int npts, int region, double *E, double *H);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * fields as scabs_eval_field, with the same arguments and results, but the
@@ -242,6 +252,14 @@ int scabs_sigma_params(const scabs_ctx *c, int64_t *n);
  * fixed. */
 int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const double *einc, double *dfdsigma,
                          double *dfdparam);
+
+/* One-call gradient: solves A^T lam = g (device, 2N doubles; g = df/dx as in
+ * scabs_sigma_gradient) with scabs_solve_transpose's rules (tol, max_iter,
+ * restart, mode; info may be NULL), then returns scabs_sigma_gradient(x, lam,
+ * einc, dfdsigma, dfdparam).  SCABS_E_NOCONV if the adjoint solve misses tol
+ * (no gradient is written then). */
+int scabs_gradient(scabs_ctx *c, const double *x, const double *g, const double *einc, double tol, int max_iter,
+                   int restart, int mode, double *dfdsigma, double *dfdparam, scabs_solve_info *info);
 
 /* Stage timing (tracing): between scabs_profile_begin and scabs_profile_end
  * every stage of every product and solve is bracketed by HIP events on the

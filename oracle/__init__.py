@@ -60,6 +60,8 @@ def lib():
         ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
         zp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
         L.or_create.restype = P
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_get_threads.restype = C.c_int
         L.or_create.argtypes = [C.c_int, dp, C.c_int, ip, ip, C.c_double, C.c_double, C.c_double, C.c_double, C.c_char_p]
         L.or_free.argtypes = [P]
         L.or_error.restype = C.c_char_p

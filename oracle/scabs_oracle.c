@@ -26,6 +26,7 @@
  * projection / interpolation maps used with an FFT convolution done in numpy.
  */
 #include <complex.h>
+#include <omp.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -116,6 +117,10 @@ typedef struct {
   double *gw;                     /* nt*7*27 value weights */
   double *gd;                     /* nt*7*27*3 gradient weights */
 } Ctx;
+
+/* host threads of the OpenMP loops (timing of the oracle on a given core count) */
+void or_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int or_get_threads(void) { return omp_get_max_threads(); }
 
 static void set_err(Ctx *c, const char *m) { snprintf(c->err, sizeof c->err, "%s", m); }
 const char *or_error(Ctx *c) { return c->err; }

@@ -25,7 +25,7 @@ SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_set_sigma_points", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
-            "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_noalloc", "scabs_eval_field_transpose", "scabs_sigma_params",
+            "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_noalloc", "scabs_dipole_field", "scabs_gradient", "scabs_eval_field_transpose", "scabs_sigma_params",
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
@@ -98,6 +98,8 @@ def load() -> C.CDLL:
     L.scabs_point_fields.argtypes = [P, P, P, P]
     L.scabs_eval_field.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
     L.scabs_eval_field_noalloc.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
+    L.scabs_dipole_field.argtypes = [P, dp, dp, C.c_int, dp, C.c_int, C.c_int, P, P]
+    L.scabs_gradient.argtypes = [P, P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, dp, C.POINTER(SolveInfo)]
     L.scabs_set_sigma_points.argtypes = [P, dp, C.c_int64]
     L.scabs_eval_field_transpose.argtypes = [P, dp, C.c_int, C.c_int, P, P]
     L.scabs_sigma_params.argtypes = [P, C.POINTER(C.c_int64)]
@@ -274,6 +276,39 @@ class Context:
         self._check(self._L.scabs_eval_field(self._c, C.c_void_p(x.data_ptr()), pp, p.shape[0], int(region),
                                              C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
         return E, H
+
+    def dipole_field(self, pos, moment, body: int, pts, region: int):
+        """Closed-form fields of the dipole at points of a region (zero outside
+        the dipole's body)."""
+        import torch
+        p, pp = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        pa, posp = _f64(np.asarray(pos, dtype=np.float64))
+        m = np.asarray(moment, dtype=np.complex128)
+        ma, mp = _f64(np.stack([m.real, m.imag], axis=1).ravel())
+        E = torch.empty((p.shape[0], 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E)
+        self._check(self._L.scabs_dipole_field(self._c, posp, mp, int(body), pp, p.shape[0], int(region),
+                                               C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
+        return E, H
+
+    def gradient(self, x, g, einc=None, tol: float = 1e-10, max_iter: int = 4000, restart: int = 200,
+                 mode: int = SCABS_FP64):
+        """One call: adjoint solve A^T lam = g, then the sigma gradient.
+        Returns (d f/d sigma per point [device], d f/d parameters [numpy], solve info)."""
+        import torch
+        x = self._dev(x)
+        g = self._dev(g)
+        npt = self.info()["n_points"]
+        dfds = torch.empty(npt, dtype=torch.float64, device=self.device)
+        dfdp = np.zeros(max(self.sigma_params(), 1))
+        if einc is not None:
+            einc = einc.resolve_conj().contiguous()
+        ep = C.c_void_p(einc.data_ptr()) if einc is not None else C.c_void_p()
+        si = SolveInfo()
+        self._check(self._L.scabs_gradient(self._c, C.c_void_p(x.data_ptr()), C.c_void_p(g.data_ptr()), ep, tol,
+                                           max_iter, restart, mode, C.c_void_p(dfds.data_ptr()),
+                                           dfdp.ctypes.data_as(C.POINTER(C.c_double)), C.byref(si)))
+        return dfds, dfdp[: self.sigma_params()], si.as_dict()
 
     def eval_field_noalloc(self, x, pts, region: int, E=None, H=None):
         """scabs_eval_field through the entry point that allocates nothing

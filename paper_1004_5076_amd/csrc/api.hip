@@ -1712,6 +1712,31 @@ int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts,
   return SCABS_OK;
 }
 
+int scabs_dipole_field(scabs_ctx *c, const double pos[3], const double moment[6], int body, const double *pts,
+                       int npts, int region, double *E, double *H) {
+  if (!c || !pos || !moment || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (body < 0 || body >= c->geo.nbody || region >= c->geo.nbody)
+    return fail(c, SCABS_E_ARG, "body or region out of range");
+  try {
+    if (region != body) {
+      HIPCHK(hipMemsetAsync(E, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
+      HIPCHK(hipMemsetAsync(H, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
+    } else {
+      DevMem tmp;
+      double *p = tmp.alloc<double>(3 * (size_t)npts);
+      HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
+      launch_dipole_points(npts, p, c->k_i, c->Z_i, pos, moment, (cx<double> *)E, (cx<double> *)H, c->stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(c->stream));
+      return SCABS_OK;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
 int scabs_eval_field_noalloc(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E,
                              double *H) {
   if (!c || !x || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
@@ -1790,6 +1815,21 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
   }
   SCABS_CATCH(c)
   return SCABS_OK;
+}
+
+int scabs_gradient(scabs_ctx *c, const double *x, const double *g, const double *einc, double tol, int max_iter,
+                   int restart, int mode, double *dfdsigma, double *dfdparam, scabs_solve_info *info) {
+  if (!c || !x || !g) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  try {
+    DevMem tmp;
+    double *lam = tmp.alloc<double>(2 * (size_t)c->lay.N);
+    HIPCHK(hipMemsetAsync(lam, 0, sizeof(double) * 2 * (size_t)c->lay.N, c->stream));
+    const int st = do_solve(c, g, lam, 1, tol, max_iter, restart, mode, info, true);
+    if (st != SCABS_OK) return st;
+    return scabs_sigma_gradient(c, x, lam, einc, dfdsigma, dfdparam);
+  }
+  SCABS_CATCH(c)
 }
 
 int scabs_profile_begin(scabs_ctx *c) {

@@ -213,6 +213,8 @@ void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &e
                          double inv_h, cx<double> *Ee, cx<double> *Ei, hipStream_t s);
 void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, const cx<double> *Ei,
                        const cx<double> *Einc, double *dfds, hipStream_t s);
+void launch_dipole_points(int npts, const double *pts, double k, double Z, const double *pos, const double *mom,
+                          cx<double> *E, cx<double> *H, hipStream_t s);
 void launch_incident_points(int np, const int *body, const PointRec<double> *pts, const double *qp, double k, double Z,
                             const double *pos, const double *mom, int bodyid, cx<double> *E, hipStream_t s);
 

@@ -789,6 +789,28 @@ void launch_incident_points(int np, const int *body, const PointRec<double> *pts
                      cx<double>{mom[4], mom[5]}, bodyid, E);
 }
 
+// the dipole's fields (interior medium) at arbitrary points, 3 complex per point
+__global__ void dipole_points_kernel(int npts, const double *__restrict__ pts, double k, double Z, double px, double py,
+                                     double pz, cx<double> m0, cx<double> m1, cx<double> m2, cx<double> *__restrict__ E,
+                                     cx<double> *__restrict__ H) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const double r0[3] = {px, py, pz};
+  const cx<double> mo[3] = {m0, m1, m2};
+  cx<double> e[3], h[3];
+  dipole_fields(k, Z, r0, mo, pts + 3 * (size_t)p, e, h);
+  for (int a = 0; a < 3; a++) {
+    E[3 * (size_t)p + a] = e[a];
+    H[3 * (size_t)p + a] = h[a];
+  }
+}
+
+void launch_dipole_points(int npts, const double *pts, double k, double Z, const double *pos, const double *mom,
+                          cx<double> *E, cx<double> *H, hipStream_t s) {
+  hipLaunchKernelGGL(dipole_points_kernel, dim3((npts + 255) / 256), dim3(256), 0, s, npts, pts, k, Z, pos[0], pos[1],
+                     pos[2], cx<double>{mom[0], mom[1]}, cx<double>{mom[2], mom[3]}, cx<double>{mom[4], mom[5]}, E, H);
+}
+
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,
                        const TriRec<double> *tris, const PointRec<double> *pts, const EdgeRec *edges, double k, double Z,
                        const double *pos, const double *mom, int bodyid, double *b, hipStream_t s) {

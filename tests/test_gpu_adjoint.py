@@ -148,6 +148,16 @@ def test_sigma_gradient_matches_oracle(grad_case):
     einc = ctx.incident_dipole_points(d.pos, d.moment, d.body)
     dfs, grad = ctx.sigma_gradient(x, lam, einc)
     print("grad gpu", grad, "oracle", grad_or, flush=True)
+    # the library's dipole field at the monitor points is the closed form the
+    # oracle evaluates (zero outside the dipole's body)
+    Ed, _ = ctx.dipole_field(d.pos, d.moment, d.body, pts, 0)
+    assert _rel(Ed.cpu().numpy(), Einc_m) < 1e-13
+    E0, _ = ctx.dipole_field(d.pos, d.moment, d.body, pts, -1)
+    assert E0.abs().max().item() == 0
+    # one call: adjoint solve and gradient together
+    dfs1, grad1, info1 = ctx.gradient(x, gg.contiguous(), einc, tol=1e-12, restart=200, max_iter=5000)
+    assert info1["status"] == 0
+    assert np.max(np.abs(grad1 - grad)) <= 1e-8 * np.max(np.abs(grad))
     assert abs(bh_g.item() - bh) < 1e-9 * abs(bh)
     assert np.max(np.abs(grad - grad_or)) <= 1e-6 * np.max(np.abs(grad_or))
     scale = np.max(np.abs(dfs_or))
