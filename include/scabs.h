@@ -69,7 +69,18 @@ typedef struct {
                       steers convergence, not the solution's accuracy */
   double pc_cell;     /* <= 0 selects 2 r_near */
   double pc_overlap;  /* < 0 selects 1.5 r_near; must not exceed pc_cell */
+  int product;        /* SCABS_PRODUCT_PFFT (0): precorrected FFT on a lattice
+                         (any mesh, approximate far field);
+                         SCABS_PRODUCT_TOEPLITZ (1): the fast-solver appendix's
+                         block-Toeplitz product on a mesh that repeats along x
+                         (exact: the discrete Galerkin operator itself).  The
+                         forward product of scabs_matvec and of the solves uses
+                         it; the transposed product, the pointwise fields and
+                         the gradient use the lattice operator either way */
 } scabs_opts;
+
+#define SCABS_PRODUCT_PFFT 0
+#define SCABS_PRODUCT_TOEPLITZ 1
 
 typedef struct {
   int64_t N, NL, NR;       /* unknowns: N = 2 NL + 3 NR (Appendix A) */
@@ -83,6 +94,13 @@ typedef struct {
   int64_t precond_entries; /* stored preconditioner coefficients */
   int64_t device_bytes;    /* device memory held by the context */
   int64_t precond_ext_entries; /* sum over clusters of their extended sets */
+  int64_t product;         /* SCABS_PRODUCT_* of the built context */
+  int64_t rings, circulant_length, ring_edges, ring_triangles;  /* block-Toeplitz: periodic
+                              rings along x, circulant length P (2^a 3^b >= 2 rings - 1),
+                              local edges and triangles of one ring (0 for the lattice) */
+  int64_t nnz_nonperiodic; /* block-Toeplitz: entries of the sparse rows of
+                              pairs with a non-periodic edge */
+  int64_t toeplitz_table_bytes; /* block-Toeplitz: FP32 spectrum tables read per product */
 } scabs_info_t;
 
 typedef struct {

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libscabs.so")
 SCABS_OK = 0
 SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCONV, SCABS_E_NAN = -1, -2, -3, -4, -5, -6, -7
 SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
+SCABS_PRODUCT_PFFT, SCABS_PRODUCT_TOEPLITZ = 0, 1
 EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_set_sigma_points", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
@@ -40,7 +41,8 @@ class ScabsError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("h", C.c_double), ("r_near", C.c_double), ("kappa_s", C.c_double), ("device", C.c_int),
-                ("stream", C.c_void_p), ("precond", C.c_int), ("pc_cell", C.c_double), ("pc_overlap", C.c_double)]
+                ("stream", C.c_void_p), ("precond", C.c_int), ("pc_cell", C.c_double), ("pc_overlap", C.c_double),
+                ("product", C.c_int)]
 
 
 class Info(C.Structure):
@@ -48,7 +50,10 @@ class Info(C.Structure):
                 ("n_tris", C.c_int64), ("n_points", C.c_int64), ("n_bodies", C.c_int64),
                 ("n_near_pairs", C.c_int64), ("nnz_near", C.c_int64), ("grid_phys", C.c_int64 * 3),
                 ("grid_fft", C.c_int64 * 3), ("nnz_near_r", C.c_int64), ("n_clusters", C.c_int64),
-                ("precond_entries", C.c_int64), ("device_bytes", C.c_int64), ("precond_ext_entries", C.c_int64)]
+                ("precond_entries", C.c_int64), ("device_bytes", C.c_int64), ("precond_ext_entries", C.c_int64),
+                ("product", C.c_int64), ("rings", C.c_int64), ("circulant_length", C.c_int64),
+                ("ring_edges", C.c_int64), ("ring_triangles", C.c_int64), ("nnz_nonperiodic", C.c_int64),
+                ("toeplitz_table_bytes", C.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -129,7 +134,7 @@ class Context:
     """One library context: a mesh, media, conductivity profile and grid."""
 
     def __init__(self, h: float, r_near: float, kappa_s: float = 1.37, device: int = 0, stream=None,
-                 precond: int = 1, pc_cell: float = -1.0, pc_overlap: float = -1.0):
+                 precond: int = 1, pc_cell: float = -1.0, pc_overlap: float = -1.0, product: int = 0):
         import torch
         L = load()
         self._L = L
@@ -137,7 +142,7 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        o = Opts(h, r_near, kappa_s, device, C.c_void_p(stream.cuda_stream), precond, pc_cell, pc_overlap)
+        o = Opts(h, r_near, kappa_s, device, C.c_void_p(stream.cuda_stream), precond, pc_cell, pc_overlap, product)
         self._c = C.c_void_p()
         self._check(L.scabs_create(C.byref(self._c), C.byref(o)))
         self.N = None

@@ -193,6 +193,20 @@ struct scabs_ctx {
   unsigned hseq = 0;
   int *flag = nullptr;
   double *noalloc_pts = nullptr;   // this device's copy of the no-allocation scratch array
+  // block-Toeplitz product (scabs_opts.product == SCABS_PRODUCT_TOEPLITZ)
+  bool toe = false;
+  RingTemplate rt;
+  ToeDev<double> t64{};
+  ToeDev<float> t32{};
+  int toe_bcap = 0;
+  int64_t toe_nnz = 0;
+  int64_t *toe_rowptr = nullptr;
+  int *toe_col = nullptr;
+  cx<double> *toe_V4 = nullptr, *toe_S4 = nullptr;
+  cx<float> *toe_V4f = nullptr, *toe_S4f = nullptr;
+  cx<double> *toe_tri64 = nullptr;
+  cx<float> *toe_tri32 = nullptr;
+  double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
 };
 
 // RAII stage timer: records a start/end event pair on the context stream
@@ -462,6 +476,7 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   op.src = P.src;
   op.srcI = nullptr;
   op.tri_out = P.tri_out;
+  op.edge_out = nullptr;
 }
 
 // Dispatch order of per-cluster work-groups: items holds (cluster, offset)
@@ -662,6 +677,230 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
                            c->stream);
 }
 
+// ---------------------------------------------------------------------------
+// block-Toeplitz product: rings, exact ring blocks, their spectra, the sparse
+// rows of the non-periodic edges
+// ---------------------------------------------------------------------------
+template <typename T>
+static void toe_common(scabs_ctx *c, ToeDev<T> &d, const RingTemplate &rt, const int *ringmap, const int *pmap,
+                       const int *esgn, const int *tloc, const int *ebody, const int *tbody, const int *be0,
+                       const int *bt0, const int64_t *ibase, const int64_t *pbase, int64_t gi_per_f,
+                       int64_t pi_per_f, const std::vector<double> &t1, const std::vector<double> &t2) {
+  d.nr = rt.nr;
+  d.P = rt.P;
+  d.ne_r = rt.ne_r;
+  d.nt_r = rt.nt_r;
+  d.Z_e = (T)c->Z_e;
+  d.Z_i = (T)c->Z_i;
+  d.ringmap = ringmap;
+  d.pmap = pmap;
+  d.edge_sgn = esgn;
+  d.tri_loc = tloc;
+  d.ebody = ebody;
+  d.tbody = tbody;
+  d.body_e0 = be0;
+  d.body_t0 = bt0;
+  d.ibase = ibase;
+  d.pbase = pbase;
+  d.gi_per_f = gi_per_f;
+  d.pi_per_f = pi_per_f;
+  std::vector<cx<T>> tw(rt.P);
+  for (int j = 0; j < rt.P; j++) {
+    const double a = -2.0 * PI * j / rt.P;
+    tw[j] = {(T)std::cos(a), (T)std::sin(a)};
+  }
+  d.tw = c->mem.upload(tw);
+  std::vector<T> a1(t1.begin(), t1.end()), a2(t2.begin(), t2.end());
+  d.t1 = c->mem.upload(a1);
+  d.t2 = c->mem.upload(a2);
+}
+
+static std::string build_toeplitz(scabs_ctx *c) {
+  const Geometry &g = c->geo;
+  RingTemplate &rt = c->rt;
+  std::string e = build_rings(g, rt);
+  if (!e.empty()) return e;
+  if (rt.P > 8192) return "too many periodic rings for the ring-axis transforms (more than 4096)";
+  if ((size_t)4 * rt.ne_r * 8 * sizeof(cx<double>) > 160 * 1024)
+    return "too many edges in one ring for the per-frequency block product (more than 320)";
+  hipStream_t s = c->stream;
+  const int nb = g.nbody, ne_r = rt.ne_r, nt_r = rt.nt_r, P = rt.P;
+  const int64_t R2 = 2 * (int64_t)NQ * nt_r;
+  std::vector<int> ebody(ne_r), tbody(nt_r);
+  for (int a = 0; a < ne_r; a++) ebody[a] = rt.tri[rt.e_tri[2 * a]].body;
+  for (int t = 0; t < nt_r; t++) tbody[t] = rt.tri[t].body;
+  std::vector<int64_t> ibase(nb + 1, 0), pbase(nb + 1, 0);
+  for (int b = 0; b < nb; b++) {
+    const int64_t neb = rt.body_e0[b + 1] - rt.body_e0[b], ntb = rt.body_t0[b + 1] - rt.body_t0[b];
+    ibase[b + 1] = ibase[b] + neb * neb;
+    pbase[b + 1] = pbase[b] + 2 * NQ * ntb * neb;
+  }
+  ToeSetupArgs a{};
+  a.nr = rt.nr;
+  a.P = P;
+  a.ne_r = ne_r;
+  a.nt_r = nt_r;
+  a.nbody = nb;
+  a.dx = rt.dx;
+  a.k_e = c->k_e;
+  a.k_i = c->k_i;
+  a.Z_e = c->Z_e;
+  a.Z_i = c->Z_i;
+  a.kappa = c->opts.kappa_s;
+  a.tri = c->mem.upload(rt.tri);
+  a.e_tri = c->mem.upload(rt.e_tri);
+  a.e_k = c->mem.upload(rt.e_k);
+  a.e_off = c->mem.upload(rt.e_off);
+  a.ebody = c->mem.upload(ebody);
+  a.body_e0 = c->mem.upload(rt.body_e0);
+  a.body_t0 = c->mem.upload(rt.body_t0);
+  a.ibase = c->mem.upload(ibase);
+  a.pbase = c->mem.upload(pbase);
+  {
+    DevMem tmp;
+    const size_t nLe = (size_t)ne_r * ne_r, nLi = (size_t)ibase[nb], nPe = (size_t)R2 * ne_r, nPi = (size_t)pbase[nb];
+    a.sLe = tmp.alloc<cx<double>>(nLe * P);
+    a.sKe = tmp.alloc<cx<double>>(nLe * P);
+    a.sLi = tmp.alloc<cx<double>>(nLi * P);
+    a.sKi = tmp.alloc<cx<double>>(nLi * P);
+    a.sPeJ = tmp.alloc<cx<double>>(nPe * P);
+    a.sPeM = tmp.alloc<cx<double>>(nPe * P);
+    a.sPiJ = tmp.alloc<cx<double>>(nPi * P);
+    a.sPiM = tmp.alloc<cx<double>>(nPi * P);
+    std::vector<cx<double>> tw(P);
+    for (int j = 0; j < P; j++) tw[j] = {std::cos(-2.0 * PI * j / P), std::sin(-2.0 * PI * j / P)};
+    cx<double> *tw64 = tmp.upload(tw);
+    launch_toe_setup(a, s);
+    HIPCHK(hipGetLastError());
+    launch_toe_series_fft(a.sLe, (int64_t)nLe, P, tw64, s);
+    launch_toe_series_fft(a.sKe, (int64_t)nLe, P, tw64, s);
+    launch_toe_series_fft(a.sLi, (int64_t)nLi, P, tw64, s);
+    launch_toe_series_fft(a.sKi, (int64_t)nLi, P, tw64, s);
+    launch_toe_series_fft(a.sPeJ, (int64_t)nPe, P, tw64, s);
+    launch_toe_series_fft(a.sPeM, (int64_t)nPe, P, tw64, s);
+    launch_toe_series_fft(a.sPiJ, (int64_t)nPi, P, tw64, s);
+    launch_toe_series_fft(a.sPiM, (int64_t)nPi, P, tw64, s);
+    HIPCHK(hipGetLastError());
+    cx<double> *GE64 = c->mem.alloc<cx<double>>(2 * nLe * P), *GI64 = c->mem.alloc<cx<double>>(2 * nLi * P);
+    cx<double> *PE64 = c->mem.alloc<cx<double>>(2 * nPe * P), *PI64 = c->mem.alloc<cx<double>>(2 * nPi * P);
+    cx<float> *GE32 = c->mem.alloc<cx<float>>(2 * nLe * P), *GI32 = c->mem.alloc<cx<float>>(2 * nLi * P);
+    cx<float> *PE32 = c->mem.alloc<cx<float>>(2 * nPe * P), *PI32 = c->mem.alloc<cx<float>>(2 * nPi * P);
+    launch_toe_layout(a, 0, a.sLe, a.sKe, (int64_t)nLe, GE64, GE32, s);
+    launch_toe_layout(a, 1, a.sLi, a.sKi, (int64_t)nLi, GI64, GI32, s);
+    launch_toe_layout(a, 2, a.sPeJ, a.sPeM, (int64_t)nPe, PE64, PE32, s);
+    launch_toe_layout(a, 3, a.sPiJ, a.sPiM, (int64_t)nPi, PI64, PI32, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    tmp.release();
+    c->t64.GE = GE64;
+    c->t64.GI = GI64;
+    c->t64.PE = PE64;
+    c->t64.PI = PI64;
+    c->t32.GE = GE32;
+    c->t32.GI = GI32;
+    c->t32.PE = PE32;
+    c->t32.PI = PI32;
+    const double ent = 2.0 * P * (double)(nLe + nLi + nPe + nPi);
+    c->toe_table_bytes[0] = ent * sizeof(cx<double>);
+    c->toe_table_bytes[1] = ent * sizeof(cx<float>);
+  }
+  // maps and per-local-triangle bases
+  std::vector<double> t1(3 * (size_t)nt_r), t2(3 * (size_t)nt_r);
+  for (int t = 0; t < nt_r; t++)
+    for (int k = 0; k < 3; k++) {
+      t1[3 * t + k] = rt.tri[t].t1[k];
+      t2[3 * t + k] = rt.tri[t].t2[k];
+    }
+  const int *ringmap = c->mem.upload(rt.ringmap), *pmap = c->mem.upload(rt.pmap);
+  const int *esgn = c->mem.upload(rt.edge_sgn), *tloc = c->mem.upload(rt.tri_loc);
+  toe_common(c, c->t64, rt, ringmap, pmap, esgn, tloc, a.ebody, c->mem.upload(tbody), a.body_e0, a.body_t0, a.ibase,
+             a.pbase, ibase[nb], pbase[nb], t1, t2);
+  toe_common(c, c->t32, rt, ringmap, pmap, esgn, tloc, a.ebody, c->t64.tbody, a.body_e0, a.body_t0, a.ibase, a.pbase,
+             ibase[nb], pbase[nb], t1, t2);
+  // sparse rows of the pairs with a non-periodic edge: full rows of the
+  // non-periodic edges, and their columns in every periodic row
+  std::vector<int> nonper;
+  for (int n = 0; n < g.ne; n++)
+    if (rt.edge_loc[n] < 0) nonper.push_back(n);
+  std::vector<int64_t> rowptr(g.ne + 1, 0);
+  for (int n = 0; n < g.ne; n++) rowptr[n + 1] = rowptr[n] + (rt.edge_loc[n] < 0 ? g.ne : (int64_t)nonper.size());
+  const int64_t nnz = rowptr[g.ne];
+  std::vector<int> rows(nnz), cols(nnz);
+  for (int n = 0; n < g.ne; n++) {
+    int64_t k = rowptr[n];
+    if (rt.edge_loc[n] < 0) {
+      for (int m = 0; m < g.ne; m++, k++) {
+        rows[k] = n;
+        cols[k] = m;
+      }
+    } else {
+      for (int m : nonper) {
+        rows[k] = n;
+        cols[k++] = m;
+      }
+    }
+  }
+  c->toe_nnz = nnz;
+  c->toe_rowptr = c->mem.upload(rowptr);
+  c->toe_col = c->mem.upload(cols);
+  c->toe_V4 = c->mem.alloc<cx<double>>(4 * (size_t)nnz);
+  c->toe_S4 = c->mem.alloc<cx<double>>(4 * (size_t)nnz);
+  c->toe_V4f = c->mem.alloc<cx<float>>(4 * (size_t)nnz);
+  c->toe_S4f = c->mem.alloc<cx<float>>(4 * (size_t)nnz);
+  {
+    DevMem tmp;
+    std::vector<TriD> all;
+    make_tri_records(g, all);
+    ToeCapArgs ca{};
+    ca.nnz = nnz;
+    ca.row = tmp.upload(rows);
+    ca.col = c->toe_col;
+    ca.et = tmp.upload(g.et);
+    ca.tedge = tmp.upload(g.tedge);
+    ca.tri = tmp.upload(all);
+    ca.sigma = tmp.upload(c->lay.sigma);
+    ca.k_e = c->k_e;
+    ca.k_i = c->k_i;
+    ca.kappa = c->opts.kappa_s;
+    ca.V4 = c->toe_V4;
+    ca.S4 = c->toe_S4;
+    ca.V4f = c->toe_V4f;
+    ca.S4f = c->toe_S4f;
+    launch_toe_cap_entries(ca, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  c->toe_bcap = 0;
+  return "";
+}
+
+// grow the per-vector buffers of the block-Toeplitz product to nb vectors
+template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *&tri_out, int nb) {
+  const int cap = sizeof(T) == sizeof(float) ? (c->toe_bcap & 0xffff) : (c->toe_bcap >> 16);
+  if (nb <= cap) return;
+  const Geometry &g = c->geo;
+  if (d.X) {
+    c->mem.free_one(d.X);
+    c->mem.free_one(d.Y);
+    c->mem.free_one(d.edge_out);
+    c->mem.free_one(d.pf);
+    c->mem.free_one(tri_out);
+  }
+  const size_t R2 = 2 * (size_t)NQ * d.nt_r;
+  d.X = c->mem.alloc<cx<T>>((size_t)d.P * 4 * d.ne_r * nb);
+  d.Y = c->mem.alloc<cx<T>>((size_t)d.P * (2 * d.ne_r + 2 * R2) * nb);
+  d.edge_out = c->mem.alloc<cx<T>>((size_t)nb * g.ne * 2);
+  d.pf = c->mem.alloc<cx<T>>((size_t)nb * g.nt * NQ * 4);
+  tri_out = c->mem.alloc<cx<T>>((size_t)nb * g.nt * 9);
+  // rows of non-periodic edges are never written by the transforms
+  HIPCHK(hipMemsetAsync(d.edge_out, 0, sizeof(cx<T>) * nb * g.ne * 2, c->stream));
+  HIPCHK(hipMemsetAsync(d.pf, 0, sizeof(cx<T>) * (size_t)nb * g.nt * NQ * 4, c->stream));
+  if (sizeof(T) == sizeof(float))
+    c->toe_bcap = (c->toe_bcap & ~0xffff) | nb;
+  else
+    c->toe_bcap = (c->toe_bcap & 0xffff) | (nb << 16);
+}
+
 static int do_build(scabs_ctx *c) {
   c->built = false;
   c->has_pc = false;
@@ -857,6 +1096,12 @@ static int do_build(scabs_ctx *c) {
     build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, V4f, S4f, V4fT, S4fT);
   }
   HIPCHK(hipStreamSynchronize(s));
+  c->toe = false;
+  if (c->opts.product == SCABS_PRODUCT_TOEPLITZ) {
+    e = build_toeplitz(c);
+    if (!e.empty()) return fail(c, SCABS_E_MESH, e);
+    c->toe = true;
+  }
   c->built = true;
   return SCABS_OK;
 }
@@ -973,6 +1218,38 @@ template <typename T> static void apply_t(scabs_ctx *c, PrecState<T> &P, const d
   }
 }
 
+// y = A x by the block-Toeplitz product for nb vectors: currents per edge,
+// ring-axis transforms, per-frequency block products, inverse transforms,
+// local and sigma terms, then the rows (sparse rows of the non-periodic
+// pairs plus the periodic sums)
+template <typename T>
+static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_out, const double *x, double *y,
+                      int nb) {
+  hipStream_t s = c->stream;
+  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
+  toe_ensure(c, d, tri_out, nb);
+  DevOperator<T> op = P.op;
+  op.rowptr = c->toe_rowptr;
+  op.col = c->toe_col;
+  op.V4 = sizeof(T) == sizeof(float) ? (const cx<T> *)c->toe_V4f : (const cx<T> *)c->toe_V4;
+  op.S4 = sizeof(T) == sizeof(float) ? (const cx<T> *)c->toe_S4f : (const cx<T> *)c->toe_S4;
+  op.V4T = op.S4T = nullptr;
+  op.tri_out = tri_out;
+  op.edge_out = d.edge_out;
+  {
+    StageTimer t(c, SCABS_STAGE_UNPACK + off);
+    launch_unpack(op, x, s, nb);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_FFT + off, c->toe_table_bytes[sizeof(T) == sizeof(float) ? 1 : 0]);
+    launch_toe_product(op, d, s, nb);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_NEAR + off);
+    launch_near_rows(op, y, s, nb);
+  }
+}
+
 // nb products (vectors stored one after another, 2N doubles each)
 static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec, bool trans = false) {
   const size_t stride = 2 * (size_t)c->lay.N;
@@ -988,6 +1265,16 @@ static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec,
   const int B = near_rows_max_batch();
   for (int k0 = 0; k0 < nb; k0 += B) {
     const int m = std::min(B, nb - k0);
+    if (c->toe) {
+      if (prec == SCABS_FP32) {
+        ensure_batch(c, c->p32, m);
+        apply_toe(c, c->p32, c->t32, c->toe_tri32, x + k0 * stride, y + k0 * stride, m);
+      } else {
+        ensure_batch(c, c->p64, m);
+        apply_toe(c, c->p64, c->t64, c->toe_tri64, x + k0 * stride, y + k0 * stride, m);
+      }
+      continue;
+    }
     if (prec == SCABS_FP32) {
       ensure_batch(c, c->p32, m);
       apply(c, c->p32, x + k0 * stride, y + k0 * stride, m);
@@ -1548,6 +1835,15 @@ int scabs_info(const scabs_ctx *c, scabs_info_t *info) {
       info->precond_entries += (c->cl.ext_ptr[k + 1] - c->cl.ext_ptr[k]) * (c->cl.core_ptr[k + 1] - c->cl.core_ptr[k]);
   info->device_bytes = (int64_t)(c->mem.bytes + c->work.bytes);
   info->precond_ext_entries = c->has_pc ? c->cl.ext_ptr[c->cl.nc] : 0;
+  info->product = c->toe ? SCABS_PRODUCT_TOEPLITZ : SCABS_PRODUCT_PFFT;
+  if (c->toe) {
+    info->rings = c->rt.nr;
+    info->circulant_length = c->rt.P;
+    info->ring_edges = c->rt.ne_r;
+    info->ring_triangles = c->rt.nt_r;
+    info->nnz_nonperiodic = c->toe_nnz;
+    info->toeplitz_table_bytes = (int64_t)c->toe_table_bytes[1];
+  }
   return SCABS_OK;
 }
 

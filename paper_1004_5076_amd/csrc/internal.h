@@ -114,6 +114,45 @@ void build_local_terms(const Geometry &g, const Layout &L, LocalTerms &lt);
 void edge_slots(const Layout &L, int e, int *slots, int *nslots);
 
 // ---------------------------------------------------------------------------
+// block-Toeplitz product (fast-solver appendix): the mesh's periodic unit
+// ---------------------------------------------------------------------------
+// FP64 triangle record for exact interactions: vertices, quadrature points
+// and weights, normal, centroid, in-plane basis (t1 along the first edge,
+// t2 = n x t1), largest centroid-vertex distance, and per half function
+// k (edge opposite vertex k) its signed coefficient s l / (2A)
+struct TriD {
+  double v[9], qp[21], qw[7], nrm[3], cen[3], t1[3], t2[3];
+  double rho, coef[3];
+  int body, pad;
+};
+
+// Rings along x: every periodic triangle is one of nt_r local triangles at
+// ring r = 0..nr-1, translated by r dx; every periodic edge (both triangles
+// periodic) one of ne_r local edges, whose two halves lie on local triangles
+// at ring offsets 0 or -1 from the edge's ring.  Local triangles and edges
+// are ordered by body.  Everything else (end caps and the edges touching
+// them) is non-periodic.
+struct RingTemplate {
+  int nr = 0, P = 0, nt_r = 0, ne_r = 0, nbody = 0;
+  double dx = 0;
+  std::vector<TriD> tri;              // nt_r template triangles at ring 0
+  std::vector<int> e_tri, e_k, e_off; // ne_r * 2: per side (0: +, 1: -) local tri, half index, ring offset
+  std::vector<int> body_e0, body_t0;  // nbody + 1: local edge / triangle ranges of each body
+  std::vector<int> ringmap;           // ne_r * nr: actual edge of local edge a at ring j (-1: none)
+  std::vector<int> pmap;              // nt_r * nr: actual triangle of local triangle t at ring j
+  std::vector<int> edge_loc, edge_ring, edge_sgn;   // per actual edge (-1 / 0 when non-periodic)
+  std::vector<int> tri_loc;           // per actual triangle (-1 when non-periodic)
+};
+
+// Detects the periodic unit along x (period = smallest vertex x spacing),
+// fills rt; an error string when fewer than 3 rings or no periodic part exist.
+std::string build_rings(const Geometry &g, RingTemplate &rt);
+// FP64 records of every triangle of the mesh
+void make_tri_records(const Geometry &g, std::vector<TriD> &out);
+// circulant length: smallest 2^a 3^b >= n
+int smooth_length(int n);
+
+// ---------------------------------------------------------------------------
 // device-side records
 // ---------------------------------------------------------------------------
 // aligned to its size, so that LDS and global accesses of one value are single

@@ -64,6 +64,9 @@ template <typename T> struct DevOperator {
   // [e][b][3] (written by the unpack step; null until a batch is used)
   cx<T> *srcI;
   cx<T> *tri_out;    // nt * 3 (half-edge) * 3 (E, H, eq14 rows)
+  // block-Toeplitz product: per vector and edge the (E, H) row sums of the
+  // periodic part, added by the row kernel ([v][e][2]; null: none)
+  const cx<T> *edge_out;
 };
 
 // ---- FFT convolution -------------------------------------------------------
@@ -224,6 +227,47 @@ void launch_eval_field(const DevOperator<double> &op, const double *qp, const do
                        double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s);
 void launch_eval_field_t(const DevOperator<double> &op, const double *qp, const double *pts, int npts, int region,
                          double k, double Z, const cx<double> *wE, double *y, hipStream_t s);
+
+// ---- block-Toeplitz product (periodic guides) ----------------------------------
+struct ToeSetupArgs {
+  int nr, P, ne_r, nt_r, nbody;
+  double dx, k_e, k_i, Z_e, Z_i, kappa;
+  const TriD *tri;                 // nt_r template triangles (ring 0)
+  const int *e_tri, *e_k, *e_off;  // ne_r * 2
+  const int *ebody;                // ne_r
+  const int *body_e0, *body_t0;    // nbody + 1
+  const int64_t *ibase, *pbase;    // nbody + 1: interior Galerkin / interior point series offsets
+  cx<double> *sLe, *sKe, *sLi, *sKi, *sPeJ, *sPeM, *sPiJ, *sPiM;   // spatial series, P each
+};
+struct ToeCapArgs {
+  int64_t nnz;
+  const int *row, *col;            // per entry: row edge, column edge
+  const int *et, *tedge;
+  const TriD *tri;                 // every triangle of the mesh
+  const double *sigma;             // per quadrature point
+  double k_e, k_i, kappa;
+  cx<double> *V4, *S4;
+  cx<float> *V4f, *S4f;
+};
+template <typename T> struct ToeDev {
+  int nr, P, ne_r, nt_r;
+  T Z_e, Z_i;
+  const int *ringmap, *pmap, *edge_sgn, *tri_loc, *ebody, *tbody, *body_e0, *body_t0;
+  const int64_t *ibase, *pbase;
+  int64_t gi_per_f, pi_per_f;
+  const cx<T> *GE, *GI, *PE, *PI;  // per-frequency pair tables (see kernels_toeplitz.hip)
+  const cx<T> *tw;                 // exp(-2 pi i j / P), j < P
+  const T *t1, *t2;                // per local triangle: in-plane basis of its point fields
+  cx<T> *X, *Y;                    // spectra of a product
+  cx<T> *edge_out;                 // [v][e][2]
+  cx<T> *pf;                       // [v][point][4]
+};
+void launch_toe_setup(const ToeSetupArgs &s, hipStream_t st);
+void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st);
+void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s);
+void launch_toe_layout(const ToeSetupArgs &s, int kind, const cx<double> *X, const cx<double> *Y, int64_t per_f,
+                       cx<double> *dst64, cx<float> *dst32, hipStream_t st);
+template <typename T> void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb);
 
 // ---- misc --------------------------------------------------------------------
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,

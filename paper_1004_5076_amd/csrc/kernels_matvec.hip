@@ -672,6 +672,11 @@ __global__ void __launch_bounds__(256) near_rows_kernel(DevOperator<T> op, doubl
     e += p0[0] + p1[0];
     h += p0[1] + p1[1];
     rr += p0[2] + p1[2];
+    if (op.edge_out) {
+      const cx<T> *eo = op.edge_out + ((size_t)b * op.ne + n) * 2;
+      e += eo[0];
+      h += eo[1];
+    }
     double *yb = y + (size_t)2 * op.N * b;
     yb[2 * r.row[0]] = e.x;
     yb[2 * r.row[0] + 1] = e.y;

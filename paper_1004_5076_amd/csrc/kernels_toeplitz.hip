@@ -1,0 +1,674 @@
+// Block-Toeplitz product of the sigma-modified PMCHW system (fast-solver
+// appendix): on a mesh that repeats along x with pitch dx, the tested
+// Galerkin operators between periodic RWG edges depend only on the ring
+// offset of the two edges, so their block Toeplitz matrices are embedded in
+// circulants of length P >= 2 nr - 1 and applied by FFTs along the ring axis
+// with one dense block product per frequency.  The sigma-weighted rows of
+// eq13 and eq14 take the one-sided fields at the quadrature (target) points,
+// which are Toeplitz in the same way (potential operators at target points),
+// before the points' Gauss weights and conductivities are applied.  Entries
+// that involve a non-periodic edge (end caps and the edges touching them)
+// are computed exactly and applied as sparse rows.  Everything here is exact
+// for the discrete Galerkin system: the same quadrature and singularity
+// treatment as the near-pair setup, no lattice approximation.
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.h"
+#include "kernels.h"
+#include "near_math.h"
+
+namespace scabs {
+
+// ---------------------------------------------------------------------------
+// exact inner integrals and tested values (FP64)
+// ---------------------------------------------------------------------------
+__device__ inline D3 tri_vertex(const TriD *A, int k, double sx) {
+  return {A->v[3 * k] + sx, A->v[3 * k + 1], A->v[3 * k + 2]};
+}
+__device__ inline D3 tri_point(const TriD *A, int q, double sx) {
+  return {A->qp[3 * q] + sx, A->qp[3 * q + 1], A->qp[3 * q + 2]};
+}
+__device__ inline bool singular_pair(const TriD *A, double sa, const TriD *B, double sb, double kappa) {
+  const double dx = A->cen[0] + sa - B->cen[0] - sb, dy = A->cen[1] - B->cen[1], dz = A->cen[2] - B->cen[2];
+  const double thr = kappa * (A->rho + B->rho);
+  return dx * dx + dy * dy + dz * dz < thr * thr;
+}
+
+struct StaticJ {
+  double J0;
+  D3 J1, Jg;
+};
+
+// half function j of the source triangle B (shifted by sb along x), at r, in
+// medium k: a = int G f_j, phi = int G div f_j, gphi = int grad G div f_j,
+// c = int grad G x f_j.  Singular pairs: static part from st (analytic), 7-point
+// rule on the smooth remainder; otherwise the plain rule on G.
+struct InnerJ {
+  Z3 a, gphi, c;
+  cx<double> phi;
+};
+__device__ void inner_j(D3 r, const TriD *B, double sb, int j, bool sing, const StaticJ &st, double k, InnerJ &o) {
+  cx<double> S0 = {0, 0};
+  Z3 S1 = {{0, 0}, {0, 0}, {0, 0}}, Sg = S1, Sc = S1;
+  const D3 vj = tri_vertex(B, j, sb);
+  for (int s = 0; s < NQ; s++) {
+    const D3 sp = tri_point(B, s, sb);
+    const double w = B->qw[s];
+    const D3 dv = r - sp;
+    const double R = sqrt(dotd(dv, dv));
+    cx<double> G = {0, 0}, dG = {0, 0};
+    if (R > 0 || sing) kernel_val(k, R, sing, G, dG);
+    Z3 gr = {{0, 0}, {0, 0}, {0, 0}};
+    if (R > 1e-14) gr = zscale(dG * (1.0 / R), dv);
+    S0 += G * w;
+    S1 = zadd(S1, zscale(G * w, sp - r));
+    const Z3 grw = {gr.x * w, gr.y * w, gr.z * w};
+    Sg = zadd(Sg, grw);
+    Sc = zadd(Sc, zcross(grw, sp - vj));
+  }
+  if (sing) {
+    const double c4 = 1.0 / (4.0 * PI);
+    S0.x += c4 * st.J0;
+    S1.x.x += c4 * st.J1.x;
+    S1.y.x += c4 * st.J1.y;
+    S1.z.x += c4 * st.J1.z;
+    Sg.x.x += c4 * st.Jg.x;
+    Sg.y.x += c4 * st.Jg.y;
+    Sg.z.x += c4 * st.Jg.z;
+    const D3 cr = crossd(st.Jg, r - vj);
+    Sc.x.x += c4 * cr.x;
+    Sc.y.x += c4 * cr.y;
+    Sc.z.x += c4 * cr.z;
+  }
+  const double cf = B->coef[j], dv = 2.0 * cf;
+  const D3 rv = r - vj;
+  const Z3 a = zadd(S1, zscale(S0, rv));
+  o.a = {a.x * cf, a.y * cf, a.z * cf};
+  o.phi = S0 * dv;
+  o.gphi = {Sg.x * dv, Sg.y * dv, Sg.z * dv};
+  o.c = {Sc.x * cf, Sc.y * cf, Sc.z * cf};
+}
+
+__device__ inline StaticJ static_of(D3 r, const TriD *B, double sb) {
+  StaticJ st;
+  tri_potentials(r, tri_vertex(B, 0, sb), tri_vertex(B, 1, sb), tri_vertex(B, 2, sb), st.J0, st.J1, st.Jg);
+  return st;
+}
+
+// Tested interactions of half function i of target triangle A (shift sa)
+// with half function j of source triangle B (shift sb):
+//   out[0..3] = L_e, K_e, L_i, K_i  (Galerkin; L tested by parts)
+//   out[4..7] = Lrot_e, Krot_e, Lsig_i, Ksig_i at A's points with conductivity
+//               sig[q] (sig null: not computed)
+// interior values only when inner != 0.  Added into out.
+__device__ void tested_pair(const TriD *A, double sa, int i, const TriD *B, double sb, int j, double ke, double ki,
+                            double kappa, bool inner, const double *sig, cx<double> *out) {
+  const bool sing = singular_pair(A, sa, B, sb, kappa);
+  const D3 vi = tri_vertex(A, i, sa);
+  const D3 n = {A->nrm[0], A->nrm[1], A->nrm[2]};
+  const double ci = A->coef[i], di = 2.0 * ci;
+  for (int q = 0; q < NQ; q++) {
+    const D3 r = tri_point(A, q, sa);
+    const double w = A->qw[q];
+    const D3 g = ci * (r - vi);
+    StaticJ st = {0, {0, 0, 0}, {0, 0, 0}};
+    if (sing) st = static_of(r, B, sb);
+    const double sg = sig ? sig[q] : 0.0;
+    for (int med = 0; med < (inner ? 2 : 1); med++) {
+      const double k = med ? ki : ke, ik2 = 1.0 / (k * k);
+      InnerJ in;
+      inner_j(r, B, sb, j, sing, st, k, in);
+      cx<double> tl = zdot(g, in.a);
+      axpy(tl, -di * ik2, in.phi);
+      out[med ? 2 : 0] += mul_j(tl) * (k * w);
+      const Z3 Kv = {-in.c.x, -in.c.y, -in.c.z};
+      out[med ? 3 : 1] += zdot(g, Kv) * w;
+      if (sg != 0.0) {
+        Z3 Lv;
+        Lv.x = mul_j(in.a.x + in.gphi.x * ik2) * k;
+        Lv.y = mul_j(in.a.y + in.gphi.y * ik2) * k;
+        Lv.z = mul_j(in.a.z + in.gphi.z * ik2) * k;
+        if (med == 0) {
+          const D3 gxn = crossd(g, n);
+          out[4] += zdot(gxn, Lv) * (w * sg);
+          out[5] += zdot(gxn, Kv) * (w * sg);
+        } else {
+          out[6] += zdot(g, Lv) * (w * sg);
+          out[7] += zdot(g, Kv) * (w * sg);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup: spatial ring blocks (series over the circulant index m in [0, P))
+// ---------------------------------------------------------------------------
+__device__ inline bool circ_offset(int m, int nr, int P, int &delta) {
+  if (m < nr) {
+    delta = m;
+    return true;
+  }
+  if (m > P - nr) {
+    delta = m - P;
+    return true;
+  }
+  return false;
+}
+
+// Galerkin ring blocks: target local edge a at ring delta, source local edge
+// b at ring 0.  Series (a, b) over m; ext: sLe/sKe[(a ne_r + b) P + m]; int
+// (same body only): sLi/sKi[(ibase_bd + (a - e0) ne_b + (b - e0)) P + m].
+__global__ void __launch_bounds__(64) toe_galerkin_kernel(ToeSetupArgs s) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)s.ne_r * s.ne_r * s.P;
+  if (gid >= total) return;
+  const int m = (int)(gid % s.P);
+  const int64_t ab = gid / s.P;
+  const int a = (int)(ab / s.ne_r), b = (int)(ab % s.ne_r);
+  const int ba = s.ebody[a], bb = s.ebody[b];
+  const bool same = ba == bb;
+  cx<double> out[8];
+  for (int t = 0; t < 8; t++) out[t] = {0, 0};
+  int delta;
+  if (circ_offset(m, s.nr, s.P, delta)) {
+    for (int sa_ = 0; sa_ < 2; sa_++) {
+      const TriD *A = s.tri + s.e_tri[2 * a + sa_];
+      const double xa = (delta + s.e_off[2 * a + sa_]) * s.dx;
+      for (int sb_ = 0; sb_ < 2; sb_++) {
+        const TriD *B = s.tri + s.e_tri[2 * b + sb_];
+        const double xb = s.e_off[2 * b + sb_] * s.dx;
+        tested_pair(A, xa, s.e_k[2 * a + sa_], B, xb, s.e_k[2 * b + sb_], s.k_e, s.k_i, s.kappa, same, nullptr, out);
+      }
+    }
+  }
+  s.sLe[ab * s.P + m] = out[0];
+  s.sKe[ab * s.P + m] = out[1];
+  if (same) {
+    const int e0 = s.body_e0[ba], neb = s.body_e0[ba + 1] - e0;
+    const int64_t ser = s.ibase[ba] + (int64_t)(a - e0) * neb + (b - e0);
+    s.sLi[ser * s.P + m] = out[2];
+    s.sKi[ser * s.P + m] = out[3];
+  }
+}
+
+// One-sided principal-value fields at the target points: local point p
+// (triangle p / 7 at ring delta, point p % 7), tangential components along
+// t1, t2 of its triangle, of unit J and unit M on source local edge b at ring
+// 0: E(J) = -Z L(f), E(M) = K(f).  Row r = 2 p + c.  ext: sPeJ/sPeM[(r ne_r + b) P + m];
+// int (same body): sPiJ/sPiM[(pbase_bd + (r - r0) ne_b + (b - e0)) P + m].
+__global__ void __launch_bounds__(64) toe_points_kernel(ToeSetupArgs s) {
+  const int np_r = NQ * s.nt_r;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)np_r * s.ne_r * s.P;
+  if (gid >= total) return;
+  const int m = (int)(gid % s.P);
+  const int64_t pb = gid / s.P;
+  const int p = (int)(pb / s.ne_r), b = (int)(pb % s.ne_r);
+  const int lt = p / NQ, q = p - lt * NQ;
+  const TriD *A = s.tri + lt;
+  const int bd = A->body, bb = s.ebody[b];
+  const bool same = bd == bb;
+  cx<double> e[8];
+  for (int t = 0; t < 8; t++) e[t] = {0, 0};
+  int delta;
+  if (circ_offset(m, s.nr, s.P, delta)) {
+    const double xa = delta * s.dx;
+    const D3 r = tri_point(A, q, xa);
+    const D3 t1 = {A->t1[0], A->t1[1], A->t1[2]}, t2 = {A->t2[0], A->t2[1], A->t2[2]};
+    for (int sb_ = 0; sb_ < 2; sb_++) {
+      const TriD *B = s.tri + s.e_tri[2 * b + sb_];
+      const double xb = s.e_off[2 * b + sb_] * s.dx;
+      const int j = s.e_k[2 * b + sb_];
+      // the point's own triangle: the rule's coincident points are handled as
+      // in the Galerkin blocks (remainder gradient 0 at R = 0)
+      const bool sing = singular_pair(A, xa, B, xb, s.kappa);
+      StaticJ st = {0, {0, 0, 0}, {0, 0, 0}};
+      if (sing) st = static_of(r, B, xb);
+      for (int med = 0; med < (same ? 2 : 1); med++) {
+        const double k = med ? s.k_i : s.k_e, Z = med ? s.Z_i : s.Z_e, ik2 = 1.0 / (k * k);
+        InnerJ in;
+        inner_j(r, B, xb, j, sing, st, k, in);
+        Z3 Lv;
+        Lv.x = mul_j(in.a.x + in.gphi.x * ik2) * k;
+        Lv.y = mul_j(in.a.y + in.gphi.y * ik2) * k;
+        Lv.z = mul_j(in.a.z + in.gphi.z * ik2) * k;
+        const Z3 EJ = {Lv.x * (-Z), Lv.y * (-Z), Lv.z * (-Z)};
+        const Z3 EM = {-in.c.x, -in.c.y, -in.c.z};
+        cx<double> *o = e + 4 * med;
+        o[0] += zdot(t1, EJ);
+        o[1] += zdot(t2, EJ);
+        o[2] += zdot(t1, EM);
+        o[3] += zdot(t2, EM);
+      }
+    }
+  }
+  for (int c = 0; c < 2; c++) {
+    const int64_t row = 2 * (int64_t)p + c;
+    s.sPeJ[(row * s.ne_r + b) * s.P + m] = e[c];
+    s.sPeM[(row * s.ne_r + b) * s.P + m] = e[2 + c];
+    if (same) {
+      const int e0 = s.body_e0[bd], neb = s.body_e0[bd + 1] - e0;
+      const int64_t r0 = 2 * (int64_t)NQ * s.body_t0[bd];
+      const int64_t ser = s.pbase[bd] + (row - r0) * neb + (b - e0);
+      s.sPiJ[ser * s.P + m] = e[4 + c];
+      s.sPiM[ser * s.P + m] = e[6 + c];
+    }
+  }
+}
+
+// Sparse rows of every edge pair with a non-periodic edge: exact tested values
+// (8 types, summed over the 2 x 2 triangle pairs of the two edges) per CSR
+// entry, in FP64 and FP32.
+__global__ void __launch_bounds__(64) toe_cap_entries_kernel(ToeCapArgs c) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.nnz) return;
+  const int n = c.row[k], m = c.col[k];
+  cx<double> out[8];
+  for (int t = 0; t < 8; t++) out[t] = {0, 0};
+  for (int sa_ = 0; sa_ < 2; sa_++) {
+    const int T = c.et[2 * n + sa_];
+    int i = 0;
+    for (int kk = 0; kk < 3; kk++)
+      if (c.tedge[3 * T + kk] == n) i = kk;
+    const double *sig = c.sigma + (size_t)T * NQ;
+    bool any = false;
+    for (int q = 0; q < NQ; q++) any |= sig[q] != 0.0;
+    for (int sb_ = 0; sb_ < 2; sb_++) {
+      const int U = c.et[2 * m + sb_];
+      int j = 0;
+      for (int kk = 0; kk < 3; kk++)
+        if (c.tedge[3 * U + kk] == m) j = kk;
+      tested_pair(c.tri + T, 0.0, i, c.tri + U, 0.0, j, c.k_e, c.k_i, c.kappa, c.tri[T].body == c.tri[U].body,
+                  any ? sig : nullptr, out);
+    }
+  }
+  for (int t = 0; t < 4; t++) {
+    c.V4[4 * k + t] = out[t];
+    c.S4[4 * k + t] = out[4 + t];
+    c.V4f[4 * k + t] = {(float)out[t].x, (float)out[t].y};
+    c.S4f[4 * k + t] = {(float)out[4 + t].x, (float)out[4 + t].y};
+  }
+}
+
+void launch_toe_setup(const ToeSetupArgs &s, hipStream_t st) {
+  const int64_t ng = (int64_t)s.ne_r * s.ne_r * s.P;
+  hipLaunchKernelGGL(toe_galerkin_kernel, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, st, s);
+  const int64_t npn = (int64_t)NQ * s.nt_r * s.ne_r * s.P;
+  hipLaunchKernelGGL(toe_points_kernel, dim3((unsigned)((npn + 63) / 64)), dim3(64), 0, st, s);
+}
+void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st) {
+  if (c.nnz == 0) return;
+  hipLaunchKernelGGL(toe_cap_entries_kernel, dim3((unsigned)((c.nnz + 63) / 64)), dim3(64), 0, st, c);
+}
+
+// ---------------------------------------------------------------------------
+// FFTs along the ring axis: groups of TOE_LINES lines of length P in LDS
+// ---------------------------------------------------------------------------
+constexpr int TOE_FFT_THREADS = 512;
+constexpr int TOE_FFT_ELEMS = 16;
+// lines per work-group: at most 8, within the Stockham stage's elements per
+// thread and within 64 KiB of LDS (padded addressing)
+template <typename T> __host__ __device__ inline int toe_lines_per_group(int P) {
+  int g = TOE_FFT_ELEMS * TOE_FFT_THREADS / P;
+  if (g > 8) g = 8;
+  while (g > 1 && (size_t)lpad_size<T>(g * P) * sizeof(cx<T>) > 65536) g--;
+  return g < 1 ? 1 : g;
+}
+template <typename T> size_t toe_fft_lds(int P) {
+  return (size_t)lpad_size<T>(toe_lines_per_group<T>(P) * P) * sizeof(cx<T>);
+}
+
+// setup: lines stored contiguously (series of length P), transformed in
+// place with the factor 1/P of the inverse folded in
+__global__ void __launch_bounds__(TOE_FFT_THREADS) toe_series_fft_kernel(cx<double> *data, int64_t nlines, int P,
+                                                                         const cx<double> *tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
+  const int G = toe_lines_per_group<double>(P);
+  const int64_t l0 = (int64_t)blockIdx.x * G;
+  const int nl = (int)(nlines - l0 < G ? nlines - l0 : G);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) buf[lpad<double>(i)] = data[l0 * P + i];
+  __syncthreads();
+  lds_fft_mr<double, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tw, P, false);
+  const double sc = 1.0 / P;
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) data[l0 * P + i] = buf[lpad<double>(i)] * sc;
+}
+
+void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s) {
+  if (nlines == 0) return;
+  const int G = toe_lines_per_group<double>(P);
+  hipLaunchKernelGGL(toe_series_fft_kernel, dim3((unsigned)((nlines + G - 1) / G)), dim3(TOE_FFT_THREADS),
+                     toe_fft_lds<double>(P), s, data, nlines, P, tw);
+}
+
+// series-major (FFT'd) -> per-frequency layouts of the block products, FP64
+// and FP32.  Pair tables: two series (X, Y) become one record {X, Y} at
+// dst[f * per_f + d] for destination d, whose source series index is given
+// by the map kind.
+//   kind 0 (Galerkin ext): d = b ne_r + a          <- series a ne_r + b
+//   kind 1 (Galerkin int): d = ibase + (b-e0) neb + (a-e0) <- ibase + (a-e0) neb + (b-e0)
+//   kind 2 (points ext):   d = b R2 + r            <- r ne_r + b
+//   kind 3 (points int):   d = pbase + (b-e0) R2b + (r-r0) <- pbase + (r-r0) neb + (b-e0)
+__device__ inline int64_t toe_src_series(const ToeSetupArgs &s, int kind, int64_t d) {
+  if (kind == 0) {
+    const int64_t b = d / s.ne_r, a = d % s.ne_r;
+    return a * s.ne_r + b;
+  }
+  if (kind == 2) {
+    const int64_t R2 = 2 * (int64_t)NQ * s.nt_r;
+    const int64_t b = d / R2, r = d % R2;
+    return r * s.ne_r + b;
+  }
+  // per-body blocks: find the body
+  for (int bd = 0; bd < s.nbody; bd++) {
+    const int64_t base = kind == 1 ? s.ibase[bd] : s.pbase[bd];
+    const int64_t next = kind == 1 ? s.ibase[bd + 1] : s.pbase[bd + 1];
+    if (d < base || d >= next) continue;
+    const int64_t neb = s.body_e0[bd + 1] - s.body_e0[bd];
+    const int64_t rows = kind == 1 ? neb : 2 * (int64_t)NQ * (s.body_t0[bd + 1] - s.body_t0[bd]);
+    const int64_t off = d - base, col = off / rows, row = off % rows;
+    return base + row * neb + col;
+  }
+  return 0;
+}
+
+__global__ void toe_layout_kernel(ToeSetupArgs s, int kind, const cx<double> *X, const cx<double> *Y, int64_t per_f,
+                                  cx<double> *dst64, cx<float> *dst32) {
+  const int64_t total = per_f * s.P;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = i / per_f, d = i % per_f;
+    const int64_t ser = toe_src_series(s, kind, d);
+    const cx<double> x = X[ser * s.P + f], y = Y[ser * s.P + f];
+    dst64[2 * i] = x;
+    dst64[2 * i + 1] = y;
+    dst32[2 * i] = {(float)x.x, (float)x.y};
+    dst32[2 * i + 1] = {(float)y.x, (float)y.y};
+  }
+}
+
+void launch_toe_layout(const ToeSetupArgs &s, int kind, const cx<double> *X, const cx<double> *Y, int64_t per_f,
+                       cx<double> *dst64, cx<float> *dst32, hipStream_t st) {
+  if (per_f == 0) return;
+  hipLaunchKernelGGL(toe_layout_kernel, dim3(4096), dim3(256), 0, st, s, kind, X, Y, per_f, dst64, dst32);
+}
+
+// ---------------------------------------------------------------------------
+// product
+// ---------------------------------------------------------------------------
+// forward: line l = slot * nb + v (slot = c ne_r + a; c: 0 J_e, 1 M (exterior
+// sources), 2 J_i, 3 M_i = -M (interior sources)); values over rings j < nr
+// gathered from the per-edge currents (template orientation), zero beyond,
+// transformed; spectrum written to X[f][l].
+template <typename T>
+__global__ void __launch_bounds__(TOE_FFT_THREADS) toe_fwd_kernel(ToeDev<T> d, const cx<T> *__restrict__ src,
+                                                                  const cx<T> *__restrict__ srcI, int ne, int nb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int P = d.P, nr = d.nr;
+  const int G = toe_lines_per_group<T>(P);
+  const int nlines = 4 * d.ne_r * nb;
+  const int l0 = blockIdx.x * G;
+  const int nl = min(G, nlines - l0);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int li = i / P, j = i - li * P;
+    const int l = l0 + li, slot = l / nb, v = l - slot * nb;
+    const int c = slot / d.ne_r, a = slot - c * d.ne_r;
+    cx<T> val = czero<T>();
+    if (j < nr) {
+      const int e = d.ringmap[(size_t)a * nr + j];
+      if (e >= 0) {
+        const int cc = c == 0 ? 0 : c == 2 ? 1 : 2;
+        const cx<T> x = nb > 1 ? srcI[((size_t)e * nb + v) * 3 + cc] : src[(size_t)e * 3 + cc];
+        const T sg = (T)d.edge_sgn[e] * (c == 3 ? T(-1) : T(1));
+        val = x * sg;
+      }
+    }
+    buf[lpad<T>(i)] = val;
+  }
+  __syncthreads();
+  lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, d.tw, P, false);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int f = i / nl, li = i - f * nl;
+    d.X[(size_t)f * nlines + l0 + li] = buf[lpad<T>(li * P + f)];
+  }
+}
+
+// per frequency: rows [0, ne_r) Galerkin (E and H rows of the local edge,
+// exterior minus interior), rows [ne_r, ne_r + R2) point fields (exterior and
+// interior tangential components).  Output slots: 2 a + (0: E, 1: H); 2 ne_r + r
+// (exterior point row r); 2 ne_r + R2 + r (interior).  Y[f][slot * nb + v].
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *xs = reinterpret_cast<cx<T> *>(smem_raw);   // [slot][v]
+  const int f = blockIdx.y;
+  const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
+  const int nin = 4 * ne_r * NB;
+  const cx<T> *Xf = d.X + (size_t)f * nin;
+  for (int i = threadIdx.x; i < nin; i += blockDim.x) xs[i] = Xf[i];
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nout = 2 * ne_r + 2 * R2;
+  cx<T> *Yf = d.Y + (size_t)f * nout * NB;
+  if (row < ne_r) {
+    const int a = row;
+    const int bd = d.ebody[a], e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
+    cx<T> out_e[NB], out_h[NB];
+    for (int med = 0; med < 2; med++) {
+      cx<T> LJ[NB], LM[NB], KJ[NB], KM[NB];
+#pragma unroll
+      for (int v = 0; v < NB; v++) LJ[v] = LM[v] = KJ[v] = KM[v] = czero<T>();
+      const int b0 = med ? e0 : 0, b1 = med ? e0 + neb : ne_r;
+      const cx<T> *G = med ? d.GI + ((size_t)f * d.gi_per_f + d.ibase[bd] + (size_t)(a - e0)) * 2
+                           : d.GE + ((size_t)f * ne_r * ne_r + a) * 2;
+      const size_t cstride = (size_t)(med ? neb : ne_r) * 2;
+      const cx<T> *xJ = xs + (size_t)(med ? 2 : 0) * ne_r * NB, *xM = xs + (size_t)(med ? 3 : 1) * ne_r * NB;
+      for (int b = b0; b < b1; b++) {
+        const cx<T> *g = G + (size_t)(b - b0) * cstride;
+        const cx<T> L = g[0], K = g[1];
+#pragma unroll
+        for (int v = 0; v < NB; v++) {
+          const cx<T> J = xJ[b * NB + v], M = xM[b * NB + v];
+          cmac(LJ[v], L, J);
+          cmac(LM[v], L, M);
+          cmac(KJ[v], K, J);
+          cmac(KM[v], K, M);
+        }
+      }
+      const T Z = med ? d.Z_i : d.Z_e, iZ = T(1) / Z, sgn = med ? T(-1) : T(1);
+#pragma unroll
+      for (int v = 0; v < NB; v++) {
+        const cx<T> E = KM[v] - LJ[v] * Z, H = -KJ[v] - LM[v] * iZ;
+        if (med == 0) {
+          out_e[v] = E;
+          out_h[v] = H;
+        } else {
+          out_e[v] += E * sgn;
+          out_h[v] += H * sgn;
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NB; v++) {
+      Yf[(size_t)(2 * a) * NB + v] = out_e[v];
+      Yf[(size_t)(2 * a + 1) * NB + v] = out_h[v];
+    }
+  } else if (row < ne_r + R2) {
+    const int r = row - ne_r, lt = r / (2 * NQ);
+    const int bd = d.tbody[lt], e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
+    const int r0 = 2 * NQ * d.body_t0[bd], R2b = 2 * NQ * (d.body_t0[bd + 1] - d.body_t0[bd]);
+    for (int med = 0; med < 2; med++) {
+      cx<T> acc[NB];
+#pragma unroll
+      for (int v = 0; v < NB; v++) acc[v] = czero<T>();
+      const int b0 = med ? e0 : 0, b1 = med ? e0 + neb : ne_r;
+      const cx<T> *G = med ? d.PI + ((size_t)f * d.pi_per_f + d.pbase[bd] + (size_t)(r - r0)) * 2
+                           : d.PE + ((size_t)f * ne_r * R2 + r) * 2;
+      const size_t cstride = (size_t)(med ? R2b : R2) * 2;
+      const cx<T> *xJ = xs + (size_t)(med ? 2 : 0) * ne_r * NB, *xM = xs + (size_t)(med ? 3 : 1) * ne_r * NB;
+      for (int b = b0; b < b1; b++) {
+        const cx<T> *g = G + (size_t)(b - b0) * cstride;
+        const cx<T> PJ = g[0], PM = g[1];
+#pragma unroll
+        for (int v = 0; v < NB; v++) {
+          cmac(acc[v], PJ, xJ[b * NB + v]);
+          cmac(acc[v], PM, xM[b * NB + v]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NB; v++) Yf[(size_t)(2 * ne_r + med * R2 + r) * NB + v] = acc[v];
+    }
+  }
+}
+
+// inverse: line l = slot * nb + v over f, inverse transform, rings i < nr
+// scattered: Galerkin slots to edge_out[v][e][2] (E, H rows; template
+// orientation back to the edge's), point slots to pf[v][point][4]
+// (exterior t1, t2, interior t1, t2).
+template <typename T>
+__global__ void __launch_bounds__(TOE_FFT_THREADS) toe_inv_kernel(ToeDev<T> d, int ne, int np, int nb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int P = d.P, nr = d.nr;
+  const int G = toe_lines_per_group<T>(P);
+  const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
+  const int nout = 2 * ne_r + 2 * R2;
+  const int nlines = nout * nb;
+  const int l0 = blockIdx.x * G;
+  const int nl = min(G, nlines - l0);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int f = i / nl, li = i - f * nl;
+    buf[lpad<T>(li * P + f)] = d.Y[(size_t)f * nlines + l0 + li];
+  }
+  __syncthreads();
+  lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, d.tw, P, true);
+  for (int i = threadIdx.x; i < nl * nr; i += blockDim.x) {
+    const int li = i / nr, j = i - li * nr;
+    const int l = l0 + li, slot = l / nb, v = l - slot * nb;
+    const cx<T> val = buf[lpad<T>(li * P + j)];
+    if (slot < 2 * ne_r) {
+      const int a = slot >> 1, h = slot & 1;
+      const int e = d.ringmap[(size_t)a * nr + j];
+      if (e >= 0) d.edge_out[((size_t)v * ne + e) * 2 + h] = val * (T)d.edge_sgn[e];
+    } else {
+      const int rr = slot - 2 * ne_r, med = rr >= R2 ? 1 : 0, r = rr - med * R2;
+      const int p = r >> 1, c = r & 1, lt = p / NQ, q = p - lt * NQ;
+      const int T_ = d.pmap[(size_t)lt * nr + j];
+      d.pf[((size_t)v * np + (size_t)T_ * NQ + q) * 4 + 2 * med + c] = val;
+    }
+  }
+}
+
+// local terms and the sigma tests of the point fields, per triangle (like
+// the lattice path's testing step, without a lattice): H-row residue
+// -1/2 <g, n x (J_e + J_i)>, eq14 Gram <g, J_e + J_i>, and on absorber points
+// w sigma (g x n).(E_e^PV + 1/2 n x M) into the H row and
+// -w sigma g.(E_i^PV + 1/2 n x M) into the eq14 row, where the PV fields
+// come from the periodic sources (their half functions of periodic edges
+// only: every other pair is in the sparse rows).  tri_out[v][T][3 half][3 row].
+template <typename T>
+__global__ void __launch_bounds__(256) toe_local_kernel(DevOperator<T> op, ToeDev<T> d, int nb) {
+  const int T_ = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (T_ >= op.nt) return;
+  const cx<T> *esrc = op.src + (size_t)3 * op.ne * v;
+  const TriRec<T> tr = op.tris[T_];
+  const bool per = d.tri_loc[T_] >= 0;
+  const T n[3] = {tr.nrm[0], tr.nrm[1], tr.nrm[2]};
+  cx<T> out[9];
+  for (int k = 0; k < 9; k++) out[k] = czero<T>();
+  bool eper[3];
+  for (int i = 0; i < 3; i++) eper[i] = d.edge_sgn[tr.edge[i]] != 0;
+  for (int q = 0; q < NQ; q++) {
+    const PointRec<T> P = op.pts[(size_t)T_ * NQ + q];
+    cx<T> Jsum[3], Mq[3];
+    for (int a = 0; a < 3; a++) Jsum[a] = Mq[a] = czero<T>();
+    for (int j = 0; j < 3; j++) {
+      const int e = tr.edge[j];
+      const cx<T> Je = esrc[3 * e], Ji = esrc[3 * e + 1], M = esrc[3 * e + 2];
+      for (int a = 0; a < 3; a++) {
+        axpy(Jsum[a], P.f[3 * j + a], Je + Ji);
+        axpy(Mq[a], P.f[3 * j + a], M);
+      }
+    }
+    cx<T> hnM[3], nJ[3];
+    hnM[0] = T(0.5) * (n[1] * Mq[2] - n[2] * Mq[1]);
+    hnM[1] = T(0.5) * (n[2] * Mq[0] - n[0] * Mq[2]);
+    hnM[2] = T(0.5) * (n[0] * Mq[1] - n[1] * Mq[0]);
+    nJ[0] = n[1] * Jsum[2] - n[2] * Jsum[1];
+    nJ[1] = n[2] * Jsum[0] - n[0] * Jsum[2];
+    nJ[2] = n[0] * Jsum[1] - n[1] * Jsum[0];
+    const T w = P.w, ws = P.w * P.sigma;
+    cx<T> Ee[3], Ei[3];
+    for (int a = 0; a < 3; a++) Ee[a] = Ei[a] = czero<T>();
+    if (per && ws != T(0)) {
+      const cx<T> *pf = d.pf + ((size_t)v * op.np + (size_t)T_ * NQ + q) * 4;
+      const int lt = d.tri_loc[T_];
+      const T *t1 = d.t1 + 3 * (size_t)lt, *t2 = d.t2 + 3 * (size_t)lt;
+      for (int a = 0; a < 3; a++) {
+        Ee[a] = pf[0] * t1[a] + pf[1] * t2[a];
+        Ei[a] = pf[2] * t1[a] + pf[3] * t2[a];
+      }
+    }
+    for (int i = 0; i < 3; i++) {
+      const T gi[3] = {P.f[3 * i], P.f[3 * i + 1], P.f[3 * i + 2]};
+      cx<T> h = czero<T>(), r14 = czero<T>();
+      for (int a = 0; a < 3; a++) {
+        axpy(h, T(-0.5) * w * gi[a], nJ[a]);
+        axpy(r14, w * gi[a], Jsum[a]);
+      }
+      if (ws != T(0)) {
+        const T gxn[3] = {gi[1] * n[2] - gi[2] * n[1], gi[2] * n[0] - gi[0] * n[2], gi[0] * n[1] - gi[1] * n[0]};
+        const bool pv = per && eper[i];
+        for (int a = 0; a < 3; a++) {
+          axpy(h, ws * gxn[a], hnM[a] + (pv ? Ee[a] : czero<T>()));
+          axpy(r14, -ws * gi[a], hnM[a] + (pv ? Ei[a] : czero<T>()));
+        }
+      }
+      out[3 * i + 1] += h;
+      out[3 * i + 2] += r14;
+    }
+  }
+  cx<T> *to = op.tri_out + (size_t)9 * op.nt * v + (size_t)T_ * 9;
+  for (int k = 0; k < 9; k++) to[k] = out[k];
+}
+
+template <typename T> void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb) {
+  const int G = toe_lines_per_group<T>(d.P);
+  const int nin = 4 * d.ne_r * nb;
+  hipLaunchKernelGGL(toe_fwd_kernel<T>, dim3((nin + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
+                     op.src, op.srcI, op.ne, nb);
+  const int R2 = 2 * NQ * d.nt_r;
+  const int rows = d.ne_r + R2;
+#define SCABS_TOE_APPLY(NBV)                                                                                         \
+  do {                                                                                                               \
+    const size_t lds = sizeof(cx<T>) * 4 * d.ne_r * (NBV);                                                           \
+    if (lds > 65536)                                                                                                 \
+      (void)hipFuncSetAttribute((const void *)toe_apply_kernel<T, NBV>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                (int)lds);                                                                           \
+    hipLaunchKernelGGL((toe_apply_kernel<T, NBV>), dim3((rows + 255) / 256, d.P), dim3(256), lds, s, d);              \
+  } while (0)
+  switch (nb) {
+    case 1: SCABS_TOE_APPLY(1); break;
+    case 2: SCABS_TOE_APPLY(2); break;
+    case 3: SCABS_TOE_APPLY(3); break;
+    case 4: SCABS_TOE_APPLY(4); break;
+    case 5: SCABS_TOE_APPLY(5); break;
+    case 6: SCABS_TOE_APPLY(6); break;
+    case 7: SCABS_TOE_APPLY(7); break;
+    default: SCABS_TOE_APPLY(8); break;
+  }
+#undef SCABS_TOE_APPLY
+  const int nout = (2 * d.ne_r + 2 * R2) * nb;
+  hipLaunchKernelGGL(toe_inv_kernel<T>, dim3((nout + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
+                     op.ne, op.np, nb);
+  hipLaunchKernelGGL(toe_local_kernel<T>, dim3((op.nt + 255) / 256, nb), dim3(256), 0, s, op, d, nb);
+}
+template void launch_toe_product<float>(const DevOperator<float> &, const ToeDev<float> &, hipStream_t, int);
+template void launch_toe_product<double>(const DevOperator<double> &, const ToeDev<double> &, hipStream_t, int);
+
+size_t toe_apply_lds_bytes(int ne_r, int nb, size_t elem) { return elem * 4 * (size_t)ne_r * nb; }
+
+}  // namespace scabs
