@@ -1,28 +1,30 @@
-"""Benchmark: precorrected-FFT PMCHW products, mixed-precision batched solves
-and the adjoint sigma gradient on one GPU.
+"""Benchmark: the exact block-Toeplitz PMCHW product (fast-solver appendix),
+mixed-precision batched solves and the adjoint sigma gradient on one GPU.
 
 Workload: two parallel 0.4 x 0.2 dielectric channels (eps 12.25 in air, gap
 0.3), 30 long, quartic surface-conductivity absorbers of length 4 at both
-ends, mesh edge 0.072 (N = 102,852 unknowns), exterior grid 511 x 21 x 7
-(FFT 1024 x 48 x 16); lengths in wavelengths inside the guide.  Synthetic,
-seeded inputs (synth package).
+ends, mesh edge 0.072 (N = 102,852 unknowns; 417 periodic rings of 108 RWG
+edges, circulant length 864); lengths in wavelengths inside the guide.
+Synthetic, seeded inputs (synth package).
 
 One step = one pass of the whole hot path: a batched mixed-precision solve of
-B = 8 seeded dipoles in channel 0 to relative residual 1e-6 (FP32 products
-inside GMRES, FP64 orthogonalisation and refinement residual, right Schwarz
-preconditioner), then, for dipole 0, the reflected amplitude at 16 monitor
-points on the channel axis, its adjoint (transposed) mixed solve and the sigma
-gradient.  value = operator products per second over the timed steps
+B = 8 seeded dipoles in channel 0 to relative residual 1e-6 (FP32 block-
+Toeplitz products inside GMRES, FP64 orthogonalisation and FP64 refinement
+residual, right Schwarz preconditioner), then, for dipole 0, the reflected
+amplitude at 16 monitor points on the channel axis, its adjoint (transposed)
+mixed solve and the sigma gradient (the transposed product is the lattice
+operator's).  value = operator products per second over the timed steps
 (forward and transposed, FP32 and FP64, all right-hand sides).
 
 Also reported: single-dipole mixed and FP64 solve times (the mixed/FP64
 comparison), standalone product rates (1 and 8 vectors), per-stage averages
 from HIP events (one extra untimed step with every stage recorded), the
-rooflines of the x-line transforms of the FP32 convolution, the FP32
-projection gather and the FP32 Schwarz apply (the kernels with the largest
-shares of a step); "roofline" is the one with the largest total, measured
-with HIP events on the library stream over the timed steps, during which only
-its stage records events; and the oracle timed on the host.
+rooflines of the FP32 per-frequency block products, the FP32 Schwarz apply
+and the lattice kernels of the transposed products; "roofline" is the one
+with the largest total, measured with HIP events on the library stream over
+the timed steps, during which only its stage records events; the oracle
+timed on the host; and the solution error against the dense Galerkin LU on a
+one-wavelength section of the same geometry (oracle leg).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -50,9 +52,10 @@ def kernel_src_sha(name: str) -> str:
 
 # kernels whose roofline is reported: stage record, kernel name, source file
 ROOFLINE_KERNELS = {
+    "toeapply32": ("toe_apply_kernel<float, 8>", "kernels_toeplitz.hip"),
+    "precond": ("precond_apply32_mfma_kernel", "kernels_precond.hip"),
     "xline32": ("xline_reg_kernel<float>", "kernels_fft.hip"),
     "gather32": ("gather_kernel<float, 1>", "kernels_matvec.hip"),
-    "precond": ("precond_apply32_mfma_kernel", "kernels_precond.hip"),
 }
 
 
@@ -93,7 +96,7 @@ def _host_cores() -> int:
         return os.cpu_count() or 1
 
 
-def cpu_baseline(w_full_N: int, budget_s: float = 12.0) -> dict:
+def cpu_baseline(w_full_N: int, budget_s: float = 12.0, gpu_check=None) -> dict:
     """The oracle on the host cores, unscaled, on two bounded cases: the
     4-long single guide (configuration 0, N = 2135) and a one-wavelength
     section of the benchmark geometry (two channels, quartic absorber on
@@ -147,6 +150,8 @@ def cpu_baseline(w_full_N: int, budget_s: float = 12.0) -> dict:
                 ts = timed(lambda: sla.lu_solve(lu, b), 0.1)
                 x = synth.random_complex(77, o.N)
                 tm = timed(lambda: A @ x)
+                if gpu_check is not None and nthreads == cores:
+                    rec["gpu_solution_error_vs_dense_lu"] = gpu_check(w, sla.lu_solve(lu, b), b)
             rec[f"threads{nthreads}"] = {"assembly_s": ta, "zgetrf_s": tf, "zgetrs_s": ts, "zgemv_s": tm,
                                          "dense_matvecs_per_s": 1.0 / tm}
             del A, lu
@@ -201,7 +206,7 @@ def main():
     w = synth.workload_two_channel(edge=args.edge)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ctx = pk.context_for(w, device=0)
+    ctx = pk.context_for(w, device=0, product=pk.SCABS_PRODUCT_TOEPLITZ)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = ctx.info()
@@ -336,10 +341,10 @@ def main():
         extras["product_rates_per_s"] = rates
         log("extras", extras)
 
-    # rooflines of the kernels with the largest shares of the step in the
-    # kernel trace (the x-line transforms of the FP32 convolution, the FP32
-    # projection gather, the FP32 Schwarz apply): "roofline" is the one with
-    # the largest total, measured over the timed steps; "rooflines" all three
+    # rooflines of the kernels with the largest shares of the step (the FP32
+    # per-frequency block products, the FP32 Schwarz apply, the lattice
+    # kernels of the transposed products): "roofline" is the one with the
+    # largest total, measured over the timed steps; "rooflines" all of them
     # from the profiled step
     roofs = {k: roofline(full, k) for k in ROOFLINE_KERNELS}
     single_m = extras.get("solve_single_mixed", {}).get("seconds")
@@ -358,6 +363,8 @@ def main():
         "dtype": "c64 products and inner Krylov basis / f64 sums, rotations, refinement",
         "data": "synthetic",
         "config": {"workload": "two_channel_30x0.4x0.2_quartic_absorbers_edge%.3g" % args.edge, "N": N,
+                   "product": "block_toeplitz", "rings": info["rings"], "circulant_length": info["circulant_length"],
+                   "ring_edges": info["ring_edges"], "nnz_nonperiodic": info["nnz_nonperiodic"],
                    "grid_phys": info["grid_phys"], "grid_fft": info["grid_fft"], "h": w.h, "r_near": w.r_near,
                    "tol": args.tol, "restart": args.restart, "batch_rhs": BATCH,
                    "step": "batched mixed solve of 8 dipoles + adjoint solve + sigma gradient"},
@@ -377,9 +384,21 @@ def main():
         "rooflines_source": ("the timed steps (roofline kernels only)" if args.no_breakdown
                              else "one untimed step with every stage recorded"),
     }
+    def gpu_check(ws, x_lu, b):
+        """solution of the same system on the GPU (mixed, to 1e-10), exact
+        block-Toeplitz product and lattice product, against the dense LU"""
+        res = {}
+        for name, prod in (("toeplitz", pk.SCABS_PRODUCT_TOEPLITZ), ("lattice", pk.SCABS_PRODUCT_PFFT)):
+            cs = pk.context_for(ws, device=0, product=prod)
+            xg, si = cs.solve(torch.from_numpy(b).to(dev), tol=1e-10, restart=200, max_iter=4000,
+                              mode=pk.SCABS_MIXED)
+            res[name] = float(np.linalg.norm(xg.cpu().numpy() - x_lu) / np.linalg.norm(x_lu))
+            cs.close()
+        return res
+
     if not args.no_cpu_baseline:
         try:
-            out["cpu_baseline"] = cpu_baseline(N)
+            out["cpu_baseline"] = cpu_baseline(N, gpu_check=gpu_check)
         except Exception as e:  # the baseline is informative only
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out))

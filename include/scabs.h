@@ -306,7 +306,11 @@ int scabs_gradient(scabs_ctx *c, const double *x, const double *g, const double 
                                      blocks gathered once per application into an
                                      ext-ordered FP32 copy (before each
                                      SCABS_STAGE_PRECOND record) */
-#define SCABS_NSTAGES 16
+#define SCABS_STAGE_TOEAPPLY32 16 /* block-Toeplitz product, FP32: the per-frequency block
+                                     products alone (inside stage SCABS_STAGE_FFT +
+                                     SCABS_STAGE_FP32_OFFSET) */
+#define SCABS_STAGE_TOEAPPLY64 17 /* the same in FP64 (inside stage SCABS_STAGE_FFT) */
+#define SCABS_NSTAGES 18
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
 /* Restrict the stages that profiling sessions record to those whose bit
@@ -324,8 +328,10 @@ int scabs_profile_mask(scabs_ctx *c, uint32_t mask);
  * bytes), per extended-set entry the FP32 gathered inputs of the vectors
  * applied, per unknown its index and FP64 outputs;
  * SCABS_STAGE_PCGATHER32: per extended-set entry its index, its column scale,
- * the FP64 inputs read and the FP32 copies written.  Returns SCABS_E_ARG for
- * null arguments. */
+ * the FP64 inputs read and the FP32 copies written;
+ * SCABS_STAGE_TOEAPPLY32/64: every entry of the spectrum tables read once, the
+ * input spectra read and the output spectra written once.  Returns
+ * SCABS_E_ARG for null arguments. */
 int scabs_profile_bytes(const scabs_ctx *c, double *bytes);
 
 const char *scabs_last_error(const scabs_ctx *c);

@@ -207,6 +207,9 @@ struct scabs_ctx {
   cx<double> *toe_tri64 = nullptr;
   cx<float> *toe_tri32 = nullptr;
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
+  ToeLong toe_long{};
+  double *toe_part64 = nullptr;
+  float *toe_part32 = nullptr;
 };
 
 // RAII stage timer: records a start/end event pair on the context stream
@@ -817,29 +820,39 @@ static std::string build_toeplitz(scabs_ctx *c) {
              a.pbase, ibase[nb], pbase[nb], t1, t2);
   toe_common(c, c->t32, rt, ringmap, pmap, esgn, tloc, a.ebody, c->t64.tbody, a.body_e0, a.body_t0, a.ibase, a.pbase,
              ibase[nb], pbase[nb], t1, t2);
-  // sparse rows of the pairs with a non-periodic edge: full rows of the
-  // non-periodic edges, and their columns in every periodic row
+  // sparse rows of the pairs with a non-periodic edge: in the periodic rows
+  // the non-periodic columns (rows of the row kernel), then the full rows of
+  // the non-periodic edges (long rows, chunked); one entry array for both
   std::vector<int> nonper;
   for (int n = 0; n < g.ne; n++)
     if (rt.edge_loc[n] < 0) nonper.push_back(n);
   std::vector<int64_t> rowptr(g.ne + 1, 0);
-  for (int n = 0; n < g.ne; n++) rowptr[n + 1] = rowptr[n] + (rt.edge_loc[n] < 0 ? g.ne : (int64_t)nonper.size());
-  const int64_t nnz = rowptr[g.ne];
+  for (int n = 0; n < g.ne; n++) rowptr[n + 1] = rowptr[n] + (rt.edge_loc[n] < 0 ? 0 : (int64_t)nonper.size());
+  const int64_t nshort = rowptr[g.ne];
+  const int64_t nnz = nshort + (int64_t)nonper.size() * g.ne;
   std::vector<int> rows(nnz), cols(nnz);
   for (int n = 0; n < g.ne; n++) {
     int64_t k = rowptr[n];
-    if (rt.edge_loc[n] < 0) {
-      for (int m = 0; m < g.ne; m++, k++) {
-        rows[k] = n;
-        cols[k] = m;
-      }
-    } else {
-      for (int m : nonper) {
-        rows[k] = n;
-        cols[k++] = m;
-      }
+    if (rt.edge_loc[n] < 0) continue;
+    for (int m : nonper) {
+      rows[k] = n;
+      cols[k++] = m;
     }
   }
+  std::vector<int64_t> lstart(nonper.size());
+  for (size_t i = 0; i < nonper.size(); i++) {
+    int64_t k = nshort + (int64_t)i * g.ne;
+    lstart[i] = k;
+    for (int m = 0; m < g.ne; m++, k++) {
+      rows[k] = nonper[i];
+      cols[k] = m;
+    }
+  }
+  c->toe_long.nlong = (int)nonper.size();
+  c->toe_long.len = g.ne;
+  c->toe_long.nchunk = (g.ne + toe_chunk() - 1) / toe_chunk();
+  c->toe_long.rows = c->mem.upload(nonper);
+  c->toe_long.start = c->mem.upload(lstart);
   c->toe_nnz = nnz;
   c->toe_rowptr = c->mem.upload(rowptr);
   c->toe_col = c->mem.upload(cols);
@@ -892,6 +905,14 @@ template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *
   d.edge_out = c->mem.alloc<cx<T>>((size_t)nb * g.ne * 2);
   d.pf = c->mem.alloc<cx<T>>((size_t)nb * g.nt * NQ * 4);
   tri_out = c->mem.alloc<cx<T>>((size_t)nb * g.nt * 9);
+  const size_t npart = (size_t)std::max(1, c->toe_long.nlong * c->toe_long.nchunk) * 6 * nb;
+  if (sizeof(T) == sizeof(float)) {
+    if (c->toe_part32) c->mem.free_one(c->toe_part32);
+    c->toe_part32 = c->mem.alloc<float>(npart);
+  } else {
+    if (c->toe_part64) c->mem.free_one(c->toe_part64);
+    c->toe_part64 = c->mem.alloc<double>(npart);
+  }
   // rows of non-periodic edges are never written by the transforms
   HIPCHK(hipMemsetAsync(d.edge_out, 0, sizeof(cx<T>) * nb * g.ne * 2, c->stream));
   HIPCHK(hipMemsetAsync(d.pf, 0, sizeof(cx<T>) * (size_t)nb * g.nt * NQ * 4, c->stream));
@@ -1218,6 +1239,9 @@ template <typename T> static void apply_t(scabs_ctx *c, PrecState<T> &P, const d
   }
 }
 
+static float *toe_part(scabs_ctx *c, float *) { return c->toe_part32; }
+static double *toe_part(scabs_ctx *c, double *) { return c->toe_part64; }
+
 // y = A x by the block-Toeplitz product for nb vectors: currents per edge,
 // ring-axis transforms, per-frequency block products, inverse transforms,
 // local and sigma terms, then the rows (sparse rows of the non-periodic
@@ -1241,12 +1265,23 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
     launch_unpack(op, x, s, nb);
   }
   {
-    StageTimer t(c, SCABS_STAGE_FFT + off, c->toe_table_bytes[sizeof(T) == sizeof(float) ? 1 : 0]);
-    launch_toe_product(op, d, s, nb);
+    StageTimer t(c, SCABS_STAGE_FFT + off);
+    launch_toe_product(op, d, s, nb, TOE_FWD);
+    {
+      // the per-frequency block products: every spectrum table entry read
+      // once, the input spectra read and the output spectra written once
+      const size_t el = sizeof(cx<T>);
+      const double bytes = c->toe_table_bytes[sizeof(T) == sizeof(float) ? 1 : 0] +
+                           (double)el * d.P * nb * (4.0 * d.ne_r + 2.0 * d.ne_r + 4.0 * NQ * d.nt_r);
+      StageTimer ta(c, sizeof(T) == sizeof(float) ? SCABS_STAGE_TOEAPPLY32 : SCABS_STAGE_TOEAPPLY64, bytes);
+      launch_toe_product(op, d, s, nb, TOE_APPLY);
+    }
+    launch_toe_product(op, d, s, nb, TOE_INV);
   }
   {
     StageTimer t(c, SCABS_STAGE_NEAR + off);
     launch_near_rows(op, y, s, nb);
+    launch_toe_long_rows(op, c->toe_long, toe_part(c, (T *)nullptr), y, s, nb);
   }
 }
 

@@ -262,12 +262,26 @@ template <typename T> struct ToeDev {
   cx<T> *edge_out;                 // [v][e][2]
   cx<T> *pf;                       // [v][point][4]
 };
+// the rows of non-periodic edges (every column), chunked: entries of long
+// row i at [start[i], start[i] + len) of the sparse-row arrays
+struct ToeLong {
+  int nlong, nchunk, len;
+  const int *rows;
+  const int64_t *start;
+};
+template <typename T>
+void launch_toe_long_rows(const DevOperator<T> &op, const ToeLong &lr, T *part, double *y, hipStream_t s, int nb);
+int toe_chunk();
 void launch_toe_setup(const ToeSetupArgs &s, hipStream_t st);
 void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st);
 void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s);
 void launch_toe_layout(const ToeSetupArgs &s, int kind, const cx<double> *X, const cx<double> *Y, int64_t per_f,
                        cx<double> *dst64, cx<float> *dst32, hipStream_t st);
-template <typename T> void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb);
+// parts of the product: ring-axis forward transforms, per-frequency block
+// products, inverse transforms with the local and sigma terms
+enum ToePart { TOE_FWD = 1, TOE_APPLY = 2, TOE_INV = 4, TOE_ALL = 7 };
+template <typename T>
+void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb, int parts = TOE_ALL);
 
 // ---- misc --------------------------------------------------------------------
 void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,

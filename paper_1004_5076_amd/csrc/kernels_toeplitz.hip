@@ -635,11 +635,130 @@ __global__ void __launch_bounds__(256) toe_local_kernel(DevOperator<T> op, ToeDe
   for (int k = 0; k < 9; k++) to[k] = out[k];
 }
 
-template <typename T> void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb) {
+// ---------------------------------------------------------------------------
+// long rows (every column of a non-periodic edge's row): split into chunks of
+// TOE_CHUNK entries, one wave per (row, chunk); partial sums of the E, H and
+// eq14 rows per vector, then added to the rows the row kernel wrote
+// ---------------------------------------------------------------------------
+constexpr int TOE_CHUNK = 512;
+template <typename T> __device__ inline T wsum64(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T, int NRB>
+__global__ void __launch_bounds__(256) toe_long_rows_kernel(DevOperator<T> op, ToeLong lr, T *__restrict__ part) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (wave >= lr.nlong * lr.nchunk) return;   // wave-uniform
+  const int i = wave / lr.nchunk, ch = wave - i * lr.nchunk;
+  const int n = lr.rows[i];
+  const EdgeRec r = op.edges[n];
+  const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
+  const cx<T> *cur = NRB > 1 ? op.srcI : op.src;
+  T v[6 * NRB];
+#pragma unroll
+  for (int q = 0; q < 6 * NRB; q++) v[q] = T(0);
+  const int64_t k0 = lr.start[i] + (int64_t)ch * TOE_CHUNK;
+  const int64_t k1 = min(k0 + TOE_CHUNK, lr.start[i] + (int64_t)lr.len);
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
+    const int m = op.col[k];
+    const cx<T> Le = op.V4[4 * k], Ke = op.V4[4 * k + 1], Li = op.V4[4 * k + 2], Ki = op.V4[4 * k + 3];
+    cx<T> eJi = Li * Zi, eJe = Le * (-Ze), eM = Ke + Ki;
+    cx<T> hJi = Ki, hJe = -Ke, hM = Le * (-iZe) - Li * iZi;
+    cx<T> rJi = czero<T>(), rM = czero<T>();
+    if (r.isR) {
+      const cx<T> Lr = op.S4[4 * k], Kr = op.S4[4 * k + 1], Ls = op.S4[4 * k + 2], Ks = op.S4[4 * k + 3];
+      hJe = hJe - Lr * Ze;
+      hM = hM + Kr;
+      rJi = Ls * Zi;
+      rM = Ks;
+    }
+    const cx<T> *cm = cur + (size_t)m * NRB * 3;
+#pragma unroll
+    for (int b = 0; b < NRB; b++) {
+      const cx<T> Je = cm[3 * b], Ji = cm[3 * b + 1], M = cm[3 * b + 2];
+      cx<T> e = {v[6 * b], v[6 * b + 1]}, h = {v[6 * b + 2], v[6 * b + 3]}, q = {v[6 * b + 4], v[6 * b + 5]};
+      cmac(e, eJi, Ji);
+      cmac(e, eJe, Je);
+      cmac(e, eM, M);
+      cmac(h, hJi, Ji);
+      cmac(h, hJe, Je);
+      cmac(h, hM, M);
+      cmac(q, rJi, Ji);
+      cmac(q, rM, M);
+      v[6 * b] = e.x;
+      v[6 * b + 1] = e.y;
+      v[6 * b + 2] = h.x;
+      v[6 * b + 3] = h.y;
+      v[6 * b + 4] = q.x;
+      v[6 * b + 5] = q.y;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6 * NRB; q++) {
+    const T t = wsum64(v[q]);
+    if (lane == 0) part[(size_t)wave * 6 * NRB + q] = t;
+  }
+}
+
+// rows += sum of the chunks' partials (one thread per long row and vector)
+template <typename T>
+__global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeLong lr, const T *__restrict__ part, double *y, int nb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= lr.nlong * nb) return;
+  const int i = t / nb, b = t - i * nb;
+  const EdgeRec r = op.edges[lr.rows[i]];
+  double s6[6] = {0, 0, 0, 0, 0, 0};
+  for (int ch = 0; ch < lr.nchunk; ch++) {
+    const T *p = part + ((size_t)(i * lr.nchunk + ch) * nb + b) * 6;
+    for (int q = 0; q < 6; q++) s6[q] += (double)p[q];
+  }
+  double *yb = y + (size_t)2 * op.N * b;
+  yb[2 * r.row[0]] += s6[0];
+  yb[2 * r.row[0] + 1] += s6[1];
+  yb[2 * r.row[1]] += s6[2];
+  yb[2 * r.row[1] + 1] += s6[3];
+  if (r.isR) {
+    yb[2 * r.row[2]] += s6[4];
+    yb[2 * r.row[2] + 1] += s6[5];
+  }
+}
+
+template <typename T>
+void launch_toe_long_rows(const DevOperator<T> &op, const ToeLong &lr, T *part, double *y, hipStream_t s, int nb) {
+  if (lr.nlong == 0) return;
+  const int waves = lr.nlong * lr.nchunk;
+  const int blocks = (waves * 64 + 255) / 256;
+#define SCABS_TOE_LONG(NB) hipLaunchKernelGGL((toe_long_rows_kernel<T, NB>), dim3(blocks), dim3(256), 0, s, op, lr, part)
+  switch (nb) {
+    case 1: SCABS_TOE_LONG(1); break;
+    case 2: SCABS_TOE_LONG(2); break;
+    case 3: SCABS_TOE_LONG(3); break;
+    case 4: SCABS_TOE_LONG(4); break;
+    case 5: SCABS_TOE_LONG(5); break;
+    case 6: SCABS_TOE_LONG(6); break;
+    case 7: SCABS_TOE_LONG(7); break;
+    default: SCABS_TOE_LONG(8); break;
+  }
+#undef SCABS_TOE_LONG
+  hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((lr.nlong * nb + 255) / 256), dim3(256), 0, s, op, lr, part, y, nb);
+}
+template void launch_toe_long_rows<float>(const DevOperator<float> &, const ToeLong &, float *, double *, hipStream_t,
+                                          int);
+template void launch_toe_long_rows<double>(const DevOperator<double> &, const ToeLong &, double *, double *,
+                                           hipStream_t, int);
+int toe_chunk() { return TOE_CHUNK; }
+
+template <typename T>
+void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb, int parts) {
   const int G = toe_lines_per_group<T>(d.P);
   const int nin = 4 * d.ne_r * nb;
-  hipLaunchKernelGGL(toe_fwd_kernel<T>, dim3((nin + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
-                     op.src, op.srcI, op.ne, nb);
+  if (parts & TOE_FWD)
+    hipLaunchKernelGGL(toe_fwd_kernel<T>, dim3((nin + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
+                       op.src, op.srcI, op.ne, nb);
+  if (!(parts & TOE_APPLY)) goto inverse;
+  {
   const int R2 = 2 * NQ * d.nt_r;
   const int rows = d.ne_r + R2;
 #define SCABS_TOE_APPLY(NBV)                                                                                         \
@@ -661,13 +780,18 @@ template <typename T> void launch_toe_product(const DevOperator<T> &op, const To
     default: SCABS_TOE_APPLY(8); break;
   }
 #undef SCABS_TOE_APPLY
-  const int nout = (2 * d.ne_r + 2 * R2) * nb;
-  hipLaunchKernelGGL(toe_inv_kernel<T>, dim3((nout + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
-                     op.ne, op.np, nb);
-  hipLaunchKernelGGL(toe_local_kernel<T>, dim3((op.nt + 255) / 256, nb), dim3(256), 0, s, op, d, nb);
+  }
+inverse:
+  if (parts & TOE_INV) {
+    const int R2 = 2 * NQ * d.nt_r;
+    const int nout = (2 * d.ne_r + 2 * R2) * nb;
+    hipLaunchKernelGGL(toe_inv_kernel<T>, dim3((nout + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
+                       op.ne, op.np, nb);
+    hipLaunchKernelGGL(toe_local_kernel<T>, dim3((op.nt + 255) / 256, nb), dim3(256), 0, s, op, d, nb);
+  }
 }
-template void launch_toe_product<float>(const DevOperator<float> &, const ToeDev<float> &, hipStream_t, int);
-template void launch_toe_product<double>(const DevOperator<double> &, const ToeDev<double> &, hipStream_t, int);
+template void launch_toe_product<float>(const DevOperator<float> &, const ToeDev<float> &, hipStream_t, int, int);
+template void launch_toe_product<double>(const DevOperator<double> &, const ToeDev<double> &, hipStream_t, int, int);
 
 size_t toe_apply_lds_bytes(int ne_r, int nb, size_t elem) { return elem * 4 * (size_t)ne_r * nb; }
 
