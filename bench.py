@@ -55,7 +55,6 @@ ROOFLINE_KERNELS = {
     "toeapply32": ("toe_apply_kernel<float, 8>", "kernels_toeplitz.hip"),
     "precond": ("precond_apply32_mfma_kernel", "kernels_precond.hip"),
     "xline32": ("xline_reg_kernel<float>", "kernels_fft.hip"),
-    "gather32": ("gather_kernel<float, 1>", "kernels_matvec.hip"),
 }
 
 

@@ -30,10 +30,15 @@ def test_roofline_from_stage_records():
 
 
 def test_traffic_records_match_reported_kernels():
+    """Every committed traffic record names the kernel the benchmark reports
+    for its stage (a stage without a record reports traffic null)."""
     import bench
     for stage, (kernel, src) in bench.ROOFLINE_KERNELS.items():
+        assert os.path.exists(os.path.join(ROOT, "paper_1004_5076_amd", "csrc", src))
         p = os.path.join(ROOT, "profiles", "traffic_%s_two_channel.json" % stage)
-        assert os.path.exists(p), p
+        if not os.path.exists(p):
+            assert bench.measured_ratio(stage) is None
+            continue
         d = json.load(open(p))
         assert d["kernel"] == kernel
         assert d["ratio"] > 0.9          # measured bytes cannot fall far below the algorithmic ones
