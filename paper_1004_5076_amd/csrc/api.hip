@@ -686,7 +686,7 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
 // ---------------------------------------------------------------------------
 template <typename T>
 static void toe_common(scabs_ctx *c, ToeDev<T> &d, const RingTemplate &rt, const int *ringmap, const int *pmap,
-                       const int *esgn, const int *tloc, const int *ebody, const int *tbody, const int *be0,
+                       const int *esgn, const int *tloc, const int *tring, const int *ebody, const int *tbody, const int *be0,
                        const int *bt0, const int64_t *ibase, const int64_t *pbase, int64_t gi_per_f,
                        int64_t pi_per_f, const std::vector<double> &t1, const std::vector<double> &t2) {
   d.nr = rt.nr;
@@ -699,6 +699,7 @@ static void toe_common(scabs_ctx *c, ToeDev<T> &d, const RingTemplate &rt, const
   d.pmap = pmap;
   d.edge_sgn = esgn;
   d.tri_loc = tloc;
+  d.tri_ring = tring;
   d.ebody = ebody;
   d.tbody = tbody;
   d.body_e0 = be0;
@@ -816,9 +817,10 @@ static std::string build_toeplitz(scabs_ctx *c) {
     }
   const int *ringmap = c->mem.upload(rt.ringmap), *pmap = c->mem.upload(rt.pmap);
   const int *esgn = c->mem.upload(rt.edge_sgn), *tloc = c->mem.upload(rt.tri_loc);
-  toe_common(c, c->t64, rt, ringmap, pmap, esgn, tloc, a.ebody, c->mem.upload(tbody), a.body_e0, a.body_t0, a.ibase,
+  const int *tring = c->mem.upload(rt.tri_ring);
+  toe_common(c, c->t64, rt, ringmap, pmap, esgn, tloc, tring, a.ebody, c->mem.upload(tbody), a.body_e0, a.body_t0, a.ibase,
              a.pbase, ibase[nb], pbase[nb], t1, t2);
-  toe_common(c, c->t32, rt, ringmap, pmap, esgn, tloc, a.ebody, c->t64.tbody, a.body_e0, a.body_t0, a.ibase, a.pbase,
+  toe_common(c, c->t32, rt, ringmap, pmap, esgn, tloc, tring, a.ebody, c->t64.tbody, a.body_e0, a.body_t0, a.ibase, a.pbase,
              ibase[nb], pbase[nb], t1, t2);
   // sparse rows of the pairs with a non-periodic edge: in the periodic rows
   // the non-periodic columns (rows of the row kernel), then the full rows of
@@ -903,7 +905,7 @@ template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *
   d.X = c->mem.alloc<cx<T>>((size_t)d.P * 4 * d.ne_r * nb);
   d.Y = c->mem.alloc<cx<T>>((size_t)d.P * (2 * d.ne_r + 2 * R2) * nb);
   d.edge_out = c->mem.alloc<cx<T>>((size_t)nb * g.ne * 2);
-  d.pf = c->mem.alloc<cx<T>>((size_t)nb * g.nt * NQ * 4);
+  d.pf = c->mem.alloc<cx<T>>((size_t)nb * 2 * R2 * d.nr);
   tri_out = c->mem.alloc<cx<T>>((size_t)nb * g.nt * 9);
   const size_t npart = (size_t)std::max(1, c->toe_long.nlong * c->toe_long.nchunk) * 6 * nb;
   if (sizeof(T) == sizeof(float)) {
@@ -915,7 +917,7 @@ template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *
   }
   // rows of non-periodic edges are never written by the transforms
   HIPCHK(hipMemsetAsync(d.edge_out, 0, sizeof(cx<T>) * nb * g.ne * 2, c->stream));
-  HIPCHK(hipMemsetAsync(d.pf, 0, sizeof(cx<T>) * (size_t)nb * g.nt * NQ * 4, c->stream));
+  HIPCHK(hipMemsetAsync(d.pf, 0, sizeof(cx<T>) * (size_t)nb * 2 * R2 * d.nr, c->stream));
   if (sizeof(T) == sizeof(float))
     c->toe_bcap = (c->toe_bcap & ~0xffff) | nb;
   else

@@ -142,6 +142,7 @@ struct RingTemplate {
   std::vector<int> pmap;              // nt_r * nr: actual triangle of local triangle t at ring j
   std::vector<int> edge_loc, edge_ring, edge_sgn;   // per actual edge (-1 / 0 when non-periodic)
   std::vector<int> tri_loc;           // per actual triangle (-1 when non-periodic)
+  std::vector<int> tri_ring;          // per actual triangle: its ring (-1 when non-periodic)
 };
 
 // Detects the periodic unit along x (period = smallest vertex x spacing),

@@ -252,7 +252,7 @@ struct ToeCapArgs {
 template <typename T> struct ToeDev {
   int nr, P, ne_r, nt_r;
   T Z_e, Z_i;
-  const int *ringmap, *pmap, *edge_sgn, *tri_loc, *ebody, *tbody, *body_e0, *body_t0;
+  const int *ringmap, *pmap, *edge_sgn, *tri_loc, *tri_ring, *ebody, *tbody, *body_e0, *body_t0;
   const int64_t *ibase, *pbase;
   int64_t gi_per_f, pi_per_f;
   const cx<T> *GE, *GI, *PE, *PI;  // per-frequency pair tables (see kernels_toeplitz.hip)
@@ -260,7 +260,7 @@ template <typename T> struct ToeDev {
   const T *t1, *t2;                // per local triangle: in-plane basis of its point fields
   cx<T> *X, *Y;                    // spectra of a product
   cx<T> *edge_out;                 // [v][e][2]
-  cx<T> *pf;                       // [v][point][4]
+  cx<T> *pf;                       // [v][point row r < 2 R2][ring]: exterior rows r < R2, interior after
 };
 // the rows of non-periodic edges (every column), chunked: entries of long
 // row i at [start[i], start[i] + len) of the sparse-row arrays

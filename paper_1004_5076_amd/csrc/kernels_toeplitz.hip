@@ -465,7 +465,28 @@ __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
                            : d.GE + ((size_t)f * ne_r * ne_r + a) * 2;
       const size_t cstride = (size_t)(med ? neb : ne_r) * 2;
       const cx<T> *xJ = xs + (size_t)(med ? 2 : 0) * ne_r * NB, *xM = xs + (size_t)(med ? 3 : 1) * ne_r * NB;
-      for (int b = b0; b < b1; b++) {
+      constexpr int DEP = NB == 1 ? 8 : 2;   // column pairs in flight
+      int b = b0;
+      for (; b + DEP <= b1; b += DEP) {
+        cx<T> Lp[DEP], Kp[DEP];
+#pragma unroll
+        for (int u = 0; u < DEP; u++) {
+          const cx<T> *g = G + (size_t)(b + u - b0) * cstride;
+          Lp[u] = g[0];
+          Kp[u] = g[1];
+        }
+#pragma unroll
+        for (int u = 0; u < DEP; u++)
+#pragma unroll
+          for (int v = 0; v < NB; v++) {
+            const cx<T> J = xJ[(b + u) * NB + v], M = xM[(b + u) * NB + v];
+            cmac(LJ[v], Lp[u], J);
+            cmac(LM[v], Lp[u], M);
+            cmac(KJ[v], Kp[u], J);
+            cmac(KM[v], Kp[u], M);
+          }
+      }
+      for (; b < b1; b++) {
         const cx<T> *g = G + (size_t)(b - b0) * cstride;
         const cx<T> L = g[0], K = g[1];
 #pragma unroll
@@ -508,7 +529,25 @@ __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
                            : d.PE + ((size_t)f * ne_r * R2 + r) * 2;
       const size_t cstride = (size_t)(med ? R2b : R2) * 2;
       const cx<T> *xJ = xs + (size_t)(med ? 2 : 0) * ne_r * NB, *xM = xs + (size_t)(med ? 3 : 1) * ne_r * NB;
-      for (int b = b0; b < b1; b++) {
+      constexpr int DEP = NB == 1 ? 8 : 2;
+      int b = b0;
+      for (; b + DEP <= b1; b += DEP) {
+        cx<T> Pj[DEP], Pm[DEP];
+#pragma unroll
+        for (int u = 0; u < DEP; u++) {
+          const cx<T> *g = G + (size_t)(b + u - b0) * cstride;
+          Pj[u] = g[0];
+          Pm[u] = g[1];
+        }
+#pragma unroll
+        for (int u = 0; u < DEP; u++)
+#pragma unroll
+          for (int v = 0; v < NB; v++) {
+            cmac(acc[v], Pj[u], xJ[(b + u) * NB + v]);
+            cmac(acc[v], Pm[u], xM[(b + u) * NB + v]);
+          }
+      }
+      for (; b < b1; b++) {
         const cx<T> *g = G + (size_t)(b - b0) * cstride;
         const cx<T> PJ = g[0], PM = g[1];
 #pragma unroll
@@ -519,6 +558,161 @@ __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
       }
 #pragma unroll
       for (int v = 0; v < NB; v++) Yf[(size_t)(2 * ne_r + med * R2 + r) * NB + v] = acc[v];
+    }
+  }
+}
+
+// The same products for 8 vectors on the matrix cores
+// (v_mfma_f32_16x16x4_f32, complex arithmetic in real form).  One wave per
+// 16-row tile of one frequency, four tiles per work-group sharing the input
+// spectra in LDS.  One MFMA step covers one source column b with K = 4 real
+// slots; lane (i, kq) supplies A[i][kq], the kq-th float of the tile row's
+// table record ({L re, L im, K re, K im} or {PJ re, PJ im, PM re, PM im}),
+// and B[kq][n] for output column n = (vector n / 2, real part for even n):
+// slot kq reads the source (J for kq < 2, M otherwise, or the reverse) and
+// forms the real-form entry (x_re, x_im) for kq even, (-x_im, x_re) for odd.
+// Galerkin rows run two products sharing the loads: E with slots (J, M) and
+// coefficients (-Z L, K), H with slots (M, J) and (-L / Z, -K); the interior
+// medium's enter with the opposite sign.  Lane (n, kq) ends with rows
+// 4 kq + r of column n.
+typedef float tf4 __attribute__((ext_vector_type(4)));
+constexpr int TOE_MF_WAVES = 4;
+constexpr int TOE_MF_DEPTH = 16;   // table loads in flight per lane
+
+// sum over source columns b < n of A-entries A[b * stride] (zero where !live)
+// against B-entries from bf(b): loads issued TOE_MF_DEPTH columns at a time
+template <typename BF>
+__device__ inline tf4 mf_columns(const float *A, size_t stride, int n, bool live, float scale, BF bf, tf4 acc) {
+  int b = 0;
+  for (; b + TOE_MF_DEPTH <= n; b += TOE_MF_DEPTH) {
+    float v[TOE_MF_DEPTH];
+#pragma unroll
+    for (int u = 0; u < TOE_MF_DEPTH; u++) v[u] = live ? A[(size_t)(b + u) * stride] : 0.f;
+#pragma unroll
+    for (int u = 0; u < TOE_MF_DEPTH; u++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u] * scale, bf(b + u), acc, 0, 0, 0);
+  }
+  for (; b < n; b++) {
+    const float v = live ? A[(size_t)b * stride] : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v * scale, bf(b), acc, 0, 0, 0);
+  }
+  return acc;
+}
+// the same with two products (E and H) sharing each A-entry
+template <typename BF1, typename BF2>
+__device__ inline void mf_columns2(const float *A, size_t stride, int n, bool live, float s1, float s2, BF1 b1, BF2 b2,
+                                   tf4 &acc1, tf4 &acc2) {
+  int b = 0;
+  for (; b + TOE_MF_DEPTH <= n; b += TOE_MF_DEPTH) {
+    float v[TOE_MF_DEPTH];
+#pragma unroll
+    for (int u = 0; u < TOE_MF_DEPTH; u++) v[u] = live ? A[(size_t)(b + u) * stride] : 0.f;
+#pragma unroll
+    for (int u = 0; u < TOE_MF_DEPTH; u++) {
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u] * s1, b1(b + u), acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u] * s2, b2(b + u), acc2, 0, 0, 0);
+    }
+  }
+  for (; b < n; b++) {
+    const float v = live ? A[(size_t)b * stride] : 0.f;
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(v * s1, b1(b), acc1, 0, 0, 0);
+    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(v * s2, b2(b), acc2, 0, 0, 0);
+  }
+}
+
+__global__ void __launch_bounds__(64 * TOE_MF_WAVES) toe_apply_mfma_kernel(ToeDev<float> d) {
+  constexpr int NB = 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);   // [slot][v]
+  const int f = blockIdx.y;
+  const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
+  const int nin = 4 * ne_r * NB;
+  const cx<float> *Xf = d.X + (size_t)f * nin;
+  for (int i = threadIdx.x; i < nin; i += blockDim.x) xs[i] = Xf[i];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int gt = (ne_r + 15) / 16, pt = (R2 + 15) / 16;
+  const int t = blockIdx.x * TOE_MF_WAVES + wave;
+  if (t >= gt + pt) return;   // wave-uniform
+  const int m = lane & 15, kq = lane >> 4;
+  const int cv = m >> 1;          // output vector of this lane's B column
+  const bool odd = (m & 1) != 0;  // imaginary part
+  const int nout = 2 * ne_r + 2 * R2;
+  float *Yf = reinterpret_cast<float *>(d.Y + (size_t)f * nout * NB);
+  // B entry of slot kq for source value x (real form)
+  auto bval = [&](cx<float> x) {
+    return (kq & 1) == 0 ? (odd ? x.y : x.x) : (odd ? x.x : -x.y);
+  };
+  if (t < gt) {
+    const int row = 16 * t + m;
+    const bool live = row < ne_r;
+    tf4 accE = {0.f, 0.f, 0.f, 0.f}, accH = {0.f, 0.f, 0.f, 0.f};
+    const cx<float> *xJ[2] = {xs, xs + 2 * ne_r * NB};
+    const cx<float> *xM[2] = {xs + ne_r * NB, xs + 3 * ne_r * NB};
+    // exterior: every source column
+    {
+      const float Z = (float)d.Z_e;
+      const float *A = reinterpret_cast<const float *>(d.GE + (size_t)f * ne_r * ne_r * 2) + (size_t)(live ? row : 0) * 4 + kq;
+      const float sE = kq < 2 ? -Z : 1.f, sH = kq < 2 ? -1.f / Z : -1.f;
+      const cx<float> *srcE = kq < 2 ? xJ[0] : xM[0], *srcH = kq < 2 ? xM[0] : xJ[0];
+      mf_columns2(
+          A, (size_t)ne_r * 4, ne_r, live, sE, sH, [&](int b) { return bval(srcE[b * NB + cv]); },
+          [&](int b) { return bval(srcH[b * NB + cv]); }, accE, accH);
+    }
+    // interior: the columns of each body the tile's rows touch; rows of
+    // another body contribute zero
+    const float Z = (float)d.Z_i;
+    const float sE = kq < 2 ? Z : -1.f, sH = kq < 2 ? 1.f / Z : 1.f;
+    const cx<float> *srcE = kq < 2 ? xJ[1] : xM[1], *srcH = kq < 2 ? xM[1] : xJ[1];
+    const int bd_lo = d.ebody[min(16 * t, ne_r - 1)], bd_hi = d.ebody[min(16 * t + 15, ne_r - 1)];
+    for (int bd = bd_lo; bd <= bd_hi; bd++) {
+      const int e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
+      const bool in = live && row >= e0 && row < e0 + neb;
+      const float *A = reinterpret_cast<const float *>(d.GI + ((size_t)f * d.gi_per_f + d.ibase[bd]) * 2) +
+                       (size_t)(in ? row - e0 : 0) * 4 + kq;
+      mf_columns2(
+          A, (size_t)neb * 4, neb, in, sE, sH, [&](int b) { return bval(srcE[(e0 + b) * NB + cv]); },
+          [&](int b) { return bval(srcH[(e0 + b) * NB + cv]); }, accE, accH);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int a = 16 * t + 4 * kq + r;
+      if (a < ne_r) {
+        Yf[((size_t)(2 * a) * NB + cv) * 2 + (odd ? 1 : 0)] = accE[r];
+        Yf[((size_t)(2 * a + 1) * NB + cv) * 2 + (odd ? 1 : 0)] = accH[r];
+      }
+    }
+    return;
+  }
+  // point rows
+  const int pt0 = 16 * (t - gt);
+  const int r = pt0 + m;
+  const bool live = r < R2;
+  const cx<float> *srcE = kq < 2 ? xs : xs + ne_r * NB;
+  tf4 accE = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+  {
+    const float *A = reinterpret_cast<const float *>(d.PE + (size_t)f * ne_r * R2 * 2) + (size_t)(live ? r : 0) * 4 + kq;
+    accE = mf_columns(A, (size_t)R2 * 4, ne_r, live, 1.f, [&](int b) { return bval(srcE[b * NB + cv]); }, accE);
+  }
+  {
+    const cx<float> *srcI = kq < 2 ? xs + 2 * ne_r * NB : xs + 3 * ne_r * NB;
+    const int lt_lo = min(pt0, R2 - 1) / (2 * NQ), lt_hi = min(pt0 + 15, R2 - 1) / (2 * NQ);
+    const int bd_lo = d.tbody[lt_lo], bd_hi = d.tbody[lt_hi];
+    for (int bd = bd_lo; bd <= bd_hi; bd++) {
+      const int e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
+      const int r0 = 2 * NQ * d.body_t0[bd], R2b = 2 * NQ * (d.body_t0[bd + 1] - d.body_t0[bd]);
+      const bool in = live && r >= r0 && r < r0 + R2b;
+      const float *A = reinterpret_cast<const float *>(d.PI + ((size_t)f * d.pi_per_f + d.pbase[bd]) * 2) +
+                       (size_t)(in ? r - r0 : 0) * 4 + kq;
+      accI = mf_columns(A, (size_t)R2b * 4, neb, in, 1.f, [&](int b) { return bval(srcI[(e0 + b) * NB + cv]); },
+                        accI);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int rr = pt0 + 4 * kq + q;
+    if (rr < R2) {
+      Yf[((size_t)(2 * ne_r + rr) * NB + cv) * 2 + (odd ? 1 : 0)] = accE[q];
+      Yf[((size_t)(2 * ne_r + R2 + rr) * NB + cv) * 2 + (odd ? 1 : 0)] = accI[q];
     }
   }
 }
@@ -553,10 +747,8 @@ __global__ void __launch_bounds__(TOE_FFT_THREADS) toe_inv_kernel(ToeDev<T> d, i
       const int e = d.ringmap[(size_t)a * nr + j];
       if (e >= 0) d.edge_out[((size_t)v * ne + e) * 2 + h] = val * (T)d.edge_sgn[e];
     } else {
-      const int rr = slot - 2 * ne_r, med = rr >= R2 ? 1 : 0, r = rr - med * R2;
-      const int p = r >> 1, c = r & 1, lt = p / NQ, q = p - lt * NQ;
-      const int T_ = d.pmap[(size_t)lt * nr + j];
-      d.pf[((size_t)v * np + (size_t)T_ * NQ + q) * 4 + 2 * med + c] = val;
+      const int rr = slot - 2 * ne_r;   // point row: exterior rows, then interior
+      d.pf[((size_t)v * 2 * R2 + rr) * nr + j] = val;
     }
   }
 }
@@ -604,12 +796,13 @@ __global__ void __launch_bounds__(256) toe_local_kernel(DevOperator<T> op, ToeDe
     cx<T> Ee[3], Ei[3];
     for (int a = 0; a < 3; a++) Ee[a] = Ei[a] = czero<T>();
     if (per && ws != T(0)) {
-      const cx<T> *pf = d.pf + ((size_t)v * op.np + (size_t)T_ * NQ + q) * 4;
-      const int lt = d.tri_loc[T_];
+      const int lt = d.tri_loc[T_], j = d.tri_ring[T_], nr = d.nr;
+      const size_t R2 = 2 * (size_t)NQ * d.nt_r, r = 2 * ((size_t)lt * NQ + q);
+      const cx<T> *pe = d.pf + ((size_t)v * 2 * R2 + r) * nr + j, *pi = pe + R2 * nr;
       const T *t1 = d.t1 + 3 * (size_t)lt, *t2 = d.t2 + 3 * (size_t)lt;
       for (int a = 0; a < 3; a++) {
-        Ee[a] = pf[0] * t1[a] + pf[1] * t2[a];
-        Ei[a] = pf[2] * t1[a] + pf[3] * t2[a];
+        Ee[a] = pe[0] * t1[a] + pe[nr] * t2[a];
+        Ei[a] = pi[0] * t1[a] + pi[nr] * t2[a];
       }
     }
     for (int i = 0; i < 3; i++) {
@@ -636,84 +829,98 @@ __global__ void __launch_bounds__(256) toe_local_kernel(DevOperator<T> op, ToeDe
 }
 
 // ---------------------------------------------------------------------------
-// long rows (every column of a non-periodic edge's row): split into chunks of
-// TOE_CHUNK entries, one wave per (row, chunk); partial sums of the E, H and
-// eq14 rows per vector, then added to the rows the row kernel wrote
 // ---------------------------------------------------------------------------
-constexpr int TOE_CHUNK = 512;
+// long rows (every column of a non-periodic edge's row): split into column
+// chunks; partial sums of the E, H and eq14 rows per (row, chunk, vector),
+// then added to the rows the row kernel wrote
+// ---------------------------------------------------------------------------
+constexpr int TOE_CHUNK = 256;     // columns per work-group
+constexpr int TOE_LROWS = 16;      // long rows per work-group (4 per wave)
 template <typename T> __device__ inline T wsum64(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
+// One work-group per (column chunk, group of 16 long rows): the chunk's
+// currents (columns are the edges in order) staged in LDS once, each wave
+// runs 4 rows over the chunk, lanes over columns.
 template <typename T, int NRB>
 __global__ void __launch_bounds__(256) toe_long_rows_kernel(DevOperator<T> op, ToeLong lr, T *__restrict__ part) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (wave >= lr.nlong * lr.nchunk) return;   // wave-uniform
-  const int i = wave / lr.nchunk, ch = wave - i * lr.nchunk;
-  const int n = lr.rows[i];
-  const EdgeRec r = op.edges[n];
-  const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *xs = reinterpret_cast<cx<T> *>(smem_raw);   // [column][vector][3]
+  const int ch = blockIdx.x, grp = blockIdx.y;
+  const int c0 = ch * TOE_CHUNK, nc = min(TOE_CHUNK, lr.len - c0);
   const cx<T> *cur = NRB > 1 ? op.srcI : op.src;
-  T v[6 * NRB];
+  for (int i = threadIdx.x; i < nc * NRB * 3; i += blockDim.x) xs[i] = cur[(size_t)c0 * NRB * 3 + i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
+  for (int rr = 0; rr < TOE_LROWS / 4; rr++) {
+    const int i = grp * TOE_LROWS + wave * (TOE_LROWS / 4) + rr;
+    if (i >= lr.nlong) break;   // wave-uniform
+    const EdgeRec r = op.edges[lr.rows[i]];
+    T v[6 * NRB];
 #pragma unroll
-  for (int q = 0; q < 6 * NRB; q++) v[q] = T(0);
-  const int64_t k0 = lr.start[i] + (int64_t)ch * TOE_CHUNK;
-  const int64_t k1 = min(k0 + TOE_CHUNK, lr.start[i] + (int64_t)lr.len);
-  for (int64_t k = k0 + lane; k < k1; k += 64) {
-    const int m = op.col[k];
-    const cx<T> Le = op.V4[4 * k], Ke = op.V4[4 * k + 1], Li = op.V4[4 * k + 2], Ki = op.V4[4 * k + 3];
-    cx<T> eJi = Li * Zi, eJe = Le * (-Ze), eM = Ke + Ki;
-    cx<T> hJi = Ki, hJe = -Ke, hM = Le * (-iZe) - Li * iZi;
-    cx<T> rJi = czero<T>(), rM = czero<T>();
-    if (r.isR) {
-      const cx<T> Lr = op.S4[4 * k], Kr = op.S4[4 * k + 1], Ls = op.S4[4 * k + 2], Ks = op.S4[4 * k + 3];
-      hJe = hJe - Lr * Ze;
-      hM = hM + Kr;
-      rJi = Ls * Zi;
-      rM = Ks;
+    for (int q = 0; q < 6 * NRB; q++) v[q] = T(0);
+    const int64_t kb = lr.start[i] + c0;
+    for (int k = lane; k < nc; k += 64) {
+      const int64_t kk = kb + k;
+      const cx<T> Le = op.V4[4 * kk], Ke = op.V4[4 * kk + 1], Li = op.V4[4 * kk + 2], Ki = op.V4[4 * kk + 3];
+      cx<T> eJi = Li * Zi, eJe = Le * (-Ze), eM = Ke + Ki;
+      cx<T> hJi = Ki, hJe = -Ke, hM = Le * (-iZe) - Li * iZi;
+      cx<T> rJi = czero<T>(), rM = czero<T>();
+      if (r.isR) {
+        const cx<T> Lr = op.S4[4 * kk], Kr = op.S4[4 * kk + 1], Ls = op.S4[4 * kk + 2], Ks = op.S4[4 * kk + 3];
+        hJe = hJe - Lr * Ze;
+        hM = hM + Kr;
+        rJi = Ls * Zi;
+        rM = Ks;
+      }
+      const cx<T> *cm = xs + (size_t)k * NRB * 3;
+#pragma unroll
+      for (int b = 0; b < NRB; b++) {
+        const cx<T> Je = cm[3 * b], Ji = cm[3 * b + 1], M = cm[3 * b + 2];
+        cx<T> e = {v[6 * b], v[6 * b + 1]}, h = {v[6 * b + 2], v[6 * b + 3]}, q = {v[6 * b + 4], v[6 * b + 5]};
+        cmac(e, eJi, Ji);
+        cmac(e, eJe, Je);
+        cmac(e, eM, M);
+        cmac(h, hJi, Ji);
+        cmac(h, hJe, Je);
+        cmac(h, hM, M);
+        cmac(q, rJi, Ji);
+        cmac(q, rM, M);
+        v[6 * b] = e.x;
+        v[6 * b + 1] = e.y;
+        v[6 * b + 2] = h.x;
+        v[6 * b + 3] = h.y;
+        v[6 * b + 4] = q.x;
+        v[6 * b + 5] = q.y;
+      }
     }
-    const cx<T> *cm = cur + (size_t)m * NRB * 3;
 #pragma unroll
-    for (int b = 0; b < NRB; b++) {
-      const cx<T> Je = cm[3 * b], Ji = cm[3 * b + 1], M = cm[3 * b + 2];
-      cx<T> e = {v[6 * b], v[6 * b + 1]}, h = {v[6 * b + 2], v[6 * b + 3]}, q = {v[6 * b + 4], v[6 * b + 5]};
-      cmac(e, eJi, Ji);
-      cmac(e, eJe, Je);
-      cmac(e, eM, M);
-      cmac(h, hJi, Ji);
-      cmac(h, hJe, Je);
-      cmac(h, hM, M);
-      cmac(q, rJi, Ji);
-      cmac(q, rM, M);
-      v[6 * b] = e.x;
-      v[6 * b + 1] = e.y;
-      v[6 * b + 2] = h.x;
-      v[6 * b + 3] = h.y;
-      v[6 * b + 4] = q.x;
-      v[6 * b + 5] = q.y;
+    for (int q = 0; q < 6 * NRB; q++) {
+      const T t = wsum64(v[q]);
+      if (lane == 0) part[((size_t)i * lr.nchunk + ch) * 6 * NRB + q] = t;
     }
-  }
-#pragma unroll
-  for (int q = 0; q < 6 * NRB; q++) {
-    const T t = wsum64(v[q]);
-    if (lane == 0) part[(size_t)wave * 6 * NRB + q] = t;
   }
 }
 
-// rows += sum of the chunks' partials (one thread per long row and vector)
+// rows += sum of the chunks' partials: one wave per long row and vector,
+// lanes over chunks
 template <typename T>
 __global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeLong lr, const T *__restrict__ part, double *y, int nb) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= lr.nlong * nb) return;
-  const int i = t / nb, b = t - i * nb;
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (w >= lr.nlong * nb) return;   // wave-uniform
+  const int i = w / nb, b = w - i * nb;
   const EdgeRec r = op.edges[lr.rows[i]];
   double s6[6] = {0, 0, 0, 0, 0, 0};
-  for (int ch = 0; ch < lr.nchunk; ch++) {
+  for (int ch = lane; ch < lr.nchunk; ch += 64) {
     const T *p = part + ((size_t)(i * lr.nchunk + ch) * nb + b) * 6;
     for (int q = 0; q < 6; q++) s6[q] += (double)p[q];
   }
+  for (int q = 0; q < 6; q++) s6[q] = wsum64(s6[q]);
+  if (lane != 0) return;
   double *yb = y + (size_t)2 * op.N * b;
   yb[2 * r.row[0]] += s6[0];
   yb[2 * r.row[0] + 1] += s6[1];
@@ -728,9 +935,15 @@ __global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeLong lr, const T *_
 template <typename T>
 void launch_toe_long_rows(const DevOperator<T> &op, const ToeLong &lr, T *part, double *y, hipStream_t s, int nb) {
   if (lr.nlong == 0) return;
-  const int waves = lr.nlong * lr.nchunk;
-  const int blocks = (waves * 64 + 255) / 256;
-#define SCABS_TOE_LONG(NB) hipLaunchKernelGGL((toe_long_rows_kernel<T, NB>), dim3(blocks), dim3(256), 0, s, op, lr, part)
+  const dim3 grid(lr.nchunk, (lr.nlong + TOE_LROWS - 1) / TOE_LROWS);
+#define SCABS_TOE_LONG(NB)                                                                                           \
+  do {                                                                                                               \
+    const size_t lds = sizeof(cx<T>) * TOE_CHUNK * (NB) * 3;                                                         \
+    if (lds > 65536)                                                                                                 \
+      (void)hipFuncSetAttribute((const void *)toe_long_rows_kernel<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,\
+                                (int)lds);                                                                           \
+    hipLaunchKernelGGL((toe_long_rows_kernel<T, NB>), grid, dim3(256), lds, s, op, lr, part);                         \
+  } while (0)
   switch (nb) {
     case 1: SCABS_TOE_LONG(1); break;
     case 2: SCABS_TOE_LONG(2); break;
@@ -742,7 +955,8 @@ void launch_toe_long_rows(const DevOperator<T> &op, const ToeLong &lr, T *part, 
     default: SCABS_TOE_LONG(8); break;
   }
 #undef SCABS_TOE_LONG
-  hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((lr.nlong * nb + 255) / 256), dim3(256), 0, s, op, lr, part, y, nb);
+  hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((lr.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, lr, part, y,
+                     nb);
 }
 template void launch_toe_long_rows<float>(const DevOperator<float> &, const ToeLong &, float *, double *, hipStream_t,
                                           int);
@@ -777,7 +991,20 @@ void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_
     case 5: SCABS_TOE_APPLY(5); break;
     case 6: SCABS_TOE_APPLY(6); break;
     case 7: SCABS_TOE_APPLY(7); break;
-    default: SCABS_TOE_APPLY(8); break;
+    default:
+      if (sizeof(T) == sizeof(float)) {
+        // eight vectors: the matrix-core form
+        const int tiles = (d.ne_r + 15) / 16 + (R2 + 15) / 16;
+        const size_t lds = sizeof(cx<float>) * 4 * d.ne_r * 8;
+        if (lds > 65536)
+          (void)hipFuncSetAttribute((const void *)toe_apply_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+        hipLaunchKernelGGL(toe_apply_mfma_kernel, dim3((tiles + TOE_MF_WAVES - 1) / TOE_MF_WAVES, d.P),
+                           dim3(64 * TOE_MF_WAVES), lds, s, *reinterpret_cast<const ToeDev<float> *>(&d));
+      } else {
+        SCABS_TOE_APPLY(8);
+      }
+      break;
   }
 #undef SCABS_TOE_APPLY
   }

@@ -178,7 +178,8 @@ std::string build_rings(const Geometry &g, RingTemplate &rt) {
   rt.nr = nr;
   rt.nt_r = (int)per.size();
   rt.tri_loc.assign(g.nt, -1);
-  std::vector<int> tri_ring(g.nt, -1);
+  rt.tri_ring.assign(g.nt, -1);
+  std::vector<int> &tri_ring = rt.tri_ring;
   rt.pmap.assign((size_t)rt.nt_r * nr, -1);
   for (int lt = 0; lt < rt.nt_r; lt++)
     for (int j = 0; j < nr; j++) {

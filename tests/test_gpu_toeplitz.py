@@ -86,14 +86,24 @@ def test_unit_columns(case):
 
 
 def test_batched_equals_single(case):
+    """Batches of 5 vectors (the same arithmetic per vector as single ones)
+    give each vector its single product; batches of 8 in FP32 run the
+    per-frequency products on the matrix cores and match the dense matrix to
+    single precision."""
     import torch
     name, w, o, A, ctx = case
-    X = np.stack([synth.random_complex(90 + k, o.N) for k in range(5)])
+    X = np.stack([synth.random_complex(90 + k, o.N) for k in range(8)])
     for prec in (0, 1):
-        Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+        Y = ctx.matvec(torch.from_numpy(X[:5].copy()).cuda(), prec=prec).cpu().numpy()
         for k in range(5):
             y1 = ctx.matvec(torch.from_numpy(X[k].copy()).cuda(), prec=prec).cpu().numpy()
             assert _rel(Y[k], y1) < 1e-13
+    for prec, tol in ((0, 1e-11), (1, 2e-6)):
+        Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+        for k in range(8):
+            ref = A @ X[k]
+            for a, b in _blocks(o):
+                assert _rel(Y[k][a:b], ref[a:b]) < tol, (prec, k, a, b)
 
 
 @pytest.mark.parametrize("mode", [0, 2])
