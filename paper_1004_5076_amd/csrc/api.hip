@@ -200,16 +200,16 @@ struct scabs_ctx {
   ToeDev<float> t32{};
   int toe_bcap = 0;
   int64_t toe_nnz = 0;
-  int64_t *toe_rowptr = nullptr;
-  int *toe_col = nullptr;
-  cx<double> *toe_V4 = nullptr, *toe_S4 = nullptr;
+  cx<double> *toe_V4 = nullptr, *toe_S4 = nullptr;   // column-major entries: short part, then long part
   cx<float> *toe_V4f = nullptr, *toe_S4f = nullptr;
+  int64_t toe_nshort = 0;
+  const int *toe_capcol = nullptr, *toe_esgn = nullptr;
   cx<double> *toe_tri64 = nullptr;
   cx<float> *toe_tri32 = nullptr;
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
-  ToeLong toe_long{};
-  double *toe_part64 = nullptr;
-  float *toe_part32 = nullptr;
+  int toe_ncap = 0;
+  double *toe_part64 = nullptr, *toe_rpart64 = nullptr;
+  float *toe_part32 = nullptr, *toe_rpart32 = nullptr;
 };
 
 // RAII stage timer: records a start/end event pair on the context stream
@@ -817,47 +817,38 @@ static std::string build_toeplitz(scabs_ctx *c) {
     }
   const int *ringmap = c->mem.upload(rt.ringmap), *pmap = c->mem.upload(rt.pmap);
   const int *esgn = c->mem.upload(rt.edge_sgn), *tloc = c->mem.upload(rt.tri_loc);
+  const int *esgn_dev = esgn;
   const int *tring = c->mem.upload(rt.tri_ring);
   toe_common(c, c->t64, rt, ringmap, pmap, esgn, tloc, tring, a.ebody, c->mem.upload(tbody), a.body_e0, a.body_t0, a.ibase,
              a.pbase, ibase[nb], pbase[nb], t1, t2);
   toe_common(c, c->t32, rt, ringmap, pmap, esgn, tloc, tring, a.ebody, c->t64.tbody, a.body_e0, a.body_t0, a.ibase, a.pbase,
              ibase[nb], pbase[nb], t1, t2);
-  // sparse rows of the pairs with a non-periodic edge: in the periodic rows
-  // the non-periodic columns (rows of the row kernel), then the full rows of
-  // the non-periodic edges (long rows, chunked); one entry array for both
+  // exact entries of the pairs with a non-periodic edge, column-major: the
+  // short part (every row against each non-periodic column; read by the
+  // periodic rows), then the long part (each non-periodic row against every
+  // column)
   std::vector<int> nonper;
   for (int n = 0; n < g.ne; n++)
     if (rt.edge_loc[n] < 0) nonper.push_back(n);
-  std::vector<int64_t> rowptr(g.ne + 1, 0);
-  for (int n = 0; n < g.ne; n++) rowptr[n + 1] = rowptr[n] + (rt.edge_loc[n] < 0 ? 0 : (int64_t)nonper.size());
-  const int64_t nshort = rowptr[g.ne];
-  const int64_t nnz = nshort + (int64_t)nonper.size() * g.ne;
+  const int64_t ncap = (int64_t)nonper.size();
+  const int64_t nshort = ncap * g.ne;
+  const int64_t nnz = 2 * nshort;
   std::vector<int> rows(nnz), cols(nnz);
-  for (int n = 0; n < g.ne; n++) {
-    int64_t k = rowptr[n];
-    if (rt.edge_loc[n] < 0) continue;
-    for (int m : nonper) {
-      rows[k] = n;
-      cols[k++] = m;
+  for (int64_t j = 0; j < ncap; j++)
+    for (int n = 0; n < g.ne; n++) {
+      rows[j * g.ne + n] = n;
+      cols[j * g.ne + n] = nonper[j];
     }
-  }
-  std::vector<int64_t> lstart(nonper.size());
-  for (size_t i = 0; i < nonper.size(); i++) {
-    int64_t k = nshort + (int64_t)i * g.ne;
-    lstart[i] = k;
-    for (int m = 0; m < g.ne; m++, k++) {
-      rows[k] = nonper[i];
-      cols[k] = m;
+  for (int m = 0; m < g.ne; m++)
+    for (int64_t i = 0; i < ncap; i++) {
+      rows[nshort + (int64_t)m * ncap + i] = nonper[i];
+      cols[nshort + (int64_t)m * ncap + i] = m;
     }
-  }
-  c->toe_long.nlong = (int)nonper.size();
-  c->toe_long.len = g.ne;
-  c->toe_long.nchunk = (g.ne + toe_chunk() - 1) / toe_chunk();
-  c->toe_long.rows = c->mem.upload(nonper);
-  c->toe_long.start = c->mem.upload(lstart);
+  c->toe_ncap = (int)ncap;
+  c->toe_nshort = nshort;
+  c->toe_capcol = c->mem.upload(nonper);
+  c->toe_esgn = esgn_dev;
   c->toe_nnz = nnz;
-  c->toe_rowptr = c->mem.upload(rowptr);
-  c->toe_col = c->mem.upload(cols);
   c->toe_V4 = c->mem.alloc<cx<double>>(4 * (size_t)nnz);
   c->toe_S4 = c->mem.alloc<cx<double>>(4 * (size_t)nnz);
   c->toe_V4f = c->mem.alloc<cx<float>>(4 * (size_t)nnz);
@@ -869,7 +860,7 @@ static std::string build_toeplitz(scabs_ctx *c) {
     ToeCapArgs ca{};
     ca.nnz = nnz;
     ca.row = tmp.upload(rows);
-    ca.col = c->toe_col;
+    ca.col = tmp.upload(cols);
     ca.et = tmp.upload(g.et);
     ca.tedge = tmp.upload(g.tedge);
     ca.tri = tmp.upload(all);
@@ -907,13 +898,18 @@ template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *
   d.edge_out = c->mem.alloc<cx<T>>((size_t)nb * g.ne * 2);
   d.pf = c->mem.alloc<cx<T>>((size_t)nb * 2 * R2 * d.nr);
   tri_out = c->mem.alloc<cx<T>>((size_t)nb * g.nt * 9);
-  const size_t npart = (size_t)std::max(1, c->toe_long.nlong * c->toe_long.nchunk) * 6 * nb;
+  const size_t npart = (size_t)std::max(1, c->toe_ncap * ((g.ne + toe_long_chunk() - 1) / toe_long_chunk())) * 6 * nb;
+  const size_t nrpart = (size_t)toe_row_groups() * nb * 6 * g.ne;
   if (sizeof(T) == sizeof(float)) {
     if (c->toe_part32) c->mem.free_one(c->toe_part32);
+    if (c->toe_rpart32) c->mem.free_one(c->toe_rpart32);
     c->toe_part32 = c->mem.alloc<float>(npart);
+    c->toe_rpart32 = c->mem.alloc<float>(nrpart);
   } else {
     if (c->toe_part64) c->mem.free_one(c->toe_part64);
+    if (c->toe_rpart64) c->mem.free_one(c->toe_rpart64);
     c->toe_part64 = c->mem.alloc<double>(npart);
+    c->toe_rpart64 = c->mem.alloc<double>(nrpart);
   }
   // rows of non-periodic edges are never written by the transforms
   HIPCHK(hipMemsetAsync(d.edge_out, 0, sizeof(cx<T>) * nb * g.ne * 2, c->stream));
@@ -1243,6 +1239,8 @@ template <typename T> static void apply_t(scabs_ctx *c, PrecState<T> &P, const d
 
 static float *toe_part(scabs_ctx *c, float *) { return c->toe_part32; }
 static double *toe_part(scabs_ctx *c, double *) { return c->toe_part64; }
+static float *toe_rpart(scabs_ctx *c, float *) { return c->toe_rpart32; }
+static double *toe_rpart(scabs_ctx *c, double *) { return c->toe_rpart64; }
 
 // y = A x by the block-Toeplitz product for nb vectors: currents per edge,
 // ring-axis transforms, per-frequency block products, inverse transforms,
@@ -1255,13 +1253,22 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
   toe_ensure(c, d, tri_out, nb);
   DevOperator<T> op = P.op;
-  op.rowptr = c->toe_rowptr;
-  op.col = c->toe_col;
-  op.V4 = sizeof(T) == sizeof(float) ? (const cx<T> *)c->toe_V4f : (const cx<T> *)c->toe_V4;
-  op.S4 = sizeof(T) == sizeof(float) ? (const cx<T> *)c->toe_S4f : (const cx<T> *)c->toe_S4;
-  op.V4T = op.S4T = nullptr;
   op.tri_out = tri_out;
   op.edge_out = d.edge_out;
+  const bool f32 = sizeof(T) == sizeof(float);
+  const cx<T> *V4 = f32 ? (const cx<T> *)c->toe_V4f : (const cx<T> *)c->toe_V4;
+  const cx<T> *S4 = f32 ? (const cx<T> *)c->toe_S4f : (const cx<T> *)c->toe_S4;
+  ToeRows<T> R;
+  R.ncap = R.nlong = c->toe_ncap;
+  R.nchunk = (c->geo.ne + toe_long_chunk() - 1) / toe_long_chunk();
+  R.capcol = c->toe_capcol;
+  R.edge_sgn = c->toe_esgn;
+  R.V4S = V4;
+  R.S4S = S4;
+  R.V4L = V4 + 4 * (size_t)c->toe_nshort;
+  R.S4L = S4 + 4 * (size_t)c->toe_nshort;
+  R.part = toe_part(c, (T *)nullptr);
+  R.rpart = toe_rpart(c, (T *)nullptr);
   {
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
     launch_unpack(op, x, s, nb);
@@ -1282,8 +1289,7 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   }
   {
     StageTimer t(c, SCABS_STAGE_NEAR + off);
-    launch_near_rows(op, y, s, nb);
-    launch_toe_long_rows(op, c->toe_long, toe_part(c, (T *)nullptr), y, s, nb);
+    launch_toe_rows(op, R, y, s, nb);
   }
 }
 

@@ -262,16 +262,22 @@ template <typename T> struct ToeDev {
   cx<T> *edge_out;                 // [v][e][2]
   cx<T> *pf;                       // [v][point row r < 2 R2][ring]: exterior rows r < R2, interior after
 };
-// the rows of non-periodic edges (every column), chunked: entries of long
-// row i at [start[i], start[i] + len) of the sparse-row arrays
-struct ToeLong {
-  int nlong, nchunk, len;
-  const int *rows;
-  const int64_t *start;
+// exact entries of the pairs with a non-periodic edge, column-major: short
+// part V4S/S4S[(j ne + n) 4 + t] (row n, non-periodic column capcol[j]),
+// long part V4L/S4L[(m nlong + i) 4 + t] (non-periodic row capcol[i],
+// column m); 4 sigma-free values (L_e, K_e, L_i, K_i) and 4 sigma values
+// (Lrot_e, Krot_e, Lsig_i, Ksig_i) per entry
+template <typename T> struct ToeRows {
+  int ncap, nlong, nchunk;
+  const int *capcol;      // the non-periodic edges
+  const int *edge_sgn;    // per edge: 0 for non-periodic edges
+  const cx<T> *V4S, *S4S, *V4L, *S4L;
+  T *part;                // [chunk][row][vector][6] partial sums of the long rows
+  T *rpart;               // [group][vector][6][edge] partial sums of the periodic rows
 };
-template <typename T>
-void launch_toe_long_rows(const DevOperator<T> &op, const ToeLong &lr, T *part, double *y, hipStream_t s, int nb);
-int toe_chunk();
+template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb);
+int toe_long_chunk();
+int toe_row_groups();
 void launch_toe_setup(const ToeSetupArgs &s, hipStream_t st);
 void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st);
 void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s);

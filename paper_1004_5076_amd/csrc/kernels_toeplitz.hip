@@ -565,154 +565,184 @@ __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
 // The same products for 8 vectors on the matrix cores
 // (v_mfma_f32_16x16x4_f32, complex arithmetic in real form).  One wave per
 // 16-row tile of one frequency, four tiles per work-group sharing the input
-// spectra in LDS.  One MFMA step covers one source column b with K = 4 real
-// slots; lane (i, kq) supplies A[i][kq], the kq-th float of the tile row's
-// table record ({L re, L im, K re, K im} or {PJ re, PJ im, PM re, PM im}),
-// and B[kq][n] for output column n = (vector n / 2, real part for even n):
-// slot kq reads the source (J for kq < 2, M otherwise, or the reverse) and
-// forms the real-form entry (x_re, x_im) for kq even, (-x_im, x_re) for odd.
+// spectra in LDS.  A tile row's table record for source column c is four
+// floats ({L re, L im, K re, K im} or {PJ re, PJ im, PM re, PM im}); lane
+// (i, kq) loads the whole record of row i, column 4 g + kq (one 16-byte load
+// per lane per group g of four columns) and MFMA step j of the group takes
+// slot j of it: A[i][kq] = record j of column 4 g + kq, B[kq][n] = the
+// real-form entry of that column for output column n (vector n / 2, real
+// part for even n).  Slot j reads the source (J for j < 2, M otherwise, or
+// the reverse) and forms (x_re, x_im) for j even, (-x_im, x_re) for odd.
 // Galerkin rows run two products sharing the loads: E with slots (J, M) and
 // coefficients (-Z L, K), H with slots (M, J) and (-L / Z, -K); the interior
 // medium's enter with the opposite sign.  Lane (n, kq) ends with rows
 // 4 kq + r of column n.
 typedef float tf4 __attribute__((ext_vector_type(4)));
 constexpr int TOE_MF_WAVES = 4;
-constexpr int TOE_MF_DEPTH = 16;   // table loads in flight per lane
+constexpr int TOE_MF_DEPTH = 4;   // 16-byte table loads per lane per chunk (two chunks in flight)
 
-// sum over source columns b < n of A-entries A[b * stride] (zero where !live)
-// against B-entries from bf(b): loads issued TOE_MF_DEPTH columns at a time
-template <typename BF>
-__device__ inline tf4 mf_columns(const float *A, size_t stride, int n, bool live, float scale, BF bf, tf4 acc) {
-  int b = 0;
-  for (; b + TOE_MF_DEPTH <= n; b += TOE_MF_DEPTH) {
-    float v[TOE_MF_DEPTH];
-#pragma unroll
-    for (int u = 0; u < TOE_MF_DEPTH; u++) v[u] = live ? A[(size_t)(b + u) * stride] : 0.f;
-#pragma unroll
-    for (int u = 0; u < TOE_MF_DEPTH; u++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u] * scale, bf(b + u), acc, 0, 0, 0);
-  }
-  for (; b < n; b++) {
-    const float v = live ? A[(size_t)b * stride] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v * scale, bf(b), acc, 0, 0, 0);
-  }
-  return acc;
+// real-form B entry of slot j for a lane of output column n (odd: imaginary)
+__device__ inline float mf_form(cx<float> x, int j, bool odd) {
+  return (j & 1) == 0 ? (odd ? x.y : x.x) : (odd ? x.x : -x.y);
 }
-// the same with two products (E and H) sharing each A-entry
-template <typename BF1, typename BF2>
-__device__ inline void mf_columns2(const float *A, size_t stride, int n, bool live, float s1, float s2, BF1 b1, BF2 b2,
-                                   tf4 &acc1, tf4 &acc2) {
-  int b = 0;
-  for (; b + TOE_MF_DEPTH <= n; b += TOE_MF_DEPTH) {
-    float v[TOE_MF_DEPTH];
+
+// chunk of TOE_MF_DEPTH column groups starting at group q0 of row records
+// Arow[c * stride] (zero where !live or c >= n; groups past the last are
+// skipped and left zero); the address is clamped so every load is in bounds
+__device__ inline void mf_load(const float *Arow, size_t stride, int n, bool live, int kq, int q0,
+                               tf4 (&v)[TOE_MF_DEPTH]) {
+  const int nq = (n + 3) >> 2;
 #pragma unroll
-    for (int u = 0; u < TOE_MF_DEPTH; u++) v[u] = live ? A[(size_t)(b + u) * stride] : 0.f;
-#pragma unroll
-    for (int u = 0; u < TOE_MF_DEPTH; u++) {
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u] * s1, b1(b + u), acc1, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u] * s2, b2(b + u), acc2, 0, 0, 0);
+  for (int u = 0; u < TOE_MF_DEPTH; u++) {
+    v[u] = tf4{0.f, 0.f, 0.f, 0.f};
+    if (q0 + u < nq) {   // uniform
+      const int c = 4 * (q0 + u) + kq;
+      const tf4 t = *reinterpret_cast<const tf4 *>(Arow + (size_t)(c < n ? c : n - 1) * stride);
+      if (live && c < n) v[u] = t;
     }
   }
-  for (; b < n; b++) {
-    const float v = live ? A[(size_t)b * stride] : 0.f;
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(v * s1, b1(b), acc1, 0, 0, 0);
-    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(v * s2, b2(b), acc2, 0, 0, 0);
+}
+
+// acc[k] += sum over source columns c < n of the row records (see mf_load)
+// against the B-entries bf(c, bv) fills for c; v holds the first chunk,
+// loaded by the caller; each chunk's successor is loaded before its MFMAs.
+// Lanes past the last column take column 0's (finite) B-entries against a
+// zero record.
+template <int NACC, typename BF>
+__device__ inline void mf_quads(const float *Arow, size_t stride, int n, bool live, int kq, BF bf, tf4 (&acc)[NACC],
+                                tf4 (&v)[TOE_MF_DEPTH]) {
+  const int nq = (n + 3) >> 2;
+  for (int q0 = 0; q0 < nq; q0 += TOE_MF_DEPTH) {
+    tf4 w[TOE_MF_DEPTH];
+    mf_load(Arow, stride, n, live, kq, q0 + TOE_MF_DEPTH, w);
+#pragma unroll
+    for (int u = 0; u < TOE_MF_DEPTH; u++) {
+      if (q0 + u >= nq) break;   // uniform
+      const int c = 4 * (q0 + u) + kq;
+      float bv[NACC][4];
+      bf(c < n ? c : 0, bv);
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+#pragma unroll
+        for (int k = 0; k < NACC; k++) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[u][j], bv[k][j], acc[k], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < TOE_MF_DEPTH; u++) v[u] = w[u];
   }
 }
+
+// Galerkin E/H B-entries of column c from sources xJ, xM with E scales
+// (sJ, sJ, sM, sM) and H scales (hM, hM, hJ, hJ)
+struct MfGalerkinB {
+  const cx<float> *xJ, *xM;
+  float sJ, sM, hM, hJ;
+  int cv;
+  bool odd;
+  __device__ void operator()(int c, float (&bv)[2][4]) const {
+    const cx<float> x = xJ[c * 8 + cv], y = xM[c * 8 + cv];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      bv[0][j] = sJ * mf_form(x, j, odd);
+      bv[0][j + 2] = sM * mf_form(y, j, odd);
+      bv[1][j] = hM * mf_form(y, j, odd);
+      bv[1][j + 2] = hJ * mf_form(x, j, odd);
+    }
+  }
+};
+// point-field B-entries: slots (J, J, M, M) of column c
+struct MfPointB {
+  const cx<float> *xJ, *xM;
+  int cv;
+  bool odd;
+  __device__ void operator()(int c, float (&bv)[1][4]) const {
+    const cx<float> x = xJ[c * 8 + cv], y = xM[c * 8 + cv];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      bv[0][j] = mf_form(x, j, odd);
+      bv[0][j + 2] = mf_form(y, j, odd);
+    }
+  }
+};
 
 __global__ void __launch_bounds__(64 * TOE_MF_WAVES) toe_apply_mfma_kernel(ToeDev<float> d) {
   constexpr int NB = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);   // [slot][v]
+  cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);   // [slot][column][v]
   const int f = blockIdx.y;
   const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
+  const int gt = (ne_r + 15) / 16, pt = (R2 + 15) / 16;
+  const int t = blockIdx.x * TOE_MF_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+  // the exterior table rows of this wave's tile, first chunk loaded before
+  // the spectra are staged (it does not depend on them)
+  const bool gal = t < gt;
+  const int row = gal ? 16 * t + m : 16 * (t - gt) + m;
+  const bool live = t < gt + pt && row < (gal ? ne_r : R2);
+  const float *Aext =
+      gal ? reinterpret_cast<const float *>(d.GE + (size_t)f * ne_r * ne_r * 2) + (size_t)(live ? row : 0) * 4
+          : reinterpret_cast<const float *>(d.PE + (size_t)f * ne_r * R2 * 2) + (size_t)(live ? row : 0) * 4;
+  const size_t sext = (size_t)(gal ? ne_r : R2) * 4;
+  tf4 v[TOE_MF_DEPTH];
+  mf_load(Aext, sext, ne_r, live, kq, 0, v);
   const int nin = 4 * ne_r * NB;
   const cx<float> *Xf = d.X + (size_t)f * nin;
   for (int i = threadIdx.x; i < nin; i += blockDim.x) xs[i] = Xf[i];
   __syncthreads();
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int gt = (ne_r + 15) / 16, pt = (R2 + 15) / 16;
-  const int t = blockIdx.x * TOE_MF_WAVES + wave;
-  if (t >= gt + pt) return;   // wave-uniform
-  const int m = lane & 15, kq = lane >> 4;
-  const int cv = m >> 1;          // output vector of this lane's B column
-  const bool odd = (m & 1) != 0;  // imaginary part
+  if (t >= gt + pt) return;
+  const int cv = m >> 1;
+  const bool odd = (m & 1) != 0;
   const int nout = 2 * ne_r + 2 * R2;
   float *Yf = reinterpret_cast<float *>(d.Y + (size_t)f * nout * NB);
-  // B entry of slot kq for source value x (real form)
-  auto bval = [&](cx<float> x) {
-    return (kq & 1) == 0 ? (odd ? x.y : x.x) : (odd ? x.x : -x.y);
-  };
-  if (t < gt) {
-    const int row = 16 * t + m;
-    const bool live = row < ne_r;
-    tf4 accE = {0.f, 0.f, 0.f, 0.f}, accH = {0.f, 0.f, 0.f, 0.f};
-    const cx<float> *xJ[2] = {xs, xs + 2 * ne_r * NB};
-    const cx<float> *xM[2] = {xs + ne_r * NB, xs + 3 * ne_r * NB};
-    // exterior: every source column
+  const cx<float> *xJe = xs, *xMe = xs + ne_r * NB, *xJi = xs + 2 * ne_r * NB, *xMi = xs + 3 * ne_r * NB;
+  if (gal) {
+    tf4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     {
       const float Z = (float)d.Z_e;
-      const float *A = reinterpret_cast<const float *>(d.GE + (size_t)f * ne_r * ne_r * 2) + (size_t)(live ? row : 0) * 4 + kq;
-      const float sE = kq < 2 ? -Z : 1.f, sH = kq < 2 ? -1.f / Z : -1.f;
-      const cx<float> *srcE = kq < 2 ? xJ[0] : xM[0], *srcH = kq < 2 ? xM[0] : xJ[0];
-      mf_columns2(
-          A, (size_t)ne_r * 4, ne_r, live, sE, sH, [&](int b) { return bval(srcE[b * NB + cv]); },
-          [&](int b) { return bval(srcH[b * NB + cv]); }, accE, accH);
+      mf_quads<2>(Aext, sext, ne_r, live, kq, MfGalerkinB{xJe, xMe, -Z, 1.f, -1.f / Z, -1.f, cv, odd}, acc, v);
     }
-    // interior: the columns of each body the tile's rows touch; rows of
-    // another body contribute zero
     const float Z = (float)d.Z_i;
-    const float sE = kq < 2 ? Z : -1.f, sH = kq < 2 ? 1.f / Z : 1.f;
-    const cx<float> *srcE = kq < 2 ? xJ[1] : xM[1], *srcH = kq < 2 ? xM[1] : xJ[1];
     const int bd_lo = d.ebody[min(16 * t, ne_r - 1)], bd_hi = d.ebody[min(16 * t + 15, ne_r - 1)];
     for (int bd = bd_lo; bd <= bd_hi; bd++) {
       const int e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
       const bool in = live && row >= e0 && row < e0 + neb;
       const float *A = reinterpret_cast<const float *>(d.GI + ((size_t)f * d.gi_per_f + d.ibase[bd]) * 2) +
-                       (size_t)(in ? row - e0 : 0) * 4 + kq;
-      mf_columns2(
-          A, (size_t)neb * 4, neb, in, sE, sH, [&](int b) { return bval(srcE[(e0 + b) * NB + cv]); },
-          [&](int b) { return bval(srcH[(e0 + b) * NB + cv]); }, accE, accH);
+                       (size_t)(in ? row - e0 : 0) * 4;
+      mf_load(A, (size_t)neb * 4, neb, in, kq, 0, v);
+      mf_quads<2>(A, (size_t)neb * 4, neb, in, kq,
+                  MfGalerkinB{xJi + e0 * NB, xMi + e0 * NB, Z, -1.f, 1.f / Z, 1.f, cv, odd}, acc, v);
     }
 #pragma unroll
     for (int r = 0; r < 4; r++) {
       const int a = 16 * t + 4 * kq + r;
       if (a < ne_r) {
-        Yf[((size_t)(2 * a) * NB + cv) * 2 + (odd ? 1 : 0)] = accE[r];
-        Yf[((size_t)(2 * a + 1) * NB + cv) * 2 + (odd ? 1 : 0)] = accH[r];
+        Yf[((size_t)(2 * a) * NB + cv) * 2 + (odd ? 1 : 0)] = acc[0][r];
+        Yf[((size_t)(2 * a + 1) * NB + cv) * 2 + (odd ? 1 : 0)] = acc[1][r];
       }
     }
     return;
   }
-  // point rows
   const int pt0 = 16 * (t - gt);
-  const int r = pt0 + m;
-  const bool live = r < R2;
-  const cx<float> *srcE = kq < 2 ? xs : xs + ne_r * NB;
-  tf4 accE = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+  tf4 accE[1] = {{0.f, 0.f, 0.f, 0.f}}, accI[1] = {{0.f, 0.f, 0.f, 0.f}};
+  mf_quads<1>(Aext, sext, ne_r, live, kq, MfPointB{xJe, xMe, cv, odd}, accE, v);
   {
-    const float *A = reinterpret_cast<const float *>(d.PE + (size_t)f * ne_r * R2 * 2) + (size_t)(live ? r : 0) * 4 + kq;
-    accE = mf_columns(A, (size_t)R2 * 4, ne_r, live, 1.f, [&](int b) { return bval(srcE[b * NB + cv]); }, accE);
-  }
-  {
-    const cx<float> *srcI = kq < 2 ? xs + 2 * ne_r * NB : xs + 3 * ne_r * NB;
     const int lt_lo = min(pt0, R2 - 1) / (2 * NQ), lt_hi = min(pt0 + 15, R2 - 1) / (2 * NQ);
     const int bd_lo = d.tbody[lt_lo], bd_hi = d.tbody[lt_hi];
     for (int bd = bd_lo; bd <= bd_hi; bd++) {
       const int e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
       const int r0 = 2 * NQ * d.body_t0[bd], R2b = 2 * NQ * (d.body_t0[bd + 1] - d.body_t0[bd]);
-      const bool in = live && r >= r0 && r < r0 + R2b;
+      const bool in = live && row >= r0 && row < r0 + R2b;
       const float *A = reinterpret_cast<const float *>(d.PI + ((size_t)f * d.pi_per_f + d.pbase[bd]) * 2) +
-                       (size_t)(in ? r - r0 : 0) * 4 + kq;
-      accI = mf_columns(A, (size_t)R2b * 4, neb, in, 1.f, [&](int b) { return bval(srcI[(e0 + b) * NB + cv]); },
-                        accI);
+                       (size_t)(in ? row - r0 : 0) * 4;
+      mf_load(A, (size_t)R2b * 4, neb, in, kq, 0, v);
+      mf_quads<1>(A, (size_t)R2b * 4, neb, in, kq, MfPointB{xJi + e0 * NB, xMi + e0 * NB, cv, odd}, accI, v);
     }
   }
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const int rr = pt0 + 4 * kq + q;
     if (rr < R2) {
-      Yf[((size_t)(2 * ne_r + rr) * NB + cv) * 2 + (odd ? 1 : 0)] = accE[q];
-      Yf[((size_t)(2 * ne_r + R2 + rr) * NB + cv) * 2 + (odd ? 1 : 0)] = accI[q];
+      Yf[((size_t)(2 * ne_r + rr) * NB + cv) * 2 + (odd ? 1 : 0)] = accE[0][q];
+      Yf[((size_t)(2 * ne_r + R2 + rr) * NB + cv) * 2 + (odd ? 1 : 0)] = accI[0][q];
     }
   }
 }
@@ -829,97 +859,214 @@ __global__ void __launch_bounds__(256) toe_local_kernel(DevOperator<T> op, ToeDe
 }
 
 // ---------------------------------------------------------------------------
+// rows: the periodic sums (edge_out), the local terms (tri_out) and the exact
+// entries of every pair with a non-periodic edge, stored column-major so that
+// lanes walk rows: short part [j][n] (every row n against non-periodic
+// column j; used by periodic rows), long part [m][i] (non-periodic row i
+// against every column m)
 // ---------------------------------------------------------------------------
-// long rows (every column of a non-periodic edge's row): split into column
-// chunks; partial sums of the E, H and eq14 rows per (row, chunk, vector),
-// then added to the rows the row kernel wrote
-// ---------------------------------------------------------------------------
-constexpr int TOE_CHUNK = 256;     // columns per work-group
-constexpr int TOE_LROWS = 16;      // long rows per work-group (4 per wave)
 template <typename T> __device__ inline T wsum64(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// One work-group per (column chunk, group of 16 long rows): the chunk's
-// currents (columns are the edges in order) staged in LDS once, each wave
-// runs 4 rows over the chunk, lanes over columns.
+// coefficients of (J_i, J_e, M) in the E, H and eq14 rows from one entry's
+// 8 tested values (sigma values on absorber rows only)
+template <typename T> struct RowCoef {
+  cx<T> eJi, eJe, eM, hJi, hJe, hM, rJi, rM;
+};
+template <typename T>
+__device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR, T Ze, T Zi) {
+  RowCoef<T> c;
+  const cx<T> Le = V4[0], Ke = V4[1], Li = V4[2], Ki = V4[3];
+  c.eJi = Li * Zi;
+  c.eJe = Le * (-Ze);
+  c.eM = Ke + Ki;
+  c.hJi = Ki;
+  c.hJe = -Ke;
+  c.hM = Le * (T(-1) / Ze) - Li * (T(1) / Zi);
+  c.rJi = czero<T>();
+  c.rM = czero<T>();
+  if (isR) {
+    const cx<T> Lr = S4[0], Kr = S4[1], Ls = S4[2], Ks = S4[3];
+    c.hJe = c.hJe - Lr * Ze;
+    c.hM = c.hM + Kr;
+    c.rJi = Ls * Zi;
+    c.rM = Ks;
+  }
+  return c;
+}
+template <typename T>
+__device__ inline void row_mac(const RowCoef<T> &c, const cx<T> *cm, cx<T> &e, cx<T> &h, cx<T> &q) {
+  const cx<T> Je = cm[0], Ji = cm[1], M = cm[2];
+  cmac(e, c.eJi, Ji);
+  cmac(e, c.eJe, Je);
+  cmac(e, c.eM, M);
+  cmac(h, c.hJi, Ji);
+  cmac(h, c.hJe, Je);
+  cmac(h, c.hM, M);
+  cmac(q, c.rJi, Ji);
+  cmac(q, c.rM, M);
+}
+
+// periodic rows against the non-periodic columns, in TOE_RG column groups
+// (one thread per (row, group)): partial sums rpart[g][b][k][n]
+constexpr int TOE_RG = 8;
 template <typename T, int NRB>
-__global__ void __launch_bounds__(256) toe_long_rows_kernel(DevOperator<T> op, ToeLong lr, T *__restrict__ part) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T> *xs = reinterpret_cast<cx<T> *>(smem_raw);   // [column][vector][3]
-  const int ch = blockIdx.x, grp = blockIdx.y;
-  const int c0 = ch * TOE_CHUNK, nc = min(TOE_CHUNK, lr.len - c0);
-  const cx<T> *cur = NRB > 1 ? op.srcI : op.src;
-  for (int i = threadIdx.x; i < nc * NRB * 3; i += blockDim.x) xs[i] = cur[(size_t)c0 * NRB * 3 + i];
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const T Ze = op.Z_e, Zi = op.Z_i, iZe = T(1) / op.Z_e, iZi = T(1) / op.Z_i;
-  for (int rr = 0; rr < TOE_LROWS / 4; rr++) {
-    const int i = grp * TOE_LROWS + wave * (TOE_LROWS / 4) + rr;
-    if (i >= lr.nlong) break;   // wave-uniform
-    const EdgeRec r = op.edges[lr.rows[i]];
-    T v[6 * NRB];
+__global__ void __launch_bounds__(256) toe_rows_part_kernel(DevOperator<T> op, ToeRows<T> R) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
+  if (n >= op.ne) return;
+  const EdgeRec r = op.edges[n];
+  const T Ze = op.Z_e, Zi = op.Z_i;
+  const cx<T> *cur = NRB > 1 ? op.srcI : op.src;   // [m][b][3]
+  cx<T> e[NRB], h[NRB], q[NRB];
 #pragma unroll
-    for (int q = 0; q < 6 * NRB; q++) v[q] = T(0);
-    const int64_t kb = lr.start[i] + c0;
-    for (int k = lane; k < nc; k += 64) {
-      const int64_t kk = kb + k;
-      const cx<T> Le = op.V4[4 * kk], Ke = op.V4[4 * kk + 1], Li = op.V4[4 * kk + 2], Ki = op.V4[4 * kk + 3];
-      cx<T> eJi = Li * Zi, eJe = Le * (-Ze), eM = Ke + Ki;
-      cx<T> hJi = Ki, hJe = -Ke, hM = Le * (-iZe) - Li * iZi;
-      cx<T> rJi = czero<T>(), rM = czero<T>();
-      if (r.isR) {
-        const cx<T> Lr = op.S4[4 * kk], Kr = op.S4[4 * kk + 1], Ls = op.S4[4 * kk + 2], Ks = op.S4[4 * kk + 3];
-        hJe = hJe - Lr * Ze;
-        hM = hM + Kr;
-        rJi = Ls * Zi;
-        rM = Ks;
+  for (int b = 0; b < NRB; b++) e[b] = h[b] = q[b] = czero<T>();
+  const int j0 = (R.ncap * g) / TOE_RG, j1 = (R.ncap * (g + 1)) / TOE_RG;
+  if (R.edge_sgn[n] != 0) {
+    constexpr int DEP = 4;
+    int j = j0;
+    for (; j + DEP <= j1; j += DEP) {
+      cx<T> V[DEP][4], S[DEP][4];
+#pragma unroll
+      for (int u = 0; u < DEP; u++) {
+        const size_t k = ((size_t)(j + u) * op.ne + n) * 4;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          V[u][t] = R.V4S[k + t];
+          S[u][t] = r.isR ? R.S4S[k + t] : czero<T>();
+        }
       }
-      const cx<T> *cm = xs + (size_t)k * NRB * 3;
 #pragma unroll
-      for (int b = 0; b < NRB; b++) {
-        const cx<T> Je = cm[3 * b], Ji = cm[3 * b + 1], M = cm[3 * b + 2];
-        cx<T> e = {v[6 * b], v[6 * b + 1]}, h = {v[6 * b + 2], v[6 * b + 3]}, q = {v[6 * b + 4], v[6 * b + 5]};
-        cmac(e, eJi, Ji);
-        cmac(e, eJe, Je);
-        cmac(e, eM, M);
-        cmac(h, hJi, Ji);
-        cmac(h, hJe, Je);
-        cmac(h, hM, M);
-        cmac(q, rJi, Ji);
-        cmac(q, rM, M);
-        v[6 * b] = e.x;
-        v[6 * b + 1] = e.y;
-        v[6 * b + 2] = h.x;
-        v[6 * b + 3] = h.y;
-        v[6 * b + 4] = q.x;
-        v[6 * b + 5] = q.y;
+      for (int u = 0; u < DEP; u++) {
+        const RowCoef<T> c = row_coef(V[u], S[u], r.isR != 0, Ze, Zi);
+        const cx<T> *cm = cur + (size_t)R.capcol[j + u] * NRB * 3;
+#pragma unroll
+        for (int b = 0; b < NRB; b++) row_mac(c, cm + 3 * b, e[b], h[b], q[b]);
       }
     }
+    for (; j < j1; j++) {
+      const size_t k = ((size_t)j * op.ne + n) * 4;
+      const RowCoef<T> c = row_coef(R.V4S + k, R.S4S + k, r.isR != 0, Ze, Zi);
+      const cx<T> *cm = cur + (size_t)R.capcol[j] * NRB * 3;
 #pragma unroll
-    for (int q = 0; q < 6 * NRB; q++) {
-      const T t = wsum64(v[q]);
-      if (lane == 0) part[((size_t)i * lr.nchunk + ch) * 6 * NRB + q] = t;
+      for (int b = 0; b < NRB; b++) row_mac(c, cm + 3 * b, e[b], h[b], q[b]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NRB; b++) {
+    T *p = R.rpart + ((size_t)(g * NRB + b) * 6) * op.ne + n;
+    p[0] = e[b].x;
+    p[(size_t)op.ne] = e[b].y;
+    p[2 * (size_t)op.ne] = h[b].x;
+    p[3 * (size_t)op.ne] = h[b].y;
+    p[4 * (size_t)op.ne] = q[b].x;
+    p[5 * (size_t)op.ne] = q[b].y;
+  }
+}
+
+// one thread per edge row: the groups' partial sums, the local terms of its
+// two halves and the periodic sums; writes the rows
+template <typename T>
+__global__ void __launch_bounds__(256) toe_rows_kernel(DevOperator<T> op, ToeRows<T> R, double *__restrict__ y, int nb) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= op.ne) return;
+  const EdgeRec r = op.edges[n];
+  for (int b = 0; b < nb; b++) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int g = 0; g < TOE_RG; g++) {
+      const T *p = R.rpart + ((size_t)(g * nb + b) * 6) * op.ne + n;
+      for (int k = 0; k < 6; k++) v[k] += (double)p[(size_t)k * op.ne];
+    }
+    const cx<T> *to = op.tri_out + (size_t)9 * op.nt * b;
+    const cx<T> *p0 = to + ((size_t)r.tri[0] * 3 + r.loc[0]) * 3;
+    const cx<T> *p1 = to + ((size_t)r.tri[1] * 3 + r.loc[1]) * 3;
+    const cx<T> *eo = op.edge_out + ((size_t)b * op.ne + n) * 2;
+    const cx<T> E = p0[0] + p1[0] + eo[0], H = p0[1] + p1[1] + eo[1], Q = p0[2] + p1[2];
+    double *yb = y + (size_t)2 * op.N * b;
+    yb[2 * r.row[0]] = v[0] + E.x;
+    yb[2 * r.row[0] + 1] = v[1] + E.y;
+    yb[2 * r.row[1]] = v[2] + H.x;
+    yb[2 * r.row[1] + 1] = v[3] + H.y;
+    if (r.isR) {
+      yb[2 * r.row[2]] = v[4] + Q.x;
+      yb[2 * r.row[2] + 1] = v[5] + Q.y;
     }
   }
 }
 
-// rows += sum of the chunks' partials: one wave per long row and vector,
-// lanes over chunks
-template <typename T>
-__global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeLong lr, const T *__restrict__ part, double *y, int nb) {
-  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (w >= lr.nlong * nb) return;   // wave-uniform
-  const int i = w / nb, b = w - i * nb;
-  const EdgeRec r = op.edges[lr.rows[i]];
-  double s6[6] = {0, 0, 0, 0, 0, 0};
-  for (int ch = lane; ch < lr.nchunk; ch += 64) {
-    const T *p = part + ((size_t)(i * lr.nchunk + ch) * nb + b) * 6;
-    for (int q = 0; q < 6; q++) s6[q] += (double)p[q];
+// long rows: one work-group per chunk of TOE_LCH columns; the chunk's
+// currents in LDS; lane i walks long row i over the chunk; partial sums per
+// (chunk, row, vector)
+constexpr int TOE_LCH = 64;
+template <typename T, int NRB>
+__global__ void __launch_bounds__(256) toe_long_kernel(DevOperator<T> op, ToeRows<T> R) {
+  __shared__ cx<T> xs[TOE_LCH * NRB * 3];
+  const int ch = blockIdx.x, c0 = ch * TOE_LCH, nc = min(TOE_LCH, op.ne - c0);
+  const cx<T> *cur = NRB > 1 ? op.srcI : op.src;
+  for (int i = threadIdx.x; i < nc * NRB * 3; i += blockDim.x) xs[i] = cur[(size_t)c0 * NRB * 3 + i];
+  __syncthreads();
+  const T Ze = op.Z_e, Zi = op.Z_i;
+  for (int i = threadIdx.x; i < R.nlong; i += blockDim.x) {
+    const EdgeRec r = op.edges[R.capcol[i]];
+    cx<T> e[NRB], h[NRB], q[NRB];
+#pragma unroll
+    for (int b = 0; b < NRB; b++) e[b] = h[b] = q[b] = czero<T>();
+    constexpr int DEP = 4;
+    int m = 0;
+    for (; m + DEP <= nc; m += DEP) {
+      cx<T> V[DEP][4], S[DEP][4];
+#pragma unroll
+      for (int u = 0; u < DEP; u++) {
+        const size_t k = ((size_t)(c0 + m + u) * R.nlong + i) * 4;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          V[u][t] = R.V4L[k + t];
+          S[u][t] = r.isR ? R.S4L[k + t] : czero<T>();
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < DEP; u++) {
+        const RowCoef<T> c = row_coef(V[u], S[u], r.isR != 0, Ze, Zi);
+        const cx<T> *cm = xs + (size_t)(m + u) * NRB * 3;
+#pragma unroll
+        for (int b = 0; b < NRB; b++) row_mac(c, cm + 3 * b, e[b], h[b], q[b]);
+      }
+    }
+    for (; m < nc; m++) {
+      const size_t k = ((size_t)(c0 + m) * R.nlong + i) * 4;
+      const RowCoef<T> c = row_coef(R.V4L + k, R.S4L + k, r.isR != 0, Ze, Zi);
+      const cx<T> *cm = xs + (size_t)m * NRB * 3;
+#pragma unroll
+      for (int b = 0; b < NRB; b++) row_mac(c, cm + 3 * b, e[b], h[b], q[b]);
+    }
+    T *p = R.part + ((size_t)ch * R.nlong + i) * NRB * 6;
+#pragma unroll
+    for (int b = 0; b < NRB; b++) {
+      p[6 * b] = e[b].x;
+      p[6 * b + 1] = e[b].y;
+      p[6 * b + 2] = h[b].x;
+      p[6 * b + 3] = h[b].y;
+      p[6 * b + 4] = q[b].x;
+      p[6 * b + 5] = q[b].y;
+    }
   }
-  for (int q = 0; q < 6; q++) s6[q] = wsum64(s6[q]);
+}
+
+// long rows += sum over chunks: one wave per (row, vector), lanes over chunks
+template <typename T>
+__global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeRows<T> R, double *y, int nb) {
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (w >= R.nlong * nb) return;   // wave-uniform
+  const int i = w / nb, b = w - i * nb;
+  const EdgeRec r = op.edges[R.capcol[i]];
+  double s6[6] = {0, 0, 0, 0, 0, 0};
+  for (int ch = lane; ch < R.nchunk; ch += 64) {
+    const T *p = R.part + (((size_t)ch * R.nlong + i) * nb + b) * 6;
+    for (int k = 0; k < 6; k++) s6[k] += (double)p[k];
+  }
+  for (int k = 0; k < 6; k++) s6[k] = wsum64(s6[k]);
   if (lane != 0) return;
   double *yb = y + (size_t)2 * op.N * b;
   yb[2 * r.row[0]] += s6[0];
@@ -932,37 +1079,33 @@ __global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeLong lr, const T *_
   }
 }
 
-template <typename T>
-void launch_toe_long_rows(const DevOperator<T> &op, const ToeLong &lr, T *part, double *y, hipStream_t s, int nb) {
-  if (lr.nlong == 0) return;
-  const dim3 grid(lr.nchunk, (lr.nlong + TOE_LROWS - 1) / TOE_LROWS);
-#define SCABS_TOE_LONG(NB)                                                                                           \
+template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb) {
+  const int nchunk = (op.ne + TOE_LCH - 1) / TOE_LCH;
+#define SCABS_TOE_ROWS(NB)                                                                                           \
   do {                                                                                                               \
-    const size_t lds = sizeof(cx<T>) * TOE_CHUNK * (NB) * 3;                                                         \
-    if (lds > 65536)                                                                                                 \
-      (void)hipFuncSetAttribute((const void *)toe_long_rows_kernel<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,\
-                                (int)lds);                                                                           \
-    hipLaunchKernelGGL((toe_long_rows_kernel<T, NB>), grid, dim3(256), lds, s, op, lr, part);                         \
+    if (R.nlong > 0) hipLaunchKernelGGL((toe_long_kernel<T, NB>), dim3(nchunk), dim3(256), 0, s, op, R);              \
+    hipLaunchKernelGGL((toe_rows_part_kernel<T, NB>), dim3((op.ne + 255) / 256, TOE_RG), dim3(256), 0, s, op, R);     \
   } while (0)
   switch (nb) {
-    case 1: SCABS_TOE_LONG(1); break;
-    case 2: SCABS_TOE_LONG(2); break;
-    case 3: SCABS_TOE_LONG(3); break;
-    case 4: SCABS_TOE_LONG(4); break;
-    case 5: SCABS_TOE_LONG(5); break;
-    case 6: SCABS_TOE_LONG(6); break;
-    case 7: SCABS_TOE_LONG(7); break;
-    default: SCABS_TOE_LONG(8); break;
+    case 1: SCABS_TOE_ROWS(1); break;
+    case 2: SCABS_TOE_ROWS(2); break;
+    case 3: SCABS_TOE_ROWS(3); break;
+    case 4: SCABS_TOE_ROWS(4); break;
+    case 5: SCABS_TOE_ROWS(5); break;
+    case 6: SCABS_TOE_ROWS(6); break;
+    case 7: SCABS_TOE_ROWS(7); break;
+    default: SCABS_TOE_ROWS(8); break;
   }
-#undef SCABS_TOE_LONG
-  hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((lr.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, lr, part, y,
-                     nb);
+#undef SCABS_TOE_ROWS
+  hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R, y, nb);
+  if (R.nlong > 0)
+    hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((R.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, R, y, nb);
 }
-template void launch_toe_long_rows<float>(const DevOperator<float> &, const ToeLong &, float *, double *, hipStream_t,
-                                          int);
-template void launch_toe_long_rows<double>(const DevOperator<double> &, const ToeLong &, double *, double *,
-                                           hipStream_t, int);
-int toe_chunk() { return TOE_CHUNK; }
+template void launch_toe_rows<float>(const DevOperator<float> &, const ToeRows<float> &, double *, hipStream_t, int);
+template void launch_toe_rows<double>(const DevOperator<double> &, const ToeRows<double> &, double *, hipStream_t,
+                                      int);
+int toe_long_chunk() { return TOE_LCH; }
+int toe_row_groups() { return TOE_RG; }
 
 template <typename T>
 void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb, int parts) {
