@@ -307,6 +307,10 @@ void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st) {
 // FFTs along the ring axis: groups of TOE_LINES lines of length P in LDS
 // ---------------------------------------------------------------------------
 constexpr int TOE_FFT_THREADS = 512;
+constexpr int TOE_GATHER = 8;   // global loads issued together per thread
+// waves per SIMD asked of the product's transforms: two work-groups per CU
+// in FP32 (registers capped at 128), one in FP64
+template <typename T> constexpr int toe_fft_waves() { return sizeof(T) == sizeof(float) ? 4 : 2; }
 constexpr int TOE_FFT_ELEMS = 16;
 // lines per work-group: at most 8, within the Stockham stage's elements per
 // thread and within 64 KiB of LDS (padded addressing)
@@ -316,8 +320,23 @@ template <typename T> __host__ __device__ inline int toe_lines_per_group(int P) 
   while (g > 1 && (size_t)lpad_size<T>(g * P) * sizeof(cx<T>) > 65536) g--;
   return g < 1 ? 1 : g;
 }
-template <typename T> size_t toe_fft_lds(int P) {
-  return (size_t)lpad_size<T>(toe_lines_per_group<T>(P) * P) * sizeof(cx<T>);
+// LDS of a line group: the padded lines, then the P twiddles
+template <typename T> __host__ __device__ inline size_t toe_tw_offset(int P) {
+  return ((size_t)lpad_size<T>(toe_lines_per_group<T>(P) * P) * sizeof(cx<T>) + 15) / 16 * 16;
+}
+template <typename T> size_t toe_fft_lds(int P) { return toe_tw_offset<T>(P) + (size_t)P * sizeof(cx<T>); }
+// dynamic LDS of a transform launch (attribute raised past 64 KiB)
+template <typename K> size_t toe_fft_launch_lds(K kernel, size_t lds) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return lds;
+}
+// twiddles copied to LDS (read by every Stockham stage)
+template <typename T>
+__device__ inline const cx<T> *toe_stage_twiddles(unsigned char *smem, const cx<T> *tw, int P) {
+  cx<T> *t = reinterpret_cast<cx<T> *>(smem + toe_tw_offset<T>(P));
+  for (int i = threadIdx.x; i < P; i += blockDim.x) t[i] = tw[i];
+  return t;
 }
 
 // setup: lines stored contiguously (series of length P), transformed in
@@ -329,9 +348,10 @@ __global__ void __launch_bounds__(TOE_FFT_THREADS) toe_series_fft_kernel(cx<doub
   const int G = toe_lines_per_group<double>(P);
   const int64_t l0 = (int64_t)blockIdx.x * G;
   const int nl = (int)(nlines - l0 < G ? nlines - l0 : G);
+  const cx<double> *tws = toe_stage_twiddles<double>(smem_raw, tw, P);
   for (int i = threadIdx.x; i < nl * P; i += blockDim.x) buf[lpad<double>(i)] = data[l0 * P + i];
   __syncthreads();
-  lds_fft_mr<double, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tw, P, false);
+  lds_fft_mr<double, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, false);
   const double sc = 1.0 / P;
   for (int i = threadIdx.x; i < nl * P; i += blockDim.x) data[l0 * P + i] = buf[lpad<double>(i)] * sc;
 }
@@ -340,7 +360,7 @@ void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<dou
   if (nlines == 0) return;
   const int G = toe_lines_per_group<double>(P);
   hipLaunchKernelGGL(toe_series_fft_kernel, dim3((unsigned)((nlines + G - 1) / G)), dim3(TOE_FFT_THREADS),
-                     toe_fft_lds<double>(P), s, data, nlines, P, tw);
+                     toe_fft_launch_lds(toe_series_fft_kernel, toe_fft_lds<double>(P)), s, data, nlines, P, tw);
 }
 
 // series-major (FFT'd) -> per-frequency layouts of the block products, FP64
@@ -402,7 +422,8 @@ void launch_toe_layout(const ToeSetupArgs &s, int kind, const cx<double> *X, con
 // gathered from the per-edge currents (template orientation), zero beyond,
 // transformed; spectrum written to X[f][l].
 template <typename T>
-__global__ void __launch_bounds__(TOE_FFT_THREADS) toe_fwd_kernel(ToeDev<T> d, const cx<T> *__restrict__ src,
+__global__ void __launch_bounds__(TOE_FFT_THREADS) __attribute__((amdgpu_waves_per_eu(toe_fft_waves<T>())))
+toe_fwd_kernel(ToeDev<T> d, const cx<T> *__restrict__ src,
                                                                   const cx<T> *__restrict__ srcI, int ne, int nb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
@@ -411,24 +432,46 @@ __global__ void __launch_bounds__(TOE_FFT_THREADS) toe_fwd_kernel(ToeDev<T> d, c
   const int nlines = 4 * d.ne_r * nb;
   const int l0 = blockIdx.x * G;
   const int nl = min(G, nlines - l0);
-  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
-    const int li = i / P, j = i - li * P;
-    const int l = l0 + li, slot = l / nb, v = l - slot * nb;
-    const int c = slot / d.ne_r, a = slot - c * d.ne_r;
-    cx<T> val = czero<T>();
-    if (j < nr) {
-      const int e = d.ringmap[(size_t)a * nr + j];
-      if (e >= 0) {
-        const int cc = c == 0 ? 0 : c == 2 ? 1 : 2;
-        const cx<T> x = nb > 1 ? srcI[((size_t)e * nb + v) * 3 + cc] : src[(size_t)e * 3 + cc];
-        const T sg = (T)d.edge_sgn[e] * (c == 3 ? T(-1) : T(1));
-        val = x * sg;
+  // gathers in batches of TOE_GATHER per thread, every load in bounds
+  // (indices clamped, results masked) so that a batch's loads overlap
+  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P);
+  const int n = nl * P;
+  for (int i0 = threadIdx.x; i0 < n; i0 += TOE_GATHER * blockDim.x) {
+    int rm[TOE_GATHER];
+#pragma unroll
+    for (int u = 0; u < TOE_GATHER; u++) {
+      const int i = min(i0 + u * (int)blockDim.x, n - 1);
+      const int li = i / P, j = min(i - li * P, nr - 1);
+      const int slot = (l0 + li) / nb, a = slot % d.ne_r;
+      rm[u] = d.ringmap[(size_t)a * nr + j];
+    }
+    cx<T> x[TOE_GATHER];
+    int sg[TOE_GATHER];
+#pragma unroll
+    for (int u = 0; u < TOE_GATHER; u++) {
+      const int i = min(i0 + u * (int)blockDim.x, n - 1);
+      const int l = l0 + i / P, slot = l / nb, v = l - slot * nb, c = slot / d.ne_r;
+      const int cc = c == 0 ? 0 : c == 2 ? 1 : 2;
+      const int e = rm[u] >= 0 ? rm[u] : 0;
+      x[u] = nb > 1 ? srcI[((size_t)e * nb + v) * 3 + cc] : src[(size_t)e * 3 + cc];
+      sg[u] = d.edge_sgn[e];
+    }
+#pragma unroll
+    for (int u = 0; u < TOE_GATHER; u++) {
+      const int i = i0 + u * (int)blockDim.x;
+      if (i < n) {
+        const int li = i / P, j = i - li * P;
+        const int c = ((l0 + li) / nb) / d.ne_r;
+        const T s = (T)sg[u] * (c == 3 ? T(-1) : T(1));
+        buf[lpad<T>(i)] = (j < nr && rm[u] >= 0) ? x[u] * s : czero<T>();
       }
     }
-    buf[lpad<T>(i)] = val;
   }
   __syncthreads();
-  lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, d.tw, P, false);
+  if (wave_fits(P, nl, blockDim.x >> 6, TOE_FFT_ELEMS))
+    lds_fft<T, TOE_FFT_ELEMS, TOE_FFT_ELEMS, true>(buf, P, nl, 1, P, 0, 1, tws, P, false);
+  else
+    lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, false);
   for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
     const int f = i / nl, li = i - f * nl;
     d.X[(size_t)f * nlines + l0 + li] = buf[lpad<T>(li * P + f)];
@@ -747,40 +790,99 @@ __global__ void __launch_bounds__(64 * TOE_MF_WAVES) toe_apply_mfma_kernel(ToeDe
   }
 }
 
+// stores of the transformed lines [w0, w1) of a group starting at line l0
+// (rings j < nr): Galerkin slots scattered to the edges of their ring
+// positions, point slots contiguous.  By the calling wave alone (its lanes
+// over j) or by the whole work-group (threads over line and ring).
+template <typename T>
+__device__ inline void toe_inv_store_lines(const ToeDev<T> &d, const cx<T> *buf, int ne, int nb, int l0, int w0, int w1,
+                                           bool by_wave) {
+  const int P = d.P, nr = d.nr, ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
+  if (!by_wave) {
+    for (int i = threadIdx.x; i < (w1 - w0) * nr; i += blockDim.x) {
+      const int li = w0 + i / nr, j = i % nr;
+      const int l = l0 + li, slot = l / nb, v = l - slot * nb;
+      const cx<T> val = buf[lpad<T>(li * P + j)];
+      if (slot < 2 * ne_r) {
+        const int e = d.ringmap[(size_t)(slot >> 1) * nr + j];
+        if (e >= 0) d.edge_out[((size_t)v * ne + e) * 2 + (slot & 1)] = val * (T)d.edge_sgn[e];
+      } else {
+        d.pf[((size_t)v * 2 * R2 + slot - 2 * ne_r) * nr + j] = val;
+      }
+    }
+    return;
+  }
+  const int t0 = threadIdx.x & 63, dt = 64;
+  for (int li = w0; li < w1; li++) {
+    const int l = l0 + li, slot = l / nb, v = l - slot * nb;   // uniform over the wave
+    const cx<T> *line = buf;
+    if (slot >= 2 * ne_r) {
+      cx<T> *dst = d.pf + ((size_t)v * 2 * R2 + slot - 2 * ne_r) * nr;
+      for (int j = t0; j < nr; j += dt) dst[j] = line[lpad<T>(li * P + j)];
+      continue;
+    }
+    const int *rmap = d.ringmap + (size_t)(slot >> 1) * nr;
+    cx<T> *dst = d.edge_out + (size_t)v * ne * 2 + (slot & 1);
+    for (int j0 = t0; j0 < nr; j0 += TOE_GATHER * dt) {
+      int rm[TOE_GATHER], sg[TOE_GATHER];
+#pragma unroll
+      for (int u = 0; u < TOE_GATHER; u++) rm[u] = rmap[min(j0 + u * dt, nr - 1)];
+#pragma unroll
+      for (int u = 0; u < TOE_GATHER; u++) sg[u] = d.edge_sgn[rm[u] >= 0 ? rm[u] : 0];
+#pragma unroll
+      for (int u = 0; u < TOE_GATHER; u++) {
+        const int j = j0 + u * dt;
+        if (j < nr && rm[u] >= 0) dst[(size_t)rm[u] * 2] = line[lpad<T>(li * P + j)] * (T)sg[u];
+      }
+    }
+  }
+}
+
 // inverse: line l = slot * nb + v over f, inverse transform, rings i < nr
 // scattered: Galerkin slots to edge_out[v][e][2] (E, H rows; template
 // orientation back to the edge's), point slots to pf[v][point][4]
 // (exterior t1, t2, interior t1, t2).
 template <typename T>
-__global__ void __launch_bounds__(TOE_FFT_THREADS) toe_inv_kernel(ToeDev<T> d, int ne, int np, int nb) {
+__global__ void __launch_bounds__(TOE_FFT_THREADS) __attribute__((amdgpu_waves_per_eu(toe_fft_waves<T>())))
+toe_inv_kernel(ToeDev<T> d, int ne, int np, int nb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
-  const int P = d.P, nr = d.nr;
+  const int P = d.P;
   const int G = toe_lines_per_group<T>(P);
-  const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
-  const int nout = 2 * ne_r + 2 * R2;
-  const int nlines = nout * nb;
+  const int nlines = (2 * d.ne_r + 4 * NQ * d.nt_r) * nb;
   const int l0 = blockIdx.x * G;
   const int nl = min(G, nlines - l0);
-  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
-    const int f = i / nl, li = i - f * nl;
-    buf[lpad<T>(li * P + f)] = d.Y[(size_t)f * nlines + l0 + li];
-  }
-  __syncthreads();
-  lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, d.tw, P, true);
-  for (int i = threadIdx.x; i < nl * nr; i += blockDim.x) {
-    const int li = i / nr, j = i - li * nr;
-    const int l = l0 + li, slot = l / nb, v = l - slot * nb;
-    const cx<T> val = buf[lpad<T>(li * P + j)];
-    if (slot < 2 * ne_r) {
-      const int a = slot >> 1, h = slot & 1;
-      const int e = d.ringmap[(size_t)a * nr + j];
-      if (e >= 0) d.edge_out[((size_t)v * ne + e) * 2 + h] = val * (T)d.edge_sgn[e];
-    } else {
-      const int rr = slot - 2 * ne_r;   // point row: exterior rows, then interior
-      d.pf[((size_t)v * 2 * R2 + rr) * nr + j] = val;
+  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P);
+  const int n = nl * P;
+  for (int i0 = threadIdx.x; i0 < n; i0 += TOE_GATHER * blockDim.x) {
+    cx<T> y[TOE_GATHER];
+#pragma unroll
+    for (int u = 0; u < TOE_GATHER; u++) {
+      const int i = min(i0 + u * (int)blockDim.x, n - 1);
+      const int f = i / nl, li = i - f * nl;
+      y[u] = d.Y[(size_t)f * nlines + l0 + li];
+    }
+#pragma unroll
+    for (int u = 0; u < TOE_GATHER; u++) {
+      const int i = i0 + u * (int)blockDim.x;
+      if (i < n) {
+        const int f = i / nl, li = i - f * nl;
+        buf[lpad<T>(li * P + f)] = y[u];
+      }
     }
   }
+  __syncthreads();
+  const int nwv = blockDim.x >> 6;
+  if (!wave_fits(P, nl, nwv, TOE_FFT_ELEMS)) {
+    lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, true);
+    toe_inv_store_lines(d, buf, ne, nb, l0, 0, nl, false);
+    return;
+  }
+  // each wave transforms its own lines and stores them: no work-group barrier
+  lds_fft_wave<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, true);
+  const int gw = (nl + nwv - 1) / nwv, wave = threadIdx.x >> 6;   // the wave's lines, as in lds_fft_wave
+  const int w0 = min(nl, wave * gw), w1 = min(nl, w0 + gw);
+  toe_inv_store_lines(d, buf, ne, nb, l0, w0, w1, true);
 }
 
 // local terms and the sigma tests of the point fields, per triangle (like
@@ -1112,8 +1214,8 @@ void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_
   const int G = toe_lines_per_group<T>(d.P);
   const int nin = 4 * d.ne_r * nb;
   if (parts & TOE_FWD)
-    hipLaunchKernelGGL(toe_fwd_kernel<T>, dim3((nin + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
-                       op.src, op.srcI, op.ne, nb);
+    hipLaunchKernelGGL(toe_fwd_kernel<T>, dim3((nin + G - 1) / G), dim3(TOE_FFT_THREADS),
+                       toe_fft_launch_lds(toe_fwd_kernel<T>, toe_fft_lds<T>(d.P)), s, d, op.src, op.srcI, op.ne, nb);
   if (!(parts & TOE_APPLY)) goto inverse;
   {
   const int R2 = 2 * NQ * d.nt_r;
@@ -1155,8 +1257,8 @@ inverse:
   if (parts & TOE_INV) {
     const int R2 = 2 * NQ * d.nt_r;
     const int nout = (2 * d.ne_r + 2 * R2) * nb;
-    hipLaunchKernelGGL(toe_inv_kernel<T>, dim3((nout + G - 1) / G), dim3(TOE_FFT_THREADS), toe_fft_lds<T>(d.P), s, d,
-                       op.ne, op.np, nb);
+    hipLaunchKernelGGL(toe_inv_kernel<T>, dim3((nout + G - 1) / G), dim3(TOE_FFT_THREADS),
+                       toe_fft_launch_lds(toe_inv_kernel<T>, toe_fft_lds<T>(d.P)), s, d, op.ne, op.np, nb);
     hipLaunchKernelGGL(toe_local_kernel<T>, dim3((op.nt + 255) / 256, nb), dim3(256), 0, s, op, d, nb);
   }
 }
