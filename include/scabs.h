@@ -307,10 +307,15 @@ int scabs_gradient(scabs_ctx *c, const double *x, const double *g, const double 
                                      ext-ordered FP32 copy (before each
                                      SCABS_STAGE_PRECOND record) */
 #define SCABS_STAGE_TOEAPPLY32 16 /* block-Toeplitz product, FP32: the per-frequency block
-                                     products alone (inside stage SCABS_STAGE_FFT +
-                                     SCABS_STAGE_FP32_OFFSET) */
-#define SCABS_STAGE_TOEAPPLY64 17 /* the same in FP64 (inside stage SCABS_STAGE_FFT) */
-#define SCABS_NSTAGES 18
+                                     products (the ring-axis transforms are recorded
+                                     as SCABS_STAGE_FFT + SCABS_STAGE_FP32_OFFSET, the
+                                     sparse rows of the non-periodic pairs as
+                                     SCABS_STAGE_NEAR + SCABS_STAGE_FP32_OFFSET) */
+#define SCABS_STAGE_TOEAPPLY64 17 /* the same in FP64 */
+#define SCABS_STAGE_TOEPRODUCT32 18 /* the whole block-Toeplitz product, FP32 (spans the
+                                       records of its parts) */
+#define SCABS_STAGE_TOEPRODUCT64 19 /* the same in FP64 */
+#define SCABS_NSTAGES 20
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
 /* Restrict the stages that profiling sessions record to those whose bit
@@ -330,8 +335,12 @@ int scabs_profile_mask(scabs_ctx *c, uint32_t mask);
  * SCABS_STAGE_PCGATHER32: per extended-set entry its index, its column scale,
  * the FP64 inputs read and the FP32 copies written;
  * SCABS_STAGE_TOEAPPLY32/64: every entry of the spectrum tables read once, the
- * input spectra read and the output spectra written once.  Returns
- * SCABS_E_ARG for null arguments. */
+ * input spectra read and the output spectra written once;
+ * SCABS_STAGE_TOEPRODUCT32/64: the spectrum tables and the stored entries of
+ * the non-periodic pairs that the product uses read once (the absorber test
+ * records only on absorber rows), the input and output vectors read and
+ * written once, and the ring-axis spectra written and read back once.
+ * Returns SCABS_E_ARG for null arguments. */
 int scabs_profile_bytes(const scabs_ctx *c, double *bytes);
 
 const char *scabs_last_error(const scabs_ctx *c);

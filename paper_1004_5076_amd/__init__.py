@@ -30,7 +30,8 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
-          "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32", "toeapply32", "toeapply64"]
+          "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32", "toeapply32", "toeapply64",
+          "toeproduct32", "toeproduct64"]
 
 
 class ScabsError(RuntimeError):

@@ -207,6 +207,7 @@ struct scabs_ctx {
   cx<double> *toe_tri64 = nullptr;
   cx<float> *toe_tri32 = nullptr;
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
+  double toe_sparse_bytes[2] = {0, 0};  // stored non-periodic entries one product reads (FP64, FP32)
   int toe_ncap = 0;
   double *toe_part64 = nullptr, *toe_rpart64 = nullptr;
   float *toe_part32 = nullptr, *toe_rpart32 = nullptr;
@@ -844,6 +845,17 @@ static std::string build_toeplitz(scabs_ctx *c) {
       rows[nshort + (int64_t)m * ncap + i] = nonper[i];
       cols[nshort + (int64_t)m * ncap + i] = m;
     }
+  {
+    // entries the row kernels read: the short part on periodic rows, the
+    // long part on non-periodic rows; absorber test records on absorber rows
+    int64_t nR = 0, nRcap = 0;
+    for (int n = 0; n < g.ne; n++) nR += c->lay.isR[n] != 0;
+    for (int n : nonper) nRcap += c->lay.isR[n] != 0;
+    const double recs = 4.0 * ((double)(g.ne - ncap) * ncap + (double)ncap * g.ne) +
+                        4.0 * ((double)(nR - nRcap) * ncap + (double)nRcap * g.ne);
+    c->toe_sparse_bytes[0] = recs * sizeof(cx<double>);
+    c->toe_sparse_bytes[1] = recs * sizeof(cx<float>);
+  }
   c->toe_ncap = (int)ncap;
   c->toe_nshort = nshort;
   c->toe_capcol = c->mem.upload(nonper);
@@ -1269,6 +1281,13 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   R.S4L = S4 + 4 * (size_t)c->toe_nshort;
   R.part = toe_part(c, (T *)nullptr);
   R.rpart = toe_rpart(c, (T *)nullptr);
+  // algorithmic bytes: per-frequency tables, stored sparse entries, the
+  // spectra (input 4 ne_r, output 2 ne_r + 4 NQ nt_r lines per vector)
+  const double el = sizeof(cx<T>);
+  const double spectra = el * d.P * nb * (4.0 * d.ne_r + 2.0 * d.ne_r + 4.0 * NQ * d.nt_r);
+  const double tables = c->toe_table_bytes[f32 ? 1 : 0], sparse = c->toe_sparse_bytes[f32 ? 1 : 0];
+  const double vectors = 2.0 * 16.0 * c->lay.N * nb;
+  StageTimer whole(c, f32 ? SCABS_STAGE_TOEPRODUCT32 : SCABS_STAGE_TOEPRODUCT64, tables + sparse + vectors + 2 * spectra);
   {
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
     launch_unpack(op, x, s, nb);
@@ -1276,15 +1295,15 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
     launch_toe_product(op, d, s, nb, TOE_FWD);
-    {
-      // the per-frequency block products: every spectrum table entry read
-      // once, the input spectra read and the output spectra written once
-      const size_t el = sizeof(cx<T>);
-      const double bytes = c->toe_table_bytes[sizeof(T) == sizeof(float) ? 1 : 0] +
-                           (double)el * d.P * nb * (4.0 * d.ne_r + 2.0 * d.ne_r + 4.0 * NQ * d.nt_r);
-      StageTimer ta(c, sizeof(T) == sizeof(float) ? SCABS_STAGE_TOEAPPLY32 : SCABS_STAGE_TOEAPPLY64, bytes);
-      launch_toe_product(op, d, s, nb, TOE_APPLY);
-    }
+  }
+  {
+    // the per-frequency block products: every spectrum table entry read
+    // once, the input spectra read and the output spectra written once
+    StageTimer ta(c, f32 ? SCABS_STAGE_TOEAPPLY32 : SCABS_STAGE_TOEAPPLY64, tables + spectra);
+    launch_toe_product(op, d, s, nb, TOE_APPLY);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_FFT + off);
     launch_toe_product(op, d, s, nb, TOE_INV);
   }
   {
