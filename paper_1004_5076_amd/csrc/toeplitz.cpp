@@ -141,36 +141,61 @@ std::string build_rings(const Geometry &g, RingTemplate &rt) {
     auto it = tmap.find(k);
     if (it == tmap.end()) continue;
     const int U = it->second;
-    // same orientation: U's vertices are the translates in the same cyclic order
-    bool same = false;
-    for (int s = 0; s < 3; s++)
-      if (g.t[3 * U] == w[s] && g.t[3 * U + 1] == w[(s + 1) % 3] && g.t[3 * U + 2] == w[(s + 2) % 3]) same = true;
-    if (!same) continue;
+    // U's vertices are the translates of T's in the same order (not only the
+    // same cyclic order): the quadrature points and local edges of U are then
+    // the translates of T's with the same indices, as the ring template needs
+    if (g.t[3 * U] != w[0] || g.t[3 * U + 1] != w[1] || g.t[3 * U + 2] != w[2]) continue;
     next[T] = U;
     prev[U] = T;
   }
-  // chains; the periodic ones have the largest length and start in ring 0
-  std::vector<std::vector<int>> chains;
-  int nr = 0;
-  for (int T = 0; T < g.nt; T++) {
-    if (prev[T] >= 0) continue;
-    std::vector<int> c;
-    for (int U = T; U >= 0 && (int)c.size() <= g.nt; U = next[U]) c.push_back(U);
-    nr = std::max(nr, (int)c.size());
-    chains.push_back(std::move(c));
-  }
-  if (nr < 3) return "the mesh has fewer than three periodic rings along x";
+  // chains of translates; each covers the rings [s, s + len) counted from
+  // the smallest x of the mesh.  The periodic part is the ring window [a, b)
+  // that the most triangles cover: chains spanning the window, cut to it,
+  // maximising (chains) x (b - a), at least 3 rings (ties: the longer window)
   auto xmin_of = [&](int T) {
     double m = 1e300;
     for (int k = 0; k < 3; k++) m = std::min(m, g.v[3 * g.t[3 * T + k]]);
     return m;
   };
-  double x0 = 1e300;
-  for (auto &c : chains)
-    if ((int)c.size() == nr) x0 = std::min(x0, xmin_of(c[0]));
+  std::vector<std::vector<int>> chains;
+  std::vector<int> cstart;
+  for (int T = 0; T < g.nt; T++) {
+    if (prev[T] >= 0) continue;
+    std::vector<int> c;
+    for (int U = T; U >= 0 && (int)c.size() <= g.nt; U = next[U]) c.push_back(U);
+    cstart.push_back((int)std::lround((xmin_of(c[0]) - lo[0]) / dx));
+    chains.push_back(std::move(c));
+  }
+  std::vector<int> starts, ends;
+  for (size_t i = 0; i < chains.size(); i++) {
+    starts.push_back(cstart[i]);
+    ends.push_back(cstart[i] + (int)chains[i].size());
+  }
+  std::sort(starts.begin(), starts.end());
+  starts.erase(std::unique(starts.begin(), starts.end()), starts.end());
+  std::sort(ends.begin(), ends.end());
+  ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+  long long best = 0;
+  int wa = 0, wb = 0;
+  for (int a : starts)
+    for (int b : ends) {
+      if (b - a < 3) continue;
+      long long n = 0;
+      for (size_t i = 0; i < chains.size(); i++)
+        n += cstart[i] <= a && cstart[i] + (int)chains[i].size() >= b;
+      const long long score = n * (b - a);
+      if (score > best || (score == best && b - a > wb - wa)) {
+        best = score;
+        wa = a;
+        wb = b;
+      }
+    }
+  if (best == 0) return "the mesh has fewer than three periodic rings along x";
+  const int nr = wb - wa;
   std::vector<std::vector<int>> per;
-  for (auto &c : chains)
-    if ((int)c.size() == nr && std::fabs(xmin_of(c[0]) - x0) < 0.25 * dx) per.push_back(c);
+  for (size_t i = 0; i < chains.size(); i++)
+    if (cstart[i] <= wa && cstart[i] + (int)chains[i].size() >= wb)
+      per.emplace_back(chains[i].begin() + (wa - cstart[i]), chains[i].begin() + (wb - cstart[i]));
   std::stable_sort(per.begin(), per.end(), [&](const std::vector<int> &a, const std::vector<int> &b) {
     if (g.body[a[0]] != g.body[b[0]]) return g.body[a[0]] < g.body[b[0]];
     return a[0] < b[0];
@@ -224,6 +249,7 @@ std::string build_rings(const Geometry &g, RingTemplate &rt) {
   }
   // order local edges by body
   const int ne_r = (int)keys.size();
+  if (ne_r == 0) return "the periodic rings along x share no RWG edge";
   std::vector<int> order(ne_r);
   for (int i = 0; i < ne_r; i++) order[i] = i;
   auto ebody = [&](int id) { return g.body[per[keys[id][0]][0]]; };

@@ -31,9 +31,25 @@ def _section():
     return w
 
 
+def _rotated():
+    """The 4-long guide with the vertex lists of every 5th triangle between
+    x = 1 and x = 2 rotated (same orientation): those triangles' quadrature
+    points and local edges no longer follow the ring template's numbering,
+    so ring detection must leave them out and their pairs become stored
+    entries; the product stays exact."""
+    w = synth.workload_small()
+    t = w.mesh.tris.copy()
+    cx = w.mesh.verts[t].mean(axis=1)[:, 0]
+    sel = np.nonzero((cx > 1.0) & (cx < 2.0))[0][::5]
+    t[sel] = t[sel][:, [1, 2, 0]]
+    w.mesh.tris = t
+    return w
+
+
 CASES = {
     "guide4": synth.workload_small,    # one guide, quadratic absorber on [2, 4], 27 rings
     "section": _section,               # two channels, quartic absorber, 14 rings
+    "rotated": _rotated,               # guide4 with part of the triangles renumbered
 }
 
 
