@@ -201,6 +201,36 @@ int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, do
  * built without a preconditioner. */
 int scabs_precond_apply(scabs_ctx *c, const double *x, double *y, int nrhs, int prec, int transpose);
 
+/* An incident source in the interior medium of one body (Sec. II).  b = 0:
+ * the electric dipole of scabs_rhs_dipole (current moment p = I l at pos).
+ * b > 0: the Gaussian beam of Sec. II, generated by the same dipole placed at
+ * the complex position pos - j b dir (a complex-source-point beam): it
+ * propagates along +dir, with its waist at pos, Rayleigh distance b and waist
+ * radius sqrt(2 b / k_i); its fields are the dipole's closed form continued
+ * to the complex distance R = sqrt(d.d), d = r - pos + j b dir (principal
+ * branch, cut on the disc of radius b around pos normal to dir), multiplied
+ * by exp(-k_i b) so that the on-axis amplitude stays of order one.  dir must
+ * be a unit vector when b > 0 (ignored otherwise). */
+typedef struct {
+  double pos[3];
+  double dir[3];
+  double b;
+  double moment[6]; /* p, re/im pairs */
+  int32_t body;
+  int32_t pad;
+} scabs_source;
+
+/* Right-hand side of a source (as scabs_rhs_dipole for b = 0).  b: device,
+ * N complex.  SCABS_E_ARG for a body out of range, b < 0 or a non-unit
+ * direction. */
+int scabs_rhs_source(scabs_ctx *c, const scabs_source *src, double *b);
+/* Incident field of a source at every quadrature point (as
+ * scabs_incident_dipole_points). */
+int scabs_incident_source_points(scabs_ctx *c, const scabs_source *src, double *E);
+/* Fields of a source at points of a region (as scabs_dipole_field). */
+int scabs_source_field(scabs_ctx *c, const scabs_source *src, const double *pts, int npts, int region, double *E,
+                       double *H);
+
 /* Incident field of an electric dipole (as scabs_rhs_dipole) at every
  * quadrature point (zero on other bodies).  E: device, n_points * 3 complex
  * (6 n_points doubles), point-major. */
@@ -222,6 +252,56 @@ int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei);
  * E, H: device, npts * 3 complex.  Plain 7-point rule on every triangle, so
  * the points must lie well away from the surface (several edge lengths). */
 int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E, double *H);
+
+/* Scattered fields as scabs_eval_field (same arguments, layouts and
+ * results), accurate close to the surface as well: for every source triangle
+ * whose centroid lies within SCABS_NEAR_FIELD_RADIUS times its radius (largest
+ * centroid-vertex distance) of the point, the static part 1/(4 pi R) of the
+ * kernel is integrated analytically over the triangle (the potential
+ * integrals of the singular-pair treatment, Appendix A) and the smooth
+ * remainder by the 7-point rule; farther triangles take the 7-point rule.
+ * Points may lie at any distance from the surface on the side of the chosen
+ * region (the field on the surface itself is not defined). */
+#define SCABS_NEAR_FIELD_RADIUS 5.0
+int scabs_eval_field_exact(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E,
+                           double *H);
+
+/* Field post-processing (Sec. I, Table I; Sec. III).  Host arrays; E holds
+ * n complex samples (re/im pairs) of one field component.
+ * scabs_swr: the standing-wave ratio max|E| / min|E| over the samples
+ * (out[0]) and the reflection coefficient (SWR - 1) / (SWR + 1) of a
+ * transmission line (out[1]).
+ * scabs_standing_wave_fit: least-squares fit of E(x) = a exp(-j beta x) +
+ * c exp(+j beta x) at the positions xs; beta fixed (beta_lo == beta_hi) or
+ * chosen in [beta_lo, beta_hi] by the smallest residual (scan of 401 values,
+ * golden-section refinement).  out: beta, |c| / |a|, relative residual, |a|,
+ * |c|, arg(c / a).
+ * scabs_decay_fit: least-squares fit of ln|E| = c0 - alpha x and of the
+ * unwrapped phase = p0 - beta x.  out: alpha, beta, relative residual of the
+ * log fit, c0.
+ * All three return SCABS_E_ARG for null pointers, too few samples or zero
+ * magnitudes. */
+int scabs_swr(const double *E, int n, double out[2]);
+int scabs_standing_wave_fit(const double *xs, const double *E, int n, double beta_lo, double beta_hi, double out[6]);
+int scabs_decay_fit(const double *xs, const double *E, int n, double out[4]);
+
+/* Decay rate of the guided wave from Poynting's theorem (Sec. III,
+ * eq_alpha_power): on the cross-section plane x = xpos, with the guide's
+ * rectangle guide = {y0, y1, z0, z1} (its surface belongs to body `body`)
+ * inside the box A = {Y0, Y1, Z0, Z1},
+ *   alpha = [int_{L'} sigma |E_tan|^2 dl + Re int_L (E x H*).n dl]
+ *           / [2 Re int_A (E x H*).x dS],
+ * L' the guide's perimeter (E_tan from the magnetic current, |E_tan| = |M|;
+ * sigma of the profile at the point), L the box boundary (outward normals).
+ * Fields are totals (scabs_eval_field_exact plus the source's incident field
+ * in its body, src may be NULL): interior on the guide rectangle, exterior on
+ * the eight rectangles around it and on L; Gauss-Legendre rules of nq x nq
+ * points per rectangle and 2 nq per segment.  x: device, the solution.
+ * out: alpha, the perimeter integral, the boundary flux, the flux through A.
+ * SCABS_E_ARG when the box does not contain the guide strictly, nq is not in
+ * [2, 64] or a perimeter point is not on the body's surface. */
+int scabs_poynting_decay(scabs_ctx *c, const double *x, const scabs_source *src, int body, double xpos,
+                         const double guide[4], const double box[4], int nq, double out[4]);
 
 /* Fields of an electric dipole (as scabs_rhs_dipole: current moment p = I l,
  * moment[6] re/im pairs, at pos inside body `body`) at points pts (host,

@@ -27,6 +27,7 @@ import subprocess
 from typing import List, Optional, Sequence
 
 import numpy as np
+import scipy.optimize as opt
 import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
@@ -89,6 +90,9 @@ def lib():
         L.or_incident_at_points.argtypes = [P, dp, zp, C.c_int, zp, zp]
         L.or_point_fields.argtypes = [P, zp, zp, zp]
         L.or_fields_at.argtypes = [P, zp, C.c_int, dp, C.c_int, zp, zp]
+        L.or_fields_at_exact.argtypes = [P, zp, C.c_int, dp, C.c_int, zp, zp]
+        L.or_source_field.argtypes = [C.c_double, C.c_double, dp, dp, C.c_double, zp, dp, zp, zp]
+        L.or_rhs_source.argtypes = [P, dp, dp, C.c_double, zp, C.c_int, zp]
         L.or_stencil.argtypes = [C.c_double, dp, ip, dp, dp]
         L.or_grid_setup.argtypes = [P, C.c_double]
         L.or_grid_weights.argtypes = [P, ip, dp, dp]
@@ -129,6 +133,19 @@ def dipole_field(k, Z, r0, p, r):
     H = np.zeros(3, complex)
     lib().or_dipole_field(k, Z, np.ascontiguousarray(r0, float), np.ascontiguousarray(p, complex),
                           np.ascontiguousarray(r, float), E, H)
+    return E, H
+
+
+def source_field(k, Z, src, r):
+    """Fields of a source (attributes pos, moment, and for a beam direction
+    and b > 0) at one point: the dipole, or the dipole at the complex position
+    pos - j b direction (Sec. II Gaussian beam), scaled by exp(-k b)."""
+    b = float(getattr(src, "b", 0.0))
+    bd = b * np.asarray(getattr(src, "direction", (1.0, 0.0, 0.0)), float)
+    E = np.zeros(3, complex)
+    H = np.zeros(3, complex)
+    lib().or_source_field(k, Z, np.ascontiguousarray(src.pos, float), np.ascontiguousarray(bd), b,
+                          np.ascontiguousarray(src.moment, complex), np.ascontiguousarray(r, float), E, H)
     return E, H
 
 
@@ -266,6 +283,129 @@ class Oracle:
         lib().or_fields_at(self._c, np.ascontiguousarray(x, complex), pts.shape[0], pts.ravel(), region,
                            E.ravel(), H.ravel())
         return E, H
+
+    def fields_at_exact(self, x, pts, region: int):
+        """Scattered fields at points, accurate near the surface (static part
+        analytic for triangles within 5 radii of the point)."""
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        E = np.zeros((pts.shape[0], 3), complex)
+        H = np.zeros((pts.shape[0], 3), complex)
+        lib().or_fields_at_exact(self._c, np.ascontiguousarray(x, complex), pts.shape[0], pts.ravel(), region,
+                                 E.ravel(), H.ravel())
+        return E, H
+
+    def rhs_source(self, src) -> np.ndarray:
+        b = float(getattr(src, "b", 0.0))
+        bd = b * np.asarray(getattr(src, "direction", (1.0, 0.0, 0.0)), float)
+        out = np.zeros(self.N, complex)
+        lib().or_rhs_source(self._c, np.ascontiguousarray(src.pos, float), np.ascontiguousarray(bd), b,
+                            np.ascontiguousarray(src.moment, complex), int(src.body), out)
+        return out
+
+    def source_fields_at(self, src, pts, region: int):
+        """Incident fields of a source at points of a region (zero outside its body)."""
+        pts = np.asarray(pts, float).reshape(-1, 3)
+        E = np.zeros((pts.shape[0], 3), complex)
+        H = np.zeros((pts.shape[0], 3), complex)
+        if region == src.body:
+            for i, r in enumerate(pts):
+                E[i], H[i] = source_field(self.k_i, self.Z_i, src, r)
+        return E, H
+
+    def total_fields_at(self, x, src, pts, region: int):
+        E, H = self.fields_at_exact(x, pts, region)
+        if src is not None:
+            Ei, Hi = self.source_fields_at(src, pts, region)
+            E, H = E + Ei, H + Hi
+        return E, H
+
+    def sigma_profile(self, ends, r) -> float:
+        """Conductivity of profile ends (Sec. IV, eq60; hat interpolant) at a point."""
+        acc = 0.0
+        for e in ends:
+            s = e.direction * (r[e.axis] - e.x0) / e.length
+            if s < 0:
+                continue
+            s = min(s, 1.0)
+            if getattr(e, "ctrl", None) is None:
+                acc += e.sigma0 * (1.0 if e.degree == 0 else s ** e.degree)
+            else:
+                acc += float(np.interp(s, np.linspace(0.0, 1.0, len(e.ctrl)), e.ctrl))
+        return acc
+
+    def magnetic_current_at(self, x, r, body: int):
+        """M = E x n at a surface point of `body` (its triangle found by
+        barycentric coordinates), from the RWG expansion."""
+        v = np.asarray(self.mesh.verts, float)
+        t = np.asarray(self.mesh.tris)
+        b = np.asarray(self.mesh.body)
+        tri = v[t]                                      # (nt, 3, 3)
+        n = self.nrm
+        h = np.einsum("ta,ta->t", r[None, :] - tri[:, 0], n)
+        cand = np.nonzero((np.abs(h) < 1e-7) & (b == body))[0]
+        best, bestv = -1, -1e300
+        for T in cand:
+            P = tri[T]
+            area2 = np.dot(np.cross(P[1] - P[0], P[2] - P[0]), n[T])
+            lam = [np.dot(np.cross(P[(k + 1) % 3] - r, P[(k + 2) % 3] - r), n[T]) / area2 for k in range(3)]
+            if min(lam) > bestv:
+                best, bestv = T, min(lam)
+        if best < 0 or bestv < -1e-7:
+            raise ValueError("point not on the surface of the body")
+        _, _, M = self.edge_currents(x)
+        P = tri[best]
+        area = 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+        Mv = np.zeros(3, complex)
+        for k in range(3):
+            e = self.tedge[best, k]
+            Mv += self.tsign[best, k] * self.elen[e] / (2 * area) * (r - P[k]) * M[e]
+        return Mv
+
+    def poynting_decay(self, x, src, body: int, xpos: float, guide, box, nq: int, ends):
+        """Decay rate from Poynting's theorem on the plane x = xpos (Sec. III,
+        eq_alpha_power): [int_L' sigma |E_tan|^2 + Re int_L (E x H*).n] /
+        [2 Re int_A (E x H*).x]; Gauss-Legendre rules (nq x nq per rectangle of
+        A, 2 nq per segment), |E_tan| = |M| on the guide surface."""
+        gx, gw = np.polynomial.legendre.leggauss(nq)
+        lx, lw = np.polynomial.legendre.leggauss(2 * nq)
+        ys = [box[0], guide[0], guide[1], box[1]]
+        zs = [box[2], guide[2], guide[3], box[3]]
+        fluxA = 0.0
+        for iy in range(3):
+            for iz in range(3):
+                hy, hz = 0.5 * (ys[iy + 1] - ys[iy]), 0.5 * (zs[iz + 1] - zs[iz])
+                cy, cz = 0.5 * (ys[iy + 1] + ys[iy]), 0.5 * (zs[iz + 1] + zs[iz])
+                Y, Zc = np.meshgrid(cy + hy * gx, cz + hz * gx, indexing="ij")
+                W = hy * hz * np.outer(gw, gw)
+                pts = np.stack([np.full(Y.size, xpos), Y.ravel(), Zc.ravel()], axis=1)
+                region = body if (iy == 1 and iz == 1) else -1
+                E, H = self.total_fields_at(x, src, pts, region)
+                S = np.cross(E, np.conj(H))
+                fluxA += float(np.sum(W.ravel() * S[:, 0].real))
+        fluxL = 0.0
+        for sd in range(4):
+            yside = sd < 2
+            lo, hi = (box[2], box[3]) if yside else (box[0], box[1])
+            tt = 0.5 * (lo + hi) + 0.5 * (hi - lo) * lx
+            if yside:
+                pts = np.stack([np.full_like(tt, xpos), np.full_like(tt, box[sd]), tt], axis=1)
+            else:
+                pts = np.stack([np.full_like(tt, xpos), tt, np.full_like(tt, box[sd])], axis=1)
+            nvec = np.zeros(3)
+            nvec[1 if yside else 2] = -1.0 if sd % 2 == 0 else 1.0
+            E, H = self.total_fields_at(x, src, pts, -1)
+            S = np.cross(E, np.conj(H))
+            fluxL += float(np.sum(0.5 * (hi - lo) * lw * (S.real @ nvec)))
+        perim = 0.0
+        for sd in range(4):
+            yside = sd < 2
+            lo, hi = (guide[2], guide[3]) if yside else (guide[0], guide[1])
+            for a in range(2 * nq):
+                tpar = 0.5 * (lo + hi) + 0.5 * (hi - lo) * lx[a]
+                r = np.array([xpos, guide[sd], tpar]) if yside else np.array([xpos, tpar, guide[sd]])
+                Mv = self.magnetic_current_at(x, r, body)
+                perim += 0.5 * (hi - lo) * lw[a] * self.sigma_profile(ends, r) * float(np.sum(np.abs(Mv) ** 2))
+        return (perim + fluxL) / (2 * fluxA), perim, fluxL, fluxA
 
     def point_basis(self):
         fv = np.zeros((self.np_, 3, 3))
@@ -594,3 +734,49 @@ def monitor_weights(xs: np.ndarray, beta: float) -> np.ndarray:
     returns w with b = w . E (the reflected amplitude)."""
     P = np.stack([np.exp(-1j * beta * xs), np.exp(1j * beta * xs)], axis=1)
     return np.linalg.pinv(P)[1]
+
+
+# ---------------------------------------------------------------------------
+# field post-processing on samples (Sec. I, Table I; Sec. III)
+# ---------------------------------------------------------------------------
+def swr(E):
+    """Standing-wave ratio max|E| / min|E| and the transmission-line
+    reflection coefficient (SWR - 1) / (SWR + 1)."""
+    a = np.abs(np.asarray(E))
+    s = float(a.max() / a.min())
+    return s, (s - 1) / (s + 1)
+
+
+def standing_wave_fit(xs, E, beta_lo: float, beta_hi: float):
+    """Least-squares E = a e^{-j beta x} + c e^{+j beta x}; beta fixed or the
+    residual's minimiser in [beta_lo, beta_hi] (dense scan, then bounded
+    scalar minimisation).  Returns (beta, |c/a|, relative residual)."""
+    xs = np.asarray(xs, float)
+    E = np.asarray(E, complex)
+
+    def fit(beta):
+        P = np.stack([np.exp(-1j * beta * xs), np.exp(1j * beta * xs)], axis=1)
+        coef, *_ = np.linalg.lstsq(P, E, rcond=None)
+        return coef, float(np.linalg.norm(E - P @ coef) / np.linalg.norm(E))
+
+    if beta_hi > beta_lo:
+        grid = np.linspace(beta_lo, beta_hi, 2001)
+        res = [fit(b)[1] for b in grid]
+        i = int(np.argmin(res))
+        lo, hi = grid[max(i - 1, 0)], grid[min(i + 1, len(grid) - 1)]
+        beta = float(opt.minimize_scalar(lambda b: fit(b)[1], bounds=(lo, hi), method="bounded",
+                                         options={"xatol": 1e-12}).x)
+    else:
+        beta = float(beta_lo)
+    coef, r = fit(beta)
+    return beta, float(abs(coef[1]) / abs(coef[0])), r
+
+
+def decay_fit(xs, E):
+    """alpha, beta of E ~ exp(-(alpha + j beta) x): straight-line fits of
+    ln|E| and of the unwrapped phase."""
+    xs = np.asarray(xs, float)
+    E = np.asarray(E, complex)
+    sa, _ = np.polyfit(xs, np.log(np.abs(E)), 1)
+    sp, _ = np.polyfit(xs, np.unwrap(np.angle(E)), 1)
+    return float(-sa), float(-sp)

@@ -707,6 +707,54 @@ void or_dipole_field(double k, double Z, const double *r0, const zc *p, const do
   }
 }
 
+/* Gaussian beam of Sec. II as a dipole at a complex position (complex source
+ * point): the dipole's closed form above with r0 replaced by r0 - j b dir,
+ * i.e. d = r - r0 + j bd (bd = b dir), R = sqrt(d.d) on the principal branch
+ * (csqrt), u = d / R, and the whole field scaled by exp(-k b).  b = 0 is the
+ * point dipole. */
+void or_source_field(double k, double Z, const double *r0, const double *bd, double b, const zc *p, const double *r,
+                     zc *E, zc *H) {
+  if (b == 0.0) { or_dipole_field(k, Z, r0, p, r, E, H); return; }
+  zc d[3] = {r[0] - r0[0] + I * bd[0], r[1] - r0[1] + I * bd[1], r[2] - r0[2] + I * bd[2]};
+  zc R = csqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  zc u[3] = {d[0] / R, d[1] / R, d[2] / R};
+  zc e = cexp(-I * k * R - k * b);
+  zc G = e / (4 * PI * R);
+  zc G1 = -(1.0 + I * k * R) * e / (4 * PI * R * R);
+  zc G2 = (2.0 + 2.0 * I * k * R - k * k * R * R) * e / (4 * PI * R * R * R);
+  zc up = u[0] * p[0] + u[1] * p[1] + u[2] * p[2];
+  H[0] = G1 * (u[1] * p[2] - u[2] * p[1]);
+  H[1] = G1 * (u[2] * p[0] - u[0] * p[2]);
+  H[2] = G1 * (u[0] * p[1] - u[1] * p[0]);
+  for (int a = 0; a < 3; a++) {
+    zc hess_p = G2 * up * u[a] + (G1 / R) * (p[a] - up * u[a]);
+    E[a] = -I * k * Z * (p[a] * G + hess_p / (k * k));
+  }
+}
+
+/* right-hand side of a source (dipole or beam) in the interior of `body` */
+int or_rhs_source(Ctx *c, const double *r0, const double *bd, double b, const zc *p, int body, zc *rhs) {
+  memset(rhs, 0, sizeof(zc) * c->N);
+  for (int T = 0; T < c->nt; T++) {
+    if (c->body[T] != body) continue;
+    for (int q = 0; q < NQ; q++) {
+      const double *r = c->qp + 3 * (T * NQ + q);
+      double w = c->qw[T * NQ + q], sg = c->sigma[T * NQ + q];
+      zc E[3], H[3];
+      or_source_field(c->k_i, c->Z_i, r0, bd, b, p, r, E, H);
+      for (int i = 0; i < 3; i++) {
+        double g[3], dg; half_rwg(c, T, i, r, g, &dg);
+        int n = c->tedge[3 * T + i];
+        int rE, rH, r14; edge_slots(c, n, &rE, &rH, &r14);
+        rhs[rE] += w * rdot_z(g, E);
+        rhs[rH] += w * rdot_z(g, H);
+        if (r14 >= 0) rhs[r14] += w * sg * rdot_z(g, E);
+      }
+    }
+  }
+  return 0;
+}
+
 /* b = [b_E^L, b_H^L, b_E^R, b_H^R, b_Esigma^R]; the incident field exists in
  * the interior medium of body `body` only (Sec. II: fields of the source in a
  * homogeneous space with the interior material). */
@@ -839,6 +887,40 @@ void or_fields_at(Ctx *c, const zc *x, int npts, const double *pts, int region, 
           zc LM = I * k * (Mq[a] * G + g[a] * rM / (k * k));
           e[a] += w * (-Z * LJ - gM[a]);
           hh[a] += w * (gJ[a] - LM / Z);
+        }
+      }
+    }
+    for (int a = 0; a < 3; a++) { E[3 * p + a] = e[a]; H[3 * p + a] = hh[a]; }
+  }
+  free(Je); free(Ji); free(M);
+}
+
+/* Fields at points close to the surface as well: per source triangle the
+ * inner integrals of inner_exact, with the static part analytic when the
+ * point lies within 5 triangle radii of the centroid (the near-field radius
+ * of the exact evaluation), the plain rule otherwise. */
+void or_fields_at_exact(Ctx *c, const zc *x, int npts, const double *pts, int region, zc *E, zc *H) {
+  zc *Je = malloc(sizeof(zc) * c->ne), *Ji = malloc(sizeof(zc) * c->ne), *M = malloc(sizeof(zc) * c->ne);
+  edge_currents(c, x, Je, Ji, M);
+  double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
+#pragma omp parallel for schedule(dynamic)
+  for (int p = 0; p < npts; p++) {
+    const double *r = pts + 3 * p;
+    zc e[3] = {0, 0, 0}, hh[3] = {0, 0, 0};
+    for (int T = 0; T < c->nt; T++) {
+      if (region >= 0 && c->body[T] != region) continue;
+      double d[3]; sub3(r, c->cen + 3 * T, d);
+      double thr = 5.0 * c->rho[T];
+      int near = dot3(d, d) < thr * thr;
+      Inner in;
+      inner_exact(c, T, r, k, near, &in);
+      for (int j = 0; j < 3; j++) {
+        int m = c->tedge[3 * T + j];
+        zc J = region < 0 ? Je[m] : Ji[m], Mm = region < 0 ? M[m] : -M[m];
+        for (int a = 0; a < 3; a++) {
+          zc L = I * k * (in.a[j][a] + in.gphi[j][a] / (k * k));   /* L(f_j), K(f_j) = -c_j */
+          e[a] += -Z * L * J - in.c[j][a] * Mm;
+          hh[a] += in.c[j][a] * J - L * Mm / Z;
         }
       }
     }

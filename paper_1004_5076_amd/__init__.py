@@ -28,7 +28,9 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_noalloc", "scabs_dipole_field", "scabs_gradient", "scabs_eval_field_transpose", "scabs_sigma_params",
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
-            "scabs_last_error", "scabs_destroy"]
+            "scabs_last_error", "scabs_destroy", "scabs_eval_field_exact", "scabs_rhs_source",
+            "scabs_incident_source_points", "scabs_source_field", "scabs_swr", "scabs_standing_wave_fit",
+            "scabs_decay_fit", "scabs_poynting_decay"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
           "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32", "toeapply32", "toeapply64",
           "toeproduct32", "toeproduct64"]
@@ -61,6 +63,26 @@ class Info(C.Structure):
         d["grid_phys"] = list(self.grid_phys)
         d["grid_fft"] = list(self.grid_fft)
         return d
+
+
+class Source(C.Structure):
+    """scabs_source: a point dipole (b = 0) or the complex-source-point beam
+    along +dir with waist at pos and Rayleigh distance b."""
+    _fields_ = [("pos", C.c_double * 3), ("dir", C.c_double * 3), ("b", C.c_double), ("moment", C.c_double * 6),
+                ("body", C.c_int32), ("pad", C.c_int32)]
+
+    @staticmethod
+    def make(pos, moment, body: int = 0, direction=(1.0, 0.0, 0.0), b: float = 0.0) -> "Source":
+        s = Source()
+        m = np.asarray(moment, dtype=np.complex128)
+        for a in range(3):
+            s.pos[a] = float(pos[a])
+            s.dir[a] = float(direction[a])
+            s.moment[2 * a] = float(m[a].real)
+            s.moment[2 * a + 1] = float(m[a].imag)
+        s.b = float(b)
+        s.body = int(body)
+        return s
 
 
 class SolveInfo(C.Structure):
@@ -115,6 +137,14 @@ def load() -> C.CDLL:
     L.scabs_profile_bytes.argtypes = [P, dp]
     L.scabs_profile_mask.argtypes = [P, C.c_uint32]
     L.scabs_last_error.restype = C.c_char_p
+    L.scabs_eval_field_exact.argtypes = [P, P, dp, C.c_int, C.c_int, P, P]
+    L.scabs_rhs_source.argtypes = [P, C.POINTER(Source), P]
+    L.scabs_incident_source_points.argtypes = [P, C.POINTER(Source), P]
+    L.scabs_source_field.argtypes = [P, C.POINTER(Source), dp, C.c_int, C.c_int, P, P]
+    L.scabs_swr.argtypes = [dp, C.c_int, dp]
+    L.scabs_standing_wave_fit.argtypes = [dp, dp, C.c_int, C.c_double, C.c_double, dp]
+    L.scabs_decay_fit.argtypes = [dp, dp, C.c_int, dp]
+    L.scabs_poynting_decay.argtypes = [P, P, C.POINTER(Source), C.c_int, C.c_double, dp, dp, C.c_int, dp]
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
     _lib = L
@@ -282,6 +312,51 @@ class Context:
         self._check(self._L.scabs_eval_field(self._c, C.c_void_p(x.data_ptr()), pp, p.shape[0], int(region),
                                              C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
         return E, H
+
+    def eval_field_exact(self, x, pts, region: int):
+        """Scattered fields at points of a region, accurate near the surface."""
+        import torch
+        x = self._dev(x)
+        p, pp = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        E = torch.empty((p.shape[0], 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E)
+        self._check(self._L.scabs_eval_field_exact(self._c, C.c_void_p(x.data_ptr()), pp, p.shape[0], int(region),
+                                                   C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
+        return E, H
+
+    def rhs_source(self, src: Source):
+        import torch
+        b = torch.empty(self.N, dtype=torch.complex128, device=self.device)
+        self._check(self._L.scabs_rhs_source(self._c, C.byref(src), C.c_void_p(b.data_ptr())))
+        return b
+
+    def incident_source_points(self, src: Source):
+        import torch
+        npt = self.info()["n_points"]
+        E = torch.empty((npt, 3), dtype=torch.complex128, device=self.device)
+        self._check(self._L.scabs_incident_source_points(self._c, C.byref(src), C.c_void_p(E.data_ptr())))
+        return E
+
+    def source_field(self, src: Source, pts, region: int):
+        import torch
+        p, pp = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        E = torch.empty((p.shape[0], 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E)
+        self._check(self._L.scabs_source_field(self._c, C.byref(src), pp, p.shape[0], int(region),
+                                               C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
+        return E, H
+
+    def poynting_decay(self, x, src: Optional[Source], body: int, xpos: float, guide, box, nq: int = 8):
+        """Decay rate from Poynting's theorem on the plane x = xpos; returns
+        (alpha, perimeter integral, boundary flux, flux through the box)."""
+        x = self._dev(x)
+        g, gp = _f64(np.asarray(guide, dtype=np.float64))
+        bx, bp = _f64(np.asarray(box, dtype=np.float64))
+        out = np.zeros(4)
+        self._check(self._L.scabs_poynting_decay(self._c, C.c_void_p(x.data_ptr()),
+                                                 C.byref(src) if src is not None else None, int(body), float(xpos),
+                                                 gp, bp, int(nq), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return tuple(float(v) for v in out)
 
     def dipole_field(self, pos, moment, body: int, pts, region: int):
         """Closed-form fields of the dipole at points of a region (zero outside
@@ -483,3 +558,42 @@ def reflected_amplitude(E_y, xs, beta: float):
     P = np.stack([np.exp(-1j * beta * xs), np.exp(1j * beta * xs)], axis=1)
     w = torch.as_tensor(np.linalg.pinv(P)[1], dtype=torch.complex128, device=E_y.device)
     return (w * E_y).sum()
+
+
+def _cplx(E):
+    e = np.ascontiguousarray(np.asarray(E, dtype=np.complex128))
+    return e, e.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def swr(E):
+    """(standing-wave ratio, reflection coefficient) of field samples."""
+    e, ep = _cplx(E)
+    out = np.zeros(2)
+    rc = load().scabs_swr(ep, e.shape[0], out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != SCABS_OK:
+        raise ScabsError(rc, "scabs_swr")
+    return float(out[0]), float(out[1])
+
+
+def standing_wave_fit(xs, E, beta_lo: float, beta_hi: float):
+    """(beta, |r|, relative residual, |a|, |c|, arg r) of E = a e^{-j beta x} + c e^{j beta x}."""
+    x = np.ascontiguousarray(np.asarray(xs, dtype=np.float64))
+    e, ep = _cplx(E)
+    out = np.zeros(6)
+    rc = load().scabs_standing_wave_fit(x.ctypes.data_as(C.POINTER(C.c_double)), ep, e.shape[0], float(beta_lo),
+                                        float(beta_hi), out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != SCABS_OK:
+        raise ScabsError(rc, "scabs_standing_wave_fit")
+    return tuple(float(v) for v in out)
+
+
+def decay_fit(xs, E):
+    """(alpha, beta, relative residual, c0) of ln|E| = c0 - alpha x, phase = p0 - beta x."""
+    x = np.ascontiguousarray(np.asarray(xs, dtype=np.float64))
+    e, ep = _cplx(E)
+    out = np.zeros(4)
+    rc = load().scabs_decay_fit(x.ctypes.data_as(C.POINTER(C.c_double)), ep, e.shape[0],
+                                out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != SCABS_OK:
+        raise ScabsError(rc, "scabs_decay_fit")
+    return tuple(float(v) for v in out)

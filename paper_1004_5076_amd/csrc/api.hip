@@ -129,6 +129,7 @@ struct scabs_ctx {
   int *col = nullptr;
   int64_t nnz = 0;
   double *qp64 = nullptr;
+  const TriD *trid = nullptr;   // per-triangle geometry records (near-surface fields)
   int *body_dev = nullptr;
   int64_t *tpos = nullptr;     // per near CSR entry (n, m): index of the entry (m, n)
   NearSetupArgs nsa{};         // near-pair tables kept for the pointwise-field pass
@@ -1030,6 +1031,11 @@ static int do_build(scabs_ctx *c) {
   for (int n = 0; n < g.ne; n++)
     if (L.isR[n]) c->nnzR += c->near.rowptr[n + 1] - c->near.rowptr[n];
   c->qp64 = c->mem.upload(g.qp);
+  {
+    std::vector<TriD> all;
+    make_tri_records(g, all);
+    c->trid = c->mem.upload(all);
+  }
   c->body_dev = c->mem.upload(g.body);
   // ---- twiddles and kernel spectra ---------------------------------------------
   std::vector<cx<double>> tw_all;
@@ -1919,14 +1925,54 @@ int scabs_layout(const scabs_ctx *c, int32_t *is_r, int32_t *idx) {
   return SCABS_OK;
 }
 
+// device form of a point dipole (b = 0) or of a complex-source-point beam
+static SourceDev source_dev(const double pos[3], const double moment[6], const double *dir, double b) {
+  SourceDev S{};
+  for (int a = 0; a < 3; a++) {
+    S.r0[a] = pos[a];
+    S.bd[a] = b > 0 ? b * dir[a] : 0.0;
+    S.p[a] = {moment[2 * a], moment[2 * a + 1]};
+  }
+  S.b = b > 0 ? b : 0.0;
+  return S;
+}
+// checks of a source descriptor: body in range, b >= 0, unit direction when b > 0
+static int check_source(scabs_ctx *c, const scabs_source *src) {
+  if (!src) return SCABS_E_ARG;
+  if (src->body < 0 || src->body >= c->geo.nbody) return fail(c, SCABS_E_ARG, "source body out of range");
+  if (!(src->b >= 0)) return fail(c, SCABS_E_ARG, "source b must be >= 0");
+  if (src->b > 0) {
+    const double n = std::sqrt(src->dir[0] * src->dir[0] + src->dir[1] * src->dir[1] + src->dir[2] * src->dir[2]);
+    if (std::fabs(n - 1.0) > 1e-9) return fail(c, SCABS_E_ARG, "beam direction must be a unit vector");
+  }
+  return SCABS_OK;
+}
+
+static void rhs_source(scabs_ctx *c, const SourceDev &S, int body, double *b) {
+  HIPCHK(hipMemsetAsync(b, 0, sizeof(double) * 2 * c->lay.N, c->stream));
+  launch_rhs_dipole(c->geo.nt, c->qp64, c->body_dev, c->p64.tris, c->p64.pts, c->edges, c->k_i, c->Z_i, S, body, b,
+                    c->stream);
+}
+
+int scabs_rhs_source(scabs_ctx *c, const scabs_source *src, double *b) {
+  if (!c || !src || !b) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (int st = check_source(c, src)) return st;
+  try {
+    rhs_source(c, source_dev(src->pos, src->moment, src->dir, src->b), src->body, b);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
 int scabs_rhs_dipole(scabs_ctx *c, const double pos[3], const double moment[6], int body, double *b) {
   if (!c || !pos || !moment || !b) return SCABS_E_ARG;
   if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
   if (body < 0 || body >= c->geo.nbody) return fail(c, SCABS_E_ARG, "body index out of range");
   try {
-    HIPCHK(hipMemsetAsync(b, 0, sizeof(double) * 2 * c->lay.N, c->stream));
-    launch_rhs_dipole(c->geo.nt, c->qp64, nullptr, nullptr, c->body_dev, c->p64.tris, c->p64.pts, c->edges, c->k_i,
-                      c->Z_i, pos, moment, body, b, c->stream);
+    rhs_source(c, source_dev(pos, moment, nullptr, 0.0), body, b);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
   }
@@ -2014,8 +2060,23 @@ int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double
   if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
   if (body < 0 || body >= c->geo.nbody) return fail(c, SCABS_E_ARG, "body index out of range");
   try {
-    launch_incident_points(c->p64.op.np, c->body_dev, c->p64.pts, c->qp64, c->k_i, c->Z_i, pos, moment, body,
-                           (cx<double> *)E, c->stream);
+    launch_incident_points(c->p64.op.np, c->body_dev, c->p64.pts, c->qp64, c->k_i, c->Z_i,
+                           source_dev(pos, moment, nullptr, 0.0), body, (cx<double> *)E, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
+int scabs_incident_source_points(scabs_ctx *c, const scabs_source *src, double *E) {
+  if (!c || !src || !E) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (int st = check_source(c, src)) return st;
+  try {
+    launch_incident_points(c->p64.op.np, c->body_dev, c->p64.pts, c->qp64, c->k_i, c->Z_i,
+                           source_dev(src->pos, src->moment, src->dir, src->b), src->body, (cx<double> *)E,
+                           c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
   }
@@ -2070,6 +2131,43 @@ int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts,
   return SCABS_OK;
 }
 
+int scabs_eval_field_exact(scabs_ctx *c, const double *x, const double *pts, int npts, int region, double *E,
+                           double *H) {
+  if (!c || !x || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (region >= c->geo.nbody) return fail(c, SCABS_E_ARG, "region out of range");
+  try {
+    DevMem tmp;
+    double *p = tmp.alloc<double>(3 * (size_t)npts);
+    HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
+    launch_unpack(c->p64.op, x, c->stream);
+    const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
+    launch_eval_field_exact(c->p64.op, c->trid, p, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
+// incident fields of a source at points of one region: the closed form in
+// the interior medium of its body, zero elsewhere
+static void source_field(scabs_ctx *c, const SourceDev &S, int body, const double *pts, int npts, int region,
+                         double *E, double *H) {
+  if (region != body) {
+    HIPCHK(hipMemsetAsync(E, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
+    HIPCHK(hipMemsetAsync(H, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return;
+  }
+  DevMem tmp;
+  double *p = tmp.alloc<double>(3 * (size_t)npts);
+  HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
+  launch_dipole_points(npts, p, c->k_i, c->Z_i, S, (cx<double> *)E, (cx<double> *)H, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
 int scabs_dipole_field(scabs_ctx *c, const double pos[3], const double moment[6], int body, const double *pts,
                        int npts, int region, double *E, double *H) {
   if (!c || !pos || !moment || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
@@ -2077,19 +2175,153 @@ int scabs_dipole_field(scabs_ctx *c, const double pos[3], const double moment[6]
   if (body < 0 || body >= c->geo.nbody || region >= c->geo.nbody)
     return fail(c, SCABS_E_ARG, "body or region out of range");
   try {
-    if (region != body) {
-      HIPCHK(hipMemsetAsync(E, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
-      HIPCHK(hipMemsetAsync(H, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
-    } else {
-      DevMem tmp;
-      double *p = tmp.alloc<double>(3 * (size_t)npts);
-      HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
-      launch_dipole_points(npts, p, c->k_i, c->Z_i, pos, moment, (cx<double> *)E, (cx<double> *)H, c->stream);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(c->stream));
-      return SCABS_OK;
+    source_field(c, source_dev(pos, moment, nullptr, 0.0), body, pts, npts, region, E, H);
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
+int scabs_source_field(scabs_ctx *c, const scabs_source *src, const double *pts, int npts, int region, double *E,
+                       double *H) {
+  if (!c || !src || !pts || npts < 1 || !E || !H) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (int st = check_source(c, src)) return st;
+  if (region >= c->geo.nbody) return fail(c, SCABS_E_ARG, "region out of range");
+  try {
+    source_field(c, source_dev(src->pos, src->moment, src->dir, src->b), src->body, pts, npts, region, E, H);
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
+// total fields at points of one region on the host: scattered (near-surface
+// accurate) plus the source's incident field where it lives
+static void total_fields_host(scabs_ctx *c, const double *x, const scabs_source *src, const std::vector<double> &pts,
+                              int region, std::vector<std::complex<double>> &E, std::vector<std::complex<double>> &H) {
+  const int n = (int)(pts.size() / 3);
+  E.assign(3 * (size_t)n, 0.0);
+  H.assign(3 * (size_t)n, 0.0);
+  if (n == 0) return;
+  DevMem tmp;
+  double *p = tmp.upload(pts);
+  cx<double> *Ed = tmp.alloc<cx<double>>(3 * (size_t)n), *Hd = tmp.alloc<cx<double>>(3 * (size_t)n);
+  launch_unpack(c->p64.op, x, c->stream);
+  const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
+  launch_eval_field_exact(c->p64.op, c->trid, p, n, region, k, Z, Ed, Hd, c->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<cx<double>> e(3 * (size_t)n), h(3 * (size_t)n), ei, hi;
+  HIPCHK(hipMemcpyAsync(e.data(), Ed, sizeof(cx<double>) * e.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(h.data(), Hd, sizeof(cx<double>) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  if (src && src->body == region) {
+    ei.resize(e.size());
+    hi.resize(h.size());
+    launch_dipole_points(n, p, c->k_i, c->Z_i, source_dev(src->pos, src->moment, src->dir, src->b), Ed, Hd, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ei.data(), Ed, sizeof(cx<double>) * e.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hi.data(), Hd, sizeof(cx<double>) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < e.size(); i++) {
+    E[i] = {e[i].x, e[i].y};
+    H[i] = {h[i].x, h[i].y};
+    if (!ei.empty()) {
+      E[i] += std::complex<double>(ei[i].x, ei[i].y);
+      H[i] += std::complex<double>(hi[i].x, hi[i].y);
     }
-    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+}
+
+int scabs_poynting_decay(scabs_ctx *c, const double *x, const scabs_source *src, int body, double xpos,
+                         const double guide[4], const double box[4], int nq, double out[4]) {
+  if (!c || !x || !guide || !box || !out) return SCABS_E_ARG;
+  if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
+  if (body < 0 || body >= c->geo.nbody) return fail(c, SCABS_E_ARG, "body out of range");
+  if (src)
+    if (int st = check_source(c, src)) return st;
+  if (nq < 2 || nq > 64) return fail(c, SCABS_E_ARG, "nq must be in [2, 64]");
+  if (!(box[0] < guide[0] && guide[0] < guide[1] && guide[1] < box[1] && box[2] < guide[2] && guide[2] < guide[3] &&
+        guide[3] < box[3]))
+    return fail(c, SCABS_E_ARG, "the box must contain the guide rectangle strictly");
+  try {
+    const Geometry &g = c->geo;
+    std::vector<double> gx, gw;
+    gauss_legendre(nq, gx, gw);
+    // rectangles of A: the guide's (interior) and the eight around it (exterior)
+    const double ys[4] = {box[0], guide[0], guide[1], box[1]}, zs[4] = {box[2], guide[2], guide[3], box[3]};
+    std::vector<double> pin, win, pex, wex;
+    for (int iy = 0; iy < 3; iy++)
+      for (int iz = 0; iz < 3; iz++) {
+        const bool inside = iy == 1 && iz == 1;
+        std::vector<double> &P = inside ? pin : pex, &W = inside ? win : wex;
+        const double hy = 0.5 * (ys[iy + 1] - ys[iy]), hz = 0.5 * (zs[iz + 1] - zs[iz]);
+        const double cy = 0.5 * (ys[iy + 1] + ys[iy]), cz = 0.5 * (zs[iz + 1] + zs[iz]);
+        for (int a = 0; a < nq; a++)
+          for (int b = 0; b < nq; b++) {
+            P.insert(P.end(), {xpos, cy + hy * gx[a], cz + hz * gx[b]});
+            W.push_back(hy * hz * gw[a] * gw[b]);
+          }
+      }
+    // boundary L of A (exterior medium): 2 nq points per side, outward normals
+    std::vector<double> pl, wl, nl;
+    for (int sd = 0; sd < 4; sd++) {
+      const bool yside = sd < 2;   // sides y = box[0], box[1], then z = box[2], box[3]
+      const double lo = yside ? box[2] : box[0], hi = yside ? box[3] : box[1];
+      std::vector<double> lx, lw;
+      gauss_legendre(2 * nq, lx, lw);
+      for (int a = 0; a < 2 * nq; a++) {
+        const double t = 0.5 * (lo + hi) + 0.5 * (hi - lo) * lx[a];
+        if (yside)
+          pl.insert(pl.end(), {xpos, box[sd], t});
+        else
+          pl.insert(pl.end(), {xpos, t, box[sd]});
+        wl.push_back(0.5 * (hi - lo) * lw[a]);
+        const double sgn = (sd % 2 == 0) ? -1.0 : 1.0;
+        nl.insert(nl.end(), {0.0, yside ? sgn : 0.0, yside ? 0.0 : sgn});
+      }
+    }
+    std::vector<std::complex<double>> Ei, Hi, Ee, He, El, Hl;
+    total_fields_host(c, x, src, pin, body, Ei, Hi);
+    total_fields_host(c, x, src, pex, -1, Ee, He);
+    total_fields_host(c, x, src, pl, -1, El, Hl);
+    auto sx = [](const std::complex<double> *E, const std::complex<double> *H) {   // (E x H*) . x
+      return (E[1] * std::conj(H[2]) - E[2] * std::conj(H[1])).real();
+    };
+    double fluxA = 0, fluxL = 0, perim = 0;
+    for (size_t i = 0; i < win.size(); i++) fluxA += win[i] * sx(&Ei[3 * i], &Hi[3 * i]);
+    for (size_t i = 0; i < wex.size(); i++) fluxA += wex[i] * sx(&Ee[3 * i], &He[3 * i]);
+    for (size_t i = 0; i < wl.size(); i++) {
+      const std::complex<double> *E = &El[3 * i], *H = &Hl[3 * i];
+      const std::complex<double> S[3] = {E[1] * std::conj(H[2]) - E[2] * std::conj(H[1]),
+                                         E[2] * std::conj(H[0]) - E[0] * std::conj(H[2]),
+                                         E[0] * std::conj(H[1]) - E[1] * std::conj(H[0])};
+      fluxL += wl[i] * (S[1].real() * nl[3 * i + 1] + S[2].real() * nl[3 * i + 2]);
+    }
+    // the guide's perimeter at xpos: sigma |E_tan|^2 = sigma |M|^2 (M = E x n)
+    std::vector<double> xh(2 * (size_t)c->lay.N);
+    HIPCHK(hipMemcpy(xh.data(), x, sizeof(double) * xh.size(), hipMemcpyDeviceToHost));
+    double ext = 0;
+    for (int i = 0; i < 4; i++) ext = std::max(ext, std::fabs(box[i]));
+    const double tol = 1e-7 * std::max(ext, std::fabs(xpos) + 1.0);
+    std::vector<double> lx, lw;
+    gauss_legendre(2 * nq, lx, lw);
+    for (int sd = 0; sd < 4; sd++) {
+      const bool yside = sd < 2;
+      const double lo = yside ? guide[2] : guide[0], hi = yside ? guide[3] : guide[1];
+      for (int a = 0; a < 2 * nq; a++) {
+        const double t = 0.5 * (lo + hi) + 0.5 * (hi - lo) * lx[a];
+        const double r[3] = {xpos, yside ? guide[sd] : t, yside ? t : guide[sd]};
+        const int T = locate_surface_point(g, r, body, tol);
+        if (T < 0) return fail(c, SCABS_E_ARG, "a point of the guide rectangle is not on the body's surface");
+        std::complex<double> J[3], M[3];
+        surface_currents_at(g, c->lay, xh.data(), T, r, false, J, M);
+        const double m2 = std::norm(M[0]) + std::norm(M[1]) + std::norm(M[2]);
+        perim += 0.5 * (hi - lo) * lw[a] * sigma_at(g, c->ends, r, T) * m2;
+      }
+    }
+    out[0] = (perim + fluxL) / (2.0 * fluxA);
+    out[1] = perim;
+    out[2] = fluxL;
+    out[3] = fluxA;
   }
   SCABS_CATCH(c)
   return SCABS_OK;

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <complex>
 #include <vector>
 
 #include "../../include/scabs.h"
@@ -95,6 +96,14 @@ struct LocalTerms {
 std::string build_geometry(const std::vector<double> &v, const std::vector<int> &t, const std::vector<int> &body,
                            Geometry &g);
 void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<double> &sigma);
+// conductivity at a point r of triangle T: profile ends evaluated at r, raw
+// per-point values taken at T's nearest quadrature point
+double sigma_at(const Geometry &g, const std::vector<SigmaEnd> &ends, const double *r, int T);
+// post-processing helpers
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+int locate_surface_point(const Geometry &g, const double *r, int body, double tol);
+void surface_currents_at(const Geometry &g, const Layout &L, const double *x, int T, const double *r, bool interior,
+                         std::complex<double> J[3], std::complex<double> M[3]);
 void build_layout(const Geometry &g, Layout &L);
 void sigma_param_jacobian(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<int64_t> &ptr,
                           std::vector<int> &idx, std::vector<double> &val, int64_t *npar);

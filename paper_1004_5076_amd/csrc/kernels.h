@@ -216,10 +216,20 @@ void launch_point_fields(const DevOperator<double> &op, const DevGrid<double> &e
                          double inv_h, cx<double> *Ee, cx<double> *Ei, hipStream_t s);
 void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, const cx<double> *Ei,
                        const cx<double> *Einc, double *dfds, hipStream_t s);
-void launch_dipole_points(int npts, const double *pts, double k, double Z, const double *pos, const double *mom,
-                          cx<double> *E, cx<double> *H, hipStream_t s);
+// fields at points near or on either side of the surface: per triangle the
+// static part analytic within SCABS_NEAR_FIELD_RADIUS triangle radii
+void launch_eval_field_exact(const DevOperator<double> &op, const TriD *tri, const double *pts, int npts, int region,
+                             double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s);
+// an incident source in the interior medium: a point dipole (b = 0) at r0 or
+// the complex-source-point beam at r0 - j b dir (bd = b dir); moment p
+struct SourceDev {
+  double r0[3], bd[3], b;
+  cx<double> p[3];
+};
+void launch_dipole_points(int npts, const double *pts, double k, double Z, const SourceDev &S, cx<double> *E,
+                          cx<double> *H, hipStream_t s);
 void launch_incident_points(int np, const int *body, const PointRec<double> *pts, const double *qp, double k, double Z,
-                            const double *pos, const double *mom, int bodyid, cx<double> *E, hipStream_t s);
+                            const SourceDev &S, int bodyid, cx<double> *E, hipStream_t s);
 
 // fields at off-surface points (currents from op.src) and the transpose of
 // their E part (adjoint currents collected into y, unknown space)
@@ -290,8 +300,8 @@ template <typename T>
 void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb, int parts = TOE_ALL);
 
 // ---- misc --------------------------------------------------------------------
-void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,
-                       const TriRec<double> *tris, const PointRec<double> *pts, const EdgeRec *edges, double k, double Z,
-                       const double *pos, const double *mom, int bodyid, double *b, hipStream_t s);
+void launch_rhs_dipole(int nt, const double *qp, const int *body, const TriRec<double> *tris,
+                       const PointRec<double> *pts, const EdgeRec *edges, double k, double Z, const SourceDev &S,
+                       int bodyid, double *b, hipStream_t s);
 
 }  // namespace scabs

@@ -15,6 +15,7 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "near_math.h"
 
 namespace scabs {
 
@@ -832,6 +833,73 @@ eval_field_kernel(DevOperator<double> op, const double *__restrict__ qp, const d
 void launch_eval_field(const DevOperator<double> &op, const double *qp, const double *pts, int npts, int region,
                        double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s) {
   hipLaunchKernelGGL(eval_field_kernel, dim3(npts), dim3(EF_THREADS), 0, s, op, qp, pts, region, k, Z, E, H);
+}
+
+// The same fields, accurate close to the surface: per source triangle the
+// inner integrals of its three half-RWG functions (inner_j), with the static
+// part 1/(4 pi R) integrated analytically and the 7-point rule on the smooth
+// remainder when the point lies within SCABS_NEAR_FIELD_RADIUS triangle radii
+// of the centroid, the plain rule otherwise.  Threads over triangles, one
+// work-group per point.
+__global__ void __launch_bounds__(EF_THREADS)
+eval_field_exact_kernel(DevOperator<double> op, const TriD *__restrict__ tri, const double *__restrict__ pts,
+                        int region, double k, double Z, cx<double> *__restrict__ E, cx<double> *__restrict__ H) {
+  const int t = blockIdx.x;
+  const D3 r = {pts[3 * t], pts[3 * t + 1], pts[3 * t + 2]};
+  const double ik2 = 1.0 / (k * k);
+  cx<double> e[3] = {{0, 0}, {0, 0}, {0, 0}}, h[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int T = threadIdx.x; T < op.nt; T += blockDim.x) {
+    const TriRec<double> tr = op.tris[T];
+    if (region >= 0 && tr.body != region) continue;
+    const TriD *B = tri + T;
+    const D3 dc = r - D3{B->cen[0], B->cen[1], B->cen[2]};
+    const double thr = SCABS_NEAR_FIELD_RADIUS * B->rho;
+    const bool near = dotd(dc, dc) < thr * thr;
+    StaticJ st = {0, {0, 0, 0}, {0, 0, 0}};
+    if (near) st = static_of(r, B, 0.0);
+    for (int j = 0; j < 3; j++) {
+      const int m = tr.edge[j];
+      const cx<double> J = op.src[3 * m + (region < 0 ? 0 : 1)];
+      const cx<double> M = region < 0 ? op.src[3 * m + 2] : -op.src[3 * m + 2];
+      InnerJ in;
+      inner_j(r, B, 0.0, j, near, st, k, in);
+      // L(f) = jk (a + k^-2 gphi), K(f) = -c; E = -Z L(J) + K(M), H = -K(J) - L(M) / Z
+      const cx<double> Lf[3] = {mul_j(in.a.x + in.gphi.x * ik2) * k, mul_j(in.a.y + in.gphi.y * ik2) * k,
+                                mul_j(in.a.z + in.gphi.z * ik2) * k};
+      const cx<double> cf[3] = {in.c.x, in.c.y, in.c.z};
+      for (int a = 0; a < 3; a++) {
+        e[a] += Lf[a] * J * (-Z) - cf[a] * M;
+        h[a] += cf[a] * J - Lf[a] * M * (1.0 / Z);
+      }
+    }
+  }
+  __shared__ cx<double> red[EF_THREADS / 64][6];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = 0; a < 3; a++) {
+    e[a].x = wsum(e[a].x);
+    e[a].y = wsum(e[a].y);
+    h[a].x = wsum(h[a].x);
+    h[a].y = wsum(h[a].y);
+  }
+  if (lane == 0)
+    for (int a = 0; a < 3; a++) {
+      red[wv][a] = e[a];
+      red[wv][3 + a] = h[a];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    cx<double> s = {0, 0};
+    for (int w = 0; w < EF_THREADS / 64; w++) s += red[w][threadIdx.x];
+    if (threadIdx.x < 3)
+      E[3 * t + threadIdx.x] = s;
+    else
+      H[3 * t + threadIdx.x - 3] = s;
+  }
+}
+
+void launch_eval_field_exact(const DevOperator<double> &op, const TriD *tri, const double *pts, int npts, int region,
+                             double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s) {
+  hipLaunchKernelGGL(eval_field_exact_kernel, dim3(npts), dim3(EF_THREADS), 0, s, op, tri, pts, region, k, Z, E, H);
 }
 
 // Transpose of the E part: for weights wE (npts x 3) the per-point

@@ -737,20 +737,66 @@ __device__ inline void dipole_fields(double k, double Z, const double *r0, const
   }
 }
 
+// complex quotient and principal square root (Re >= 0, cut on the negative axis)
+__device__ inline cx<double> cdivd(cx<double> a, cx<double> b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den};
+}
+__device__ inline cx<double> csqrtd(cx<double> z) {
+  const double r = hypot(z.x, z.y);
+  const double re = sqrt(0.5 * (r + z.x)), im = sqrt(0.5 * fmax(r - z.x, 0.0));
+  return {re, z.y < 0 ? -im : im};
+}
+
+// Fields of a source (SourceDev) in the medium (k, Z): b = 0 the point
+// dipole above; b > 0 the same closed form continued to the complex source
+// position r0 - j b dir (a complex-source-point beam along +dir with its
+// waist at r0): complex distance R = sqrt(d.d), d = r - r0 + j b dir,
+// principal branch, complex unit vector u = d / R, all times exp(-k b) so
+// that the beam's on-axis amplitude stays of order one.
+__device__ inline void source_fields(const SourceDev &S, double k, double Z, const double *r, cx<double> *E,
+                                     cx<double> *H) {
+  if (S.b == 0.0) {
+    dipole_fields(k, Z, S.r0, S.p, r, E, H);
+    return;
+  }
+  const cx<double> d[3] = {{r[0] - S.r0[0], S.bd[0]}, {r[1] - S.r0[1], S.bd[1]}, {r[2] - S.r0[2], S.bd[2]}};
+  const cx<double> R = csqrtd(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const cx<double> u[3] = {cdivd(d[0], R), cdivd(d[1], R), cdivd(d[2], R)};
+  // exp(-jkR - kb)
+  const double mag = exp(k * R.y - k * S.b);
+  double sn, cs;
+  sincos(-k * R.x, &sn, &cs);
+  const cx<double> ph = {mag * cs, mag * sn};
+  const double c4 = 1.0 / (4.0 * PI);
+  const cx<double> kR = R * k, R2 = R * R, R3 = R2 * R;
+  const cx<double> G = cdivd(ph * c4, R);
+  const cx<double> G1 = cdivd((cx<double>{1.0, 0.0} + mul_j(kR)) * ph, R2) * (-c4);
+  const cx<double> G2 = cdivd((cx<double>{2.0, 0.0} + mul_j(kR) * 2.0 - kR * kR) * ph, R3) * c4;
+  const cx<double> up = u[0] * S.p[0] + u[1] * S.p[1] + u[2] * S.p[2];
+  H[0] = G1 * (u[1] * S.p[2] - u[2] * S.p[1]);
+  H[1] = G1 * (u[2] * S.p[0] - u[0] * S.p[2]);
+  H[2] = G1 * (u[0] * S.p[1] - u[1] * S.p[0]);
+  const cx<double> G1R = cdivd(G1, R);
+  for (int a = 0; a < 3; a++) {
+    const cx<double> hp = G2 * up * u[a] + G1R * (S.p[a] - up * u[a]);
+    const cx<double> t = S.p[a] * G + hp * (1.0 / (k * k));
+    E[a] = mul_j(t) * (-k * Z);
+  }
+}
+
 __global__ void rhs_dipole_kernel(int nt, const int *__restrict__ body, const TriRec<double> *__restrict__ tris,
                                   const PointRec<double> *__restrict__ pts, const double *__restrict__ qp,
-                                  const EdgeRec *__restrict__ edges, double k, double Z, double px, double py,
-                                  double pz, cx<double> m0, cx<double> m1, cx<double> m2, int bodyid, double *b) {
+                                  const EdgeRec *__restrict__ edges, double k, double Z, SourceDev S, int bodyid,
+                                  double *b) {
   int T = blockIdx.x * blockDim.x + threadIdx.x;
   if (T >= nt || body[T] != bodyid) return;
-  const double r0[3] = {px, py, pz};
-  const cx<double> p[3] = {m0, m1, m2};
   cx<double> acc[3][3];
   for (int i = 0; i < 3; i++) acc[i][0] = acc[i][1] = acc[i][2] = czero<double>();
   for (int q = 0; q < NQ; q++) {
     const PointRec<double> &P = pts[T * NQ + q];
     cx<double> E[3], H[3];
-    dipole_fields(k, Z, r0, p, qp + 3 * ((size_t)T * NQ + q), E, H);
+    source_fields(S, k, Z, qp + 3 * ((size_t)T * NQ + q), E, H);
     for (int i = 0; i < 3; i++) {
       const double *gi = P.f + 3 * i;
       cx<double> ge = rdot(gi, E), gh = rdot(gi, H);
@@ -770,60 +816,47 @@ __global__ void rhs_dipole_kernel(int nt, const int *__restrict__ body, const Tr
   }
 }
 
-// incident field of the dipole at every quadrature point of its body (zero on
+// incident field of the source at every quadrature point of its body (zero on
 // the other bodies)
 __global__ void incident_points_kernel(int np, const int *__restrict__ body, const PointRec<double> *__restrict__ pts,
-                                       const double *__restrict__ qp, double k, double Z, double px, double py,
-                                       double pz, cx<double> m0, cx<double> m1, cx<double> m2, int bodyid,
+                                       const double *__restrict__ qp, double k, double Z, SourceDev S, int bodyid,
                                        cx<double> *__restrict__ E) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
   cx<double> e[3] = {{0, 0}, {0, 0}, {0, 0}}, h[3];
-  if (body[pts[p].tri] == bodyid) {
-    const double r0[3] = {px, py, pz};
-    const cx<double> mo[3] = {m0, m1, m2};
-    dipole_fields(k, Z, r0, mo, qp + 3 * (size_t)p, e, h);
-  }
+  if (body[pts[p].tri] == bodyid) source_fields(S, k, Z, qp + 3 * (size_t)p, e, h);
   for (int a = 0; a < 3; a++) E[3 * (size_t)p + a] = e[a];
 }
 
 void launch_incident_points(int np, const int *body, const PointRec<double> *pts, const double *qp, double k, double Z,
-                            const double *pos, const double *mom, int bodyid, cx<double> *E, hipStream_t s) {
-  hipLaunchKernelGGL(incident_points_kernel, dim3((np + 255) / 256), dim3(256), 0, s, np, body, pts, qp, k, Z, pos[0],
-                     pos[1], pos[2], cx<double>{mom[0], mom[1]}, cx<double>{mom[2], mom[3]},
-                     cx<double>{mom[4], mom[5]}, bodyid, E);
+                            const SourceDev &S, int bodyid, cx<double> *E, hipStream_t s) {
+  hipLaunchKernelGGL(incident_points_kernel, dim3((np + 255) / 256), dim3(256), 0, s, np, body, pts, qp, k, Z, S,
+                     bodyid, E);
 }
 
-// the dipole's fields (interior medium) at arbitrary points, 3 complex per point
-__global__ void dipole_points_kernel(int npts, const double *__restrict__ pts, double k, double Z, double px, double py,
-                                     double pz, cx<double> m0, cx<double> m1, cx<double> m2, cx<double> *__restrict__ E,
-                                     cx<double> *__restrict__ H) {
+// the source's fields (interior medium) at arbitrary points, 3 complex per point
+__global__ void dipole_points_kernel(int npts, const double *__restrict__ pts, double k, double Z, SourceDev S,
+                                     cx<double> *__restrict__ E, cx<double> *__restrict__ H) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npts) return;
-  const double r0[3] = {px, py, pz};
-  const cx<double> mo[3] = {m0, m1, m2};
   cx<double> e[3], h[3];
-  dipole_fields(k, Z, r0, mo, pts + 3 * (size_t)p, e, h);
+  source_fields(S, k, Z, pts + 3 * (size_t)p, e, h);
   for (int a = 0; a < 3; a++) {
     E[3 * (size_t)p + a] = e[a];
     H[3 * (size_t)p + a] = h[a];
   }
 }
 
-void launch_dipole_points(int npts, const double *pts, double k, double Z, const double *pos, const double *mom,
-                          cx<double> *E, cx<double> *H, hipStream_t s) {
-  hipLaunchKernelGGL(dipole_points_kernel, dim3((npts + 255) / 256), dim3(256), 0, s, npts, pts, k, Z, pos[0], pos[1],
-                     pos[2], cx<double>{mom[0], mom[1]}, cx<double>{mom[2], mom[3]}, cx<double>{mom[4], mom[5]}, E, H);
+void launch_dipole_points(int npts, const double *pts, double k, double Z, const SourceDev &S, cx<double> *E,
+                          cx<double> *H, hipStream_t s) {
+  hipLaunchKernelGGL(dipole_points_kernel, dim3((npts + 255) / 256), dim3(256), 0, s, npts, pts, k, Z, S, E, H);
 }
 
-void launch_rhs_dipole(int nt, const double *qp, const double *qw, const double *sigma, const int *body,
-                       const TriRec<double> *tris, const PointRec<double> *pts, const EdgeRec *edges, double k, double Z,
-                       const double *pos, const double *mom, int bodyid, double *b, hipStream_t s) {
-  (void)qw;
-  (void)sigma;
+void launch_rhs_dipole(int nt, const double *qp, const int *body, const TriRec<double> *tris,
+                       const PointRec<double> *pts, const EdgeRec *edges, double k, double Z, const SourceDev &S,
+                       int bodyid, double *b, hipStream_t s) {
   hipLaunchKernelGGL(rhs_dipole_kernel, dim3((nt + 127) / 128), dim3(128), 0, s, nt, body, tris, pts, qp, edges, k, Z,
-                     pos[0], pos[1], pos[2], cx<double>{mom[0], mom[1]}, cx<double>{mom[2], mom[3]},
-                     cx<double>{mom[4], mom[5]}, bodyid, b);
+                     S, bodyid, b);
 }
 
 }  // namespace scabs

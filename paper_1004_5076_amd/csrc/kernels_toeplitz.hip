@@ -23,79 +23,6 @@ namespace scabs {
 // ---------------------------------------------------------------------------
 // exact inner integrals and tested values (FP64)
 // ---------------------------------------------------------------------------
-__device__ inline D3 tri_vertex(const TriD *A, int k, double sx) {
-  return {A->v[3 * k] + sx, A->v[3 * k + 1], A->v[3 * k + 2]};
-}
-__device__ inline D3 tri_point(const TriD *A, int q, double sx) {
-  return {A->qp[3 * q] + sx, A->qp[3 * q + 1], A->qp[3 * q + 2]};
-}
-__device__ inline bool singular_pair(const TriD *A, double sa, const TriD *B, double sb, double kappa) {
-  const double dx = A->cen[0] + sa - B->cen[0] - sb, dy = A->cen[1] - B->cen[1], dz = A->cen[2] - B->cen[2];
-  const double thr = kappa * (A->rho + B->rho);
-  return dx * dx + dy * dy + dz * dz < thr * thr;
-}
-
-struct StaticJ {
-  double J0;
-  D3 J1, Jg;
-};
-
-// half function j of the source triangle B (shifted by sb along x), at r, in
-// medium k: a = int G f_j, phi = int G div f_j, gphi = int grad G div f_j,
-// c = int grad G x f_j.  Singular pairs: static part from st (analytic), 7-point
-// rule on the smooth remainder; otherwise the plain rule on G.
-struct InnerJ {
-  Z3 a, gphi, c;
-  cx<double> phi;
-};
-__device__ void inner_j(D3 r, const TriD *B, double sb, int j, bool sing, const StaticJ &st, double k, InnerJ &o) {
-  cx<double> S0 = {0, 0};
-  Z3 S1 = {{0, 0}, {0, 0}, {0, 0}}, Sg = S1, Sc = S1;
-  const D3 vj = tri_vertex(B, j, sb);
-  for (int s = 0; s < NQ; s++) {
-    const D3 sp = tri_point(B, s, sb);
-    const double w = B->qw[s];
-    const D3 dv = r - sp;
-    const double R = sqrt(dotd(dv, dv));
-    cx<double> G = {0, 0}, dG = {0, 0};
-    if (R > 0 || sing) kernel_val(k, R, sing, G, dG);
-    Z3 gr = {{0, 0}, {0, 0}, {0, 0}};
-    if (R > 1e-14) gr = zscale(dG * (1.0 / R), dv);
-    S0 += G * w;
-    S1 = zadd(S1, zscale(G * w, sp - r));
-    const Z3 grw = {gr.x * w, gr.y * w, gr.z * w};
-    Sg = zadd(Sg, grw);
-    Sc = zadd(Sc, zcross(grw, sp - vj));
-  }
-  if (sing) {
-    const double c4 = 1.0 / (4.0 * PI);
-    S0.x += c4 * st.J0;
-    S1.x.x += c4 * st.J1.x;
-    S1.y.x += c4 * st.J1.y;
-    S1.z.x += c4 * st.J1.z;
-    Sg.x.x += c4 * st.Jg.x;
-    Sg.y.x += c4 * st.Jg.y;
-    Sg.z.x += c4 * st.Jg.z;
-    const D3 cr = crossd(st.Jg, r - vj);
-    Sc.x.x += c4 * cr.x;
-    Sc.y.x += c4 * cr.y;
-    Sc.z.x += c4 * cr.z;
-  }
-  const double cf = B->coef[j], dv = 2.0 * cf;
-  const D3 rv = r - vj;
-  const Z3 a = zadd(S1, zscale(S0, rv));
-  o.a = {a.x * cf, a.y * cf, a.z * cf};
-  o.phi = S0 * dv;
-  o.gphi = {Sg.x * dv, Sg.y * dv, Sg.z * dv};
-  o.c = {Sc.x * cf, Sc.y * cf, Sc.z * cf};
-}
-
-__device__ inline StaticJ static_of(D3 r, const TriD *B, double sb) {
-  StaticJ st;
-  tri_potentials(r, tri_vertex(B, 0, sb), tri_vertex(B, 1, sb), tri_vertex(B, 2, sb), st.J0, st.J1, st.Jg);
-  return st;
-}
-
 // Tested interactions of half function i of target triangle A (shift sa)
 // with half function j of source triangle B (shift sb):
 //   out[0..3] = L_e, K_e, L_i, K_i  (Galerkin; L tested by parts)

@@ -141,6 +141,23 @@ std::string build_geometry(const std::vector<double> &v, const std::vector<int> 
 }
 
 // sigma = sum of sigma0 * u(s) over absorbers (eq60), s = dir (x - x0) / L
+// conductivity of one profile end (not a raw end) at coordinate xa along its
+// axis: sigma0 s^d or the hat interpolant of the control values, s =
+// dir (xa - x0) / L, zero for s < 0 and held at s = 1 beyond the end
+static double profile_value(const SigmaEnd &e, double xa) {
+  double s = e.dir * (xa - e.x0) / e.length;
+  if (s < 0) return 0.0;
+  s = std::min(s, 1.0);
+  if (e.ctrl.empty()) return e.sigma0 * (e.degree == 0 ? 1.0 : std::pow(s, e.degree));
+  int n = (int)e.ctrl.size();
+  double step = 1.0 / (n - 1), acc = 0;
+  for (int k = 0; k < n; k++) {
+    double a = std::fabs(s - (double)k / (n - 1)) / step;
+    if (a < 1) acc += e.ctrl[k] * (1 - a);
+  }
+  return acc;
+}
+
 void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vector<double> &sigma) {
   size_t np = (size_t)g.nt * NQ;
   sigma.assign(np, 0.0);
@@ -149,23 +166,30 @@ void eval_sigma(const Geometry &g, const std::vector<SigmaEnd> &ends, std::vecto
       for (size_t i = 0; i < np; i++) sigma[i] += e.pts[i];
       continue;
     }
-    for (size_t i = 0; i < np; i++) {
-      double s = e.dir * (g.qp[3 * i + e.axis] - e.x0) / e.length;
-      if (s < 0) continue;
-      s = std::min(s, 1.0);
-      if (e.ctrl.empty()) {
-        sigma[i] += e.sigma0 * (e.degree == 0 ? 1.0 : std::pow(s, e.degree));
-      } else {
-        int n = (int)e.ctrl.size();
-        double step = 1.0 / (n - 1), acc = 0;
-        for (int k = 0; k < n; k++) {
-          double a = std::fabs(s - (double)k / (n - 1)) / step;
-          if (a < 1) acc += e.ctrl[k] * (1 - a);
-        }
-        sigma[i] += acc;
+    for (size_t i = 0; i < np; i++) sigma[i] += profile_value(e, g.qp[3 * i + e.axis]);
+  }
+}
+
+double sigma_at(const Geometry &g, const std::vector<SigmaEnd> &ends, const double *r, int T) {
+  double acc = 0.0;
+  for (const SigmaEnd &e : ends) {
+    if (e.pts.empty()) {
+      acc += profile_value(e, r[e.axis]);
+      continue;
+    }
+    int best = 0;
+    double bd = 1e300;
+    for (int q = 0; q < NQ; q++) {
+      const double *p = g.qp.data() + 3 * ((size_t)T * NQ + q);
+      const double d = (p[0] - r[0]) * (p[0] - r[0]) + (p[1] - r[1]) * (p[1] - r[1]) + (p[2] - r[2]) * (p[2] - r[2]);
+      if (d < bd) {
+        bd = d;
+        best = q;
       }
     }
+    acc += e.pts[(size_t)T * NQ + best];
   }
+  return acc;
 }
 
 // d sigma_q / d p per quadrature point (CSR over points): parameters are, end

@@ -207,6 +207,17 @@ class Dipole:
     body: int = 0
 
 
+@dataclass
+class Beam:
+    """Gaussian-beam source (Sec. II): a dipole of moment `moment` at the
+    complex position pos - j b direction; waist at pos, Rayleigh distance b."""
+    pos: np.ndarray
+    moment: np.ndarray
+    body: int = 0
+    direction: tuple = (1.0, 0.0, 0.0)
+    b: float = 1.0
+
+
 def seeded_dipole(seed: int, base=(0.5, 0.0, 0.0), jitter=(0.05, 0.02, 0.02), body: int = 0) -> Dipole:
     rng = SplitMix64(seed)
     pos = np.array([base[i] + rng.uniform_range(-jitter[i], jitter[i]) for i in range(3)])
