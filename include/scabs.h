@@ -191,6 +191,19 @@ int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, i
 int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                           int mode, scabs_solve_info *info);
 
+/* Several contexts' systems at once (batching across operators of uneven N:
+ * absorber lengths, wavelengths, geometries).  Context i solves nrhs[i]
+ * systems b[i] -> x[i] (device, its own N) as scabs_solve with the shared
+ * tol, max_iter, restart and mode; info[i] (NULL, or info itself NULL) gets
+ * nrhs[i] records.  The contexts run concurrently, each on its own stream
+ * driven by its own host thread, so their launches interleave on the GPU;
+ * results equal those of scabs_solve per context.  The contexts must be
+ * distinct (SCABS_E_ARG otherwise) and not used elsewhere during the call.
+ * Returns SCABS_OK, else an error of some context (preferred over
+ * SCABS_E_NOCONV); per-context messages via scabs_last_error. */
+int scabs_solve_batched(scabs_ctx *const *ctxs, int nctx, const double *const *b, double *const *x, const int *nrhs,
+                        double tol, int max_iter, int restart, int mode, scabs_solve_info *const *info);
+
 /* The right preconditioner of the solves on its own: y = M x (transpose = 0)
  * or y = M^T x (transpose = 1), M the restricted additive Schwarz operator
  * (the stored core rows of each cluster's inverted exact near-field block,

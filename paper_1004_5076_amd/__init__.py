@@ -30,7 +30,7 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy", "scabs_eval_field_exact", "scabs_rhs_source",
             "scabs_incident_source_points", "scabs_source_field", "scabs_swr", "scabs_standing_wave_fit",
-            "scabs_decay_fit", "scabs_poynting_decay"]
+            "scabs_decay_fit", "scabs_poynting_decay", "scabs_solve_batched"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
           "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32", "toeapply32", "toeapply64",
           "toeproduct32", "toeproduct64"]
@@ -145,6 +145,8 @@ def load() -> C.CDLL:
     L.scabs_standing_wave_fit.argtypes = [dp, dp, C.c_int, C.c_double, C.c_double, dp]
     L.scabs_decay_fit.argtypes = [dp, dp, C.c_int, dp]
     L.scabs_poynting_decay.argtypes = [P, P, C.POINTER(Source), C.c_int, C.c_double, dp, dp, C.c_int, dp]
+    L.scabs_solve_batched.argtypes = [C.POINTER(P), C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_int),
+                                      C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(C.POINTER(SolveInfo))]
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
     _lib = L
@@ -467,6 +469,34 @@ class Context:
             self._check(rc)
         out = [infos[k].as_dict() for k in range(nrhs)]
         return x, (out[0] if b.dim() == 1 else out)
+
+
+def solve_batched(ctxs: Sequence["Context"], bs, tol: float = 1e-6, max_iter: int = 2000, restart: int = 60,
+                  mode: int = SCABS_MIXED, raise_on_noconv: bool = False):
+    """scabs_solve_batched: context i solves the systems bs[i] (one vector or
+    a stack); the contexts run concurrently.  Returns ([x_i], [infos_i])."""
+    import torch
+    n = len(ctxs)
+    if n != len(bs) or n == 0:
+        raise ValueError("one right-hand side block per context")
+    bs = [c._dev(b) for c, b in zip(ctxs, bs)]
+    xs = [torch.zeros_like(b) for b in bs]
+    nr = [1 if b.dim() == 1 else b.shape[0] for b in bs]
+    infos = [(SolveInfo * k)() for k in nr]
+    L = load()
+    cp = (C.c_void_p * n)(*[c._c for c in ctxs])
+    bp = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    ip = (C.POINTER(SolveInfo) * n)(*[C.cast(i, C.POINTER(SolveInfo)) for i in infos])
+    rc = L.scabs_solve_batched(cp, n, bp, xp, (C.c_int * n)(*nr), tol, max_iter, restart, mode, ip)
+    if rc != SCABS_OK and (rc != SCABS_E_NOCONV or raise_on_noconv):
+        for c in ctxs:
+            msg = L.scabs_last_error(c._c).decode()
+            if msg:
+                raise ScabsError(rc, msg)
+        raise ScabsError(rc, "scabs_solve_batched")
+    out = [[inf[k].as_dict() for k in range(m)] for inf, m in zip(infos, nr)]
+    return xs, out
 
 
 def context_for(workload, device: int = 0, kappa_s: float = 1.37, h: Optional[float] = None,

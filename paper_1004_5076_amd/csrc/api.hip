@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -2053,6 +2054,36 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
 int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                           int mode, scabs_solve_info *info) {
   return do_solve(c, b, x, nrhs, tol, max_iter, restart, mode, info, true);
+}
+
+int scabs_solve_batched(scabs_ctx *const *ctxs, int nctx, const double *const *b, double *const *x, const int *nrhs,
+                        double tol, int max_iter, int restart, int mode, scabs_solve_info *const *info) {
+  if (!ctxs || nctx < 1 || !b || !x || !nrhs) return SCABS_E_ARG;
+  for (int i = 0; i < nctx; i++) {
+    if (!ctxs[i] || !b[i] || !x[i] || nrhs[i] < 1) return SCABS_E_ARG;
+    for (int j = 0; j < i; j++)
+      if (ctxs[j] == ctxs[i]) return fail(ctxs[i], SCABS_E_ARG, "a context appears twice in scabs_solve_batched");
+    if (!ctxs[i]->built) return fail(ctxs[i], SCABS_E_STATE, "scabs_build has not succeeded");
+  }
+  // every context's restarted GMRES on its own stream, driven by its own
+  // host thread: the systems' launches interleave on the GPU while each
+  // host thread waits on its own Arnoldi read-backs
+  std::vector<int> st(nctx, SCABS_OK);
+  std::vector<std::thread> th;
+  th.reserve(nctx);
+  for (int i = 0; i < nctx; i++)
+    th.emplace_back([&, i] {
+      if (hipSetDevice(ctxs[i]->opts.device) != hipSuccess) {
+        st[i] = fail(ctxs[i], SCABS_E_HIP, "hipSetDevice failed");
+        return;
+      }
+      st[i] = do_solve(ctxs[i], b[i], x[i], nrhs[i], tol, max_iter, restart, mode, info ? info[i] : nullptr, false);
+    });
+  for (auto &t : th) t.join();
+  int worst = SCABS_OK;
+  for (int i = 0; i < nctx; i++)
+    if (st[i] != SCABS_OK && (worst == SCABS_OK || worst == SCABS_E_NOCONV)) worst = st[i];
+  return worst;
 }
 
 int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double moment[6], int body, double *E) {
