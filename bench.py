@@ -225,6 +225,14 @@ def main():
     setup_s = time.perf_counter() - t0
     info = ctx.info()
     log("setup", f"{setup_s:.2f}s", info)
+    # the library's autotuner picks the product's launch choices on this
+    # context (part of the setup, outside the timed region)
+    t1 = time.perf_counter()
+    tune = ctx.autotune(reps=3)
+    tune_s = time.perf_counter() - t1
+    tune_chosen = {str(r["nrhs"]): {k: r[k] for k in ("apply_form", "groups", "lines", "us")}
+                   for r in tune if r["chosen"]}
+    log("autotune", f"{tune_s:.2f}s", tune_chosen)
     N = ctx.N
     d0 = w.dipoles[0]
 
@@ -394,6 +402,7 @@ def main():
         "stage_avg_us": stage_avg_us,
         "stage_total_ms": stage_total_ms,
         "roofline": roofline(prof, top),
+        "autotune": {"seconds": tune_s, "chosen": tune_chosen, "candidates": len(tune)},
         "rooflines": roofs,
         "product_roofline": product_roofline(full),
         "rooflines_source": ("the timed steps (roofline kernels only)" if args.no_breakdown

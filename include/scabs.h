@@ -191,6 +191,34 @@ int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, i
 int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                           int mode, scabs_solve_info *info);
 
+/* Autotuner of the block-Toeplitz product (contexts built with
+ * SCABS_PRODUCT_TOEPLITZ; SCABS_E_STATE otherwise).  Launch choices, kept
+ * per context separately for products of fewer than 8 vectors (class 0) and
+ * of 8 vectors (class 1): the apply form of the per-frequency block
+ * products (0: matrix cores for 8 FP32 vectors, vector ALUs otherwise; 1:
+ * vector ALUs), the number of column groups of the periodic rows' sparse
+ * part (1-16) and the ring-axis lines per transform work-group (0: the
+ * largest that fits 64 KiB of LDS).  Every choice computes the same product
+ * (only the order of sums over column groups changes).
+ * scabs_autotune times every candidate (forms {0, 1} for class 1, groups
+ * {4, 8, 16}, lines {4, largest}) on FP32 products of this context, reps
+ * products each after one warm-up, with HIP events on the context stream,
+ * and keeps the fastest per class; rec (max_rec entries, may be NULL when
+ * max_rec is 0) receives one record per candidate and *n_rec (may be NULL)
+ * their number.  scabs_set_tune sets one class's choices directly
+ * (SCABS_E_ARG for values out of range). */
+typedef struct {
+  int32_t nrhs;        /* 1 (class 0) or 8 (class 1) */
+  int32_t apply_form;
+  int32_t groups;
+  int32_t lines;
+  double us;           /* mean product time */
+  int32_t chosen;      /* 1 for the kept candidate of its class */
+  int32_t pad;
+} scabs_tune_record;
+int scabs_autotune(scabs_ctx *c, int reps, scabs_tune_record *rec, int max_rec, int *n_rec);
+int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines);
+
 /* Several contexts' systems at once (batching across operators of uneven N:
  * absorber lengths, wavelengths, geometries).  Context i solves nrhs[i]
  * systems b[i] -> x[i] (device, its own N) as scabs_solve with the shared

@@ -30,7 +30,7 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_sigma_gradient", "scabs_profile_begin", "scabs_profile_end", "scabs_profile_mask", "scabs_profile_bytes",
             "scabs_last_error", "scabs_destroy", "scabs_eval_field_exact", "scabs_rhs_source",
             "scabs_incident_source_points", "scabs_source_field", "scabs_swr", "scabs_standing_wave_fit",
-            "scabs_decay_fit", "scabs_poynting_decay", "scabs_solve_batched"]
+            "scabs_decay_fit", "scabs_poynting_decay", "scabs_solve_batched", "scabs_autotune", "scabs_set_tune"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
           "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32", "toeapply32", "toeapply64",
           "toeproduct32", "toeproduct64"]
@@ -83,6 +83,14 @@ class Source(C.Structure):
         s.b = float(b)
         s.body = int(body)
         return s
+
+
+class TuneRecord(C.Structure):
+    _fields_ = [("nrhs", C.c_int32), ("apply_form", C.c_int32), ("groups", C.c_int32), ("lines", C.c_int32),
+                ("us", C.c_double), ("chosen", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
 class SolveInfo(C.Structure):
@@ -147,6 +155,8 @@ def load() -> C.CDLL:
     L.scabs_poynting_decay.argtypes = [P, P, C.POINTER(Source), C.c_int, C.c_double, dp, dp, C.c_int, dp]
     L.scabs_solve_batched.argtypes = [C.POINTER(P), C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_int),
                                       C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(C.POINTER(SolveInfo))]
+    L.scabs_autotune.argtypes = [P, C.c_int, C.POINTER(TuneRecord), C.c_int, C.POINTER(C.c_int)]
+    L.scabs_set_tune.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
     _lib = L
@@ -347,6 +357,17 @@ class Context:
         self._check(self._L.scabs_source_field(self._c, C.byref(src), pp, p.shape[0], int(region),
                                                C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr())))
         return E, H
+
+    def autotune(self, reps: int = 3):
+        """Time the block-Toeplitz product's launch choices and keep the
+        fastest per class (fewer than 8 / 8 vectors); returns the records."""
+        recs = (TuneRecord * 64)()
+        n = C.c_int(0)
+        self._check(self._L.scabs_autotune(self._c, int(reps), recs, 64, C.byref(n)))
+        return [recs[i].as_dict() for i in range(min(n.value, 64))]
+
+    def set_tune(self, nrhs_class: int, form: int, groups: int, lines: int):
+        self._check(self._L.scabs_set_tune(self._c, int(nrhs_class), int(form), int(groups), int(lines)))
 
     def poynting_decay(self, x, src: Optional[Source], body: int, xpos: float, guide, box, nq: int = 8):
         """Decay rate from Poynting's theorem on the plane x = xpos; returns

@@ -210,6 +210,10 @@ struct scabs_ctx {
   cx<float> *toe_tri32 = nullptr;
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
   double toe_sparse_bytes[2] = {0, 0};  // stored non-periodic entries one product reads (FP64, FP32)
+  // launch choices of the product for fewer than 8 and for 8 vectors:
+  // {apply form (0 matrix cores at 8 FP32 vectors, 1 vector ALUs), column
+  // groups of the periodic rows, transform lines per work-group (0: largest)}
+  int toe_tune[2][3] = {{0, 8, 0}, {0, 8, 0}};
   int toe_ncap = 0;
   double *toe_part64 = nullptr, *toe_rpart64 = nullptr;
   float *toe_part32 = nullptr, *toe_rpart32 = nullptr;
@@ -696,6 +700,8 @@ static void toe_common(scabs_ctx *c, ToeDev<T> &d, const RingTemplate &rt, const
   d.P = rt.P;
   d.ne_r = rt.ne_r;
   d.nt_r = rt.nt_r;
+  d.lines = toe_max_lines(rt.P, sizeof(T) == sizeof(float));
+  d.apply_form = 0;
   d.Z_e = (T)c->Z_e;
   d.Z_i = (T)c->Z_i;
   d.ringmap = ringmap;
@@ -1288,6 +1294,13 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   R.S4L = S4 + 4 * (size_t)c->toe_nshort;
   R.part = toe_part(c, (T *)nullptr);
   R.rpart = toe_rpart(c, (T *)nullptr);
+  {
+    const int *tn = c->toe_tune[nb >= 8 ? 1 : 0];
+    const int lmax = toe_max_lines(d.P, f32);
+    d.apply_form = tn[0];
+    R.groups = std::max(1, std::min(tn[1], toe_row_groups()));
+    d.lines = tn[2] > 0 ? std::min(tn[2], lmax) : lmax;
+  }
   // algorithmic bytes: per-frequency tables, stored sparse entries, the
   // spectra (input 4 ne_r, output 2 ne_r + 4 NQ nt_r lines per vector)
   const double el = sizeof(cx<T>);
@@ -2054,6 +2067,81 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
 int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                           int mode, scabs_solve_info *info) {
   return do_solve(c, b, x, nrhs, tol, max_iter, restart, mode, info, true);
+}
+
+// launch choices of the block-Toeplitz product, checked against the kernels'
+// limits: form 0/1, groups 1..toe_row_groups(), lines 0 (largest) or
+// 1..toe_max_lines
+static int check_tune(scabs_ctx *c, int form, int groups, int lines) {
+  if (form != 0 && form != 1) return fail(c, SCABS_E_ARG, "apply form must be 0 or 1");
+  if (groups < 1 || groups > toe_row_groups()) return fail(c, SCABS_E_ARG, "column groups out of range");
+  if (lines < 0 || lines > toe_max_lines(c->rt.P, true)) return fail(c, SCABS_E_ARG, "transform lines out of range");
+  return SCABS_OK;
+}
+
+int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines) {
+  if (!c) return SCABS_E_ARG;
+  if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "needs a built block-Toeplitz context");
+  if (nrhs_class != 0 && nrhs_class != 1) return fail(c, SCABS_E_ARG, "nrhs_class must be 0 (< 8) or 1 (8)");
+  if (int st = check_tune(c, form, groups, lines)) return st;
+  c->toe_tune[nrhs_class][0] = form;
+  c->toe_tune[nrhs_class][1] = groups;
+  c->toe_tune[nrhs_class][2] = lines;
+  return SCABS_OK;
+}
+
+int scabs_autotune(scabs_ctx *c, int reps, scabs_tune_record *rec, int max_rec, int *n_rec) {
+  if (!c || reps < 1 || max_rec < 0 || (max_rec > 0 && !rec)) return SCABS_E_ARG;
+  if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "autotuning applies to a built block-Toeplitz context");
+  try {
+    const size_t stride = 2 * (size_t)c->lay.N;
+    DevMem tmp;
+    double *x = tmp.alloc<double>(stride * 8), *y = tmp.alloc<double>(stride * 8);
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * stride * 8, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int lmax = toe_max_lines(c->rt.P, true);
+    int nr = 0;
+    for (int cls = 0; cls < 2; cls++) {
+      const int nb = cls ? 8 : 1;
+      double best = 1e300;
+      int bestc[3] = {0, 8, 0}, first = nr;
+      std::vector<int> line_cands = {lmax};
+      if (lmax > 4) line_cands.insert(line_cands.begin(), 4);
+      for (int form = 0; form < (cls ? 2 : 1); form++)
+        for (int groups : {4, 8, 16})
+          for (int lines : line_cands) {
+            c->toe_tune[cls][0] = form;
+            c->toe_tune[cls][1] = groups;
+            c->toe_tune[cls][2] = lines;
+            matvec_n(c, x, y, nb, SCABS_FP32);   // warm
+            HIPCHK(hipEventRecord(e0, c->stream));
+            for (int r = 0; r < reps; r++) matvec_n(c, x, y, nb, SCABS_FP32);
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / reps;
+            if (nr < max_rec) rec[nr] = scabs_tune_record{nb, form, groups, lines, us, 0, 0};
+            nr++;
+            if (us < best) {
+              best = us;
+              bestc[0] = form;
+              bestc[1] = groups;
+              bestc[2] = lines;
+            }
+          }
+      for (int k = 0; k < 3; k++) c->toe_tune[cls][k] = bestc[k];
+      for (int i = first; i < std::min(nr, max_rec); i++)
+        rec[i].chosen = rec[i].apply_form == bestc[0] && rec[i].groups == bestc[1] && rec[i].lines == bestc[2];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_rec) *n_rec = nr;
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
 }
 
 int scabs_solve_batched(scabs_ctx *const *ctxs, int nctx, const double *const *b, double *const *x, const int *nrhs,

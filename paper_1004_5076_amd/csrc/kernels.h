@@ -271,6 +271,8 @@ template <typename T> struct ToeDev {
   cx<T> *X, *Y;                    // spectra of a product
   cx<T> *edge_out;                 // [v][e][2]
   cx<T> *pf;                       // [v][point row r < 2 R2][ring]: exterior rows r < R2, interior after
+  int lines;                       // ring-axis lines per transform work-group (<= toe_max_lines)
+  int apply_form;                  // 8 FP32 vectors: 0 matrix cores, 1 vector ALUs
 };
 // exact entries of the pairs with a non-periodic edge, column-major: short
 // part V4S/S4S[(j ne + n) 4 + t] (row n, non-periodic column capcol[j]),
@@ -284,10 +286,12 @@ template <typename T> struct ToeRows {
   const cx<T> *V4S, *S4S, *V4L, *S4L;
   T *part;                // [chunk][row][vector][6] partial sums of the long rows
   T *rpart;               // [group][vector][6][edge] partial sums of the periodic rows
+  int groups;             // column groups of the periodic rows (<= toe_row_groups())
 };
 template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb);
 int toe_long_chunk();
-int toe_row_groups();
+int toe_row_groups();   // the largest number of column groups
+int toe_max_lines(int P, bool fp32);   // the largest transform line group for circulant length P
 void launch_toe_setup(const ToeSetupArgs &s, hipStream_t st);
 void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st);
 void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s);

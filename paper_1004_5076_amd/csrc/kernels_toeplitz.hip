@@ -240,18 +240,20 @@ constexpr int TOE_GATHER = 8;   // global loads issued together per thread
 template <typename T> constexpr int toe_fft_waves() { return sizeof(T) == sizeof(float) ? 4 : 2; }
 constexpr int TOE_FFT_ELEMS = 16;
 // lines per work-group: at most 8, within the Stockham stage's elements per
-// thread and within 64 KiB of LDS (padded addressing)
+// thread and within 64 KiB of LDS (padded addressing); the product's
+// transforms take d.lines <= this (tuned)
 template <typename T> __host__ __device__ inline int toe_lines_per_group(int P) {
   int g = TOE_FFT_ELEMS * TOE_FFT_THREADS / P;
   if (g > 8) g = 8;
   while (g > 1 && (size_t)lpad_size<T>(g * P) * sizeof(cx<T>) > 65536) g--;
   return g < 1 ? 1 : g;
 }
-// LDS of a line group: the padded lines, then the P twiddles
-template <typename T> __host__ __device__ inline size_t toe_tw_offset(int P) {
-  return ((size_t)lpad_size<T>(toe_lines_per_group<T>(P) * P) * sizeof(cx<T>) + 15) / 16 * 16;
+int toe_max_lines(int P, bool fp32) { return fp32 ? toe_lines_per_group<float>(P) : toe_lines_per_group<double>(P); }
+// LDS of a group of G lines: the padded lines, then the P twiddles
+template <typename T> __host__ __device__ inline size_t toe_tw_offset(int P, int G) {
+  return ((size_t)lpad_size<T>(G * P) * sizeof(cx<T>) + 15) / 16 * 16;
 }
-template <typename T> size_t toe_fft_lds(int P) { return toe_tw_offset<T>(P) + (size_t)P * sizeof(cx<T>); }
+template <typename T> size_t toe_fft_lds(int P, int G) { return toe_tw_offset<T>(P, G) + (size_t)P * sizeof(cx<T>); }
 // dynamic LDS of a transform launch (attribute raised past 64 KiB)
 template <typename K> size_t toe_fft_launch_lds(K kernel, size_t lds) {
   if (lds > 65536)
@@ -260,8 +262,8 @@ template <typename K> size_t toe_fft_launch_lds(K kernel, size_t lds) {
 }
 // twiddles copied to LDS (read by every Stockham stage)
 template <typename T>
-__device__ inline const cx<T> *toe_stage_twiddles(unsigned char *smem, const cx<T> *tw, int P) {
-  cx<T> *t = reinterpret_cast<cx<T> *>(smem + toe_tw_offset<T>(P));
+__device__ inline const cx<T> *toe_stage_twiddles(unsigned char *smem, const cx<T> *tw, int P, int G) {
+  cx<T> *t = reinterpret_cast<cx<T> *>(smem + toe_tw_offset<T>(P, G));
   for (int i = threadIdx.x; i < P; i += blockDim.x) t[i] = tw[i];
   return t;
 }
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(TOE_FFT_THREADS) toe_series_fft_kernel(cx<doub
   const int G = toe_lines_per_group<double>(P);
   const int64_t l0 = (int64_t)blockIdx.x * G;
   const int nl = (int)(nlines - l0 < G ? nlines - l0 : G);
-  const cx<double> *tws = toe_stage_twiddles<double>(smem_raw, tw, P);
+  const cx<double> *tws = toe_stage_twiddles<double>(smem_raw, tw, P, G);
   for (int i = threadIdx.x; i < nl * P; i += blockDim.x) buf[lpad<double>(i)] = data[l0 * P + i];
   __syncthreads();
   lds_fft_mr<double, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, false);
@@ -287,7 +289,7 @@ void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<dou
   if (nlines == 0) return;
   const int G = toe_lines_per_group<double>(P);
   hipLaunchKernelGGL(toe_series_fft_kernel, dim3((unsigned)((nlines + G - 1) / G)), dim3(TOE_FFT_THREADS),
-                     toe_fft_launch_lds(toe_series_fft_kernel, toe_fft_lds<double>(P)), s, data, nlines, P, tw);
+                     toe_fft_launch_lds(toe_series_fft_kernel, toe_fft_lds<double>(P, G)), s, data, nlines, P, tw);
 }
 
 // series-major (FFT'd) -> per-frequency layouts of the block products, FP64
@@ -355,13 +357,13 @@ toe_fwd_kernel(ToeDev<T> d, const cx<T> *__restrict__ src,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   const int P = d.P, nr = d.nr;
-  const int G = toe_lines_per_group<T>(P);
+  const int G = d.lines;
   const int nlines = 4 * d.ne_r * nb;
   const int l0 = blockIdx.x * G;
   const int nl = min(G, nlines - l0);
   // gathers in batches of TOE_GATHER per thread, every load in bounds
   // (indices clamped, results masked) so that a batch's loads overlap
-  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P);
+  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P, G);
   const int n = nl * P;
   for (int i0 = threadIdx.x; i0 < n; i0 += TOE_GATHER * blockDim.x) {
     int rm[TOE_GATHER];
@@ -775,11 +777,11 @@ toe_inv_kernel(ToeDev<T> d, int ne, int np, int nb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
   const int P = d.P;
-  const int G = toe_lines_per_group<T>(P);
+  const int G = d.lines;
   const int nlines = (2 * d.ne_r + 4 * NQ * d.nt_r) * nb;
   const int l0 = blockIdx.x * G;
   const int nl = min(G, nlines - l0);
-  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P);
+  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P, G);
   const int n = nl * P;
   for (int i0 = threadIdx.x; i0 < n; i0 += TOE_GATHER * blockDim.x) {
     cx<T> y[TOE_GATHER];
@@ -939,9 +941,9 @@ __device__ inline void row_mac(const RowCoef<T> &c, const cx<T> *cm, cx<T> &e, c
   cmac(q, c.rM, M);
 }
 
-// periodic rows against the non-periodic columns, in TOE_RG column groups
+// periodic rows against the non-periodic columns, in R.groups column groups
 // (one thread per (row, group)): partial sums rpart[g][b][k][n]
-constexpr int TOE_RG = 8;
+constexpr int TOE_RG_MAX = 16;
 template <typename T, int NRB>
 __global__ void __launch_bounds__(256) toe_rows_part_kernel(DevOperator<T> op, ToeRows<T> R) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
@@ -952,7 +954,7 @@ __global__ void __launch_bounds__(256) toe_rows_part_kernel(DevOperator<T> op, T
   cx<T> e[NRB], h[NRB], q[NRB];
 #pragma unroll
   for (int b = 0; b < NRB; b++) e[b] = h[b] = q[b] = czero<T>();
-  const int j0 = (R.ncap * g) / TOE_RG, j1 = (R.ncap * (g + 1)) / TOE_RG;
+  const int j0 = (R.ncap * g) / R.groups, j1 = (R.ncap * (g + 1)) / R.groups;
   if (R.edge_sgn[n] != 0) {
     constexpr int DEP = 4;
     int j = j0;
@@ -1004,7 +1006,7 @@ __global__ void __launch_bounds__(256) toe_rows_kernel(DevOperator<T> op, ToeRow
   const EdgeRec r = op.edges[n];
   for (int b = 0; b < nb; b++) {
     double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int g = 0; g < TOE_RG; g++) {
+    for (int g = 0; g < R.groups; g++) {
       const T *p = R.rpart + ((size_t)(g * nb + b) * 6) * op.ne + n;
       for (int k = 0; k < 6; k++) v[k] += (double)p[(size_t)k * op.ne];
     }
@@ -1113,7 +1115,7 @@ template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRo
 #define SCABS_TOE_ROWS(NB)                                                                                           \
   do {                                                                                                               \
     if (R.nlong > 0) hipLaunchKernelGGL((toe_long_kernel<T, NB>), dim3(nchunk), dim3(256), 0, s, op, R);              \
-    hipLaunchKernelGGL((toe_rows_part_kernel<T, NB>), dim3((op.ne + 255) / 256, TOE_RG), dim3(256), 0, s, op, R);     \
+    hipLaunchKernelGGL((toe_rows_part_kernel<T, NB>), dim3((op.ne + 255) / 256, R.groups), dim3(256), 0, s, op, R);     \
   } while (0)
   switch (nb) {
     case 1: SCABS_TOE_ROWS(1); break;
@@ -1134,15 +1136,15 @@ template void launch_toe_rows<float>(const DevOperator<float> &, const ToeRows<f
 template void launch_toe_rows<double>(const DevOperator<double> &, const ToeRows<double> &, double *, hipStream_t,
                                       int);
 int toe_long_chunk() { return TOE_LCH; }
-int toe_row_groups() { return TOE_RG; }
+int toe_row_groups() { return TOE_RG_MAX; }
 
 template <typename T>
 void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb, int parts) {
-  const int G = toe_lines_per_group<T>(d.P);
+  const int G = d.lines;
   const int nin = 4 * d.ne_r * nb;
   if (parts & TOE_FWD)
     hipLaunchKernelGGL(toe_fwd_kernel<T>, dim3((nin + G - 1) / G), dim3(TOE_FFT_THREADS),
-                       toe_fft_launch_lds(toe_fwd_kernel<T>, toe_fft_lds<T>(d.P)), s, d, op.src, op.srcI, op.ne, nb);
+                       toe_fft_launch_lds(toe_fwd_kernel<T>, toe_fft_lds<T>(d.P, G)), s, d, op.src, op.srcI, op.ne, nb);
   if (!(parts & TOE_APPLY)) goto inverse;
   {
   const int R2 = 2 * NQ * d.nt_r;
@@ -1164,7 +1166,7 @@ void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_
     case 6: SCABS_TOE_APPLY(6); break;
     case 7: SCABS_TOE_APPLY(7); break;
     default:
-      if (sizeof(T) == sizeof(float)) {
+      if (sizeof(T) == sizeof(float) && d.apply_form == 0) {
         // eight vectors: the matrix-core form
         const int tiles = (d.ne_r + 15) / 16 + (R2 + 15) / 16;
         const size_t lds = sizeof(cx<float>) * 4 * d.ne_r * 8;
@@ -1185,7 +1187,7 @@ inverse:
     const int R2 = 2 * NQ * d.nt_r;
     const int nout = (2 * d.ne_r + 2 * R2) * nb;
     hipLaunchKernelGGL(toe_inv_kernel<T>, dim3((nout + G - 1) / G), dim3(TOE_FFT_THREADS),
-                       toe_fft_launch_lds(toe_inv_kernel<T>, toe_fft_lds<T>(d.P)), s, d, op.ne, op.np, nb);
+                       toe_fft_launch_lds(toe_inv_kernel<T>, toe_fft_lds<T>(d.P, G)), s, d, op.ne, op.np, nb);
     hipLaunchKernelGGL(toe_local_kernel<T>, dim3((op.nt + 255) / 256, nb), dim3(256), 0, s, op, d, nb);
   }
 }

@@ -137,3 +137,47 @@ def test_solve_matches_dense_lu(case, mode):
     err = _rel(x.cpu().numpy(), x_lu)
     print(name, "mode", mode, "solution vs dense LU", err, flush=True)
     assert err < 1e-8
+
+
+def test_every_launch_choice_is_exact(case):
+    """The tunable launch choices (apply form, column groups of the sparse
+    rows, transform lines per work-group) change only the order of sums:
+    every one keeps the products exact."""
+    import torch
+    name, w, o, A, ctx = case
+    X = np.stack([synth.random_complex(200 + k, o.N) for k in range(8)])
+    R1 = A @ X[0]
+    R8 = X @ A.T
+    for cls in (0, 1):
+        for form in ((0,) if cls == 0 else (0, 1)):
+            for groups in (1, 3, 16):
+                for lines in (1, 2, 0):
+                    ctx.set_tune(cls, form, groups, lines)
+                    if cls == 0:
+                        y = ctx.matvec(torch.from_numpy(X[0].copy()).cuda(), prec=0).cpu().numpy()
+                        assert _rel(y, R1) < 1e-11, (cls, form, groups, lines)
+                    else:
+                        Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=1).cpu().numpy()
+                        assert _rel(Y, R8) < 2e-6, (cls, form, groups, lines)
+    ctx.set_tune(0, 0, 8, 0)
+    ctx.set_tune(1, 0, 8, 0)
+    import paper_1004_5076_amd as pk
+    with pytest.raises(pk.ScabsError):
+        ctx.set_tune(1, 2, 8, 0)
+    with pytest.raises(pk.ScabsError):
+        ctx.set_tune(0, 0, 17, 0)
+
+
+def test_autotune_keeps_fastest(case):
+    import torch
+    name, w, o, A, ctx = case
+    recs = ctx.autotune(reps=2)
+    print(name, "autotune", recs, flush=True)
+    for nrhs in (1, 8):
+        rs = [r for r in recs if r["nrhs"] == nrhs]
+        assert len(rs) >= 3
+        chosen = [r for r in rs if r["chosen"]]
+        assert len(chosen) == 1 and chosen[0]["us"] == min(r["us"] for r in rs)
+    x = synth.random_complex(210, o.N)
+    y = ctx.matvec(torch.from_numpy(x).cuda(), prec=0).cpu().numpy()
+    assert _rel(y, A @ x) < 1e-11
