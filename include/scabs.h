@@ -58,7 +58,19 @@ typedef struct {
                       centroid-vertex distance; <= 0 selects 1.37 */
   int device;      /* HIP device ordinal */
   void *stream;    /* hipStream_t; NULL = a stream created by the library */
-  int precond;     /* 1: restricted additive Schwarz preconditioner on the exact
+  int precond;     /* 2 (SCABS_PRECOND_PAPER, block-Toeplitz contexts only): the
+                      preconditioners of the fast-solver appendix, the inverse
+                      of the circulant that embeds the block-Toeplitz A_LL
+                      (sigma-free periodic edges; applied by FFTs along the
+                      rings, per-frequency inverse symbols computed once in
+                      FP64 by Gauss-Jordan) and the block-diagonal inverse of
+                      A_RR (absorber unknowns grouped in boxes of side
+                      pc_cell, no overlap, exact near-field blocks as below);
+                      L unknowns of non-periodic edges are passed through.
+                      3 (SCABS_PRECOND_CIRC_SCHWARZ): the same circulant
+                      inverse on A_LL with the restricted additive Schwarz
+                      preconditioner below (with its overlap) on A_RR.
+                      1: restricted additive Schwarz preconditioner on the exact
                       near-field matrix (boxes of side pc_cell grown by
                       pc_overlap); 0: none.  Where a grown box would hold
                       more than 8192 unknowns (or its core more than 4096),
@@ -79,6 +91,10 @@ typedef struct {
                          the gradient use the lattice operator either way */
 } scabs_opts;
 
+#define SCABS_PRECOND_NONE 0
+#define SCABS_PRECOND_SCHWARZ 1
+#define SCABS_PRECOND_PAPER 2
+#define SCABS_PRECOND_CIRC_SCHWARZ 3
 #define SCABS_PRODUCT_PFFT 0
 #define SCABS_PRODUCT_TOEPLITZ 1
 

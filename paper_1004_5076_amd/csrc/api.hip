@@ -139,6 +139,11 @@ struct scabs_ctx {
   PrecState<double> p64;
   // preconditioner
   bool has_pc = false;
+  bool pc_schwarz = false;   // the Schwarz (or, paper mode, block-diagonal A_RR) part
+  int64_t pc_n_core = 0;     // unknowns in the cluster cores (N, or 3 N_R in paper mode)
+  bool pc_circ = false;      // the circulant A_LL part (paper mode)
+  cx<double> *pc_T64 = nullptr, *pc_cX64 = nullptr, *pc_cY64 = nullptr;
+  cx<float> *pc_T32 = nullptr, *pc_cX32 = nullptr, *pc_cY32 = nullptr;
   Clusters cl;
   int64_t nnzR = 0;
   int64_t *pc_ext_ptr = nullptr, *pc_core_ptr = nullptr, *pc_r_off = nullptr;
@@ -543,13 +548,18 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   hipStream_t s = c->stream;
   double cell = c->opts.pc_cell > 0 ? c->opts.pc_cell : 2.0 * c->opts.r_near;
   double ov = c->opts.pc_overlap >= 0 ? c->opts.pc_overlap : 1.5 * c->opts.r_near;
+  // paper mode: block diagonal on the absorber unknowns only (no overlap);
+  // the hybrid keeps the overlap (restricted additive Schwarz on A_RR)
+  const bool paper = c->opts.precond == SCABS_PRECOND_PAPER || c->opts.precond == SCABS_PRECOND_CIRC_SCHWARZ;
+  if (c->opts.precond == SCABS_PRECOND_PAPER) ov = 0.0;
+  const std::vector<int> *mask = paper ? &L.isR : nullptr;
   // boxes that would hold more unknowns than one work-group inverts shrink
   // the cell and overlap together until every cluster fits
   std::string e;
   bool too_large = false;
   for (int attempt = 0;; attempt++) {
     too_large = false;
-    e = build_clusters(g, L, cell, ov, c->cl, &too_large);
+    e = build_clusters(g, L, cell, ov, c->cl, &too_large, mask);
     if (!too_large || attempt == 30) break;
     cell *= 0.85;
     ov *= 0.85;
@@ -558,7 +568,9 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   if (too_large) throw std::string("preconditioner clusters above the largest invertible block remain");
   // the cores must partition the unknowns (the applies write every unknown
   // once and the transposed apply permutes x into core order)
-  if (c->cl.core_ptr[c->cl.nc] != L.N) throw std::string("preconditioner cores do not cover every unknown once");
+  const int64_t covered = paper ? 3 * (int64_t)L.NR : (int64_t)L.N;
+  if (c->cl.core_ptr[c->cl.nc] != covered)
+    throw std::string("preconditioner cores do not cover every unknown once");
   LocalTerms lt;
   build_local_terms(g, L, lt);
   const Clusters &cl = c->cl;
@@ -673,6 +685,38 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (st) throw std::string("a preconditioner block is singular");
+  c->pc_n_core = cl.core_ptr[cl.nc];
+  c->has_pc = true;
+  c->pc_schwarz = true;
+}
+
+// circulant part of the paper-mode preconditioner: the inverse symbol of
+// A_LL at every frequency of the block-Toeplitz product, both precisions
+static void build_circulant(scabs_ctx *c) {
+  const ToeDev<double> &d = c->t64;
+  const int n = 2 * d.ne_r;
+  if (n > pc_circ_max_order()) throw std::string("ring too large for the circulant preconditioner");
+  const size_t mat = (size_t)d.P * n * n;
+  DevMem tmp;
+  cx<double> *S = tmp.alloc<cx<double>>(mat), *B = tmp.alloc<cx<double>>(mat);
+  c->pc_T64 = c->mem.alloc<cx<double>>(mat);
+  c->pc_T32 = c->mem.alloc<cx<float>>(mat);
+  HIPCHK(hipMemsetAsync(S, 0, sizeof(cx<double>) * mat, c->stream));
+  launch_pc_circ_setup(d, S, B, c->pc_T64, c->pc_T32, c->stream);
+  HIPCHK(hipGetLastError());
+  const size_t spec = (size_t)d.P * n * 8;   // up to 8 vectors per apply
+  c->pc_cX64 = c->mem.alloc<cx<double>>(spec);
+  c->pc_cY64 = c->mem.alloc<cx<double>>(spec);
+  c->pc_cX32 = c->mem.alloc<cx<float>>(spec);
+  c->pc_cY32 = c->mem.alloc<cx<float>>(spec);
+  // a singular symbol leaves NaN in its inverse
+  std::vector<cx<double>> probe(std::min(mat, (size_t)4096));
+  HIPCHK(hipMemcpyAsync(probe.data(), c->pc_T64, sizeof(cx<double>) * probe.size(), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (const cx<double> &v : probe)
+    if (!std::isfinite(v.x) || !std::isfinite(v.y)) throw std::string("the circulant symbol of A_LL is singular");
+  c->pc_circ = true;
   c->has_pc = true;
 }
 
@@ -682,7 +726,7 @@ static void apply_precond(scabs_ctx *c, const cx<double> *x, cx<double> *y, bool
     launch_precond_apply(c->pc_n_items, c->pc_items, c->pc_ext_ptr, c->pc_ext_slot, c->pc_core_ptr, c->pc_core_slot,
                          c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, x, y, c->pc_max_ext, c->stream);
   else
-    launch_precond_apply_t<double>(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
+    launch_precond_apply_t<double>(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_n_core, c->pc_ext_ptr, c->pc_core_ptr, c->pc_core_slot,
                            c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr, c->pc_inv_pos, c->pc_tmp, c->pc_xc, x, y,
                            c->stream);
 }
@@ -943,6 +987,11 @@ template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *
 static int do_build(scabs_ctx *c) {
   c->built = false;
   c->has_pc = false;
+  c->pc_schwarz = false;
+  c->pc_circ = false;
+  if (c->opts.precond >= SCABS_PRECOND_PAPER && c->opts.product != SCABS_PRODUCT_TOEPLITZ)
+    return fail(c, SCABS_E_ARG, "the circulant preconditioner needs the block-Toeplitz product");
+  if (c->opts.precond < 0 || c->opts.precond > SCABS_PRECOND_CIRC_SCHWARZ) return fail(c, SCABS_E_ARG, "unknown precond");
   c->mem.release();
   c->work.release();
   c->work_restart = -1;
@@ -1119,7 +1168,7 @@ static int do_build(scabs_ctx *c) {
     uint8_t *cij = tmp.upload(c->near.cij);
     launch_near_assemble(c->nnz, cptr, cpair, cij, a.blocks, V4, S4, V4f, S4f, s);
     HIPCHK(hipGetLastError());
-    if (c->opts.precond) {
+    if (c->opts.precond && !(c->opts.precond >= SCABS_PRECOND_PAPER && c->lay.NR == 0)) {
       cx<double> *X8 = tmp.alloc<cx<double>>(8 * (size_t)c->nnz);
       launch_exact_assemble(c->nnz, cptr, cpair, cij, a.blocks_exact, X8, s);
       HIPCHK(hipGetLastError());
@@ -1145,6 +1194,7 @@ static int do_build(scabs_ctx *c) {
     e = build_toeplitz(c);
     if (!e.empty()) return fail(c, SCABS_E_MESH, e);
     c->toe = true;
+    if (c->opts.precond >= SCABS_PRECOND_PAPER) build_circulant(c);
   }
   c->built = true;
   return SCABS_OK;
@@ -1372,7 +1422,35 @@ static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec,
 // x: nb vectors of N, FP64, or FP32 (the inner solves' basis, read directly
 // by the gathers of the FP32 apply and of the transposed apply)
 template <typename TI>
+static void apply_schwarz_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb, bool trans, int prec);
+
+// paper mode, A_LL part: rows of the sigma-free periodic edges from the
+// inverse circulant (FP32 tables for the FP32 inner solves), the other L rows
+// copied; written after the block-diagonal part, which leaves them alone
+// (forward) or zero (transposed)
+template <typename TI>
+static void apply_circ_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb, bool trans, int prec) {
+  const int64_t N = c->lay.N;
+  StageTimer tm(c, trans ? SCABS_STAGE_PRECOND_T : SCABS_STAGE_PRECOND);
+  for (int b0 = 0; b0 < nb; b0 += 8) {
+    const int m = std::min(8, nb - b0);
+    if (prec == SCABS_FP32)
+      launch_pc_circ_apply<TI, float>(c->t32, c->edges, c->pc_T32, x + b0 * N, N, m, trans, c->pc_cX32, c->pc_cY32,
+                                      y + b0 * N, c->geo.ne, c->stream);
+    else
+      launch_pc_circ_apply<TI, double>(c->t64, c->edges, c->pc_T64, x + b0 * N, N, m, trans, c->pc_cX64,
+                                       c->pc_cY64, y + b0 * N, c->geo.ne, c->stream);
+  }
+}
+
+template <typename TI>
 static void apply_precond_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb, bool trans, int prec) {
+  if (c->pc_schwarz) apply_schwarz_n(c, x, y, nb, trans, prec);
+  if (c->pc_circ) apply_circ_n(c, x, y, nb, trans, prec);
+}
+
+template <typename TI>
+static void apply_schwarz_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb, bool trans, int prec) {
   const size_t N = (size_t)c->lay.N;
   if (!trans && prec == SCABS_FP32) {
     const int B = precond_apply32_max_batch();
@@ -1401,7 +1479,7 @@ static void apply_precond_n(scabs_ctx *c, const cx<TI> *x, cx<double> *y, int nb
     if (!trans) throw std::string("the FP64 Schwarz apply takes FP64 inputs");
     for (int k = 0; k < nb; k++) {
       StageTimer tm(c, SCABS_STAGE_PRECOND_T);
-      launch_precond_apply_t<TI>(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_ext_ptr, c->pc_core_ptr,
+      launch_precond_apply_t<TI>(c->pc_n_t_items, c->pc_t_items, c->lay.N, c->pc_n_core, c->pc_ext_ptr, c->pc_core_ptr,
                                  c->pc_core_slot, c->pc_r_off, PcStore{c->pc_Rt, c->pc_Rs}, c->pc_inv_ptr,
                                  c->pc_inv_pos, c->pc_tmp, c->pc_xc, x + k * N, y + k * N, c->stream);
     }
@@ -1910,13 +1988,13 @@ int scabs_info(const scabs_ctx *c, scabs_info_t *info) {
     info->grid_fft[a] = c->grids[0].N[a];
   }
   info->nnz_near_r = c->nnzR;
-  info->n_clusters = c->has_pc ? c->cl.nc : 0;
+  info->n_clusters = c->pc_schwarz ? c->cl.nc : 0;
   info->precond_entries = 0;
-  if (c->has_pc)
+  if (c->pc_schwarz)
     for (int k = 0; k < c->cl.nc; k++)
       info->precond_entries += (c->cl.ext_ptr[k + 1] - c->cl.ext_ptr[k]) * (c->cl.core_ptr[k + 1] - c->cl.core_ptr[k]);
   info->device_bytes = (int64_t)(c->mem.bytes + c->work.bytes);
-  info->precond_ext_entries = c->has_pc ? c->cl.ext_ptr[c->cl.nc] : 0;
+  info->precond_ext_entries = c->pc_schwarz ? c->cl.ext_ptr[c->cl.nc] : 0;
   info->product = c->toe ? SCABS_PRODUCT_TOEPLITZ : SCABS_PRODUCT_PFFT;
   if (c->toe) {
     info->rings = c->rt.nr;

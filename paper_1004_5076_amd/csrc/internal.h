@@ -118,7 +118,8 @@ constexpr int PC_MAX_CORE = 4096;
 // grown box holds more than PC_MAX_EXT unknowns or its core more than
 // PC_MAX_CORE.
 std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl,
-                           bool *too_large);
+                           bool *too_large,
+                           const std::vector<int> *mask = nullptr);
 void build_local_terms(const Geometry &g, const Layout &L, LocalTerms &lt);
 void edge_slots(const Layout &L, int e, int *slots, int *nslots);
 

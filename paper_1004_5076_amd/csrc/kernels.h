@@ -208,7 +208,7 @@ void launch_near_rows_t(const DevOperator<T> &op, const int64_t *tpos, double *y
 // dispatch order (work-group i runs entry i; cluster -1 marks an empty entry)
 int precond_t_cols_per_item();
 template <typename TI>   // double or float inputs x
-void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
+void launch_precond_apply_t(int n_items, const int *items, int64_t N, int64_t n_core, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, cx<double> *xc,
                             const cx<TI> *x, cx<double> *y, hipStream_t s);
@@ -292,6 +292,15 @@ template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRo
 int toe_long_chunk();
 int toe_row_groups();   // the largest number of column groups
 int toe_max_lines(int P, bool fp32);   // the largest transform line group for circulant length P
+// circulant preconditioner of A_LL: symbol S and its inverse B (workspaces of
+// P (2 ne_r)^2), inverse tables T64/T32[f][j][i]; apply to nb vectors x
+// (rows of L periodic edges written to y, non-periodic L rows copied)
+void launch_pc_circ_setup(const ToeDev<double> &d, cx<double> *S, cx<double> *B, cx<double> *T64, cx<float> *T32,
+                          hipStream_t s);
+int pc_circ_max_order();
+template <typename TI, typename T>
+void launch_pc_circ_apply(const ToeDev<T> &d, const EdgeRec *edges, const cx<T> *Tinv, const cx<TI> *x, int64_t N,
+                          int nb, bool trans, cx<T> *X, cx<T> *Y, cx<double> *y, int ne, hipStream_t s);
 void launch_toe_setup(const ToeSetupArgs &s, hipStream_t st);
 void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st);
 void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s);

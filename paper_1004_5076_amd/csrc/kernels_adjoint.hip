@@ -625,15 +625,18 @@ __global__ void precond_t_sum_kernel(int64_t N, const int64_t *__restrict__ inv_
   }
 }
 
-// xc: N entries of work space (x in core order)
+// xc: n_core entries of work space (x in core order; n_core = N when the
+// cores cover every unknown, fewer when the clusters cover a subset); y: all
+// N rows written (zero outside the cores)
 template <typename TI>
-void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int64_t *ext_ptr,
+void launch_precond_apply_t(int n_items, const int *items, int64_t N, int64_t n_core, const int64_t *ext_ptr,
                             const int64_t *core_ptr, const int *core_slot, const int64_t *r_off, PcStore pc,
                             const int64_t *inv_ptr, const int64_t *inv_pos, cx<double> *tmp, cx<double> *xc,
                             const cx<TI> *x, cx<double> *y, hipStream_t s) {
   if (N == 0) return;
-  hipLaunchKernelGGL(precond_t_gather_kernel<TI>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, core_slot, x,
-                     xc);
+  if (n_core > 0)
+    hipLaunchKernelGGL(precond_t_gather_kernel<TI>, dim3((unsigned)((n_core + 255) / 256)), dim3(256), 0, s, n_core,
+                       core_slot, x, xc);
   if (n_items > 0)
     hipLaunchKernelGGL(precond_t_dots_kernel, dim3(n_items), dim3(PT_THREADS), 0, s, items, ext_ptr, core_ptr, r_off,
                        pc, (const cx<double> *)xc, tmp);
@@ -641,7 +644,8 @@ void launch_precond_apply_t(int n_items, const int *items, int64_t N, const int6
                      y);
 }
 #define SCABS_APPLY_T(TI)                                                                                         \
-  template void launch_precond_apply_t<TI>(int, const int *, int64_t, const int64_t *, const int64_t *, const int *, \
+  template void launch_precond_apply_t<TI>(int, const int *, int64_t, int64_t, const int64_t *, const int64_t *,    \
+                                           const int *,                                                             \
                                            const int64_t *, PcStore, const int64_t *, const int64_t *, cx<double> *,  \
                                            cx<double> *, const cx<TI> *, cx<double> *, hipStream_t);
 SCABS_APPLY_T(double)

@@ -1196,4 +1196,276 @@ template void launch_toe_product<double>(const DevOperator<double> &, const ToeD
 
 size_t toe_apply_lds_bytes(int ne_r, int nb, size_t elem) { return elem * 4 * (size_t)ne_r * nb; }
 
+// ---------------------------------------------------------------------------
+// circulant preconditioner of the lossless guide block A_LL (fast-solver
+// appendix): on the unknowns J, M of the sigma-free periodic edges A_LL is
+// block Toeplitz over the rings with the blocks of the E and H rows
+//   E = -(Z_e L_e + Z_i L_i) J + (K_e + K_i) M
+//   H = -(K_e + K_i) J - (L_e / Z_e + L_i / Z_i) M        (J_i = -J, M_i = -M)
+// embedded in its circulant of length P (the product's); the inverse of the
+// circulant is the per-frequency inverse of the symbol.  Frequency vectors
+// are ordered (J_0, M_0, J_1, M_1, ...) over the template edges.
+// ---------------------------------------------------------------------------
+// symbol at frequency blockIdx.y, 2 ne_r square, row-major (rows E_a, H_a)
+__global__ void pc_circ_symbol_kernel(ToeDev<double> d, cx<double> *__restrict__ S) {
+  const int f = blockIdx.y, ne_r = d.ne_r, n = 2 * ne_r;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ne_r * ne_r) return;
+  const int b = (int)(idx / ne_r), a = (int)(idx % ne_r);
+  const cx<double> *ge = d.GE + ((size_t)f * ne_r * ne_r + (size_t)b * ne_r + a) * 2;
+  cx<double> Le = ge[0], Ke = ge[1], Li = {0, 0}, Ki = {0, 0};
+  const int bd = d.ebody[a];
+  if (d.ebody[b] == bd) {
+    const int e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
+    const cx<double> *gi = d.GI + ((size_t)f * d.gi_per_f + d.ibase[bd] + (size_t)(b - e0) * neb + (a - e0)) * 2;
+    Li = gi[0];
+    Ki = gi[1];
+  }
+  const double P = d.P, Ze = d.Z_e, Zi = d.Z_i;   // the tables hold the symbol / P
+  cx<double> *r0 = S + ((size_t)f * n + 2 * a) * n, *r1 = r0 + n;
+  r0[2 * b] = (Le * Ze + Li * Zi) * (-P);
+  r0[2 * b + 1] = (Ke + Ki) * P;
+  r1[2 * b] = (Ke + Ki) * (-P);
+  r1[2 * b + 1] = (Le * (1.0 / Ze) + Li * (1.0 / Zi)) * (-P);
+}
+
+// batched inverse by Gauss-Jordan elimination with partial pivoting (FP64):
+// A (n x n row-major, destroyed) -> B = A^-1, one work-group per matrix,
+// n <= PC_GJ_MAX; a zero pivot leaves B's matrix filled with NaN
+constexpr int PC_GJ_THREADS = 1024, PC_GJ_MAX = 1024;
+__global__ void __launch_bounds__(PC_GJ_THREADS) gj_inverse_kernel(cx<double> *A, cx<double> *B, int n) {
+  A += (size_t)blockIdx.x * n * n;
+  B += (size_t)blockIdx.x * n * n;
+  __shared__ double rv[PC_GJ_THREADS];
+  __shared__ int ri[PC_GJ_THREADS];
+  __shared__ cx<double> m[PC_GJ_MAX];
+  __shared__ cx<double> piv;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int i = t; i < n * n; i += nt) B[i] = (i / n == i % n) ? cx<double>{1.0, 0.0} : cx<double>{0.0, 0.0};
+  for (int k = 0; k < n; k++) {
+    __syncthreads();
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + t; i < n; i += nt) {
+      const cx<double> v = A[(size_t)i * n + k];
+      const double a = v.x * v.x + v.y * v.y;
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    rv[t] = best;
+    ri[t] = bi;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (t < w && (rv[t + w] > rv[t] || (rv[t + w] == rv[t] && ri[t + w] < ri[t]))) {
+        rv[t] = rv[t + w];
+        ri[t] = ri[t + w];
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    if (p != k)
+      for (int j = t; j < n; j += nt) {
+        const cx<double> a0 = A[(size_t)k * n + j], b0 = B[(size_t)k * n + j];
+        A[(size_t)k * n + j] = A[(size_t)p * n + j];
+        B[(size_t)k * n + j] = B[(size_t)p * n + j];
+        A[(size_t)p * n + j] = a0;
+        B[(size_t)p * n + j] = b0;
+      }
+    __syncthreads();
+    if (t == 0) {
+      const cx<double> v = A[(size_t)k * n + k];
+      const double den = v.x * v.x + v.y * v.y;
+      piv = den > 0 ? cx<double>{v.x / den, -v.y / den} : cx<double>{NAN, NAN};
+    }
+    __syncthreads();
+    for (int j = t; j < n; j += nt) {
+      A[(size_t)k * n + j] = A[(size_t)k * n + j] * piv;
+      B[(size_t)k * n + j] = B[(size_t)k * n + j] * piv;
+    }
+    for (int i = t; i < n; i += nt) m[i] = i == k ? cx<double>{0.0, 0.0} : A[(size_t)i * n + k];
+    __syncthreads();
+    for (int64_t q = t; q < (int64_t)n * 2 * n; q += nt) {
+      const int i = (int)(q / (2 * n)), j = (int)(q % (2 * n));
+      if (i == k) continue;
+      if (j < n)
+        A[(size_t)i * n + j] -= m[i] * A[(size_t)k * n + j];
+      else
+        B[(size_t)i * n + j - n] -= m[i] * B[(size_t)k * n + j - n];
+    }
+  }
+}
+
+// inverse tables Tinv[f][j][i] = (S(f)^-1)[i][j] / P in both precisions
+__global__ void pc_circ_store_kernel(const cx<double> *__restrict__ B, int n, int64_t total, double invP,
+                                     cx<double> *__restrict__ T64, cx<float> *__restrict__ T32) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = q / ((int64_t)n * n), r = q % ((int64_t)n * n);
+    const int j = (int)(r / n), i = (int)(r % n);
+    const cx<double> v = B[(size_t)f * n * n + (size_t)i * n + j] * invP;
+    T64[q] = v;
+    T32[q] = {(float)v.x, (float)v.y};
+  }
+}
+
+void launch_pc_circ_setup(const ToeDev<double> &d, cx<double> *S, cx<double> *B, cx<double> *T64, cx<float> *T32,
+                          hipStream_t s) {
+  const int n = 2 * d.ne_r;
+  const int64_t ab = (int64_t)d.ne_r * d.ne_r;
+  hipLaunchKernelGGL(pc_circ_symbol_kernel, dim3((unsigned)((ab + 255) / 256), d.P), dim3(256), 0, s, d, S);
+  hipLaunchKernelGGL(gj_inverse_kernel, dim3(d.P), dim3(PC_GJ_THREADS), 0, s, S, B, n);
+  const int64_t total = (int64_t)d.P * n * n;
+  hipLaunchKernelGGL(pc_circ_store_kernel, dim3(4096), dim3(256), 0, s, (const cx<double> *)B, n, total,
+                     1.0 / d.P, T64, T32);
+}
+int pc_circ_max_order() { return PC_GJ_MAX; }
+
+// forward: lines l = (2 a + s) nb + v (s = 0 J, 1 M of template edge a,
+// vector v): the L unknowns of the periodic edges at rings j < nr (template
+// orientation), zero for absorber edges and beyond; transformed; X[f][l]
+template <typename TI, typename T>
+__global__ void __launch_bounds__(TOE_FFT_THREADS) __attribute__((amdgpu_waves_per_eu(toe_fft_waves<T>())))
+pc_circ_fwd_kernel(ToeDev<T> d, const EdgeRec *__restrict__ edges, const cx<TI> *__restrict__ x, int64_t N, int nb,
+                   cx<T> *__restrict__ X) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int P = d.P, nr = d.nr, G = d.lines;
+  const int nlines = 2 * d.ne_r * nb;
+  const int l0 = blockIdx.x * G, nl = min(G, nlines - l0);
+  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P, G);
+  const int n = nl * P;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int li = i / P, j = i - li * P;
+    const int l = l0 + li, q = l / nb, v = l - q * nb, a = q >> 1, sl = q & 1;
+    cx<T> val = czero<T>();
+    if (j < nr) {
+      const int e = d.ringmap[(size_t)a * nr + j];
+      if (e >= 0) {
+        const EdgeRec r = edges[e];
+        if (!r.isR) {
+          const cx<TI> u = x[(size_t)v * N + r.col[sl]];
+          val = cx<T>{(T)u.x, (T)u.y} * (T)d.edge_sgn[e];
+        }
+      }
+    }
+    buf[lpad<T>(i)] = val;
+  }
+  __syncthreads();
+  if (wave_fits(P, nl, blockDim.x >> 6, TOE_FFT_ELEMS))
+    lds_fft<T, TOE_FFT_ELEMS, TOE_FFT_ELEMS, true>(buf, P, nl, 1, P, 0, 1, tws, P, false);
+  else
+    lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, false);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int f = i / nl, li = i - f * nl;
+    X[(size_t)f * nlines + l0 + li] = buf[lpad<T>(li * P + f)];
+  }
+}
+
+// per frequency: Y[f][i][v] = sum_j Tinv[f][j][i] X[f][j][v]; transposed:
+// the symbol's inverse at -f, transposed
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) pc_circ_apply_kernel(const cx<T> *__restrict__ Tinv, const cx<T> *__restrict__ X,
+                                                             cx<T> *__restrict__ Y, int n, int P, int trans) {
+  const int f = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int fs = trans ? (P - f) % P : f;
+  const cx<T> *Xf = X + (size_t)f * n * NB;
+  cx<T> acc[NB];
+#pragma unroll
+  for (int v = 0; v < NB; v++) acc[v] = czero<T>();
+  for (int j = 0; j < n; j++) {
+    const cx<T> c = trans ? Tinv[((size_t)fs * n + i) * n + j] : Tinv[((size_t)fs * n + j) * n + i];
+#pragma unroll
+    for (int v = 0; v < NB; v++) acc[v] += c * Xf[(size_t)j * NB + v];
+  }
+#pragma unroll
+  for (int v = 0; v < NB; v++) Y[((size_t)f * n + i) * NB + v] = acc[v];
+}
+
+// inverse transform of the lines; rings j < nr of L periodic edges written
+// to y (template orientation back to the edge's)
+template <typename T>
+__global__ void __launch_bounds__(TOE_FFT_THREADS) __attribute__((amdgpu_waves_per_eu(toe_fft_waves<T>())))
+pc_circ_inv_kernel(ToeDev<T> d, const EdgeRec *__restrict__ edges, const cx<T> *__restrict__ Y, int64_t N, int nb,
+                   cx<double> *__restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int P = d.P, nr = d.nr, G = d.lines;
+  const int nlines = 2 * d.ne_r * nb;
+  const int l0 = blockIdx.x * G, nl = min(G, nlines - l0);
+  const cx<T> *tws = toe_stage_twiddles<T>(smem_raw, d.tw, P, G);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int f = i / nl, li = i - f * nl;
+    buf[lpad<T>(li * P + f)] = Y[(size_t)f * nlines + l0 + li];
+  }
+  __syncthreads();
+  lds_fft_mr<T, TOE_FFT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, true);
+  for (int i = threadIdx.x; i < nl * nr; i += blockDim.x) {
+    const int li = i / nr, j = i - li * nr;
+    const int l = l0 + li, q = l / nb, v = l - q * nb, a = q >> 1, sl = q & 1;
+    const int e = d.ringmap[(size_t)a * nr + j];
+    if (e < 0) continue;
+    const EdgeRec r = edges[e];
+    if (r.isR) continue;
+    const cx<T> val = buf[lpad<T>(li * P + j)] * (T)d.edge_sgn[e];
+    y[(size_t)v * N + r.col[sl]] = {(double)val.x, (double)val.y};
+  }
+}
+
+// L unknowns of non-periodic edges pass through (no block of A_LL covers them)
+template <typename TI>
+__global__ void pc_identity_kernel(const EdgeRec *__restrict__ edges, const int *__restrict__ edge_sgn, int ne,
+                                   const cx<TI> *__restrict__ x, int64_t N, int nb, cx<double> *__restrict__ y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x, v = blockIdx.y;
+  if (e >= ne || v >= nb) return;
+  const EdgeRec r = edges[e];
+  if (r.isR || edge_sgn[e] != 0) return;
+  for (int s = 0; s < 2; s++) {
+    const cx<TI> u = x[(size_t)v * N + r.col[s]];
+    y[(size_t)v * N + r.col[s]] = {(double)u.x, (double)u.y};
+  }
+}
+
+template <typename TI, typename T>
+void launch_pc_circ_apply(const ToeDev<T> &d, const EdgeRec *edges, const cx<T> *Tinv, const cx<TI> *x, int64_t N,
+                          int nb, bool trans, cx<T> *X, cx<T> *Y, cx<double> *y, int ne, hipStream_t s) {
+  const int G = d.lines, n = 2 * d.ne_r;
+  const int nlines = n * nb;
+  hipLaunchKernelGGL((pc_circ_fwd_kernel<TI, T>), dim3((nlines + G - 1) / G), dim3(TOE_FFT_THREADS),
+                     toe_fft_launch_lds((pc_circ_fwd_kernel<TI, T>), toe_fft_lds<T>(d.P, G)), s, d, edges, x, N, nb,
+                     X);
+#define SCABS_PC_APPLY(NBV)                                                                                          \
+  hipLaunchKernelGGL((pc_circ_apply_kernel<T, NBV>), dim3((n + 255) / 256, d.P), dim3(256), 0, s, (const cx<T> *)Tinv, \
+                     (const cx<T> *)X, Y, n, d.P, trans ? 1 : 0)
+  switch (nb) {
+    case 1: SCABS_PC_APPLY(1); break;
+    case 2: SCABS_PC_APPLY(2); break;
+    case 3: SCABS_PC_APPLY(3); break;
+    case 4: SCABS_PC_APPLY(4); break;
+    case 5: SCABS_PC_APPLY(5); break;
+    case 6: SCABS_PC_APPLY(6); break;
+    case 7: SCABS_PC_APPLY(7); break;
+    default: SCABS_PC_APPLY(8); break;
+  }
+#undef SCABS_PC_APPLY
+  hipLaunchKernelGGL(pc_circ_inv_kernel<T>, dim3((nlines + G - 1) / G), dim3(TOE_FFT_THREADS),
+                     toe_fft_launch_lds(pc_circ_inv_kernel<T>, toe_fft_lds<T>(d.P, G)), s, d, edges,
+                     (const cx<T> *)Y, N, nb, y);
+  hipLaunchKernelGGL(pc_identity_kernel<TI>, dim3((ne + 255) / 256, nb), dim3(256), 0, s, edges, d.edge_sgn, ne, x,
+                     N, nb, y);
+}
+template void launch_pc_circ_apply<double, double>(const ToeDev<double> &, const EdgeRec *, const cx<double> *,
+                                                   const cx<double> *, int64_t, int, bool, cx<double> *, cx<double> *,
+                                                   cx<double> *, int, hipStream_t);
+template void launch_pc_circ_apply<float, float>(const ToeDev<float> &, const EdgeRec *, const cx<float> *,
+                                                 const cx<float> *, int64_t, int, bool, cx<float> *, cx<float> *,
+                                                 cx<double> *, int, hipStream_t);
+template void launch_pc_circ_apply<double, float>(const ToeDev<float> &, const EdgeRec *, const cx<float> *,
+                                                  const cx<double> *, int64_t, int, bool, cx<float> *, cx<float> *,
+                                                  cx<double> *, int, hipStream_t);
+template void launch_pc_circ_apply<float, double>(const ToeDev<double> &, const EdgeRec *, const cx<double> *,
+                                                  const cx<float> *, int64_t, int, bool, cx<double> *, cx<double> *,
+                                                  cx<double> *, int, hipStream_t);
+
 }  // namespace scabs

@@ -1,6 +1,7 @@
 // Host-side setup: RWG edges, quadrature points, surface conductivity,
 // unknown layout, lattice boxes and the near-pair structure.
 #include <algorithm>
+#include <limits>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -451,7 +452,7 @@ void edge_slots(const Layout &L, int e, int *slots, int *nslots) {
 }
 
 std::string build_clusters(const Geometry &g, const Layout &L, double cell, double overlap, Clusters &cl,
-                           bool *too_large) {
+                           bool *too_large, const std::vector<int> *mask) {
   *too_large = false;
   if (!(cell > 0) || overlap < 0 || overlap > cell) return "preconditioner cell must be > 0 and overlap in [0, cell]";
   const int ne = g.ne;
@@ -470,17 +471,19 @@ std::string build_clusters(const Geometry &g, const Layout &L, double cell, doub
       nc3[a] = std::max(nc3[a], key[e][a] + 1);
     }
   auto cid = [&](int x, int y, int z) { return ((int64_t)x * nc3[1] + y) * nc3[2] + z; };
+  // edges outside the mask take part in no cluster (sorted to the end)
   std::vector<int> order(ne);
   std::iota(order.begin(), order.end(), 0);
   std::vector<int64_t> k1(ne);
-  for (int e = 0; e < ne; e++) k1[e] = cid(key[e][0], key[e][1], key[e][2]);
+  const int64_t none = std::numeric_limits<int64_t>::max();
+  for (int e = 0; e < ne; e++) k1[e] = (mask && !(*mask)[e]) ? none : cid(key[e][0], key[e][1], key[e][2]);
   std::sort(order.begin(), order.end(), [&](int a, int b) { return k1[a] != k1[b] ? k1[a] < k1[b] : a < b; });
   std::vector<int64_t> sk(ne);
   for (int i = 0; i < ne; i++) sk[i] = k1[order[i]];
   // one cluster per non-empty cell
   std::vector<int64_t> cells;
   for (int i = 0; i < ne; i++)
-    if (i == 0 || sk[i] != sk[i - 1]) cells.push_back(sk[i]);
+    if (sk[i] != none && (i == 0 || sk[i] != sk[i - 1])) cells.push_back(sk[i]);
   cl = Clusters();
   cl.nc = (int)cells.size();
   std::vector<std::vector<int>> ext(cl.nc), core(cl.nc);
