@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscabs.so")
-SOURCES = ["setup.cpp", "toeplitz.cpp", "postproc.cpp", "kernels_fft.hip", "kernels_toeplitz.hip", "kernels_matvec.hip", "kernels_near.hip", "kernels_krylov.hip", "kernels_precond.hip", "kernels_adjoint.hip", "api.hip"]
+SOURCES = ["setup.cpp", "toeplitz.cpp", "postproc.cpp", "kernels_fft.hip", "kernels_toeplitz.hip", "kernels_toeplitz_t.hip", "kernels_matvec.hip", "kernels_near.hip", "kernels_krylov.hip", "kernels_precond.hip", "kernels_adjoint.hip", "api.hip"]
 ARCH = os.environ.get("SCABS_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [

@@ -213,6 +213,10 @@ struct scabs_ctx {
   const int *toe_capcol = nullptr, *toe_esgn = nullptr;
   cx<double> *toe_tri64 = nullptr;
   cx<float> *toe_tri32 = nullptr;
+  // transposed product: circulant, long and short column parts per precision
+  cx<float> *toe_tcol32 = nullptr, *toe_lcol32 = nullptr, *toe_scol32 = nullptr;
+  cx<double> *toe_tcol64 = nullptr, *toe_lcol64 = nullptr, *toe_scol64 = nullptr;
+  int *toe_capidx = nullptr;   // per edge its non-periodic index, -1 for periodic edges
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
   double toe_sparse_bytes[2] = {0, 0};  // stored non-periodic entries one product reads (FP64, FP32)
   // launch choices of the product for fewer than 8 and for 8 vectors:
@@ -911,6 +915,18 @@ static std::string build_toeplitz(scabs_ctx *c) {
   c->toe_ncap = (int)ncap;
   c->toe_nshort = nshort;
   c->toe_capcol = c->mem.upload(nonper);
+  {
+    std::vector<int> capidx(g.ne, -1);
+    for (size_t j = 0; j < nonper.size(); j++) capidx[nonper[j]] = (int)j;
+    c->toe_capidx = c->mem.upload(capidx);
+    const size_t nc = std::max<size_t>(1, nonper.size());
+    c->toe_tcol32 = c->mem.alloc<cx<float>>(4 * (size_t)g.ne);
+    c->toe_lcol32 = c->mem.alloc<cx<float>>(3 * (size_t)g.ne);
+    c->toe_scol32 = c->mem.alloc<cx<float>>(3 * nc);
+    c->toe_tcol64 = c->mem.alloc<cx<double>>(4 * (size_t)g.ne);
+    c->toe_lcol64 = c->mem.alloc<cx<double>>(3 * (size_t)g.ne);
+    c->toe_scol64 = c->mem.alloc<cx<double>>(3 * nc);
+  }
   c->toe_esgn = esgn_dev;
   c->toe_nnz = nnz;
   c->toe_V4 = c->mem.alloc<cx<double>>(4 * (size_t)nnz);
@@ -1321,15 +1337,8 @@ static double *toe_rpart(scabs_ctx *c, double *) { return c->toe_rpart64; }
 // ring-axis transforms, per-frequency block products, inverse transforms,
 // local and sigma terms, then the rows (sparse rows of the non-periodic
 // pairs plus the periodic sums)
-template <typename T>
-static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_out, const double *x, double *y,
-                      int nb) {
-  hipStream_t s = c->stream;
-  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
-  toe_ensure(c, d, tri_out, nb);
-  DevOperator<T> op = P.op;
-  op.tri_out = tri_out;
-  op.edge_out = d.edge_out;
+// the stored entries of the non-periodic pairs in the product's precision
+template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
   const bool f32 = sizeof(T) == sizeof(float);
   const cx<T> *V4 = f32 ? (const cx<T> *)c->toe_V4f : (const cx<T> *)c->toe_V4;
   const cx<T> *S4 = f32 ? (const cx<T> *)c->toe_S4f : (const cx<T> *)c->toe_S4;
@@ -1344,6 +1353,55 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   R.S4L = S4 + 4 * (size_t)c->toe_nshort;
   R.part = toe_part(c, (T *)nullptr);
   R.rpart = toe_rpart(c, (T *)nullptr);
+  R.groups = 8;
+  return R;
+}
+
+// y = A^T z for one vector with the transposed block-Toeplitz product
+template <typename T>
+static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_out, const double *z, double *y) {
+  hipStream_t s = c->stream;
+  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
+  toe_ensure(c, d, tri_out, 1);
+  DevOperator<T> op = P.op;
+  op.tri_out = tri_out;
+  const bool f32 = sizeof(T) == sizeof(float);
+  ToeRows<T> R = toe_rows_of<T>(c);
+  d.lines = toe_max_lines(d.P, f32);
+  cx<T> *tcol = f32 ? (cx<T> *)c->toe_tcol32 : (cx<T> *)c->toe_tcol64;
+  cx<T> *lcol = f32 ? (cx<T> *)c->toe_lcol32 : (cx<T> *)c->toe_lcol64;
+  cx<T> *scol = f32 ? (cx<T> *)c->toe_scol32 : (cx<T> *)c->toe_scol64;
+  {
+    StageTimer t(c, SCABS_STAGE_UNPACK + off);
+    launch_unpack_rows(op, z, s);
+    // point weights are written only at periodic triangles' points
+    HIPCHK(hipMemsetAsync(d.pf, 0, sizeof(cx<T>) * 2 * 2 * (size_t)NQ * d.nt_r * d.nr, s));
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_FFT + off);
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_FWD);
+  }
+  {
+    StageTimer t(c, f32 ? SCABS_STAGE_TOEAPPLY32 : SCABS_STAGE_TOEAPPLY64);
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_APPLY);
+  }
+  {
+    StageTimer t(c, SCABS_STAGE_NEAR + off);
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_INV);
+  }
+}
+
+template <typename T>
+static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_out, const double *x, double *y,
+                      int nb) {
+  hipStream_t s = c->stream;
+  const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
+  toe_ensure(c, d, tri_out, nb);
+  DevOperator<T> op = P.op;
+  op.tri_out = tri_out;
+  op.edge_out = d.edge_out;
+  const bool f32 = sizeof(T) == sizeof(float);
+  ToeRows<T> R = toe_rows_of<T>(c);
   {
     const int *tn = c->toe_tune[nb >= 8 ? 1 : 0];
     const int lmax = toe_max_lines(d.P, f32);
@@ -1387,10 +1445,16 @@ static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec,
   const size_t stride = 2 * (size_t)c->lay.N;
   if (trans) {
     for (int k = 0; k < nb; k++) {
-      if (prec == SCABS_FP32)
+      if (c->toe) {
+        if (prec == SCABS_FP32)
+          apply_toe_t(c, c->p32, c->t32, c->toe_tri32, x + k * stride, y + k * stride);
+        else
+          apply_toe_t(c, c->p64, c->t64, c->toe_tri64, x + k * stride, y + k * stride);
+      } else if (prec == SCABS_FP32) {
         apply_t(c, c->p32, x + k * stride, y + k * stride);
-      else
+      } else {
         apply_t(c, c->p64, x + k * stride, y + k * stride);
+      }
     }
     return;
   }

@@ -288,6 +288,38 @@ template <typename T> struct ToeRows {
   T *rpart;               // [group][vector][6][edge] partial sums of the periodic rows
   int groups;             // column groups of the periodic rows (<= toe_row_groups())
 };
+// coefficients of (J_i, J_e, M) in the E, H and eq14 rows from one entry's
+// 8 tested values (sigma values on absorber rows only)
+template <typename T> struct RowCoef {
+  cx<T> eJi, eJe, eM, hJi, hJe, hM, rJi, rM;
+};
+template <typename T>
+__device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR, T Ze, T Zi) {
+  RowCoef<T> c;
+  const cx<T> Le = V4[0], Ke = V4[1], Li = V4[2], Ki = V4[3];
+  c.eJi = Li * Zi;
+  c.eJe = Le * (-Ze);
+  c.eM = Ke + Ki;
+  c.hJi = Ki;
+  c.hJe = -Ke;
+  c.hM = Le * (T(-1) / Ze) - Li * (T(1) / Zi);
+  c.rJi = czero<T>();
+  c.rM = czero<T>();
+  if (isR) {
+    const cx<T> Lr = S4[0], Kr = S4[1], Ls = S4[2], Ks = S4[3];
+    c.hJe = c.hJe - Lr * Ze;
+    c.hM = c.hM + Kr;
+    c.rJi = Ls * Zi;
+    c.rM = Ks;
+  }
+  return c;
+}
+// transposed block-Toeplitz product of one vector (rows z unpacked into
+// op.src): circulant columns tcol[e][4], long-part columns lcol[e][3],
+// short-part columns scol[j][3] (capidx: edge -> non-periodic index or -1)
+template <typename T>
+void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const ToeRows<T> &R, cx<T> *tcol,
+                          cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts);
 template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb);
 int toe_long_chunk();
 int toe_row_groups();   // the largest number of column groups

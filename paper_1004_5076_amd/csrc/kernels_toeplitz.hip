@@ -902,32 +902,6 @@ template <typename T> __device__ inline T wsum64(T v) {
   return v;
 }
 
-// coefficients of (J_i, J_e, M) in the E, H and eq14 rows from one entry's
-// 8 tested values (sigma values on absorber rows only)
-template <typename T> struct RowCoef {
-  cx<T> eJi, eJe, eM, hJi, hJe, hM, rJi, rM;
-};
-template <typename T>
-__device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR, T Ze, T Zi) {
-  RowCoef<T> c;
-  const cx<T> Le = V4[0], Ke = V4[1], Li = V4[2], Ki = V4[3];
-  c.eJi = Li * Zi;
-  c.eJe = Le * (-Ze);
-  c.eM = Ke + Ki;
-  c.hJi = Ki;
-  c.hJe = -Ke;
-  c.hM = Le * (T(-1) / Ze) - Li * (T(1) / Zi);
-  c.rJi = czero<T>();
-  c.rM = czero<T>();
-  if (isR) {
-    const cx<T> Lr = S4[0], Kr = S4[1], Ls = S4[2], Ks = S4[3];
-    c.hJe = c.hJe - Lr * Ze;
-    c.hM = c.hM + Kr;
-    c.rJi = Ls * Zi;
-    c.rM = Ks;
-  }
-  return c;
-}
 template <typename T>
 __device__ inline void row_mac(const RowCoef<T> &c, const cx<T> *cm, cx<T> &e, cx<T> &h, cx<T> &q) {
   const cx<T> Je = cm[0], Ji = cm[1], M = cm[2];

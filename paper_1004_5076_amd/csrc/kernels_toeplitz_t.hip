@@ -1,0 +1,395 @@
+// Transposed block-Toeplitz product y = A^T z (the adjoint solves of the
+// gradient), exact like the forward product.  Every stage of the forward
+// product is transposed:
+//  * the circulant block products: with the forward tables T(f) (row a,
+//    column b), the transposed circulant takes T_ab(-f) contracted over the
+//    row index a, so the row weights are transformed forward along the rings,
+//    multiplied per frequency by the tables at P - f, and transformed back
+//    onto the column slots (J_e, M, J_i, M_i = -M) of the periodic edges;
+//  * the sigma tests of the periodic test halves against the periodic point
+//    fields: per point the tangential weights that the tests give to the
+//    exterior and interior fields (the point rows of the circulant);
+//  * the local terms (residues, Gram block, the 1/2 n x M part of the sigma
+//    tests) per triangle;
+//  * the stored entries of the non-periodic pairs: the short part (periodic
+//    rows, non-periodic columns) summed per non-periodic column, the long
+//    part (non-periodic rows, every column) summed per column.
+// One vector per call (the adjoint solves have one right-hand side).
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace scabs {
+
+constexpr int TT_THREADS = 512;
+constexpr int TT_ELEMS = 16;
+
+// LDS of a group of G transform lines: padded lines, then P twiddles
+template <typename T> inline size_t tt_tw_offset(int P, int G) {
+  return ((size_t)lpad_size<T>(G * P) * sizeof(cx<T>) + 15) / 16 * 16;
+}
+template <typename T> inline size_t tt_lds(int P, int G) { return tt_tw_offset<T>(P, G) + (size_t)P * sizeof(cx<T>); }
+template <typename T>
+__device__ inline const cx<T> *tt_twiddles(unsigned char *smem, const cx<T> *tw, int P, int G) {
+  cx<T> *t = reinterpret_cast<cx<T> *>(smem + ((size_t)lpad_size<T>(G * P) * sizeof(cx<T>) + 15) / 16 * 16);
+  for (int i = threadIdx.x; i < P; i += blockDim.x) t[i] = tw[i];
+  return t;
+}
+template <typename K> size_t tt_launch_lds(K kernel, size_t lds) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return lds;
+}
+
+// ---------------------------------------------------------------------------
+// local terms and sigma tests, transposed, per triangle.  rows[e] = (z_E,
+// z_H, z_14) of edge e (op.src after the row unpack).  Per test half i the
+// forward H and eq14 rows read, at every point q (w the weight, ws = w sigma,
+// Jsum = sum_j f_j (J_e + J_i)_j, Mq = sum_j f_j M_j):
+//   h_i   += -1/2 w g_i.(n x Jsum) + ws (g_i x n).(1/2 n x Mq + E_e^PV)
+//   r14_i += w g_i.Jsum - ws g_i.(1/2 n x Mq + E_i^PV)
+// (PV fields only for periodic test halves of periodic triangles).  The
+// transpose collects per point Jsum' = sum_i [-1/2 w z_H (g_i x n) + w z_14
+// g_i], Mq' = sum_i [1/2 ws z_H ((g_i x n) x n) - 1/2 ws z_14 (g_i x n)], and
+// the field weights E_e' = sum_i ws z_H (g_i x n), E_i' = -sum_i ws z_14 g_i,
+// projected on the point's tangents into the point-row weights pw (ring-major
+// like the forward point fields).  Per half j of the triangle the columns
+// receive (J_e', J_i', M') = (f_j.Jsum', f_j.Jsum', f_j.Mq').
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) toe_t_local_kernel(DevOperator<T> op, ToeDev<T> d) {
+  const int T_ = blockIdx.x * blockDim.x + threadIdx.x;
+  if (T_ >= op.nt) return;
+  const cx<T> *rows = op.src;
+  const TriRec<T> tr = op.tris[T_];
+  const bool per = d.tri_loc[T_] >= 0;
+  const T n[3] = {tr.nrm[0], tr.nrm[1], tr.nrm[2]};
+  cx<T> zH[3], zQ[3];
+  bool eper[3];
+  for (int i = 0; i < 3; i++) {
+    const int e = tr.edge[i];
+    zH[i] = rows[3 * e + 1];
+    zQ[i] = rows[3 * e + 2];
+    eper[i] = d.edge_sgn[e] != 0;
+  }
+  cx<T> out[9];
+  for (int k = 0; k < 9; k++) out[k] = czero<T>();
+  for (int q = 0; q < NQ; q++) {
+    const PointRec<T> P = op.pts[(size_t)T_ * NQ + q];
+    const T w = P.w, ws = P.w * P.sigma;
+    cx<T> Js[3], Ms[3], Ee[3], Ei[3];
+    for (int a = 0; a < 3; a++) Js[a] = Ms[a] = Ee[a] = Ei[a] = czero<T>();
+    for (int i = 0; i < 3; i++) {
+      const T g[3] = {P.f[3 * i], P.f[3 * i + 1], P.f[3 * i + 2]};
+      const T gxn[3] = {g[1] * n[2] - g[2] * n[1], g[2] * n[0] - g[0] * n[2], g[0] * n[1] - g[1] * n[0]};
+      const T gxnxn[3] = {gxn[1] * n[2] - gxn[2] * n[1], gxn[2] * n[0] - gxn[0] * n[2],
+                          gxn[0] * n[1] - gxn[1] * n[0]};
+      for (int a = 0; a < 3; a++) {
+        axpy(Js[a], T(-0.5) * w * gxn[a], zH[i]);
+        axpy(Js[a], w * g[a], zQ[i]);
+      }
+      if (ws != T(0)) {
+        for (int a = 0; a < 3; a++) {
+          axpy(Ms[a], T(0.5) * ws * gxnxn[a], zH[i]);
+          axpy(Ms[a], T(-0.5) * ws * gxn[a], zQ[i]);
+        }
+        if (per && eper[i])
+          for (int a = 0; a < 3; a++) {
+            axpy(Ee[a], ws * gxn[a], zH[i]);
+            axpy(Ei[a], -ws * g[a], zQ[i]);
+          }
+      }
+    }
+    for (int j = 0; j < 3; j++) {
+      cx<T> fj = czero<T>(), fm = czero<T>();
+      for (int a = 0; a < 3; a++) {
+        axpy(fj, P.f[3 * j + a], Js[a]);
+        axpy(fm, P.f[3 * j + a], Ms[a]);
+      }
+      out[3 * j] += fj;
+      out[3 * j + 1] += fj;
+      out[3 * j + 2] += fm;
+    }
+    if (per) {
+      const int lt = d.tri_loc[T_], jr = d.tri_ring[T_], nr = d.nr;
+      const size_t R2 = 2 * (size_t)NQ * d.nt_r, r = 2 * ((size_t)lt * NQ + q);
+      const T *t1 = d.t1 + 3 * (size_t)lt, *t2 = d.t2 + 3 * (size_t)lt;
+      cx<T> e1 = czero<T>(), e2 = czero<T>(), i1 = czero<T>(), i2 = czero<T>();
+      for (int a = 0; a < 3; a++) {
+        axpy(e1, t1[a], Ee[a]);
+        axpy(e2, t2[a], Ee[a]);
+        axpy(i1, t1[a], Ei[a]);
+        axpy(i2, t2[a], Ei[a]);
+      }
+      cx<T> *pw = d.pf + r * nr + jr;
+      pw[0] = e1;
+      pw[nr] = e2;
+      pw[R2 * nr] = i1;
+      pw[(R2 + 1) * nr] = i2;
+    }
+  }
+  cx<T> *to = op.tri_out + (size_t)T_ * 9;
+  for (int k = 0; k < 9; k++) to[k] = out[k];
+}
+
+// ---------------------------------------------------------------------------
+// row lines (forward transform): line s < 2 ne_r: rows E (s even) and H of
+// template edge s / 2 at the periodic edges of the rings (template
+// orientation); line 2 ne_r + rr: point-row weights pw[rr][j]; zero beyond
+// the rings; spectra to Y[f][line]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(TT_THREADS) toe_t_fwd_kernel(DevOperator<T> op, ToeDev<T> d) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int P = d.P, nr = d.nr, G = d.lines, ne_r = d.ne_r;
+  const int nlines = 2 * ne_r + 4 * NQ * d.nt_r;
+  const int l0 = blockIdx.x * G, nl = min(G, nlines - l0);
+  const cx<T> *tws = tt_twiddles<T>(smem_raw, d.tw, P, G);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int li = i / P, j = i - li * P, l = l0 + li;
+    cx<T> val = czero<T>();
+    if (j < nr) {
+      if (l < 2 * ne_r) {
+        const int e = d.ringmap[(size_t)(l >> 1) * nr + j];
+        if (e >= 0) val = op.src[3 * e + (l & 1)] * (T)d.edge_sgn[e];
+      } else {
+        val = d.pf[(size_t)(l - 2 * ne_r) * nr + j];
+      }
+    }
+    buf[lpad<T>(i)] = val;
+  }
+  __syncthreads();
+  lds_fft_mr<T, TT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, false);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int f = i / nl, li = i - f * nl;
+    d.Y[(size_t)f * nlines + l0 + li] = buf[lpad<T>(li * P + f)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per frequency f, one wave per template edge b (column): the four column
+// slots from the row spectra with the tables at P - f, rows contracted
+//   J_e' = sum_a (-Z_e L E - K H) + sum_r PJ_e W_e     (exterior)
+//   M'   = sum_a (K E - L H / Z_e) + sum_r PM_e W_e
+//   J_i' = sum_a (Z_i L E + K H)   + sum_r PJ_i W_i     (interior, b's body)
+//   M_i' = sum_a (-K E + L H / Z_i) + sum_r PM_i W_i
+// written to X[f][slot ne_r + b] (slots J_e, M, J_i, M_i)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) toe_t_apply_kernel(ToeDev<T> d) {
+  const int f = blockIdx.y;
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= d.ne_r) return;   // wave-uniform
+  const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r, nout = 2 * ne_r + 2 * R2, P = d.P;
+  const int fr = f == 0 ? 0 : P - f;
+  const cx<T> *Yf = d.Y + (size_t)f * nout;
+  const int bd = d.ebody[b], e0 = d.body_e0[bd], neb = d.body_e0[bd + 1] - e0;
+  const int r0 = 2 * NQ * d.body_t0[bd], R2b = 2 * NQ * (d.body_t0[bd + 1] - d.body_t0[bd]);
+  const T Ze = d.Z_e, Zi = d.Z_i, iZe = T(1) / Ze, iZi = T(1) / Zi;
+  cx<T> je = czero<T>(), me = czero<T>(), ji = czero<T>(), mi = czero<T>();
+  const cx<T> *G = d.GE + ((size_t)fr * ne_r * ne_r + (size_t)b * ne_r) * 2;
+  for (int a = lane; a < ne_r; a += 64) {
+    const cx<T> L = G[2 * a], K = G[2 * a + 1], E = Yf[2 * a], H = Yf[2 * a + 1];
+    je += (L * E) * (-Ze) - K * H;
+    me += K * E - (L * H) * iZe;
+  }
+  const cx<T> *GI = d.GI + ((size_t)fr * d.gi_per_f + d.ibase[bd] + (size_t)(b - e0) * neb) * 2;
+  for (int a = lane; a < neb; a += 64) {
+    const cx<T> L = GI[2 * a], K = GI[2 * a + 1], E = Yf[2 * (e0 + a)], H = Yf[2 * (e0 + a) + 1];
+    ji += (L * E) * Zi + K * H;
+    mi += (L * H) * iZi - K * E;
+  }
+  const cx<T> *PE = d.PE + ((size_t)fr * ne_r * R2 + (size_t)b * R2) * 2;
+  for (int r = lane; r < R2; r += 64) {
+    const cx<T> W = Yf[2 * ne_r + r];
+    je += PE[2 * r] * W;
+    me += PE[2 * r + 1] * W;
+  }
+  const cx<T> *PI = d.PI + ((size_t)fr * d.pi_per_f + d.pbase[bd] + (size_t)(b - e0) * R2b) * 2;
+  for (int r = lane; r < R2b; r += 64) {
+    const cx<T> W = Yf[2 * ne_r + R2 + r0 + r];
+    ji += PI[2 * r] * W;
+    mi += PI[2 * r + 1] * W;
+  }
+  T s[8] = {je.x, je.y, me.x, me.y, ji.x, ji.y, mi.x, mi.y};
+#pragma unroll
+  for (int k = 0; k < 8; k++)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o, 64);
+  if (lane != 0) return;
+  cx<T> *Xf = d.X + (size_t)f * 4 * ne_r;
+  Xf[b] = {s[0], s[1]};
+  Xf[ne_r + b] = {s[2], s[3]};
+  Xf[2 * ne_r + b] = {s[4], s[5]};
+  Xf[3 * ne_r + b] = {s[6], s[7]};
+}
+
+// column lines (inverse transform): slot c of template edge b over the
+// rings; tcol[e][c] at the periodic edges (template orientation back to the
+// edge's; slot 3 carries -M, so its value enters M with the opposite sign)
+template <typename T>
+__global__ void __launch_bounds__(TT_THREADS) toe_t_inv_kernel(ToeDev<T> d, cx<T> *__restrict__ tcol) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+  const int P = d.P, nr = d.nr, G = d.lines, ne_r = d.ne_r;
+  const int nlines = 4 * ne_r;
+  const int l0 = blockIdx.x * G, nl = min(G, nlines - l0);
+  const cx<T> *tws = tt_twiddles<T>(smem_raw, d.tw, P, G);
+  for (int i = threadIdx.x; i < nl * P; i += blockDim.x) {
+    const int f = i / nl, li = i - f * nl;
+    buf[lpad<T>(li * P + f)] = d.X[(size_t)f * nlines + l0 + li];
+  }
+  __syncthreads();
+  lds_fft_mr<T, TT_ELEMS>(buf, P, nl, 1, P, 0, 1, tws, P, true);
+  for (int i = threadIdx.x; i < nl * nr; i += blockDim.x) {
+    const int li = i / nr, j = i - li * nr, l = l0 + li;
+    const int c = l / ne_r, b = l - c * ne_r;
+    const int e = d.ringmap[(size_t)b * nr + j];
+    if (e < 0) continue;
+    const T sg = (T)d.edge_sgn[e] * (c == 3 ? T(-1) : T(1));
+    tcol[(size_t)e * 4 + c] = buf[lpad<T>(li * P + j)] * sg;
+  }
+}
+
+// transposed entry of a stored pair: the column currents' weights from the
+// row weights (z_E, z_H, z_14) of the pair's row edge
+template <typename T> struct ColAcc {
+  cx<T> je, ji, m;
+};
+template <typename T>
+__device__ inline void col_mac(const RowCoef<T> &c, cx<T> zE, cx<T> zH, cx<T> zQ, ColAcc<T> &o) {
+  cmac(o.je, c.eJe, zE);
+  cmac(o.je, c.hJe, zH);
+  cmac(o.ji, c.eJi, zE);
+  cmac(o.ji, c.hJi, zH);
+  cmac(o.ji, c.rJi, zQ);
+  cmac(o.m, c.eM, zE);
+  cmac(o.m, c.hM, zH);
+  cmac(o.m, c.rM, zQ);
+}
+
+// short part transposed: one work-group per non-periodic column j, threads
+// over the periodic rows n; scol[j] = (J_e', J_i', M')
+template <typename T>
+__global__ void __launch_bounds__(256) toe_t_short_kernel(DevOperator<T> op, ToeRows<T> R, cx<T> *__restrict__ scol) {
+  const int j = blockIdx.x;
+  const T Ze = op.Z_e, Zi = op.Z_i;
+  ColAcc<T> o = {czero<T>(), czero<T>(), czero<T>()};
+  for (int n = threadIdx.x; n < op.ne; n += blockDim.x) {
+    if (R.edge_sgn[n] == 0) continue;
+    const EdgeRec r = op.edges[n];
+    const size_t k = ((size_t)j * op.ne + n) * 4;
+    const RowCoef<T> c = row_coef(R.V4S + k, R.S4S + k, r.isR != 0, Ze, Zi);
+    col_mac(c, op.src[3 * n], op.src[3 * n + 1], op.src[3 * n + 2], o);
+  }
+  __shared__ T red[6][4];
+  T v[6] = {o.je.x, o.je.y, o.ji.x, o.ji.y, o.m.x, o.m.y};
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v[k] += __shfl_xor(v[k], s, 64);
+    if (lane == 0) red[k][w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    T t = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) t += red[threadIdx.x][q];
+    reinterpret_cast<T *>(scol + (size_t)j * 3)[threadIdx.x] = t;
+  }
+}
+
+// long part transposed: one thread per column m, over the non-periodic rows
+template <typename T>
+__global__ void __launch_bounds__(256) toe_t_long_kernel(DevOperator<T> op, ToeRows<T> R, cx<T> *__restrict__ lcol) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= op.ne) return;
+  const T Ze = op.Z_e, Zi = op.Z_i;
+  ColAcc<T> o = {czero<T>(), czero<T>(), czero<T>()};
+  for (int i = 0; i < R.nlong; i++) {
+    const int n = R.capcol[i];
+    const EdgeRec r = op.edges[n];
+    const size_t k = ((size_t)m * R.nlong + i) * 4;
+    const RowCoef<T> c = row_coef(R.V4L + k, R.S4L + k, r.isR != 0, Ze, Zi);
+    col_mac(c, op.src[3 * n], op.src[3 * n + 1], op.src[3 * n + 2], o);
+  }
+  lcol[(size_t)m * 3] = o.je;
+  lcol[(size_t)m * 3 + 1] = o.ji;
+  lcol[(size_t)m * 3 + 2] = o.m;
+}
+
+// per edge: the circulant columns (periodic edges), the long and short parts
+// and the local terms of its two halves, onto the unknowns (J^L = J_e - J_i
+// and M^L on sigma-free edges; J_e, J_i, M on absorber edges)
+template <typename T>
+__global__ void __launch_bounds__(256)
+toe_t_combine_kernel(DevOperator<T> op, ToeRows<T> R, const cx<T> *__restrict__ tcol, const cx<T> *__restrict__ lcol,
+                     const cx<T> *__restrict__ scol, const int *__restrict__ capidx, double *__restrict__ y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= op.ne) return;
+  const EdgeRec r = op.edges[e];
+  cx<T> je = lcol[(size_t)e * 3], ji = lcol[(size_t)e * 3 + 1], m = lcol[(size_t)e * 3 + 2];
+  if (R.edge_sgn[e] != 0) {
+    je += tcol[(size_t)e * 4];
+    m += tcol[(size_t)e * 4 + 1] + tcol[(size_t)e * 4 + 3];
+    ji += tcol[(size_t)e * 4 + 2];
+  }
+  const int ci = capidx[e];
+  if (ci >= 0) {
+    je += scol[(size_t)ci * 3];
+    ji += scol[(size_t)ci * 3 + 1];
+    m += scol[(size_t)ci * 3 + 2];
+  }
+  for (int s = 0; s < 2; s++) {
+    const cx<T> *h = op.tri_out + ((size_t)r.tri[s] * 3 + r.loc[s]) * 3;
+    je += h[0];
+    ji += h[1];
+    m += h[2];
+  }
+  auto put = [&](int slot, cx<T> v) {
+    y[2 * (size_t)slot] = (double)v.x;
+    y[2 * (size_t)slot + 1] = (double)v.y;
+  };
+  if (!r.isR) {
+    put(r.col[0], je - ji);
+    put(r.col[1], m);
+  } else {
+    put(r.col[0], je);
+    put(r.col[1], ji);
+    put(r.col[2], m);
+  }
+}
+
+template <typename T>
+void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const ToeRows<T> &R, cx<T> *tcol,
+                          cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts) {
+  const int G = d.lines;
+  const int nrow = 2 * d.ne_r + 4 * NQ * d.nt_r, ncol = 4 * d.ne_r;
+  if (parts & TOE_FWD) {
+    hipLaunchKernelGGL(toe_t_local_kernel<T>, dim3((op.nt + 255) / 256), dim3(256), 0, s, op, d);
+    hipLaunchKernelGGL(toe_t_fwd_kernel<T>, dim3((nrow + G - 1) / G), dim3(TT_THREADS),
+                       tt_launch_lds(toe_t_fwd_kernel<T>, tt_lds<T>(d.P, G)), s, op, d);
+  }
+  if (parts & TOE_APPLY)
+    hipLaunchKernelGGL(toe_t_apply_kernel<T>, dim3((d.ne_r + 3) / 4, d.P), dim3(256), 0, s, d);
+  if (parts & TOE_INV) {
+    hipLaunchKernelGGL(toe_t_inv_kernel<T>, dim3((ncol + G - 1) / G), dim3(TT_THREADS),
+                       tt_launch_lds(toe_t_inv_kernel<T>, tt_lds<T>(d.P, G)), s, d, tcol);
+    if (R.ncap > 0)
+      hipLaunchKernelGGL(toe_t_short_kernel<T>, dim3(R.ncap), dim3(256), 0, s, op, R, scol);
+    hipLaunchKernelGGL(toe_t_long_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R, lcol);
+    hipLaunchKernelGGL(toe_t_combine_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R,
+                       (const cx<T> *)tcol, (const cx<T> *)lcol, (const cx<T> *)scol, capidx, y);
+  }
+}
+template void launch_toe_product_t<float>(const DevOperator<float> &, const ToeDev<float> &, const ToeRows<float> &,
+                                          cx<float> *, cx<float> *, cx<float> *, const int *, double *, hipStream_t,
+                                          int);
+template void launch_toe_product_t<double>(const DevOperator<double> &, const ToeDev<double> &,
+                                           const ToeRows<double> &, cx<double> *, cx<double> *, cx<double> *,
+                                           const int *, double *, hipStream_t, int);
+
+}  // namespace scabs

@@ -181,3 +181,43 @@ def test_autotune_keeps_fastest(case):
     x = synth.random_complex(210, o.N)
     y = ctx.matvec(torch.from_numpy(x).cuda(), prec=0).cpu().numpy()
     assert _rel(y, A @ x) < 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-6)])
+def test_transposed_product_matches_dense(case, prec, tol):
+    """A^T z with the transposed block-Toeplitz product (circulant at -f,
+    transposed sigma tests, local terms and stored entries) against the
+    oracle's dense matrix, per column block."""
+    import torch
+    name, w, o, A, ctx = case
+    for seed in (85, 86):
+        z = synth.random_complex(seed, o.N)
+        ref = A.T @ z
+        y = ctx.matvec(torch.from_numpy(z).cuda(), prec=prec, transpose=True).cpu().numpy()
+        for a, b in _blocks(o):
+            e = _rel(y[a:b], ref[a:b])
+            print(name, "transposed prec", prec, "cols", a, b, "rel err", e, flush=True)
+            assert e < tol, (a, b)
+
+
+def test_transposed_solve_matches_dense_lu(case):
+    import torch
+    import paper_1004_5076_amd as pk
+    name, w, o, A, ctx = case
+    g = synth.random_complex(87, o.N)
+    lam, info = ctx.solve(torch.from_numpy(g).cuda(), tol=1e-11, max_iter=4000, restart=200, mode=pk.SCABS_MIXED,
+                          transpose=True)
+    assert info["status"] == 0, info
+    ref = oracle.lu_solve(A.T.copy(), g)
+    assert _rel(lam.cpu().numpy(), ref) < 1e-8
+
+
+def test_transposed_bilinear_identity(case):
+    """y^T (A x) = x^T (A^T y) with both block-Toeplitz products, FP64."""
+    import torch
+    name, w, o, A, ctx = case
+    x = torch.from_numpy(synth.random_complex(88, o.N)).cuda()
+    y = torch.from_numpy(synth.random_complex(89, o.N)).cuda()
+    a = (y * ctx.matvec(x)).sum().item()
+    b = (x * ctx.matvec(y, transpose=True)).sum().item()
+    assert abs(a - b) <= 1e-12 * abs(a)
