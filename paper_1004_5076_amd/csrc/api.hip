@@ -217,6 +217,8 @@ struct scabs_ctx {
   cx<float> *toe_tcol32 = nullptr, *toe_lcol32 = nullptr, *toe_scol32 = nullptr;
   cx<double> *toe_tcol64 = nullptr, *toe_lcol64 = nullptr, *toe_scol64 = nullptr;
   int *toe_capidx = nullptr;   // per edge its non-periodic index, -1 for periodic edges
+  int *toe_abs_tri = nullptr;  // triangles carrying an absorber edge (exact point fields)
+  int toe_nabs = 0;
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
   double toe_sparse_bytes[2] = {0, 0};  // stored non-periodic entries one product reads (FP64, FP32)
   // launch choices of the product for fewer than 8 and for 8 vectors:
@@ -375,6 +377,7 @@ static void build_precision(scabs_ctx *c, PrecState<T> &P, const std::vector<cx<
   }
   P.tris = c->mem.upload(tr);
   P.src = c->mem.alloc<cx<T>>((size_t)g.ne * 3);
+  P.srcI = nullptr;
   P.tri_out = c->mem.alloc<cx<T>>((size_t)g.nt * 9);
   P.V4 = V4;
   P.S4 = S4;
@@ -919,6 +922,12 @@ static std::string build_toeplitz(scabs_ctx *c) {
     std::vector<int> capidx(g.ne, -1);
     for (size_t j = 0; j < nonper.size(); j++) capidx[nonper[j]] = (int)j;
     c->toe_capidx = c->mem.upload(capidx);
+    std::vector<int> abs_tri;
+    for (int T = 0; T < g.nt; T++)
+      if (c->lay.isR[g.tedge[3 * T]] || c->lay.isR[g.tedge[3 * T + 1]] || c->lay.isR[g.tedge[3 * T + 2]])
+        abs_tri.push_back(T);
+    c->toe_nabs = (int)abs_tri.size();
+    c->toe_abs_tri = abs_tri.empty() ? nullptr : c->mem.upload(abs_tri);
     const size_t nc = std::max<size_t>(1, nonper.size());
     c->toe_tcol32 = c->mem.alloc<cx<float>>(4 * (size_t)g.ne);
     c->toe_lcol32 = c->mem.alloc<cx<float>>(3 * (size_t)g.ne);
@@ -1009,6 +1018,18 @@ static int do_build(scabs_ctx *c) {
     return fail(c, SCABS_E_ARG, "the circulant preconditioner needs the block-Toeplitz product");
   if (c->opts.precond < 0 || c->opts.precond > SCABS_PRECOND_CIRC_SCHWARZ) return fail(c, SCABS_E_ARG, "unknown precond");
   c->mem.release();
+  // every device buffer of the last build is gone: forget the per-vector
+  // buffers the products grow on demand, so that growing them never frees an
+  // address the new build has been handed again
+  c->t64 = ToeDev<double>{};
+  c->t32 = ToeDev<float>{};
+  c->toe_bcap = 0;
+  c->toe_tri64 = nullptr;
+  c->toe_tri32 = nullptr;
+  c->toe_part64 = c->toe_rpart64 = nullptr;
+  c->toe_part32 = c->toe_rpart32 = nullptr;
+  c->p64.srcI = nullptr;
+  c->p32.srcI = nullptr;
   c->work.release();
   c->work_restart = -1;
   c->work_N = -1;
@@ -2360,6 +2381,11 @@ static void point_fields(scabs_ctx *c, const double *x, cx<double> *Ee, cx<doubl
   a.Ee = Ee;
   a.Ei = Ei;
   launch_near_point_fields(a, s);
+  // the block-Toeplitz operator is the Galerkin matrix itself: its sigma tests
+  // read the exact fields, summed directly at the absorber triangles' points
+  if (c->toe)
+    launch_point_fields_exact(P.op, c->trid, c->toe_abs_tri, c->toe_nabs, c->k_e, c->Z_e, c->k_i, c->Z_i,
+                              c->opts.kappa_s, Ee, Ei, s);
   HIPCHK(hipGetLastError());
 }
 

@@ -218,6 +218,11 @@ void launch_sigma_grad(const DevOperator<double> &op, const cx<double> *Ee, cons
                        const cx<double> *Einc, double *dfds, hipStream_t s);
 // fields at points near or on either side of the surface: per triangle the
 // static part analytic within SCABS_NEAR_FIELD_RADIUS triangle radii
+// one-sided fields of the discrete Galerkin operator at the quadrature points
+// of the listed triangles, by direct summation (overwrites those points)
+void launch_point_fields_exact(const DevOperator<double> &op, const TriD *tri, const int *list, int nlist,
+                               double k_e, double Z_e, double k_i, double Z_i, double kappa, cx<double> *Ee,
+                               cx<double> *Ei, hipStream_t s);
 void launch_eval_field_exact(const DevOperator<double> &op, const TriD *tri, const double *pts, int npts, int region,
                              double k, double Z, cx<double> *E, cx<double> *H, hipStream_t s);
 // an incident source in the interior medium: a point dipole (b = 0) at r0 or

@@ -906,6 +906,154 @@ void launch_eval_field_exact(const DevOperator<double> &op, const TriD *tri, con
   hipLaunchKernelGGL(eval_field_exact_kernel, dim3(npts), dim3(EF_THREADS), 0, s, op, tri, pts, region, k, Z, E, H);
 }
 
+// ---------------------------------------------------------------------------
+// One-sided fields of the discrete Galerkin operator itself (Appendix A) at
+// the quadrature points of listed triangles, by direct summation over every
+// source triangle with the inner integrals the dense tests use: singular pairs
+// (centroid distance below kappa (rho_T + rho_B)) take the static part of G
+// analytically and the seven-point rule on the smooth remainder, all others
+// the seven-point rule on G.  Adds the residue 1/2 n x M of the point's own
+// triangle (exterior limit of the exterior field, interior limit of the
+// interior field with M_i = -M).
+// ---------------------------------------------------------------------------
+// E at r of J = sum_j J_j f_j, M = sum_j M_j f_j on source triangle B in
+// medium (k, Z), f_j = coef_j (r' - v_j):
+//   E = -Z jk (sum_j a_j J_j + k^-2 sum_j gphi_j J_j) - sum_j c_j M_j
+// with the weighted currents Jw = sum coef_j J_j, Jv = sum coef_j J_j v_j:
+//   sum a_j J_j    = Jw S1 + S0 (Jw r - Jv)       S0 = int G, S1 = int G (r' - r)
+//   sum gphi_j J_j = 2 Jw Sg                      Sg = int grad G
+//   sum c_j M_j    = Mw Cg - Sg x Mv              Cg = int grad G x r'
+// so each source point's kernel value is computed once for all three halves.
+__device__ inline Z3 zcross3(Z3 a, Z3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ inline void tri_field(D3 r, const TriD *B, const cx<double> J[3], const cx<double> M[3], bool sing,
+                                 const StaticJ &st, double k, double Z, cx<double> E[3]) {
+  cx<double> Jw = {0, 0}, Mw = {0, 0};
+  Z3 Jv = {{0, 0}, {0, 0}, {0, 0}}, Mv = Jv;
+  for (int j = 0; j < 3; j++) {
+    const double cf = B->coef[j];
+    const D3 vj = tri_vertex(B, j, 0.0);
+    const cx<double> cj = J[j] * cf, cm = M[j] * cf;
+    Jw += cj;
+    Mw += cm;
+    Jv = zadd(Jv, zscale(cj, vj));
+    Mv = zadd(Mv, zscale(cm, vj));
+  }
+  cx<double> S0 = {0, 0};
+  Z3 S1 = {{0, 0}, {0, 0}, {0, 0}}, Sg = S1, Cg = S1;
+  for (int s = 0; s < NQ; s++) {
+    const D3 sp = tri_point(B, s, 0.0);
+    const double w = B->qw[s];
+    const D3 dv = r - sp;
+    const double R = sqrt(dotd(dv, dv));
+    cx<double> G = {0, 0}, dG = {0, 0};
+    if (R > 0 || sing) kernel_val(k, R, sing, G, dG);
+    Z3 grw = {{0, 0}, {0, 0}, {0, 0}};
+    if (R > 1e-14) grw = zscale(dG * (w / R), dv);
+    S0 += G * w;
+    S1 = zadd(S1, zscale(G * w, sp - r));
+    Sg = zadd(Sg, grw);
+    Cg = zadd(Cg, zcross(grw, sp));
+  }
+  // sum_j c_j M_j from the rule; the static part adds c4 Jg x (Mw r - Mv)
+  Z3 C = zadd({Cg.x * Mw, Cg.y * Mw, Cg.z * Mw}, zcross3(Mv, Sg));
+  if (sing) {
+    const double c4 = 1.0 / (4.0 * PI);
+    S0.x += c4 * st.J0;
+    S1.x.x += c4 * st.J1.x;
+    S1.y.x += c4 * st.J1.y;
+    S1.z.x += c4 * st.J1.z;
+    Sg.x.x += c4 * st.Jg.x;
+    Sg.y.x += c4 * st.Jg.y;
+    Sg.z.x += c4 * st.Jg.z;
+    const Z3 mr = {Mw * r.x - Mv.x, Mw * r.y - Mv.y, Mw * r.z - Mv.z};
+    const Z3 cs = zcross3({{st.Jg.x, 0}, {st.Jg.y, 0}, {st.Jg.z, 0}}, mr);
+    C = zadd(C, {cs.x * c4, cs.y * c4, cs.z * c4});
+  }
+  const Z3 Jr = {Jw * r.x - Jv.x, Jw * r.y - Jv.y, Jw * r.z - Jv.z};
+  const cx<double> ga[3] = {S1.x * Jw + S0 * Jr.x, S1.y * Jw + S0 * Jr.y, S1.z * Jw + S0 * Jr.z};
+  const cx<double> gs[3] = {Sg.x * Jw, Sg.y * Jw, Sg.z * Jw};
+  const cx<double> cc[3] = {C.x, C.y, C.z};
+  const double ik2 = 2.0 / (k * k);
+  for (int a = 0; a < 3; a++) {
+    cx<double> t = ga[a];
+    axpy(t, ik2, gs[a]);
+    E[a] = mul_j(t) * (-Z * k) - cc[a];
+  }
+}
+
+__global__ void __launch_bounds__(EF_THREADS)
+point_fields_exact_kernel(DevOperator<double> op, const TriD *__restrict__ tri, const int *__restrict__ list,
+                          double k_e, double Z_e, double k_i, double Z_i, double kappa, cx<double> *__restrict__ Ee,
+                          cx<double> *__restrict__ Ei) {
+  const int T = list[blockIdx.x / NQ], q = blockIdx.x % NQ;
+  const TriD *A = tri + T;
+  const D3 r = tri_point(A, q, 0.0);
+  const int body = op.tris[T].body;
+  cx<double> e[3] = {{0, 0}, {0, 0}, {0, 0}}, ii[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int S = threadIdx.x; S < op.nt; S += blockDim.x) {
+    const TriRec<double> tr = op.tris[S];
+    const TriD *B = tri + S;
+    const bool sing = singular_pair(A, 0.0, B, 0.0, kappa);
+    StaticJ st = {0, {0, 0, 0}, {0, 0, 0}};
+    if (sing) st = static_of(r, B, 0.0);
+    cx<double> Je[3], Ji[3], M[3], Mi[3], f[3];
+    for (int j = 0; j < 3; j++) {
+      const cx<double> *src = op.src + 3 * (size_t)tr.edge[j];
+      Je[j] = src[0];
+      Ji[j] = src[1];
+      M[j] = src[2];
+      Mi[j] = -src[2];
+    }
+    tri_field(r, B, Je, M, sing, st, k_e, Z_e, f);
+    for (int a = 0; a < 3; a++) e[a] += f[a];
+    if (tr.body == body) {
+      tri_field(r, B, Ji, Mi, sing, st, k_i, Z_i, f);
+      for (int a = 0; a < 3; a++) ii[a] += f[a];
+    }
+  }
+  __shared__ cx<double> red[EF_THREADS / 64][6];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = 0; a < 3; a++) {
+    e[a].x = wsum(e[a].x);
+    e[a].y = wsum(e[a].y);
+    ii[a].x = wsum(ii[a].x);
+    ii[a].y = wsum(ii[a].y);
+  }
+  if (lane == 0)
+    for (int a = 0; a < 3; a++) {
+      red[wv][a] = e[a];
+      red[wv][3 + a] = ii[a];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int p = T * NQ + q;
+    const PointRec<double> P = op.pts[p];
+    const TriRec<double> tr = op.tris[T];
+    cx<double> Mq[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int j = 0; j < 3; j++) {
+      const cx<double> Mj = op.src[3 * (size_t)tr.edge[j] + 2];
+      for (int a = 0; a < 3; a++) axpy(Mq[a], P.f[3 * j + a], Mj);
+    }
+    const double *n = tr.nrm;
+    const cx<double> hnM[3] = {(n[1] * Mq[2] - n[2] * Mq[1]) * 0.5, (n[2] * Mq[0] - n[0] * Mq[2]) * 0.5,
+                               (n[0] * Mq[1] - n[1] * Mq[0]) * 0.5};
+    const int a = threadIdx.x % 3;
+    cx<double> sum = {0, 0};
+    for (int w = 0; w < EF_THREADS / 64; w++) sum += red[w][threadIdx.x];
+    (threadIdx.x < 3 ? Ee : Ei)[3 * (size_t)p + a] = sum + hnM[a];
+  }
+}
+
+void launch_point_fields_exact(const DevOperator<double> &op, const TriD *tri, const int *list, int nlist,
+                               double k_e, double Z_e, double k_i, double Z_i, double kappa, cx<double> *Ee,
+                               cx<double> *Ei, hipStream_t s) {
+  if (nlist <= 0) return;
+  hipLaunchKernelGGL(point_fields_exact_kernel, dim3(nlist * NQ), dim3(EF_THREADS), 0, s, op, tri, list, k_e, Z_e,
+                     k_i, Z_i, kappa, Ee, Ei);
+}
+
 // Transpose of the E part: for weights wE (npts x 3) the per-point
 // coefficients of the half-RWG currents,
 //   J_j: w_p sum_t wE_t . (-Z jk (f_j G + k^-2 grad G div f_j))

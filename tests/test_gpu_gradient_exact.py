@@ -1,0 +1,162 @@
+"""Adjoint sigma gradient on block-Toeplitz contexts, whose product, transposed
+product and one-sided point fields at absorber points are the discrete
+Galerkin operator of Appendix A itself:
+
+* point fields at the points of absorber triangles against the dense
+  oracle's (same inner-integral rules), FP64 to 1e-10;
+* the full gradient of the reflected power at the monitor points with 256
+  piecewise-linear control values (differentiation form on a 4-long guide,
+  N = 2135) against the dense-oracle gradient (LU solves of A and A^T), to
+  1e-8 of its largest entry;
+* the differentiation form at full size (20-long guide, 4-long absorber, 256
+  control values seeded U[0, 2], N = 18,846): torch.autograd through the
+  library's adjoint against central differences on 16 seeded control
+  values, each difference two rebuilds and two FP64 solves to a relative
+  residual of 1e-12.  The reflected power is about 1e-7 (the reflected
+  amplitude some 3e-4 of the guided field), so differences at the step 1e-6
+  carry the solves' noise: about 0.5% of the largest gradient entry,
+  asserted at 5%; at the step 1e-3 noise and truncation error are both near
+  1e-5 of it, asserted at 1e-4."""
+import copy
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _ctx(w):
+    import paper_1004_5076_amd as pk
+    return pk.context_for(w, device=0, product=pk.SCABS_PRODUCT_TOEPLITZ)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.workload_gradient(guide_len=2.0, absorber=2.0, edge=0.15, n_ctrl=256, n_monitor=8)
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    A = o.dense()
+    ctx = _ctx(w)
+    assert ctx.info()["product"] == 1
+    print("gradient case N", ctx.N, flush=True)
+    return w, o, A, ctx
+
+
+def _absorber_points(o):
+    tri = np.repeat(np.arange(o.nt), oracle.NQ)
+    return (o.isR[o.tedge[tri]] != 0).any(axis=1)
+
+
+def test_exact_point_fields_match_dense_oracle(small):
+    import torch
+    w, o, A, ctx = small
+    x = synth.random_complex(91, o.N)
+    Ee, Ei = ctx.point_fields(torch.from_numpy(x).cuda())
+    Re, Ri = o.point_fields(x)
+    sel = _absorber_points(o)
+    assert sel.sum() > 0
+    for g, r in ((Ee.cpu().numpy(), Re), (Ei.cpu().numpy(), Ri)):
+        err = np.max(np.abs(g[sel] - r[sel])) / np.max(np.abs(r[sel]))
+        print("exact point fields rel", err, flush=True)
+        assert err < 1e-10
+
+
+def test_gradient_matches_dense_oracle(small):
+    """d |b|^2 / d ctrl, b the reflected amplitude fitted at the monitor
+    points; oracle: LU solves of the dense A and A^T, its exact point fields,
+    the chain rule through the hat interpolant."""
+    import torch
+    import paper_1004_5076_amd as pk
+    w, o, A, ctx = small
+    d = w.dipoles[0]
+    xs, beta = w.notes["monitor_x"], w.notes["beta"]
+    pts = np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], 1)
+    wts = oracle.monitor_weights(xs, beta)
+    # oracle
+    x_or = oracle.lu_solve(A, o.rhs_dipole(d))
+    Einc_m = np.array([oracle.dipole_field(o.k_i, o.Z_i, d.pos, d.moment, p)[0] for p in pts])
+    q = wts @ o.field_matrix(pts, 0).reshape(len(xs), 3, o.N)[:, 1, :]
+    bh = wts @ Einc_m[:, 1] + q @ x_or
+    g = np.conj(bh) * q
+    lam_or = oracle.lu_solve(A.T.copy(), g)
+    Ee, Ei = o.point_fields(x_or)
+    Einc, _ = o.incident_at_points(d)
+    grad_or = o.pwl_jacobian(w.sigma[0]).T @ o.sigma_gradient_points(lam_or, Ee, Ei, Einc)
+    # GPU: forward solve, adjoint right-hand side, one-call adjoint gradient
+    x, info = ctx.solve(ctx.rhs_dipole(d.pos, d.moment, d.body), tol=1e-12, restart=200, mode=pk.SCABS_FP64,
+                        max_iter=5000)
+    assert info["status"] == 0
+    assert _rel(x.cpu().numpy(), x_or) < 1e-9
+    wE = np.zeros((len(xs), 3), complex)
+    wE[:, 1] = wts
+    qg = ctx.eval_field_transpose(pts, 0, torch.from_numpy(wE).cuda())
+    E, _ = ctx.eval_field(x, pts, 0)
+    Ed, _ = ctx.dipole_field(d.pos, d.moment, d.body, pts, 0)
+    bh_g = (torch.from_numpy(wts).cuda() * (Ed[:, 1] + E[:, 1])).sum()
+    assert abs(bh_g.item() - bh) < 1e-9 * abs(bh)
+    gg = (torch.conj(bh_g) * qg).contiguous()
+    einc = ctx.incident_dipole_points(d.pos, d.moment, d.body)
+    dfs, grad, info = ctx.gradient(x, gg, einc, tol=1e-12, restart=200, max_iter=5000)
+    assert info["status"] == 0
+    scale = np.max(np.abs(grad_or))
+    err = np.max(np.abs(grad - grad_or)) / scale
+    print("gradient vs dense oracle: max rel", err, "nonzero controls", int((np.abs(grad_or) > 0).sum()), flush=True)
+    assert err < 1e-8
+
+
+def test_differentiation_form_full_size_central_differences():
+    import torch
+    import paper_1004_5076_amd as pk
+    w = synth.workload_gradient()          # 20 + 4 long guide, edge 0.1, 256 control values
+    end = w.sigma[0]
+    d = w.dipoles[0]
+    xs, beta = w.notes["monitor_x"], w.notes["beta"]
+    pts = np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], 1)
+    t0 = time.time()
+    ctx = _ctx(w)
+    print("full-size differentiation form N", ctx.N, "build", round(time.time() - t0, 2), "s", flush=True)
+    assert ctx.N == 18846
+    Ed, _ = ctx.dipole_field(d.pos, d.moment, d.body, pts, 0)
+    Einc_y = Ed[:, 1].contiguous()
+
+    def set_params(c, values):
+        e = copy.copy(end)
+        e.ctrl = np.asarray(values, float)
+        c.set_sigma([e])
+
+    def objective(params):
+        x = pk.sigma_solve(params, ctx, set_params, d, tol=1e-12, restart=300, mode=pk.SCABS_FP64)
+        E = pk.field_at(x, ctx, pts, 0)
+        return pk.reflected_amplitude(Einc_y + E[:, 1], xs, beta).abs() ** 2
+
+    p0 = torch.tensor(end.ctrl, dtype=torch.float64, requires_grad=True)
+    t0 = time.time()
+    f = objective(p0)
+    f.backward()
+    grad = p0.grad.numpy()
+    print("objective", f.item(), "forward + adjoint", round(time.time() - t0, 2), "s", flush=True)
+    scale = np.max(np.abs(grad))
+    rng = synth.SplitMix64(4242)
+    cand = [k for k in range(256) if end.ctrl[k] > 0.01]
+    ks = sorted({cand[int(rng.uniform_range(0.0, len(cand)))] for _ in range(40)})[:16]
+    assert len(ks) == 16
+    for dl, bound in ((1e-6, 5e-2), (1e-3, 1e-4)):
+        worst = 0.0
+        for k in ks:
+            pp, pm = end.ctrl.copy(), end.ctrl.copy()
+            pp[k] += dl
+            pm[k] -= dl
+            with torch.no_grad():
+                fd = (objective(torch.tensor(pp)).item() - objective(torch.tensor(pm)).item()) / (2 * dl)
+            worst = max(worst, abs(fd - grad[k]) / scale)
+            print(f"step {dl:g} control {k}: adjoint {grad[k]:.6e} central difference {fd:.6e}", flush=True)
+        print(f"step {dl:g}: worst |fd - adjoint| / max |adjoint| {worst:.3e}", flush=True)
+        assert worst < bound
