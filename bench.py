@@ -12,15 +12,16 @@ B = 8 seeded dipoles in channel 0 to relative residual 1e-6 (FP32 block-
 Toeplitz products inside GMRES, FP64 orthogonalisation and FP64 refinement
 residual, right Schwarz preconditioner), then, for dipole 0, the reflected
 amplitude at 16 monitor points on the channel axis, its adjoint (transposed)
-mixed solve and the sigma gradient (the transposed product is the lattice
-operator's).  value = operator products per second over the timed steps
-(forward and transposed, FP32 and FP64, all right-hand sides).
+mixed solve with the exact transposed block-Toeplitz product and the sigma
+gradient from the Galerkin matrix's own point fields.  value = operator
+products per second over the timed steps (forward and transposed, FP32 and
+FP64, all right-hand sides).
 
 Also reported: single-dipole mixed and FP64 solve times (the mixed/FP64
 comparison), standalone product rates (1 and 8 vectors), per-stage averages
 from HIP events (one extra untimed step with every stage recorded), the
-rooflines of the FP32 per-frequency block products, the FP32 Schwarz apply
-and the lattice kernels of the transposed products; "roofline" is the one
+rooflines of the FP32 per-frequency block products (forward and transposed)
+and the FP32 Schwarz apply; "roofline" is the one
 with the largest total, measured with HIP events on the library stream over
 the timed steps, during which only its stage records events; the oracle
 timed on the host; and the solution error against the dense Galerkin LU on a
@@ -54,7 +55,7 @@ def kernel_src_sha(name: str) -> str:
 ROOFLINE_KERNELS = {
     "toeapply32": ("toe_apply_mfma_kernel", "kernels_toeplitz.hip"),
     "precond": ("precond_apply32_mfma_kernel", "kernels_precond.hip"),
-    "xline32": ("xline_reg_kernel<float>", "kernels_fft.hip"),
+    "toeapplyt32": ("toe_t_apply_kernel<float>", "kernels_toeplitz_t.hip"),
 }
 
 
@@ -364,8 +365,8 @@ def main():
         log("extras", extras)
 
     # rooflines of the kernels with the largest shares of the step (the FP32
-    # per-frequency block products, the FP32 Schwarz apply, the lattice
-    # kernels of the transposed products): "roofline" is the one with the
+    # per-frequency block products, forward and transposed, the FP32 Schwarz
+    # apply): "roofline" is the one with the
     # largest total, measured over the timed steps; "rooflines" all of them
     # from the profiled step
     roofs = {k: roofline(full, k) for k in ROOFLINE_KERNELS}

@@ -196,10 +196,15 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
                 int mode, scabs_solve_info *info);
 
 /* Transposed system (adjoint method).  y = A^T x, same argument rules as
- * scabs_matvec; the lattice convolution is symmetric, so the transpose runs
- * the testing and projection steps in reverse (test-side sources with value
- * and derivative stencil weights, convolution, values read at the source
- * points) and the near correction through the mirrored pair entries. */
+ * scabs_matvec (nrhs vectors are applied one at a time).  Precorrected-FFT
+ * context: the lattice convolution is symmetric, so the transpose runs the
+ * testing and projection steps in reverse (test-side sources with value and
+ * derivative stencil weights, convolution, values read at the source points)
+ * and the near correction through the mirrored pair entries.  Block-Toeplitz
+ * context (fast-solver appendix): the exact transpose of the Galerkin matrix,
+ * the ring-circulant blocks taken at frequency -f and contracted over the
+ * row index, the local and sigma-point terms transposed per triangle, and
+ * the stored entries of non-periodic edges read by column. */
 int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, int prec);
 
 /* Solve A^T x = b; arguments and precision modes as scabs_solve (the right
@@ -298,9 +303,14 @@ int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double
  * exterior-medium field of J_e, M_e) and Ei = E_i^- (interior limit of the
  * interior-medium field of J_i, M_i, without the incident field), each
  * n_points * 3 complex on the device.  These are the fields the sigma-weighted
- * tests of eq13 (rotated by n x) and eq14 integrate (Appendix A).  Exact at
- * the points of triangles carrying an absorber edge; elsewhere the near-pair
- * correction is omitted. */
+ * tests of eq13 (rotated by n x) and eq14 integrate (Appendix A), for the
+ * context's operator.  Precorrected-FFT context: the lattice operator's,
+ * exact at the points of triangles carrying an absorber edge (elsewhere the
+ * near-pair correction is omitted).  Block-Toeplitz context: the Galerkin
+ * matrix's own at the points of triangles carrying an absorber edge -- on
+ * periodic triangles the two in-plane components (the ones the sigma tests
+ * read; normal component 0), on the others full vectors by direct summation
+ * over every source triangle -- and 0 at all other points. */
 int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei);
 
 /* Scattered fields at off-surface points pts (host, npts * 3) from currents x
@@ -452,7 +462,12 @@ int scabs_gradient(scabs_ctx *c, const double *x, const double *g, const double 
 #define SCABS_STAGE_TOEPRODUCT32 18 /* the whole block-Toeplitz product, FP32 (spans the
                                        records of its parts) */
 #define SCABS_STAGE_TOEPRODUCT64 19 /* the same in FP64 */
-#define SCABS_NSTAGES 20
+#define SCABS_STAGE_TOEAPPLYT32 20 /* transposed block-Toeplitz product, FP32: the
+                                      per-frequency transposed block products (its
+                                      transforms are recorded as those of the forward
+                                      product) */
+#define SCABS_STAGE_TOEAPPLYT64 21 /* the same in FP64 */
+#define SCABS_NSTAGES 22
 int scabs_profile_begin(scabs_ctx *c);
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count);
 /* Restrict the stages that profiling sessions record to those whose bit
@@ -471,8 +486,9 @@ int scabs_profile_mask(scabs_ctx *c, uint32_t mask);
  * applied, per unknown its index and FP64 outputs;
  * SCABS_STAGE_PCGATHER32: per extended-set entry its index, its column scale,
  * the FP64 inputs read and the FP32 copies written;
- * SCABS_STAGE_TOEAPPLY32/64: every entry of the spectrum tables read once, the
- * input spectra read and the output spectra written once;
+ * SCABS_STAGE_TOEAPPLY32/64 and SCABS_STAGE_TOEAPPLYT32/64: every entry of
+ * the spectrum tables read once, the input spectra read and the output
+ * spectra written once;
  * SCABS_STAGE_TOEPRODUCT32/64: the spectrum tables and the stored entries of
  * the non-periodic pairs that the product uses read once (the absorber test
  * records only on absorber rows), the input and output vectors read and

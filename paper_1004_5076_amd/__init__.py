@@ -33,7 +33,7 @@ EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_cl
             "scabs_decay_fit", "scabs_poynting_decay", "scabs_solve_batched", "scabs_autotune", "scabs_set_tune"]
 STAGES = ["unpack64", "project64", "fft64", "interp64", "near64", "unpack32", "project32", "fft32", "interp32",
           "near32", "precond", "ortho", "precond_t", "xline32", "gather32", "pcgather32", "toeapply32", "toeapply64",
-          "toeproduct32", "toeproduct64"]
+          "toeproduct32", "toeproduct64", "toeapplyt32", "toeapplyt64"]
 
 
 class ScabsError(RuntimeError):

@@ -211,14 +211,17 @@ struct scabs_ctx {
   cx<float> *toe_V4f = nullptr, *toe_S4f = nullptr;
   int64_t toe_nshort = 0;
   const int *toe_capcol = nullptr, *toe_esgn = nullptr;
+  const unsigned char *toe_eflag = nullptr;   // per edge: bit 0 periodic, bit 1 absorber
   cx<double> *toe_tri64 = nullptr;
   cx<float> *toe_tri32 = nullptr;
   // transposed product: circulant, long and short column parts per precision
   cx<float> *toe_tcol32 = nullptr, *toe_lcol32 = nullptr, *toe_scol32 = nullptr;
   cx<double> *toe_tcol64 = nullptr, *toe_lcol64 = nullptr, *toe_scol64 = nullptr;
   int *toe_capidx = nullptr;   // per edge its non-periodic index, -1 for periodic edges
-  int *toe_abs_tri = nullptr;  // triangles carrying an absorber edge (exact point fields)
-  int toe_nabs = 0;
+  // exact point fields: triangles carrying an absorber edge (periodic ones,
+  // the others) and the triangles of non-periodic edge halves (mask of halves)
+  int *toe_abs_per = nullptr, *toe_abs_np = nullptr, *toe_np_tri = nullptr, *toe_np_mask = nullptr;
+  int toe_nabs_per = 0, toe_nabs_np = 0, toe_nnp = 0;
   double toe_table_bytes[2] = {0, 0};   // per-frequency tables of one product (FP64, FP32)
   double toe_sparse_bytes[2] = {0, 0};  // stored non-periodic entries one product reads (FP64, FP32)
   // launch choices of the product for fewer than 8 and for 8 vectors:
@@ -922,19 +925,35 @@ static std::string build_toeplitz(scabs_ctx *c) {
     std::vector<int> capidx(g.ne, -1);
     for (size_t j = 0; j < nonper.size(); j++) capidx[nonper[j]] = (int)j;
     c->toe_capidx = c->mem.upload(capidx);
-    std::vector<int> abs_tri;
-    for (int T = 0; T < g.nt; T++)
-      if (c->lay.isR[g.tedge[3 * T]] || c->lay.isR[g.tedge[3 * T + 1]] || c->lay.isR[g.tedge[3 * T + 2]])
-        abs_tri.push_back(T);
-    c->toe_nabs = (int)abs_tri.size();
-    c->toe_abs_tri = abs_tri.empty() ? nullptr : c->mem.upload(abs_tri);
+    std::vector<int> abs_per, abs_np, np_tri, np_mask;
+    for (int T = 0; T < g.nt; T++) {
+      const int *te = g.tedge.data() + 3 * T;
+      if (c->lay.isR[te[0]] || c->lay.isR[te[1]] || c->lay.isR[te[2]])
+        (rt.tri_loc[T] >= 0 ? abs_per : abs_np).push_back(T);
+      int mask = 0;
+      for (int k = 0; k < 3; k++) mask |= (rt.edge_loc[te[k]] < 0) << k;
+      if (mask) {
+        np_tri.push_back(T);
+        np_mask.push_back(mask);
+      }
+    }
+    c->toe_nabs_per = (int)abs_per.size();
+    c->toe_nabs_np = (int)abs_np.size();
+    c->toe_nnp = (int)np_tri.size();
+    c->toe_abs_per = abs_per.empty() ? nullptr : c->mem.upload(abs_per);
+    c->toe_abs_np = abs_np.empty() ? nullptr : c->mem.upload(abs_np);
+    c->toe_np_tri = np_tri.empty() ? nullptr : c->mem.upload(np_tri);
+    c->toe_np_mask = np_mask.empty() ? nullptr : c->mem.upload(np_mask);
     const size_t nc = std::max<size_t>(1, nonper.size());
     c->toe_tcol32 = c->mem.alloc<cx<float>>(4 * (size_t)g.ne);
     c->toe_lcol32 = c->mem.alloc<cx<float>>(3 * (size_t)g.ne);
-    c->toe_scol32 = c->mem.alloc<cx<float>>(3 * nc);
+    c->toe_scol32 = c->mem.alloc<cx<float>>(3 * nc * TOE_T_SHORT_SPLIT);
     c->toe_tcol64 = c->mem.alloc<cx<double>>(4 * (size_t)g.ne);
     c->toe_lcol64 = c->mem.alloc<cx<double>>(3 * (size_t)g.ne);
-    c->toe_scol64 = c->mem.alloc<cx<double>>(3 * nc);
+    c->toe_scol64 = c->mem.alloc<cx<double>>(3 * nc * TOE_T_SHORT_SPLIT);
+    std::vector<unsigned char> ef(g.ne);
+    for (int n = 0; n < g.ne; n++) ef[n] = (unsigned char)((rt.edge_sgn[n] != 0) | ((c->lay.isR[n] != 0) << 1));
+    c->toe_eflag = c->mem.upload(ef);
   }
   c->toe_esgn = esgn_dev;
   c->toe_nnz = nnz;
@@ -1368,6 +1387,7 @@ template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
   R.nchunk = (c->geo.ne + toe_long_chunk() - 1) / toe_long_chunk();
   R.capcol = c->toe_capcol;
   R.edge_sgn = c->toe_esgn;
+  R.eflag = c->toe_eflag;
   R.V4S = V4;
   R.S4S = S4;
   R.V4L = V4 + 4 * (size_t)c->toe_nshort;
@@ -1403,7 +1423,11 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
     launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_FWD);
   }
   {
-    StageTimer t(c, f32 ? SCABS_STAGE_TOEAPPLY32 : SCABS_STAGE_TOEAPPLY64);
+    // every spectrum table entry read once, the row spectra (2 ne_r + 4 NQ
+    // nt_r lines) read and the column spectra (4 ne_r lines) written once
+    const double spectra = (double)sizeof(cx<T>) * d.P * (6.0 * d.ne_r + 4.0 * NQ * d.nt_r);
+    StageTimer t(c, f32 ? SCABS_STAGE_TOEAPPLYT32 : SCABS_STAGE_TOEAPPLYT64,
+                 c->toe_table_bytes[f32 ? 1 : 0] + spectra);
     launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_APPLY);
   }
   {
@@ -2372,6 +2396,27 @@ int scabs_incident_source_points(scabs_ctx *c, const scabs_source *src, double *
 static void point_fields(scabs_ctx *c, const double *x, cx<double> *Ee, cx<double> *Ei) {
   PrecState<double> &P = c->p64;
   hipStream_t s = c->stream;
+  if (c->toe) {
+    // the block-Toeplitz operator is the Galerkin matrix itself, and its sigma
+    // tests read the exact fields at the absorber triangles' points: on
+    // periodic triangles the tangential fields of the product's own point
+    // lines (periodic sources) plus the non-periodic edges' halves, on the
+    // others a direct sum over every source triangle; zero elsewhere
+    const size_t np = (size_t)P.op.np;
+    HIPCHK(hipMemsetAsync(Ee, 0, 3 * np * sizeof(cx<double>), s));
+    HIPCHK(hipMemsetAsync(Ei, 0, 3 * np * sizeof(cx<double>), s));
+    DevMem tmp;
+    double *y = tmp.alloc<double>(2 * (size_t)c->lay.N);
+    apply_toe(c, c->p64, c->t64, c->toe_tri64, x, y, 1);
+    launch_toe_point_fields(P.op, c->t64, c->trid, c->toe_abs_per, c->toe_nabs_per, c->toe_np_tri, c->toe_np_mask,
+                            c->toe_nnp, c->k_e, c->Z_e, c->k_i, c->Z_i, c->opts.kappa_s, Ee, Ei, s);
+    launch_point_fields_exact(P.op, c->trid, c->toe_abs_np, c->toe_nabs_np, c->k_e, c->Z_e, c->k_i, c->Z_i,
+                              c->opts.kappa_s, Ee, Ei, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    tmp.release();
+    return;
+  }
   launch_unpack(P.op, x, s);
   launch_project(P.op, P.grids, P.gather, s);
   for (const DevGrid<double> &g : P.grids) launch_conv(g, s);
@@ -2381,11 +2426,6 @@ static void point_fields(scabs_ctx *c, const double *x, cx<double> *Ee, cx<doubl
   a.Ee = Ee;
   a.Ei = Ei;
   launch_near_point_fields(a, s);
-  // the block-Toeplitz operator is the Galerkin matrix itself: its sigma tests
-  // read the exact fields, summed directly at the absorber triangles' points
-  if (c->toe)
-    launch_point_fields_exact(P.op, c->trid, c->toe_abs_tri, c->toe_nabs, c->k_e, c->Z_e, c->k_i, c->Z_i,
-                              c->opts.kappa_s, Ee, Ei, s);
   HIPCHK(hipGetLastError());
 }
 

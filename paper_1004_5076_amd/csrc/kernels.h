@@ -279,6 +279,13 @@ template <typename T> struct ToeDev {
   int lines;                       // ring-axis lines per transform work-group (<= toe_max_lines)
   int apply_form;                  // 8 FP32 vectors: 0 matrix cores, 1 vector ALUs
 };
+
+// block-Toeplitz contexts: tangential fields at points of periodic absorber
+// triangles from the product's point lines (pf of the last FP64 product of
+// x) plus the non-periodic edges' halves summed directly and the residue
+void launch_toe_point_fields(const DevOperator<double> &op, const ToeDev<double> &d, const TriD *tri, const int *list,
+                             int nlist, const int *np_tri, const int *np_mask, int nnp, double k_e, double Z_e,
+                             double k_i, double Z_i, double kappa, cx<double> *Ee, cx<double> *Ei, hipStream_t s);
 // exact entries of the pairs with a non-periodic edge, column-major: short
 // part V4S/S4S[(j ne + n) 4 + t] (row n, non-periodic column capcol[j]),
 // long part V4L/S4L[(m nlong + i) 4 + t] (non-periodic row capcol[i],
@@ -288,6 +295,7 @@ template <typename T> struct ToeRows {
   int ncap, nlong, nchunk;
   const int *capcol;      // the non-periodic edges
   const int *edge_sgn;    // per edge: 0 for non-periodic edges
+  const unsigned char *eflag;   // per edge: bit 0 periodic, bit 1 absorber (R) edge
   const cx<T> *V4S, *S4S, *V4L, *S4L;
   T *part;                // [chunk][row][vector][6] partial sums of the long rows
   T *rpart;               // [group][vector][6][edge] partial sums of the periodic rows
@@ -321,7 +329,9 @@ __device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR
 }
 // transposed block-Toeplitz product of one vector (rows z unpacked into
 // op.src): circulant columns tcol[e][4], long-part columns lcol[e][3],
-// short-part columns scol[j][3] (capidx: edge -> non-periodic index or -1)
+// short-part partial columns scol[j][TOE_T_SHORT_SPLIT][3] (capidx: edge ->
+// non-periodic index or -1)
+constexpr int TOE_T_SHORT_SPLIT = 16;
 template <typename T>
 void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const ToeRows<T> &R, cx<T> *tcol,
                           cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts);

@@ -1054,6 +1054,97 @@ void launch_point_fields_exact(const DevOperator<double> &op, const TriD *tri, c
                      k_i, Z_i, kappa, Ee, Ei);
 }
 
+// Block-Toeplitz contexts, points of periodic absorber triangles: the
+// product's own point lines hold the tangential principal-value fields of
+// every periodic edge's currents there (pf, template tangents t1, t2); the
+// half functions of the non-periodic edges (listed per triangle with a mask of
+// their local halves) are summed directly with the same inner integrals, and
+// the residue 1/2 n x M is added.  The point lines carry the two in-plane
+// components only (all the sigma tests read); the normal component of what
+// Ee / Ei hold is kept.  One wave per point.
+__global__ void __launch_bounds__(64)
+toe_point_fields_kernel(DevOperator<double> op, ToeDev<double> d, const TriD *__restrict__ tri,
+                        const int *__restrict__ list, const int *__restrict__ np_tri, const int *__restrict__ np_mask,
+                        int nnp, double k_e, double Z_e, double k_i, double Z_i, double kappa,
+                        cx<double> *__restrict__ Ee, cx<double> *__restrict__ Ei) {
+  const int T = list[blockIdx.x / NQ], q = blockIdx.x % NQ;
+  const TriD *A = tri + T;
+  const D3 r = tri_point(A, q, 0.0);
+  const int body = op.tris[T].body;
+  cx<double> e[3] = {{0, 0}, {0, 0}, {0, 0}}, ii[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int i = threadIdx.x; i < nnp; i += 64) {
+    const int S = np_tri[i], mask = np_mask[i];
+    const TriRec<double> tr = op.tris[S];
+    const TriD *B = tri + S;
+    const bool sing = singular_pair(A, 0.0, B, 0.0, kappa);
+    StaticJ st = {0, {0, 0, 0}, {0, 0, 0}};
+    if (sing) st = static_of(r, B, 0.0);
+    cx<double> Je[3], Ji[3], M[3], Mi[3], f[3];
+    for (int j = 0; j < 3; j++) {
+      const cx<double> *src = op.src + 3 * (size_t)tr.edge[j];
+      const bool on = (mask >> j) & 1;
+      Je[j] = on ? src[0] : cx<double>{0, 0};
+      Ji[j] = on ? src[1] : cx<double>{0, 0};
+      M[j] = on ? src[2] : cx<double>{0, 0};
+      Mi[j] = -M[j];
+    }
+    tri_field(r, B, Je, M, sing, st, k_e, Z_e, f);
+    for (int a = 0; a < 3; a++) e[a] += f[a];
+    if (tr.body == body) {
+      tri_field(r, B, Ji, Mi, sing, st, k_i, Z_i, f);
+      for (int a = 0; a < 3; a++) ii[a] += f[a];
+    }
+  }
+  for (int a = 0; a < 3; a++) {
+    e[a].x = wsum(e[a].x);
+    e[a].y = wsum(e[a].y);
+    ii[a].x = wsum(ii[a].x);
+    ii[a].y = wsum(ii[a].y);
+  }
+  if (threadIdx.x != 0) return;
+  const int p = T * NQ + q;
+  const PointRec<double> P = op.pts[p];
+  const TriRec<double> tr = op.tris[T];
+  cx<double> Mq[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int j = 0; j < 3; j++) {
+    const cx<double> Mj = op.src[3 * (size_t)tr.edge[j] + 2];
+    for (int a = 0; a < 3; a++) axpy(Mq[a], P.f[3 * j + a], Mj);
+  }
+  const double *n = tr.nrm;
+  const cx<double> hnM[3] = {(n[1] * Mq[2] - n[2] * Mq[1]) * 0.5, (n[2] * Mq[0] - n[0] * Mq[2]) * 0.5,
+                             (n[0] * Mq[1] - n[1] * Mq[0]) * 0.5};
+  const int lt = d.tri_loc[T], j = d.tri_ring[T], nr = d.nr;
+  const size_t R2 = 2 * (size_t)NQ * d.nt_r, row = 2 * ((size_t)lt * NQ + q);
+  const cx<double> *pe = d.pf + row * nr + j, *pi = pe + R2 * nr;
+  const double *t1 = d.t1 + 3 * (size_t)lt, *t2 = d.t2 + 3 * (size_t)lt;
+  for (int side = 0; side < 2; side++) {
+    const cx<double> *pv = side == 0 ? pe : pi;
+    const cx<double> *dir = side == 0 ? e : ii;
+    cx<double> *dst = (side == 0 ? Ee : Ei) + 3 * (size_t)p;
+    cx<double> dn = dir[0] * n[0], ln = dst[0] * n[0];
+    axpy(dn, n[1], dir[1]);
+    axpy(dn, n[2], dir[2]);
+    axpy(ln, n[1], dst[1]);
+    axpy(ln, n[2], dst[2]);
+    cx<double> out[3];
+    for (int a = 0; a < 3; a++) {
+      cx<double> v = pv[0] * t1[a] + pv[nr] * t2[a] + hnM[a] + dir[a];
+      axpy(v, -n[a], dn);    // tangential part of the direct sum
+      axpy(v, n[a], ln);     // normal component kept
+      out[a] = v;
+    }
+    for (int a = 0; a < 3; a++) dst[a] = out[a];
+  }
+}
+
+void launch_toe_point_fields(const DevOperator<double> &op, const ToeDev<double> &d, const TriD *tri, const int *list,
+                             int nlist, const int *np_tri, const int *np_mask, int nnp, double k_e, double Z_e,
+                             double k_i, double Z_i, double kappa, cx<double> *Ee, cx<double> *Ei, hipStream_t s) {
+  if (nlist <= 0) return;
+  hipLaunchKernelGGL(toe_point_fields_kernel, dim3(nlist * NQ), dim3(64), 0, s, op, d, tri, list, np_tri, np_mask, nnp,
+                     k_e, Z_e, k_i, Z_i, kappa, Ee, Ei);
+}
+
 // Transpose of the E part: for weights wE (npts x 3) the per-point
 // coefficients of the half-RWG currents,
 //   J_j: w_p sum_t wE_t . (-Z jk (f_j G + k^-2 grad G div f_j))

@@ -271,18 +271,21 @@ __device__ inline void col_mac(const RowCoef<T> &c, cx<T> zE, cx<T> zH, cx<T> zQ
   cmac(o.m, c.rM, zQ);
 }
 
-// short part transposed: one work-group per non-periodic column j, threads
-// over the periodic rows n; scol[j] = (J_e', J_i', M')
+// short part transposed: work-group (non-periodic column j, row chunk s),
+// threads over the chunk's periodic rows n; the chunk's partial (J_e', J_i',
+// M') goes to scol[j][s], summed in a fixed order by the combine kernel
 template <typename T>
 __global__ void __launch_bounds__(256) toe_t_short_kernel(DevOperator<T> op, ToeRows<T> R, cx<T> *__restrict__ scol) {
-  const int j = blockIdx.x;
+  const int j = blockIdx.x, sp = blockIdx.y;
+  const int chunk = (op.ne + TOE_T_SHORT_SPLIT - 1) / TOE_T_SHORT_SPLIT;
+  const int n0 = sp * chunk, n1 = min(op.ne, n0 + chunk);
   const T Ze = op.Z_e, Zi = op.Z_i;
   ColAcc<T> o = {czero<T>(), czero<T>(), czero<T>()};
-  for (int n = threadIdx.x; n < op.ne; n += blockDim.x) {
-    if (R.edge_sgn[n] == 0) continue;
-    const EdgeRec r = op.edges[n];
+  for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    const int fl = R.eflag[n];
+    if (!(fl & 1)) continue;   // non-periodic rows are in the long part
     const size_t k = ((size_t)j * op.ne + n) * 4;
-    const RowCoef<T> c = row_coef(R.V4S + k, R.S4S + k, r.isR != 0, Ze, Zi);
+    const RowCoef<T> c = row_coef(R.V4S + k, R.S4S + k, (fl & 2) != 0, Ze, Zi);
     col_mac(c, op.src[3 * n], op.src[3 * n + 1], op.src[3 * n + 2], o);
   }
   __shared__ T red[6][4];
@@ -298,27 +301,30 @@ __global__ void __launch_bounds__(256) toe_t_short_kernel(DevOperator<T> op, Toe
   if (threadIdx.x < 6) {
     T t = 0;
     for (int q = 0; q < (int)(blockDim.x >> 6); q++) t += red[threadIdx.x][q];
-    reinterpret_cast<T *>(scol + (size_t)j * 3)[threadIdx.x] = t;
+    reinterpret_cast<T *>(scol + ((size_t)j * TOE_T_SHORT_SPLIT + sp) * 3)[threadIdx.x] = t;
   }
 }
 
-// long part transposed: one thread per column m, over the non-periodic rows
+// long part transposed: one wave per column m, lanes over the non-periodic
+// rows (a column's records are contiguous), then a wave sum
 template <typename T>
 __global__ void __launch_bounds__(256) toe_t_long_kernel(DevOperator<T> op, ToeRows<T> R, cx<T> *__restrict__ lcol) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= op.ne) return;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= op.ne) return;   // wave-uniform
   const T Ze = op.Z_e, Zi = op.Z_i;
   ColAcc<T> o = {czero<T>(), czero<T>(), czero<T>()};
-  for (int i = 0; i < R.nlong; i++) {
+  for (int i = lane; i < R.nlong; i += 64) {
     const int n = R.capcol[i];
-    const EdgeRec r = op.edges[n];
     const size_t k = ((size_t)m * R.nlong + i) * 4;
-    const RowCoef<T> c = row_coef(R.V4L + k, R.S4L + k, r.isR != 0, Ze, Zi);
+    const RowCoef<T> c = row_coef(R.V4L + k, R.S4L + k, (R.eflag[n] & 2) != 0, Ze, Zi);
     col_mac(c, op.src[3 * n], op.src[3 * n + 1], op.src[3 * n + 2], o);
   }
-  lcol[(size_t)m * 3] = o.je;
-  lcol[(size_t)m * 3 + 1] = o.ji;
-  lcol[(size_t)m * 3 + 2] = o.m;
+  T v[6] = {o.je.x, o.je.y, o.ji.x, o.ji.y, o.m.x, o.m.y};
+#pragma unroll
+  for (int k = 0; k < 6; k++)
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v[k] += __shfl_xor(v[k], s, 64);
+  if (lane < 6) reinterpret_cast<T *>(lcol + (size_t)m * 3)[lane] = v[lane];
 }
 
 // per edge: the circulant columns (periodic edges), the long and short parts
@@ -338,11 +344,13 @@ toe_t_combine_kernel(DevOperator<T> op, ToeRows<T> R, const cx<T> *__restrict__ 
     ji += tcol[(size_t)e * 4 + 2];
   }
   const int ci = capidx[e];
-  if (ci >= 0) {
-    je += scol[(size_t)ci * 3];
-    ji += scol[(size_t)ci * 3 + 1];
-    m += scol[(size_t)ci * 3 + 2];
-  }
+  if (ci >= 0)
+    for (int sp = 0; sp < TOE_T_SHORT_SPLIT; sp++) {
+      const cx<T> *sc = scol + ((size_t)ci * TOE_T_SHORT_SPLIT + sp) * 3;
+      je += sc[0];
+      ji += sc[1];
+      m += sc[2];
+    }
   for (int s = 0; s < 2; s++) {
     const cx<T> *h = op.tri_out + ((size_t)r.tri[s] * 3 + r.loc[s]) * 3;
     je += h[0];
@@ -379,8 +387,8 @@ void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const To
     hipLaunchKernelGGL(toe_t_inv_kernel<T>, dim3((ncol + G - 1) / G), dim3(TT_THREADS),
                        tt_launch_lds(toe_t_inv_kernel<T>, tt_lds<T>(d.P, G)), s, d, tcol);
     if (R.ncap > 0)
-      hipLaunchKernelGGL(toe_t_short_kernel<T>, dim3(R.ncap), dim3(256), 0, s, op, R, scol);
-    hipLaunchKernelGGL(toe_t_long_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R, lcol);
+      hipLaunchKernelGGL(toe_t_short_kernel<T>, dim3(R.ncap, TOE_T_SHORT_SPLIT), dim3(256), 0, s, op, R, scol);
+    hipLaunchKernelGGL(toe_t_long_kernel<T>, dim3((op.ne + 3) / 4), dim3(256), 0, s, op, R, lcol);
     hipLaunchKernelGGL(toe_t_combine_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R,
                        (const cx<T> *)tcol, (const cx<T> *)lcol, (const cx<T> *)scol, capidx, y);
   }

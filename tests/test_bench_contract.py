@@ -20,8 +20,8 @@ def test_more_than_one_gpu_is_refused():
 
 def test_roofline_from_stage_records():
     import bench
-    prof = {"xline32": {"ms": 6.0, "count": 3, "bytes": 3 * 160e6}}
-    r = bench.roofline(prof, "xline32")
+    prof = {"toeapply32": {"ms": 6.0, "count": 3, "bytes": 3 * 160e6}}
+    r = bench.roofline(prof, "toeapply32")
     assert abs(r["avg_launch_us"] - 2000.0) < 1e-9
     assert abs(r["bytes_per_launch"] - 160e6) < 1e-3
     assert abs(r["achieved"] - 160e6 / 2e-3 / 1e9) < 1e-9   # GB/s

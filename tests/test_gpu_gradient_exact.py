@@ -2,8 +2,11 @@
 product and one-sided point fields at absorber points are the discrete
 Galerkin operator of Appendix A itself:
 
-* point fields at the points of absorber triangles against the dense
-  oracle's (same inner-integral rules), FP64 to 1e-10;
+* tangential point fields (the components the sigma tests read) at the
+  points of absorber triangles against the dense oracle's (same
+  inner-integral rules), FP64 to 1e-10: periodic triangles from the
+  product's point lines plus the non-periodic edges' halves, the end caps by
+  direct summation;
 * the full gradient of the reflected power at the monitor points with 256
   piecewise-linear control values (differentiation form on a 4-long guide,
   N = 2135) against the dense-oracle gradient (LU solves of A and A^T), to
@@ -63,10 +66,25 @@ def test_exact_point_fields_match_dense_oracle(small):
     Re, Ri = o.point_fields(x)
     sel = _absorber_points(o)
     assert sel.sum() > 0
+    n = np.repeat(o.nrm, oracle.NQ, axis=0)[sel]
+
+    def tangential(E):
+        return E - np.einsum("pa,pa->p", E, n)[:, None] * n
+
     for g, r in ((Ee.cpu().numpy(), Re), (Ei.cpu().numpy(), Ri)):
-        err = np.max(np.abs(g[sel] - r[sel])) / np.max(np.abs(r[sel]))
-        print("exact point fields rel", err, flush=True)
+        gt, rt = tangential(g[sel]), tangential(r[sel])
+        err = np.max(np.abs(gt - rt)) / np.max(np.abs(rt))
+        print("exact tangential point fields rel", err, flush=True)
         assert err < 1e-10
+        # the end cap's points (non-periodic triangles) carry full vectors,
+        # the periodic ones none in the normal direction, other points none
+        gn = np.abs(np.einsum("pa,pa->p", g[sel], n))
+        cap = gn > 0
+        assert 0 < cap.sum() < sel.sum()
+        err = np.max(np.abs(g[sel][cap] - r[sel][cap])) / np.max(np.abs(r[sel][cap]))
+        print("end-cap full vectors rel", err, "points", int(cap.sum()), flush=True)
+        assert err < 1e-10
+        assert not np.any(g[~sel])
 
 
 def test_gradient_matches_dense_oracle(small):
