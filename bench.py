@@ -238,8 +238,9 @@ def main():
     d0 = w.dipoles[0]
 
     if args.products_only:
-        # the roofline kernels alone, for counter runs: batched FP32 products
-        # and one GMRES step of the batch (one FP32 Schwarz apply to 8 vectors)
+        # the roofline kernels alone, for counter runs: batched FP32 products,
+        # single-vector transposed FP32 products and one GMRES step of the
+        # batch (one FP32 Schwarz apply to 8 vectors)
         X = torch.from_numpy(np.stack([synth.random_complex(3 + k, N) for k in range(BATCH)])).to(dev)
         b = ctx.rhs_dipole(d0.pos, d0.moment, d0.body)
         bb = torch.stack([b] * BATCH).contiguous()
@@ -248,6 +249,8 @@ def main():
         ctx.profile_begin()
         for _ in range(args.products_only):
             ctx.matvec(X, prec=pk.SCABS_FP32)
+        for _ in range(args.products_only):
+            ctx.matvec(X[0], prec=pk.SCABS_FP32, transpose=True)
         for _ in range(args.products_only):
             ctx.solve(bb, tol=0.5, max_iter=1, restart=1, mode=pk.SCABS_MIXED)
         prof = ctx.profile_end()
