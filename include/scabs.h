@@ -212,6 +212,18 @@ int scabs_matvec_transpose(scabs_ctx *c, const double *x, double *y, int nrhs, i
 int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, int max_iter, int restart,
                           int mode, scabs_solve_info *info);
 
+/* HIP graphs in the Krylov solves (on by default).  Every Arnoldi step
+ * launches the same sequence (preconditioner, then product, on nb vectors):
+ * the first step of a shape (vectors, precision, transpose) runs it as usual
+ * and captures it into a graph, later steps copy the step's basis vectors
+ * into a staging buffer the graph reads and replay it (one launch instead of
+ * one per kernel).  Results are the same bit for bit either way.  Graphs are
+ * dropped whenever a buffer they read is reallocated (larger batches, a new
+ * restart length), at scabs_build and at tuning changes; a shape whose capture
+ * the runtime refuses keeps the ordinary launches.  Not used while stage
+ * profiling is on.  on = 0 turns them off and frees them. */
+int scabs_set_graphs(scabs_ctx *c, int on);
+
 /* Autotuner of the block-Toeplitz product (contexts built with
  * SCABS_PRODUCT_TOEPLITZ; SCABS_E_STATE otherwise).  Launch choices, kept
  * per context separately for products of fewer than 8 vectors (class 0) and

@@ -23,7 +23,7 @@ SCABS_OK = 0
 SCABS_E_ARG, SCABS_E_MESH, SCABS_E_STATE, SCABS_E_HIP, SCABS_E_OOM, SCABS_E_NOCONV, SCABS_E_NAN = -1, -2, -3, -4, -5, -6, -7
 SCABS_FP64, SCABS_FP32, SCABS_MIXED = 0, 1, 2
 SCABS_PRODUCT_PFFT, SCABS_PRODUCT_TOEPLITZ = 0, 1
-EXPORTED = ["scabs_create", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
+EXPORTED = ["scabs_create", "scabs_set_graphs", "scabs_set_mesh", "scabs_set_media", "scabs_sigma_clear", "scabs_sigma_add_monomial",
             "scabs_sigma_add_pwl", "scabs_set_sigma_points", "scabs_build", "scabs_info", "scabs_layout", "scabs_rhs_dipole", "scabs_matvec",
             "scabs_solve", "scabs_matvec_transpose", "scabs_solve_transpose", "scabs_precond_apply", "scabs_incident_dipole_points",
             "scabs_point_fields", "scabs_eval_field", "scabs_eval_field_noalloc", "scabs_dipole_field", "scabs_gradient", "scabs_eval_field_transpose", "scabs_sigma_params",
@@ -157,6 +157,7 @@ def load() -> C.CDLL:
                                       C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(C.POINTER(SolveInfo))]
     L.scabs_autotune.argtypes = [P, C.c_int, C.POINTER(TuneRecord), C.c_int, C.POINTER(C.c_int)]
     L.scabs_set_tune.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.scabs_set_graphs.argtypes = [P, C.c_int]
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
     _lib = L
@@ -365,6 +366,10 @@ class Context:
         n = C.c_int(0)
         self._check(self._L.scabs_autotune(self._c, int(reps), recs, 64, C.byref(n)))
         return [recs[i].as_dict() for i in range(min(n.value, 64))]
+
+    def set_graphs(self, on: bool):
+        """scabs_set_graphs: replay each Arnoldi step's launches from a HIP graph."""
+        self._check(self._L.scabs_set_graphs(self._c, int(bool(on))))
 
     def set_tune(self, nrhs_class: int, form: int, groups: int, lines: int):
         self._check(self._L.scabs_set_tune(self._c, int(nrhs_class), int(form), int(groups), int(lines)))

@@ -25,6 +25,7 @@ void kr_update(cx<double> *w, const cx<VT> *V, int64_t ldv, int jn, const cx<dou
 void kr_norm(const cx<double> *w, int64_t N, double *part, double *out, hipStream_t s);
 template <typename VT> void kr_scale(cx<VT> *dst, const cx<double> *src, const double *nrm, int64_t N, hipStream_t s);
 void kr_widen(const cx<float> *src, cx<double> *dst, int64_t n, hipStream_t s);
+void kr_zero(void *p, size_t bytes, hipStream_t s);
 template <typename VT>
 void kr_ortho_pass(const cx<VT> *V, int64_t ldv, int jn, cx<double> *w, int64_t N, const KrRun &run, int with_norm,
                    cx<double> *part, double *npart, cx<double> *hcol, int64_t hstride, int64_t hoff,
@@ -170,6 +171,18 @@ struct scabs_ctx {
   int64_t work_N = -1;
   cx<double> *w = nullptr, *r = nullptr, *d = nullptr, *hcol = nullptr, *part = nullptr;
   cx<double> *z = nullptr, *t = nullptr;
+  // HIP graphs of an Arnoldi step's preconditioner + product launches, one
+  // per (vectors, precision, basis precision, transpose), captured on first
+  // use and replayed every step; the step's basis vector is copied into
+  // gstage first (the graph reads fixed addresses).  Dropped whenever a
+  // buffer they read is reallocated, at a rebuild and at a tuning change.
+  struct StepGraph {
+    hipGraphExec_t exec;
+    int nb, prec, vt, trans;
+  };
+  std::vector<StepGraph> step_graphs;
+  bool graphs_on = true;
+  cx<double> *gstage = nullptr;
   // Krylov bases: FP64 for FP64 solves, FP32 for the single-precision inner
   // solves of the mixed mode (each grown on demand)
   DevMem workV64, workV32;
@@ -232,6 +245,15 @@ struct scabs_ctx {
   double *toe_part64 = nullptr, *toe_rpart64 = nullptr;
   float *toe_part32 = nullptr, *toe_rpart32 = nullptr;
 };
+
+// drop the captured Arnoldi-step graphs (before any buffer they read goes)
+static void clear_graphs(scabs_ctx *c) {
+  if (c->step_graphs.empty()) return;
+  (void)hipStreamSynchronize(c->stream);   // none of them may still be running
+  for (auto &g : c->step_graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  c->step_graphs.clear();
+}
 
 // RAII stage timer: records a start/end event pair on the context stream
 struct StageTimer {
@@ -992,6 +1014,7 @@ static std::string build_toeplitz(scabs_ctx *c) {
 template <typename T> static void toe_ensure(scabs_ctx *c, ToeDev<T> &d, cx<T> *&tri_out, int nb) {
   const int cap = sizeof(T) == sizeof(float) ? (c->toe_bcap & 0xffff) : (c->toe_bcap >> 16);
   if (nb <= cap) return;
+  clear_graphs(c);
   const Geometry &g = c->geo;
   if (d.X) {
     c->mem.free_one(d.X);
@@ -1036,6 +1059,7 @@ static int do_build(scabs_ctx *c) {
   if (c->opts.precond >= SCABS_PRECOND_PAPER && c->opts.product != SCABS_PRODUCT_TOEPLITZ)
     return fail(c, SCABS_E_ARG, "the circulant preconditioner needs the block-Toeplitz product");
   if (c->opts.precond < 0 || c->opts.precond > SCABS_PRECOND_CIRC_SCHWARZ) return fail(c, SCABS_E_ARG, "unknown precond");
+  clear_graphs(c);
   c->mem.release();
   // every device buffer of the last build is gone: forget the per-vector
   // buffers the products grow on demand, so that growing them never frees an
@@ -1262,6 +1286,7 @@ static int do_build(scabs_ctx *c) {
 // Grow the per-vector buffers of one precision to hold nb vectors.
 template <typename T> static void ensure_batch(scabs_ctx *c, PrecState<T> &P, int nb) {
   if (nb <= P.bcap) return;
+  clear_graphs(c);
   const Geometry &g = c->geo;
   c->mem.free_one(P.src);
   c->mem.free_one(P.tri_out);
@@ -1415,8 +1440,9 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
   {
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
     launch_unpack_rows(op, z, s);
-    // point weights are written only at periodic triangles' points
-    HIPCHK(hipMemsetAsync(d.pf, 0, sizeof(cx<T>) * 2 * 2 * (size_t)NQ * d.nt_r * d.nr, s));
+    // point weights are written only at periodic triangles' points (a fill
+    // kernel: this sequence may be captured into a graph)
+    kr_zero(d.pf, sizeof(cx<T>) * 2 * 2 * (size_t)NQ * d.nt_r * d.nr, s);
   }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
@@ -1625,12 +1651,14 @@ constexpr size_t KR_NRM = KR_MAX_SYSTEMS + 2;
 static void ensure_work(scabs_ctx *c, int restart, int nb) {
   int64_t N = c->lay.N;
   if (c->work_restart >= restart && c->work_N == N && c->work_nb >= nb) return;
+  clear_graphs(c);
   c->work.release();
   c->w = c->work.alloc<cx<double>>(N * nb);
   c->r = c->work.alloc<cx<double>>(N * nb);
   c->d = c->work.alloc<cx<double>>(N * nb);
   c->z = c->work.alloc<cx<double>>(N * nb);
   c->t = c->work.alloc<cx<double>>(N * nb);
+  c->gstage = c->work.alloc<cx<double>>(N * nb);
   const size_t hentries = KR_NRM + 2 * (size_t)(restart + 2) * nb;
   c->hblock = c->work.alloc<cx<double>>(hentries);
   c->nrm = reinterpret_cast<double *>(c->hblock);
@@ -1701,6 +1729,67 @@ static const cx<double> *operator_input(scabs_ctx *c, const cx<float> *v, int64_
   return c->t;
 }
 
+// w = A M v for the nb basis vectors at v (the launches of one Arnoldi step
+// between its host synchronisations)
+template <typename VT>
+static void step_sequence(scabs_ctx *c, const cx<VT> *v, int nb, int prec, bool trans) {
+  if (c->has_pc) {
+    // the preconditioner's gathers read the basis vectors in their own
+    // precision (no widened copy)
+    apply_precond_n(c, v, c->z, nb, trans, prec);
+    matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
+  } else {
+    const cx<double> *vj = operator_input(c, v, (int64_t)c->lay.N * nb);
+    matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
+  }
+}
+
+// The step sequence from a HIP graph: the basis vectors are copied into the
+// staging buffer the graph reads, then the graph replays the launches.  The
+// first use of a shape runs the sequence eagerly (it grows any per-vector
+// buffers), then captures it (thread-local mode: other threads of a batched
+// solve keep launching).  Not while stage profiling records events.
+template <typename VT>
+static void step_product(scabs_ctx *c, const cx<VT> *v, int nb, int prec, bool trans) {
+  if (!c->graphs_on || c->prof_on) {
+    step_sequence(c, v, nb, prec, trans);
+    return;
+  }
+  hipStream_t s = c->stream;
+  const int vt = sizeof(VT) == sizeof(float);
+  const scabs_ctx::StepGraph *hit = nullptr;
+  for (const auto &g : c->step_graphs)
+    if (g.nb == nb && g.prec == prec && g.vt == vt && g.trans == (int)trans) hit = &g;
+  if (hit && !hit->exec) {   // this shape could not be captured: launches as usual
+    step_sequence(c, v, nb, prec, trans);
+    return;
+  }
+  cx<VT> *stage = reinterpret_cast<cx<VT> *>(c->gstage);
+  HIPCHK(hipMemcpyAsync(stage, v, sizeof(cx<VT>) * (size_t)c->lay.N * nb, hipMemcpyDeviceToDevice, s));
+  if (hit) {
+    HIPCHK(hipGraphLaunch(hit->exec, s));
+    return;
+  }
+  step_sequence(c, (const cx<VT> *)stage, nb, prec, trans);   // this step's product, eagerly
+  // capture: nothing runs while the stream records, so a failure here can
+  // only be the capture's; the shape then keeps the ordinary launches
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    bool ok = true;
+    try {
+      step_sequence(c, (const cx<VT> *)stage, nb, prec, trans);
+    } catch (...) {
+      ok = false;
+    }
+    hipGraph_t graph = nullptr;
+    ok = hipStreamEndCapture(s, &graph) == hipSuccess && ok && graph;
+    if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  if (!exec) (void)hipGetLastError();
+  c->step_graphs.push_back({exec, nb, prec, vt, (int)trans});
+}
+
 // ---------------------------------------------------------------------------
 // GMRES on a batch of right-hand sides (restarted; classical Gram-Schmidt
 // with a second pass where the first lost more than 1 - 1/sqrt(2) of the
@@ -1755,17 +1844,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
     int j = 0;
     // w = A M v_j for every vector of the batch (the batched stages take all
     // nb vectors; only the orthogonalisation is restricted to running systems)
-    auto enqueue_product = [&](int jj) {
-      if (c->has_pc) {
-        // the preconditioner's gathers read the basis vectors in their own
-        // precision (no widened copy)
-        apply_precond_n(c, V + (size_t)jj * ldv, c->z, nb, trans, prec);
-        matvec_n(c, (const double *)c->z, (double *)c->w, nb, prec, trans);
-      } else {
-        const cx<double> *vj = operator_input(c, V + (size_t)jj * ldv, ldv);
-        matvec_n(c, (const double *)vj, (double *)c->w, nb, prec, trans);
-      }
-    };
+    auto enqueue_product = [&](int jj) { step_product(c, V + (size_t)jj * ldv, nb, prec, trans); };
     // the product of step j is already in the stream (enqueued during step
     // j - 1, before the host's Givens update; unused if the cycle ends there)
     bool pending = false;
@@ -2266,11 +2345,23 @@ static int check_tune(scabs_ctx *c, int form, int groups, int lines) {
   return SCABS_OK;
 }
 
+int scabs_set_graphs(scabs_ctx *c, int on) {
+  if (!c) return SCABS_E_ARG;
+  try {
+    HIPCHK(hipSetDevice(c->opts.device));
+    clear_graphs(c);
+    c->graphs_on = on != 0;
+  }
+  SCABS_CATCH(c)
+  return SCABS_OK;
+}
+
 int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines) {
   if (!c) return SCABS_E_ARG;
   if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "needs a built block-Toeplitz context");
   if (nrhs_class != 0 && nrhs_class != 1) return fail(c, SCABS_E_ARG, "nrhs_class must be 0 (< 8) or 1 (8)");
   if (int st = check_tune(c, form, groups, lines)) return st;
+  clear_graphs(c);
   c->toe_tune[nrhs_class][0] = form;
   c->toe_tune[nrhs_class][1] = groups;
   c->toe_tune[nrhs_class][2] = lines;
@@ -2280,6 +2371,7 @@ int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines
 int scabs_autotune(scabs_ctx *c, int reps, scabs_tune_record *rec, int max_rec, int *n_rec) {
   if (!c || reps < 1 || max_rec < 0 || (max_rec > 0 && !rec)) return SCABS_E_ARG;
   if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "autotuning applies to a built block-Toeplitz context");
+  clear_graphs(c);
   try {
     const size_t stride = 2 * (size_t)c->lay.N;
     DevMem tmp;
@@ -2799,6 +2891,7 @@ void scabs_destroy(scabs_ctx *c) {
   if (!c) return;
   hipSetDevice(c->opts.device);
   if (c->stream) hipStreamSynchronize(c->stream);
+  clear_graphs(c);
   c->work.release();
   c->workV64.release();
   c->workV32.release();

@@ -387,6 +387,15 @@ template void kr_scale_run<float>(cx<float> *, const cx<double> *, const double 
 template void kr_scale_run<double>(cx<double> *, const cx<double> *, const double *, int64_t, const KrRun &,
                                    hipStream_t);
 
+// zero fill by a kernel (unlike a memset node it may sit in a captured graph)
+__global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+void kr_zero(void *p, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / sizeof(uint32_t));
+  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(reduce_blocks(n)), dim3(KR_THREADS), 0, s, (uint32_t *)p, n);
+}
 void kr_widen(const cx<float> *src, cx<double> *dst, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(widen_kernel, dim3(reduce_blocks(n)), dim3(KR_THREADS), 0, s, src, dst, n);
 }
