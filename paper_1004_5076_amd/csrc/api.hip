@@ -1420,6 +1420,7 @@ template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
   R.part = toe_part(c, (T *)nullptr);
   R.rpart = toe_rpart(c, (T *)nullptr);
   R.groups = 8;
+  R.sparse_form = 0;
   return R;
 }
 
@@ -1478,6 +1479,7 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
     const int lmax = toe_max_lines(d.P, f32);
     d.apply_form = tn[0];
     R.groups = std::max(1, std::min(tn[1], toe_row_groups()));
+    R.sparse_form = tn[0];   // the 8-vector sparse rows follow the block products' form
     d.lines = tn[2] > 0 ? std::min(tn[2], lmax) : lmax;
   }
   // algorithmic bytes: per-frequency tables, stored sparse entries, the

@@ -300,6 +300,7 @@ template <typename T> struct ToeRows {
   T *part;                // [chunk][row][vector][6] partial sums of the long rows
   T *rpart;               // [group][vector][6][edge] partial sums of the periodic rows
   int groups;             // column groups of the periodic rows (<= toe_row_groups())
+  int sparse_form;        // 8 FP32 vectors: 0 matrix cores, 1 vector ALUs
 };
 // coefficients of (J_i, J_e, M) in the E, H and eq14 rows from one entry's
 // 8 tested values (sigma values on absorber rows only)

@@ -1059,6 +1059,201 @@ __global__ void __launch_bounds__(256) toe_long_kernel(DevOperator<T> op, ToeRow
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sparse rows of 8 FP32 vectors on the matrix cores.  A stored pair holds
+// two 16-byte records {L_e, K_e}, {L_i, K_i} (on absorber rows two more, the
+// sigma tests' {L_r, K_r}, {L_s, K_s}); with the column's currents the row
+// sums (the coefficients of row_coef) are
+//   E = L_e (-Z_e J_e) + K_e M + L_i (Z_i J_i) + K_i M
+//   H = L_e (-M / Z_e) + K_e (-J_e) + L_i (-M / Z_i) + K_i J_i
+//       [+ L_r (-Z_e J_e) + K_r M]
+//   Q = [L_s (Z_i J_i) + K_s M]
+// As in the block products, lane (i, kq) loads the records of row i, column
+// 4 g + kq, MFMA step j takes slot j of a record and the B entries are the
+// real forms of the scaled currents (output column n: vector n / 2, real
+// part for even n); lane (n, kq) ends with rows 4 kq + r of column n.
+// ---------------------------------------------------------------------------
+struct SpForms {
+  float e1[4], h1[4], e2[4], h2[4], h3[4], q4[4];
+};
+__device__ inline void sp_forms(const cx<float> *cm, float Ze, float Zi, bool odd, SpForms &b) {
+  const cx<float> Je = cm[0], Ji = cm[1], M = cm[2];
+  const cx<float> a = Je * (-Ze), mz = M * (-1.f / Ze), ci = Ji * Zi, mi = M * (-1.f / Zi), nJe = -Je;
+#pragma unroll
+  for (int j = 0; j < 2; j++) {
+    b.e1[j] = mf_form(a, j, odd);
+    b.e1[j + 2] = mf_form(M, j, odd);
+    b.h1[j] = mf_form(mz, j, odd);
+    b.h1[j + 2] = mf_form(nJe, j, odd);
+    b.e2[j] = mf_form(ci, j, odd);
+    b.e2[j + 2] = mf_form(M, j, odd);
+    b.h2[j] = mf_form(mi, j, odd);
+    b.h2[j + 2] = mf_form(Ji, j, odd);
+    b.h3[j] = b.e1[j];
+    b.h3[j + 2] = b.e1[j + 2];
+    b.q4[j] = b.e2[j];
+    b.q4[j + 2] = b.e2[j + 2];
+  }
+}
+// one 16-row tile's records of one column: r[0..1] always, r[2..3] on absorber rows
+struct SpRec {
+  tf4 r[4];
+};
+__device__ inline void sp_load(const cx<float> *V4, const cx<float> *S4, size_t k, bool live, bool isR, bool withR,
+                               SpRec &o) {
+  const tf4 z = {0.f, 0.f, 0.f, 0.f};
+  o.r[0] = live ? *reinterpret_cast<const tf4 *>(V4 + k) : z;
+  o.r[1] = live ? *reinterpret_cast<const tf4 *>(V4 + k + 2) : z;
+  if (withR) {   // wave-uniform
+    o.r[2] = isR ? *reinterpret_cast<const tf4 *>(S4 + k) : z;
+    o.r[3] = isR ? *reinterpret_cast<const tf4 *>(S4 + k + 2) : z;
+  }
+}
+__device__ inline void sp_mfma(const SpRec &a, const SpForms &b, bool withR, tf4 &E, tf4 &H, tf4 &Q) {
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    E = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r[0][j], b.e1[j], E, 0, 0, 0);
+    H = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r[0][j], b.h1[j], H, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r[1][j], b.e2[j], E, 0, 0, 0);
+    H = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r[1][j], b.h2[j], H, 0, 0, 0);
+  }
+  if (withR) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      H = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r[2][j], b.h3[j], H, 0, 0, 0);
+      Q = __builtin_amdgcn_mfma_f32_16x16x4f32(a.r[3][j], b.q4[j], Q, 0, 0, 0);
+    }
+  }
+}
+
+// periodic rows against the non-periodic columns of group g: one wave per
+// 16-row tile, the group's column currents in LDS (dynamic, [column][v][3]);
+// partial sums rpart[g][v][6][row] as toe_rows_part_kernel writes them
+__global__ void __launch_bounds__(256) toe_rows_part_mfma_kernel(DevOperator<float> op, ToeRows<float> R) {
+  constexpr int NB = 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);
+  const int g = blockIdx.y;
+  const int j0 = (R.ncap * g) / R.groups, j1 = (R.ncap * (g + 1)) / R.groups, nj = j1 - j0;
+  for (int i = threadIdx.x; i < nj * NB * 3; i += blockDim.x) {
+    const int jj = i / (NB * 3);
+    xs[i] = op.srcI[(size_t)R.capcol[j0 + jj] * NB * 3 + (i - jj * NB * 3)];
+  }
+  __syncthreads();
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (16 * tile >= op.ne) return;   // wave-uniform
+  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+  const int n = 16 * tile + m;
+  const int fl = n < op.ne ? R.eflag[n] : 0;
+  const bool live = (fl & 1) != 0, isR = live && (fl & 2) != 0;
+  const bool withR = __ballot(isR) != 0;
+  const float Ze = op.Z_e, Zi = op.Z_i;
+  const int cv = m >> 1;
+  const bool odd = (m & 1) != 0;
+  tf4 E = {0.f, 0.f, 0.f, 0.f}, H = E, Q = E;
+  const int nq = (nj + 3) >> 2;
+  const size_t rowk = (size_t)(live ? n : 0) * 4;
+  SpRec cur{}, nxt{};
+  {
+    const bool cok = kq < nj;
+    sp_load(R.V4S, R.S4S, (size_t)(j0 + (cok ? kq : 0)) * op.ne * 4 + rowk, live && cok, isR && cok, withR, cur);
+  }
+  for (int q = 0; q < nq; q++) {
+    const int jj = 4 * q + kq;
+    if (q + 1 < nq) {   // next column group's records first
+      const int jn = jj + 4;
+      const bool cok = jn < nj;
+      sp_load(R.V4S, R.S4S, (size_t)(j0 + (cok ? jn : 0)) * op.ne * 4 + rowk, live && cok, isR && cok, withR, nxt);
+    }
+    SpForms b;
+    sp_forms(xs + ((size_t)(jj < nj ? jj : 0) * NB + cv) * 3, Ze, Zi, odd, b);
+    sp_mfma(cur, b, withR, E, H, Q);
+    cur = nxt;
+  }
+  float *p = R.rpart + (size_t)((g * NB + cv) * 6 + (odd ? 1 : 0)) * op.ne;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const int nr = 16 * tile + 4 * kq + r;
+    if (nr < op.ne) {
+      p[nr] = E[r];
+      p[2 * (size_t)op.ne + nr] = H[r];
+      p[4 * (size_t)op.ne + nr] = Q[r];
+    }
+  }
+}
+
+// long rows: one work-group per chunk of TOE_LCH columns (their currents in
+// LDS); each wave takes TOE_SP_TILES row tiles at a time and walks the
+// chunk's column groups, the next group's records loaded before the current
+// group's products, the B entries shared by its tiles; partial sums per
+// (chunk, row, vector) as toe_long_kernel writes them
+constexpr int TOE_SP_TILES = 2;
+__global__ void __launch_bounds__(256) toe_long_mfma_kernel(DevOperator<float> op, ToeRows<float> R) {
+  constexpr int NB = 8;
+  __shared__ cx<float> xs[TOE_LCH * NB * 3];
+  const int ch = blockIdx.x, c0 = ch * TOE_LCH, nc = min(TOE_LCH, op.ne - c0);
+  for (int i = threadIdx.x; i < nc * NB * 3; i += blockDim.x) xs[i] = op.srcI[(size_t)c0 * NB * 3 + i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+  const int cv = m >> 1;
+  const bool odd = (m & 1) != 0;
+  const float Ze = op.Z_e, Zi = op.Z_i;
+  const int ntile = (R.nlong + 15) / 16, nq = (nc + 3) >> 2;
+  for (int t0 = wave * TOE_SP_TILES; t0 < ntile; t0 += 4 * TOE_SP_TILES) {
+    bool live[TOE_SP_TILES], isR[TOE_SP_TILES], withR[TOE_SP_TILES];
+    size_t rowk[TOE_SP_TILES];
+    tf4 E[TOE_SP_TILES], H[TOE_SP_TILES], Q[TOE_SP_TILES];
+#pragma unroll
+    for (int u = 0; u < TOE_SP_TILES; u++) {
+      const int i = 16 * (t0 + u) + m;
+      live[u] = t0 + u < ntile && i < R.nlong;
+      isR[u] = live[u] && (R.eflag[R.capcol[live[u] ? i : 0]] & 2) != 0;
+      withR[u] = __ballot(isR[u]) != 0;
+      rowk[u] = (size_t)(live[u] ? i : 0) * 4;
+      E[u] = tf4{0.f, 0.f, 0.f, 0.f};
+      H[u] = E[u];
+      Q[u] = E[u];
+    }
+    SpRec a[TOE_SP_TILES], an[TOE_SP_TILES];
+    {
+      const bool cok = kq < nc;
+      const size_t ck = (size_t)(c0 + (cok ? kq : 0)) * R.nlong * 4;
+#pragma unroll
+      for (int u = 0; u < TOE_SP_TILES; u++)
+        sp_load(R.V4L, R.S4L, ck + rowk[u], live[u] && cok, isR[u] && cok, withR[u], a[u]);
+    }
+    for (int q = 0; q < nq; q++) {
+      const int col = 4 * q + kq;
+      if (q + 1 < nq) {
+        const bool cok = col + 4 < nc;
+        const size_t ck = (size_t)(c0 + (cok ? col + 4 : 0)) * R.nlong * 4;
+#pragma unroll
+        for (int u = 0; u < TOE_SP_TILES; u++)
+          sp_load(R.V4L, R.S4L, ck + rowk[u], live[u] && cok, isR[u] && cok, withR[u], an[u]);
+      }
+      SpForms b;
+      sp_forms(xs + ((size_t)(col < nc ? col : 0) * NB + cv) * 3, Ze, Zi, odd, b);
+#pragma unroll
+      for (int u = 0; u < TOE_SP_TILES; u++) {
+        sp_mfma(a[u], b, withR[u], E[u], H[u], Q[u]);
+        a[u] = an[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TOE_SP_TILES; u++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = 16 * (t0 + u) + 4 * kq + r;
+        if (t0 + u < ntile && i < R.nlong) {
+          float *p = R.part + (((size_t)ch * R.nlong + i) * NB + cv) * 6 + (odd ? 1 : 0);
+          p[0] = E[u][r];
+          p[2] = H[u][r];
+          p[4] = Q[u][r];
+        }
+      }
+  }
+}
+
 // long rows += sum over chunks: one wave per (row, vector), lanes over chunks
 template <typename T>
 __global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeRows<T> R, double *y, int nb) {
@@ -1086,6 +1281,20 @@ __global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeRows<T> R, double *
 
 template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb) {
   const int nchunk = (op.ne + TOE_LCH - 1) / TOE_LCH;
+  // 8 FP32 vectors: both sparse parts on the matrix cores (the group's column
+  // currents must fit the LDS)
+  const size_t sp_lds = sizeof(cx<float>) * 8 * 3 * (size_t)((R.ncap + R.groups - 1) / R.groups + 1);
+  if (sizeof(T) == sizeof(float) && nb == 8 && R.sparse_form == 0 && sp_lds <= 65536) {
+    const DevOperator<float> &of = *reinterpret_cast<const DevOperator<float> *>(&op);
+    const ToeRows<float> &rf = *reinterpret_cast<const ToeRows<float> *>(&R);
+    if (R.nlong > 0) hipLaunchKernelGGL(toe_long_mfma_kernel, dim3(nchunk), dim3(256), 0, s, of, rf);
+    hipLaunchKernelGGL(toe_rows_part_mfma_kernel, dim3((op.ne + 63) / 64, R.groups), dim3(256), sp_lds, s, of, rf);
+    hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R, y, nb);
+    if (R.nlong > 0)
+      hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((R.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, R, y,
+                         nb);
+    return;
+  }
 #define SCABS_TOE_ROWS(NB)                                                                                           \
   do {                                                                                                               \
     if (R.nlong > 0) hipLaunchKernelGGL((toe_long_kernel<T, NB>), dim3(nchunk), dim3(256), 0, s, op, R);              \
