@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
 
 // The same products for 8 vectors on the matrix cores
 // (v_mfma_f32_16x16x4_f32, complex arithmetic in real form).  One wave per
-// 16-row tile of one frequency, four tiles per work-group sharing the input
+// 16-row tile of one frequency, 16 tiles per work-group sharing the input
 // spectra in LDS.  A tile row's table record for source column c is four
 // floats ({L re, L im, K re, K im} or {PJ re, PJ im, PM re, PM im}); lane
 // (i, kq) loads the whole record of row i, column 4 g + kq (one 16-byte load
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
 // medium's enter with the opposite sign.  Lane (n, kq) ends with rows
 // 4 kq + r of column n.
 typedef float tf4 __attribute__((ext_vector_type(4)));
-constexpr int TOE_MF_WAVES = 4;
+constexpr int TOE_MF_WAVES = 16;
 constexpr int TOE_MF_DEPTH = 4;   // 16-byte table loads per lane per chunk (two chunks in flight)
 
 // real-form B entry of slot j for a lane of output column n (odd: imaginary)
@@ -971,14 +971,14 @@ __global__ void __launch_bounds__(256) toe_rows_part_kernel(DevOperator<T> op, T
   }
 }
 
-// one thread per edge row: the groups' partial sums, the local terms of its
-// two halves and the periodic sums; writes the rows
+// one thread per (edge row, vector): the groups' partial sums, the local
+// terms of its two halves and the periodic sums; writes the rows
 template <typename T>
 __global__ void __launch_bounds__(256) toe_rows_kernel(DevOperator<T> op, ToeRows<T> R, double *__restrict__ y, int nb) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
   if (n >= op.ne) return;
   const EdgeRec r = op.edges[n];
-  for (int b = 0; b < nb; b++) {
+  {
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int g = 0; g < R.groups; g++) {
       const T *p = R.rpart + ((size_t)(g * nb + b) * 6) * op.ne + n;
@@ -1289,7 +1289,7 @@ template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRo
     const ToeRows<float> &rf = *reinterpret_cast<const ToeRows<float> *>(&R);
     if (R.nlong > 0) hipLaunchKernelGGL(toe_long_mfma_kernel, dim3(nchunk), dim3(256), 0, s, of, rf);
     hipLaunchKernelGGL(toe_rows_part_mfma_kernel, dim3((op.ne + 63) / 64, R.groups), dim3(256), sp_lds, s, of, rf);
-    hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R, y, nb);
+    hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op, R, y, nb);
     if (R.nlong > 0)
       hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((R.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, R, y,
                          nb);
@@ -1311,7 +1311,7 @@ template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRo
     default: SCABS_TOE_ROWS(8); break;
   }
 #undef SCABS_TOE_ROWS
-  hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256), dim3(256), 0, s, op, R, y, nb);
+  hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op, R, y, nb);
   if (R.nlong > 0)
     hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((R.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, R, y, nb);
 }
