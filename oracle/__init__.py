@@ -83,6 +83,7 @@ def lib():
         L.or_static_integrals.argtypes = [dp, dp, dp, dp, dp, dp, dp]
         L.or_dense.restype = C.c_int
         L.or_dense.argtypes = [P, zp]
+        L.or_dense_rows.argtypes = [P, C.c_int, ip, zp]
         L.or_local_coo.restype = C.c_long
         L.or_local_coo.argtypes = [P, ip, ip, zp, C.c_long]
         L.or_dipole_field.argtypes = [C.c_double, C.c_double, dp, zp, dp, zp, zp]
@@ -246,6 +247,16 @@ class Oracle:
         if rc:
             raise RuntimeError(lib().or_error(self._c).decode())
         return A
+
+    def dense_rows(self, rows) -> np.ndarray:
+        """Rows of the dense Galerkin matrix (eq19) without assembling the rest:
+        the pairs whose test triangle carries one of the rows' edges."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        out = np.zeros((len(rows), self.N), complex)
+        rc = lib().or_dense_rows(self._c, len(rows), rows, out.ravel())
+        if rc < 0:
+            raise RuntimeError(lib().or_error(self._c).decode())
+        return out
 
     def local_coo(self):
         cap = 64 * self.ne + 64

@@ -537,9 +537,13 @@ void or_pair_blocks_exact(const Ctx *c, int T, int Tp, double k, Blocks *b) {
 /* stamping into the unknown/row layout                                */
 /* ------------------------------------------------------------------ */
 /* sink: dense (row-major N x N) or a triplet list */
-typedef struct { zc *dense; int N; int *ri, *ci; zc *val; long cap, cnt; } Sink;
+typedef struct { zc *dense; int N; int *ri, *ci; zc *val; long cap, cnt; const int *rmap; } Sink;
 static inline void sink_add(Sink *s, int r, int col, zc v) {
   if (v == 0) return;
+  if (s->rmap) {   /* selected rows only: row r goes to block row rmap[r] */
+    if (s->rmap[r] < 0) return;
+    r = s->rmap[r];
+  }
   if (s->dense) {
     double *p = (double *)&s->dense[(size_t)r * s->N + col];
 #pragma omp atomic
@@ -672,6 +676,43 @@ int or_dense(Ctx *c, zc *A) {
   }
   for (int T = 0; T < c->nt; T++) stamp_local(c, T, &s);
   return 0;
+}
+
+/* Selected rows of the dense Galerkin matrix (eq19), assembled exactly as
+ * or_dense assembles them but only from the pairs whose test triangle carries
+ * one of the rows' edges: out[k][N] = A[rows[k]][:] (row-major, nrows x N). */
+int or_dense_rows(Ctx *c, int nrows, const int *rows, zc *out) {
+  if (!c->isR) { set_err(c, "layout not built"); return -1; }
+  int *rmap = malloc(sizeof(int) * c->N);
+  for (int r = 0; r < c->N; r++) rmap[r] = -1;
+  for (int k = 0; k < nrows; k++) {
+    if (rows[k] < 0 || rows[k] >= c->N) { free(rmap); set_err(c, "row out of range"); return -1; }
+    rmap[rows[k]] = k;
+  }
+  memset(out, 0, sizeof(zc) * (size_t)nrows * c->N);
+  Sink s = {out, c->N, NULL, NULL, NULL, 0, 0, rmap};
+  /* triangles testing a selected row */
+  int *sel = calloc(c->nt, sizeof(int));
+  for (int T = 0; T < c->nt; T++)
+    for (int i = 0; i < 3; i++) {
+      int rE, rH, r14; edge_slots(c, c->tedge[3 * T + i], &rE, &rH, &r14);
+      if (rmap[rE] >= 0 || rmap[rH] >= 0 || (r14 >= 0 && rmap[r14] >= 0)) sel[T] = 1;
+    }
+  for (int T = 0; T < c->nt; T++) {
+    if (!sel[T]) continue;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int Tp = 0; Tp < c->nt; Tp++) {
+      Blocks be, bi;
+      or_pair_blocks_exact(c, T, Tp, c->k_e, &be);
+      int same = c->body[T] == c->body[Tp];
+      if (same) or_pair_blocks_exact(c, T, Tp, c->k_i, &bi);
+      stamp_pair(c, T, Tp, &be, same ? &bi : NULL, 1.0, &s);
+    }
+    stamp_local(c, T, &s);
+  }
+  free(sel);
+  free(rmap);
+  return nrows;
 }
 
 /* local terms only, as triplets (used by the pFFT operator) */

@@ -434,3 +434,20 @@ def test_gmres_dense_matches_lu():
     x_g = oracle.gmres_dense(A, b, tol=1e-11)
     assert np.linalg.norm(A @ x_g - b) < 2e-11 * np.linalg.norm(b)
     assert np.linalg.norm(x_g - x_lu) < 1e-7 * np.linalg.norm(x_lu)
+
+
+def test_dense_rows_equal_dense_matrix_rows():
+    """or_dense_rows (the pairs of the selected rows' test triangles only)
+    against the full dense assembly on the 4-long guide: E, H and eq14 rows
+    of sigma-free and absorber edges, in a scrambled order."""
+    w = synth.workload_small()
+    o = oracle.Oracle(w.mesh, w.omega, w.eps_in)
+    o.set_sigma(w.sigma)
+    A = o.dense()
+    rE, rH, r14 = o.edge_rows()
+    ls = np.nonzero(o.isR == 0)[0][[3, 100]]
+    rs = np.nonzero(o.isR != 0)[0][[5, 200]]
+    rows = np.array([rH[ls[1]], rE[ls[0]], r14[rs[0]], rE[rs[1]], rH[rs[0]], r14[rs[1]]])
+    R = o.dense_rows(rows)
+    err = np.max(np.abs(R - A[rows])) / np.max(np.abs(A[rows]))
+    assert err < 1e-13, err
