@@ -967,12 +967,14 @@ static std::string build_toeplitz(scabs_ctx *c) {
     c->toe_np_tri = np_tri.empty() ? nullptr : c->mem.upload(np_tri);
     c->toe_np_mask = np_mask.empty() ? nullptr : c->mem.upload(np_mask);
     const size_t nc = std::max<size_t>(1, nonper.size());
-    c->toe_tcol32 = c->mem.alloc<cx<float>>(4 * (size_t)g.ne);
-    c->toe_lcol32 = c->mem.alloc<cx<float>>(3 * (size_t)g.ne);
-    c->toe_scol32 = c->mem.alloc<cx<float>>(3 * nc * TOE_T_SHORT_SPLIT);
-    c->toe_tcol64 = c->mem.alloc<cx<double>>(4 * (size_t)g.ne);
-    c->toe_lcol64 = c->mem.alloc<cx<double>>(3 * (size_t)g.ne);
-    c->toe_scol64 = c->mem.alloc<cx<double>>(3 * nc * TOE_T_SHORT_SPLIT);
+    // column outputs of the transposed product for up to 8 vectors
+    const size_t V = 8;
+    c->toe_tcol32 = c->mem.alloc<cx<float>>(4 * (size_t)g.ne * V);
+    c->toe_lcol32 = c->mem.alloc<cx<float>>(3 * (size_t)g.ne * V);
+    c->toe_scol32 = c->mem.alloc<cx<float>>(3 * nc * TOE_T_SHORT_SPLIT * V);
+    c->toe_tcol64 = c->mem.alloc<cx<double>>(4 * (size_t)g.ne * V);
+    c->toe_lcol64 = c->mem.alloc<cx<double>>(3 * (size_t)g.ne * V);
+    c->toe_scol64 = c->mem.alloc<cx<double>>(3 * nc * TOE_T_SHORT_SPLIT * V);
     std::vector<unsigned char> ef(g.ne);
     for (int n = 0; n < g.ne; n++) ef[n] = (unsigned char)((rt.edge_sgn[n] != 0) | ((c->lay.isR[n] != 0) << 1));
     c->toe_eflag = c->mem.upload(ef);
@@ -1424,12 +1426,15 @@ template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
   return R;
 }
 
-// y = A^T z for one vector with the transposed block-Toeplitz product
+// y = A^T z for nb <= 8 vectors (one after another, 2N doubles each) with
+// the transposed block-Toeplitz product
 template <typename T>
-static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_out, const double *z, double *y) {
+static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_out, const double *z, double *y,
+                        int nb) {
   hipStream_t s = c->stream;
   const int off = sizeof(T) == sizeof(float) ? SCABS_STAGE_FP32_OFFSET : 0;
-  toe_ensure(c, d, tri_out, 1);
+  ensure_batch(c, P, nb);
+  toe_ensure(c, d, tri_out, nb);
   DevOperator<T> op = P.op;
   op.tri_out = tri_out;
   const bool f32 = sizeof(T) == sizeof(float);
@@ -1438,28 +1443,34 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
   cx<T> *tcol = f32 ? (cx<T> *)c->toe_tcol32 : (cx<T> *)c->toe_tcol64;
   cx<T> *lcol = f32 ? (cx<T> *)c->toe_lcol32 : (cx<T> *)c->toe_lcol64;
   cx<T> *scol = f32 ? (cx<T> *)c->toe_scol32 : (cx<T> *)c->toe_scol64;
+  const size_t stride = 2 * (size_t)c->lay.N;
   {
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
-    launch_unpack_rows(op, z, s);
+    for (int v = 0; v < nb; v++) {
+      DevOperator<T> ov = op;
+      ov.src = op.src + (size_t)3 * op.ne * v;
+      launch_unpack_rows(ov, z + v * stride, s);
+    }
     // point weights are written only at periodic triangles' points (a fill
     // kernel: this sequence may be captured into a graph)
-    kr_zero(d.pf, sizeof(cx<T>) * 2 * 2 * (size_t)NQ * d.nt_r * d.nr, s);
+    kr_zero(d.pf, sizeof(cx<T>) * 2 * 2 * (size_t)NQ * d.nt_r * d.nr * nb, s);
   }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
-    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_FWD);
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_FWD, nb);
   }
   {
     // every spectrum table entry read once, the row spectra (2 ne_r + 4 NQ
-    // nt_r lines) read and the column spectra (4 ne_r lines) written once
-    const double spectra = (double)sizeof(cx<T>) * d.P * (6.0 * d.ne_r + 4.0 * NQ * d.nt_r);
+    // nt_r lines per vector) read and the column spectra (4 ne_r lines per
+    // vector) written once
+    const double spectra = (double)sizeof(cx<T>) * d.P * nb * (6.0 * d.ne_r + 4.0 * NQ * d.nt_r);
     StageTimer t(c, f32 ? SCABS_STAGE_TOEAPPLYT32 : SCABS_STAGE_TOEAPPLYT64,
                  c->toe_table_bytes[f32 ? 1 : 0] + spectra);
-    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_APPLY);
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_APPLY, nb);
   }
   {
     StageTimer t(c, SCABS_STAGE_NEAR + off);
-    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_INV);
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_INV, nb);
   }
 }
 
@@ -1516,14 +1527,19 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
 // nb products (vectors stored one after another, 2N doubles each)
 static void matvec_n(scabs_ctx *c, const double *x, double *y, int nb, int prec, bool trans = false) {
   const size_t stride = 2 * (size_t)c->lay.N;
+  if (trans && c->toe) {
+    for (int k0 = 0; k0 < nb; k0 += 8) {
+      const int m = std::min(8, nb - k0);
+      if (prec == SCABS_FP32)
+        apply_toe_t(c, c->p32, c->t32, c->toe_tri32, x + k0 * stride, y + k0 * stride, m);
+      else
+        apply_toe_t(c, c->p64, c->t64, c->toe_tri64, x + k0 * stride, y + k0 * stride, m);
+    }
+    return;
+  }
   if (trans) {
     for (int k = 0; k < nb; k++) {
-      if (c->toe) {
-        if (prec == SCABS_FP32)
-          apply_toe_t(c, c->p32, c->t32, c->toe_tri32, x + k * stride, y + k * stride);
-        else
-          apply_toe_t(c, c->p64, c->t64, c->toe_tri64, x + k * stride, y + k * stride);
-      } else if (prec == SCABS_FP32) {
+      if (prec == SCABS_FP32) {
         apply_t(c, c->p32, x + k * stride, y + k * stride);
       } else {
         apply_t(c, c->p64, x + k * stride, y + k * stride);

@@ -328,14 +328,14 @@ __device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR
   }
   return c;
 }
-// transposed block-Toeplitz product of one vector (rows z unpacked into
-// op.src): circulant columns tcol[e][4], long-part columns lcol[e][3],
-// short-part partial columns scol[j][TOE_T_SHORT_SPLIT][3] (capidx: edge ->
-// non-periodic index or -1)
+// transposed block-Toeplitz product of nb <= 8 vectors (rows z unpacked
+// into op.src, one slice of 3 ne per vector): circulant columns
+// tcol[v][e][4], long-part columns lcol[v][e][3], short-part partial columns
+// scol[v][j][TOE_T_SHORT_SPLIT][3] (capidx: edge -> non-periodic index or -1)
 constexpr int TOE_T_SHORT_SPLIT = 16;
 template <typename T>
 void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const ToeRows<T> &R, cx<T> *tcol,
-                          cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts);
+                          cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts, int nb);
 template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb);
 int toe_long_chunk();
 int toe_row_groups();   // the largest number of column groups

@@ -243,3 +243,32 @@ def test_rebuilds_keep_products_exact(case):
         for a, b in zip(products(), ref):
             assert torch.equal(a, b)
     assert _rel(ref[0].cpu().numpy(), A @ x.cpu().numpy()) < 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-6)])
+def test_batched_transposed_products(case, prec, tol):
+    """Transposed products of 3 and 8 vectors at once (tables and stored
+    entries read once for all of them) equal the single-vector products and
+    the dense A^T."""
+    import torch
+    name, w, o, A, ctx = case
+    for nb in (3, 8):
+        Z = np.stack([synth.random_complex(1400 + 10 * nb + k, o.N) for k in range(nb)])
+        Y = ctx.matvec(torch.from_numpy(Z).cuda(), prec=prec, transpose=True).cpu().numpy()
+        for k in range(nb):
+            y1 = ctx.matvec(torch.from_numpy(Z[k]).cuda(), prec=prec, transpose=True).cpu().numpy()
+            d = np.max(np.abs(Y[k] - y1)) / np.max(np.abs(y1))
+            assert d <= (1e-15 if prec == 0 else 1e-6), (nb, k, d)
+            assert _rel(Y[k], A.T @ Z[k]) < tol
+
+
+def test_batched_transposed_solve(case):
+    import torch
+    import paper_1004_5076_amd as pk
+    name, w, o, A, ctx = case
+    G = np.stack([synth.random_complex(1500 + k, o.N) for k in range(3)])
+    lam, infos = ctx.solve(torch.from_numpy(G).cuda(), tol=1e-10, max_iter=4000, restart=200, mode=pk.SCABS_MIXED,
+                           transpose=True)
+    assert all(i["status"] == 0 for i in infos)
+    for k in range(3):
+        assert _rel(lam[k].cpu().numpy(), oracle.lu_solve(A.T.copy(), G[k])) < 1e-8
