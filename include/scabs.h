@@ -196,7 +196,8 @@ int scabs_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double tol, 
                 int mode, scabs_solve_info *info);
 
 /* Transposed system (adjoint method).  y = A^T x, same argument rules as
- * scabs_matvec (nrhs vectors are applied one at a time).  Precorrected-FFT
+ * scabs_matvec (block-Toeplitz contexts apply up to 8 vectors per pass, the
+ * lattice product one at a time).  Precorrected-FFT
  * context: the lattice convolution is symmetric, so the transpose runs the
  * testing and projection steps in reverse (test-side sources with value and
  * derivative stencil weights, convolution, values read at the source points)
