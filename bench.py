@@ -55,7 +55,7 @@ def kernel_src_sha(name: str) -> str:
 ROOFLINE_KERNELS = {
     "toeapply32": ("toe_apply_mfma_kernel", "kernels_toeplitz.hip"),
     "precond": ("precond_apply32_mfma_kernel", "kernels_precond.hip"),
-    "toeapplyt32": ("toe_t_apply_kernel<float>", "kernels_toeplitz_t.hip"),
+    "toeapplyt32": ("toe_t_apply_kernel<float, 1>", "kernels_toeplitz_t.hip"),
 }
 
 
