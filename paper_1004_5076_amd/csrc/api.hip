@@ -1439,7 +1439,7 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
   op.tri_out = tri_out;
   const bool f32 = sizeof(T) == sizeof(float);
   ToeRows<T> R = toe_rows_of<T>(c);
-  d.lines = toe_max_lines(d.P, f32);
+  d.lines = toe_t_max_lines(d.P, f32);
   cx<T> *tcol = f32 ? (cx<T> *)c->toe_tcol32 : (cx<T> *)c->toe_tcol64;
   cx<T> *lcol = f32 ? (cx<T> *)c->toe_lcol32 : (cx<T> *)c->toe_lcol64;
   cx<T> *scol = f32 ? (cx<T> *)c->toe_scol32 : (cx<T> *)c->toe_scol64;

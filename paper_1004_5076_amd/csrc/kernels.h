@@ -333,6 +333,7 @@ __device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR
 // tcol[v][e][4], long-part columns lcol[v][e][3], short-part partial columns
 // scol[v][j][TOE_T_SHORT_SPLIT][3] (capidx: edge -> non-periodic index or -1)
 constexpr int TOE_T_SHORT_SPLIT = 16;
+int toe_t_max_lines(int P, bool fp32);   // transform lines per work-group of the transposed product
 template <typename T>
 void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const ToeRows<T> &R, cx<T> *tcol,
                           cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts, int nb);

@@ -28,6 +28,7 @@ namespace scabs {
 
 constexpr int TT_THREADS = 512;
 constexpr int TT_ELEMS = 16;
+static_assert(TT_THREADS * TT_ELEMS >= 8192, "a work-group must hold one line of the longest circulant the build accepts");
 
 // LDS of a group of G transform lines: padded lines, then P twiddles
 template <typename T> inline size_t tt_tw_offset(int P, int G) {
@@ -40,6 +41,16 @@ __device__ inline const cx<T> *tt_twiddles(unsigned char *smem, const cx<T> *tw,
   for (int i = threadIdx.x; i < P; i += blockDim.x) t[i] = tw[i];
   return t;
 }
+// lines per transform work-group of the transposed product: at most 8,
+// within the Stockham stages' elements per thread (a hard limit of the
+// transform) and with the padded lines within 64 KiB of LDS
+template <typename T> inline int tt_lines(int P) {
+  int g = TT_ELEMS * TT_THREADS / P;
+  if (g > 8) g = 8;
+  while (g > 1 && (size_t)lpad_size<T>(g * P) * sizeof(cx<T>) > 65536) g--;
+  return g < 1 ? 1 : g;
+}
+int toe_t_max_lines(int P, bool fp32) { return fp32 ? tt_lines<float>(P) : tt_lines<double>(P); }
 template <typename K> size_t tt_launch_lds(K kernel, size_t lds) {
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
