@@ -231,7 +231,7 @@ def main():
     t1 = time.perf_counter()
     tune = ctx.autotune(reps=3)
     tune_s = time.perf_counter() - t1
-    tune_chosen = {str(r["nrhs"]): {k: r[k] for k in ("apply_form", "groups", "lines", "us")}
+    tune_chosen = {str(r["nrhs"]): {k: r[k] for k in ("apply_form", "groups", "lines", "overlap", "us")}
                    for r in tune if r["chosen"]}
     log("autotune", f"{tune_s:.2f}s", tune_chosen)
     N = ctx.N

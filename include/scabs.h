@@ -231,11 +231,16 @@ int scabs_set_graphs(scabs_ctx *c, int on);
  * of 8 vectors (class 1): the apply form of the per-frequency block
  * products (0: matrix cores for 8 FP32 vectors, vector ALUs otherwise; 1:
  * vector ALUs), the number of column groups of the periodic rows' sparse
- * part (1-16) and the ring-axis lines per transform work-group (0: the
- * largest that fits 64 KiB of LDS).  Every choice computes the same product
- * (only the order of sums over column groups changes).
+ * part (1-16), the ring-axis lines per transform work-group (0: the
+ * largest that fits 64 KiB of LDS) and the overlap of the stored entries'
+ * sparse parts (1: on a second stream of the context, the short part beside
+ * the forward transforms and the long part beside the inverse transforms,
+ * the block products alone on the chip; 0: after the transforms, on the
+ * context stream).  The transposed products follow their class's overlap.
+ * Every choice computes the same product (only the order of sums over
+ * column groups changes).
  * scabs_autotune times every candidate (forms {0, 1} for class 1, groups
- * {4, 8, 16}, lines {4, largest}) on FP32 products of this context, reps
+ * {4, 8, 16}, lines {4, largest}, overlap {0, 1}) on FP32 products of this context, reps
  * products each after one warm-up, with HIP events on the context stream,
  * and keeps the fastest per class; rec (max_rec entries, may be NULL when
  * max_rec is 0) receives one record per candidate and *n_rec (may be NULL)
@@ -248,10 +253,10 @@ typedef struct {
   int32_t lines;
   double us;           /* mean product time */
   int32_t chosen;      /* 1 for the kept candidate of its class */
-  int32_t pad;
+  int32_t overlap;
 } scabs_tune_record;
 int scabs_autotune(scabs_ctx *c, int reps, scabs_tune_record *rec, int max_rec, int *n_rec);
-int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines);
+int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines, int overlap);
 
 /* Several contexts' systems at once (batching across operators of uneven N:
  * absorber lengths, wavelengths, geometries).  Context i solves nrhs[i]

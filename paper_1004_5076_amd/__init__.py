@@ -87,7 +87,7 @@ class Source(C.Structure):
 
 class TuneRecord(C.Structure):
     _fields_ = [("nrhs", C.c_int32), ("apply_form", C.c_int32), ("groups", C.c_int32), ("lines", C.c_int32),
-                ("us", C.c_double), ("chosen", C.c_int32), ("pad", C.c_int32)]
+                ("us", C.c_double), ("chosen", C.c_int32), ("overlap", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
@@ -156,7 +156,7 @@ def load() -> C.CDLL:
     L.scabs_solve_batched.argtypes = [C.POINTER(P), C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_int),
                                       C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(C.POINTER(SolveInfo))]
     L.scabs_autotune.argtypes = [P, C.c_int, C.POINTER(TuneRecord), C.c_int, C.POINTER(C.c_int)]
-    L.scabs_set_tune.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.scabs_set_tune.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     L.scabs_set_graphs.argtypes = [P, C.c_int]
     L.scabs_last_error.argtypes = [P]
     L.scabs_destroy.argtypes = [P]
@@ -371,8 +371,9 @@ class Context:
         """scabs_set_graphs: replay each Arnoldi step's launches from a HIP graph."""
         self._check(self._L.scabs_set_graphs(self._c, int(bool(on))))
 
-    def set_tune(self, nrhs_class: int, form: int, groups: int, lines: int):
-        self._check(self._L.scabs_set_tune(self._c, int(nrhs_class), int(form), int(groups), int(lines)))
+    def set_tune(self, nrhs_class: int, form: int, groups: int, lines: int, overlap: int = 0):
+        self._check(self._L.scabs_set_tune(self._c, int(nrhs_class), int(form), int(groups), int(lines),
+                                           int(overlap)))
 
     def poynting_decay(self, x, src: Optional[Source], body: int, xpos: float, guide, box, nq: int = 8):
         """Decay rate from Poynting's theorem on the plane x = xpos; returns

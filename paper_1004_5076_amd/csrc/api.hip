@@ -109,6 +109,10 @@ struct scabs_ctx {
   scabs_opts opts{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream of the block-Toeplitz products (the stored entries' sparse
+  // parts beside the transforms), default priority; fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_side[4] = {nullptr, nullptr, nullptr, nullptr};
   std::string err;
   // inputs
   std::vector<double> verts;
@@ -239,8 +243,10 @@ struct scabs_ctx {
   double toe_sparse_bytes[2] = {0, 0};  // stored non-periodic entries one product reads (FP64, FP32)
   // launch choices of the product for fewer than 8 and for 8 vectors:
   // {apply form (0 matrix cores at 8 FP32 vectors, 1 vector ALUs), column
-  // groups of the periodic rows, transform lines per work-group (0: largest)}
-  int toe_tune[2][3] = {{0, 8, 0}, {0, 8, 0}};
+  // groups of the periodic rows, transform lines per work-group (0: largest),
+  // sparse parts on the second stream beside the transforms (1) or after
+  // them (0)}
+  int toe_tune[2][4] = {{0, 8, 0, 0}, {0, 8, 0, 0}};
   int toe_ncap = 0;
   double *toe_part64 = nullptr, *toe_rpart64 = nullptr;
   float *toe_part32 = nullptr, *toe_rpart32 = nullptr;
@@ -262,7 +268,8 @@ struct StageTimer {
   double bytes;
   int launches;
   hipEvent_t e0 = nullptr;
-  StageTimer(scabs_ctx *cc, int st, double b = 0, int n = 1);
+  hipStream_t strm;
+  StageTimer(scabs_ctx *cc, int st, double b = 0, int n = 1, hipStream_t on = nullptr);
   ~StageTimer();
 };
 
@@ -274,14 +281,15 @@ static hipEvent_t next_event(scabs_ctx *c) {
   }
   return c->ev_pool[c->ev_used++];
 }
-StageTimer::StageTimer(scabs_ctx *cc, int st, double b, int n) : c(cc), stage(st), bytes(b), launches(n) {
-  if (c->prof_on && ((c->prof_mask >> st) & 1u) && (e0 = next_event(c))) hipEventRecord(e0, c->stream);
+StageTimer::StageTimer(scabs_ctx *cc, int st, double b, int n, hipStream_t on)
+    : c(cc), stage(st), bytes(b), launches(n), strm(on ? on : cc->stream) {
+  if (c->prof_on && ((c->prof_mask >> st) & 1u) && (e0 = next_event(c))) hipEventRecord(e0, strm);
 }
 StageTimer::~StageTimer() {
   if (!e0) return;
   hipEvent_t e1 = next_event(c);
   if (!e1) return;
-  hipEventRecord(e1, c->stream);
+  hipEventRecord(e1, strm);
   c->prof_recs.push_back({stage, e0, e1, bytes, launches});
 }
 
@@ -1426,6 +1434,13 @@ template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
   return R;
 }
 
+// ordering between the context stream and its second stream: 'to' waits for
+// the work enqueued so far on 'from' (event k of the product's four)
+static void stream_after(scabs_ctx *c, hipStream_t to, hipStream_t from, int k) {
+  HIPCHK(hipEventRecord(c->ev_side[k], from));
+  HIPCHK(hipStreamWaitEvent(to, c->ev_side[k], 0));
+}
+
 // y = A^T z for nb <= 8 vectors (one after another, 2N doubles each) with
 // the transposed block-Toeplitz product
 template <typename T>
@@ -1444,6 +1459,10 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
   cx<T> *lcol = f32 ? (cx<T> *)c->toe_lcol32 : (cx<T> *)c->toe_lcol64;
   cx<T> *scol = f32 ? (cx<T> *)c->toe_scol32 : (cx<T> *)c->toe_scol64;
   const size_t stride = 2 * (size_t)c->lay.N;
+  const bool side = c->toe_tune[nb >= 8 ? 1 : 0][3] != 0;
+  auto parts = [&](hipStream_t on, int which) {
+    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, on, which, nb);
+  };
   {
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
     for (int v = 0; v < nb; v++) {
@@ -1455,10 +1474,19 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
     // kernel: this sequence may be captured into a graph)
     kr_zero(d.pf, sizeof(cx<T>) * 2 * 2 * (size_t)NQ * d.nt_r * d.nr * nb, s);
   }
+  // with the second stream: the short part beside the local terms and
+  // forward transforms, the long part beside the inverse transforms; the
+  // block products run alone
+  if (side) {
+    stream_after(c, c->side, s, 0);
+    StageTimer t(c, SCABS_STAGE_NEAR + off, 0, 1, c->side);
+    parts(c->side, TOE_SHORT);
+  }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
-    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_FWD, nb);
+    parts(s, TOE_FWD);
   }
+  if (side) stream_after(c, s, c->side, 1);
   {
     // every spectrum table entry read once, the row spectra (2 ne_r + 4 NQ
     // nt_r lines per vector) read and the column spectra (4 ne_r lines per
@@ -1466,11 +1494,28 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
     const double spectra = (double)sizeof(cx<T>) * d.P * nb * (6.0 * d.ne_r + 4.0 * NQ * d.nt_r);
     StageTimer t(c, f32 ? SCABS_STAGE_TOEAPPLYT32 : SCABS_STAGE_TOEAPPLYT64,
                  c->toe_table_bytes[f32 ? 1 : 0] + spectra);
-    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_APPLY, nb);
+    parts(s, TOE_APPLY);
   }
-  {
+  if (side) {
+    stream_after(c, c->side, s, 2);
+    {
+      StageTimer t(c, SCABS_STAGE_NEAR + off, 0, 1, c->side);
+      parts(c->side, TOE_LONG);
+    }
+    {
+      StageTimer t(c, SCABS_STAGE_FFT + off);
+      parts(s, TOE_INV);
+    }
+    stream_after(c, s, c->side, 3);
     StageTimer t(c, SCABS_STAGE_NEAR + off);
-    launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, s, TOE_INV, nb);
+    parts(s, TOE_SUM);
+  } else {
+    {
+      StageTimer t(c, SCABS_STAGE_FFT + off);
+      parts(s, TOE_INV);
+    }
+    StageTimer t(c, SCABS_STAGE_NEAR + off);
+    parts(s, TOE_SHORT | TOE_LONG | TOE_SUM);
   }
 }
 
@@ -1485,9 +1530,11 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   op.edge_out = d.edge_out;
   const bool f32 = sizeof(T) == sizeof(float);
   ToeRows<T> R = toe_rows_of<T>(c);
+  bool side = false;
   {
     const int *tn = c->toe_tune[nb >= 8 ? 1 : 0];
     const int lmax = toe_max_lines(d.P, f32);
+    side = tn[3] != 0;
     d.apply_form = tn[0];
     R.groups = std::max(1, std::min(tn[1], toe_row_groups()));
     R.sparse_form = tn[0];   // the 8-vector sparse rows follow the block products' form
@@ -1504,23 +1551,38 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
     StageTimer t(c, SCABS_STAGE_UNPACK + off);
     launch_unpack(op, x, s, nb);
   }
+  // with the second stream: the stored entries' short part beside the
+  // forward transforms, the long part beside the inverse transforms and the
+  // local terms; the block products run alone
+  if (side) {
+    stream_after(c, c->side, s, 0);
+    StageTimer t(c, SCABS_STAGE_NEAR + off, 0, 1, c->side);
+    launch_toe_rows(op, R, y, c->side, nb, TOE_SHORT);
+  }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
     launch_toe_product(op, d, s, nb, TOE_FWD);
   }
+  if (side) stream_after(c, s, c->side, 1);
   {
     // the per-frequency block products: every spectrum table entry read
     // once, the input spectra read and the output spectra written once
     StageTimer ta(c, f32 ? SCABS_STAGE_TOEAPPLY32 : SCABS_STAGE_TOEAPPLY64, tables + spectra);
     launch_toe_product(op, d, s, nb, TOE_APPLY);
   }
+  if (side) {
+    stream_after(c, c->side, s, 2);
+    StageTimer t(c, SCABS_STAGE_NEAR + off, 0, 1, c->side);
+    launch_toe_rows(op, R, y, c->side, nb, TOE_LONG);
+  }
   {
     StageTimer t(c, SCABS_STAGE_FFT + off);
     launch_toe_product(op, d, s, nb, TOE_INV);
   }
+  if (side) stream_after(c, s, c->side, 3);
   {
     StageTimer t(c, SCABS_STAGE_NEAR + off);
-    launch_toe_rows(op, R, y, s, nb);
+    launch_toe_rows(op, R, y, s, nb, side ? TOE_SUM : TOE_ALL);
   }
 }
 
@@ -2083,6 +2145,9 @@ int scabs_create(scabs_ctx **out, const scabs_opts *o) {
     if (hipStreamCreate(&c->stream) != hipSuccess) return SCABS_E_HIP;
     c->own_stream = true;
   }
+  if (hipStreamCreate(&c->side) != hipSuccess) return SCABS_E_HIP;
+  for (hipEvent_t &e : c->ev_side)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SCABS_E_HIP;
   *out = c.release();
   return SCABS_OK;
 }
@@ -2356,8 +2421,9 @@ int scabs_solve_transpose(scabs_ctx *c, const double *b, double *x, int nrhs, do
 // launch choices of the block-Toeplitz product, checked against the kernels'
 // limits: form 0/1, groups 1..toe_row_groups(), lines 0 (largest) or
 // 1..toe_max_lines
-static int check_tune(scabs_ctx *c, int form, int groups, int lines) {
+static int check_tune(scabs_ctx *c, int form, int groups, int lines, int overlap) {
   if (form != 0 && form != 1) return fail(c, SCABS_E_ARG, "apply form must be 0 or 1");
+  if (overlap != 0 && overlap != 1) return fail(c, SCABS_E_ARG, "overlap must be 0 or 1");
   if (groups < 1 || groups > toe_row_groups()) return fail(c, SCABS_E_ARG, "column groups out of range");
   if (lines < 0 || lines > toe_max_lines(c->rt.P, true)) return fail(c, SCABS_E_ARG, "transform lines out of range");
   return SCABS_OK;
@@ -2374,15 +2440,16 @@ int scabs_set_graphs(scabs_ctx *c, int on) {
   return SCABS_OK;
 }
 
-int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines) {
+int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines, int overlap) {
   if (!c) return SCABS_E_ARG;
   if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "needs a built block-Toeplitz context");
   if (nrhs_class != 0 && nrhs_class != 1) return fail(c, SCABS_E_ARG, "nrhs_class must be 0 (< 8) or 1 (8)");
-  if (int st = check_tune(c, form, groups, lines)) return st;
+  if (int st = check_tune(c, form, groups, lines, overlap)) return st;
   clear_graphs(c);
   c->toe_tune[nrhs_class][0] = form;
   c->toe_tune[nrhs_class][1] = groups;
   c->toe_tune[nrhs_class][2] = lines;
+  c->toe_tune[nrhs_class][3] = overlap;
   return SCABS_OK;
 }
 
@@ -2403,35 +2470,39 @@ int scabs_autotune(scabs_ctx *c, int reps, scabs_tune_record *rec, int max_rec, 
     for (int cls = 0; cls < 2; cls++) {
       const int nb = cls ? 8 : 1;
       double best = 1e300;
-      int bestc[3] = {0, 8, 0}, first = nr;
+      int bestc[4] = {0, 8, 0, 0}, first = nr;
       std::vector<int> line_cands = {lmax};
       if (lmax > 4) line_cands.insert(line_cands.begin(), 4);
       for (int form = 0; form < (cls ? 2 : 1); form++)
         for (int groups : {4, 8, 16})
-          for (int lines : line_cands) {
-            c->toe_tune[cls][0] = form;
-            c->toe_tune[cls][1] = groups;
-            c->toe_tune[cls][2] = lines;
-            matvec_n(c, x, y, nb, SCABS_FP32);   // warm
-            HIPCHK(hipEventRecord(e0, c->stream));
-            for (int r = 0; r < reps; r++) matvec_n(c, x, y, nb, SCABS_FP32);
-            HIPCHK(hipEventRecord(e1, c->stream));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            const double us = 1e3 * ms / reps;
-            if (nr < max_rec) rec[nr] = scabs_tune_record{nb, form, groups, lines, us, 0, 0};
-            nr++;
-            if (us < best) {
-              best = us;
-              bestc[0] = form;
-              bestc[1] = groups;
-              bestc[2] = lines;
+          for (int lines : line_cands)
+            for (int overlap = 0; overlap < 2; overlap++) {
+              c->toe_tune[cls][0] = form;
+              c->toe_tune[cls][1] = groups;
+              c->toe_tune[cls][2] = lines;
+              c->toe_tune[cls][3] = overlap;
+              matvec_n(c, x, y, nb, SCABS_FP32);   // warm
+              HIPCHK(hipEventRecord(e0, c->stream));
+              for (int r = 0; r < reps; r++) matvec_n(c, x, y, nb, SCABS_FP32);
+              HIPCHK(hipEventRecord(e1, c->stream));
+              HIPCHK(hipEventSynchronize(e1));
+              float ms = 0;
+              HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+              const double us = 1e3 * ms / reps;
+              if (nr < max_rec) rec[nr] = scabs_tune_record{nb, form, groups, lines, us, 0, overlap};
+              nr++;
+              if (us < best) {
+                best = us;
+                bestc[0] = form;
+                bestc[1] = groups;
+                bestc[2] = lines;
+                bestc[3] = overlap;
+              }
             }
-          }
-      for (int k = 0; k < 3; k++) c->toe_tune[cls][k] = bestc[k];
+      for (int k = 0; k < 4; k++) c->toe_tune[cls][k] = bestc[k];
       for (int i = first; i < std::min(nr, max_rec); i++)
-        rec[i].chosen = rec[i].apply_form == bestc[0] && rec[i].groups == bestc[1] && rec[i].lines == bestc[2];
+        rec[i].chosen = rec[i].apply_form == bestc[0] && rec[i].groups == bestc[1] && rec[i].lines == bestc[2] &&
+                        rec[i].overlap == bestc[3];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2917,6 +2988,10 @@ void scabs_destroy(scabs_ctx *c) {
   if (c->hpin) hipHostFree(c->hpin);
   if (c->hflag) hipHostFree(c->hflag);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  if (c->side) hipStreamSynchronize(c->side);
+  for (hipEvent_t e : c->ev_side)
+    if (e) hipEventDestroy(e);
+  if (c->side) hipStreamDestroy(c->side);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }

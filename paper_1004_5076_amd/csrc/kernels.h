@@ -334,10 +334,20 @@ __device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR
 // scol[v][j][TOE_T_SHORT_SPLIT][3] (capidx: edge -> non-periodic index or -1)
 constexpr int TOE_T_SHORT_SPLIT = 16;
 int toe_t_max_lines(int P, bool fp32);   // transform lines per work-group of the transposed product
+// parts of the product, launched separately so that the sparse parts can run
+// on a second stream beside the transforms: ring-axis forward transforms
+// (with the transposed product's local terms), per-frequency block products,
+// inverse transforms (with the forward product's local and sigma terms), the
+// stored entries' short part (periodic rows x non-periodic columns) and long
+// part (non-periodic rows x every column), and the final sums into y
+enum ToePart { TOE_FWD = 1, TOE_APPLY = 2, TOE_INV = 4, TOE_SHORT = 8, TOE_LONG = 16, TOE_SUM = 32, TOE_ALL = 63 };
 template <typename T>
 void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const ToeRows<T> &R, cx<T> *tcol,
                           cx<T> *lcol, cx<T> *scol, const int *capidx, double *y, hipStream_t s, int parts, int nb);
-template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb);
+// the forward product's stored entries: parts TOE_SHORT, TOE_LONG, TOE_SUM
+template <typename T>
+void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb,
+                     int parts = TOE_ALL);
 int toe_long_chunk();
 int toe_row_groups();   // the largest number of column groups
 int toe_max_lines(int P, bool fp32);   // the largest transform line group for circulant length P
@@ -355,9 +365,6 @@ void launch_toe_cap_entries(const ToeCapArgs &c, hipStream_t st);
 void launch_toe_series_fft(cx<double> *data, int64_t nlines, int P, const cx<double> *tw, hipStream_t s);
 void launch_toe_layout(const ToeSetupArgs &s, int kind, const cx<double> *X, const cx<double> *Y, int64_t per_f,
                        cx<double> *dst64, cx<float> *dst32, hipStream_t st);
-// parts of the product: ring-axis forward transforms, per-frequency block
-// products, inverse transforms with the local and sigma terms
-enum ToePart { TOE_FWD = 1, TOE_APPLY = 2, TOE_INV = 4, TOE_ALL = 7 };
 template <typename T>
 void launch_toe_product(const DevOperator<T> &op, const ToeDev<T> &d, hipStream_t s, int nb, int parts = TOE_ALL);
 

@@ -1279,45 +1279,47 @@ __global__ void toe_long_reduce_kernel(DevOperator<T> op, ToeRows<T> R, double *
   }
 }
 
-template <typename T> void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb) {
+template <typename T>
+void launch_toe_rows(const DevOperator<T> &op, const ToeRows<T> &R, double *y, hipStream_t s, int nb, int parts) {
   const int nchunk = (op.ne + TOE_LCH - 1) / TOE_LCH;
+  const bool lng = (parts & TOE_LONG) && R.nlong > 0, sht = (parts & TOE_SHORT) != 0;
   // 8 FP32 vectors: both sparse parts on the matrix cores (the group's column
   // currents must fit the LDS)
   const size_t sp_lds = sizeof(cx<float>) * 8 * 3 * (size_t)((R.ncap + R.groups - 1) / R.groups + 1);
   if (sizeof(T) == sizeof(float) && nb == 8 && R.sparse_form == 0 && sp_lds <= 65536) {
     const DevOperator<float> &of = *reinterpret_cast<const DevOperator<float> *>(&op);
     const ToeRows<float> &rf = *reinterpret_cast<const ToeRows<float> *>(&R);
-    if (R.nlong > 0) hipLaunchKernelGGL(toe_long_mfma_kernel, dim3(nchunk), dim3(256), 0, s, of, rf);
-    hipLaunchKernelGGL(toe_rows_part_mfma_kernel, dim3((op.ne + 63) / 64, R.groups), dim3(256), sp_lds, s, of, rf);
-    hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op, R, y, nb);
-    if (R.nlong > 0)
-      hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((R.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, R, y,
-                         nb);
-    return;
-  }
+    if (lng) hipLaunchKernelGGL(toe_long_mfma_kernel, dim3(nchunk), dim3(256), 0, s, of, rf);
+    if (sht)
+      hipLaunchKernelGGL(toe_rows_part_mfma_kernel, dim3((op.ne + 63) / 64, R.groups), dim3(256), sp_lds, s, of, rf);
+  } else {
 #define SCABS_TOE_ROWS(NB)                                                                                           \
   do {                                                                                                               \
-    if (R.nlong > 0) hipLaunchKernelGGL((toe_long_kernel<T, NB>), dim3(nchunk), dim3(256), 0, s, op, R);              \
-    hipLaunchKernelGGL((toe_rows_part_kernel<T, NB>), dim3((op.ne + 255) / 256, R.groups), dim3(256), 0, s, op, R);     \
+    if (lng) hipLaunchKernelGGL((toe_long_kernel<T, NB>), dim3(nchunk), dim3(256), 0, s, op, R);                      \
+    if (sht)                                                                                                         \
+      hipLaunchKernelGGL((toe_rows_part_kernel<T, NB>), dim3((op.ne + 255) / 256, R.groups), dim3(256), 0, s, op, R);   \
   } while (0)
-  switch (nb) {
-    case 1: SCABS_TOE_ROWS(1); break;
-    case 2: SCABS_TOE_ROWS(2); break;
-    case 3: SCABS_TOE_ROWS(3); break;
-    case 4: SCABS_TOE_ROWS(4); break;
-    case 5: SCABS_TOE_ROWS(5); break;
-    case 6: SCABS_TOE_ROWS(6); break;
-    case 7: SCABS_TOE_ROWS(7); break;
-    default: SCABS_TOE_ROWS(8); break;
-  }
+    switch (nb) {
+      case 1: SCABS_TOE_ROWS(1); break;
+      case 2: SCABS_TOE_ROWS(2); break;
+      case 3: SCABS_TOE_ROWS(3); break;
+      case 4: SCABS_TOE_ROWS(4); break;
+      case 5: SCABS_TOE_ROWS(5); break;
+      case 6: SCABS_TOE_ROWS(6); break;
+      case 7: SCABS_TOE_ROWS(7); break;
+      default: SCABS_TOE_ROWS(8); break;
+    }
 #undef SCABS_TOE_ROWS
+  }
+  if (!(parts & TOE_SUM)) return;
   hipLaunchKernelGGL(toe_rows_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op, R, y, nb);
   if (R.nlong > 0)
     hipLaunchKernelGGL(toe_long_reduce_kernel<T>, dim3((R.nlong * nb * 64 + 255) / 256), dim3(256), 0, s, op, R, y, nb);
 }
-template void launch_toe_rows<float>(const DevOperator<float> &, const ToeRows<float> &, double *, hipStream_t, int);
+template void launch_toe_rows<float>(const DevOperator<float> &, const ToeRows<float> &, double *, hipStream_t, int,
+                                     int);
 template void launch_toe_rows<double>(const DevOperator<double> &, const ToeRows<double> &, double *, hipStream_t,
-                                      int);
+                                      int, int);
 int toe_long_chunk() { return TOE_LCH; }
 int toe_row_groups() { return TOE_RG_MAX; }
 

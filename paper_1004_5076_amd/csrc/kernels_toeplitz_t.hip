@@ -499,23 +499,25 @@ void launch_toe_product_t(const DevOperator<T> &op, const ToeDev<T> &d, const To
     else
       hipLaunchKernelGGL((toe_t_apply_kernel<T, TT_NB>), dim3((d.ne_r + 3) / 4, d.P), dim3(256), 0, s, d, nb);
   }
-  if (parts & TOE_INV) {
+  if (parts & TOE_INV)
     hipLaunchKernelGGL(toe_t_inv_kernel<T>, dim3((ncol + G - 1) / G), dim3(TT_THREADS),
                        tt_launch_lds(toe_t_inv_kernel<T>, tt_lds<T>(d.P, G)), s, d, tcol, op.ne, nb);
-    if (R.ncap > 0) {
-      if (nb == 1)
-        hipLaunchKernelGGL(toe_t_short_kernel<T>, dim3(R.ncap, TOE_T_SHORT_SPLIT), dim3(256), 0, s, op, R, scol);
-      else
-        hipLaunchKernelGGL(toe_t_short_nb_kernel<T>, dim3(R.ncap, TOE_T_SHORT_SPLIT), dim3(256), 0, s, op, R, scol,
-                           nb);
-    }
+  if ((parts & TOE_SHORT) && R.ncap > 0) {
+    if (nb == 1)
+      hipLaunchKernelGGL(toe_t_short_kernel<T>, dim3(R.ncap, TOE_T_SHORT_SPLIT), dim3(256), 0, s, op, R, scol);
+    else
+      hipLaunchKernelGGL(toe_t_short_nb_kernel<T>, dim3(R.ncap, TOE_T_SHORT_SPLIT), dim3(256), 0, s, op, R, scol,
+                         nb);
+  }
+  if (parts & TOE_LONG) {
     if (nb == 1)
       hipLaunchKernelGGL((toe_t_long_kernel<T, 1>), dim3((op.ne + 3) / 4), dim3(256), 0, s, op, R, lcol, nb);
     else
       hipLaunchKernelGGL((toe_t_long_kernel<T, TT_NB>), dim3((op.ne + 3) / 4), dim3(256), 0, s, op, R, lcol, nb);
+  }
+  if (parts & TOE_SUM)
     hipLaunchKernelGGL(toe_t_combine_kernel<T>, dim3((op.ne + 255) / 256, nb), dim3(256), 0, s, op, R,
                        (const cx<T> *)tcol, (const cx<T> *)lcol, (const cx<T> *)scol, capidx, y);
-  }
 }
 template void launch_toe_product_t<float>(const DevOperator<float> &, const ToeDev<float> &, const ToeRows<float> &,
                                           cx<float> *, cx<float> *, cx<float> *, const int *, double *, hipStream_t,

@@ -141,24 +141,37 @@ def test_solve_matches_dense_lu(case, mode):
 
 def test_every_launch_choice_is_exact(case):
     """The tunable launch choices (apply form, column groups of the sparse
-    rows, transform lines per work-group) change only the order of sums:
-    every one keeps the products exact."""
+    rows, transform lines per work-group, the sparse parts on the second
+    stream) change only the order of sums: every one keeps the products
+    exact, forward and transposed, and the overlap changes no bit."""
     import torch
     name, w, o, A, ctx = case
     X = np.stack([synth.random_complex(200 + k, o.N) for k in range(8)])
     R1 = A @ X[0]
     R8 = X @ A.T
+    T1 = A.T @ X[0]
+    T8 = X @ A
+    Xd = torch.from_numpy(X).cuda()
     for cls in (0, 1):
         for form in ((0,) if cls == 0 else (0, 1)):
             for groups in (1, 3, 16):
                 for lines in (1, 2, 0):
-                    ctx.set_tune(cls, form, groups, lines)
-                    if cls == 0:
-                        y = ctx.matvec(torch.from_numpy(X[0].copy()).cuda(), prec=0).cpu().numpy()
-                        assert _rel(y, R1) < 1e-11, (cls, form, groups, lines)
-                    else:
-                        Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=1).cpu().numpy()
-                        assert _rel(Y, R8) < 2e-6, (cls, form, groups, lines)
+                    outs = []
+                    for overlap in (0, 1):
+                        ctx.set_tune(cls, form, groups, lines, overlap)
+                        key = (cls, form, groups, lines, overlap)
+                        if cls == 0:
+                            y = ctx.matvec(Xd[0].clone(), prec=0)
+                            yt = ctx.matvec(Xd[0].clone(), prec=0, transpose=True)
+                            assert _rel(y.cpu().numpy(), R1) < 1e-11, key
+                            assert _rel(yt.cpu().numpy(), T1) < 1e-11, key
+                        else:
+                            y = ctx.matvec(Xd, prec=1)
+                            yt = ctx.matvec(Xd, prec=1, transpose=True)
+                            assert _rel(y.cpu().numpy(), R8) < 2e-6, key
+                            assert _rel(yt.cpu().numpy(), T8) < 2e-6, key
+                        outs.append((y, yt))
+                    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), key
     ctx.set_tune(0, 0, 8, 0)
     ctx.set_tune(1, 0, 8, 0)
     import paper_1004_5076_amd as pk
@@ -166,6 +179,8 @@ def test_every_launch_choice_is_exact(case):
         ctx.set_tune(1, 2, 8, 0)
     with pytest.raises(pk.ScabsError):
         ctx.set_tune(0, 0, 17, 0)
+    with pytest.raises(pk.ScabsError):
+        ctx.set_tune(0, 0, 8, 0, 2)
 
 
 def test_autotune_keeps_fastest(case):
