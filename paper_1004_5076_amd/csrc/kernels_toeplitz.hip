@@ -415,13 +415,14 @@ template <typename T, int NB>
 __global__ void __launch_bounds__(256) toe_apply_kernel(ToeDev<T> d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *xs = reinterpret_cast<cx<T> *>(smem_raw);   // [slot][v]
-  const int f = blockIdx.y;
+  int part, f;
+  toe_xcd_order(part, f);
   const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
   const int nin = 4 * ne_r * NB;
   const cx<T> *Xf = d.X + (size_t)f * nin;
   for (int i = threadIdx.x; i < nin; i += blockDim.x) xs[i] = Xf[i];
   __syncthreads();
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = part * blockDim.x + threadIdx.x;
   const int nout = 2 * ne_r + 2 * R2;
   cx<T> *Yf = d.Y + (size_t)f * nout * NB;
   if (row < ne_r) {
@@ -640,10 +641,11 @@ __global__ void __launch_bounds__(64 * TOE_MF_WAVES) toe_apply_mfma_kernel(ToeDe
   constexpr int NB = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float> *xs = reinterpret_cast<cx<float> *>(smem_raw);   // [slot][column][v]
-  const int f = blockIdx.y;
+  int part, f;
+  toe_xcd_order(part, f);
   const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r;
   const int gt = (ne_r + 15) / 16, pt = (R2 + 15) / 16;
-  const int t = blockIdx.x * TOE_MF_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = part * TOE_MF_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
   // the exterior table rows of this wave's tile, first chunk loaded before
   // the spectra are staged (it does not depend on them)

@@ -198,8 +198,9 @@ constexpr int TT_NB = 8;   // vectors per call
 // kernel's registers low)
 template <typename T, int NBM>
 __global__ void __launch_bounds__(256) toe_t_apply_kernel(ToeDev<T> d, int nb) {
-  const int f = blockIdx.y;
-  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  int part, f;
+  toe_xcd_order(part, f);
+  const int b = part * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (b >= d.ne_r) return;   // wave-uniform
   const int ne_r = d.ne_r, R2 = 2 * NQ * d.nt_r, nout = 2 * ne_r + 2 * R2, P = d.P;
   const int fr = f == 0 ? 0 : P - f;
