@@ -1434,6 +1434,14 @@ template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
   return R;
 }
 
+// the second stream and its events, made when a tuning first asks for the
+// overlap (outside any graph capture)
+static void ensure_side(scabs_ctx *c) {
+  if (c->side) return;
+  HIPCHK(hipStreamCreate(&c->side));
+  for (hipEvent_t &e : c->ev_side) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
 // ordering between the context stream and its second stream: 'to' waits for
 // the work enqueued so far on 'from' (event k of the product's four)
 static void stream_after(scabs_ctx *c, hipStream_t to, hipStream_t from, int k) {
@@ -1459,7 +1467,7 @@ static void apply_toe_t(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri
   cx<T> *lcol = f32 ? (cx<T> *)c->toe_lcol32 : (cx<T> *)c->toe_lcol64;
   cx<T> *scol = f32 ? (cx<T> *)c->toe_scol32 : (cx<T> *)c->toe_scol64;
   const size_t stride = 2 * (size_t)c->lay.N;
-  const bool side = c->toe_tune[nb >= 8 ? 1 : 0][3] != 0;
+  const bool side = c->toe_tune[nb >= 8 ? 1 : 0][3] != 0 && c->side;
   auto parts = [&](hipStream_t on, int which) {
     launch_toe_product_t(op, d, R, tcol, lcol, scol, c->toe_capidx, y, on, which, nb);
   };
@@ -1534,7 +1542,7 @@ static void apply_toe(scabs_ctx *c, PrecState<T> &P, ToeDev<T> &d, cx<T> *&tri_o
   {
     const int *tn = c->toe_tune[nb >= 8 ? 1 : 0];
     const int lmax = toe_max_lines(d.P, f32);
-    side = tn[3] != 0;
+    side = tn[3] != 0 && c->side;
     d.apply_form = tn[0];
     R.groups = std::max(1, std::min(tn[1], toe_row_groups()));
     R.sparse_form = tn[0];   // the 8-vector sparse rows follow the block products' form
@@ -1714,10 +1722,17 @@ static void read_back(scabs_ctx *c, hipStream_t s, size_t nnrm, int nb, int stri
   for (unsigned spin = 1;; spin++) {
     if (*f == seq) break;
     if ((spin & 16383) == 0) {
+      // a liveness check only: while another thread of a batched solve
+      // captures its graph the runtime may refuse the query, which is asked
+      // again later
       const hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
         if (*f == seq) break;
         throw HipError{hipErrorLaunchFailure, "Arnoldi read-back: the stream finished without setting the host flag"};
+      }
+      if (e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureImplicit) {
+        (void)hipGetLastError();
+        continue;
       }
       if (e != hipErrorNotReady) throw HipError{e, "hipStreamQuery"};
     }
@@ -2145,9 +2160,6 @@ int scabs_create(scabs_ctx **out, const scabs_opts *o) {
     if (hipStreamCreate(&c->stream) != hipSuccess) return SCABS_E_HIP;
     c->own_stream = true;
   }
-  if (hipStreamCreate(&c->side) != hipSuccess) return SCABS_E_HIP;
-  for (hipEvent_t &e : c->ev_side)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SCABS_E_HIP;
   *out = c.release();
   return SCABS_OK;
 }
@@ -2445,6 +2457,13 @@ int scabs_set_tune(scabs_ctx *c, int nrhs_class, int form, int groups, int lines
   if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "needs a built block-Toeplitz context");
   if (nrhs_class != 0 && nrhs_class != 1) return fail(c, SCABS_E_ARG, "nrhs_class must be 0 (< 8) or 1 (8)");
   if (int st = check_tune(c, form, groups, lines, overlap)) return st;
+  try {
+    if (overlap) {
+      HIPCHK(hipSetDevice(c->opts.device));
+      ensure_side(c);
+    }
+  }
+  SCABS_CATCH(c)
   clear_graphs(c);
   c->toe_tune[nrhs_class][0] = form;
   c->toe_tune[nrhs_class][1] = groups;
@@ -2458,10 +2477,12 @@ int scabs_autotune(scabs_ctx *c, int reps, scabs_tune_record *rec, int max_rec, 
   if (!c->built || !c->toe) return fail(c, SCABS_E_STATE, "autotuning applies to a built block-Toeplitz context");
   clear_graphs(c);
   try {
+    HIPCHK(hipSetDevice(c->opts.device));
     const size_t stride = 2 * (size_t)c->lay.N;
     DevMem tmp;
     double *x = tmp.alloc<double>(stride * 8), *y = tmp.alloc<double>(stride * 8);
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * stride * 8, c->stream));
+    ensure_side(c);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
