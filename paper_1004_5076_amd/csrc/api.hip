@@ -253,9 +253,23 @@ struct scabs_ctx {
 };
 
 // drop the captured Arnoldi-step graphs (before any buffer they read goes)
+// waits for a stream that is not capturing itself; while another thread of a
+// batched solve captures its graph the runtime may refuse the wait, which is
+// then asked again
+static hipError_t sync_stream(hipStream_t s) {
+  for (;;) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipErrorStreamCaptureUnsupported && e != hipErrorStreamCaptureImplicit) return e;
+    (void)hipGetLastError();
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return e;
+    std::this_thread::yield();
+  }
+}
+
 static void clear_graphs(scabs_ctx *c) {
   if (c->step_graphs.empty()) return;
-  (void)hipStreamSynchronize(c->stream);   // none of them may still be running
+  (void)sync_stream(c->stream);   // none of them may still be running
   for (auto &g : c->step_graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   c->step_graphs.clear();
