@@ -307,11 +307,12 @@ def main():
         log("stages avg us (profiled step)",
             {k: (v["ms"] / v["count"] * 1e3 if v["count"] else 0.0) for k, v in full.items()})
         top = max(ROOFLINE_KERNELS, key=lambda k: full[k]["ms"])
-        timed_stages = [top]
+        timed_stages = [top, "toeproduct32"]
     else:
-        timed_stages = list(ROOFLINE_KERNELS)
-    # timed steps: only the roofline kernel's stage records events (the
-    # others would add events to every Arnoldi step)
+        timed_stages = list(ROOFLINE_KERNELS) + ["toeproduct32"]
+    # timed steps: only the roofline kernel's stage and the whole FP32
+    # product record events (two per launch; events around every stage would
+    # add ~75 ms per step)
     ctx.profile_mask(timed_stages)
     torch.cuda.synchronize()
     ctx.profile_begin()
@@ -408,9 +409,10 @@ def main():
         "roofline": roofline(prof, top),
         "autotune": {"seconds": tune_s, "chosen": tune_chosen, "candidates": len(tune)},
         "rooflines": roofs,
-        "product_roofline": product_roofline(full),
+        "product_roofline": product_roofline(prof),
         "rooflines_source": ("the timed steps (roofline kernels only)" if args.no_breakdown
                              else "one untimed step with every stage recorded"),
+        "product_roofline_source": "the timed steps",
     }
     def gpu_check(ws, x_lu, b):
         """solution of the same system on the GPU (mixed, to 1e-10), exact

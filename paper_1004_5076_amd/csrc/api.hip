@@ -253,9 +253,10 @@ struct scabs_ctx {
 };
 
 // drop the captured Arnoldi-step graphs (before any buffer they read goes)
-// waits for a stream that is not capturing itself; while another thread of a
-// batched solve captures its graph the runtime may refuse the wait, which is
-// then asked again
+// waits for a stream that is not capturing itself (every synchronisation of
+// the library goes through here); while another thread of a batched solve
+// captures its graph the runtime may refuse the wait, which is then asked
+// again
 static hipError_t sync_stream(hipStream_t s) {
   for (;;) {
     const hipError_t e = hipStreamSynchronize(s);
@@ -737,7 +738,7 @@ static void build_preconditioner(scabs_ctx *c, const cx<double> *X8, DevMem &tmp
   HIPCHK(hipGetLastError());
   int st = 0;
   HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(sync_stream(s));
   if (st) throw std::string("a preconditioner block is singular");
   c->pc_n_core = cl.core_ptr[cl.nc];
   c->has_pc = true;
@@ -767,7 +768,7 @@ static void build_circulant(scabs_ctx *c) {
   std::vector<cx<double>> probe(std::min(mat, (size_t)4096));
   HIPCHK(hipMemcpyAsync(probe.data(), c->pc_T64, sizeof(cx<double>) * probe.size(), hipMemcpyDeviceToHost,
                         c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(sync_stream(c->stream));
   for (const cx<double> &v : probe)
     if (!std::isfinite(v.x) || !std::isfinite(v.y)) throw std::string("the circulant symbol of A_LL is singular");
   c->pc_circ = true;
@@ -901,7 +902,7 @@ static std::string build_toeplitz(scabs_ctx *c) {
     launch_toe_layout(a, 2, a.sPeJ, a.sPeM, (int64_t)nPe, PE64, PE32, s);
     launch_toe_layout(a, 3, a.sPiJ, a.sPiM, (int64_t)nPi, PI64, PI32, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(sync_stream(s));
     tmp.release();
     c->t64.GE = GE64;
     c->t64.GI = GI64;
@@ -1028,7 +1029,7 @@ static std::string build_toeplitz(scabs_ctx *c) {
     ca.S4f = c->toe_S4f;
     launch_toe_cap_entries(ca, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(sync_stream(s));
   }
   c->toe_bcap = 0;
   return "";
@@ -1276,12 +1277,12 @@ static int do_build(scabs_ctx *c) {
       cx<double> *X8 = tmp.alloc<cx<double>>(8 * (size_t)c->nnz);
       launch_exact_assemble(c->nnz, cptr, cpair, cij, a.blocks_exact, X8, s);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(sync_stream(s));
       tmp.free_one(a.blocks);
       tmp.free_one(a.blocks_exact);
       build_preconditioner(c, X8, tmp);
     }
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(sync_stream(s));
     tmp.release();
     // FP32 transposed product: mirrored copies of the near values, read in row order
     cx<float> *V4fT = c->mem.alloc<cx<float>>(4 * (size_t)c->nnz);
@@ -1292,7 +1293,7 @@ static int do_build(scabs_ctx *c) {
     build_precision<double>(c, c->p64, tw_all, tw_off, ghat64, ghat32, V4, S4, nullptr, nullptr);
     build_precision<float>(c, c->p32, tw_all, tw_off, ghat64, ghat32, V4f, S4f, V4fT, S4fT);
   }
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(sync_stream(s));
   c->toe = false;
   if (c->opts.product == SCABS_PRODUCT_TOEPLITZ) {
     e = build_toeplitz(c);
@@ -1797,7 +1798,7 @@ static void dev_norms(scabs_ctx *c, const cx<double> *v, int nb, double *out) {
   const int64_t N = c->lay.N;
   for (int b = 0; b < nb; b++) kr_norm(v + b * N, N, c->nrm_part, c->nrm + b, c->stream);
   HIPCHK(hipMemcpyAsync(out, c->nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(sync_stream(c->stream));
 }
 
 struct GmresResult {
@@ -2059,7 +2060,7 @@ static void gmres_batch(scabs_ctx *c, int nb, const cx<double> *rhs, cx<double> 
       HIPCHK(hipMemcpyAsync(h1, yb.data(), sizeof(cx<double>) * jj, hipMemcpyHostToDevice, s));
       kr_update(c->t + b * N, V + b * N, ldv, jj, h1, N, +1.0, s);
       // the host vector yb must outlive the copy
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(sync_stream(s));
     }
     if (c->has_pc) {
       apply_precond_n(c, c->t, c->z, nb, trans, prec);
@@ -2142,7 +2143,7 @@ static int solve_batch(scabs_ctx *c, int nb, const cx<double> *b, cx<double> *x,
       if (g[a].iters == 0 && !g[a].converged) stalled[k] = 1;
     }
   }
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(sync_stream(s));
   tmp.release();
   int worst = SCABS_OK;
   for (int k = 0; k < nb; k++) {
@@ -2350,7 +2351,7 @@ int scabs_rhs_source(scabs_ctx *c, const scabs_source *src, double *b) {
   try {
     rhs_source(c, source_dev(src->pos, src->moment, src->dir, src->b), src->body, b);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2363,7 +2364,7 @@ int scabs_rhs_dipole(scabs_ctx *c, const double pos[3], const double moment[6], 
   try {
     rhs_source(c, source_dev(pos, moment, nullptr, 0.0), body, b);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2376,7 +2377,7 @@ static int do_matvec(scabs_ctx *c, const double *x, double *y, int nrhs, int pre
   try {
     matvec_n(c, x, y, nrhs, prec, trans);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2399,7 +2400,7 @@ int scabs_precond_apply(scabs_ctx *c, const double *x, double *y, int nrhs, int 
   try {
     apply_precond_n(c, (const cx<double> *)x, (cx<double> *)y, nrhs, transpose != 0, prec);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2419,7 +2420,7 @@ static int do_solve(scabs_ctx *c, const double *b, double *x, int nrhs, double t
     kr_finite(x, (int64_t)stride * nrhs, c->flag, c->stream);
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
     if (bad) return fail(c, SCABS_E_NAN, "non-finite value in b or x");
     int worst = SCABS_OK;
     for (int k0 = 0; k0 < nrhs; k0 += B) {
@@ -2585,7 +2586,7 @@ int scabs_incident_dipole_points(scabs_ctx *c, const double pos[3], const double
     launch_incident_points(c->p64.op.np, c->body_dev, c->p64.pts, c->qp64, c->k_i, c->Z_i,
                            source_dev(pos, moment, nullptr, 0.0), body, (cx<double> *)E, c->stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2600,7 +2601,7 @@ int scabs_incident_source_points(scabs_ctx *c, const scabs_source *src, double *
                            source_dev(src->pos, src->moment, src->dir, src->b), src->body, (cx<double> *)E,
                            c->stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2629,7 +2630,7 @@ static void point_fields(scabs_ctx *c, const double *x, cx<double> *Ee, cx<doubl
     launch_point_fields_exact(P.op, c->trid, c->toe_abs_np, c->toe_nabs_np, c->k_e, c->Z_e, c->k_i, c->Z_i,
                               c->opts.kappa_s, Ee, Ei, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(sync_stream(s));
     tmp.release();
     return;
   }
@@ -2650,7 +2651,7 @@ int scabs_point_fields(scabs_ctx *c, const double *x, double *Ee, double *Ei) {
   if (!c->built) return fail(c, SCABS_E_STATE, "scabs_build has not succeeded");
   try {
     point_fields(c, x, (cx<double> *)Ee, (cx<double> *)Ei);
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2668,7 +2669,7 @@ int scabs_eval_field(scabs_ctx *c, const double *x, const double *pts, int npts,
     const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
     launch_eval_field(c->p64.op, c->qp64, p, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H, c->stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2687,7 +2688,7 @@ int scabs_eval_field_exact(scabs_ctx *c, const double *x, const double *pts, int
     const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
     launch_eval_field_exact(c->p64.op, c->trid, p, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H, c->stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2700,7 +2701,7 @@ static void source_field(scabs_ctx *c, const SourceDev &S, int body, const doubl
   if (region != body) {
     HIPCHK(hipMemsetAsync(E, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
     HIPCHK(hipMemsetAsync(H, 0, sizeof(cx<double>) * 3 * (size_t)npts, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
     return;
   }
   DevMem tmp;
@@ -2708,7 +2709,7 @@ static void source_field(scabs_ctx *c, const SourceDev &S, int body, const doubl
   HIPCHK(hipMemcpyAsync(p, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, c->stream));
   launch_dipole_points(npts, p, c->k_i, c->Z_i, S, (cx<double> *)E, (cx<double> *)H, c->stream);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(sync_stream(c->stream));
 }
 
 int scabs_dipole_field(scabs_ctx *c, const double pos[3], const double moment[6], int body, const double *pts,
@@ -2763,7 +2764,7 @@ static void total_fields_host(scabs_ctx *c, const double *x, const scabs_source 
     HIPCHK(hipMemcpyAsync(ei.data(), Ed, sizeof(cx<double>) * e.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(hi.data(), Hd, sizeof(cx<double>) * h.size(), hipMemcpyDeviceToHost, c->stream));
   }
-  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(sync_stream(c->stream));
   for (size_t i = 0; i < e.size(); i++) {
     E[i] = {e[i].x, e[i].y};
     H[i] = {h[i].x, h[i].y};
@@ -2885,7 +2886,7 @@ int scabs_eval_field_noalloc(scabs_ctx *c, const double *x, const double *pts, i
     launch_eval_field(c->p64.op, c->qp64, c->noalloc_pts, npts, region, k, Z, (cx<double> *)E, (cx<double> *)H,
                       c->stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2902,7 +2903,7 @@ int scabs_eval_field_transpose(scabs_ctx *c, const double *pts, int npts, int re
     const double k = region < 0 ? c->k_e : c->k_i, Z = region < 0 ? c->Z_e : c->Z_i;
     launch_eval_field_t(c->p64.op, c->qp64, p, npts, region, k, Z, (const cx<double> *)wE, y, c->stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
   }
   SCABS_CATCH(c)
   return SCABS_OK;
@@ -2931,7 +2932,7 @@ int scabs_sigma_gradient(scabs_ctx *c, const double *x, const double *lam, const
     HIPCHK(hipGetLastError());
     std::vector<double> h(dfdparam ? np : 0);
     if (dfdparam) HIPCHK(hipMemcpyAsync(h.data(), dfds, np * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(sync_stream(c->stream));
     tmp.release();
     if (dfdparam) {
       // chain rule through the profile: d sigma_q / d p for every end's parameters
@@ -2983,7 +2984,7 @@ int scabs_profile_mask(scabs_ctx *c, uint32_t mask) {
 int scabs_profile_end(scabs_ctx *c, double *ms, int64_t *count) {
   if (!c) return SCABS_E_ARG;
   c->prof_on = false;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, SCABS_E_HIP, "stream synchronisation failed");
+  if (sync_stream(c->stream) != hipSuccess) return fail(c, SCABS_E_HIP, "stream synchronisation failed");
   for (int k = 0; k < SCABS_NSTAGES; k++) {
     if (ms) ms[k] = 0;
     if (count) count[k] = 0;
@@ -3014,7 +3015,7 @@ const char *scabs_last_error(const scabs_ctx *c) { return c ? c->err.c_str() : "
 void scabs_destroy(scabs_ctx *c) {
   if (!c) return;
   hipSetDevice(c->opts.device);
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)sync_stream(c->stream);
   clear_graphs(c);
   c->work.release();
   c->workV64.release();
@@ -3023,7 +3024,7 @@ void scabs_destroy(scabs_ctx *c) {
   if (c->hpin) hipHostFree(c->hpin);
   if (c->hflag) hipHostFree(c->hflag);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-  if (c->side) hipStreamSynchronize(c->side);
+  if (c->side) (void)sync_stream(c->side);
   for (hipEvent_t e : c->ev_side)
     if (e) hipEventDestroy(e);
   if (c->side) hipStreamDestroy(c->side);
