@@ -1452,9 +1452,10 @@ template <typename T> static ToeRows<T> toe_rows_of(scabs_ctx *c) {
 // the second stream and its events, made when a tuning first asks for the
 // overlap (outside any graph capture)
 static void ensure_side(scabs_ctx *c) {
-  if (c->side) return;
+  if (c->side) return;   // the stream is set last: it implies the events
+  for (hipEvent_t &e : c->ev_side)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPCHK(hipStreamCreate(&c->side));
-  for (hipEvent_t &e : c->ev_side) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 // ordering between the context stream and its second stream: 'to' waits for
