@@ -50,6 +50,9 @@ CASES = {
     "guide4": synth.workload_small,    # one guide, quadratic absorber on [2, 4], 27 rings
     "section": _section,               # two channels, quartic absorber, 14 rings
     "rotated": _rotated,               # guide4 with part of the triangles renumbered
+    # 30 rings: circulant length 64, a multiple of 8, so the per-frequency
+    # kernels take their XCD-ordered grids
+    "guide44": lambda: synth.workload_small(length=4.4),
 }
 
 
@@ -71,6 +74,8 @@ def test_layout_and_rings(case):
     info = ctx.info()
     assert info["product"] == 1 and info["N"] == o.N
     assert info["rings"] >= 3 and info["circulant_length"] >= 2 * info["rings"] - 1
+    if name == "guide44":
+        assert info["circulant_length"] % 8 == 0
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-6)])
