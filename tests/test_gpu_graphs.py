@@ -2,7 +2,8 @@
 preconditioner + product launches are replayed from a captured graph equal
 the solves with ordinary launches bit for bit -- FP64 and mixed, forward and
 transposed, 1, 3 and 8 right-hand sides, block-Toeplitz and lattice
-contexts, the Schwarz and the circulant + Schwarz preconditioners -- over
+contexts, the block-Toeplitz sparse parts on the second stream or not, the
+Schwarz and the circulant + Schwarz preconditioners -- over
 several solves in a row (hundreds of replays, each between the host's
 read-backs and the eager Gram-Schmidt launches) and across batch-size
 changes (buffers regrown, graphs dropped and captured again), and inside
@@ -50,6 +51,18 @@ def toe_ctx():
 @pytest.mark.parametrize("mode", [0, 2])
 def test_toeplitz_graph_solves_equal_eager(toe_ctx, mode):
     _compare(toe_ctx, [(mode, False, 1), (mode, False, 3), (mode, False, 8), (mode, True, 1), (mode, False, 1)])
+
+
+def test_graphs_with_second_stream_equal_eager():
+    """With the stored entries' sparse parts on the context's second stream
+    (overlap 1), the captured graphs take that stream in through the fork and
+    join events; the solves still equal the eager ones bit for bit."""
+    import paper_1004_5076_amd as pk
+    ctx = pk.context_for(synth.workload_small(), device=0, product=pk.SCABS_PRODUCT_TOEPLITZ)
+    for cls in (0, 1):
+        ctx.set_tune(cls, 0, 8, 0, 1)
+    _compare(ctx, [(2, False, 8), (2, False, 1), (2, True, 1), (0, True, 8), (0, False, 3)])
+    ctx.close()
 
 
 def test_lattice_graph_solves_equal_eager():
