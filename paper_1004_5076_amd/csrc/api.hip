@@ -1748,6 +1748,9 @@ static void read_back(scabs_ctx *c, hipStream_t s, size_t nnrm, int nb, int stri
       }
       if (e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureImplicit) {
         (void)hipGetLastError();
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone)
+          throw HipError{e, "Arnoldi read-back on a capturing stream"};
         continue;
       }
       if (e != hipErrorNotReady) throw HipError{e, "hipStreamQuery"};
