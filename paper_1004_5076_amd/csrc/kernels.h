@@ -333,7 +333,7 @@ __device__ inline RowCoef<T> row_coef(const cx<T> *V4, const cx<T> *S4, bool isR
 // tcol[v][e][4], long-part columns lcol[v][e][3], short-part partial columns
 // scol[v][j][TOE_T_SHORT_SPLIT][3] (capidx: edge -> non-periodic index or -1)
 constexpr int TOE_T_SHORT_SPLIT = 16;
-int toe_t_max_lines(int P, bool fp32);
+int toe_t_max_lines(int P, bool fp32);   // transform lines per work-group of the transposed product
 // Work-groups are dispatched round-robin over the chip's 8 XCDs, each with
 // its own L2.  A launch of gridDim.x work-groups per frequency over
 // gridDim.y = P frequencies takes its (part, frequency) so that the parts of
@@ -350,7 +350,7 @@ __device__ inline void toe_xcd_order(int &part, int &f) {
   const int L = blockIdx.y * gx + blockIdx.x, k = L >> 3, q = k / gx;
   f = q * 8 + (L & 7);
   part = k - q * gx;
-}   // transform lines per work-group of the transposed product
+}
 // parts of the product, launched separately so that the sparse parts can run
 // on a second stream beside the transforms: ring-axis forward transforms
 // (with the transposed product's local terms), per-frequency block products,
