@@ -5,7 +5,8 @@ pairs by or_dense_rows): E, H and eq14 rows of periodic edges in both
 channels, of end-cap edges and of absorber edges at both ends.  Checked: the
 FP64 and FP32 products of a seeded vector and the FP32 product of a seeded
 batch of 8 (the matrix-core form) at those rows, and whole rows from the
-transposed product of unit vectors.  Scale of a row's error: the sum of the
+transposed product of unit vectors (FP64, and FP32 one at a time and as a
+batch of 8).  Scale of a row's error: the sum of the
 magnitudes of its terms."""
 import numpy as np
 import pytest
@@ -83,6 +84,27 @@ def test_batched_fp32_product_at_sampled_rows(big):
     Y = ctx.matvec(torch.from_numpy(X).cuda(), prec=1).cpu().numpy()
     for k in range(8):
         _check(Y[k, rows], R, X[k], 1e-6, "batch vector %d" % k)
+
+
+def test_fp32_and_batched_transposed_products_give_rows(big):
+    """FP32 transposed products of unit vectors, one at a time and as one
+    batch of 8 (the batched instances), against the dense rows: error per
+    row scaled by the sum of the row's magnitudes."""
+    import torch
+    w, o, ctx, rows, R = big
+    ks = list(range(min(8, len(rows))))
+    E = np.zeros((len(ks), o.N), complex)
+    for n, k in enumerate(ks):
+        E[n, rows[k]] = 1.0
+    Ed = torch.from_numpy(E).cuda()
+    Y8 = ctx.matvec(Ed, prec=1, transpose=True).cpu().numpy()
+    for n, k in enumerate(ks):
+        y1 = ctx.matvec(Ed[n].clone(), prec=1, transpose=True).cpu().numpy()
+        scale = np.sum(np.abs(R[k]))
+        e1 = np.max(np.abs(y1 - R[k])) / scale
+        e8 = np.max(np.abs(Y8[n] - R[k])) / scale
+        print("row", rows[k], "FP32 transposed: single", e1, "batched", e8, flush=True)
+        assert e1 < 1e-6 and e8 < 1e-6
 
 
 def test_transposed_product_gives_rows(big):
